@@ -1,0 +1,34 @@
+"""CPU FP64 oracle for randomized Nystrom PCG (Frangella, Tropp & Udell).
+
+TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+benchmark's CPU-baseline leg may import this package.  The library under
+``paper_2110_02820_amd`` never imports it and shares no code with it.
+
+Everything here is plain NumPy/SciPy in float64, written from the paper's
+definitions and algorithms in their order and notation, with no blocking,
+fusion or reordering beyond what a definition states (the RBF operator is
+evaluated in row blocks only so that it fits in memory; each block is the
+textbook formula).
+
+Pinned parts (tests/test_oracle_*.py):
+  operators        -- against scipy.spatial.distance / explicit products
+  nystrom          -- Lemma (Nystrom properties), closed form of eq. (nys-unstable),
+                      exact recovery for rank(A) <= l
+  precond          -- P P^{-1} = I, spectrum of P^{-1}, Woodbury identity
+  pcg              -- dense Cholesky solve (LAPACK), scipy.sparse.linalg.cg iterates,
+                      iteration counts for rank(A) < l and rank(A) = l,
+                      CG iteration bound with the exact condition number
+  power            -- power estimate against the exact spectral norm of E
+  grad             -- central finite differences of dense solves and a closed form
+  philox           -- Random123 known-answer vectors
+Parity unpinned: none of the functions above is unpinned; the mixed-precision
+forms have no oracle of their own (they are judged by this FP64 oracle's true
+residual).
+"""
+from .operators import DenseOp, XtXOp, RBFOp, rbf_kernel_block  # noqa: F401
+from .nystrom import orthonormalize, matlab_eps, randomized_nystrom  # noqa: F401
+from .precond import precond_inv_apply, precond_matrix, precond_inv_matrix  # noqa: F401
+from .pcg import nystrom_pcg, true_relres, dense_solve  # noqa: F401
+from .power import rand_pow_err_est  # noqa: F401
+from .grad import adjoint_gradients  # noqa: F401
+from .philox import philox4x32_10, gaussian_philox  # noqa: F401

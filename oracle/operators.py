@@ -1,0 +1,92 @@
+"""Operators A for the regularised system (A + mu I) x = b, in float64.
+
+A is symmetric psd and is reached only through products A V (Section 1.1:
+the method touches A through matvecs).  Three forms:
+
+* DenseOp  -- an explicit symmetric n x n matrix.
+* XtXOp    -- ridge normal equations, A = scale * X^T X for data X (m x n)
+              (Section 1.4, eq. (RidgeRegression); scale absorbs the 1/n factor).
+* RBFOp    -- Gaussian kernel matrix K_ij = exp(-||x_i - x_j||^2 / (2 sigma^2))
+              for points x_i (rows of X, n x d) (Section 6.3, kernel ridge
+              regression).  K is never stored whole; row blocks are formed on
+              demand.
+
+Stored float32 data is promoted exactly to float64, so the oracle and a device
+path reading the same float32 array define the identical matrix A.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+_BLOCK = 2048
+
+
+class DenseOp:
+    def __init__(self, A: np.ndarray):
+        self.A = np.asarray(A, dtype=np.float64)
+        self.n = self.A.shape[0]
+
+    def matmat(self, V: np.ndarray) -> np.ndarray:
+        return self.A @ V
+
+    def dense(self) -> np.ndarray:
+        return self.A
+
+
+class XtXOp:
+    def __init__(self, X: np.ndarray, scale: float = 1.0):
+        self.X = np.asarray(X, dtype=np.float64)
+        self.scale = float(scale)
+        self.n = self.X.shape[1]
+
+    def matmat(self, V: np.ndarray) -> np.ndarray:
+        # A V = scale * X^T (X V): two products, no n x n matrix is formed.
+        return self.scale * (self.X.T @ (self.X @ V))
+
+    def dense(self) -> np.ndarray:
+        return self.scale * (self.X.T @ self.X)
+
+
+def rbf_kernel_block(Xr: np.ndarray, Xc: np.ndarray, sigma: float) -> np.ndarray:
+    """K(Xr, Xc) with entries exp(-||x - y||^2 / (2 sigma^2)).
+
+    The squared distance is expanded as ||x||^2 + ||y||^2 - 2 x^T y (exact
+    identity) and clipped at 0, since a squared distance is never negative.
+    """
+    Xr = np.asarray(Xr, dtype=np.float64)
+    Xc = np.asarray(Xc, dtype=np.float64)
+    d2 = (Xr * Xr).sum(1)[:, None] + (Xc * Xc).sum(1)[None, :] - 2.0 * (Xr @ Xc.T)
+    np.maximum(d2, 0.0, out=d2)
+    return np.exp(-d2 / (2.0 * sigma * sigma))
+
+
+class RBFOp:
+    def __init__(self, X: np.ndarray, sigma: float):
+        self.X = np.asarray(X, dtype=np.float64)
+        self.sigma = float(sigma)
+        self.n = self.X.shape[0]
+
+    def rows(self, idx) -> np.ndarray:
+        return rbf_kernel_block(self.X[idx], self.X, self.sigma)
+
+    def matmat(self, V: np.ndarray) -> np.ndarray:
+        V = np.asarray(V, dtype=np.float64)
+        out = np.empty((self.n,) + V.shape[1:], dtype=np.float64)
+        for i in range(0, self.n, _BLOCK):
+            out[i:i + _BLOCK] = rbf_kernel_block(self.X[i:i + _BLOCK], self.X, self.sigma) @ V
+        return out
+
+    def dense(self) -> np.ndarray:
+        return rbf_kernel_block(self.X, self.X, self.sigma)
+
+    def dsigma_matmat(self, V: np.ndarray) -> np.ndarray:
+        """(dK/dsigma) V with dK_ij/dsigma = K_ij ||x_i - x_j||^2 / sigma^3."""
+        V = np.asarray(V, dtype=np.float64)
+        out = np.empty((self.n,) + V.shape[1:], dtype=np.float64)
+        s = self.sigma
+        for i in range(0, self.n, _BLOCK):
+            Xr = self.X[i:i + _BLOCK]
+            d2 = (Xr * Xr).sum(1)[:, None] + (self.X * self.X).sum(1)[None, :] - 2.0 * (Xr @ self.X.T)
+            np.maximum(d2, 0.0, out=d2)
+            out[i:i + _BLOCK] = (np.exp(-d2 / (2 * s * s)) * d2 / s ** 3) @ V
+        return out
