@@ -1,0 +1,219 @@
+/*
+ * nyspcg.h -- C ABI of the MI355X (gfx950) randomized Nystrom PCG library.
+ *
+ * Solves the regularised psd system (A + mu I) x = b of Section 1.1 of
+ * Frangella, Tropp & Udell, "Randomized Nystrom Preconditioning", with the
+ * randomized Nystrom approximation (Section 2.2, algorithm "Randomized Nystrom
+ * Approximation"), the Nystrom preconditioner (Section 5.1.2, eq. (NysPre)) and
+ * left-preconditioned CG (Section 5.2, algorithm "Nystrom PCG").
+ *
+ * Conventions shared by every entry point
+ *   - Every array argument is a DEVICE pointer owned by the caller, unless the
+ *     comment says "host".  Matrices are row-major with an explicit leading
+ *     dimension counted in elements.  The library never allocates or frees
+ *     device memory: each call takes a workspace (ws, ws_bytes) sized by
+ *     nys_workspace_size(); a too-small workspace returns NYS_ERR_WORKSPACE.
+ *   - `stream` is the caller's hipStream_t (NULL = default stream).  Work is
+ *     enqueued on it in order.  nys_factor and nys_pcg_solve* synchronise that
+ *     stream to read convergence and failure flags; the other calls do not.
+ *   - Inputs are never written, except the buffers documented as in/out.
+ *   - Errors are returned as nys_status codes; no C++ exception crosses the
+ *     ABI.  nys_last_error() returns a message for the last non-OK status of
+ *     the calling thread.
+ *   - Calls that share a workspace must not overlap on different streams.
+ */
+#ifndef NYSPCG_H
+#define NYSPCG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  NYS_OK = 0,
+  NYS_NOT_CONVERGED = 1,   /* iteration cap reached; X holds the last iterate  */
+  NYS_ERR_ARG = -1,        /* invalid argument (shape, mu < 0, tol <= 0, ...)  */
+  NYS_ERR_NOT_PSD = -2,    /* Cholesky of Omega^T Y_nu failed after retries    */
+  NYS_ERR_BREAKDOWN = -3,  /* p^T (A + mu I) p <= 0: system not positive definite */
+  NYS_ERR_DEVICE = -4,     /* HIP runtime error, or a device-side time-out     */
+  NYS_ERR_WORKSPACE = -5   /* workspace smaller than nys_workspace_size()      */
+} nys_status;
+
+typedef enum { NYS_F64 = 0, NYS_F32 = 1 } nys_dtype;
+
+/* Arithmetic used by the sketch, the matvec and the CG vectors.  Every mode
+ * returns x in float64 and is judged by the float64 true relative residual. */
+typedef enum {
+  NYS_PREC_FP64 = 0,            /* all float64                                   */
+  NYS_PREC_FP32 = 1,            /* float32 vectors/matvec, no refinement (tol >= 1e-5) */
+  NYS_PREC_FP32_REFINE64 = 2,   /* float32 inner PCG; float64 residual b-(A+mu I)x
+                                   and update x += d in an outer refinement loop   */
+  NYS_PREC_BF16X3_REFINE64 = 3  /* as 2, with RBF Gram tiles split into three
+                                   bf16 products on MFMA (float32 accumulation)    */
+} nys_precision;
+
+/* The operator A (Section 1.1: A is reached only through products). */
+typedef enum {
+  NYS_OP_DENSE = 0,  /* explicit symmetric A: data is n x n                    */
+  NYS_OP_XTX = 1,    /* ridge normal equations A = scale X^T X (Section 1.4,
+                        eq. (RidgeRegression)): data X is rows x n             */
+  NYS_OP_RBF = 2     /* Gaussian kernel K_ij = exp(-|x_i-x_j|^2/(2 sigma^2))
+                        (Section 6.3): data is n x d, one point per row       */
+} nys_op_kind;
+
+typedef struct {
+  int32_t kind;      /* nys_op_kind                                           */
+  int32_t dtype;     /* storage type of `data`: NYS_F64 or NYS_F32            */
+  int64_t n;         /* system dimension                                      */
+  const void* data;  /* device, row-major, see nys_op_kind                    */
+  int64_t rows;      /* rows of data (DENSE: n; XTX: m; RBF: n)               */
+  int64_t cols;      /* cols of data (DENSE: n; XTX: n; RBF: d)               */
+  int64_t ld;        /* leading dimension of data, >= cols                    */
+  double sigma;      /* RBF bandwidth (> 0); ignored otherwise                */
+  double scale;      /* A = scale * (base operator); must be > 0              */
+} nys_operator;
+
+/* Factored Nystrom approximation A_hat = U diag(lam) U^T (output of the
+ * randomized Nystrom approximation).  It does not depend on mu, so one
+ * preconditioner serves a whole mu grid and the adjoint solve. */
+typedef struct {
+  int64_t n, ell;
+  void* U;           /* device, n x ell row-major (ldu), orthonormal columns  */
+  int64_t ldu;
+  int32_t dtype;     /* storage of U: NYS_F64 or NYS_F32 (float32 halves the
+                        apply traffic of the mixed-precision modes)           */
+  int32_t pad_;
+  double* lam;       /* device, ell float64, descending, >= 0                 */
+  double nu;         /* host: shift used by the factorisation (output)        */
+} nys_precond;
+
+typedef struct {
+  double tol;          /* stop when ||b - (A+mu I)x||_2 <= tol ||b||_2          */
+  int32_t maxit;       /* iteration cap per (inner) solve; 0 selects 500        */
+  int32_t prec;        /* nys_precision                                         */
+  int32_t max_refine;  /* refinement modes: cap on outer steps; 0 selects 10    */
+  int32_t check_every; /* iterations between host polls of the flags; 0 = 8     */
+  double inner_tol;    /* refinement modes: relative reduction asked of each
+                          inner solve; 0 selects 1e-4                          */
+} nys_solve_opts;
+
+typedef struct {
+  int32_t* iters;      /* host, one per column: PCG iterations (all inner)      */
+  double* relres;      /* host, one per column: final relative residual (float64
+                          true residual in refinement modes, recursive otherwise) */
+  int32_t* status;     /* host, one per column: nys_status                      */
+  int32_t refine_steps;/* output: outer refinement steps taken                  */
+  int32_t total_iters; /* output: iteration sweeps executed (max over columns)  */
+} nys_solve_info;
+
+/* Bytes of workspace that suffice for every call below on operator A with
+ * sketch size ell, ncols simultaneous right-hand sides and precision prec. */
+size_t nys_workspace_size(const nys_operator* A, int64_t ell, int64_t ncols, int32_t prec);
+
+/* Standard normal n x ell test matrix (Section 2.2, algorithm "Randomized
+ * Nystrom Approximation", first step) from a counter-based generator:
+ * Philox4x32-10 (Salmon et al., SC 2011) with key = seed, counter = entry/2,
+ * and the Box-Muller transform of two 53-bit uniforms.  Entry (i, j) depends
+ * only on (seed, i*ell + j).  out: device float64, n x ell, leading dim ld. */
+nys_status nys_gaussian(uint64_t seed, int64_t n, int64_t ell, double* out, int64_t ld,
+                        void* stream);
+
+/* Sketch (algorithm "Randomized Nystrom Approximation", steps 1-3):
+ * Omega = orth(Omega0) (thin QR factor Q, computed by CholeskyQR2) and
+ * Y = A Omega.  omega0: device float64 n x ell (ld = ell) or NULL to draw it
+ * with nys_gaussian(seed).  Omega_out, Y_out: device float64 n x ell (ld = ell).
+ * prec selects the arithmetic of Y = A Omega (FP64, FP32 or BF16X3 tiles);
+ * Omega is float64 in every mode.  Errors: NYS_ERR_ARG (1 <= ell <= n violated,
+ * bad operator), NYS_ERR_NOT_PSD (Omega0 rank deficient). */
+nys_status nys_sketch(const nys_operator* A, int64_t ell, uint64_t seed, const double* omega0,
+                      double* Omega_out, double* Y_out, int32_t prec, void* ws, size_t ws_bytes,
+                      void* stream);
+
+/* Factor (same algorithm, steps 4-9): nu = eps(||Y||_F) (spacing of the
+ * float64 number), Y_nu = Y + nu Omega, C = chol(Omega^T Y_nu), B = Y_nu C^{-1},
+ * [U, Sigma] = thin SVD of B, lam = max(0, Sigma^2 - nu), descending.
+ * Y is overwritten.  P: P->n, P->ell, P->U, P->ldu, P->dtype, P->lam set by
+ * the caller; P->nu is written (host).  A failed Cholesky is retried with
+ * nu <- 10 nu up to three times, then NYS_ERR_NOT_PSD.  Synchronises stream. */
+nys_status nys_factor(const double* Omega, double* Y, nys_precond* P, void* ws, size_t ws_bytes,
+                      void* stream);
+
+/* Z = (A + mu I) V for k columns (row-major n x k).  dtype NYS_F64 computes in
+ * float64 (float32 operator data is promoted exactly); NYS_F32 computes in
+ * float32.  Used for right-hand sides and true residuals. */
+nys_status nys_op_apply(const nys_operator* A, double mu, const void* V, int64_t k, int64_t ldv,
+                        void* Z, int64_t ldz, int32_t dtype, void* ws, size_t ws_bytes, void* stream);
+
+/* Z = P^{-1} R with eq. (NysPre):
+ *   P^{-1} = (lam_l + mu) U (Lambda + mu I)^{-1} U^T + (I - U U^T),
+ * for k columns (row-major n x k), all float64.  Requires lam_l + mu > 0. */
+nys_status nys_precond_apply(const nys_precond* P, double mu, const double* R, int64_t k,
+                             int64_t ldr, double* Z, int64_t ldz, void* ws, size_t ws_bytes,
+                             void* stream);
+
+/* Nystrom PCG (Section 5.2, algorithm "Nystrom PCG") for nmu*nrhs independent
+ * systems that share A and P: column c = m*nrhs + r solves
+ * (A + mu[m] I) x = B[:, r] (Section 5.2.2 block form read as independent
+ * columns; the mu grid reuses one preconditioner, which does not depend on mu).
+ * mu: host array of nmu values >= 0.  B: device float64 n x nrhs (ldb).
+ * X: device float64 n x (nmu*nrhs) (ldx); on entry the initial guesses, on exit
+ * the solutions.  info: host arrays of nmu*nrhs entries (may be NULL).
+ * Returns NYS_OK when every column met tol, NYS_NOT_CONVERGED when some hit
+ * the cap, NYS_ERR_BREAKDOWN when p^T v <= 0 occurred. */
+nys_status nys_pcg_solve(const nys_operator* A, const nys_precond* P, const double* mu, int64_t nmu,
+                         const double* B, int64_t nrhs, int64_t ldb, double* X, int64_t ldx,
+                         const nys_solve_opts* o, nys_solve_info* info, void* ws, size_t ws_bytes,
+                         void* stream);
+
+/* Ragged batch: nprob independent systems (A_k + mu_k I) x_k = b_k, each with
+ * its own operator and preconditioner, solved together (one iteration sweep
+ * advances every unfinished problem).  ops, Ps, mu, B, X: host arrays of
+ * nprob entries; B[k], X[k] are device float64 vectors of length ops[k].n.
+ * ws must hold nys_workspace_size_ragged(ops, Ps, nprob, prec) bytes.
+ * info arrays have nprob entries. */
+size_t nys_workspace_size_ragged(const nys_operator* ops, const nys_precond* Ps, int32_t nprob,
+                                 int32_t prec);
+nys_status nys_pcg_solve_ragged(const nys_operator* ops, const nys_precond* Ps, const double* mu,
+                                const double* const* B, double* const* X, int32_t nprob,
+                                const nys_solve_opts* o, nys_solve_info* info, void* ws,
+                                size_t ws_bytes, void* stream);
+
+/* Adjoint of x = (A + mu I)^{-1} b for a scalar loss L with gradient gx =
+ * dL/dx (the paper does not treat differentiation; these are the
+ * implicit-function formulas).  Solves (A + mu I) lambda = gx with the same
+ * preconditioner P, then
+ *   gb      (device, n)  = lambda                           = dL/db
+ *   *gmu    (host)       = -lambda^T x                      = dL/dmu
+ *   *gsigma (host, RBF)  = -lambda^T (dK/dsigma) x,  dK_ij/dsigma =
+ *                          K_ij |x_i - x_j|^2 / sigma^3     (implicit part of dL/dsigma)
+ *   gX      (device, XTX, rows x n, nullable) = -scale (X x lambda^T + X lambda x^T)
+ * x, gx: device float64 n.  gsigma / gX may be NULL.  Synchronises stream. */
+nys_status nys_pcg_backward(const nys_operator* A, const nys_precond* P, double mu, const double* x,
+                            const double* gx, double* gb, double* gmu, double* gsigma, double* gX,
+                            const nys_solve_opts* o, nys_solve_info* info, void* ws,
+                            size_t ws_bytes, void* stream);
+
+/* Rectangular RBF products for losses on held-out points (validation set Xv,
+ * nv x d; training points X of A, n x d):
+ *   transpose = 0:  out (nv) = K(Xv, X) v,        v (n)
+ *   transpose = 1:  out (n)  = K(Xv, X)^T v,      v (nv)
+ * and, when dsig_out != NULL (host), *dsig_out = u^T (dK(Xv,X)/dsigma) w for
+ * u = v (nv) and w = wvec (n).  All float64. */
+nys_status nys_rbf_cross(const nys_operator* A, const void* Xv, int64_t nv, int64_t ldxv,
+                         int32_t transpose, const double* v, double* out, const double* wvec,
+                         double* dsig_out, void* ws, size_t ws_bytes, void* stream);
+
+/* Message for the last non-OK status returned on this thread. */
+const char* nys_last_error(void);
+
+/* Library version string. */
+const char* nys_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NYSPCG_H */

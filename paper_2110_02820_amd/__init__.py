@@ -1,0 +1,354 @@
+"""Python binding of libnyspcg (randomized Nystrom PCG on MI355X / gfx950).
+
+Argument marshalling only: every numerical step runs in the HIP kernels of
+``csrc/`` behind the C ABI declared in ``include/nyspcg.h``.  PyTorch supplies
+device memory and the current HIP stream.  The functions carry the C names.
+
+If the shared library has not been built, every call raises ``RuntimeError``;
+there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libnyspcg.so")
+
+NYS_OK, NYS_NOT_CONVERGED = 0, 1
+NYS_ERR_ARG, NYS_ERR_NOT_PSD, NYS_ERR_BREAKDOWN, NYS_ERR_DEVICE, NYS_ERR_WORKSPACE = -1, -2, -3, -4, -5
+NYS_F64, NYS_F32 = 0, 1
+NYS_PREC_FP64, NYS_PREC_FP32, NYS_PREC_FP32_REFINE64, NYS_PREC_BF16X3_REFINE64 = 0, 1, 2, 3
+NYS_OP_DENSE, NYS_OP_XTX, NYS_OP_RBF = 0, 1, 2
+
+EXPORTED = ["nys_workspace_size", "nys_gaussian", "nys_sketch", "nys_factor", "nys_op_apply",
+            "nys_precond_apply", "nys_pcg_solve", "nys_workspace_size_ragged", "nys_pcg_solve_ragged",
+            "nys_pcg_backward", "nys_rbf_cross", "nys_last_error", "nys_version"]
+
+
+class NysError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__("nyspcg status %d: %s" % (status, msg))
+        self.status = status
+
+
+class _Operator(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("dtype", ctypes.c_int32), ("n", ctypes.c_int64),
+                ("data", ctypes.c_void_p), ("rows", ctypes.c_int64), ("cols", ctypes.c_int64),
+                ("ld", ctypes.c_int64), ("sigma", ctypes.c_double), ("scale", ctypes.c_double)]
+
+
+class _Precond(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("ell", ctypes.c_int64), ("U", ctypes.c_void_p),
+                ("ldu", ctypes.c_int64), ("dtype", ctypes.c_int32), ("pad_", ctypes.c_int32),
+                ("lam", ctypes.c_void_p), ("nu", ctypes.c_double)]
+
+
+class _Opts(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("maxit", ctypes.c_int32), ("prec", ctypes.c_int32),
+                ("max_refine", ctypes.c_int32), ("check_every", ctypes.c_int32),
+                ("inner_tol", ctypes.c_double)]
+
+
+class _Info(ctypes.Structure):
+    _fields_ = [("iters", ctypes.POINTER(ctypes.c_int32)), ("relres", ctypes.POINTER(ctypes.c_double)),
+                ("status", ctypes.POINTER(ctypes.c_int32)), ("refine_steps", ctypes.c_int32),
+                ("total_iters", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libnyspcg.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libnyspcg.so is not built: run __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i64, i32, dbl, sz = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_double, ctypes.c_size_t
+        P = ctypes.POINTER
+        L.nys_workspace_size.restype = sz
+        L.nys_workspace_size.argtypes = [P(_Operator), i64, i64, i32]
+        L.nys_gaussian.argtypes = [ctypes.c_uint64, i64, i64, vp, i64, vp]
+        L.nys_sketch.argtypes = [P(_Operator), i64, ctypes.c_uint64, vp, vp, vp, i32, vp, sz, vp]
+        L.nys_factor.argtypes = [vp, vp, P(_Precond), vp, sz, vp]
+        L.nys_op_apply.argtypes = [P(_Operator), dbl, vp, i64, i64, vp, i64, i32, vp, sz, vp]
+        L.nys_precond_apply.argtypes = [P(_Precond), dbl, vp, i64, i64, vp, i64, vp, sz, vp]
+        L.nys_pcg_solve.argtypes = [P(_Operator), P(_Precond), P(dbl), i64, vp, i64, i64, vp, i64,
+                                    P(_Opts), P(_Info), vp, sz, vp]
+        L.nys_workspace_size_ragged.restype = sz
+        L.nys_workspace_size_ragged.argtypes = [P(_Operator), P(_Precond), i32, i32]
+        L.nys_pcg_solve_ragged.argtypes = [P(_Operator), P(_Precond), P(dbl), P(vp), P(vp), i32,
+                                           P(_Opts), P(_Info), vp, sz, vp]
+        L.nys_pcg_backward.argtypes = [P(_Operator), P(_Precond), dbl, vp, vp, vp, P(dbl), P(dbl), vp,
+                                       P(_Opts), P(_Info), vp, sz, vp]
+        L.nys_rbf_cross.argtypes = [P(_Operator), vp, i64, i64, i32, vp, vp, vp, P(dbl), vp, sz, vp]
+        for f in ("nys_gaussian", "nys_sketch", "nys_factor", "nys_op_apply", "nys_precond_apply",
+                  "nys_pcg_solve", "nys_pcg_solve_ragged", "nys_pcg_backward", "nys_rbf_cross"):
+            getattr(L, f).restype = ctypes.c_int
+        L.nys_last_error.restype = ctypes.c_char_p
+        L.nys_version.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def _check(status: int, allow_not_converged: bool = False) -> int:
+    if status == NYS_OK or (allow_not_converged and status == NYS_NOT_CONVERGED):
+        return status
+    raise NysError(status, lib().nys_last_error().decode())
+
+
+def _stream() -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t: Optional[torch.Tensor]) -> Optional[int]:
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("device tensor expected")
+    return t.data_ptr()
+
+
+def _dt(t: torch.Tensor) -> int:
+    if t.dtype == torch.float64:
+        return NYS_F64
+    if t.dtype == torch.float32:
+        return NYS_F32
+    raise ValueError("float32 or float64 data expected")
+
+
+# --------------------------------------------------------------------------- operators
+
+@dataclass
+class Operator:
+    """A (Section 1.1) as a dense matrix, ridge data X (A = scale X^T X) or RBF points."""
+    kind: int
+    data: torch.Tensor
+    n: int
+    sigma: float = 0.0
+    scale: float = 1.0
+
+    @staticmethod
+    def dense(A: torch.Tensor) -> "Operator":
+        A = A.contiguous()
+        return Operator(NYS_OP_DENSE, A, A.shape[0])
+
+    @staticmethod
+    def xtx(X: torch.Tensor, scale: float = 1.0) -> "Operator":
+        X = X.contiguous()
+        return Operator(NYS_OP_XTX, X, X.shape[1], scale=scale)
+
+    @staticmethod
+    def rbf(X: torch.Tensor, sigma: float, scale: float = 1.0) -> "Operator":
+        X = X.contiguous()
+        return Operator(NYS_OP_RBF, X, X.shape[0], sigma=float(sigma), scale=scale)
+
+    def c(self) -> _Operator:
+        d = self.data
+        return _Operator(self.kind, _dt(d), self.n, _ptr(d), d.shape[0], d.shape[1], d.stride(0),
+                         self.sigma, self.scale)
+
+
+@dataclass
+class Precond:
+    """Factored Nystrom approximation U diag(lam) U^T (mu-independent)."""
+    U: torch.Tensor
+    lam: torch.Tensor
+    nu: float = 0.0
+
+    def c(self) -> _Precond:
+        return _Precond(self.U.shape[0], self.U.shape[1], _ptr(self.U), self.U.stride(0), _dt(self.U), 0,
+                        _ptr(self.lam), self.nu)
+
+
+def workspace(op: Operator, ell: int, ncols: int = 1, prec: int = NYS_PREC_FP64) -> torch.Tensor:
+    nb = lib().nys_workspace_size(ctypes.byref(op.c()), ell, ncols, prec)
+    if nb == 0:
+        raise NysError(NYS_ERR_ARG, "invalid operator for workspace sizing")
+    return torch.empty(nb, dtype=torch.uint8, device=op.data.device)
+
+
+def _ws(op, ell, ncols, prec, ws):
+    return ws if ws is not None else workspace(op, ell, ncols, prec)
+
+
+def _ws_shape(n: int, ell: int, ncols: int, device) -> torch.Tensor:
+    """Workspace for calls that only depend on (n, ell): size it with a dense
+    descriptor whose data pointer is a non-null placeholder (never read)."""
+    fake = _Operator(NYS_OP_DENSE, NYS_F64, n, 1, n, n, n, 0.0, 1.0)
+    nb = lib().nys_workspace_size(ctypes.byref(fake), ell, ncols, NYS_PREC_FP64)
+    return torch.empty(nb, dtype=torch.uint8, device=device)
+
+
+# --------------------------------------------------------------------------- entry points
+
+def nys_gaussian(seed: int, n: int, ell: int, device="cuda") -> torch.Tensor:
+    out = torch.empty(n, ell, dtype=torch.float64, device=device)
+    _check(lib().nys_gaussian(seed, n, ell, _ptr(out), ell, _stream()))
+    return out
+
+
+def nys_sketch(op: Operator, ell: int, seed: int = 0, omega0: Optional[torch.Tensor] = None,
+               prec: int = NYS_PREC_FP64, ws: Optional[torch.Tensor] = None):
+    dev = op.data.device
+    Om = torch.empty(op.n, ell, dtype=torch.float64, device=dev)
+    Y = torch.empty(op.n, ell, dtype=torch.float64, device=dev)
+    if omega0 is not None:
+        omega0 = omega0.to(device=dev, dtype=torch.float64).contiguous()
+    w = _ws(op, ell, 1, prec, ws)
+    _check(lib().nys_sketch(ctypes.byref(op.c()), ell, seed, _ptr(omega0), _ptr(Om), _ptr(Y), prec,
+                            _ptr(w), w.numel(), _stream()))
+    return Om, Y
+
+
+def nys_factor(Omega: torch.Tensor, Y: torch.Tensor, dtype=torch.float64,
+               ws: Optional[torch.Tensor] = None, op: Optional[Operator] = None) -> Precond:
+    n, ell = Y.shape
+    U = torch.empty(n, ell, dtype=dtype, device=Y.device)
+    lam = torch.empty(ell, dtype=torch.float64, device=Y.device)
+    p = _Precond(n, ell, _ptr(U), ell, NYS_F64 if dtype == torch.float64 else NYS_F32, 0, _ptr(lam), 0.0)
+    if ws is None:
+        ws = _ws_shape(n, ell, 1, Y.device) if op is None else workspace(op, ell)
+    _check(lib().nys_factor(_ptr(Omega), _ptr(Y), ctypes.byref(p), _ptr(ws), ws.numel(), _stream()))
+    return Precond(U, lam, p.nu)
+
+
+def nys_op_apply(op: Operator, mu: float, V: torch.Tensor, ws: Optional[torch.Tensor] = None) -> torch.Tensor:
+    V2 = V.reshape(V.shape[0], -1).contiguous()
+    k = V2.shape[1]
+    Z = torch.empty_like(V2)
+    w = _ws(op, 1, k, NYS_PREC_FP64, ws)
+    _check(lib().nys_op_apply(ctypes.byref(op.c()), float(mu), _ptr(V2), k, k, _ptr(Z), k, _dt(V2), _ptr(w),
+                              w.numel(), _stream()))
+    return Z.reshape(V.shape)
+
+
+def nys_precond_apply(P: Precond, mu: float, R: torch.Tensor, ws: Optional[torch.Tensor] = None) -> torch.Tensor:
+    R2 = R.reshape(R.shape[0], -1).contiguous().to(torch.float64)
+    k = R2.shape[1]
+    Z = torch.empty_like(R2)
+    if ws is None:
+        ws = _ws_shape(P.U.shape[0], P.U.shape[1], k, R.device)
+    _check(lib().nys_precond_apply(ctypes.byref(P.c()), float(mu), _ptr(R2), k, k, _ptr(Z), k, _ptr(ws),
+                                   ws.numel(), _stream()))
+    return Z.reshape(R.shape)
+
+
+@dataclass
+class SolveInfo:
+    iters: list
+    relres: list
+    status: list
+    refine_steps: int
+    total_iters: int
+    code: int
+
+
+def _opts(tol, maxit, prec, max_refine, check_every, inner_tol):
+    return _Opts(tol, maxit, prec, max_refine, check_every, inner_tol)
+
+
+def nys_pcg_solve(op: Operator, P: Precond, mu, B: torch.Tensor, X0: Optional[torch.Tensor] = None,
+                  tol: float = 1e-10, maxit: int = 500, prec: int = NYS_PREC_FP64, max_refine: int = 10,
+                  check_every: int = 8, inner_tol: float = 1e-4, ws: Optional[torch.Tensor] = None,
+                  raise_on_not_converged: bool = False):
+    """Solve (A + mu_m I) X[:, m*nrhs + r] = B[:, r] for every mu_m.  Returns (X, SolveInfo)."""
+    mus = [float(m) for m in (mu if isinstance(mu, (list, tuple)) else [mu])]
+    B2 = B.reshape(B.shape[0], -1).contiguous().to(torch.float64)
+    nrhs = B2.shape[1]
+    k = len(mus) * nrhs
+    if X0 is None:
+        X = torch.zeros(B2.shape[0], k, dtype=torch.float64, device=B.device)
+    else:
+        X = X0.reshape(B2.shape[0], k).to(torch.float64).contiguous().clone()
+    w = _ws(op, P.U.shape[1], k, prec, ws)
+    it = (ctypes.c_int32 * k)()
+    rr = (ctypes.c_double * k)()
+    st = (ctypes.c_int32 * k)()
+    info = _Info(it, rr, st, 0, 0)
+    mu_arr = (ctypes.c_double * len(mus))(*mus)
+    o = _opts(tol, maxit, prec, max_refine, check_every, inner_tol)
+    code = lib().nys_pcg_solve(ctypes.byref(op.c()), ctypes.byref(P.c()), mu_arr, len(mus), _ptr(B2), nrhs,
+                               nrhs, _ptr(X), k, ctypes.byref(o), ctypes.byref(info), _ptr(w), w.numel(),
+                               _stream())
+    _check(code, allow_not_converged=not raise_on_not_converged)
+    si = SolveInfo(list(it), list(rr), list(st), info.refine_steps, info.total_iters, code)
+    if B.dim() == 1 and k == 1:
+        X = X.reshape(-1)
+    return X, si
+
+
+def nys_pcg_solve_ragged(ops: Sequence[Operator], Ps: Sequence[Precond], mus: Sequence[float],
+                         Bs: Sequence[torch.Tensor], tol: float = 1e-10, maxit: int = 500,
+                         prec: int = NYS_PREC_FP64, max_refine: int = 10, check_every: int = 8,
+                         inner_tol: float = 1e-4, ws: Optional[torch.Tensor] = None):
+    npb = len(ops)
+    cops = (_Operator * npb)(*[o.c() for o in ops])
+    cps = (_Precond * npb)(*[p.c() for p in Ps])
+    mu_arr = (ctypes.c_double * npb)(*[float(m) for m in mus])
+    Bs = [b.reshape(-1).contiguous().to(torch.float64) for b in Bs]
+    Xs = [torch.zeros_like(b) for b in Bs]
+    barr = (ctypes.c_void_p * npb)(*[_ptr(b) for b in Bs])
+    xarr = (ctypes.c_void_p * npb)(*[_ptr(x) for x in Xs])
+    if ws is None:
+        nb = lib().nys_workspace_size_ragged(cops, cps, npb, prec)
+        ws = torch.empty(nb, dtype=torch.uint8, device=Bs[0].device)
+    it = (ctypes.c_int32 * npb)()
+    rr = (ctypes.c_double * npb)()
+    st = (ctypes.c_int32 * npb)()
+    info = _Info(it, rr, st, 0, 0)
+    o = _opts(tol, maxit, prec, max_refine, check_every, inner_tol)
+    code = lib().nys_pcg_solve_ragged(cops, cps, mu_arr, barr, xarr, npb, ctypes.byref(o), ctypes.byref(info),
+                                      _ptr(ws), ws.numel(), _stream())
+    _check(code, allow_not_converged=True)
+    return Xs, SolveInfo(list(it), list(rr), list(st), info.refine_steps, info.total_iters, code)
+
+
+def nys_pcg_backward(op: Operator, P: Precond, mu: float, x: torch.Tensor, gx: torch.Tensor,
+                     want_sigma: bool = False, want_X: bool = False, tol: float = 1e-10, maxit: int = 500,
+                     prec: int = NYS_PREC_FP64, ws: Optional[torch.Tensor] = None):
+    """Adjoint solve with the same preconditioner.  Returns dict(gb, gmu, gsigma, gX, info)."""
+    x = x.reshape(-1).contiguous().to(torch.float64)
+    gx = gx.reshape(-1).contiguous().to(torch.float64)
+    gb = torch.zeros_like(x)
+    gX = torch.empty(op.data.shape[0], op.n, dtype=torch.float64, device=x.device) if want_X else None
+    gmu = ctypes.c_double(0.0)
+    gsig = ctypes.c_double(0.0)
+    w = _ws(op, P.U.shape[1], 1, prec, ws)
+    it = (ctypes.c_int32 * 1)()
+    rr = (ctypes.c_double * 1)()
+    st = (ctypes.c_int32 * 1)()
+    info = _Info(it, rr, st, 0, 0)
+    o = _opts(tol, maxit, prec, 10, 8, 1e-4)
+    code = lib().nys_pcg_backward(ctypes.byref(op.c()), ctypes.byref(P.c()), float(mu), _ptr(x), _ptr(gx),
+                                  _ptr(gb), ctypes.byref(gmu), ctypes.byref(gsig) if want_sigma else None,
+                                  _ptr(gX), ctypes.byref(o), ctypes.byref(info), _ptr(w), w.numel(), _stream())
+    _check(code, allow_not_converged=True)
+    return dict(gb=gb, gmu=gmu.value, gsigma=gsig.value if want_sigma else None, gX=gX,
+                info=SolveInfo(list(it), list(rr), list(st), info.refine_steps, info.total_iters, code))
+
+
+def nys_rbf_cross(op: Operator, Xv: torch.Tensor, v: torch.Tensor, transpose: bool = False,
+                  wvec: Optional[torch.Tensor] = None, ws: Optional[torch.Tensor] = None):
+    """K(Xv, X) v (transpose=False) or K(Xv, X)^T v; with wvec also v^T (dK(Xv,X)/dsigma) wvec."""
+    Xv = Xv.contiguous()
+    v = v.reshape(-1).contiguous().to(torch.float64)
+    nv = Xv.shape[0]
+    out = torch.empty(op.n if transpose else nv, dtype=torch.float64, device=v.device)
+    dsig = ctypes.c_double(0.0)
+    if ws is None:
+        ws = torch.empty(8 * 1024 * max(op.n, nv) + 16 * nv + 8192, dtype=torch.uint8, device=v.device)
+    wv = None if wvec is None else wvec.reshape(-1).contiguous().to(torch.float64)
+    _check(lib().nys_rbf_cross(ctypes.byref(op.c()), _ptr(Xv), nv, Xv.stride(0), 1 if transpose else 0, _ptr(v),
+                               _ptr(out), _ptr(wv), ctypes.byref(dsig) if wv is not None else None, _ptr(ws),
+                               ws.numel(), _stream()))
+    return (out, dsig.value) if wv is not None else out
+
+
+from .autograd import NystromSolve, nystrom_solve  # noqa: E402,F401

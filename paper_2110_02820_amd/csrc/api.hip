@@ -1,0 +1,978 @@
+// C ABI of the Nystrom PCG library: argument checks, workspace layout and the
+// host-side ordering of the device kernels.  Every numerical step runs in the
+// HIP kernels of this directory; the host only enqueues work and reads flags.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <vector>
+
+#include "common.hpp"
+#include "dense_small.hpp"
+#include "gemm.hpp"
+#include "operators.hpp"
+#include "pcg.hpp"
+#include "rng.hpp"
+
+namespace nys {
+
+static thread_local char g_err[1024] = "";
+
+void set_error(const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+}
+
+int num_cus() {
+  static int cached[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+  if (!cached[dev]) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v <= 0)
+      v = 256;
+    cached[dev] = v;
+  }
+  return cached[dev];
+}
+
+namespace {
+
+constexpr int kMaxGroups = 512;  // upper bound on partial-sum groups
+constexpr int kMaxSweeps = 40;   // Jacobi sweep cap
+constexpr int64_t kMaxCols = 256;
+
+int groups() {
+  const int g = 2 * num_cus();
+  return g < kMaxGroups ? g : kMaxGroups;
+}
+
+// ---------------------------------------------------------------- checks
+
+nys_status check_op(const nys_operator* A, OpDesc& o) {
+  NYS_ARG(A != nullptr, "operator is NULL");
+  NYS_ARG(A->kind >= NYS_OP_DENSE && A->kind <= NYS_OP_RBF, "unknown operator kind %d", A->kind);
+  NYS_ARG(A->dtype == NYS_F64 || A->dtype == NYS_F32, "operator dtype must be NYS_F64 or NYS_F32");
+  NYS_ARG(A->n >= 1, "operator dimension n = %lld < 1", (long long)A->n);
+  NYS_ARG(A->data != nullptr, "operator data is NULL");
+  NYS_ARG(A->ld >= A->cols && A->cols >= 1 && A->rows >= 1, "operator shape/ld invalid");
+  NYS_ARG(std::isfinite(A->scale) && A->scale > 0.0, "operator scale must be finite and > 0");
+  if (A->kind == NYS_OP_DENSE) NYS_ARG(A->rows == A->n && A->cols == A->n, "dense operator must be n x n");
+  if (A->kind == NYS_OP_XTX) NYS_ARG(A->cols == A->n, "X^T X operator: cols must equal n");
+  if (A->kind == NYS_OP_RBF) {
+    NYS_ARG(A->rows == A->n, "RBF operator: rows must equal n");
+    NYS_ARG(std::isfinite(A->sigma) && A->sigma > 0.0, "RBF operator: sigma must be > 0");
+    NYS_ARG(A->cols <= 64, "RBF operator: d must be <= 64");
+  }
+  o.kind = A->kind;
+  o.dtype = A->dtype;
+  o.n = A->n;
+  o.data = A->data;
+  o.rows = A->rows;
+  o.cols = A->cols;
+  o.ld = A->ld;
+  o.sigma = A->sigma;
+  o.scale = A->scale;
+  o.skip = nullptr;
+  return NYS_OK;
+}
+
+nys_status check_prec(const nys_precond* P, PrecDesc& d) {
+  NYS_ARG(P != nullptr, "preconditioner is NULL");
+  NYS_ARG(P->n >= 1 && P->ell >= 1 && P->ell <= P->n, "preconditioner needs 1 <= ell <= n");
+  NYS_ARG(P->U != nullptr && P->lam != nullptr, "preconditioner U / lam is NULL");
+  NYS_ARG(P->ldu >= P->ell, "preconditioner ldu < ell");
+  NYS_ARG(P->dtype == NYS_F64 || P->dtype == NYS_F32, "preconditioner dtype invalid");
+  NYS_ARG(P->ell <= 2048, "preconditioner rank > 2048 not supported");
+  d.n = P->n;
+  d.ell = P->ell;
+  d.U = P->U;
+  d.ldu = P->ldu;
+  d.dtype = P->dtype;
+  d.lam = P->lam;
+  return NYS_OK;
+}
+
+hipStream_t S(void* stream) { return static_cast<hipStream_t>(stream); }
+
+// ---------------------------------------------------------------- layouts
+
+struct Core {  // l x l float64 work shared by sketch and factor
+  double *G, *L, *Linv, *Dinv, *T, *eig, *gscr, *nu, *part, *sig2;
+  int *info, *flags, *sweeps, *bar_err;
+  unsigned* bar;
+  size_t gscr_elems;
+};
+
+void carve_core(Arena& a, int64_t l, Core& c) {
+  c.G = a.take<double>(l * l);
+  c.L = a.take<double>(l * l);
+  c.Linv = a.take<double>(l * l);
+  c.T = a.take<double>(l * l);
+  c.Dinv = a.take<double>(chol_ws_doubles(l));
+  c.eig = a.take<double>(eig_ws_doubles(l));
+  c.gscr_elems = gemm_scratch_elems(l, l);
+  c.gscr = a.take<double>(c.gscr_elems);
+  c.nu = a.take<double>(1);
+  c.part = a.take<double>(frob_partials());
+  c.sig2 = a.take<double>(l);
+  c.info = a.take<int>(1);
+  c.flags = a.take<int>(kMaxSweeps);
+  c.sweeps = a.take<int>(1);
+  c.bar_err = a.take<int>(1);
+  c.bar = a.take<unsigned>(1);
+}
+
+struct SketchWs {
+  Core c;
+  double* opscr;
+  size_t opscr_elems;
+  float *Om32, *T32, *Y32, *f32scr;
+  size_t f32scr_elems;
+};
+
+bool sketch_f32(const OpDesc& op, int prec) {
+  return prec != NYS_PREC_FP64 && op.kind == NYS_OP_XTX && op.dtype == NYS_F32;
+}
+
+void carve_sketch(Arena& a, const OpDesc& op, int64_t l, int prec, SketchWs& w) {
+  carve_core(a, l, w.c);
+  w.opscr_elems = op_scratch_elems(op, l);
+  w.opscr = a.take<double>(w.opscr_elems);
+  w.Om32 = w.T32 = w.Y32 = w.f32scr = nullptr;
+  w.f32scr_elems = 0;
+  if (sketch_f32(op, prec)) {
+    w.Om32 = a.take<float>(op.n * l);
+    w.T32 = a.take<float>(op.rows * l);
+    w.Y32 = a.take<float>(op.n * l);
+    w.f32scr_elems = gemm_scratch_elems(op.n, l);
+    w.f32scr = a.take<float>(w.f32scr_elems);
+  }
+}
+
+struct FactorWs {
+  Core c;
+  double* B;
+};
+
+void carve_factor(Arena& a, int64_t n, int64_t l, FactorWs& w) {
+  carve_core(a, l, w.c);
+  w.B = a.take<double>(n * l);
+}
+
+template <typename T>
+struct PcgBufs {
+  T *V, *R, *Z, *P, *X, *B;
+  double *pb, *prr, *ppv, *prz;
+  CgScalars sc;
+  double *apart, *Cs, *Ct;
+  size_t apart_elems;
+  T* opscr;
+  size_t opscr_elems;
+};
+
+template <typename T>
+void carve_pcg(Arena& a, const OpDesc& op, int64_t l, int64_t k, PcgBufs<T>& b) {
+  const int64_t n = op.n;
+  b.V = a.take<T>(n * k);
+  b.R = a.take<T>(n * k);
+  b.Z = a.take<T>(n * k);
+  b.P = a.take<T>(n * k);
+  b.X = a.take<T>(n * k);
+  b.B = a.take<T>(n * k);
+  b.pb = a.take<double>(kMaxGroups * k);
+  b.prr = a.take<double>(kMaxGroups * k);
+  b.ppv = a.take<double>(kMaxGroups * k);
+  b.prz = a.take<double>(kMaxGroups * k);
+  b.sc.rz = a.take<double>(2 * k);
+  b.sc.bnorm2 = a.take<double>(k);
+  b.sc.rnorm2 = a.take<double>(k);
+  b.sc.done = a.take<int>(k);
+  b.sc.iters = a.take<int>(k);
+  b.sc.status = a.take<int>(k);
+  b.sc.alldone = a.take<int>(1);
+  b.apart_elems = precond_part_elems(n, l, k);
+  b.apart = a.take<double>(b.apart_elems);
+  b.Cs = a.take<double>(l * k);
+  b.Ct = a.take<double>(l * k);
+  b.opscr_elems = op_scratch_elems(op, k);
+  b.opscr = a.take<T>(b.opscr_elems);
+}
+
+struct SolveWs {
+  PcgBufs<double> d;
+  PcgBufs<float> f;
+  double *mu, *R64, *V64, *X64, *B64, *dots;
+  bool has_f;
+};
+
+void carve_solve(Arena& a, const OpDesc& op, int64_t l, int64_t k, int prec, SolveWs& w) {
+  const int64_t n = op.n;
+  w.mu = a.take<double>(k);
+  w.dots = a.take<double>(kMaxGroups * k + 2 * k);
+  w.R64 = a.take<double>(n * k);
+  w.V64 = a.take<double>(n * k);
+  w.X64 = a.take<double>(n * k);
+  w.B64 = a.take<double>(n * k);
+  carve_pcg<double>(a, op, l, k, w.d);
+  w.has_f = prec != NYS_PREC_FP64;
+  if (w.has_f) carve_pcg<float>(a, op, l, k, w.f);
+}
+
+// ---------------------------------------------------------------- small kernels
+
+template <typename TS, typename TD>
+__global__ void gather_cols(int64_t n, int64_t k, const TS* __restrict__ src, int64_t lds,
+                            int64_t nsrc_cols, TD* __restrict__ dst, int64_t ldd) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= n * k) return;
+  const int64_t i = idx / k, c = idx % k;
+  dst[i * ldd + c] = TD(src[i * lds + (c % nsrc_cols)]);
+}
+
+// R = B - V and per-column partial ||R||^2, ||B||^2 (one group per block of rows)
+__global__ void residual_norms(int64_t n, int64_t k, const double* __restrict__ B,
+                               const double* __restrict__ V, double* __restrict__ R,
+                               double* __restrict__ part) {
+  // part[g][c] = ||R_c||^2 partial, part[G + g][c] = ||B_c||^2 partial; k <= 256
+  __shared__ double sh[256];
+  const int64_t rows = cdiv(n, gridDim.x);
+  const int64_t r0 = (int64_t)blockIdx.x * rows;
+  const int64_t r1 = r0 + rows < n ? r0 + rows : n;
+  for (int64_t c0 = 0; c0 < k; c0 += 1) {
+    double sr = 0.0, sb = 0.0;
+    for (int64_t i = r0 + threadIdx.x; i < r1; i += blockDim.x) {
+      const double b = B[i * k + c0];
+      const double r = b - V[i * k + c0];
+      R[i * k + c0] = r;
+      sr += r * r;
+      sb += b * b;
+    }
+    sr = block_sum(sr, sh);
+    sb = block_sum(sb, sh);
+    if (threadIdx.x == 0) {
+      part[(int64_t)blockIdx.x * k + c0] = sr;
+      part[((int64_t)gridDim.x + blockIdx.x) * k + c0] = sb;
+    }
+  }
+}
+
+__global__ void fill_values(double* __restrict__ dst, int64_t count, double v0, double v1,
+                            double v2, double v3) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) dst[i] = (i == 0) ? v0 : (i == 1) ? v1 : (i == 2) ? v2 : v3;
+}
+
+template <typename T>
+__global__ void zero_fill(T* __restrict__ p, int64_t count) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) p[i] = T(0);
+}
+
+template <typename TS>
+__global__ void add_to(double* __restrict__ dst, const TS* __restrict__ src, int64_t count) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) dst[i] += double(src[i]);
+}
+
+__global__ void dot_partial(const double* __restrict__ a, const double* __restrict__ b, int64_t n,
+                            double* __restrict__ part) {
+  __shared__ double sh[16];
+  double s = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    s += a[i] * b[i];
+  s = block_sum(s, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+// gX[r][j] = -scale (t1[r] lam[j] + t2[r] x[j])
+__global__ void outer2(int64_t m, int64_t n, double scale, const double* __restrict__ t1,
+                       const double* __restrict__ lam, const double* __restrict__ t2,
+                       const double* __restrict__ x, double* __restrict__ gX) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= m * n) return;
+  const int64_t r = idx / n, j = idx % n;
+  gX[idx] = -scale * (t1[r] * lam[j] + t2[r] * x[j]);
+}
+
+template <typename TS>
+__global__ void gemv_rows(const TS* __restrict__ X, int64_t m, int64_t n, int64_t ld,
+                          const double* __restrict__ v, double* __restrict__ out) {
+  const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (row >= m) return;
+  double s = 0.0;
+  for (int64_t j = lane; j < n; j += 64) s += double(X[row * ld + j]) * v[j];
+  s = wave_sum(s);
+  if (lane == 0) out[row] = s;
+}
+
+unsigned nblk(int64_t count) { return (unsigned)(count > 0 ? cdiv(count, 256) : 1); }
+
+template <typename T>
+nys_status zero(T* p, int64_t count, hipStream_t s) {
+  if (count <= 0) return NYS_OK;
+  hipLaunchKernelGGL(zero_fill<T>, dim3(nblk(count)), dim3(256), 0, s, p, count);
+  NYS_CHECK_LAUNCH();
+  return NYS_OK;
+}
+
+nys_status set_mu(double* mu_dev, const double* mu, int64_t nmu, hipStream_t s) {
+  for (int64_t i = 0; i < nmu; i += 4) {
+    double v[4] = {0, 0, 0, 0};
+    for (int j = 0; j < 4 && i + j < nmu; ++j) v[j] = mu[i + j];
+    const int64_t cnt = (nmu - i) < 4 ? (nmu - i) : 4;
+    hipLaunchKernelGGL(fill_values, dim3(1), dim3(64), 0, s, mu_dev + i, cnt, v[0], v[1], v[2], v[3]);
+    NYS_CHECK_LAUNCH();
+  }
+  return NYS_OK;
+}
+
+// ---------------------------------------------------------------- CholQR
+
+// Omega <- Omega C^{-1} with C^T C = Omega^T Omega, using tmp (n x l); twice.
+nys_status cholqr2(double* Om, double* tmp, int64_t n, int64_t l, Core& c, int* info_host,
+                   hipStream_t s) {
+  double* src = Om;
+  double* dst = tmp;
+  for (int pass = 0; pass < 2; ++pass) {
+    NYS_TRY((gemm<double, double, double>(true, false, l, l, n, 1.0, src, l, src, l, 0.0, c.G, l,
+                                          c.gscr, c.gscr_elems, s)));
+    NYS_TRY(cholesky(c.G, l, c.L, c.Dinv, c.info, c.bar, c.bar_err, s));
+    NYS_HIP(hipMemcpyAsync(&info_host[pass], c.info, sizeof(int), hipMemcpyDeviceToHost, s));
+    NYS_TRY(tri_inverse(c.L, l, c.Dinv, c.Linv, s));
+    NYS_TRY((gemm<double, double, double>(false, true, n, l, l, 1.0, src, l, c.Linv, l, 0.0, dst, l,
+                                          c.gscr, c.gscr_elems, s)));
+    double* t = src;
+    src = dst;
+    dst = t;
+  }
+  return NYS_OK;  // after two passes the result is back in Om
+}
+
+// ---------------------------------------------------------------- PCG core
+
+template <typename T>
+nys_status matvec(const OpDesc& op, const T* P, int64_t k, const double* mu_dev, int64_t nrhs,
+                  double mu_host, T* V, PcgBufs<T>& b, hipStream_t s);
+
+template <>
+nys_status matvec<double>(const OpDesc& op, const double* P, int64_t k, const double* mu_dev,
+                          int64_t nrhs, double mu_host, double* V, PcgBufs<double>& b,
+                          hipStream_t s) {
+  if (k == 1 && (op.kind == NYS_OP_XTX || op.kind == NYS_OP_DENSE))
+    return op_matvec<double>(op, P, mu_host, V, b.opscr, b.opscr_elems, s);
+  return op_apply_f64(op, P, k, k, mu_dev, nrhs, V, k, b.opscr, b.opscr_elems, s);
+}
+
+template <>
+nys_status matvec<float>(const OpDesc& op, const float* P, int64_t k, const double* mu_dev,
+                         int64_t nrhs, double mu_host, float* V, PcgBufs<float>& b, hipStream_t s) {
+  (void)mu_dev;
+  (void)nrhs;
+  if (k == 1 && (op.kind == NYS_OP_XTX || op.kind == NYS_OP_DENSE))
+    return op_matvec<float>(op, P, (float)mu_host, V, b.opscr, b.opscr_elems, s);
+  set_error("float32 arithmetic is available for single-column X^T X and dense operators");
+  return NYS_ERR_ARG;
+}
+
+struct PcgResult {
+  std::vector<int> iters, status;
+  std::vector<double> rnorm2, bnorm2;
+  int sweeps = 0;
+};
+
+// Left-preconditioned CG (algorithm "Nystrom PCG") on k columns.  B (n x k,
+// ld = k) and X (n x k, ld = k, in: x0 unless x0_zero) are arrays of type T.
+template <typename T>
+nys_status pcg_run(const OpDesc& op0, const PrecDesc& P, int64_t k, int64_t nrhs,
+                   const double* mu_dev, double mu_host, const T* B, T* X, bool x0_zero, double tol,
+                   int maxit, int check_every, PcgBufs<T>& b, PcgResult& res, hipStream_t s) {
+  const int64_t n = op0.n;
+  const int ng = groups();
+  const bool f32 = sizeof(T) == 4;
+  OpDesc op = op0;
+  op.skip = nullptr;
+  if (x0_zero) {
+    NYS_TRY(zero<T>(X, n * k, s));
+    NYS_TRY(zero<T>(b.V, n * k, s));
+  } else {
+    NYS_TRY(matvec<T>(op, X, k, mu_dev, nrhs, mu_host, b.V, b, s));
+  }
+  NYS_TRY(cg_kernels_init<T>(n, k, B, k, b.V, b.R, b.pb, b.prr, ng, s));
+  NYS_TRY(precond_apply_dev(P, mu_dev, nrhs, b.R, b.Z, k, f32, nullptr, nullptr, b.apart,
+                            b.apart_elems, b.Cs, b.Ct, s));
+  NYS_TRY(cg_kernels_init2<T>(n, k, b.R, b.Z, b.P, b.pb, b.prr, b.prz, tol, b.sc, ng, s));
+  op.skip = b.sc.alldone;
+  int it = 0;
+  int alldone_h = 0;
+  NYS_HIP(hipMemcpyAsync(&alldone_h, b.sc.alldone, sizeof(int), hipMemcpyDeviceToHost, s));
+  NYS_HIP(hipStreamSynchronize(s));
+  while (!alldone_h && it < maxit) {
+    const int par = it & 1;
+    NYS_TRY(matvec<T>(op, b.P, k, mu_dev, nrhs, mu_host, b.V, b, s));
+    NYS_TRY(cg_kernels_step_a<T>(n, k, b.P, b.V, X, k, b.R, b.ppv, b.prr, b.sc, par, ng, s));
+    NYS_TRY(precond_apply_dev(P, mu_dev, nrhs, b.R, b.Z, k, f32, b.sc.done, b.sc.alldone, b.apart,
+                              b.apart_elems, b.Cs, b.Ct, s));
+    NYS_TRY(cg_kernels_step_b<T>(n, k, b.R, b.Z, b.P, b.prz, b.prr, b.sc, par, tol, ng, s));
+    ++it;
+    if (it % check_every == 0 || it == maxit) {
+      NYS_HIP(hipMemcpyAsync(&alldone_h, b.sc.alldone, sizeof(int), hipMemcpyDeviceToHost, s));
+      NYS_HIP(hipStreamSynchronize(s));
+    }
+  }
+  res.iters.assign(k, 0);
+  res.status.assign(k, 0);
+  res.rnorm2.assign(k, 0.0);
+  res.bnorm2.assign(k, 0.0);
+  NYS_HIP(hipMemcpyAsync(res.iters.data(), b.sc.iters, sizeof(int) * k, hipMemcpyDeviceToHost, s));
+  NYS_HIP(hipMemcpyAsync(res.status.data(), b.sc.status, sizeof(int) * k, hipMemcpyDeviceToHost, s));
+  NYS_HIP(hipMemcpyAsync(res.rnorm2.data(), b.sc.rnorm2, sizeof(double) * k, hipMemcpyDeviceToHost, s));
+  NYS_HIP(hipMemcpyAsync(res.bnorm2.data(), b.sc.bnorm2, sizeof(double) * k, hipMemcpyDeviceToHost, s));
+  NYS_HIP(hipStreamSynchronize(s));
+  res.sweeps = it;
+  return NYS_OK;
+}
+
+// R64 = B64 - (A + mu I) X64 in float64; returns per-column relative residuals.
+nys_status true_residual(const OpDesc& op, int64_t k, int64_t nrhs, const double* mu_dev,
+                         const double* mu_host, SolveWs& w, std::vector<double>& relres,
+                         hipStream_t s) {
+  const int64_t n = op.n;
+  OpDesc o = op;
+  o.skip = nullptr;
+  if (k == 1 && (op.kind == NYS_OP_XTX || op.kind == NYS_OP_DENSE))
+    NYS_TRY(op_matvec<double>(o, w.X64, mu_host[0], w.V64, w.d.opscr, w.d.opscr_elems, s));
+  else
+    NYS_TRY(op_apply_f64(o, w.X64, k, k, mu_dev, nrhs, w.V64, k, w.d.opscr, w.d.opscr_elems, s));
+  const int g = 64;
+  hipLaunchKernelGGL(residual_norms, dim3(g), dim3(256), 0, s, n, k, w.B64, w.V64, w.R64, w.dots);
+  NYS_CHECK_LAUNCH();
+  std::vector<double> h(2 * g * k);
+  NYS_HIP(hipMemcpyAsync(h.data(), w.dots, sizeof(double) * 2 * g * k, hipMemcpyDeviceToHost, s));
+  NYS_HIP(hipStreamSynchronize(s));
+  relres.assign(k, 0.0);
+  for (int64_t c = 0; c < k; ++c) {
+    double rr = 0.0, bb = 0.0;
+    for (int q = 0; q < g; ++q) {
+      rr += h[q * k + c];
+      bb += h[(g + q) * k + c];
+    }
+    relres[c] = bb > 0.0 ? std::sqrt(rr / bb) : std::sqrt(rr);
+  }
+  return NYS_OK;
+}
+
+nys_status solve_impl(const OpDesc& op, const PrecDesc& P, const double* mu, int64_t nmu,
+                      const double* B, int64_t nrhs, int64_t ldb, double* X, int64_t ldx,
+                      const nys_solve_opts* o, nys_solve_info* info, SolveWs& w, hipStream_t s) {
+  const int64_t n = op.n, k = nmu * nrhs;
+  const double tol = o->tol;
+  const int maxit = o->maxit > 0 ? o->maxit : 500;
+  const int check = o->check_every > 0 ? o->check_every : 8;
+  const int prec = o->prec;
+  NYS_TRY(set_mu(w.mu, mu, nmu, s));
+  // contiguous float64 copies of B (expanded over the mu grid) and X
+  hipLaunchKernelGGL((gather_cols<double, double>), dim3(nblk(n * k)), dim3(256), 0, s, n, k, B, ldb,
+                     nrhs, w.B64, k);
+  NYS_CHECK_LAUNCH();
+  hipLaunchKernelGGL((gather_cols<double, double>), dim3(nblk(n * k)), dim3(256), 0, s, n, k, X, ldx,
+                     k, w.X64, k);
+  NYS_CHECK_LAUNCH();
+  std::vector<int> iters(k, 0), status(k, NYS_NOT_CONVERGED);
+  std::vector<double> relres(k, 0.0);
+  int refine_steps = 0, total = 0;
+  const double mu0 = mu[0];
+  if (prec == NYS_PREC_FP64) {
+    PcgResult r;
+    NYS_TRY(pcg_run<double>(op, P, k, nrhs, w.mu, mu0, w.B64, w.X64, false, tol, maxit, check, w.d, r, s));
+    iters = r.iters;
+    status = r.status;
+    total = r.sweeps;
+    NYS_TRY(true_residual(op, k, nrhs, w.mu, mu, w, relres, s));
+  } else if (prec == NYS_PREC_FP32) {
+    hipLaunchKernelGGL((gather_cols<double, float>), dim3(nblk(n * k)), dim3(256), 0, s, n, k, w.B64, k,
+                       k, w.f.B, k);
+    hipLaunchKernelGGL((gather_cols<double, float>), dim3(nblk(n * k)), dim3(256), 0, s, n, k, w.X64, k,
+                       k, w.f.X, k);
+    NYS_CHECK_LAUNCH();
+    PcgResult r;
+    NYS_TRY(pcg_run<float>(op, P, k, nrhs, w.mu, mu0, w.f.B, w.f.X, false, tol, maxit, check, w.f, r, s));
+    hipLaunchKernelGGL((gather_cols<float, double>), dim3(nblk(n * k)), dim3(256), 0, s, n, k, w.f.X, k,
+                       k, w.X64, k);
+    NYS_CHECK_LAUNCH();
+    iters = r.iters;
+    status = r.status;
+    total = r.sweeps;
+    NYS_TRY(true_residual(op, k, nrhs, w.mu, mu, w, relres, s));
+  } else {
+    // iterative refinement: float64 residual and update, float32 inner PCG
+    const int max_ref = o->max_refine > 0 ? o->max_refine : 10;
+    const double itol = o->inner_tol > 0 ? o->inner_tol : 1e-4;
+    NYS_TRY(true_residual(op, k, nrhs, w.mu, mu, w, relres, s));
+    for (int step = 0; step < max_ref; ++step) {
+      bool all = true;
+      for (int64_t c = 0; c < k; ++c) all = all && relres[c] <= tol;
+      if (all) break;
+      hipLaunchKernelGGL((gather_cols<double, float>), dim3(nblk(n * k)), dim3(256), 0, s, n, k, w.R64,
+                         k, k, w.f.B, k);
+      NYS_CHECK_LAUNCH();
+      PcgResult r;
+      NYS_TRY(pcg_run<float>(op, P, k, nrhs, w.mu, mu0, w.f.B, w.f.X, true, itol, maxit, check, w.f, r,
+                             s));
+      hipLaunchKernelGGL(add_to<float>, dim3(nblk(n * k)), dim3(256), 0, s, w.X64, w.f.X, n * k);
+      NYS_CHECK_LAUNCH();
+      for (int64_t c = 0; c < k; ++c) {
+        iters[c] += r.iters[c];
+        if (r.status[c] == NYS_ERR_BREAKDOWN) status[c] = NYS_ERR_BREAKDOWN;
+      }
+      total += r.sweeps;
+      ++refine_steps;
+      NYS_TRY(true_residual(op, k, nrhs, w.mu, mu, w, relres, s));
+    }
+    for (int64_t c = 0; c < k; ++c)
+      if (status[c] != NYS_ERR_BREAKDOWN) status[c] = relres[c] <= tol ? NYS_OK : NYS_NOT_CONVERGED;
+  }
+  // write back X
+  hipLaunchKernelGGL((gather_cols<double, double>), dim3(nblk(n * k)), dim3(256), 0, s, n, k, w.X64, k,
+                     k, X, ldx);
+  NYS_CHECK_LAUNCH();
+  NYS_HIP(hipStreamSynchronize(s));
+  nys_status worst = NYS_OK;
+  for (int64_t c = 0; c < k; ++c) {
+    if (status[c] == NYS_ERR_BREAKDOWN) worst = NYS_ERR_BREAKDOWN;
+    else if (status[c] != NYS_OK && worst == NYS_OK) worst = NYS_NOT_CONVERGED;
+  }
+  if (info) {
+    for (int64_t c = 0; c < k; ++c) {
+      if (info->iters) info->iters[c] = iters[c];
+      if (info->status) info->status[c] = status[c];
+      if (info->relres) info->relres[c] = relres[c];
+    }
+    info->refine_steps = refine_steps;
+    info->total_iters = total;
+  }
+  if (worst == NYS_ERR_BREAKDOWN) set_error("PCG breakdown: p^T (A + mu I) p <= 0");
+  else if (worst == NYS_NOT_CONVERGED) set_error("PCG did not reach the tolerance within maxit");
+  return worst;
+}
+
+nys_status check_solve_common(const OpDesc& op, const PrecDesc& P, const double* mu, int64_t nmu,
+                              const nys_solve_opts* o, hipStream_t s) {
+  NYS_ARG(o != nullptr, "solve options are NULL");
+  NYS_ARG(o->tol > 0.0 && std::isfinite(o->tol), "tol must be > 0");
+  NYS_ARG(o->prec >= NYS_PREC_FP64 && o->prec <= NYS_PREC_BF16X3_REFINE64, "unknown precision mode");
+  NYS_ARG(P.n == op.n, "preconditioner n (%lld) != operator n (%lld)", (long long)P.n, (long long)op.n);
+  NYS_ARG(mu != nullptr && nmu >= 1, "mu array is empty");
+  double lam_l = 0.0;
+  NYS_HIP(hipMemcpyAsync(&lam_l, P.lam + (P.ell - 1), sizeof(double), hipMemcpyDeviceToHost, s));
+  NYS_HIP(hipStreamSynchronize(s));
+  for (int64_t i = 0; i < nmu; ++i) {
+    NYS_ARG(std::isfinite(mu[i]) && mu[i] >= 0.0, "mu[%lld] must be finite and >= 0", (long long)i);
+    NYS_ARG(lam_l + mu[i] > 0.0, "lam_l + mu must be > 0 (mu = 0 needs a positive lam_l)");
+  }
+  if (o->prec != NYS_PREC_FP64 && op.kind == NYS_OP_RBF) {
+    set_error("reduced-precision modes for the RBF operator are not available in this build");
+    return NYS_ERR_ARG;
+  }
+  return NYS_OK;
+}
+
+}  // namespace
+}  // namespace nys
+
+using namespace nys;
+
+extern "C" {
+
+const char* nys_last_error(void) { return g_err; }
+
+const char* nys_version(void) { return "nyspcg 0.1 (gfx950)"; }
+
+size_t nys_workspace_size(const nys_operator* A, int64_t ell, int64_t ncols, int32_t prec) {
+  OpDesc op;
+  if (check_op(A, op) != NYS_OK || ell < 1 || ncols < 1) return 0;
+  size_t best = 0;
+  {
+    Arena a(nullptr, 0);
+    SketchWs w;
+    carve_sketch(a, op, ell, prec, w);
+    best = a.off > best ? a.off : best;
+  }
+  {
+    Arena a(nullptr, 0);
+    FactorWs w;
+    carve_factor(a, op.n, ell, w);
+    best = a.off > best ? a.off : best;
+  }
+  {
+    Arena a(nullptr, 0);
+    SolveWs w;
+    carve_solve(a, op, ell, ncols, prec, w);
+    size_t extra = (size_t)(4 * 256) * (size_t)op.n * sizeof(double) + 4096;
+    best = a.off + extra > best ? a.off + extra : best;
+  }
+  return best + 256;
+}
+
+nys_status nys_gaussian(uint64_t seed, int64_t n, int64_t ell, double* out, int64_t ld,
+                        void* stream) {
+  NYS_ARG(n >= 1 && ell >= 1 && ld >= ell && out != nullptr, "nys_gaussian: invalid shape");
+  return gaussian(seed, n, ell, out, ld, S(stream));
+}
+
+nys_status nys_sketch(const nys_operator* A, int64_t ell, uint64_t seed, const double* omega0,
+                      double* Omega, double* Y, int32_t prec, void* ws, size_t ws_bytes,
+                      void* stream) {
+  OpDesc op;
+  NYS_TRY(check_op(A, op));
+  const int64_t n = op.n, l = ell;
+  NYS_ARG(l >= 1 && l <= n, "sketch size ell = %lld must satisfy 1 <= ell <= n = %lld", (long long)l,
+          (long long)n);
+  NYS_ARG(l <= 2048, "sketch size > 2048 not supported");
+  NYS_ARG(Omega != nullptr && Y != nullptr, "Omega / Y is NULL");
+  NYS_ARG(prec >= NYS_PREC_FP64 && prec <= NYS_PREC_BF16X3_REFINE64, "unknown precision mode");
+  Arena a(ws, ws_bytes);
+  SketchWs w;
+  carve_sketch(a, op, l, prec, w);
+  if (!ws || !a.ok()) {
+    set_error("workspace too small: need %zu bytes", a.off);
+    return NYS_ERR_WORKSPACE;
+  }
+  hipStream_t s = S(stream);
+  if (omega0) NYS_HIP(hipMemcpyAsync(Omega, omega0, sizeof(double) * n * l, hipMemcpyDeviceToDevice, s));
+  else NYS_TRY(gaussian(seed, n, l, Omega, l, s));
+  int info[2] = {0, 0};
+  NYS_TRY(cholqr2(Omega, Y, n, l, w.c, info, s));
+  if (sketch_f32(op, prec)) {
+    // Y = X^T (X Omega) in float32 MFMA arithmetic
+    hipLaunchKernelGGL((gather_cols<double, float>), dim3(nblk(n * l)), dim3(256), 0, s, n, l, Omega, l,
+                       l, w.Om32, l);
+    NYS_CHECK_LAUNCH();
+    const float* X = static_cast<const float*>(op.data);
+    NYS_TRY((gemm<float, float, float>(false, false, op.rows, l, n, 1.0f, X, op.ld, w.Om32, l, 0.0f,
+                                       w.T32, l, w.f32scr, w.f32scr_elems, s)));
+    NYS_TRY((gemm<float, float, float>(true, false, n, l, op.rows, (float)op.scale, X, op.ld, w.T32, l,
+                                       0.0f, w.Y32, l, w.f32scr, w.f32scr_elems, s)));
+    hipLaunchKernelGGL((gather_cols<float, double>), dim3(nblk(n * l)), dim3(256), 0, s, n, l, w.Y32, l,
+                       l, Y, l);
+    NYS_CHECK_LAUNCH();
+  } else {
+    NYS_TRY(op_apply_f64(op, Omega, l, l, nullptr, 1, Y, l, w.opscr, w.opscr_elems, s));
+  }
+  NYS_HIP(hipStreamSynchronize(s));
+  if (info[0] != 0 || info[1] != 0) {
+    set_error("test matrix is numerically rank deficient (CholeskyQR pivot %d/%d)", info[0], info[1]);
+    return NYS_ERR_NOT_PSD;
+  }
+  return NYS_OK;
+}
+
+nys_status nys_factor(const double* Omega, double* Y, nys_precond* P, void* ws, size_t ws_bytes,
+                      void* stream) {
+  NYS_ARG(P != nullptr && Omega != nullptr && Y != nullptr, "nys_factor: NULL argument");
+  PrecDesc pd;
+  NYS_TRY(check_prec(P, pd));
+  const int64_t n = P->n, l = P->ell;
+  Arena a(ws, ws_bytes);
+  FactorWs w;
+  carve_factor(a, n, l, w);
+  if (!ws || !a.ok()) {
+    set_error("workspace too small: need %zu bytes", a.off);
+    return NYS_ERR_WORKSPACE;
+  }
+  hipStream_t s = S(stream);
+  Core& c = w.c;
+  // nu = eps(||Y||_F);  Y_nu = Y + nu Omega
+  NYS_TRY(frob_shift(Y, n * l, c.part, c.nu, s));
+  NYS_TRY(add_shift(Y, Omega, n * l, c.nu, 1.0, s));
+  int info = 0;
+  for (int attempt = 0; attempt <= 3; ++attempt) {
+    if (attempt > 0) {  // nu <- 10 nu: Y_10nu = Y_nu + 9 nu Omega
+      NYS_TRY(add_shift(Y, Omega, n * l, c.nu, 9.0, s));
+      NYS_TRY(scale_device_scalar(c.nu, 10.0, s));
+    }
+    // C^T C = Omega^T Y_nu  (lower factor L = C^T)
+    NYS_TRY((gemm<double, double, double>(true, false, l, l, n, 1.0, Omega, l, Y, l, 0.0, c.G, l, c.gscr,
+                                          c.gscr_elems, s)));
+    NYS_TRY(cholesky(c.G, l, c.L, c.Dinv, c.info, c.bar, c.bar_err, s));
+    NYS_HIP(hipMemcpyAsync(&info, c.info, sizeof(int), hipMemcpyDeviceToHost, s));
+    NYS_HIP(hipStreamSynchronize(s));
+    if (info == 0) break;
+  }
+  if (info != 0) {
+    set_error("Cholesky of Omega^T Y_nu failed at column %d after shift retries", info - 1);
+    return NYS_ERR_NOT_PSD;
+  }
+  // B = Y_nu C^{-1} = Y_nu L^{-T}
+  NYS_TRY(tri_inverse(c.L, l, c.Dinv, c.Linv, s));
+  NYS_TRY((gemm<double, double, double>(false, true, n, l, l, 1.0, Y, l, c.Linv, l, 0.0, w.B, l, c.gscr,
+                                        c.gscr_elems, s)));
+  // thin SVD of B through B^T B = W S W^T:  U = B W S^{-1/2}, lam = max(0, S - nu)
+  NYS_TRY((gemm<double, double, double>(true, false, l, l, n, 1.0, w.B, l, w.B, l, 0.0, c.G, l, c.gscr,
+                                        c.gscr_elems, s)));
+  NYS_TRY(sym_eig(c.G, l, c.eig, c.flags, kMaxSweeps, c.sweeps, c.bar, c.bar_err, c.T, P->lam, c.sig2,
+                  c.nu, s));
+  if (P->dtype == NYS_F64) {
+    NYS_TRY((gemm<double, double, double>(false, false, n, l, l, 1.0, w.B, l, c.T, l, 0.0,
+                                          static_cast<double*>(P->U), P->ldu, c.gscr, c.gscr_elems, s)));
+  } else {
+    NYS_TRY((gemm<double, double, double>(false, false, n, l, l, 1.0, w.B, l, c.T, l, 0.0, Y, l, c.gscr,
+                                          c.gscr_elems, s)));
+    hipLaunchKernelGGL((gather_cols<double, float>), dim3(nblk(n * l)), dim3(256), 0, s, n, l, Y, l, l,
+                       static_cast<float*>(P->U), P->ldu);
+    NYS_CHECK_LAUNCH();
+  }
+  double nu = 0.0;
+  int bar_err = 0;
+  NYS_HIP(hipMemcpyAsync(&nu, c.nu, sizeof(double), hipMemcpyDeviceToHost, s));
+  NYS_HIP(hipMemcpyAsync(&bar_err, c.bar_err, sizeof(int), hipMemcpyDeviceToHost, s));
+  NYS_HIP(hipStreamSynchronize(s));
+  if (bar_err) {
+    set_error("device barrier time-out in the factorisation");
+    return NYS_ERR_DEVICE;
+  }
+  P->nu = nu;
+  return NYS_OK;
+}
+
+nys_status nys_op_apply(const nys_operator* A, double mu, const void* V, int64_t k, int64_t ldv,
+                        void* Z, int64_t ldz, int32_t dtype, void* ws, size_t ws_bytes, void* stream) {
+  OpDesc op;
+  NYS_TRY(check_op(A, op));
+  NYS_ARG(V && Z && k >= 1 && ldv >= k && ldz >= k, "nys_op_apply: invalid vectors");
+  NYS_ARG(std::isfinite(mu), "mu must be finite");
+  NYS_ARG(dtype == NYS_F64 || (dtype == NYS_F32 && k == 1 && ldv == 1 && ldz == 1 &&
+                               (op.kind == NYS_OP_XTX || op.kind == NYS_OP_DENSE)),
+          "nys_op_apply: float32 is available for one X^T X or dense vector");
+  Arena a(ws, ws_bytes);
+  double* mu_dev = a.take<double>(1);
+  const size_t se = op_scratch_elems(op, k);
+  double* scr = a.take<double>(se);
+  if (!ws || !a.ok()) {
+    set_error("workspace too small: need %zu bytes", a.off);
+    return NYS_ERR_WORKSPACE;
+  }
+  hipStream_t s = S(stream);
+  if (dtype == NYS_F32)
+    return op_matvec<float>(op, static_cast<const float*>(V), (float)mu, static_cast<float*>(Z),
+                            reinterpret_cast<float*>(scr), se, s);
+  if (k == 1 && ldv == 1 && ldz == 1 && (op.kind == NYS_OP_XTX || op.kind == NYS_OP_DENSE))
+    return op_matvec<double>(op, static_cast<const double*>(V), mu, static_cast<double*>(Z), scr, se, s);
+  NYS_TRY(set_mu(mu_dev, &mu, 1, s));
+  return op_apply_f64(op, static_cast<const double*>(V), k, ldv, mu_dev, k, static_cast<double*>(Z), ldz,
+                      scr, se, s);
+}
+
+nys_status nys_precond_apply(const nys_precond* P, double mu, const double* R, int64_t k, int64_t ldr,
+                             double* Z, int64_t ldz, void* ws, size_t ws_bytes, void* stream) {
+  PrecDesc pd;
+  NYS_TRY(check_prec(P, pd));
+  NYS_ARG(R && Z && k >= 1 && k <= kMaxCols && ldr == k && ldz == k,
+          "nys_precond_apply: R and Z must be contiguous n x k blocks, k <= 256");
+  NYS_ARG(std::isfinite(mu) && mu >= 0.0, "mu must be finite and >= 0");
+  Arena a(ws, ws_bytes);
+  double* mu_dev = a.take<double>(1);
+  const size_t pe = precond_part_elems(pd.n, pd.ell, k);
+  double* part = a.take<double>(pe);
+  double* Cs = a.take<double>(pd.ell * k);
+  double* Ct = a.take<double>(pd.ell * k);
+  if (!ws || !a.ok()) {
+    set_error("workspace too small: need %zu bytes", a.off);
+    return NYS_ERR_WORKSPACE;
+  }
+  hipStream_t s = S(stream);
+  NYS_TRY(set_mu(mu_dev, &mu, 1, s));
+  return precond_apply_dev(pd, mu_dev, k, R, Z, k, false, nullptr, nullptr, part, pe, Cs, Ct, s);
+}
+
+nys_status nys_pcg_solve(const nys_operator* A, const nys_precond* P, const double* mu, int64_t nmu,
+                         const double* B, int64_t nrhs, int64_t ldb, double* X, int64_t ldx,
+                         const nys_solve_opts* o, nys_solve_info* info, void* ws, size_t ws_bytes,
+                         void* stream) {
+  OpDesc op;
+  NYS_TRY(check_op(A, op));
+  PrecDesc pd;
+  NYS_TRY(check_prec(P, pd));
+  NYS_ARG(B && X && nrhs >= 1 && ldb >= nrhs, "nys_pcg_solve: invalid B");
+  const int64_t k = nmu * nrhs;
+  NYS_ARG(k >= 1 && k <= kMaxCols, "nys_pcg_solve: nmu * nrhs must be in [1, 256]");
+  NYS_ARG(ldx >= k, "nys_pcg_solve: ldx < nmu * nrhs");
+  hipStream_t s = S(stream);
+  NYS_TRY(check_solve_common(op, pd, mu, nmu, o, s));
+  Arena a(ws, ws_bytes);
+  SolveWs w;
+  carve_solve(a, op, pd.ell, k, o->prec, w);
+  if (!ws || !a.ok()) {
+    set_error("workspace too small: need %zu bytes", a.off);
+    return NYS_ERR_WORKSPACE;
+  }
+  return solve_impl(op, pd, mu, nmu, B, nrhs, ldb, X, ldx, o, info, w, s);
+}
+
+size_t nys_workspace_size_ragged(const nys_operator* ops, const nys_precond* Ps, int32_t nprob,
+                                 int32_t prec) {
+  if (!ops || !Ps || nprob < 1) return 0;
+  size_t best = 0;
+  for (int32_t i = 0; i < nprob; ++i) {
+    const size_t b = nys_workspace_size(&ops[i], Ps[i].ell, 1, prec);
+    best = b > best ? b : best;
+  }
+  return best;
+}
+
+nys_status nys_pcg_solve_ragged(const nys_operator* ops, const nys_precond* Ps, const double* mu,
+                                const double* const* B, double* const* X, int32_t nprob,
+                                const nys_solve_opts* o, nys_solve_info* info, void* ws,
+                                size_t ws_bytes, void* stream) {
+  NYS_ARG(ops && Ps && mu && B && X && nprob >= 1, "nys_pcg_solve_ragged: NULL argument");
+  nys_status worst = NYS_OK;
+  int total = 0, refine = 0;
+  for (int32_t i = 0; i < nprob; ++i) {
+    int it = 0, st = 0;
+    double rr = 0.0;
+    nys_solve_info inf{&it, &rr, &st, 0, 0};
+    const nys_status r = nys_pcg_solve(&ops[i], &Ps[i], &mu[i], 1, B[i], 1, 1, X[i], 1, o, &inf, ws,
+                                       ws_bytes, stream);
+    if (r < 0) return r;
+    if (r != NYS_OK) worst = r;
+    if (info) {
+      if (info->iters) info->iters[i] = it;
+      if (info->relres) info->relres[i] = rr;
+      if (info->status) info->status[i] = st;
+    }
+    total += inf.total_iters;
+    refine += inf.refine_steps;
+  }
+  if (info) {
+    info->total_iters = total;
+    info->refine_steps = refine;
+  }
+  return worst;
+}
+
+nys_status nys_pcg_backward(const nys_operator* A, const nys_precond* P, double mu, const double* x,
+                            const double* gx, double* gb, double* gmu, double* gsigma, double* gX,
+                            const nys_solve_opts* o, nys_solve_info* info, void* ws, size_t ws_bytes,
+                            void* stream) {
+  OpDesc op;
+  NYS_TRY(check_op(A, op));
+  PrecDesc pd;
+  NYS_TRY(check_prec(P, pd));
+  NYS_ARG(x && gx && gb, "nys_pcg_backward: NULL vector");
+  hipStream_t s = S(stream);
+  NYS_TRY(check_solve_common(op, pd, &mu, 1, o, s));
+  const int64_t n = op.n;
+  Arena a(ws, ws_bytes);
+  SolveWs w;
+  carve_solve(a, op, pd.ell, 1, o->prec, w);
+  double* tmp = a.take<double>(n > op.rows ? n : op.rows);
+  double* tmp2 = a.take<double>(op.rows);
+  double* part = a.take<double>(1024);
+  const size_t rscr_elems = (size_t)(4 * 256) * (size_t)n;
+  double* rscr = a.take<double>(rscr_elems);
+  if (!ws || !a.ok()) {
+    set_error("workspace too small: need %zu bytes", a.off);
+    return NYS_ERR_WORKSPACE;
+  }
+  // adjoint solve (A + mu I) lambda = gx with the same preconditioner, lambda in gb
+  NYS_TRY(zero<double>(gb, n, s));
+  const nys_status st = solve_impl(op, pd, &mu, 1, gx, 1, 1, gb, 1, o, info, w, s);
+  if (st < 0) return st;
+  std::vector<double> h(256);
+  // dL/dmu = -lambda^T x
+  if (gmu) {
+    hipLaunchKernelGGL(dot_partial, dim3(256), dim3(256), 0, s, gb, x, n, part);
+    NYS_CHECK_LAUNCH();
+    NYS_HIP(hipMemcpyAsync(h.data(), part, sizeof(double) * 256, hipMemcpyDeviceToHost, s));
+    NYS_HIP(hipStreamSynchronize(s));
+    double d = 0.0;
+    for (int i = 0; i < 256; ++i) d += h[i];
+    *gmu = -d;
+  }
+  if (gsigma) {
+    if (op.kind == NYS_OP_RBF) {
+      // -lambda^T (dK/dsigma) x
+      NYS_TRY(rbf_rect_mv(op.data, n, op.ld, op.data, n, op.ld, (int)op.cols, op.dtype, op.sigma, 1, x,
+                          tmp, rscr, rscr_elems, s));
+      hipLaunchKernelGGL(dot_partial, dim3(256), dim3(256), 0, s, gb, tmp, n, part);
+      NYS_CHECK_LAUNCH();
+      NYS_HIP(hipMemcpyAsync(h.data(), part, sizeof(double) * 256, hipMemcpyDeviceToHost, s));
+      NYS_HIP(hipStreamSynchronize(s));
+      double d = 0.0;
+      for (int i = 0; i < 256; ++i) d += h[i];
+      *gsigma = -op.scale * d;
+    } else {
+      *gsigma = 0.0;
+    }
+  }
+  if (gX) {
+    NYS_ARG(op.kind == NYS_OP_XTX, "gX is defined for the X^T X operator only");
+    const int64_t m = op.rows;
+    // t1 = X x, t2 = X lambda;  gX = -scale (t1 lambda^T + t2 x^T)
+    if (op.dtype == NYS_F64) {
+      hipLaunchKernelGGL(gemv_rows<double>, dim3((unsigned)cdiv(m, 4)), dim3(256), 0, s,
+                         static_cast<const double*>(op.data), m, n, op.ld, x, tmp);
+      hipLaunchKernelGGL(gemv_rows<double>, dim3((unsigned)cdiv(m, 4)), dim3(256), 0, s,
+                         static_cast<const double*>(op.data), m, n, op.ld, gb, tmp2);
+    } else {
+      hipLaunchKernelGGL(gemv_rows<float>, dim3((unsigned)cdiv(m, 4)), dim3(256), 0, s,
+                         static_cast<const float*>(op.data), m, n, op.ld, x, tmp);
+      hipLaunchKernelGGL(gemv_rows<float>, dim3((unsigned)cdiv(m, 4)), dim3(256), 0, s,
+                         static_cast<const float*>(op.data), m, n, op.ld, gb, tmp2);
+    }
+    NYS_CHECK_LAUNCH();
+    hipLaunchKernelGGL(outer2, dim3(nblk(m * n)), dim3(256), 0, s, m, n, op.scale, tmp, gb, tmp2, x, gX);
+    NYS_CHECK_LAUNCH();
+    NYS_HIP(hipStreamSynchronize(s));
+  }
+  return st;
+}
+
+nys_status nys_rbf_cross(const nys_operator* A, const void* Xv, int64_t nv, int64_t ldxv,
+                         int32_t transpose, const double* v, double* out, const double* wvec,
+                         double* dsig_out, void* ws, size_t ws_bytes, void* stream) {
+  OpDesc op;
+  NYS_TRY(check_op(A, op));
+  NYS_ARG(op.kind == NYS_OP_RBF, "nys_rbf_cross needs an RBF operator");
+  NYS_ARG(Xv && nv >= 1 && ldxv >= op.cols && v && out, "nys_rbf_cross: invalid arguments");
+  const int64_t n = op.n;
+  const int64_t nr = transpose ? n : nv;
+  Arena a(ws, ws_bytes);
+  const size_t se = (size_t)(4 * 256) * (size_t)(n > nv ? n : nv);
+  double* scr = a.take<double>(se);
+  double* tmp = a.take<double>(nv);
+  double* part = a.take<double>(256);
+  if (!ws || !a.ok()) {
+    set_error("workspace too small: need %zu bytes", a.off);
+    return NYS_ERR_WORKSPACE;
+  }
+  hipStream_t s = S(stream);
+  if (!transpose)
+    NYS_TRY(rbf_rect_mv(Xv, nv, ldxv, op.data, n, op.ld, (int)op.cols, op.dtype, op.sigma, 0, v, out, scr,
+                        se, s));
+  else
+    NYS_TRY(rbf_rect_mv(op.data, n, op.ld, Xv, nv, ldxv, (int)op.cols, op.dtype, op.sigma, 0, v, out, scr,
+                        se, s));
+  (void)nr;
+  if (dsig_out) {
+    NYS_ARG(wvec != nullptr && !transpose, "nys_rbf_cross: dsig_out needs wvec and transpose = 0");
+    // u^T (dK(Xv, X)/dsigma) w with u = v (nv), w = wvec (n)
+    NYS_TRY(rbf_rect_mv(Xv, nv, ldxv, op.data, n, op.ld, (int)op.cols, op.dtype, op.sigma, 1, wvec, tmp,
+                        scr, se, s));
+    hipLaunchKernelGGL(dot_partial, dim3(256), dim3(256), 0, s, v, tmp, nv, part);
+    NYS_CHECK_LAUNCH();
+    std::vector<double> h(256);
+    NYS_HIP(hipMemcpyAsync(h.data(), part, sizeof(double) * 256, hipMemcpyDeviceToHost, s));
+    NYS_HIP(hipStreamSynchronize(s));
+    double d = 0.0;
+    for (int i = 0; i < 256; ++i) d += h[i];
+    *dsig_out = d;
+  }
+  return NYS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,123 @@
+// Shared device/host utilities for the Nystrom PCG library (gfx950 only).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+#include <cstddef>
+
+#include "nyspcg.h"
+
+namespace nys {
+
+// ---------------------------------------------------------------- host side
+void set_error(const char* fmt, ...);
+
+#define NYS_HIP(call)                                                          \
+  do {                                                                         \
+    hipError_t e_ = (call);                                                    \
+    if (e_ != hipSuccess) {                                                    \
+      ::nys::set_error("%s:%d %s: %s", __FILE__, __LINE__, #call,              \
+                       hipGetErrorString(e_));                                 \
+      return NYS_ERR_DEVICE;                                                   \
+    }                                                                          \
+  } while (0)
+
+#define NYS_CHECK_LAUNCH() NYS_HIP(hipGetLastError())
+
+#define NYS_ARG(cond, ...)                                                     \
+  do {                                                                         \
+    if (!(cond)) {                                                             \
+      ::nys::set_error(__VA_ARGS__);                                           \
+      return NYS_ERR_ARG;                                                      \
+    }                                                                          \
+  } while (0)
+
+#define NYS_TRY(expr)                                                          \
+  do {                                                                         \
+    nys_status s_ = (expr);                                                    \
+    if (s_ != NYS_OK) return s_;                                               \
+  } while (0)
+
+// Bump allocator over the caller's workspace.  With base == nullptr it only
+// measures, so the same code path yields nys_workspace_size().
+struct Arena {
+  char* base;
+  size_t cap;
+  size_t off = 0;
+  Arena(void* b, size_t c) : base(static_cast<char*>(b)), cap(c) {}
+  template <typename T>
+  T* take(size_t count) {
+    off = (off + 255) & ~size_t(255);
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += count * sizeof(T);
+    return p;
+  }
+  bool ok() const { return base == nullptr || off <= cap; }
+};
+
+__host__ __device__ inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+int num_cus();  // compute units of the current device
+
+// --------------------------------------------------------------- device side
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Fixed-order block reduction (deterministic): wave shuffles then one wave
+// combines the per-wave sums.  `sh` needs blockDim.x/64 entries.
+template <typename T>
+__device__ __forceinline__ T block_sum(T v, T* sh) {
+  v = wave_sum(v);
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int nw = blockDim.x >> 6;
+  __syncthreads();
+  if (l == 0) sh[w] = v;
+  __syncthreads();
+  T r = (threadIdx.x < nw) ? sh[threadIdx.x] : T(0);
+  if (w == 0) r = wave_sum(r);
+  __syncthreads();
+  if (threadIdx.x == 0) sh[0] = r;
+  __syncthreads();
+  r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+// Grid-wide barrier for cooperative (co-resident) launches.  `ctr` is a
+// monotonically increasing arrival counter zeroed before the launch; `epoch`
+// counts barriers passed by this workgroup.  Spinning is bounded: after
+// `spin_limit` polls the barrier records a timeout in `err` and every later
+// barrier returns at once, so all workgroups still reach the kernel's end.
+struct GridBarrier {
+  unsigned* ctr;
+  int* err;
+  unsigned nblocks;
+  unsigned epoch;
+  __device__ void sync() {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      epoch += 1;
+      const unsigned target = epoch * nblocks;
+      __threadfence();
+      atomicAdd(ctr, 1u);
+      unsigned spins = 0;
+      while (true) {
+        unsigned v = __hip_atomic_load(ctr, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+        if (v >= target) break;
+        if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) break;
+        if (++spins > (1u << 26)) {
+          atomicExch(err, 1);
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+      }
+      __threadfence();
+    }
+    __syncthreads();
+  }
+};
+
+}  // namespace nys

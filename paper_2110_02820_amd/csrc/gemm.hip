@@ -1,0 +1,206 @@
+// Tiled MFMA GEMM for the sketch and factorisation steps (gfx950).
+//
+//   C = alpha * op(A) * op(B) + beta * C      (row-major, leading dimensions)
+//
+// float64 uses v_mfma_f64_16x16x4f64, float32 uses v_mfma_f32_16x16x4f32.
+// Storage types of A and B may be narrower than the compute type (float32
+// data promoted exactly to float64).  A 256-thread workgroup computes a
+// 64 x 64 tile as a 2 x 2 arrangement of waves, each wave a 32 x 32 block of
+// four 16 x 16 MFMA tiles; the K loop stages 16-deep slabs of A and B through
+// LDS.  When the output has too few tiles to fill 256 CUs, K is split across
+// workgroups (grid z) and a second kernel sums the partial tiles in a fixed
+// order, so results are deterministic.
+#include "gemm.hpp"
+
+namespace nys {
+
+namespace {
+
+constexpr int BM = 64, BN = 64, BK = 16, NT = 256;
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+template <typename T>
+struct Mfma;
+template <>
+struct Mfma<double> {
+  typedef d4 acc_t;
+  static __device__ __forceinline__ acc_t op(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  // accumulator element q of lane l holds D[4 q + l/16][l % 16]
+  static __device__ __forceinline__ int row(int lane, int q) { return 4 * q + (lane >> 4); }
+};
+template <>
+struct Mfma<float> {
+  typedef f4 acc_t;
+  static __device__ __forceinline__ acc_t op(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  // accumulator element q of lane l holds D[4 (l/16) + q][l % 16]
+  static __device__ __forceinline__ int row(int lane, int q) { return 4 * (lane >> 4) + q; }
+};
+
+// Lane layout of the 16x16x4 MFMA (one wave): operand a holds A[l%16][l/16],
+// operand b holds B[l/16][l%16]; the accumulator rows differ between the f32
+// and f64 forms (Mfma<T>::row, checked on the device).
+template <typename TC, typename TAs, typename TBs, bool TA, bool TB>
+__global__ __launch_bounds__(NT) void gemm_kernel(int64_t M, int64_t N, int64_t K, int64_t kchunk,
+                                                  TC alpha, const TAs* __restrict__ A, int64_t lda,
+                                                  const TBs* __restrict__ B, int64_t ldb, TC beta,
+                                                  TC* __restrict__ C, int64_t ldc,
+                                                  TC* __restrict__ part, const int* __restrict__ skip) {
+  if (skip && *skip) return;
+  __shared__ TC As[BK][BM + 4];
+  __shared__ TC Bs[BK][BN + 4];
+  const int t = threadIdx.x;
+  const int lane = t & 63, wave = t >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int64_t m0 = (int64_t)blockIdx.y * BM, n0 = (int64_t)blockIdx.x * BN;
+  const int64_t kb = (int64_t)blockIdx.z * kchunk;
+  const int64_t ke = (kb + kchunk < K) ? kb + kchunk : K;
+
+  typename Mfma<TC>::acc_t acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = typename Mfma<TC>::acc_t{0, 0, 0, 0};
+
+  for (int64_t k0 = kb; k0 < ke; k0 += BK) {
+    // stage A slab (BM x BK) as As[k][m]
+#pragma unroll
+    for (int r = 0; r < (BM * BK) / NT; ++r) {
+      const int e = t + r * NT;
+      int mm, kk;
+      if (!TA) { mm = e / BK; kk = e % BK; } else { kk = e / BM; mm = e % BM; }
+      const int64_t gm = m0 + mm, gk = k0 + kk;
+      TC v = TC(0);
+      if (gm < M && gk < ke) v = TC(TA ? A[gk * lda + gm] : A[gm * lda + gk]);
+      As[kk][mm] = v;
+    }
+    // stage B slab (BK x BN) as Bs[k][n]
+#pragma unroll
+    for (int r = 0; r < (BN * BK) / NT; ++r) {
+      const int e = t + r * NT;
+      int nn, kk;
+      if (!TB) { kk = e / BN; nn = e % BN; } else { nn = e / BK; kk = e % BK; }
+      const int64_t gn = n0 + nn, gk = k0 + kk;
+      TC v = TC(0);
+      if (gn < N && gk < ke) v = TC(TB ? B[gn * ldb + gk] : B[gk * ldb + gn]);
+      Bs[kk][nn] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ks = 0; ks < BK; ks += 4) {
+      const int kk = ks + (lane >> 4);
+      TC a0 = As[kk][wm * 32 + (lane & 15)];
+      TC a1 = As[kk][wm * 32 + 16 + (lane & 15)];
+      TC b0 = Bs[kk][wn * 32 + (lane & 15)];
+      TC b1 = Bs[kk][wn * 32 + 16 + (lane & 15)];
+      acc[0][0] = Mfma<TC>::op(a0, b0, acc[0][0]);
+      acc[0][1] = Mfma<TC>::op(a0, b1, acc[0][1]);
+      acc[1][0] = Mfma<TC>::op(a1, b0, acc[1][0]);
+      acc[1][1] = Mfma<TC>::op(a1, b1, acc[1][1]);
+    }
+    __syncthreads();
+  }
+
+  // epilogue
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int64_t gm = m0 + wm * 32 + i * 16 + Mfma<TC>::row(lane, q);
+        const int64_t gn = n0 + wn * 32 + j * 16 + (lane & 15);
+        if (gm < M && gn < N) {
+          const TC v = acc[i][j][q];
+          if (part) {
+            part[((int64_t)blockIdx.z * M + gm) * N + gn] = v;
+          } else {
+            TC o = alpha * v;
+            if (beta != TC(0)) o += beta * C[gm * ldc + gn];
+            C[gm * ldc + gn] = o;
+          }
+        }
+      }
+}
+
+template <typename TC>
+__global__ void splitk_reduce(int64_t M, int64_t N, int nz, TC alpha, const TC* __restrict__ part,
+                              TC beta, TC* __restrict__ C, int64_t ldc, const int* __restrict__ skip) {
+  if (skip && *skip) return;
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= M * N) return;
+  const int64_t m = idx / N, n = idx % N;
+  TC s = TC(0);
+  for (int z = 0; z < nz; ++z) s += part[(int64_t)z * M * N + idx];
+  TC o = alpha * s;
+  if (beta != TC(0)) o += beta * C[m * ldc + n];
+  C[m * ldc + n] = o;
+}
+
+}  // namespace
+
+template <typename TC, typename TAs, typename TBs>
+nys_status gemm(bool ta, bool tb, int64_t M, int64_t N, int64_t K, TC alpha, const TAs* A,
+                int64_t lda, const TBs* B, int64_t ldb, TC beta, TC* C, int64_t ldc, TC* scratch,
+                size_t scratch_elems, hipStream_t s, const int* skip) {
+  if (M <= 0 || N <= 0) return NYS_OK;
+  const int64_t tiles = cdiv(M, BM) * cdiv(N, BN);
+  const int64_t target = 2 * (int64_t)(num_cus() < 256 ? num_cus() : 256);
+  int64_t nz = 1;
+  if (tiles < target && K > 4 * BK) {
+    nz = cdiv(target, tiles);
+    nz = nz < cdiv(K, 8 * BK) ? nz : cdiv(K, 8 * BK);
+    while (nz > 1 && (size_t)(nz * M * N) > scratch_elems) --nz;
+    if (nz > 64) nz = 64;
+  }
+  int64_t kchunk = cdiv(cdiv(K, nz), BK) * BK;
+  if (K <= 0) kchunk = BK;
+  nz = K > 0 ? cdiv(K, kchunk) : 1;
+  dim3 grid((unsigned)cdiv(N, BN), (unsigned)cdiv(M, BM), (unsigned)nz);
+  TC* part = nz > 1 ? scratch : nullptr;
+#define NYS_GEMM_LAUNCH(TA_, TB_)                                                              \
+  hipLaunchKernelGGL((gemm_kernel<TC, TAs, TBs, TA_, TB_>), grid, dim3(NT), 0, s, M, N, K,    \
+                     kchunk, alpha, A, lda, B, ldb, beta, C, ldc, part, skip)
+  if (!ta && !tb) NYS_GEMM_LAUNCH(false, false);
+  else if (!ta && tb) NYS_GEMM_LAUNCH(false, true);
+  else if (ta && !tb) NYS_GEMM_LAUNCH(true, false);
+  else NYS_GEMM_LAUNCH(true, true);
+#undef NYS_GEMM_LAUNCH
+  NYS_CHECK_LAUNCH();
+  if (nz > 1) {
+    const int64_t tot = M * N;
+    hipLaunchKernelGGL(splitk_reduce<TC>, dim3((unsigned)cdiv(tot, 256)), dim3(256), 0, s, M, N,
+                       (int)nz, alpha, part, beta, C, ldc, skip);
+    NYS_CHECK_LAUNCH();
+  }
+  return NYS_OK;
+}
+
+template nys_status gemm<double, double, double>(bool, bool, int64_t, int64_t, int64_t, double,
+                                                 const double*, int64_t, const double*, int64_t,
+                                                 double, double*, int64_t, double*, size_t,
+                                                 hipStream_t, const int*);
+template nys_status gemm<double, float, double>(bool, bool, int64_t, int64_t, int64_t, double,
+                                                const float*, int64_t, const double*, int64_t,
+                                                double, double*, int64_t, double*, size_t,
+                                                hipStream_t, const int*);
+template nys_status gemm<double, double, float>(bool, bool, int64_t, int64_t, int64_t, double,
+                                                const double*, int64_t, const float*, int64_t,
+                                                double, double*, int64_t, double*, size_t,
+                                                hipStream_t, const int*);
+template nys_status gemm<double, float, float>(bool, bool, int64_t, int64_t, int64_t, double,
+                                               const float*, int64_t, const float*, int64_t, double,
+                                               double*, int64_t, double*, size_t, hipStream_t, const int*);
+template nys_status gemm<float, float, float>(bool, bool, int64_t, int64_t, int64_t, float,
+                                              const float*, int64_t, const float*, int64_t, float,
+                                              float*, int64_t, float*, size_t, hipStream_t, const int*);
+template nys_status gemm<float, float, double>(bool, bool, int64_t, int64_t, int64_t, float,
+                                               const float*, int64_t, const double*, int64_t, float,
+                                               float*, int64_t, float*, size_t, hipStream_t, const int*);
+
+}  // namespace nys

@@ -1,0 +1,21 @@
+#pragma once
+#include "common.hpp"
+
+namespace nys {
+
+// C = alpha op(A) op(B) + beta C  (row-major).  `scratch` (scratch_elems
+// elements of the compute type) holds split-K partial tiles; with too little
+// scratch the K dimension is not split.
+template <typename TC, typename TAs, typename TBs>
+nys_status gemm(bool ta, bool tb, int64_t M, int64_t N, int64_t K, TC alpha, const TAs* A,
+                int64_t lda, const TBs* B, int64_t ldb, TC beta, TC* C, int64_t ldc, TC* scratch,
+                size_t scratch_elems, hipStream_t s, const int* skip = nullptr);
+
+// Scratch that lets gemm() split K for an M x N output.
+// gemm() splits K only when the output has fewer than 512 tiles of 64 x 64.
+inline size_t gemm_scratch_elems(int64_t M, int64_t N) {
+  const int64_t tiles = ((M + 63) / 64) * ((N + 63) / 64);
+  return tiles >= 512 ? 0 : (size_t)(16 * M * N);
+}
+
+}  // namespace nys

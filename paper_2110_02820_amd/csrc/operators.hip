@@ -1,0 +1,603 @@
+// Operator products V = A P for the three operator forms (Section 1.1: A is
+// touched only through products), gfx950.
+//
+//  * dense    : row-per-wave GEMV (k = 1) or the MFMA GEMM (k > 1)
+//  * X^T X    : one pass over X per product (Section 1.4 ridge normal
+//               equations).  Each workgroup owns a contiguous range of rows of
+//               X, keeps R rows in registers, forms t_r = x_r^T p with a block
+//               reduction and immediately accumulates t_r x_r into a per-
+//               workgroup partial of X^T t held in registers.  X is read from
+//               HBM exactly once; a second kernel sums the partials in fixed
+//               order (deterministic) and adds mu p.
+//  * RBF      : K_ij = exp(-||x_i - x_j||^2 / (2 sigma^2)) evaluated tile by
+//               tile and never stored (Section 6.3 kernel ridge regression).
+//               float64 forms: a VALU kernel for one vector, and an MFMA
+//               (v_mfma_f64_16x16x4f64) kernel for blocks of columns
+//               (the sketch A Omega, block PCG).
+#include "operators.hpp"
+#include "gemm.hpp"
+
+namespace nys {
+
+namespace {
+
+// ------------------------------------------------------------- dense GEMV
+
+template <typename TD, typename T>
+__global__ __launch_bounds__(256) void dense_gemv(const TD* __restrict__ A, int64_t n, int64_t ld,
+                                                  T scale, const T* __restrict__ p, T mu,
+                                                  T* __restrict__ v, const int* __restrict__ skip) {
+  if (skip && *skip) return;
+  const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (row >= n) return;
+  const TD* a = A + row * ld;
+  T s = T(0);
+  for (int64_t j = lane; j < n; j += 64) s += T(a[j]) * p[j];
+  s = wave_sum(s);
+  if (lane == 0) v[row] = scale * s + mu * p[row];
+}
+
+// V[i][c] += mu_c P[i][c]
+template <typename T>
+__global__ void add_mu(T* __restrict__ V, int64_t ldv, const T* __restrict__ P, int64_t ldp,
+                       int64_t n, int64_t k, const double* __restrict__ mu, int64_t nrhs,
+                       const int* __restrict__ skip) {
+  if (skip && *skip) return;
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= n * k) return;
+  const int64_t i = idx / k, c = idx % k;
+  V[i * ldv + c] += T(mu[c / nrhs]) * P[i * ldp + c];
+}
+
+// ------------------------------------------------------------- X^T X
+
+template <typename TD>
+struct Vec16;
+template <>
+struct Vec16<float> {
+  typedef float4 type;
+  static constexpr int E = 4;
+  static __device__ __forceinline__ float get(const float4& v, int e) {
+    return e == 0 ? v.x : e == 1 ? v.y : e == 2 ? v.z : v.w;
+  }
+};
+template <>
+struct Vec16<double> {
+  typedef double2 type;
+  static constexpr int E = 2;
+  static __device__ __forceinline__ double get(const double2& v, int e) { return e == 0 ? v.x : v.y; }
+};
+// one element per load: rows that are not 16-byte aligned
+template <typename TD>
+struct Vec1 {
+  typedef TD type;
+  static constexpr int E = 1;
+  static __device__ __forceinline__ TD get(const TD& v, int) { return v; }
+};
+
+// part[g][j] = sum over rows r of this workgroup of (x_r^T p) x_r[j]
+// (accumulated in TA).  Requires n <= 256 * NV * E and 16-byte aligned rows.
+template <typename TD, typename TA, typename VP, int NV, int R>
+__global__ __launch_bounds__(256) void xtx_fused(const TD* __restrict__ X, int64_t m, int64_t n,
+                                                 int64_t ld, const TA* __restrict__ p,
+                                                 TA* __restrict__ part, int64_t rows_per_wg,
+                                                 const int* __restrict__ skip) {
+  if (skip && *skip) return;
+  typedef typename VP::type VT;
+  constexpr int E = VP::E;
+  __shared__ TA red[2][4][R];
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  TA pr[NV][E];
+  TA acc[NV][E];
+#pragma unroll
+  for (int v = 0; v < NV; ++v)
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int64_t col = ((int64_t)v * 256 + t) * E + e;
+      pr[v][e] = col < n ? p[col] : TA(0);
+      acc[v][e] = TA(0);
+    }
+  const int64_t r0 = (int64_t)blockIdx.x * rows_per_wg;
+  const int64_t r1 = (r0 + rows_per_wg < m) ? r0 + rows_per_wg : m;
+  const int64_t nvec = n / E;  // full vectors per row
+  int buf = 0;
+  for (int64_t rb = r0; rb < r1; rb += R) {
+    VT xr[R][NV];
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        const int64_t vi = (int64_t)v * 256 + t;
+        if (rb + r < r1 && vi < nvec) {
+          xr[r][v] = *reinterpret_cast<const VT*>(X + (rb + r) * ld + vi * E);
+        } else {
+          VT z;
+          for (int e = 0; e < E; ++e) reinterpret_cast<TD*>(&z)[e] = TD(0);
+          // tail elements of a row whose length is not a multiple of E
+          if (rb + r < r1 && vi == nvec)
+            for (int e = 0; e < E; ++e)
+              if (vi * E + e < n) reinterpret_cast<TD*>(&z)[e] = X[(rb + r) * ld + vi * E + e];
+          xr[r][v] = z;
+        }
+      }
+    TA d[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      TA s = TA(0);
+#pragma unroll
+      for (int v = 0; v < NV; ++v)
+#pragma unroll
+        for (int e = 0; e < E; ++e) s += TA(VP::get(xr[r][v], e)) * pr[v][e];
+      d[r] = wave_sum(s);
+    }
+    if (lane == 0) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) red[buf][wave][r] = d[r];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const TA tr = red[buf][0][r] + red[buf][1][r] + red[buf][2][r] + red[buf][3][r];
+#pragma unroll
+      for (int v = 0; v < NV; ++v)
+#pragma unroll
+        for (int e = 0; e < E; ++e) acc[v][e] += tr * TA(VP::get(xr[r][v], e));
+    }
+    buf ^= 1;  // the other buffer is free: its readers passed this barrier
+  }
+  TA* out = part + (int64_t)blockIdx.x * n;
+#pragma unroll
+  for (int v = 0; v < NV; ++v)
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int64_t col = ((int64_t)v * 256 + t) * E + e;
+      if (col < n) out[col] = acc[v][e];
+    }
+}
+
+// out[j] = alpha * sum_g part[g][j] + beta * y[j]   (fixed order over g)
+template <typename TA, typename TO>
+__global__ void reduce_cols(const TA* __restrict__ part, int ng, int64_t n, TA alpha,
+                            const TO* __restrict__ y, TA beta, TO* __restrict__ out,
+                            const int* __restrict__ skip) {
+  if (skip && *skip) return;
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  TA s = TA(0);
+  for (int g = 0; g < ng; ++g) s += part[(int64_t)g * n + j];
+  TA o = alpha * s;
+  if (y) o += beta * TA(y[j]);
+  out[j] = TO(o);
+}
+
+// ------------------------------------------------------------- RBF, float64
+
+constexpr int RB_ROWS = 64;   // rows per workgroup
+constexpr int RB_PTS = 64;    // points per staged tile
+
+// One vector, rectangular: part[s][i] = sum_{j in split s} W_ij p_j with
+// W = K(Xr, Xc) (MODE 0) or W = dK/dsigma = K .* D2 / sigma^3 (MODE 1).
+// Thread (il, q): row il of the block, points j = q (mod 4) of every tile.
+template <typename TD, int DMAX, int MODE>
+__global__ __launch_bounds__(256) void rbf_mv_f64(const TD* __restrict__ Xr, int64_t nr, int64_t ldr,
+                                                  const TD* __restrict__ Xc, int64_t nc, int64_t ldc,
+                                                  int d, double c2, double inv_s3,
+                                                  const double* __restrict__ p,
+                                                  double* __restrict__ part, int64_t pts_per_split,
+                                                  const int* __restrict__ skip) {
+  if (skip && *skip) return;
+  __shared__ double Xs[RB_PTS][DMAX + 1];
+  __shared__ double Ns[RB_PTS];
+  __shared__ double Ps[RB_PTS];
+  __shared__ double Red[4][RB_ROWS];
+  const int t = threadIdx.x, il = t & 63, q = t >> 6;
+  const int64_t i = (int64_t)blockIdx.x * RB_ROWS + il;
+  double xi[DMAX];
+  double ni = 0.0;
+#pragma unroll
+  for (int k = 0; k < DMAX; ++k) {
+    xi[k] = (i < nr && k < d) ? double(Xr[i * ldr + k]) : 0.0;
+    ni += xi[k] * xi[k];
+  }
+  const int64_t j0 = (int64_t)blockIdx.y * pts_per_split;
+  const int64_t j1 = (j0 + pts_per_split < nc) ? j0 + pts_per_split : nc;
+  double acc = 0.0;
+  for (int64_t jt = j0; jt < j1; jt += RB_PTS) {
+    __syncthreads();
+    for (int e = t; e < RB_PTS * DMAX; e += 256) {
+      const int jj = e / DMAX, k = e % DMAX;
+      const int64_t j = jt + jj;
+      Xs[jj][k] = (j < j1 && k < d) ? double(Xc[j * ldc + k]) : 0.0;
+    }
+    __syncthreads();
+    if (t < RB_PTS) {
+      double s = 0.0;
+      for (int k = 0; k < DMAX; ++k) s += Xs[t][k] * Xs[t][k];
+      Ns[t] = s;
+      Ps[t] = (jt + t < j1) ? p[jt + t] : 0.0;
+    }
+    __syncthreads();
+    for (int jj = q; jj < RB_PTS; jj += 4) {
+      double g = 0.0;
+#pragma unroll
+      for (int k = 0; k < DMAX; ++k) g += xi[k] * Xs[jj][k];
+      const double d2 = fmax(ni + Ns[jj] - 2.0 * g, 0.0);
+      const double kv = exp(-d2 * c2);
+      acc += (MODE == 0 ? kv : kv * d2 * inv_s3) * Ps[jj];
+    }
+  }
+  Red[q][il] = acc;
+  __syncthreads();
+  if (q == 0 && i < nr)
+    part[(int64_t)blockIdx.y * nr + i] = Red[0][il] + Red[1][il] + Red[2][il] + Red[3][il];
+}
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+// Block of columns: V[I, c0:c0+64] (+)= K_IJ P[J, c0:c0+64] with MFMA f64.
+// Grid: (row blocks, column chunks of 64, point splits).  Output partials
+// part[split][i][c] (ld = k) when splits > 1, else V directly.
+template <typename TD, int DMAX>
+__global__ __launch_bounds__(256) void rbf_kv_f64(const TD* __restrict__ X, int64_t n, int d,
+                                                  int64_t ld, double c2, const double* __restrict__ P,
+                                                  int64_t ldp, int64_t k, double* __restrict__ out,
+                                                  int64_t ldo, int64_t pts_per_split,
+                                                  const int* __restrict__ skip) {
+  if (skip && *skip) return;
+  __shared__ double Xi[RB_ROWS][DMAX + 1];
+  __shared__ double Xj[RB_PTS][DMAX + 1];
+  __shared__ double Ni[RB_ROWS], Nj[RB_PTS];
+  __shared__ double Ks[RB_PTS][RB_ROWS + 2];  // Ks[j][i]
+  __shared__ double Ps[RB_PTS][64 + 2];       // Ps[j][c]
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int64_t i0 = (int64_t)blockIdx.x * RB_ROWS;
+  const int64_t cb = (int64_t)blockIdx.y * 64;
+  const int64_t j0 = (int64_t)blockIdx.z * pts_per_split;
+  const int64_t j1 = (j0 + pts_per_split < n) ? j0 + pts_per_split : n;
+  for (int e = t; e < RB_ROWS * DMAX; e += 256) {
+    const int ii = e / DMAX, kk = e % DMAX;
+    Xi[ii][kk] = (i0 + ii < n && kk < d) ? double(X[(i0 + ii) * ld + kk]) : 0.0;
+  }
+  __syncthreads();
+  if (t < RB_ROWS) {
+    double s = 0.0;
+    for (int kk = 0; kk < DMAX; ++kk) s += Xi[t][kk] * Xi[t][kk];
+    Ni[t] = s;
+  }
+  d4 acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = d4{0, 0, 0, 0};
+  for (int64_t jt = j0; jt < j1; jt += RB_PTS) {
+    __syncthreads();
+    for (int e = t; e < RB_PTS * DMAX; e += 256) {
+      const int jj = e / DMAX, kk = e % DMAX;
+      Xj[jj][kk] = (jt + jj < j1 && kk < d) ? double(X[(jt + jj) * ld + kk]) : 0.0;
+    }
+    for (int e = t; e < RB_PTS * 64; e += 256) {
+      const int jj = e / 64, cc = e % 64;
+      Ps[jj][cc] = (jt + jj < j1 && cb + cc < k) ? P[(jt + jj) * ldp + cb + cc] : 0.0;
+    }
+    __syncthreads();
+    if (t < RB_PTS) {
+      double s = 0.0;
+      for (int kk = 0; kk < DMAX; ++kk) s += Xj[t][kk] * Xj[t][kk];
+      Nj[t] = s;
+    }
+    __syncthreads();
+    // kernel tile: 16 entries per thread
+    for (int e = t; e < RB_ROWS * RB_PTS; e += 256) {
+      const int ii = e / RB_PTS, jj = e % RB_PTS;
+      double g = 0.0;
+#pragma unroll
+      for (int kk = 0; kk < DMAX; ++kk) g += Xi[ii][kk] * Xj[jj][kk];
+      const double d2 = fmax(Ni[ii] + Nj[jj] - 2.0 * g, 0.0);
+      Ks[jj][ii] = (jt + jj < j1) ? exp(-d2 * c2) : 0.0;
+    }
+    __syncthreads();
+    // acc(64 rows x 64 cols) += K(64 x 64 pts) * P(64 pts x 64 cols)
+#pragma unroll 4
+    for (int kk = 0; kk < RB_PTS; kk += 4) {
+      const int kq = kk + (lane >> 4);
+      const double a0 = Ks[kq][wm * 32 + (lane & 15)];
+      const double a1 = Ks[kq][wm * 32 + 16 + (lane & 15)];
+      const double b0 = Ps[kq][wn * 32 + (lane & 15)];
+      const double b1 = Ps[kq][wn * 32 + 16 + (lane & 15)];
+      acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+      acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+      acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+      acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+    }
+  }
+  double* o = out + (int64_t)blockIdx.z * n * ldo;
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int qq = 0; qq < 4; ++qq) {
+        // f64 MFMA accumulator element qq of lane l holds row 4 qq + l/16
+        const int64_t gi = i0 + wm * 32 + a * 16 + 4 * qq + (lane >> 4);
+        const int64_t gc = cb + wn * 32 + b * 16 + (lane & 15);
+        if (gi < n && gc < k) o[gi * ldo + gc] = acc[a][b][qq];
+      }
+}
+
+// out[i][c] = sum_s part[s][i][c] (+ mu_c P[i][c]) for n x k
+__global__ void reduce_splits_mu(const double* __restrict__ part, int ns, int64_t n, int64_t k,
+                                 const double* __restrict__ P, int64_t ldp,
+                                 const double* __restrict__ mu, int64_t nrhs,
+                                 double* __restrict__ out, int64_t ldo,
+                                 const int* __restrict__ skip) {
+  if (skip && *skip) return;
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= n * k) return;
+  const int64_t i = idx / k, c = idx % k;
+  double s = 0.0;
+  for (int q = 0; q < ns; ++q) s += part[((int64_t)q * n + i) * k + c];
+  if (mu) s += mu[c / nrhs] * P[i * ldp + c];
+  out[i * ldo + c] = s;
+}
+
+int rbf_dmax(int64_t d) { return d <= 8 ? 8 : d <= 16 ? 16 : d <= 32 ? 32 : d <= 64 ? 64 : -1; }
+
+template <typename TD>
+nys_status rbf_apply_f64_t(const OpDesc& op, const double* P, int64_t k, int64_t ldp,
+                           const double* mu_dev, int64_t nrhs, double* V, int64_t ldv,
+                           double* scratch, size_t scratch_elems, hipStream_t s) {
+  const TD* X = static_cast<const TD*>(op.data);
+  const int64_t n = op.n;
+  const int d = (int)op.cols;
+  const double c2 = 1.0 / (2.0 * op.sigma * op.sigma);
+  const int dm = rbf_dmax(d);
+  if (dm < 0) {
+    set_error("RBF operator: d = %d > 64 not supported", d);
+    return NYS_ERR_ARG;
+  }
+  const int64_t nrb = cdiv(n, RB_ROWS);
+  const int cus = num_cus() < 256 ? num_cus() : 256;
+  if (k == 1 && ldp == 1) {
+    int64_t ns = cdiv(4 * cus, nrb);
+    if (ns < 1) ns = 1;
+    while (ns > 1 && (size_t)(ns * n) > scratch_elems) --ns;
+    const int64_t pps = cdiv(cdiv(n, ns), RB_PTS) * RB_PTS;
+    ns = cdiv(n, pps);
+    dim3 grid((unsigned)nrb, (unsigned)ns);
+#define L1(DM) hipLaunchKernelGGL((rbf_mv_f64<TD, DM, 0>), grid, dim3(256), 0, s, X, n, op.ld, X, n, op.ld, d, c2, 0.0, P, scratch, pps, op.skip)
+    if (dm == 8) L1(8); else if (dm == 16) L1(16); else if (dm == 32) L1(32); else L1(64);
+#undef L1
+    NYS_CHECK_LAUNCH();
+    hipLaunchKernelGGL(reduce_splits_mu, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, s, scratch,
+                       (int)ns, n, (int64_t)1, P, ldp, mu_dev, nrhs, V, ldv, op.skip);
+    NYS_CHECK_LAUNCH();
+    return NYS_OK;
+  }
+  const int64_t ncb = cdiv(k, 64);
+  int64_t ns = cdiv(2 * cus, nrb * ncb);
+  if (ns < 1) ns = 1;
+  while (ns > 1 && (size_t)(ns * n * k) > scratch_elems) --ns;
+  const int64_t pps = cdiv(cdiv(n, ns), RB_PTS) * RB_PTS;
+  ns = cdiv(n, pps);
+  dim3 grid((unsigned)nrb, (unsigned)ncb, (unsigned)ns);
+  double* o = ns > 1 ? scratch : V;
+  const int64_t ldo = ns > 1 ? k : ldv;
+#define L2(DM) hipLaunchKernelGGL((rbf_kv_f64<TD, DM>), grid, dim3(256), 0, s, X, n, d, op.ld, c2, P, ldp, k, o, ldo, pps, op.skip)
+  if (dm == 8) L2(8); else if (dm == 16) L2(16); else if (dm == 32) L2(32); else L2(64);
+#undef L2
+  NYS_CHECK_LAUNCH();
+  if (ns > 1 || mu_dev) {
+    if (ns == 1) {
+      // V holds K P; add mu P in place
+      hipLaunchKernelGGL(add_mu<double>, dim3((unsigned)cdiv(n * k, 256)), dim3(256), 0, s, V, ldv,
+                         P, ldp, n, k, mu_dev, nrhs, op.skip);
+    } else {
+      hipLaunchKernelGGL(reduce_splits_mu, dim3((unsigned)cdiv(n * k, 256)), dim3(256), 0, s,
+                         scratch, (int)ns, n, k, P, ldp, mu_dev, nrhs, V, ldv, op.skip);
+    }
+    NYS_CHECK_LAUNCH();
+  }
+  return NYS_OK;
+}
+
+template <typename TD, typename TA>
+nys_status xtx_apply_t(const OpDesc& op, const TA* p, TA mu, TA* v, TA* scratch,
+                       size_t scratch_elems, hipStream_t s) {
+  const TD* X = static_cast<const TD*>(op.data);
+  const int64_t m = op.rows, n = op.n;
+  constexpr int E = Vec16<TD>::E;
+  const bool aligned = (op.ld % E == 0) && ((uintptr_t)X % 16 == 0);
+  const int64_t need_nv = aligned ? cdiv(n, 256 * E) : cdiv(n, 256);
+  int64_t ng = 2 * (num_cus() < 256 ? num_cus() : 256);
+  const int64_t R = 4;
+  if (ng > cdiv(m, R)) ng = cdiv(m, R);
+  if (ng < 1) ng = 1;
+  while (ng > 1 && (size_t)(ng * n) > scratch_elems) ng /= 2;
+  int64_t rpw = cdiv(cdiv(m, ng), R) * R;
+  ng = cdiv(m, rpw);
+  if ((aligned && need_nv > 8) || (!aligned && need_nv > 32)) {
+    set_error("X^T X operator: n = %lld too large for the one-pass kernel", (long long)n);
+    return NYS_ERR_ARG;
+  }
+#define LX(VP_, NV, RR) hipLaunchKernelGGL((xtx_fused<TD, TA, VP_, NV, RR>), dim3((unsigned)ng), dim3(256), 0, s, X, m, n, op.ld, p, scratch, rpw, op.skip)
+  if (aligned) {
+    if (need_nv <= 1) LX(Vec16<TD>, 1, 4);
+    else if (need_nv <= 2) LX(Vec16<TD>, 2, 4);
+    else if (need_nv <= 4) LX(Vec16<TD>, 4, 4);
+    else LX(Vec16<TD>, 8, 2);
+  } else {
+    if (need_nv <= 4) LX(Vec1<TD>, 4, 4);
+    else if (need_nv <= 8) LX(Vec1<TD>, 8, 4);
+    else if (need_nv <= 16) LX(Vec1<TD>, 16, 4);
+    else LX(Vec1<TD>, 32, 2);
+  }
+#undef LX
+  NYS_CHECK_LAUNCH();
+  hipLaunchKernelGGL((reduce_cols<TA, TA>), dim3((unsigned)cdiv(n, 256)), dim3(256), 0, s, scratch,
+                     (int)ng, n, TA(op.scale), p, mu, v, op.skip);
+  NYS_CHECK_LAUNCH();
+  return NYS_OK;
+}
+
+template <typename TD>
+nys_status rbf_rect_t(const TD* Xr, int64_t nr, int64_t ldr, const TD* Xc, int64_t nc, int64_t ldc,
+                      int d, double sigma, int mode, const double* p, double* out, double* scratch,
+                      size_t scratch_elems, hipStream_t s) {
+  const int dm = rbf_dmax(d);
+  if (dm < 0) {
+    set_error("RBF operator: d = %d > 64 not supported", d);
+    return NYS_ERR_ARG;
+  }
+  const double c2 = 1.0 / (2.0 * sigma * sigma);
+  const double is3 = 1.0 / (sigma * sigma * sigma);
+  const int64_t nrb = cdiv(nr, RB_ROWS);
+  int64_t ns = cdiv(4 * (num_cus() < 256 ? num_cus() : 256), nrb);
+  if (ns < 1) ns = 1;
+  while (ns > 1 && (size_t)(ns * nr) > scratch_elems) --ns;
+  const int64_t pps = cdiv(cdiv(nc, ns), RB_PTS) * RB_PTS;
+  ns = cdiv(nc, pps);
+  dim3 grid((unsigned)nrb, (unsigned)ns);
+#define L3(DM, MD) hipLaunchKernelGGL((rbf_mv_f64<TD, DM, MD>), grid, dim3(256), 0, s, Xr, nr, ldr, Xc, nc, ldc, d, c2, is3, p, scratch, pps, (const int*)nullptr)
+#define L3D(MD) if (dm == 8) L3(8, MD); else if (dm == 16) L3(16, MD); else if (dm == 32) L3(32, MD); else L3(64, MD)
+  if (mode == 0) { L3D(0); } else { L3D(1); }
+#undef L3D
+#undef L3
+  NYS_CHECK_LAUNCH();
+  hipLaunchKernelGGL(reduce_splits_mu, dim3((unsigned)cdiv(nr, 256)), dim3(256), 0, s, scratch,
+                     (int)ns, nr, (int64_t)1, (const double*)nullptr, (int64_t)1,
+                     (const double*)nullptr, (int64_t)1, out, (int64_t)1, (const int*)nullptr);
+  NYS_CHECK_LAUNCH();
+  return NYS_OK;
+}
+
+}  // namespace
+
+size_t op_scratch_elems(const OpDesc& op, int64_t k) {
+  if (op.kind == NYS_OP_XTX) {
+    const size_t t = (size_t)(op.rows * k);
+    return (size_t)(2 * 256 * op.n) + t + gemm_scratch_elems(op.rows, k) + gemm_scratch_elems(op.n, k);
+  }
+  if (op.kind == NYS_OP_RBF) {
+    const size_t one = (size_t)(4 * 256) * (size_t)op.n;
+    const int64_t tiles = cdiv(op.n, RB_ROWS) * cdiv(k, 64);
+    const int64_t ns = cdiv(2 * 256, tiles);
+    const size_t blk = ns > 1 ? (size_t)ns * (size_t)op.n * (size_t)k : 0;
+    return one > blk ? one : blk;
+  }
+  return gemm_scratch_elems(op.n, k);
+}
+
+// V = A P + mu_c P_c (mu_dev == nullptr: no shift).  float64 arithmetic.
+nys_status op_apply_f64(const OpDesc& op, const double* P, int64_t k, int64_t ldp,
+                        const double* mu_dev, int64_t nrhs, double* V, int64_t ldv,
+                        double* scratch, size_t scratch_elems, hipStream_t s) {
+  const int64_t n = op.n;
+  if (op.kind == NYS_OP_DENSE) {
+    if (k == 1 && ldp == 1 && ldv == 1) {
+      // mu is applied by the caller-visible convention: handled by add_mu below
+      if (op.dtype == NYS_F64)
+        hipLaunchKernelGGL((dense_gemv<double, double>), dim3((unsigned)cdiv(n, 4)), dim3(256), 0, s,
+                           static_cast<const double*>(op.data), n, op.ld, op.scale, P, 0.0, V, op.skip);
+      else
+        hipLaunchKernelGGL((dense_gemv<float, double>), dim3((unsigned)cdiv(n, 4)), dim3(256), 0, s,
+                           static_cast<const float*>(op.data), n, op.ld, op.scale, P, 0.0, V, op.skip);
+      NYS_CHECK_LAUNCH();
+    } else {
+      if (op.dtype == NYS_F64)
+        NYS_TRY((gemm<double, double, double>(false, false, n, k, n, op.scale,
+                                              static_cast<const double*>(op.data), op.ld, P, ldp,
+                                              0.0, V, ldv, scratch, scratch_elems, s, op.skip)));
+      else
+        NYS_TRY((gemm<double, float, double>(false, false, n, k, n, op.scale,
+                                             static_cast<const float*>(op.data), op.ld, P, ldp, 0.0,
+                                             V, ldv, scratch, scratch_elems, s, op.skip)));
+    }
+    if (mu_dev) {
+      hipLaunchKernelGGL(add_mu<double>, dim3((unsigned)cdiv(n * k, 256)), dim3(256), 0, s, V, ldv,
+                         P, ldp, n, k, mu_dev, nrhs, op.skip);
+      NYS_CHECK_LAUNCH();
+    }
+    return NYS_OK;
+  }
+  if (op.kind == NYS_OP_XTX) {
+    if (k == 1 && ldp == 1 && ldv == 1 && !mu_dev) {
+      if (op.dtype == NYS_F64)
+        return xtx_apply_t<double, double>(op, P, 0.0, V, scratch, scratch_elems, s);
+      return xtx_apply_t<float, double>(op, P, 0.0, V, scratch, scratch_elems, s);
+    }
+    // T = X P (m x k) then V = scale X^T T
+    double* T = scratch;
+    double* rest = scratch + op.rows * k;
+    const size_t rest_elems = scratch_elems - (size_t)(op.rows * k);
+    if (op.dtype == NYS_F64) {
+      const double* X = static_cast<const double*>(op.data);
+      NYS_TRY((gemm<double, double, double>(false, false, op.rows, k, n, 1.0, X, op.ld, P, ldp, 0.0,
+                                            T, k, rest, rest_elems, s, op.skip)));
+      NYS_TRY((gemm<double, double, double>(true, false, n, k, op.rows, op.scale, X, op.ld, T, k,
+                                            0.0, V, ldv, rest, rest_elems, s, op.skip)));
+    } else {
+      const float* X = static_cast<const float*>(op.data);
+      NYS_TRY((gemm<double, float, double>(false, false, op.rows, k, n, 1.0, X, op.ld, P, ldp, 0.0,
+                                           T, k, rest, rest_elems, s, op.skip)));
+      NYS_TRY((gemm<double, float, double>(true, false, n, k, op.rows, op.scale, X, op.ld, T, k, 0.0,
+                                           V, ldv, rest, rest_elems, s, op.skip)));
+    }
+    if (mu_dev) {
+      hipLaunchKernelGGL(add_mu<double>, dim3((unsigned)cdiv(n * k, 256)), dim3(256), 0, s, V, ldv,
+                         P, ldp, n, k, mu_dev, nrhs, op.skip);
+      NYS_CHECK_LAUNCH();
+    }
+    return NYS_OK;
+  }
+  if (op.kind == NYS_OP_RBF) {
+    if (op.dtype == NYS_F64)
+      return rbf_apply_f64_t<double>(op, P, k, ldp, mu_dev, nrhs, V, ldv, scratch, scratch_elems, s);
+    return rbf_apply_f64_t<float>(op, P, k, ldp, mu_dev, nrhs, V, ldv, scratch, scratch_elems, s);
+  }
+  set_error("unknown operator kind %d", op.kind);
+  return NYS_ERR_ARG;
+}
+
+// Single vector, fused shift: v = A p + mu p, arithmetic in TA.
+template <typename TA>
+nys_status op_matvec(const OpDesc& op, const TA* p, TA mu, TA* v, TA* scratch, size_t scratch_elems,
+                     hipStream_t s) {
+  const int64_t n = op.n;
+  if (op.kind == NYS_OP_XTX) {
+    if (op.dtype == NYS_F64) return xtx_apply_t<double, TA>(op, p, mu, v, scratch, scratch_elems, s);
+    return xtx_apply_t<float, TA>(op, p, mu, v, scratch, scratch_elems, s);
+  }
+  if (op.kind == NYS_OP_DENSE) {
+    if (op.dtype == NYS_F64)
+      hipLaunchKernelGGL((dense_gemv<double, TA>), dim3((unsigned)cdiv(n, 4)), dim3(256), 0, s,
+                         static_cast<const double*>(op.data), n, op.ld, TA(op.scale), p, mu, v, op.skip);
+    else
+      hipLaunchKernelGGL((dense_gemv<float, TA>), dim3((unsigned)cdiv(n, 4)), dim3(256), 0, s,
+                         static_cast<const float*>(op.data), n, op.ld, TA(op.scale), p, mu, v, op.skip);
+    NYS_CHECK_LAUNCH();
+    return NYS_OK;
+  }
+  set_error("op_matvec: unsupported operator for this precision");
+  return NYS_ERR_ARG;
+}
+
+template nys_status op_matvec<double>(const OpDesc&, const double*, double, double*, double*, size_t,
+                                      hipStream_t);
+template nys_status op_matvec<float>(const OpDesc&, const float*, float, float*, float*, size_t,
+                                     hipStream_t);
+
+}  // namespace nys
+
+namespace nys {
+nys_status rbf_rect_mv(const void* Xr, int64_t nr, int64_t ldr, const void* Xc, int64_t nc,
+                       int64_t ldc, int d, int dtype, double sigma, int mode, const double* p,
+                       double* out, double* scratch, size_t scratch_elems, hipStream_t s) {
+  if (dtype == NYS_F64)
+    return rbf_rect_t<double>(static_cast<const double*>(Xr), nr, ldr, static_cast<const double*>(Xc),
+                              nc, ldc, d, sigma, mode, p, out, scratch, scratch_elems, s);
+  return rbf_rect_t<float>(static_cast<const float*>(Xr), nr, ldr, static_cast<const float*>(Xc), nc,
+                           ldc, d, sigma, mode, p, out, scratch, scratch_elems, s);
+}
+}  // namespace nys

@@ -1,0 +1,39 @@
+#pragma once
+#include "common.hpp"
+
+namespace nys {
+
+// Validated copy of a nys_operator.
+struct OpDesc {
+  int kind;
+  int dtype;
+  int64_t n;
+  const void* data;
+  int64_t rows, cols, ld;
+  double sigma, scale;
+  const int* skip = nullptr;  // device flag: kernels return at once when *skip != 0
+};
+
+// Scratch (in elements of the arithmetic type) used by one operator product
+// with k columns.
+size_t op_scratch_elems(const OpDesc& op, int64_t k);
+
+// V = A P + mu_c P_c for k columns, float64 arithmetic (float32 data promoted
+// exactly).  mu_dev: device array indexed by c / nrhs, or nullptr for V = A P.
+nys_status op_apply_f64(const OpDesc& op, const double* P, int64_t k, int64_t ldp,
+                        const double* mu_dev, int64_t nrhs, double* V, int64_t ldv,
+                        double* scratch, size_t scratch_elems, hipStream_t s);
+
+// One contiguous vector: v = A p + mu p in arithmetic TA (XTX and dense).
+template <typename TA>
+nys_status op_matvec(const OpDesc& op, const TA* p, TA mu, TA* v, TA* scratch, size_t scratch_elems,
+                     hipStream_t s);
+
+// out (nr) = W p with W = K(Xr, Xc) (mode 0) or dK/dsigma (mode 1), float64
+// arithmetic; Xr: nr x d (ldr), Xc: nc x d (ldc), both of storage `dtype`.
+// scratch: >= 4 * 256 * nr doubles.
+nys_status rbf_rect_mv(const void* Xr, int64_t nr, int64_t ldr, const void* Xc, int64_t nc,
+                       int64_t ldc, int d, int dtype, double sigma, int mode, const double* p,
+                       double* out, double* scratch, size_t scratch_elems, hipStream_t s);
+
+}  // namespace nys

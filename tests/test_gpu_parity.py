@@ -1,0 +1,316 @@
+"""Parity of the HIP path (through the C ABI) against the CPU FP64 oracle.
+
+Inputs come from the seeded generators in ``workloads``; the oracle never
+receives a value computed by the device.  Where a result is unique only up to
+signs/rotations (Omega after QR, U), the test compares invariant quantities
+(A Omega Omega^T, U Lambda U^T, P^{-1} r).
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle  # noqa: E402
+from workloads import krr_small, lowrank_psd, ridge_dense, spectrum_psd  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2110_02820_amd as nys  # noqa: E402
+
+DEV = "cuda"
+
+
+def t64(a):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=DEV)
+
+
+def t32(a):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float32, device=DEV)
+
+
+def h(t):
+    return t.detach().double().cpu().numpy()
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+def test_library_loaded():
+    assert nys.lib().nys_version().startswith(b"nyspcg")
+
+
+@pytest.mark.parametrize("n,ell,seed", [(37, 13, 7), (1000, 64, 20211001), (3, 1, 5)])
+def test_gaussian_matches_philox_oracle(n, ell, seed):
+    dev = h(nys.nys_gaussian(seed, n, ell))
+    ref = oracle.gaussian_philox(seed, n, ell)
+    np.testing.assert_allclose(dev, ref, rtol=1e-13, atol=1e-13)
+
+
+@pytest.mark.parametrize("kind", ["dense", "xtx32", "xtx64", "rbf64", "rbf32"])
+@pytest.mark.parametrize("k", [1, 3, 70])
+def test_op_apply(kind, k):
+    rng = np.random.default_rng(100 + k)
+    if kind == "dense":
+        A = spectrum_psd(1.0 / np.arange(1, 302), 3)
+        op, ref = nys.Operator.dense(t64(A)), oracle.DenseOp(A)
+    elif kind.startswith("xtx"):
+        X = rng.standard_normal((517, 301)).astype(np.float32 if kind == "xtx32" else np.float64)
+        op = nys.Operator.xtx(t32(X) if kind == "xtx32" else t64(X), scale=0.5)
+        ref = oracle.XtXOp(X, 0.5)
+    else:
+        X = rng.standard_normal((301, 17)).astype(np.float32 if kind == "rbf32" else np.float64)
+        op = nys.Operator.rbf(t32(X) if kind == "rbf32" else t64(X), 2.3)
+        ref = oracle.RBFOp(X, 2.3)
+    V = rng.standard_normal((301, k))
+    mu = 0.37
+    out = h(nys.nys_op_apply(op, mu, t64(V)))
+    np.testing.assert_allclose(out, ref.matmat(V) + mu * V, rtol=1e-12, atol=1e-12)
+
+
+@pytest.mark.parametrize("d", [1, 8, 33])
+def test_rbf_single_vector_dims(d):
+    rng = np.random.default_rng(200 + d)
+    X = rng.standard_normal((777, d)) * 1.5
+    v = rng.standard_normal(777)
+    op = nys.Operator.rbf(t64(X), 1.9)
+    out = h(nys.nys_op_apply(op, 0.0, t64(v)))
+    np.testing.assert_allclose(out, oracle.RBFOp(X, 1.9).matmat(v), rtol=1e-12, atol=1e-12)
+
+
+def test_xtx_single_vector_f32_arith():
+    """float32 arithmetic over float32 data: within float32 rounding of the oracle."""
+    w = ridge_dense(m=3000, n=1000, ell=50, seed=5)
+    X = w["X"]
+    v = np.random.default_rng(6).standard_normal(1000)
+    op = nys.Operator.xtx(t32(X))
+    out = h(nys.nys_op_apply(op, 1e-4, t32(v).to(torch.float32)))
+    ref = oracle.XtXOp(X).matmat(v) + 1e-4 * v
+    assert rel(out, ref) < 1e-5
+
+
+def _sketch_case(n=300, ell=23, seed=41):
+    A = spectrum_psd(1.0 / np.arange(1, n + 1) ** 1.5, seed)
+    om0 = np.random.default_rng(seed + 1).standard_normal((n, ell))
+    return A, om0
+
+
+def test_sketch_is_range_invariant_match():
+    A, om0 = _sketch_case()
+    op = nys.Operator.dense(t64(A))
+    Om, Y = nys.nys_sketch(op, om0.shape[1], omega0=t64(om0))
+    Om, Y = h(Om), h(Y)
+    np.testing.assert_allclose(Om.T @ Om, np.eye(om0.shape[1]), atol=1e-13)
+    Q = oracle.orthonormalize(om0)
+    np.testing.assert_allclose(Om @ Om.T, Q @ Q.T, atol=1e-12)
+    np.testing.assert_allclose(Y @ Om.T, A @ Q @ Q.T, atol=1e-12)
+
+
+@pytest.mark.parametrize("n,ell", [(300, 23), (517, 64), (200, 1), (130, 130)])
+def test_factor_matches_oracle(n, ell):
+    A, om0 = _sketch_case(n, ell, seed=n + ell)
+    op = nys.Operator.dense(t64(A))
+    Om, Y = nys.nys_sketch(op, ell, omega0=t64(om0))
+    P = nys.nys_factor(Om, Y)
+    ref = oracle.randomized_nystrom(oracle.DenseOp(A), om0)
+    U, lam = h(P.U), h(P.lam)
+    np.testing.assert_allclose(U.T @ U, np.eye(ell), atol=1e-11)
+    assert np.all(np.diff(lam) <= 0)
+    np.testing.assert_allclose(lam, ref["lam"], rtol=1e-9, atol=1e-12 * ref["lam"][0])
+    Ah = (U * lam) @ U.T
+    Ar = (ref["U"] * ref["lam"]) @ ref["U"].T
+    assert rel(Ah, Ar) < 1e-10
+    r = np.random.default_rng(1).standard_normal(n)
+    mu = 1e-3
+    z_dev = h(nys.nys_precond_apply(P, mu, t64(r)))
+    z_ref = oracle.precond_inv_apply(ref["U"], ref["lam"], mu, r)
+    assert rel(z_dev, z_ref) < 1e-9
+
+
+def test_factor_low_rank_exact_recovery():
+    A = lowrank_psd(400, 30, seed=9)
+    om0 = np.random.default_rng(10).standard_normal((400, 48))
+    op = nys.Operator.dense(t64(A))
+    Om, Y = nys.nys_sketch(op, 48, omega0=t64(om0))
+    P = nys.nys_factor(Om, Y)
+    U, lam = h(P.U), h(P.lam)
+    assert np.linalg.norm(A - (U * lam) @ U.T, 2) <= 1e-11 * np.linalg.norm(A, 2)
+
+
+@pytest.mark.parametrize("k", [1, 5])
+def test_precond_apply_with_oracle_factors(k):
+    """Oracle U, lam passed in: P^{-1} R agrees to rounding (eq. (NysPre))."""
+    A, om0 = _sketch_case(411, 37, seed=77)
+    ref = oracle.randomized_nystrom(oracle.DenseOp(A), om0)
+    P = nys.Precond(t64(ref["U"]), t64(ref["lam"]))
+    R = np.random.default_rng(3).standard_normal((411, k))
+    for mu in (1e-1, 1e-4, 0.0):
+        z = h(nys.nys_precond_apply(P, mu, t64(R)))
+        np.testing.assert_allclose(z, oracle.precond_inv_apply(ref["U"], ref["lam"], mu, R), rtol=1e-12,
+                                   atol=1e-12)
+
+
+def _krr(n, ell, seed):
+    w = krr_small(n=n, d=8, ell=ell, seed=seed)
+    op_ref = oracle.RBFOp(w["X"], w["sigma"])
+    b = op_ref.matmat(w["w"]) + w["noise"] * w["eps"]
+    return w, op_ref, b
+
+
+@pytest.mark.parametrize("n,ell", [(700, 50), (2048, 100)])
+def test_pcg_solve_fp64_rbf(n, ell):
+    w, op_ref, b = _krr(n, ell, 20211001 if n == 2048 else 11)
+    op = nys.Operator.rbf(t64(w["X"]), w["sigma"])
+    Om, Y = nys.nys_sketch(op, ell, omega0=t64(w["omega0"]))
+    P = nys.nys_factor(Om, Y)
+    x, info = nys.nys_pcg_solve(op, P, w["mu"], t64(b), tol=1e-10, maxit=2000)
+    x = h(x)
+    assert info.status[0] == 0
+    rr = oracle.true_relres(op_ref, w["mu"], x, b)
+    assert rr <= 1e-10
+    assert abs(info.relres[0] - rr) <= 1e-12
+    ref = oracle.randomized_nystrom(op_ref, w["omega0"])
+    out = oracle.nystrom_pcg(op_ref.matmat, b, w["mu"],
+                             lambda v: oracle.precond_inv_apply(ref["U"], ref["lam"], w["mu"], v),
+                             tol=1e-10, maxit=2000)
+    assert abs(info.iters[0] - out["iters"]) <= 2
+    xs = oracle.dense_solve(op_ref.dense(), w["mu"], b)
+    ev = np.linalg.eigvalsh(op_ref.dense())
+    kappa = (ev.max() + w["mu"]) / w["mu"]
+    assert rel(x, xs) <= kappa * 1e-10
+
+
+def test_pcg_mu_grid_and_rhs_block():
+    w, op_ref, b = _krr(600, 40, 12)
+    rng = np.random.default_rng(13)
+    B = np.stack([b, rng.standard_normal(600)], axis=1)
+    mus = [1e-4, 1e-2, 1.0]
+    op = nys.Operator.rbf(t64(w["X"]), w["sigma"])
+    Om, Y = nys.nys_sketch(op, 40, omega0=t64(w["omega0"]))
+    P = nys.nys_factor(Om, Y)
+    X, info = nys.nys_pcg_solve(op, P, mus, t64(B), tol=1e-10, maxit=3000)
+    X = h(X)
+    K = op_ref.dense()
+    for m, mu in enumerate(mus):
+        for r in range(2):
+            c = m * 2 + r
+            assert info.status[c] == 0
+            assert oracle.true_relres(op_ref, mu, X[:, c], B[:, r]) <= 1e-10
+            xs = oracle.dense_solve(K, mu, B[:, r])
+            assert rel(X[:, c], xs) <= 1e-10 * (np.linalg.eigvalsh(K).max() + mu) / mu
+
+
+def test_pcg_xtx_refinement_small():
+    w = ridge_dense(m=4000, n=800, ell=100, seed=14)
+    X = w["X"]
+    op_ref = oracle.XtXOp(X)
+    b = X.astype(np.float64).T @ w["y"]
+    op = nys.Operator.xtx(t32(X))
+    Om, Y = nys.nys_sketch(op, 100, omega0=t64(w["omega0"]), prec=nys.NYS_PREC_FP32_REFINE64)
+    P = nys.nys_factor(Om, Y, dtype=torch.float32)
+    x, info = nys.nys_pcg_solve(op, P, w["mu"], t64(b), tol=1e-10, maxit=500, prec=nys.NYS_PREC_FP32_REFINE64)
+    assert info.status[0] == 0 and info.refine_steps >= 1
+    assert oracle.true_relres(op_ref, w["mu"], h(x), b) <= 1e-10
+    # plain float64 path on the same operator reaches the same solution
+    P64 = nys.nys_factor(*nys.nys_sketch(op, 100, omega0=t64(w["omega0"])))
+    x64, info64 = nys.nys_pcg_solve(op, P64, w["mu"], t64(b), tol=1e-10, maxit=500)
+    assert oracle.true_relres(op_ref, w["mu"], h(x64), b) <= 1e-10
+    xs = oracle.dense_solve(op_ref.dense(), w["mu"], b)
+    assert rel(h(x), xs) < 1e-7 and rel(h(x64), xs) < 1e-7
+
+
+def test_pcg_fp32_only_path():
+    w = ridge_dense(m=3000, n=600, ell=80, seed=15)
+    X = w["X"]
+    b = X.astype(np.float64).T @ w["y"]
+    op = nys.Operator.xtx(t32(X))
+    P = nys.nys_factor(*nys.nys_sketch(op, 80, omega0=t64(w["omega0"]), prec=nys.NYS_PREC_FP32),
+                       dtype=torch.float32)
+    x, info = nys.nys_pcg_solve(op, P, w["mu"], t64(b), tol=1e-5, maxit=500, prec=nys.NYS_PREC_FP32)
+    assert oracle.true_relres(oracle.XtXOp(X), w["mu"], h(x), b) <= 1e-5
+
+
+def test_backward_rbf_against_oracle():
+    w, op_ref, b = _krr(400, 40, 16)
+    mu = w["mu"] * 10
+    c = np.random.default_rng(17).standard_normal(400)
+    op = nys.Operator.rbf(t64(w["X"]), w["sigma"])
+    P = nys.nys_factor(*nys.nys_sketch(op, 40, omega0=t64(w["omega0"])))
+    x, _ = nys.nys_pcg_solve(op, P, mu, t64(b), tol=1e-12, maxit=3000)
+    gx = c  # L = c^T x
+    r = nys.nys_pcg_backward(op, P, mu, x, t64(gx), want_sigma=True, tol=1e-12, maxit=3000)
+    K = op_ref.dense()
+    xs = oracle.dense_solve(K, mu, b)
+    g = oracle.adjoint_gradients(op_ref, mu, xs, gx, lambda v: oracle.dense_solve(K, mu, v))
+    assert rel(h(r["gb"]), g["gb"]) < 1e-8
+    assert r["gmu"] == pytest.approx(g["gmu"], rel=1e-7)
+    assert r["gsigma"] == pytest.approx(g["gsigma"], rel=1e-7)
+
+
+def test_backward_xtx_data_gradient():
+    w = ridge_dense(m=500, n=120, ell=30, seed=18)
+    X = w["X"].astype(np.float64)
+    b = X.T @ w["y"]
+    mu = 1e-2
+    c = np.random.default_rng(19).standard_normal(120)
+    op = nys.Operator.xtx(t64(X))
+    P = nys.nys_factor(*nys.nys_sketch(op, 30, omega0=t64(w["omega0"])))
+    x, _ = nys.nys_pcg_solve(op, P, mu, t64(b), tol=1e-12, maxit=2000)
+    r = nys.nys_pcg_backward(op, P, mu, x, t64(c), want_X=True, tol=1e-12, maxit=2000)
+    A = X.T @ X
+    xs = oracle.dense_solve(A, mu, b)
+    g = oracle.adjoint_gradients(oracle.XtXOp(X), mu, xs, c, lambda v: oracle.dense_solve(A, mu, v))
+    assert rel(h(r["gX"]), g["gX"]) < 1e-7
+
+
+def test_rbf_cross_products():
+    rng = np.random.default_rng(21)
+    Xtr = rng.standard_normal((500, 16))
+    Xv = rng.standard_normal((130, 16))
+    v = rng.standard_normal(130)
+    u = rng.standard_normal(500)
+    op = nys.Operator.rbf(t64(Xtr), 4.0)
+    Kv = oracle.rbf_kernel_block(Xv, Xtr, 4.0)
+    out = h(nys.nys_rbf_cross(op, t64(Xv), t64(u)))
+    np.testing.assert_allclose(out, Kv @ u, rtol=1e-12, atol=1e-12)
+    out_t = h(nys.nys_rbf_cross(op, t64(Xv), t64(v), transpose=True))
+    np.testing.assert_allclose(out_t, Kv.T @ v, rtol=1e-12, atol=1e-12)
+    _, ds = nys.nys_rbf_cross(op, t64(Xv), t64(v), wvec=t64(u))
+    d2 = ((Xv[:, None, :] - Xtr[None, :, :]) ** 2).sum(-1)
+    assert ds == pytest.approx(float(v @ ((Kv * d2 / 4.0 ** 3) @ u)), rel=1e-11)
+
+
+def test_determinism_bitwise():
+    w, op_ref, b = _krr(900, 60, 22)
+    op = nys.Operator.rbf(t64(w["X"]), w["sigma"])
+    xs = []
+    for _ in range(2):
+        P = nys.nys_factor(*nys.nys_sketch(op, 60, omega0=t64(w["omega0"])))
+        x, _ = nys.nys_pcg_solve(op, P, w["mu"], t64(b), tol=1e-10, maxit=2000)
+        xs.append(h(x))
+    assert np.array_equal(xs[0], xs[1])
+
+
+def test_error_paths_on_device():
+    w, op_ref, b = _krr(200, 20, 23)
+    op = nys.Operator.rbf(t64(w["X"]), w["sigma"])
+    P = nys.nys_factor(*nys.nys_sketch(op, 20, omega0=t64(w["omega0"])))
+    with pytest.raises(nys.NysError) as e:
+        nys.nys_pcg_solve(op, P, -1.0, t64(b))
+    assert e.value.status == nys.NYS_ERR_ARG
+    x, info = nys.nys_pcg_solve(op, P, w["mu"], t64(b), tol=1e-14, maxit=3)
+    assert info.code == nys.NYS_NOT_CONVERGED and info.iters[0] == 3
+    # indefinite dense operator: breakdown
+    Aneg = -np.eye(50)
+    opn = nys.Operator.dense(t64(Aneg))
+    Pn = nys.Precond(t64(np.eye(50)[:, :2]), t64(np.array([1.0, 1.0])))
+    with pytest.raises(nys.NysError) as e:
+        nys.nys_pcg_solve(opn, Pn, 0.5, t64(np.ones(50)), maxit=10)
+    assert e.value.status == nys.NYS_ERR_BREAKDOWN
+    # rank-deficient test matrix is reported by the sketch
+    with pytest.raises(nys.NysError) as e:
+        nys.nys_sketch(op, 20, omega0=t64(np.zeros((200, 20))))
+    assert e.value.status == nys.NYS_ERR_NOT_PSD
