@@ -165,10 +165,8 @@ void carve_factor(Arena& a, int64_t n, int64_t l, FactorWs& w) {
 template <typename T>
 struct PcgBufs {
   T *V, *R, *Z, *P, *X, *B;
-  double *pb, *prr, *ppv, *prz;
+  PcgWork w;
   CgScalars sc;
-  double *apart, *Cs, *Ct;
-  size_t apart_elems;
   T* opscr;
   size_t opscr_elems;
 };
@@ -182,21 +180,25 @@ void carve_pcg(Arena& a, const OpDesc& op, int64_t l, int64_t k, PcgBufs<T>& b) 
   b.P = a.take<T>(n * k);
   b.X = a.take<T>(n * k);
   b.B = a.take<T>(n * k);
-  b.pb = a.take<double>(kMaxGroups * k);
-  b.prr = a.take<double>(kMaxGroups * k);
-  b.ppv = a.take<double>(kMaxGroups * k);
-  b.prz = a.take<double>(kMaxGroups * k);
+  b.w.pb = a.take<double>(kMaxGroups * k);
+  b.w.prr = a.take<double>(kMaxGroups * k);
+  b.w.ppv = a.take<double>(kMaxGroups * k);
+  b.w.prz = a.take<double>(kMaxGroups * k);
+  b.w.apart_elems = precond_part_elems(n, l, k);
+  b.w.apart = a.take<double>(b.w.apart_elems);
+  b.w.Cs = a.take<double>(l * k);
+  b.w.Ct = a.take<double>(l * k);
   b.sc.rz = a.take<double>(2 * k);
   b.sc.bnorm2 = a.take<double>(k);
   b.sc.rnorm2 = a.take<double>(k);
+  b.sc.alpha = a.take<double>(k);
+  b.sc.beta = a.take<double>(k);
   b.sc.done = a.take<int>(k);
+  b.sc.conv = a.take<int>(k);
   b.sc.iters = a.take<int>(k);
   b.sc.status = a.take<int>(k);
   b.sc.alldone = a.take<int>(1);
-  b.apart_elems = precond_part_elems(n, l, k);
-  b.apart = a.take<double>(b.apart_elems);
-  b.Cs = a.take<double>(l * k);
-  b.Ct = a.take<double>(l * k);
+  b.sc.ctr = a.take<unsigned>(64);
   b.opscr_elems = op_scratch_elems(op, k);
   b.opscr = a.take<T>(b.opscr_elems);
 }
@@ -392,20 +394,16 @@ nys_status pcg_run(const OpDesc& op0, const PrecDesc& P, int64_t k, int64_t nrhs
                    const double* mu_dev, double mu_host, const T* B, T* X, bool x0_zero, double tol,
                    int maxit, int check_every, PcgBufs<T>& b, PcgResult& res, hipStream_t s) {
   const int64_t n = op0.n;
-  const int ng = groups();
-  const bool f32 = sizeof(T) == 4;
   OpDesc op = op0;
   op.skip = nullptr;
+  NYS_HIP(hipMemsetAsync(b.sc.ctr, 0, sizeof(unsigned) * 64, s));
   if (x0_zero) {
     NYS_TRY(zero<T>(X, n * k, s));
     NYS_TRY(zero<T>(b.V, n * k, s));
   } else {
     NYS_TRY(matvec<T>(op, X, k, mu_dev, nrhs, mu_host, b.V, b, s));
   }
-  NYS_TRY(cg_kernels_init<T>(n, k, B, k, b.V, b.R, b.pb, b.prr, ng, s));
-  NYS_TRY(precond_apply_dev(P, mu_dev, nrhs, b.R, b.Z, k, f32, nullptr, nullptr, b.apart,
-                            b.apart_elems, b.Cs, b.Ct, s));
-  NYS_TRY(cg_kernels_init2<T>(n, k, b.R, b.Z, b.P, b.pb, b.prr, b.prz, tol, b.sc, ng, s));
+  NYS_TRY(pcg_setup<T>(n, k, P, mu_dev, nrhs, B, b.V, b.R, b.Z, b.P, b.w, b.sc, tol, s));
   op.skip = b.sc.alldone;
   int it = 0;
   int alldone_h = 0;
@@ -414,10 +412,7 @@ nys_status pcg_run(const OpDesc& op0, const PrecDesc& P, int64_t k, int64_t nrhs
   while (!alldone_h && it < maxit) {
     const int par = it & 1;
     NYS_TRY(matvec<T>(op, b.P, k, mu_dev, nrhs, mu_host, b.V, b, s));
-    NYS_TRY(cg_kernels_step_a<T>(n, k, b.P, b.V, X, k, b.R, b.ppv, b.prr, b.sc, par, ng, s));
-    NYS_TRY(precond_apply_dev(P, mu_dev, nrhs, b.R, b.Z, k, f32, b.sc.done, b.sc.alldone, b.apart,
-                              b.apart_elems, b.Cs, b.Ct, s));
-    NYS_TRY(cg_kernels_step_b<T>(n, k, b.R, b.Z, b.P, b.prz, b.prr, b.sc, par, tol, ng, s));
+    NYS_TRY(pcg_iteration<T>(n, k, P, mu_dev, nrhs, b.V, X, k, b.R, b.Z, b.P, b.w, b.sc, par, tol, s));
     ++it;
     if (it % check_every == 0 || it == maxit) {
       NYS_HIP(hipMemcpyAsync(&alldone_h, b.sc.alldone, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -780,13 +775,15 @@ nys_status nys_precond_apply(const nys_precond* P, double mu, const double* R, i
   double* part = a.take<double>(pe);
   double* Cs = a.take<double>(pd.ell * k);
   double* Ct = a.take<double>(pd.ell * k);
+  unsigned* ctr = a.take<unsigned>(64);
   if (!ws || !a.ok()) {
     set_error("workspace too small: need %zu bytes", a.off);
     return NYS_ERR_WORKSPACE;
   }
   hipStream_t s = S(stream);
   NYS_TRY(set_mu(mu_dev, &mu, 1, s));
-  return precond_apply_dev(pd, mu_dev, k, R, Z, k, false, nullptr, nullptr, part, pe, Cs, Ct, s);
+  NYS_HIP(hipMemsetAsync(ctr, 0, sizeof(unsigned) * 64, s));
+  return precond_apply_standalone(pd, mu_dev, R, Z, k, part, pe, Cs, Ct, ctr, s);
 }
 
 nys_status nys_pcg_solve(const nys_operator* A, const nys_precond* P, const double* mu, int64_t nmu,

@@ -260,28 +260,19 @@ __global__ __launch_bounds__(256) void trinv_blocks(const double* __restrict__ L
 
 // ---------------------------------------------------------------- Jacobi
 
-struct JacArgs {
-  double* A0;      // m x m working copy (round parity 0)
-  double* A1;      // m x m working copy (round parity 1)
-  double* V;       // m x m eigenvectors (columns)
-  int64_t m;       // even order (l or l+1)
-  int max_sweeps;
-  int* flags;      // [max_sweeps] "a rotation happened" per sweep (zeroed)
-  int* sweeps_out; // sweeps executed
-  double* evals;   // m: diagonal of the final matrix (the eigenvalues)
-  unsigned* bar;
-  int* bar_err;
-};
+constexpr int JB = 32;       // Jacobi block size
+constexpr int JS = 2 * JB;   // order of one block-pair subproblem
 
 __device__ __forceinline__ int64_t rr_index(int64_t pos, int64_t r, int64_t m) {
   return pos == 0 ? 0 : 1 + ((pos - 1 + r) % (m - 1));
 }
 
 // Rotation (c, s) with J_pp = c, J_pq = s, J_qp = -s, J_qq = c that zeroes
-// entry (p, q) of J^T A J (symmetric 2x2 Schur decomposition).
-__device__ __forceinline__ bool jacobi_rot(double app, double aqq, double apq, double& c,
-                                           double& s) {
-  const double thr = 2.220446049250313e-16 * sqrt(fabs(app) * fabs(aqq));
+// entry (p, q) of J^T A J (symmetric 2x2 Schur decomposition).  Returns false
+// (identity) when |a_pq| is negligible relative to sqrt(|a_pp a_qq|).
+__device__ __forceinline__ bool jacobi_rot(double app, double aqq, double apq, double floor_abs,
+                                           double& c, double& s) {
+  const double thr = fmax(2.220446049250313e-16 * sqrt(fabs(app) * fabs(aqq)), floor_abs);
   if (!(fabs(apq) > thr) || fabs(apq) < 1e-300) {
     c = 1.0;
     s = 0.0;
@@ -295,60 +286,223 @@ __device__ __forceinline__ bool jacobi_rot(double app, double aqq, double apq, d
   return true;
 }
 
-__global__ __launch_bounds__(256) void jacobi_coop(JacArgs a) {
-  extern __shared__ double rot[];  // [2 * (m/2)] : c then s
+// Block two-sided Jacobi.  The m x m matrix (m = nblk * JB, nblk even) is cut
+// into JB x JB blocks; a round pairs the blocks by the round-robin schedule.
+// Phase 1: one workgroup per block pair (P, Q) loads the JS x JS subproblem
+// [A_PP A_PQ; A_QP A_QQ] into LDS, runs cyclic Jacobi sweeps on it and keeps
+// the accumulated rotation J_k.  Phase 2: every workgroup applies the
+// rotations, A <- J^T A J (tiles pair k x pair k': J_k^T A_kk' J_k') and
+// V <- V J.  Two grid barriers per round; nblk - 1 rounds per sweep.
+struct JacArgs {
+  double* A;       // m x m
+  double* V;       // m x m eigenvectors (columns)
+  double* J;       // (nblk/2) x JS x JS rotations of the current round
+  int64_t m;
+  int nblk;
+  int max_sweeps;
+  int inner_sweeps;
+  int* flags;      // [max_sweeps] "a rotation happened" per sweep (zeroed)
+  int* sweeps_out;
+  double* evals;   // m: diagonal of the final matrix
+  unsigned* bar;
+  int* bar_err;
+};
+
+__device__ __forceinline__ int64_t pair_index(int nblk, int k, int64_t r, int t) {
+  const int64_t blk = (t < JB) ? rr_index(k, r, nblk) : rr_index(nblk - 1 - k, r, nblk);
+  return blk * JB + (t & (JB - 1));
+}
+
+typedef double jd4 __attribute__((ext_vector_type(4)));
+
+// out(64x64) = opA(X) * Y on MFMA f64 (4 waves, each a 32x32 quadrant).
+// TRANS_X: use X^T (X[p][i]) instead of X (X[i][p]).  Results are returned in
+// the wave's accumulators; element q of lane l of tile (ti, tj) is
+// out[wm*32 + ti*16 + 4q + l/16][wn*32 + tj*16 + l%16].
+template <bool TRANS_X>
+__device__ __forceinline__ void mm64(const double (*X)[JS + 1], const double (*Y)[JS + 1], jd4 acc[2][2]) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = jd4{0, 0, 0, 0};
+#pragma unroll 4
+  for (int k0 = 0; k0 < JS; k0 += 4) {
+    const int kk = k0 + (lane >> 4);
+    const int r0 = wm * 32 + (lane & 15), r1 = r0 + 16;
+    const int c0 = wn * 32 + (lane & 15), c1 = c0 + 16;
+    const double a0 = TRANS_X ? X[kk][r0] : X[r0][kk];
+    const double a1 = TRANS_X ? X[kk][r1] : X[r1][kk];
+    const double b0 = Y[kk][c0], b1 = Y[kk][c1];
+    acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+    acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+    acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+    acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+  }
+}
+
+template <typename F>
+__device__ __forceinline__ void mm64_store(const jd4 acc[2][2], F f) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        f(wm * 32 + i * 16 + 4 * q + (lane >> 4), wn * 32 + j * 16 + (lane & 15), acc[i][j][q]);
+}
+
+__global__ __launch_bounds__(256) void jacobi_block_coop(JacArgs a) {
+  __shared__ double S[JS][JS + 1];
+  __shared__ double Jm[JS][JS + 1];
+  __shared__ double cs[JS / 2], sn[JS / 2];
+  __shared__ int pp[JS / 2], qq[JS / 2];
+  __shared__ int64_t gi[JS], gj[JS];
+  __shared__ int rotated, any_s;
   GridBarrier gb{a.bar, a.bar_err, gridDim.x, 0};
-  const int64_t m = a.m, half = m / 2;
-  double* cs = rot;
-  double* sn = rot + half;
-  const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t gsz = (int64_t)gridDim.x * blockDim.x;
-  int64_t round = 0;
+  const int t = threadIdx.x;
+  const int64_t m = a.m;
+  const int nblk = a.nblk, npair = nblk / 2;
+  // absolute floor of the rotation test: eps times the largest diagonal entry
+  // of the input (rotations below it change eigenvalues by less than that)
+  __shared__ double dmax_s;
+  {
+    double dm = 0.0;
+    for (int64_t i = t; i < m; i += 256) dm = fmax(dm, a.A[i * m + i]);
+    __shared__ double red[256];
+    red[t] = dm;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+      if (t < st) red[t] = fmax(red[t], red[t + st]);
+      __syncthreads();
+    }
+    if (t == 0) dmax_s = red[0];
+    __syncthreads();
+  }
+  const double floor_abs = 2.220446049250313e-16 * dmax_s;
+  gb.sync();  // every workgroup has read the input diagonal before any rotation
   int sweep = 0;
   for (sweep = 0; sweep < a.max_sweeps; ++sweep) {
-    for (int64_t r = 0; r < m - 1; ++r, ++round) {
-      const double* Ar = (round & 1) ? a.A1 : a.A0;
-      double* Aw = (round & 1) ? a.A0 : a.A1;
-      bool any = false;
-      for (int64_t k = threadIdx.x; k < half; k += blockDim.x) {
-        const int64_t p = rr_index(k, r, m), q = rr_index(m - 1 - k, r, m);
-        double c, s;
-        any |= jacobi_rot(Ar[p * m + p], Ar[q * m + q], Ar[p * m + q], c, s);
-        cs[k] = c;
-        sn[k] = s;
+    for (int64_t r = 0; r < nblk - 1; ++r) {
+      // ---- phase 1: block-pair subproblems in LDS
+      for (int k = blockIdx.x; k < npair; k += gridDim.x) {
+        if (t < JS) gi[t] = pair_index(nblk, k, r, t);
+        if (t == 0) rotated = 0;
+        __syncthreads();
+        for (int e = t; e < JS * JS; e += 256) {
+          const int i = e / JS, j = e % JS;
+          S[i][j] = a.A[gi[i] * m + gi[j]];
+          Jm[i][j] = (i == j) ? 1.0 : 0.0;
+        }
+        __syncthreads();
+        for (int isw = 0; isw < a.inner_sweeps; ++isw) {
+          if (t == 0) any_s = 0;
+          __syncthreads();
+          for (int ir = 0; ir < JS - 1; ++ir) {
+            if (t < JS / 2) {
+              const int p = (int)rr_index(t, ir, JS), q = (int)rr_index(JS - 1 - t, ir, JS);
+              double c, sv;
+              if (jacobi_rot(S[p][p], S[q][q], S[p][q], floor_abs, c, sv)) any_s = 1;
+              cs[t] = c;
+              sn[t] = sv;
+              pp[t] = p;
+              qq[t] = q;
+            }
+            __syncthreads();
+            // S <- R^T S R on 2x2 blocks (rows pair k1, cols pair k2)
+            for (int e = t; e < (JS / 2) * (JS / 2); e += 256) {
+              const int k1 = e >> 5, k2 = e & 31;
+              const double s1 = sn[k1], s2 = sn[k2];
+              if (s1 == 0.0 && s2 == 0.0) continue;
+              const int p1 = pp[k1], q1 = qq[k1], p2 = pp[k2], q2 = qq[k2];
+              const double c1 = cs[k1], c2 = cs[k2];
+              const double app = S[p1][p2], apq = S[p1][q2], aqp = S[q1][p2], aqq = S[q1][q2];
+              const double bpp = c1 * app - s1 * aqp, bpq = c1 * apq - s1 * aqq;
+              const double bqp = s1 * app + c1 * aqp, bqq = s1 * apq + c1 * aqq;
+              double npp = c2 * bpp - s2 * bpq, npq = s2 * bpp + c2 * bpq;
+              double nqp = c2 * bqp - s2 * bqq, nqq = s2 * bqp + c2 * bqq;
+              if (k1 == k2) {
+                npq = 0.0;
+                nqp = 0.0;
+              }
+              S[p1][p2] = npp;
+              S[p1][q2] = npq;
+              S[q1][p2] = nqp;
+              S[q1][q2] = nqq;
+            }
+            // Jm <- Jm R (row i, pair kk)
+            for (int e = t; e < JS * (JS / 2); e += 256) {
+              const int i = e >> 5, kk = e & 31;
+              const double sv = sn[kk];
+              if (sv == 0.0) continue;
+              const double c = cs[kk];
+              const int p = pp[kk], q = qq[kk];
+              const double vp = Jm[i][p], vq = Jm[i][q];
+              Jm[i][p] = c * vp - sv * vq;
+              Jm[i][q] = sv * vp + c * vq;
+            }
+            __syncthreads();
+          }
+          if (any_s) rotated = 1;
+          __syncthreads();
+          if (!any_s) break;
+          __syncthreads();
+        }
+        for (int e = t; e < JS * JS; e += 256) {
+          a.J[(int64_t)k * JS * JS + e] = Jm[e / JS][e % JS];
+          a.A[gi[e / JS] * m + gi[e % JS]] = S[e / JS][e % JS];
+        }
+        if (t == 0 && rotated) a.flags[sweep] = 1;
+        __syncthreads();
       }
-      if (any && blockIdx.x == 0) a.flags[sweep] = 1;
-      __syncthreads();
-      // A blocks: rows pair k1, cols pair k2
-      for (int64_t e = gtid; e < half * half; e += gsz) {
-        const int64_t k1 = e / half, k2 = e % half;
-        const int64_t p1 = rr_index(k1, r, m), q1 = rr_index(m - 1 - k1, r, m);
-        const int64_t p2 = rr_index(k2, r, m), q2 = rr_index(m - 1 - k2, r, m);
-        const double c1 = cs[k1], s1 = sn[k1], c2 = cs[k2], s2 = sn[k2];
-        const double app = Ar[p1 * m + p2], apq = Ar[p1 * m + q2];
-        const double aqp = Ar[q1 * m + p2], aqq = Ar[q1 * m + q2];
-        // rows: row_p' = c row_p - s row_q ; row_q' = s row_p + c row_q
-        const double bpp = c1 * app - s1 * aqp, bpq = c1 * apq - s1 * aqq;
-        const double bqp = s1 * app + c1 * aqp, bqq = s1 * apq + c1 * aqq;
-        // cols: col_p' = c col_p - s col_q ; col_q' = s col_p + c col_q
-        double npp = c2 * bpp - s2 * bpq, npq = s2 * bpp + c2 * bpq;
-        double nqp = c2 * bqp - s2 * bqq, nqq = s2 * bqp + c2 * bqq;
-        if (k1 == k2 && sn[k1] != 0.0) { npq = 0.0; nqp = 0.0; }
-        Aw[p1 * m + p2] = npp;
-        Aw[p1 * m + q2] = npq;
-        Aw[q1 * m + p2] = nqp;
-        Aw[q1 * m + q2] = nqq;
-      }
-      // V <- V J (row i, pair k)
-      for (int64_t e = gtid; e < m * half; e += gsz) {
-        const int64_t i = e / half, k = e % half;
-        const double s = sn[k];
-        if (s == 0.0) continue;
-        const double c = cs[k];
-        const int64_t p = rr_index(k, r, m), q = rr_index(m - 1 - k, r, m);
-        const double vp = a.V[i * m + p], vq = a.V[i * m + q];
-        a.V[i * m + p] = c * vp - s * vq;
-        a.V[i * m + q] = s * vp + c * vq;
+      gb.sync();
+      // ---- phase 2: A <- J^T A J on off-diagonal pair tiles, V <- V J (MFMA)
+      const int ntile_a = npair * npair;
+      const int64_t nrb = m / JS;
+      const int64_t ntile_v = nrb * npair;
+      for (int64_t task = blockIdx.x; task < ntile_a + ntile_v; task += gridDim.x) {
+        jd4 acc[2][2];
+        if (task < ntile_a) {
+          const int k1 = (int)(task / npair), k2 = (int)(task % npair);
+          if (k1 == k2) continue;  // written by phase 1
+          if (t < JS) {
+            gi[t] = pair_index(nblk, k1, r, t);
+            gj[t] = pair_index(nblk, k2, r, t);
+          }
+          __syncthreads();
+          for (int e = t; e < JS * JS; e += 256) {
+            const int i = e / JS, j = e % JS;
+            S[i][j] = a.A[gi[i] * m + gj[j]];
+            Jm[i][j] = a.J[(int64_t)k1 * JS * JS + e];
+          }
+          __syncthreads();
+          mm64<true>(Jm, S, acc);  // T = J_k1^T S
+          __syncthreads();
+          mm64_store(acc, [&](int i, int j, double v) { S[i][j] = v; });
+          for (int e = t; e < JS * JS; e += 256) Jm[e / JS][e % JS] = a.J[(int64_t)k2 * JS * JS + e];
+          __syncthreads();
+          mm64<false>(S, Jm, acc);  // T J_k2
+          mm64_store(acc, [&](int i, int j, double v) { a.A[gi[i] * m + gj[j]] = v; });
+          __syncthreads();
+        } else {
+          const int64_t vt = task - ntile_a;
+          const int64_t rb = vt / npair;
+          const int k = (int)(vt % npair);
+          if (t < JS) gj[t] = pair_index(nblk, k, r, t);
+          __syncthreads();
+          for (int e = t; e < JS * JS; e += 256) {
+            const int i = e / JS, j = e % JS;
+            S[i][j] = a.V[(rb * JS + i) * m + gj[j]];
+            Jm[i][j] = a.J[(int64_t)k * JS * JS + e];
+          }
+          __syncthreads();
+          mm64<false>(S, Jm, acc);
+          mm64_store(acc, [&](int i, int j, double v) { a.V[(rb * JS + i) * m + gj[j]] = v; });
+          __syncthreads();
+        }
       }
       gb.sync();
     }
@@ -357,12 +511,12 @@ __global__ __launch_bounds__(256) void jacobi_coop(JacArgs a) {
       break;
     }
   }
+  const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + t;
   if (gtid == 0) a.sweeps_out[0] = sweep;
-  // after `round` rounds the newest copy is A1 when round is odd
-  const double* Afin = (round & 1) ? a.A1 : a.A0;
-  for (int64_t i = gtid; i < m; i += gsz) a.evals[i] = Afin[i * m + i];
+  for (int64_t i = gtid; i < m; i += (int64_t)gridDim.x * blockDim.x) a.evals[i] = a.A[i * m + i];
 }
 
+// A = (G + G^T)/2 padded to m x m (padding: isolated eigenvalue -1), V = I.
 __global__ void jacobi_init(const double* __restrict__ G, int64_t l, int64_t m,
                             double* __restrict__ A0, double* __restrict__ V) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -370,7 +524,7 @@ __global__ void jacobi_init(const double* __restrict__ G, int64_t l, int64_t m,
   const int64_t i = idx / m, j = idx % m;
   double v;
   if (i < l && j < l) v = 0.5 * (G[i * l + j] + G[j * l + i]);
-  else v = (i == j) ? -1.0 : 0.0;  // padding index: isolated eigenvalue -1
+  else v = (i == j) ? -1.0 : 0.0;
   A0[idx] = v;
   V[idx] = (i == j) ? 1.0 : 0.0;
 }
@@ -455,31 +609,42 @@ nys_status tri_inverse(const double* L, int64_t n, const double* Dinv, double* X
   return NYS_OK;
 }
 
+// one inner sweep per round for large problems (the outer sweeps refine the
+// pairs again); small problems are a single block pair, solved to convergence
+int inner_sweeps_for(int64_t l) { return l <= JS ? 30 : 1; }
+
+int jac_nblk(int64_t l) {
+  int nb = (int)cdiv(l, JB);
+  if (nb < 2) nb = 2;
+  if (nb & 1) ++nb;
+  return nb;
+}
+
 size_t eig_ws_doubles(int64_t l) {
-  const int64_t m = l + (l & 1);
-  return (size_t)(3 * m * m + m);
+  const int64_t nb = jac_nblk(l);
+  const int64_t m = nb * JB;
+  return (size_t)(2 * m * m + m + (nb / 2) * JS * JS);
 }
 
 nys_status sym_eig(const double* G, int64_t l, double* work, int* flags, int max_sweeps,
                    int* sweeps_out, unsigned* bar, int* bar_err, double* T, double* lam,
                    double* sig2, const double* nu, hipStream_t s) {
-  const int64_t m = l + (l & 1);
-  double* A0 = work;
-  double* A1 = work + m * m;
-  double* V = work + 2 * m * m;
-  double* ev = work + 3 * m * m;
-  hipLaunchKernelGGL(jacobi_init, dim3((unsigned)cdiv(m * m, 256)), dim3(256), 0, s, G, l, m, A0, V);
+  const int nb = jac_nblk(l);
+  const int64_t m = (int64_t)nb * JB;
+  double* A = work;
+  double* V = work + m * m;
+  double* ev = work + 2 * m * m;
+  double* J = ev + m;
+  hipLaunchKernelGGL(jacobi_init, dim3((unsigned)cdiv(m * m, 256)), dim3(256), 0, s, G, l, m, A, V);
   NYS_CHECK_LAUNCH();
   NYS_HIP(hipMemsetAsync(flags, 0, sizeof(int) * max_sweeps, s));
   NYS_HIP(hipMemsetAsync(bar, 0, sizeof(unsigned), s));
   NYS_HIP(hipMemsetAsync(bar_err, 0, sizeof(int), s));
-  JacArgs a{A0, A1, V, m, max_sweeps, flags, sweeps_out, ev, bar, bar_err};
-  const size_t shmem = sizeof(double) * m;
-  const int64_t need = cdiv((m / 2) * (m / 2) + m * (m / 2), 256);
-  const int g = coop_blocks((const void*)jacobi_coop, 256, shmem,
-                            (int)(need < 256 ? (need > 0 ? need : 1) : 256));
+  JacArgs a{A, V, J, m, nb, max_sweeps, inner_sweeps_for(l), flags, sweeps_out, ev, bar, bar_err};
+  const int64_t tasks = (int64_t)(nb / 2) * (nb / 2) + (m / JS) * (nb / 2);
+  const int g = coop_blocks((const void*)jacobi_block_coop, 256, 0, (int)(tasks < 256 ? tasks : 256));
   void* args[] = {&a};
-  NYS_HIP(hipLaunchCooperativeKernel((const void*)jacobi_coop, dim3(g), dim3(256), args, shmem, s));
+  NYS_HIP(hipLaunchCooperativeKernel((const void*)jacobi_block_coop, dim3(g), dim3(256), args, 0, s));
   hipLaunchKernelGGL(eig_finalize, dim3((unsigned)cdiv(l, 256)), dim3(256), 0, s, ev, V, l, m,
                      nu, T, lam, sig2);
   NYS_CHECK_LAUNCH();

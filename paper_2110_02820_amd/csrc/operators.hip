@@ -156,19 +156,34 @@ __global__ __launch_bounds__(256) void xtx_fused(const TD* __restrict__ X, int64
     }
 }
 
-// out[j] = alpha * sum_g part[g][j] + beta * y[j]   (fixed order over g)
+// out[j] = alpha * sum_g part[g][j] + beta * y[j].  Block = 32 columns x 8
+// slices of g; each thread sums its slice with two accumulators, then the
+// slices are combined in order in LDS (fixed order: deterministic).
 template <typename TA, typename TO>
-__global__ void reduce_cols(const TA* __restrict__ part, int ng, int64_t n, TA alpha,
-                            const TO* __restrict__ y, TA beta, TO* __restrict__ out,
-                            const int* __restrict__ skip) {
+__global__ __launch_bounds__(256) void reduce_cols(const TA* __restrict__ part, int ng, int64_t n, TA alpha,
+                                                   const TO* __restrict__ y, TA beta, TO* __restrict__ out,
+                                                   const int* __restrict__ skip) {
   if (skip && *skip) return;
-  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= n) return;
-  TA s = TA(0);
-  for (int g = 0; g < ng; ++g) s += part[(int64_t)g * n + j];
-  TA o = alpha * s;
-  if (y) o += beta * TA(y[j]);
-  out[j] = TO(o);
+  __shared__ TA sh[8][33];
+  const int c = threadIdx.x & 31, sl = threadIdx.x >> 5;
+  const int64_t j = (int64_t)blockIdx.x * 32 + c;
+  TA a0 = TA(0), a1 = TA(0);
+  if (j < n) {
+    int g = sl;
+    for (; g + 8 < ng; g += 16) {
+      a0 += part[(int64_t)g * n + j];
+      a1 += part[(int64_t)(g + 8) * n + j];
+    }
+    if (g < ng) a0 += part[(int64_t)g * n + j];
+  }
+  sh[sl][c] = a0 + a1;
+  __syncthreads();
+  if (sl == 0 && j < n) {
+    TA s = ((sh[0][c] + sh[1][c]) + (sh[2][c] + sh[3][c])) + ((sh[4][c] + sh[5][c]) + (sh[6][c] + sh[7][c]));
+    TA o = alpha * s;
+    if (y) o += beta * TA(y[j]);
+    out[j] = TO(o);
+  }
 }
 
 // ------------------------------------------------------------- RBF, float64
@@ -410,7 +425,7 @@ nys_status xtx_apply_t(const OpDesc& op, const TA* p, TA mu, TA* v, TA* scratch,
   constexpr int E = Vec16<TD>::E;
   const bool aligned = (op.ld % E == 0) && ((uintptr_t)X % 16 == 0);
   const int64_t need_nv = aligned ? cdiv(n, 256 * E) : cdiv(n, 256);
-  int64_t ng = 2 * (num_cus() < 256 ? num_cus() : 256);
+  int64_t ng = (num_cus() < 256 ? num_cus() : 256);
   const int64_t R = 4;
   if (ng > cdiv(m, R)) ng = cdiv(m, R);
   if (ng < 1) ng = 1;
@@ -435,7 +450,7 @@ nys_status xtx_apply_t(const OpDesc& op, const TA* p, TA mu, TA* v, TA* scratch,
   }
 #undef LX
   NYS_CHECK_LAUNCH();
-  hipLaunchKernelGGL((reduce_cols<TA, TA>), dim3((unsigned)cdiv(n, 256)), dim3(256), 0, s, scratch,
+  hipLaunchKernelGGL((reduce_cols<TA, TA>), dim3((unsigned)cdiv(n, 32)), dim3(256), 0, s, scratch,
                      (int)ng, n, TA(op.scale), p, mu, v, op.skip);
   NYS_CHECK_LAUNCH();
   return NYS_OK;

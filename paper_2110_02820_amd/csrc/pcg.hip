@@ -2,12 +2,13 @@
 // iteration (Section 5.2, algorithm "Nystrom PCG") on the device.
 //
 // Vectors are n x k row-major blocks (k independent columns, k <= 256); a
-// single right-hand side is k = 1.  Every reduction is two-stage with a fixed
-// order (per-workgroup partials, then a fixed-order sum), so results are
-// bitwise reproducible run to run.  CG scalars live on the device: the host
-// enqueues iterations without reading them and polls the convergence flags
-// only every few iterations.  rz (= r^T z) is double-buffered by iteration
-// parity so a kernel can read the old value while one workgroup writes the new.
+// single right-hand side is k = 1.  CG scalars live on the device.  Each
+// dot product is reduced in a fixed order by the LAST workgroup of the kernel
+// that produced the per-workgroup partials (an arrival counter tells a
+// workgroup that it is last), so results are bitwise reproducible and no
+// separate reduction launch is needed; that workgroup also derives the CG
+// scalars (alpha, beta, stopping flags).  rz (= r^T z) is double-buffered by
+// iteration parity.
 #include "pcg.hpp"
 #include "gemm.hpp"
 
@@ -30,8 +31,8 @@ struct ColMap {
   }
 };
 
-// Sum per column over the threads of a block that share a column; result in
-// sh[c] (size kp).  `sh` has NT doubles.
+// Per-column sum over the threads of a block that share a column; result in
+// sh[c] for c < kp.  `sh` has NT doubles.
 __device__ __forceinline__ void colmap_reduce(double v, const ColMap& cm, double* sh) {
   __syncthreads();
   sh[threadIdx.x] = v;
@@ -42,20 +43,70 @@ __device__ __forceinline__ void colmap_reduce(double v, const ColMap& cm, double
   }
 }
 
-__device__ __forceinline__ double sum_partials(const double* part, int ng, int64_t k, int64_t c) {
+// True in exactly one workgroup: the last of `nblocks` to arrive.  Partial
+// results written before the call are visible to it afterwards.  The last
+// workgroup re-arms the counter for the next kernel.
+__device__ __forceinline__ bool last_block(unsigned* ctr, unsigned nblocks) {
+  __shared__ int am;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    const unsigned t = atomicAdd(ctr, 1u);
+    am = (t == nblocks - 1) ? 1 : 0;
+  }
+  __syncthreads();
+  if (am) {
+    __threadfence();
+    if (threadIdx.x == 0) *ctr = 0u;
+  }
+  return am != 0;
+}
+
+// Fixed-order sum of part[g][c], g < ng, by a whole block (all threads get it).
+__device__ __forceinline__ double block_reduce_col(const double* part, int ng, int64_t k, int64_t c,
+                                                   double* sh) {
   double s = 0.0;
-  for (int g = 0; g < ng; ++g) s += part[(int64_t)g * k + c];
-  return s;
+  for (int g = threadIdx.x; g < ng; g += NT) s += part[(int64_t)g * k + c];
+  return block_sum(s, sh);
+}
+
+// Fixed-order sum by one thread with four independent accumulators.
+__device__ __forceinline__ double thread_reduce_col(const double* part, int ng, int64_t k, int64_t c) {
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  int g = 0;
+  for (; g + 3 < ng; g += 4) {
+    a0 += part[(int64_t)g * k + c];
+    a1 += part[(int64_t)(g + 1) * k + c];
+    a2 += part[(int64_t)(g + 2) * k + c];
+    a3 += part[(int64_t)(g + 3) * k + c];
+  }
+  for (; g < ng; ++g) a0 += part[(int64_t)g * k + c];
+  return (a0 + a1) + (a2 + a3);
+}
+
+// Call f(c, total) for every column c < k from the partials (last block only).
+template <typename F>
+__device__ __forceinline__ void reduce_cols_last(const double* part, int ng, int64_t k, double* sh, F f) {
+  if (k <= 8) {
+    for (int64_t c = 0; c < k; ++c) {
+      const double v = block_reduce_col(part, ng, k, c, sh);
+      if (threadIdx.x == 0) f(c, v);
+      __syncthreads();
+    }
+  } else {
+    for (int64_t c = threadIdx.x; c < k; c += NT) f(c, thread_reduce_col(part, ng, k, c));
+    __syncthreads();
+  }
 }
 
 // ---------------------------------------------------------------- set-up
 
-// R = B - V (V = A_mu X); partial ||B||^2 and ||R||^2 per column.
+// R = B - V; ||B||^2, ||R||^2 -> scalars (last block): stopping flags, iters = 0.
 template <typename T>
 __global__ __launch_bounds__(NT) void cg_init_residual(int64_t n, int64_t k, const T* __restrict__ B,
-                                                       int64_t ldb, const T* __restrict__ V,
-                                                       T* __restrict__ R, double* __restrict__ pb,
-                                                       double* __restrict__ prr, int64_t rpw) {
+                                                       const T* __restrict__ V, T* __restrict__ R,
+                                                       double* __restrict__ pb, double* __restrict__ prr,
+                                                       int64_t rpw, double tol, CgScalars sc) {
   __shared__ double sh[NT];
   ColMap cm(k);
   const int64_t r0 = (int64_t)blockIdx.x * rpw;
@@ -63,7 +114,7 @@ __global__ __launch_bounds__(NT) void cg_init_residual(int64_t n, int64_t k, con
   double sb = 0.0, sr = 0.0;
   if (cm.c < k)
     for (int64_t i = r0 + cm.roff; i < r1; i += cm.rstep) {
-      const T b = B[i * ldb + cm.c];
+      const T b = B[i * k + cm.c];
       const T r = b - V[i * k + cm.c];
       R[i * k + cm.c] = r;
       sb += double(b) * double(b);
@@ -73,39 +124,27 @@ __global__ __launch_bounds__(NT) void cg_init_residual(int64_t n, int64_t k, con
   if (threadIdx.x < k) pb[blockIdx.x * k + threadIdx.x] = sh[threadIdx.x];
   colmap_reduce(sr, cm, sh);
   if (threadIdx.x < k) prr[blockIdx.x * k + threadIdx.x] = sh[threadIdx.x];
-}
-
-// P = Z; rz[0][c] = sum partials; bnorm2; done flags for columns already converged.
-__global__ void cg_init_scalars(int64_t k, int ng, const double* __restrict__ pb,
-                                const double* __restrict__ prr, const double* __restrict__ prz,
-                                double tol, CgScalars sc) {
-  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= k) return;
-  const double b2 = sum_partials(pb, ng, k, c);
-  const double r2 = sum_partials(prr, ng, k, c);
-  sc.bnorm2[c] = b2;
-  sc.rnorm2[c] = r2;
-  sc.rz[c] = sum_partials(prz, ng, k, c);
-  sc.iters[c] = 0;
-  const bool conv = r2 <= tol * tol * b2;
-  sc.done[c] = conv ? 1 : 0;
-  sc.status[c] = conv ? NYS_OK : NYS_NOT_CONVERGED;
-}
-
-template <typename T>
-__global__ void copy_cols(int64_t n, int64_t k, const T* __restrict__ Z, T* __restrict__ P) {
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx < n * k) P[idx] = Z[idx];
+  if (!last_block(sc.ctr, gridDim.x)) return;
+  const int ng = gridDim.x;
+  reduce_cols_last(pb, ng, k, sh, [&](int64_t c, double v) { sc.bnorm2[c] = v; });
+  reduce_cols_last(prr, ng, k, sh, [&](int64_t c, double v) {
+    sc.rnorm2[c] = v;
+    const bool conv = v <= tol * tol * sc.bnorm2[c];
+    sc.done[c] = conv ? 1 : 0;
+    sc.conv[c] = conv ? 1 : 0;
+    sc.status[c] = conv ? NYS_OK : NYS_NOT_CONVERGED;
+    sc.iters[c] = 0;
+  });
 }
 
 // ---------------------------------------------------------------- iteration
 
-// partial p^T v per column
+// partial p^T v; last block: alpha = rz / p^T v (breakdown when p^T v <= 0).
 template <typename T>
-__global__ __launch_bounds__(NT) void cg_pv_partial(int64_t n, int64_t k, const T* __restrict__ P,
-                                                    const T* __restrict__ V, double* __restrict__ ppv,
-                                                    int64_t rpw, const int* __restrict__ alldone) {
-  if (*alldone) return;
+__global__ __launch_bounds__(NT) void cg_pv_alpha(int64_t n, int64_t k, const T* __restrict__ P,
+                                                  const T* __restrict__ V, double* __restrict__ ppv,
+                                                  int64_t rpw, CgScalars sc, int par) {
+  if (*sc.alldone) return;
   __shared__ double sh[NT];
   ColMap cm(k);
   const int64_t r0 = (int64_t)blockIdx.x * rpw;
@@ -116,37 +155,36 @@ __global__ __launch_bounds__(NT) void cg_pv_partial(int64_t n, int64_t k, const 
       s += double(P[i * k + cm.c]) * double(V[i * k + cm.c]);
   colmap_reduce(s, cm, sh);
   if (threadIdx.x < k) ppv[blockIdx.x * k + threadIdx.x] = sh[threadIdx.x];
-}
-
-// alpha = rz / p^T v; X += alpha P; R -= alpha V; partial ||R||^2.
-template <typename T>
-__global__ __launch_bounds__(NT) void cg_update(int64_t n, int64_t k, int ng_pv,
-                                                const double* __restrict__ ppv, CgScalars sc, int par,
-                                                const T* __restrict__ P, const T* __restrict__ V,
-                                                T* __restrict__ X, int64_t ldx, T* __restrict__ R,
-                                                double* __restrict__ prr, int64_t rpw) {
-  if (*sc.alldone) return;
-  __shared__ double sh[NT];
-  __shared__ double alpha_s[NT];
-  ColMap cm(k);
-  for (int64_t c = threadIdx.x; c < k; c += NT) {
+  if (!last_block(sc.ctr, gridDim.x)) return;
+  reduce_cols_last(ppv, gridDim.x, k, sh, [&](int64_t c, double pv) {
     double a = 0.0;
     if (!sc.done[c]) {
-      const double pv = sum_partials(ppv, ng_pv, k, c);
       if (pv > 0.0) {
         a = sc.rz[par * k + c] / pv;
-      } else if (blockIdx.x == 0) {
+      } else {
         sc.status[c] = NYS_ERR_BREAKDOWN;
+        sc.done[c] = 1;
       }
     }
-    alpha_s[c] = a;
-  }
-  __syncthreads();
+    sc.alpha[c] = a;
+  });
+}
+
+// X += alpha P; R -= alpha V; ||R||^2 -> last block: stopping test, iters++.
+template <typename T>
+__global__ __launch_bounds__(NT) void cg_update(int64_t n, int64_t k, const T* __restrict__ P,
+                                                const T* __restrict__ V, T* __restrict__ X,
+                                                int64_t ldx, T* __restrict__ R,
+                                                double* __restrict__ prr, int64_t rpw, double tol,
+                                                CgScalars sc) {
+  if (*sc.alldone) return;
+  __shared__ double sh[NT];
+  ColMap cm(k);
   const int64_t r0 = (int64_t)blockIdx.x * rpw;
   const int64_t r1 = r0 + rpw < n ? r0 + rpw : n;
   double s = 0.0;
   if (cm.c < k) {
-    const T a = T(alpha_s[cm.c]);
+    const T a = T(sc.alpha[cm.c]);
     for (int64_t i = r0 + cm.roff; i < r1; i += cm.rstep) {
       const int64_t e = i * k + cm.c;
       X[i * ldx + cm.c] += a * P[e];
@@ -157,15 +195,46 @@ __global__ __launch_bounds__(NT) void cg_update(int64_t n, int64_t k, int ng_pv,
   }
   colmap_reduce(s, cm, sh);
   if (threadIdx.x < k) prr[blockIdx.x * k + threadIdx.x] = sh[threadIdx.x];
+  if (!last_block(sc.ctr, gridDim.x)) return;
+  reduce_cols_last(prr, gridDim.x, k, sh, [&](int64_t c, double rr) {
+    if (!sc.done[c]) {
+      sc.rnorm2[c] = rr;
+      sc.iters[c] += 1;
+      const bool conv = rr <= tol * tol * sc.bnorm2[c];
+      sc.conv[c] = conv ? 1 : 0;
+      if (conv) sc.status[c] = NYS_OK;
+    }
+  });
 }
 
-// partial rz and the direction update are split: cg_rz_partial computes
-// r^T z per column; cg_direction applies beta and the stopping test.
+// Last-block tail of the r^T z kernels.  init: rz[0] = r^T z.  Iteration:
+// beta = rz_new / rz[par], rz[1-par] = rz_new, done |= conv; all-done flag.
+__device__ void rz_tail(const double* prz, int ng, int64_t k, double* sh, CgScalars sc, int par,
+                        bool init) {
+  reduce_cols_last(prz, ng, k, sh, [&](int64_t c, double rzn) {
+    if (init) {
+      sc.rz[c] = rzn;
+      sc.beta[c] = 0.0;
+    } else if (!sc.done[c]) {
+      sc.beta[c] = rzn / sc.rz[par * k + c];
+      sc.rz[(1 - par) * k + c] = rzn;
+      if (sc.conv[c]) sc.done[c] = 1;
+    }
+  });
+  __shared__ int any;
+  if (threadIdx.x == 0) any = 0;
+  __syncthreads();
+  for (int64_t c = threadIdx.x; c < k; c += NT)
+    if (!sc.done[c]) any = 1;
+  __syncthreads();
+  if (threadIdx.x == 0) *sc.alldone = any ? 0 : 1;
+}
+
 template <typename T>
-__global__ __launch_bounds__(NT) void cg_rz_partial(int64_t n, int64_t k, const T* __restrict__ R,
-                                                    const T* __restrict__ Z, double* __restrict__ prz,
-                                                    int64_t rpw, const int* __restrict__ alldone) {
-  if (alldone && *alldone) return;
+__global__ __launch_bounds__(NT) void cg_rz(int64_t n, int64_t k, const T* __restrict__ R,
+                                            const T* __restrict__ Z, double* __restrict__ prz,
+                                            int64_t rpw, CgScalars sc, int par, int init) {
+  if (!init && *sc.alldone) return;
   __shared__ double sh[NT];
   ColMap cm(k);
   const int64_t r0 = (int64_t)blockIdx.x * rpw;
@@ -176,287 +245,313 @@ __global__ __launch_bounds__(NT) void cg_rz_partial(int64_t n, int64_t k, const 
       s += double(R[i * k + cm.c]) * double(Z[i * k + cm.c]);
   colmap_reduce(s, cm, sh);
   if (threadIdx.x < k) prz[blockIdx.x * k + threadIdx.x] = sh[threadIdx.x];
+  if (!last_block(sc.ctr, gridDim.x)) return;
+  rz_tail(prz, gridDim.x, k, sh, sc, par, init != 0);
 }
 
-// beta = rz_new / rz_old; P = Z + beta P for unfinished columns; stopping test
-// ||r||^2 <= tol^2 ||b||^2 on the recursive residual; iteration counters.
+// P = Z + beta P for unfinished columns (init: P = Z for every column).
 template <typename T>
-__global__ __launch_bounds__(NT) void cg_direction(int64_t n, int64_t k, int ng, const double* __restrict__ prz,
-                                                   const double* __restrict__ prr, CgScalars sc, int par,
-                                                   double tol, const T* __restrict__ Z,
-                                                   T* __restrict__ P, int64_t rpw) {
-  if (*sc.alldone) return;
-  __shared__ double beta_s[NT];
-  __shared__ int upd_s[NT];
-  ColMap cm(k);
-  for (int64_t c = threadIdx.x; c < k; c += NT) {
-    int upd = 0;
-    double beta = 0.0;
-    if (!sc.done[c]) {
-      const double rzn = sum_partials(prz, ng, k, c);
-      const double rr = sum_partials(prr, ng, k, c);
-      beta = rzn / sc.rz[par * k + c];
-      const bool brk = sc.status[c] == NYS_ERR_BREAKDOWN;
-      const bool conv = rr <= tol * tol * sc.bnorm2[c];
-      upd = (brk || conv) ? 0 : 1;
-      if (blockIdx.x == 0) {
-        sc.rz[(1 - par) * k + c] = rzn;
-        sc.rnorm2[c] = rr;
-        if (!brk) sc.iters[c] += 1;
-        if (conv && !brk) sc.status[c] = NYS_OK;
-        if (conv || brk) sc.done[c] = 1;
-      }
-    }
-    beta_s[c] = beta;
-    upd_s[c] = upd;
-  }
-  __syncthreads();
-  const int64_t r0 = (int64_t)blockIdx.x * rpw;
-  const int64_t r1 = r0 + rpw < n ? r0 + rpw : n;
-  if (cm.c < k && upd_s[cm.c]) {
-    const T b = T(beta_s[cm.c]);
-    for (int64_t i = r0 + cm.roff; i < r1; i += cm.rstep) {
-      const int64_t e = i * k + cm.c;
-      P[e] = Z[e] + b * P[e];
-    }
-  }
-}
-
-// all-done flag: 1 when every column is done
-__global__ void cg_alldone(int64_t k, CgScalars sc) {
-  __shared__ int any;
-  if (threadIdx.x == 0) any = 0;
-  __syncthreads();
-  for (int64_t c = threadIdx.x; c < k; c += blockDim.x)
-    if (!sc.done[c]) any = 1;
-  __syncthreads();
-  if (threadIdx.x == 0) *sc.alldone = any ? 0 : 1;
-}
-
-// ---------------------------------------------------------------- apply
-
-// part[g][j] = sum_{i in rows of g} U[i][j] r[i]   (k = 1)
-template <typename TU, typename T, int LQ>
-__global__ __launch_bounds__(NT) void utr_partial(int64_t n, int64_t l, const TU* __restrict__ U,
-                                                  int64_t ldu, const T* __restrict__ r,
-                                                  double* __restrict__ part, int64_t rpw,
-                                                  const int* __restrict__ alldone) {
-  if (alldone && *alldone) return;
-  __shared__ T rs[NT];
-  const int t = threadIdx.x;
-  const int64_t r0 = (int64_t)blockIdx.x * rpw;
-  const int64_t r1 = r0 + rpw < n ? r0 + rpw : n;
-  T acc[LQ];
-#pragma unroll
-  for (int q = 0; q < LQ; ++q) acc[q] = T(0);
-  for (int64_t ib = r0; ib < r1; ib += NT) {
-    __syncthreads();
-    rs[t] = (ib + t < r1) ? r[ib + t] : T(0);
-    __syncthreads();
-    const int cnt = (int)((r1 - ib) < NT ? (r1 - ib) : NT);
-    for (int ii = 0; ii < cnt; ++ii) {
-      const T ri = rs[ii];
-      const TU* u = U + (ib + ii) * ldu;
-#pragma unroll
-      for (int q = 0; q < LQ; ++q) {
-        const int64_t j = t + (int64_t)q * NT;
-        if (j < l) acc[q] += T(u[j]) * ri;
-      }
-    }
-  }
-#pragma unroll
-  for (int q = 0; q < LQ; ++q) {
-    const int64_t j = t + (int64_t)q * NT;
-    if (j < l) part[(int64_t)blockIdx.x * l + j] = double(acc[q]);
-  }
-}
-
-// C'[j][c] = ((lam_l + mu_c)/(lam_j + mu_c) - 1) * sum_g part[g][j][c]
-__global__ void apply_scale(int64_t l, int64_t k, int ng, const double* __restrict__ part,
-                            const double* __restrict__ lam, const double* __restrict__ mu,
-                            int64_t nrhs, double* __restrict__ Cs, const int* __restrict__ done) {
+__global__ void cg_direction(int64_t n, int64_t k, const T* __restrict__ Z, T* __restrict__ P,
+                             CgScalars sc, int init) {
+  if (!init && *sc.alldone) return;
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= l * k) return;
-  const int64_t j = idx / k, c = idx % k;
-  double s = 0.0;
-  for (int g = 0; g < ng; ++g) s += part[(int64_t)g * l * k + idx];
-  const double m = mu[c / nrhs];
-  const double f = (lam[l - 1] + m) / (lam[j] + m) - 1.0;
-  Cs[idx] = (done && done[c]) ? 0.0 : f * s;
+  if (idx >= n * k) return;
+  const int64_t c = idx % k;
+  if (init) {
+    P[idx] = Z[idx];
+  } else if (!sc.done[c]) {
+    P[idx] = Z[idx] + T(sc.beta[c]) * P[idx];
+  }
 }
 
-// z_i = r_i + sum_j U[i][j] C'[j]  (k = 1), one wave per row, C' in LDS.
+// ---------------------------------------------------------------- apply, k = 1
+
+// C'[j] = ((lam_l + mu)/(lam_j + mu) - 1) (U^T r)[j].  Grid (column blocks of
+// 64, row chunks); thread (tx, ty): column tx of the block, rows ty (mod 4).
+// The last row chunk of each column block to finish sums the chunk partials
+// in chunk order.
 template <typename TU, typename T>
-__global__ __launch_bounds__(NT) void uc_rows(int64_t n, int64_t l, const TU* __restrict__ U, int64_t ldu,
-                                              const double* __restrict__ Cs, const T* __restrict__ r,
-                                              T* __restrict__ z, int64_t rows_per_wave,
-                                              const int* __restrict__ alldone) {
+__global__ __launch_bounds__(NT) void utr_scale(int64_t n, int64_t l, const TU* __restrict__ U,
+                                                int64_t ldu, const T* __restrict__ r,
+                                                double* __restrict__ part, int64_t rows_per_chunk,
+                                                const double* __restrict__ lam,
+                                                const double* __restrict__ mu, double* __restrict__ Cs,
+                                                unsigned* __restrict__ ctr,
+                                                const int* __restrict__ alldone) {
   if (alldone && *alldone) return;
+  __shared__ double red[4][64];
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  const int64_t j = (int64_t)blockIdx.x * 64 + tx;
+  const int64_t i0 = (int64_t)blockIdx.y * rows_per_chunk;
+  const int64_t i1 = i0 + rows_per_chunk < n ? i0 + rows_per_chunk : n;
+  double a0 = 0.0, a1 = 0.0;
+  if (j < l) {
+    int64_t i = i0 + ty;
+    for (; i + 4 < i1; i += 8) {
+      a0 += double(U[i * ldu + j]) * double(r[i]);
+      a1 += double(U[(i + 4) * ldu + j]) * double(r[i + 4]);
+    }
+    if (i < i1) a0 += double(U[i * ldu + j]) * double(r[i]);
+  }
+  red[ty][tx] = a0 + a1;
+  __syncthreads();
+  if (ty == 0 && j < l)
+    part[(int64_t)blockIdx.y * l + j] = (red[0][tx] + red[1][tx]) + (red[2][tx] + red[3][tx]);
+  if (!last_block(ctr + blockIdx.x, gridDim.y)) return;
+  // chunk partials: thread (tx, ty) sums chunks q = ty (mod 4), then in order
+  double sp = 0.0;
+  if (j < l)
+    for (unsigned q = ty; q < gridDim.y; q += 4) sp += part[(int64_t)q * l + j];
+  red[ty][tx] = sp;
+  __syncthreads();
+  if (ty == 0 && j < l) {
+    const double sum = (red[0][tx] + red[1][tx]) + (red[2][tx] + red[3][tx]);
+    const double m = mu[0];
+    Cs[j] = ((lam[l - 1] + m) / (lam[j] + m) - 1.0) * sum;
+  }
+}
+
+// z_i = r_i + sum_j U[i][j] C'[j] (one wave per row).  mode 0: plain apply;
+// mode 1: also r^T z for the set-up; mode 2: r^T z, beta and flags.
+template <typename TU, typename T>
+__global__ __launch_bounds__(NT) void uc_rz(int64_t n, int64_t l, const TU* __restrict__ U, int64_t ldu,
+                                            const double* __restrict__ Cs, const T* __restrict__ r,
+                                            T* __restrict__ z, int64_t rows_per_wave,
+                                            double* __restrict__ prz, CgScalars sc, int par, int mode) {
+  if (mode == 2 && *sc.alldone) return;
   extern __shared__ char smem[];
   T* cs = reinterpret_cast<T*>(smem);
+  __shared__ double sh[NT];
   for (int64_t j = threadIdx.x; j < l; j += NT) cs[j] = T(Cs[j]);
   __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int64_t w = (int64_t)blockIdx.x * 4 + wave;
-  const int64_t i0 = w * rows_per_wave;
-  for (int64_t i = i0; i < i0 + rows_per_wave && i < n; ++i) {
-    const TU* u = U + i * ldu;
-    T s = T(0);
-    for (int64_t j = lane; j < l; j += 64) s += T(u[j]) * cs[j];
-    s = wave_sum(s);
-    if (lane == 0) z[i] = r[i] + s;
+  const int64_t w0 = ((int64_t)blockIdx.x * 4 + wave) * rows_per_wave;
+  const int64_t w1 = w0 + rows_per_wave < n ? w0 + rows_per_wave : n;
+  double rzp = 0.0;
+  for (int64_t ib = w0; ib < w1; ib += 4) {
+    // four rows at once: independent loads in flight
+    T s0 = T(0), s1 = T(0), s2 = T(0), s3 = T(0);
+    const int64_t nr = (w1 - ib) < 4 ? (w1 - ib) : 4;
+    const TU* u0 = U + ib * ldu;
+    for (int64_t j = lane; j < l; j += 64) {
+      const T c = cs[j];
+      s0 += T(u0[j]) * c;
+      if (nr > 1) s1 += T(u0[ldu + j]) * c;
+      if (nr > 2) s2 += T(u0[2 * ldu + j]) * c;
+      if (nr > 3) s3 += T(u0[3 * ldu + j]) * c;
+    }
+    s0 = wave_sum(s0);
+    s1 = wave_sum(s1);
+    s2 = wave_sum(s2);
+    s3 = wave_sum(s3);
+    const T sv[4] = {s0, s1, s2, s3};
+    for (int q = 0; q < nr; ++q) {
+      const T ri = r[ib + q];
+      const T zi = ri + sv[q];
+      if (lane == q) z[ib + q] = zi;
+      rzp += double(ri) * double(zi);
+    }
   }
+  if (mode == 0) return;
+  // every lane of a wave holds the same rzp; lane 0 contributes it
+  const double tot = block_sum(lane == 0 ? rzp : 0.0, sh);
+  if (threadIdx.x == 0) prz[blockIdx.x] = tot;
+  if (!last_block(sc.ctr, gridDim.x)) return;
+  rz_tail(prz, gridDim.x, 1, sh, sc, par, mode == 1);
 }
 
-int64_t rows_per_group(int64_t n, int ng) { return cdiv(n, ng); }
+// ---------------------------------------------------------------- apply, k > 1
+
+// C'[j][c] = ((lam_l + mu_c)/(lam_j + mu_c) - 1) C[j][c]
+__global__ void apply_scale_blk(int64_t l, int64_t k, const double* __restrict__ C,
+                                const double* __restrict__ lam, const double* __restrict__ mu,
+                                int64_t nrhs, double* __restrict__ Cs, const int* __restrict__ done,
+                                const int* __restrict__ alldone) {
+  if (alldone && *alldone) return;
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= l * k) return;
+  const int64_t j = idx / k, c = idx % k;
+  const double m = mu[c / nrhs];
+  const double f = (lam[l - 1] + m) / (lam[j] + m) - 1.0;
+  Cs[idx] = (done && done[c]) ? 0.0 : f * C[idx];
+}
+
+template <typename T>
+__global__ void copy_vec(int64_t count, const T* __restrict__ src, T* __restrict__ dst,
+                         const int* __restrict__ alldone) {
+  if (alldone && *alldone) return;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) dst[i] = src[i];
+}
+
+int64_t groups_for(int64_t n, int64_t k) {
+  int64_t g = cdiv(n * k, 1024);
+  if (g < 1) g = 1;
+  if (g > 512) g = 512;
+  return g;
+}
+
+// k = 1: Cs = scaled U^T r.
+nys_status utr_launch(const PrecDesc& P, const double* mu_dev, const void* R, bool f32, double* part,
+                      double* Cs, unsigned* ctr, const int* alldone, hipStream_t s) {
+  const int64_t n = P.n, l = P.ell;
+  const int64_t cb = cdiv(l, 64);
+  int64_t rc = cdiv(512, cb);
+  if (rc > cdiv(n, 64)) rc = cdiv(n, 64);
+  if (rc < 1) rc = 1;
+  const int64_t rpc = cdiv(n, rc);
+  rc = cdiv(n, rpc);
+  dim3 grid((unsigned)cb, (unsigned)rc);
+#define LU(TU_, T_)                                                                                \
+  hipLaunchKernelGGL((utr_scale<TU_, T_>), grid, dim3(NT), 0, s, n, l, static_cast<const TU_*>(P.U), \
+                     P.ldu, static_cast<const T_*>(R), part, rpc, P.lam, mu_dev, Cs, ctr, alldone)
+  if (P.dtype == NYS_F64 && !f32) LU(double, double);
+  else if (P.dtype == NYS_F64 && f32) LU(double, float);
+  else if (P.dtype == NYS_F32 && !f32) LU(float, double);
+  else LU(float, float);
+#undef LU
+  NYS_CHECK_LAUNCH();
+  return NYS_OK;
+}
+
+nys_status uc_launch(const PrecDesc& P, const double* Cs, const void* R, void* Z, bool f32, double* prz,
+                     const CgScalars& sc, int par, int mode, hipStream_t s) {
+  const int64_t n = P.n, l = P.ell;
+  int64_t rpw = cdiv(n, 4 * 512);  // at most 512 workgroups (partial buffer size)
+  rpw = cdiv(rpw < 4 ? 4 : rpw, 4) * 4;
+  const int64_t nb = cdiv(cdiv(n, rpw), 4);
+  const size_t sh = (size_t)l * (f32 ? 4 : 8);
+#define LC(TU_, T_)                                                                                  \
+  hipLaunchKernelGGL((uc_rz<TU_, T_>), dim3((unsigned)nb), dim3(NT), sh, s, n, l,                    \
+                     static_cast<const TU_*>(P.U), P.ldu, Cs, static_cast<const T_*>(R),              \
+                     static_cast<T_*>(Z), rpw, prz, sc, par, mode)
+  if (P.dtype == NYS_F64 && !f32) LC(double, double);
+  else if (P.dtype == NYS_F64 && f32) LC(double, float);
+  else if (P.dtype == NYS_F32 && !f32) LC(float, double);
+  else LC(float, float);
+#undef LC
+  NYS_CHECK_LAUNCH();
+  return NYS_OK;
+}
+
+// Block apply Z = R + U (f .* (U^T R)) through the MFMA GEMM (float64 vectors).
+nys_status apply_block(const PrecDesc& P, const double* mu_dev, int64_t nrhs, const double* R, double* Z,
+                       int64_t k, const int* done, const int* alldone, double* part, size_t part_elems,
+                       double* C, double* Cs, hipStream_t s) {
+  const int64_t n = P.n, l = P.ell;
+  if (P.dtype == NYS_F64)
+    NYS_TRY((gemm<double, double, double>(true, false, l, k, n, 1.0, static_cast<const double*>(P.U), P.ldu, R,
+                                          k, 0.0, C, k, part, part_elems, s, alldone)));
+  else
+    NYS_TRY((gemm<double, float, double>(true, false, l, k, n, 1.0, static_cast<const float*>(P.U), P.ldu, R,
+                                         k, 0.0, C, k, part, part_elems, s, alldone)));
+  hipLaunchKernelGGL(apply_scale_blk, dim3((unsigned)cdiv(l * k, 256)), dim3(256), 0, s, l, k, C, P.lam,
+                     mu_dev, nrhs, Cs, done, alldone);
+  NYS_CHECK_LAUNCH();
+  hipLaunchKernelGGL(copy_vec<double>, dim3((unsigned)cdiv(n * k, 256)), dim3(256), 0, s, n * k, R, Z,
+                     alldone);
+  NYS_CHECK_LAUNCH();
+  if (P.dtype == NYS_F64)
+    NYS_TRY((gemm<double, double, double>(false, false, n, k, l, 1.0, static_cast<const double*>(P.U), P.ldu,
+                                          Cs, k, 1.0, Z, k, part, part_elems, s, alldone)));
+  else
+    NYS_TRY((gemm<double, float, double>(false, false, n, k, l, 1.0, static_cast<const float*>(P.U), P.ldu,
+                                         Cs, k, 1.0, Z, k, part, part_elems, s, alldone)));
+  return NYS_OK;
+}
 
 }  // namespace
 
 // ---------------------------------------------------------------- host API
 
-nys_status precond_apply_dev(const PrecDesc& P, const double* mu_dev, int64_t nrhs, const void* R,
-                             void* Z, int64_t k, bool f32, const int* done, const int* alldone,
-                             double* part, size_t part_elems, double* Cs, void* Ctmp,
-                             hipStream_t s) {
-  const int64_t n = P.n, l = P.ell;
-  const int ng = 2 * (num_cus() < 256 ? num_cus() : 256);
-  if (k == 1) {
-    const int64_t rpw = rows_per_group(n, ng);
-    const int lq = (int)cdiv(l, NT);
-#define LU(TU_, T_, LQ_)                                                                    \
-  hipLaunchKernelGGL((utr_partial<TU_, T_, LQ_>), dim3(ng), dim3(NT), 0, s, n, l,          \
-                     static_cast<const TU_*>(P.U), P.ldu, static_cast<const T_*>(R), part, rpw, alldone)
-#define LUQ(TU_, T_) \
-  if (lq <= 1) LU(TU_, T_, 1); else if (lq <= 2) LU(TU_, T_, 2); else if (lq <= 4) LU(TU_, T_, 4); else LU(TU_, T_, 8)
-    if (lq > 8) { set_error("preconditioner rank > 2048 not supported"); return NYS_ERR_ARG; }
-    if (P.dtype == NYS_F64 && !f32) { LUQ(double, double); }
-    else if (P.dtype == NYS_F64 && f32) { LUQ(double, float); }
-    else if (P.dtype == NYS_F32 && !f32) { LUQ(float, double); }
-    else { LUQ(float, float); }
-#undef LUQ
-#undef LU
-    NYS_CHECK_LAUNCH();
-    hipLaunchKernelGGL(apply_scale, dim3((unsigned)cdiv(l, 256)), dim3(256), 0, s, l, (int64_t)1, ng,
-                       part, P.lam, mu_dev, nrhs, Cs, done);
-    NYS_CHECK_LAUNCH();
-    const int64_t rpwave = 4;
-    const unsigned nb = (unsigned)cdiv(cdiv(n, rpwave), 4);
-    const size_t sh = (size_t)l * (f32 ? 4 : 8);
-#define LC(TU_, T_)                                                                               \
-  hipLaunchKernelGGL((uc_rows<TU_, T_>), dim3(nb), dim3(NT), sh, s, n, l, static_cast<const TU_*>(P.U), \
-                     P.ldu, Cs, static_cast<const T_*>(R), static_cast<T_*>(Z), rpwave, alldone)
-    if (P.dtype == NYS_F64 && !f32) LC(double, double);
-    else if (P.dtype == NYS_F64 && f32) LC(double, float);
-    else if (P.dtype == NYS_F32 && !f32) LC(float, double);
-    else LC(float, float);
-#undef LC
-    NYS_CHECK_LAUNCH();
-    return NYS_OK;
-  }
-  // block form: C = U^T R (l x k), C' = f .* C, Z = R + U C'
-  if (f32) {
-    set_error("float32 block preconditioner apply is not available; use k = 1 or float64");
-    return NYS_ERR_ARG;
-  }
-  const double* Rd = static_cast<const double*>(R);
-  double* Zd = static_cast<double*>(Z);
-  double* C = static_cast<double*>(Ctmp);
-  if (P.dtype == NYS_F64)
-    NYS_TRY((gemm<double, double, double>(true, false, l, k, n, 1.0, static_cast<const double*>(P.U),
-                                          P.ldu, Rd, k, 0.0, C, k, part, part_elems, s)));
-  else
-    NYS_TRY((gemm<double, float, double>(true, false, l, k, n, 1.0, static_cast<const float*>(P.U),
-                                         P.ldu, Rd, k, 0.0, C, k, part, part_elems, s)));
-  hipLaunchKernelGGL(apply_scale, dim3((unsigned)cdiv(l * k, 256)), dim3(256), 0, s, l, k, 1, C,
-                     P.lam, mu_dev, nrhs, Cs, done);
-  NYS_CHECK_LAUNCH();
-  NYS_HIP(hipMemcpyAsync(Zd, Rd, sizeof(double) * n * k, hipMemcpyDeviceToDevice, s));
-  if (P.dtype == NYS_F64)
-    NYS_TRY((gemm<double, double, double>(false, false, n, k, l, 1.0, static_cast<const double*>(P.U),
-                                          P.ldu, Cs, k, 1.0, Zd, k, part, part_elems, s)));
-  else
-    NYS_TRY((gemm<double, float, double>(false, false, n, k, l, 1.0, static_cast<const float*>(P.U),
-                                         P.ldu, Cs, k, 1.0, Zd, k, part, part_elems, s)));
-  return NYS_OK;
-}
-
 size_t precond_part_elems(int64_t n, int64_t l, int64_t k) {
-  const size_t a = (size_t)(2 * 256) * (size_t)l * (size_t)k;
+  const size_t a = (size_t)512 * (size_t)l * (size_t)k;
   const size_t b = gemm_scratch_elems(l, k);
   const size_t c = gemm_scratch_elems(n, k);
   size_t m = a > b ? a : b;
   return m > c ? m : c;
 }
 
+nys_status precond_apply_standalone(const PrecDesc& P, const double* mu_dev, const double* R, double* Z,
+                                    int64_t k, double* part, size_t part_elems, double* Cs, double* Ct,
+                                    unsigned* ctr, hipStream_t s) {
+  if (k == 1) {
+    NYS_TRY(utr_launch(P, mu_dev, R, false, part, Cs, ctr, nullptr, s));
+    CgScalars none{};
+    return uc_launch(P, Cs, R, Z, false, nullptr, none, 0, 0, s);
+  }
+  return apply_block(P, mu_dev, k, R, Z, k, nullptr, nullptr, part, part_elems, Ct, Cs, s);
+}
+
 template <typename T>
-nys_status cg_kernels_init(int64_t n, int64_t k, const T* B, int64_t ldb, const T* V, T* R,
-                           double* pb, double* prr, int ng, hipStream_t s) {
-  const int64_t rpw = rows_per_group(n, ng);
-  hipLaunchKernelGGL(cg_init_residual<T>, dim3(ng), dim3(NT), 0, s, n, k, B, ldb, V, R, pb, prr, rpw);
+nys_status pcg_setup(int64_t n, int64_t k, const PrecDesc& P, const double* mu_dev, int64_t nrhs,
+                     const T* B, const T* V, T* R, T* Z, T* Pd, PcgWork& w, const CgScalars& sc, double tol,
+                     hipStream_t s) {
+  const bool f32 = sizeof(T) == 4;
+  const int64_t ng = groups_for(n, k);
+  const int64_t rpw = cdiv(n, ng);
+  hipLaunchKernelGGL(cg_init_residual<T>, dim3((unsigned)ng), dim3(NT), 0, s, n, k, B, V, R, w.pb, w.prr, rpw,
+                     tol, sc);
+  NYS_CHECK_LAUNCH();
+  if (k == 1) {
+    NYS_TRY(utr_launch(P, mu_dev, R, f32, w.apart, w.Cs, sc.ctr + 1, nullptr, s));
+    NYS_TRY(uc_launch(P, w.Cs, R, Z, f32, w.prz, sc, 0, 1, s));
+  } else {
+    if (f32) {
+      set_error("float32 block preconditioner apply is not available; use k = 1 or float64");
+      return NYS_ERR_ARG;
+    }
+    NYS_TRY(apply_block(P, mu_dev, nrhs, reinterpret_cast<const double*>(R), reinterpret_cast<double*>(Z), k,
+                        nullptr, nullptr, w.apart, w.apart_elems, w.Ct, w.Cs, s));
+    hipLaunchKernelGGL(cg_rz<T>, dim3((unsigned)ng), dim3(NT), 0, s, n, k, R, Z, w.prz, rpw, sc, 0, 1);
+    NYS_CHECK_LAUNCH();
+  }
+  hipLaunchKernelGGL(cg_direction<T>, dim3((unsigned)cdiv(n * k, 256)), dim3(256), 0, s, n, k, Z, Pd, sc, 1);
   NYS_CHECK_LAUNCH();
   return NYS_OK;
 }
 
 template <typename T>
-nys_status cg_kernels_init2(int64_t n, int64_t k, const T* R, const T* Z, T* P, double* pb,
-                            double* prr, double* prz, double tol, const CgScalars& sc, int ng,
-                            hipStream_t s) {
-  const int64_t rpw = rows_per_group(n, ng);
-  hipLaunchKernelGGL(cg_rz_partial<T>, dim3(ng), dim3(NT), 0, s, n, k, R, Z, prz, rpw,
-                     (const int*)nullptr);
+nys_status pcg_iteration(int64_t n, int64_t k, const PrecDesc& P, const double* mu_dev, int64_t nrhs,
+                         const T* V, T* X, int64_t ldx, T* R, T* Z, T* Pd, PcgWork& w, const CgScalars& sc,
+                         int par, double tol, hipStream_t s) {
+  const bool f32 = sizeof(T) == 4;
+  const int64_t ng = groups_for(n, k);
+  const int64_t rpw = cdiv(n, ng);
+  hipLaunchKernelGGL(cg_pv_alpha<T>, dim3((unsigned)ng), dim3(NT), 0, s, n, k, Pd, V, w.ppv, rpw, sc, par);
   NYS_CHECK_LAUNCH();
-  hipLaunchKernelGGL(cg_init_scalars, dim3((unsigned)cdiv(k, 256)), dim3(256), 0, s, k, ng, pb, prr,
-                     prz, tol, sc);
+  hipLaunchKernelGGL(cg_update<T>, dim3((unsigned)ng), dim3(NT), 0, s, n, k, Pd, V, X, ldx, R, w.prr, rpw, tol,
+                     sc);
   NYS_CHECK_LAUNCH();
-  hipLaunchKernelGGL(copy_cols<T>, dim3((unsigned)cdiv(n * k, 256)), dim3(256), 0, s, n, k, Z, P);
-  NYS_CHECK_LAUNCH();
-  hipLaunchKernelGGL(cg_alldone, dim3(1), dim3(256), 0, s, k, sc);
-  NYS_CHECK_LAUNCH();
-  return NYS_OK;
-}
-
-template <typename T>
-nys_status cg_kernels_step_a(int64_t n, int64_t k, const T* P, const T* V, T* X, int64_t ldx, T* R,
-                             double* ppv, double* prr, const CgScalars& sc, int par, int ng,
-                             hipStream_t s) {
-  const int64_t rpw = rows_per_group(n, ng);
-  hipLaunchKernelGGL(cg_pv_partial<T>, dim3(ng), dim3(NT), 0, s, n, k, P, V, ppv, rpw, sc.alldone);
-  NYS_CHECK_LAUNCH();
-  hipLaunchKernelGGL(cg_update<T>, dim3(ng), dim3(NT), 0, s, n, k, ng, ppv, sc, par, P, V, X, ldx, R,
-                     prr, rpw);
-  NYS_CHECK_LAUNCH();
-  return NYS_OK;
-}
-
-template <typename T>
-nys_status cg_kernels_step_b(int64_t n, int64_t k, const T* R, const T* Z, T* P, double* prz,
-                             const double* prr, const CgScalars& sc, int par, double tol, int ng,
-                             hipStream_t s) {
-  const int64_t rpw = rows_per_group(n, ng);
-  hipLaunchKernelGGL(cg_rz_partial<T>, dim3(ng), dim3(NT), 0, s, n, k, R, Z, prz, rpw, sc.alldone);
-  NYS_CHECK_LAUNCH();
-  hipLaunchKernelGGL(cg_direction<T>, dim3(ng), dim3(NT), 0, s, n, k, ng, prz, prr, sc, par, tol, Z, P,
-                     rpw);
-  NYS_CHECK_LAUNCH();
-  hipLaunchKernelGGL(cg_alldone, dim3(1), dim3(256), 0, s, k, sc);
+  if (k == 1) {
+    NYS_TRY(utr_launch(P, mu_dev, R, f32, w.apart, w.Cs, sc.ctr + 1, sc.alldone, s));
+    NYS_TRY(uc_launch(P, w.Cs, R, Z, f32, w.prz, sc, par, 2, s));
+  } else {
+    if (f32) {
+      set_error("float32 block preconditioner apply is not available; use k = 1 or float64");
+      return NYS_ERR_ARG;
+    }
+    NYS_TRY(apply_block(P, mu_dev, nrhs, reinterpret_cast<const double*>(R), reinterpret_cast<double*>(Z), k,
+                        sc.done, sc.alldone, w.apart, w.apart_elems, w.Ct, w.Cs, s));
+    hipLaunchKernelGGL(cg_rz<T>, dim3((unsigned)ng), dim3(NT), 0, s, n, k, R, Z, w.prz, rpw, sc, par, 0);
+    NYS_CHECK_LAUNCH();
+  }
+  hipLaunchKernelGGL(cg_direction<T>, dim3((unsigned)cdiv(n * k, 256)), dim3(256), 0, s, n, k, Z, Pd, sc, 0);
   NYS_CHECK_LAUNCH();
   return NYS_OK;
 }
 
-#define NYS_INST(T)                                                                                  \
-  template nys_status cg_kernels_init<T>(int64_t, int64_t, const T*, int64_t, const T*, T*, double*, \
-                                         double*, int, hipStream_t);                                 \
-  template nys_status cg_kernels_init2<T>(int64_t, int64_t, const T*, const T*, T*, double*,         \
-                                          double*, double*, double, const CgScalars&, int,           \
-                                          hipStream_t);                                              \
-  template nys_status cg_kernels_step_a<T>(int64_t, int64_t, const T*, const T*, T*, int64_t, T*,    \
-                                           double*, double*, const CgScalars&, int, int,             \
-                                           hipStream_t);                                             \
-  template nys_status cg_kernels_step_b<T>(int64_t, int64_t, const T*, const T*, T*, double*,        \
-                                           const double*, const CgScalars&, int, double, int,        \
-                                           hipStream_t);
-NYS_INST(double)
-NYS_INST(float)
-#undef NYS_INST
+template nys_status pcg_setup<double>(int64_t, int64_t, const PrecDesc&, const double*, int64_t, const double*,
+                                      const double*, double*, double*, double*, PcgWork&, const CgScalars&,
+                                      double, hipStream_t);
+template nys_status pcg_setup<float>(int64_t, int64_t, const PrecDesc&, const double*, int64_t, const float*,
+                                     const float*, float*, float*, float*, PcgWork&, const CgScalars&, double,
+                                     hipStream_t);
+template nys_status pcg_iteration<double>(int64_t, int64_t, const PrecDesc&, const double*, int64_t,
+                                          const double*, double*, int64_t, double*, double*, double*, PcgWork&,
+                                          const CgScalars&, int, double, hipStream_t);
+template nys_status pcg_iteration<float>(int64_t, int64_t, const PrecDesc&, const double*, int64_t, const float*,
+                                         float*, int64_t, float*, float*, float*, PcgWork&, const CgScalars&, int,
+                                         double, hipStream_t);
 
 }  // namespace nys

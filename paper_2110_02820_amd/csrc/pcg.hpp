@@ -12,46 +12,48 @@ struct PrecDesc {
   const double* lam;
 };
 
-// Per-column CG scalars (device arrays, k entries each; rz has 2k).
+// Per-column CG scalars (device arrays of k entries unless noted).
 struct CgScalars {
   double* rz;      // [2][k] r^T z, double-buffered by iteration parity
-  double* bnorm2;  // [k]
-  double* rnorm2;  // [k] recursive ||r||^2 after the last update
-  int* done;       // [k]
-  int* iters;      // [k]
-  int* status;     // [k]
+  double* bnorm2;  // ||b||^2
+  double* rnorm2;  // recursive ||r||^2 after the last update
+  double* alpha;
+  double* beta;
+  int* done;       // column finished (converged or broken down)
+  int* conv;       // stopping test met by the last update
+  int* iters;
+  int* status;
   int* alldone;    // [1]
+  unsigned* ctr;   // [64] arrival counters of the last-workgroup reductions (zeroed once)
 };
 
-// Z = P^{-1} R (eq. (NysPre)) for k columns (n x k row-major, ld = k).
-// f32 selects float vectors (R, Z); U may be float or double.  mu_dev: device
-// array indexed by column / nrhs.  done (nullable): columns to leave at Z = R.
-// part: partial sums (precond_part_elems doubles); Cs: l x k doubles;
-// Ctmp: l x k doubles.
-nys_status precond_apply_dev(const PrecDesc& P, const double* mu_dev, int64_t nrhs, const void* R,
-                             void* Z, int64_t k, bool f32, const int* done, const int* alldone,
-                             double* part, size_t part_elems, double* Cs, void* Ctmp,
-                             hipStream_t s);
+// Partial-sum buffers of one PCG run.
+struct PcgWork {
+  double *pb, *prr, *ppv, *prz;  // 512 x k each
+  double* apart;                 // precond_part_elems
+  size_t apart_elems;
+  double *Cs, *Ct;               // l x k each
+};
+
 size_t precond_part_elems(int64_t n, int64_t l, int64_t k);
 
-// R = B - V, partial ||B||^2 (pb) and ||R||^2 (prr); ng groups.
+// Z = P^{-1} R (eq. (NysPre)) for k float64 columns, outside the CG loop.
+// `ctr` points to 64 zeroed counters.
+nys_status precond_apply_standalone(const PrecDesc& P, const double* mu_dev, const double* R, double* Z,
+                                    int64_t k, double* part, size_t part_elems, double* Cs, double* Ct,
+                                    unsigned* ctr, hipStream_t s);
+
+// R = B - V, Z = P^{-1} R, P = Z, scalars (rz, ||b||, flags).  sc.ctr zeroed.
 template <typename T>
-nys_status cg_kernels_init(int64_t n, int64_t k, const T* B, int64_t ldb, const T* V, T* R,
-                           double* pb, double* prr, int ng, hipStream_t s);
-// rz from R, Z; scalars; P = Z; stopping flags.
+nys_status pcg_setup(int64_t n, int64_t k, const PrecDesc& P, const double* mu_dev, int64_t nrhs,
+                     const T* B, const T* V, T* R, T* Z, T* Pd, PcgWork& w, const CgScalars& sc, double tol,
+                     hipStream_t s);
+
+// One iteration after V = (A + mu I) P: alpha, X/R update, stopping test,
+// Z = P^{-1} R, beta, P = Z + beta P.  par = iteration parity.
 template <typename T>
-nys_status cg_kernels_init2(int64_t n, int64_t k, const T* R, const T* Z, T* P, double* pb,
-                            double* prr, double* prz, double tol, const CgScalars& sc, int ng,
-                            hipStream_t s);
-// p^T v partials, alpha, X += alpha P, R -= alpha V, ||R||^2 partials.
-template <typename T>
-nys_status cg_kernels_step_a(int64_t n, int64_t k, const T* P, const T* V, T* X, int64_t ldx, T* R,
-                             double* ppv, double* prr, const CgScalars& sc, int par, int ng,
-                             hipStream_t s);
-// r^T z partials, beta, P = Z + beta P, stopping test, all-done flag.
-template <typename T>
-nys_status cg_kernels_step_b(int64_t n, int64_t k, const T* R, const T* Z, T* P, double* prz,
-                             const double* prr, const CgScalars& sc, int par, double tol, int ng,
-                             hipStream_t s);
+nys_status pcg_iteration(int64_t n, int64_t k, const PrecDesc& P, const double* mu_dev, int64_t nrhs,
+                         const T* V, T* X, int64_t ldx, T* R, T* Z, T* Pd, PcgWork& w, const CgScalars& sc,
+                         int par, double tol, hipStream_t s);
 
 }  // namespace nys
