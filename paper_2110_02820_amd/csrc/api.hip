@@ -4,6 +4,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <vector>
 
@@ -101,8 +102,7 @@ hipStream_t S(void* stream) { return static_cast<hipStream_t>(stream); }
 
 struct Core {  // l x l float64 work shared by sketch and factor
   double *G, *L, *Linv, *Dinv, *T, *eig, *gscr, *nu, *part, *sig2;
-  int *info, *flags, *sweeps, *bar_err;
-  unsigned* bar;
+  int *info, *flags, *sweeps, *conv;
   size_t gscr_elems;
 };
 
@@ -121,8 +121,7 @@ void carve_core(Arena& a, int64_t l, Core& c) {
   c.info = a.take<int>(1);
   c.flags = a.take<int>(kMaxSweeps);
   c.sweeps = a.take<int>(1);
-  c.bar_err = a.take<int>(1);
-  c.bar = a.take<unsigned>(1);
+  c.conv = a.take<int>(1);
 }
 
 struct SketchWs {
@@ -343,7 +342,7 @@ nys_status cholqr2(double* Om, double* tmp, int64_t n, int64_t l, Core& c, int* 
   for (int pass = 0; pass < 2; ++pass) {
     NYS_TRY((gemm<double, double, double>(true, false, l, l, n, 1.0, src, l, src, l, 0.0, c.G, l,
                                           c.gscr, c.gscr_elems, s)));
-    NYS_TRY(cholesky(c.G, l, c.L, c.Dinv, c.info, c.bar, c.bar_err, s));
+    NYS_TRY(cholesky(c.G, l, c.L, c.Dinv, c.info, s));
     NYS_HIP(hipMemcpyAsync(&info_host[pass], c.info, sizeof(int), hipMemcpyDeviceToHost, s));
     NYS_TRY(tri_inverse(c.L, l, c.Dinv, c.Linv, s));
     NYS_TRY((gemm<double, double, double>(false, true, n, l, l, 1.0, src, l, c.Linv, l, 0.0, dst, l,
@@ -405,14 +404,23 @@ nys_status pcg_run(const OpDesc& op0, const PrecDesc& P, int64_t k, int64_t nrhs
   }
   NYS_TRY(pcg_setup<T>(n, k, P, mu_dev, nrhs, B, b.V, b.R, b.Z, b.P, b.w, b.sc, tol, s));
   op.skip = b.sc.alldone;
+  // single column with a partial-sum operator product: fused iteration
+  const bool fused = k == 1 && (op.kind == NYS_OP_XTX || (op.kind == NYS_OP_RBF && sizeof(T) == 8));
   int it = 0;
   int alldone_h = 0;
   NYS_HIP(hipMemcpyAsync(&alldone_h, b.sc.alldone, sizeof(int), hipMemcpyDeviceToHost, s));
   NYS_HIP(hipStreamSynchronize(s));
   while (!alldone_h && it < maxit) {
     const int par = it & 1;
-    NYS_TRY(matvec<T>(op, b.P, k, mu_dev, nrhs, mu_host, b.V, b, s));
-    NYS_TRY(pcg_iteration<T>(n, k, P, mu_dev, nrhs, b.V, X, k, b.R, b.Z, b.P, b.w, b.sc, par, tol, s));
+    if (fused) {
+      int ng = 0;
+      NYS_TRY(op_matvec_partials<T>(op, b.P, b.opscr, b.opscr_elems, &ng, s));
+      NYS_TRY(pcg_iteration_fused<T>(n, P, mu_dev, mu_host, b.opscr, ng, op.scale, b.V, X, b.R, b.Z, b.P, b.w,
+                                     b.sc, par, tol, s));
+    } else {
+      NYS_TRY(matvec<T>(op, b.P, k, mu_dev, nrhs, mu_host, b.V, b, s));
+      NYS_TRY(pcg_iteration<T>(n, k, P, mu_dev, nrhs, b.V, X, k, b.R, b.Z, b.P, b.w, b.sc, par, tol, s));
+    }
     ++it;
     if (it % check_every == 0 || it == maxit) {
       NYS_HIP(hipMemcpyAsync(&alldone_h, b.sc.alldone, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -693,7 +701,7 @@ nys_status nys_factor(const double* Omega, double* Y, nys_precond* P, void* ws, 
     // C^T C = Omega^T Y_nu  (lower factor L = C^T)
     NYS_TRY((gemm<double, double, double>(true, false, l, l, n, 1.0, Omega, l, Y, l, 0.0, c.G, l, c.gscr,
                                           c.gscr_elems, s)));
-    NYS_TRY(cholesky(c.G, l, c.L, c.Dinv, c.info, c.bar, c.bar_err, s));
+    NYS_TRY(cholesky(c.G, l, c.L, c.Dinv, c.info, s));
     NYS_HIP(hipMemcpyAsync(&info, c.info, sizeof(int), hipMemcpyDeviceToHost, s));
     NYS_HIP(hipStreamSynchronize(s));
     if (info == 0) break;
@@ -709,7 +717,7 @@ nys_status nys_factor(const double* Omega, double* Y, nys_precond* P, void* ws, 
   // thin SVD of B through B^T B = W S W^T:  U = B W S^{-1/2}, lam = max(0, S - nu)
   NYS_TRY((gemm<double, double, double>(true, false, l, l, n, 1.0, w.B, l, w.B, l, 0.0, c.G, l, c.gscr,
                                         c.gscr_elems, s)));
-  NYS_TRY(sym_eig(c.G, l, c.eig, c.flags, kMaxSweeps, c.sweeps, c.bar, c.bar_err, c.T, P->lam, c.sig2,
+  NYS_TRY(sym_eig(c.G, l, c.eig, c.flags, kMaxSweeps, c.sweeps, c.conv, c.T, P->lam, c.sig2,
                   c.nu, s));
   if (P->dtype == NYS_F64) {
     NYS_TRY((gemm<double, double, double>(false, false, n, l, l, 1.0, w.B, l, c.T, l, 0.0,
@@ -722,14 +730,13 @@ nys_status nys_factor(const double* Omega, double* Y, nys_precond* P, void* ws, 
     NYS_CHECK_LAUNCH();
   }
   double nu = 0.0;
-  int bar_err = 0;
+  int sweeps = 0;
   NYS_HIP(hipMemcpyAsync(&nu, c.nu, sizeof(double), hipMemcpyDeviceToHost, s));
-  NYS_HIP(hipMemcpyAsync(&bar_err, c.bar_err, sizeof(int), hipMemcpyDeviceToHost, s));
+  NYS_HIP(hipMemcpyAsync(&sweeps, c.sweeps, sizeof(int), hipMemcpyDeviceToHost, s));
   NYS_HIP(hipStreamSynchronize(s));
-  if (bar_err) {
-    set_error("device barrier time-out in the factorisation");
-    return NYS_ERR_DEVICE;
-  }
+  if (std::getenv("NYS_VERBOSE"))
+    std::fprintf(stderr, "[nyspcg] factor n=%lld l=%lld nu=%.3e jacobi_sweeps=%d\n", (long long)n,
+                 (long long)l, nu, sweeps);
   P->nu = nu;
   return NYS_OK;
 }

@@ -86,38 +86,4 @@ __device__ __forceinline__ T block_sum(T v, T* sh) {
   return r;
 }
 
-// Grid-wide barrier for cooperative (co-resident) launches.  `ctr` is a
-// monotonically increasing arrival counter zeroed before the launch; `epoch`
-// counts barriers passed by this workgroup.  Spinning is bounded: after
-// `spin_limit` polls the barrier records a timeout in `err` and every later
-// barrier returns at once, so all workgroups still reach the kernel's end.
-struct GridBarrier {
-  unsigned* ctr;
-  int* err;
-  unsigned nblocks;
-  unsigned epoch;
-  __device__ void sync() {
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      epoch += 1;
-      const unsigned target = epoch * nblocks;
-      __threadfence();
-      atomicAdd(ctr, 1u);
-      unsigned spins = 0;
-      while (true) {
-        unsigned v = __hip_atomic_load(ctr, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-        if (v >= target) break;
-        if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) break;
-        if (++spins > (1u << 26)) {
-          atomicExch(err, 1);
-          break;
-        }
-        __builtin_amdgcn_s_sleep(1);
-      }
-      __threadfence();
-    }
-    __syncthreads();
-  }
-};
-
 }  // namespace nys

@@ -8,6 +8,8 @@
 //     parallel ordering (every round rotates m/2 disjoint pairs), cooperative
 //     launch with one grid barrier per round
 //   * descending sort of the eigenvalues and the scaled eigenvector matrix
+#include <cstdlib>
+
 #include "dense_small.hpp"
 
 namespace nys {
@@ -15,6 +17,22 @@ namespace nys {
 namespace {
 
 constexpr int NB = 32;  // block size of the blocked Cholesky / inverse
+
+// Reciprocal and reciprocal square root from the hardware estimates
+// (v_rcp_f64 / v_rsq_f64) refined by one Newton step, which restores full
+// float64 accuracy; they replace IEEE division / square root on the short
+// dependent chains of the rotation and pivot computations.
+__device__ __forceinline__ double frcp(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(r, fma(-x, r, 1.0), r);
+  return fma(r, fma(-x, r, 1.0), r);
+}
+__device__ __forceinline__ double frsq(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  y = y * fma(-0.5 * x, y * y, 1.5);
+  return y * fma(-0.5 * x, y * y, 1.5);
+}
+
 
 // ---------------------------------------------------------------- shift
 
@@ -70,8 +88,6 @@ struct CholArgs {
   int64_t n;
   double* Dinv;     // nblk x NB x NB inverses of the diagonal blocks
   int* info;        // 0 = ok, k+1 = non-positive pivot at column k
-  unsigned* bar;
-  int* bar_err;
 };
 
 // Unblocked Cholesky + inverse of one NB x NB diagonal block in LDS.
@@ -92,6 +108,7 @@ __device__ void factor_diag_block(CholArgs a, int kb, double (*T)[NB + 1], doubl
   __shared__ int bad;
   if (t == 0) bad = 0;
   __syncthreads();
+  __shared__ double rinv;
   for (int k = 0; k < NB; ++k) {
     if (t == 0) {
       const double d = T[k][k];
@@ -99,13 +116,16 @@ __device__ void factor_diag_block(CholArgs a, int kb, double (*T)[NB + 1], doubl
         bad = 1;
         if (k < nbk && atomicCAS(a.info, 0, (int)(base + k + 1)) == 0) {}
         T[k][k] = 1.0;
+        rinv = 1.0;
       } else {
-        T[k][k] = sqrt(d);
+        const double y = frsq(d);  // 1 / sqrt(d)
+        T[k][k] = d * y;
+        rinv = y;
       }
     }
     __syncthreads();
-    const double dk = T[k][k];
-    for (int i = k + 1 + t; i < NB; i += blockDim.x) T[i][k] /= dk;
+    const double ri = rinv;
+    for (int i = k + 1 + t; i < NB; i += blockDim.x) T[i][k] *= ri;
     __syncthreads();
     for (int e = t; e < NB * NB; e += blockDim.x) {
       const int i = e / NB, j = e % NB;
@@ -113,16 +133,17 @@ __device__ void factor_diag_block(CholArgs a, int kb, double (*T)[NB + 1], doubl
     }
     __syncthreads();
   }
-  // inverse by forward substitution, one column per thread
-  if (t < NB) {
-    const int j = t;
-    for (int i = 0; i < NB; ++i) {
-      double s = (i == j) ? 1.0 : 0.0;
-      for (int k = j; k < i; ++k) s -= T[i][k] * Ti[k][j];
-      Ti[i][j] = (i >= j) ? s / T[i][i] : 0.0;
+  // inverse of the lower factor, row by row: Ti[i][j] = (delta_ij - sum_{k<i}
+  // T[i][k] Ti[k][j]) / T[i][i], the NB columns j in parallel
+  for (int i = 0; i < NB; ++i) {
+    if (t < NB) {
+      const int j = t;
+      double sacc = (i == j) ? 1.0 : 0.0;
+      for (int k = j; k < i; ++k) sacc -= T[i][k] * Ti[k][j];
+      Ti[i][j] = (j <= i) ? sacc * frcp(T[i][i]) : 0.0;
     }
+    __syncthreads();
   }
-  __syncthreads();
   for (int e = t; e < NB * NB; e += blockDim.x) {
     const int i = e / NB, j = e % NB;
     if (i < nbk && j < nbk) a.L[(base + i) * n + base + j] = (j <= i) ? T[i][j] : 0.0;
@@ -131,73 +152,75 @@ __device__ void factor_diag_block(CholArgs a, int kb, double (*T)[NB + 1], doubl
   (void)bad;
 }
 
-__global__ __launch_bounds__(256) void chol_coop(CholArgs a) {
+// Blocked right-looking Cholesky, one launch per step (the stream orders
+// them): diagonal block (one workgroup), panel below it, trailing update.
+__global__ __launch_bounds__(256) void chol_diag(CholArgs a, int kb) {
+  if (*((volatile int*)a.info) != 0) return;
+  __shared__ double T[NB][NB + 1];
+  __shared__ double Ti[NB][NB + 1];
+  factor_diag_block(a, kb, T, Ti);
+}
+
+// L[ib,kb] = A[ib,kb] * Dinv_kb^T for ib = kb + 1 + blockIdx.x
+__global__ __launch_bounds__(256) void chol_panel(CholArgs a, int kb) {
+  if (*((volatile int*)a.info) != 0) return;
   __shared__ double T[NB][NB + 1];
   __shared__ double Ti[NB][NB + 1];
   __shared__ double Lb[NB][NB + 1];
-  GridBarrier gb{a.bar, a.bar_err, gridDim.x, 0};
   const int64_t n = a.n;
-  const int nblk = (int)cdiv(n, NB);
   const int t = threadIdx.x;
-  for (int kb = 0; kb < nblk; ++kb) {
-    if (blockIdx.x == 0) factor_diag_block(a, kb, T, Ti);
-    gb.sync();
-    if (*((volatile int*)a.info) != 0) break;
-    // panel: L[ib,kb] = A[ib,kb] * Dinv_kb^T for ib > kb
-    const double* Di = a.Dinv + (int64_t)kb * NB * NB;
-    for (int ib = kb + 1 + blockIdx.x; ib < nblk; ib += gridDim.x) {
-      const int64_t r0 = (int64_t)ib * NB, c0 = (int64_t)kb * NB;
-      for (int e = t; e < NB * NB; e += blockDim.x) {
-        const int i = e / NB, j = e % NB;
-        Lb[i][j] = (r0 + i < n && c0 + j < n) ? a.L[(r0 + i) * n + c0 + j] : 0.0;
-        Ti[i][j] = Di[e];
-      }
-      __syncthreads();
-      for (int e = t; e < NB * NB; e += blockDim.x) {
-        const int i = e / NB, j = e % NB;
-        double s = 0.0;
-        for (int k = 0; k <= j; ++k) s += Lb[i][k] * Ti[j][k];
-        T[i][j] = s;
-      }
-      __syncthreads();
-      for (int e = t; e < NB * NB; e += blockDim.x) {
-        const int i = e / NB, j = e % NB;
-        if (r0 + i < n && c0 + j < n) a.L[(r0 + i) * n + c0 + j] = T[i][j];
-      }
-      __syncthreads();
-    }
-    gb.sync();
-    // trailing update: A[ib,jb] -= L[ib,kb] L[jb,kb]^T for kb < jb <= ib
-    const int rem = nblk - kb - 1;
-    const int ntile = rem * (rem + 1) / 2;
-    for (int tt = blockIdx.x; tt < ntile; tt += gridDim.x) {
-      // tile index -> (ib, jb) with jb <= ib
-      int ii = (int)((sqrt(8.0 * tt + 1.0) - 1.0) * 0.5);
-      while ((ii + 1) * (ii + 2) / 2 <= tt) ++ii;
-      while (ii * (ii + 1) / 2 > tt) --ii;
-      const int jj = tt - ii * (ii + 1) / 2;
-      const int ib = kb + 1 + ii, jb = kb + 1 + jj;
-      const int64_t c0 = (int64_t)kb * NB;
-      for (int e = t; e < NB * NB; e += blockDim.x) {
-        const int i = e / NB, k = e % NB;
-        const int64_t ri = (int64_t)ib * NB + i, rj = (int64_t)jb * NB + i;
-        Lb[i][k] = (ri < n) ? a.L[ri * n + c0 + k] : 0.0;
-        T[i][k] = (rj < n) ? a.L[rj * n + c0 + k] : 0.0;
-      }
-      __syncthreads();
-      for (int e = t; e < NB * NB; e += blockDim.x) {
-        const int i = e / NB, j = e % NB;
-        const int64_t gi = (int64_t)ib * NB + i, gj = (int64_t)jb * NB + j;
-        if (gi < n && gj < n && gj <= gi) {
-          double s = 0.0;
+  const int ib = kb + 1 + blockIdx.x;
+  const double* Di = a.Dinv + (int64_t)kb * NB * NB;
+  const int64_t r0 = (int64_t)ib * NB, c0 = (int64_t)kb * NB;
+  for (int e = t; e < NB * NB; e += blockDim.x) {
+    const int i = e / NB, j = e % NB;
+    Lb[i][j] = (r0 + i < n && c0 + j < n) ? a.L[(r0 + i) * n + c0 + j] : 0.0;
+    Ti[i][j] = Di[e];
+  }
+  __syncthreads();
+  for (int e = t; e < NB * NB; e += blockDim.x) {
+    const int i = e / NB, j = e % NB;
+    double sacc = 0.0;
+    for (int k = 0; k <= j; ++k) sacc += Lb[i][k] * Ti[j][k];
+    T[i][j] = sacc;
+  }
+  __syncthreads();
+  for (int e = t; e < NB * NB; e += blockDim.x) {
+    const int i = e / NB, j = e % NB;
+    if (r0 + i < n && c0 + j < n) a.L[(r0 + i) * n + c0 + j] = T[i][j];
+  }
+}
+
+// A[ib,jb] -= L[ib,kb] L[jb,kb]^T for kb < jb <= ib, one tile per workgroup
+__global__ __launch_bounds__(256) void chol_trail(CholArgs a, int kb) {
+  if (*((volatile int*)a.info) != 0) return;
+  __shared__ double T[NB][NB + 1];
+  __shared__ double Lb[NB][NB + 1];
+  const int64_t n = a.n;
+  const int t = threadIdx.x;
+  const int tt = blockIdx.x;
+  int ii = (int)((sqrt(8.0 * tt + 1.0) - 1.0) * 0.5);
+  while ((ii + 1) * (ii + 2) / 2 <= tt) ++ii;
+  while (ii * (ii + 1) / 2 > tt) --ii;
+  const int jj = tt - ii * (ii + 1) / 2;
+  const int ib = kb + 1 + ii, jb = kb + 1 + jj;
+  const int64_t c0 = (int64_t)kb * NB;
+  for (int e = t; e < NB * NB; e += blockDim.x) {
+    const int i = e / NB, k = e % NB;
+    const int64_t ri = (int64_t)ib * NB + i, rj = (int64_t)jb * NB + i;
+    Lb[i][k] = (ri < n) ? a.L[ri * n + c0 + k] : 0.0;
+    T[i][k] = (rj < n) ? a.L[rj * n + c0 + k] : 0.0;
+  }
+  __syncthreads();
+  for (int e = t; e < NB * NB; e += blockDim.x) {
+    const int i = e / NB, j = e % NB;
+    const int64_t gi = (int64_t)ib * NB + i, gj = (int64_t)jb * NB + j;
+    if (gi < n && gj < n && gj <= gi) {
+      double sacc = 0.0;
 #pragma unroll 8
-          for (int k = 0; k < NB; ++k) s += Lb[i][k] * T[j][k];
-          a.L[gi * n + gj] -= s;
-        }
-      }
-      __syncthreads();
+      for (int k = 0; k < NB; ++k) sacc += Lb[i][k] * T[j][k];
+      a.L[gi * n + gj] -= sacc;
     }
-    gb.sync();
   }
 }
 
@@ -260,8 +283,9 @@ __global__ __launch_bounds__(256) void trinv_blocks(const double* __restrict__ L
 
 // ---------------------------------------------------------------- Jacobi
 
-constexpr int JB = 32;       // Jacobi block size
+constexpr int JB = 16;       // Jacobi block size
 constexpr int JS = 2 * JB;   // order of one block-pair subproblem
+constexpr int JH = JS / 2;   // rotation pairs per inner round
 
 __device__ __forceinline__ int64_t rr_index(int64_t pos, int64_t r, int64_t m) {
   return pos == 0 ? 0 : 1 + ((pos - 1 + r) % (m - 1));
@@ -269,43 +293,52 @@ __device__ __forceinline__ int64_t rr_index(int64_t pos, int64_t r, int64_t m) {
 
 // Rotation (c, s) with J_pp = c, J_pq = s, J_qp = -s, J_qq = c that zeroes
 // entry (p, q) of J^T A J (symmetric 2x2 Schur decomposition).  Returns false
-// (identity) when |a_pq| is negligible relative to sqrt(|a_pp a_qq|).
+// (identity) when |a_pq| is below max(eps sqrt(|a_pp a_qq|), floor_abs).
 __device__ __forceinline__ bool jacobi_rot(double app, double aqq, double apq, double floor_abs,
                                            double& c, double& s) {
-  const double thr = fmax(2.220446049250313e-16 * sqrt(fabs(app) * fabs(aqq)), floor_abs);
-  if (!(fabs(apq) > thr) || fabs(apq) < 1e-300) {
+  const double a2 = apq * apq;
+  const double thr2 = fmax(4.930380657631324e-32 * fabs(app * aqq), floor_abs * floor_abs);
+  if (!(a2 > thr2) || fabs(apq) < 1e-300) {
     c = 1.0;
     s = 0.0;
     return false;
   }
-  const double tau = (aqq - app) / (2.0 * apq);
-  const double tt = (tau >= 0.0) ? 1.0 / (tau + sqrt(1.0 + tau * tau))
-                                 : -1.0 / (-tau + sqrt(1.0 + tau * tau));
-  c = 1.0 / sqrt(1.0 + tt * tt);
-  s = tt * c;
+  const double tau = (aqq - app) * 0.5 * frcp(apq);
+  double t;
+  if (fabs(tau) > 1e100) {
+    t = 0.5 * frcp(tau);
+  } else {
+    const double h = fma(tau, tau, 1.0);
+    const double root = h * frsq(h);  // sqrt(1 + tau^2)
+    t = frcp(fabs(tau) + root);
+    if (tau < 0.0) t = -t;
+  }
+  c = frsq(fma(t, t, 1.0));
+  s = t * c;
   return true;
 }
 
 // Block two-sided Jacobi.  The m x m matrix (m = nblk * JB, nblk even) is cut
 // into JB x JB blocks; a round pairs the blocks by the round-robin schedule.
-// Phase 1: one workgroup per block pair (P, Q) loads the JS x JS subproblem
-// [A_PP A_PQ; A_QP A_QQ] into LDS, runs cyclic Jacobi sweeps on it and keeps
-// the accumulated rotation J_k.  Phase 2: every workgroup applies the
-// rotations, A <- J^T A J (tiles pair k x pair k': J_k^T A_kk' J_k') and
-// V <- V J.  Two grid barriers per round; nblk - 1 rounds per sweep.
+// Phase 1 (one workgroup per block pair (P, Q)): load the JS x JS subproblem
+// [A_PP A_PQ; A_QP A_QQ] into LDS, run a cyclic Jacobi sweep on it, keep the
+// accumulated rotation J_k and write the rotated subproblem back.  Phase 2
+// (one workgroup per tile): A <- J^T A J on the off-diagonal pair tiles
+// (J_k^T A_kk' J_k') and V <- V J.  Phases are separate launches on the
+// stream (the kernel boundary orders them); nblk - 1 rounds make a sweep.
+// Every kernel returns at once when the converged flag is set, so the host
+// may enqueue whole sweeps and poll the flag only now and then.
 struct JacArgs {
   double* A;       // m x m
   double* V;       // m x m eigenvectors (columns)
   double* J;       // (nblk/2) x JS x JS rotations of the current round
   int64_t m;
   int nblk;
-  int max_sweeps;
   int inner_sweeps;
   int* flags;      // [max_sweeps] "a rotation happened" per sweep (zeroed)
+  int* conv;       // converged flag (zeroed)
   int* sweeps_out;
-  double* evals;   // m: diagonal of the final matrix
-  unsigned* bar;
-  int* bar_err;
+  double* floor;   // rotation floor (device scalar)
 };
 
 __device__ __forceinline__ int64_t pair_index(int nblk, int k, int64_t r, int t) {
@@ -315,205 +348,188 @@ __device__ __forceinline__ int64_t pair_index(int nblk, int k, int64_t r, int t)
 
 typedef double jd4 __attribute__((ext_vector_type(4)));
 
-// out(64x64) = opA(X) * Y on MFMA f64 (4 waves, each a 32x32 quadrant).
-// TRANS_X: use X^T (X[p][i]) instead of X (X[i][p]).  Results are returned in
-// the wave's accumulators; element q of lane l of tile (ti, tj) is
-// out[wm*32 + ti*16 + 4q + l/16][wn*32 + tj*16 + l%16].
+// out(JS x JS) = opX(X) * Y on MFMA f64: 4 waves, wave w computes the 16 x 16
+// quadrant (w/2, w%2).  TRANS_X: use X^T (X[p][i]) instead of X (X[i][p]).
+// Accumulator element q of lane l is out[wm*16 + 4q + l/16][wn*16 + l%16].
+static_assert(JS == 32, "quadrant layout assumes 32 x 32 subproblems");
 template <bool TRANS_X>
-__device__ __forceinline__ void mm64(const double (*X)[JS + 1], const double (*Y)[JS + 1], jd4 acc[2][2]) {
+__device__ __forceinline__ jd4 mmjs(const double (*X)[JS + 1], const double (*Y)[JS + 1]) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wm = wave >> 1, wn = wave & 1;
+  jd4 acc = jd4{0, 0, 0, 0};
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j) acc[i][j] = jd4{0, 0, 0, 0};
-#pragma unroll 4
   for (int k0 = 0; k0 < JS; k0 += 4) {
     const int kk = k0 + (lane >> 4);
-    const int r0 = wm * 32 + (lane & 15), r1 = r0 + 16;
-    const int c0 = wn * 32 + (lane & 15), c1 = c0 + 16;
-    const double a0 = TRANS_X ? X[kk][r0] : X[r0][kk];
-    const double a1 = TRANS_X ? X[kk][r1] : X[r1][kk];
-    const double b0 = Y[kk][c0], b1 = Y[kk][c1];
-    acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
-    acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
-    acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
-    acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+    const int r = wm * 16 + (lane & 15), c = wn * 16 + (lane & 15);
+    const double av = TRANS_X ? X[kk][r] : X[r][kk];
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, Y[kk][c], acc, 0, 0, 0);
   }
+  return acc;
 }
 
 template <typename F>
-__device__ __forceinline__ void mm64_store(const jd4 acc[2][2], F f) {
+__device__ __forceinline__ void mmjs_store(const jd4 acc, F f) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wm = wave >> 1, wn = wave & 1;
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j)
-#pragma unroll
-      for (int q = 0; q < 4; ++q)
-        f(wm * 32 + i * 16 + 4 * q + (lane >> 4), wn * 32 + j * 16 + (lane & 15), acc[i][j][q]);
+  for (int q = 0; q < 4; ++q) f(wm * 16 + 4 * q + (lane >> 4), wn * 16 + (lane & 15), acc[q]);
 }
 
-__global__ __launch_bounds__(256) void jacobi_block_coop(JacArgs a) {
+// floor = 1e-14 * max diagonal entry: the tile updates leave off-diagonal
+// rounding noise of a few eps ||A||; rotations below the floor move the
+// eigenvalues by less than it, so converged sweeps stop.
+__global__ void jac_floor(const double* __restrict__ A, int64_t m, double* __restrict__ floor) {
+  __shared__ double red[256];
+  double dm = 0.0;
+  for (int64_t i = threadIdx.x; i < m; i += 256) dm = fmax(dm, A[i * m + i]);
+  red[threadIdx.x] = dm;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if (threadIdx.x < st) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + st]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) floor[0] = 1e-14 * red[0];
+}
+
+__global__ __launch_bounds__(256) void jac_phase1(JacArgs a, int64_t r, int sweep) {
+  if (*a.conv) return;
   __shared__ double S[JS][JS + 1];
   __shared__ double Jm[JS][JS + 1];
-  __shared__ double cs[JS / 2], sn[JS / 2];
-  __shared__ int pp[JS / 2], qq[JS / 2];
-  __shared__ int64_t gi[JS], gj[JS];
+  __shared__ double cs[JH], sn[JH];
+  __shared__ int pp[JH], qq[JH];
+  __shared__ int64_t gi[JS];
   __shared__ int rotated, any_s;
-  GridBarrier gb{a.bar, a.bar_err, gridDim.x, 0};
+  const int t = threadIdx.x;
+  const int64_t m = a.m;
+  const int k = blockIdx.x;
+  const double floor_abs = *a.floor;
+  if (t < JS) gi[t] = pair_index(a.nblk, k, r, t);
+  if (t == 0) rotated = 0;
+  __syncthreads();
+  for (int e = t; e < JS * JS; e += 256) {
+    const int i = e / JS, j = e % JS;
+    S[i][j] = a.A[gi[i] * m + gi[j]];
+    Jm[i][j] = (i == j) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  for (int isw = 0; isw < a.inner_sweeps; ++isw) {
+    if (t == 0) any_s = 0;
+    __syncthreads();
+    for (int ir = 0; ir < JS - 1; ++ir) {
+      if (t < JH) {
+        const int p = (int)rr_index(t, ir, JS), q = (int)rr_index(JS - 1 - t, ir, JS);
+        double c, sv;
+        if (jacobi_rot(S[p][p], S[q][q], S[p][q], floor_abs, c, sv)) any_s = 1;
+        cs[t] = c;
+        sn[t] = sv;
+        pp[t] = p;
+        qq[t] = q;
+      }
+      __syncthreads();
+      // S <- R^T S R on 2x2 blocks (rows pair k1, cols pair k2)
+      for (int e = t; e < JH * JH; e += 256) {
+        const int k1 = e / JH, k2 = e % JH;
+        const double s1 = sn[k1], s2 = sn[k2];
+        if (s1 == 0.0 && s2 == 0.0) continue;
+        const int p1 = pp[k1], q1 = qq[k1], p2 = pp[k2], q2 = qq[k2];
+        const double c1 = cs[k1], c2 = cs[k2];
+        const double app = S[p1][p2], apq = S[p1][q2], aqp = S[q1][p2], aqq = S[q1][q2];
+        const double bpp = c1 * app - s1 * aqp, bpq = c1 * apq - s1 * aqq;
+        const double bqp = s1 * app + c1 * aqp, bqq = s1 * apq + c1 * aqq;
+        double npp = c2 * bpp - s2 * bpq, npq = s2 * bpp + c2 * bpq;
+        double nqp = c2 * bqp - s2 * bqq, nqq = s2 * bqp + c2 * bqq;
+        if (k1 == k2) {
+          npq = 0.0;
+          nqp = 0.0;
+        }
+        S[p1][p2] = npp;
+        S[p1][q2] = npq;
+        S[q1][p2] = nqp;
+        S[q1][q2] = nqq;
+      }
+      // Jm <- Jm R (row i, pair kk)
+      for (int e = t; e < JS * JH; e += 256) {
+        const int i = e / JH, kk = e % JH;
+        const double sv = sn[kk];
+        if (sv == 0.0) continue;
+        const double c = cs[kk];
+        const int p = pp[kk], q = qq[kk];
+        const double vp = Jm[i][p], vq = Jm[i][q];
+        Jm[i][p] = c * vp - sv * vq;
+        Jm[i][q] = sv * vp + c * vq;
+      }
+      __syncthreads();
+    }
+    if (any_s) rotated = 1;
+    __syncthreads();
+    if (!any_s) break;
+    __syncthreads();
+  }
+  for (int e = t; e < JS * JS; e += 256) {
+    a.J[(int64_t)k * JS * JS + e] = Jm[e / JS][e % JS];
+    a.A[gi[e / JS] * m + gi[e % JS]] = S[e / JS][e % JS];
+  }
+  if (t == 0 && rotated) a.flags[sweep] = 1;
+}
+
+__global__ __launch_bounds__(256) void jac_phase2(JacArgs a, int64_t r) {
+  if (*a.conv) return;
+  __shared__ double S[JS][JS + 1];
+  __shared__ double Jm[JS][JS + 1];
+  __shared__ int64_t gi[JS], gj[JS];
   const int t = threadIdx.x;
   const int64_t m = a.m;
   const int nblk = a.nblk, npair = nblk / 2;
-  // absolute floor of the rotation test: eps times the largest diagonal entry
-  // of the input (rotations below it change eigenvalues by less than that)
-  __shared__ double dmax_s;
-  {
-    double dm = 0.0;
-    for (int64_t i = t; i < m; i += 256) dm = fmax(dm, a.A[i * m + i]);
-    __shared__ double red[256];
-    red[t] = dm;
+  const int64_t ntile_a = (int64_t)npair * npair;
+  const int64_t task = blockIdx.x;
+  jd4 acc;
+  if (task < ntile_a) {
+    const int k1 = (int)(task / npair), k2 = (int)(task % npair);
+    if (k1 == k2) return;  // written by phase 1
+    if (t < JS) {
+      gi[t] = pair_index(nblk, k1, r, t);
+      gj[t] = pair_index(nblk, k2, r, t);
+    }
     __syncthreads();
-    for (int st = 128; st > 0; st >>= 1) {
-      if (t < st) red[t] = fmax(red[t], red[t + st]);
-      __syncthreads();
+    for (int e = t; e < JS * JS; e += 256) {
+      const int i = e / JS, j = e % JS;
+      S[i][j] = a.A[gi[i] * m + gj[j]];
+      Jm[i][j] = a.J[(int64_t)k1 * JS * JS + e];
     }
-    if (t == 0) dmax_s = red[0];
     __syncthreads();
-  }
-  const double floor_abs = 2.220446049250313e-16 * dmax_s;
-  gb.sync();  // every workgroup has read the input diagonal before any rotation
-  int sweep = 0;
-  for (sweep = 0; sweep < a.max_sweeps; ++sweep) {
-    for (int64_t r = 0; r < nblk - 1; ++r) {
-      // ---- phase 1: block-pair subproblems in LDS
-      for (int k = blockIdx.x; k < npair; k += gridDim.x) {
-        if (t < JS) gi[t] = pair_index(nblk, k, r, t);
-        if (t == 0) rotated = 0;
-        __syncthreads();
-        for (int e = t; e < JS * JS; e += 256) {
-          const int i = e / JS, j = e % JS;
-          S[i][j] = a.A[gi[i] * m + gi[j]];
-          Jm[i][j] = (i == j) ? 1.0 : 0.0;
-        }
-        __syncthreads();
-        for (int isw = 0; isw < a.inner_sweeps; ++isw) {
-          if (t == 0) any_s = 0;
-          __syncthreads();
-          for (int ir = 0; ir < JS - 1; ++ir) {
-            if (t < JS / 2) {
-              const int p = (int)rr_index(t, ir, JS), q = (int)rr_index(JS - 1 - t, ir, JS);
-              double c, sv;
-              if (jacobi_rot(S[p][p], S[q][q], S[p][q], floor_abs, c, sv)) any_s = 1;
-              cs[t] = c;
-              sn[t] = sv;
-              pp[t] = p;
-              qq[t] = q;
-            }
-            __syncthreads();
-            // S <- R^T S R on 2x2 blocks (rows pair k1, cols pair k2)
-            for (int e = t; e < (JS / 2) * (JS / 2); e += 256) {
-              const int k1 = e >> 5, k2 = e & 31;
-              const double s1 = sn[k1], s2 = sn[k2];
-              if (s1 == 0.0 && s2 == 0.0) continue;
-              const int p1 = pp[k1], q1 = qq[k1], p2 = pp[k2], q2 = qq[k2];
-              const double c1 = cs[k1], c2 = cs[k2];
-              const double app = S[p1][p2], apq = S[p1][q2], aqp = S[q1][p2], aqq = S[q1][q2];
-              const double bpp = c1 * app - s1 * aqp, bpq = c1 * apq - s1 * aqq;
-              const double bqp = s1 * app + c1 * aqp, bqq = s1 * apq + c1 * aqq;
-              double npp = c2 * bpp - s2 * bpq, npq = s2 * bpp + c2 * bpq;
-              double nqp = c2 * bqp - s2 * bqq, nqq = s2 * bqp + c2 * bqq;
-              if (k1 == k2) {
-                npq = 0.0;
-                nqp = 0.0;
-              }
-              S[p1][p2] = npp;
-              S[p1][q2] = npq;
-              S[q1][p2] = nqp;
-              S[q1][q2] = nqq;
-            }
-            // Jm <- Jm R (row i, pair kk)
-            for (int e = t; e < JS * (JS / 2); e += 256) {
-              const int i = e >> 5, kk = e & 31;
-              const double sv = sn[kk];
-              if (sv == 0.0) continue;
-              const double c = cs[kk];
-              const int p = pp[kk], q = qq[kk];
-              const double vp = Jm[i][p], vq = Jm[i][q];
-              Jm[i][p] = c * vp - sv * vq;
-              Jm[i][q] = sv * vp + c * vq;
-            }
-            __syncthreads();
-          }
-          if (any_s) rotated = 1;
-          __syncthreads();
-          if (!any_s) break;
-          __syncthreads();
-        }
-        for (int e = t; e < JS * JS; e += 256) {
-          a.J[(int64_t)k * JS * JS + e] = Jm[e / JS][e % JS];
-          a.A[gi[e / JS] * m + gi[e % JS]] = S[e / JS][e % JS];
-        }
-        if (t == 0 && rotated) a.flags[sweep] = 1;
-        __syncthreads();
-      }
-      gb.sync();
-      // ---- phase 2: A <- J^T A J on off-diagonal pair tiles, V <- V J (MFMA)
-      const int ntile_a = npair * npair;
-      const int64_t nrb = m / JS;
-      const int64_t ntile_v = nrb * npair;
-      for (int64_t task = blockIdx.x; task < ntile_a + ntile_v; task += gridDim.x) {
-        jd4 acc[2][2];
-        if (task < ntile_a) {
-          const int k1 = (int)(task / npair), k2 = (int)(task % npair);
-          if (k1 == k2) continue;  // written by phase 1
-          if (t < JS) {
-            gi[t] = pair_index(nblk, k1, r, t);
-            gj[t] = pair_index(nblk, k2, r, t);
-          }
-          __syncthreads();
-          for (int e = t; e < JS * JS; e += 256) {
-            const int i = e / JS, j = e % JS;
-            S[i][j] = a.A[gi[i] * m + gj[j]];
-            Jm[i][j] = a.J[(int64_t)k1 * JS * JS + e];
-          }
-          __syncthreads();
-          mm64<true>(Jm, S, acc);  // T = J_k1^T S
-          __syncthreads();
-          mm64_store(acc, [&](int i, int j, double v) { S[i][j] = v; });
-          for (int e = t; e < JS * JS; e += 256) Jm[e / JS][e % JS] = a.J[(int64_t)k2 * JS * JS + e];
-          __syncthreads();
-          mm64<false>(S, Jm, acc);  // T J_k2
-          mm64_store(acc, [&](int i, int j, double v) { a.A[gi[i] * m + gj[j]] = v; });
-          __syncthreads();
-        } else {
-          const int64_t vt = task - ntile_a;
-          const int64_t rb = vt / npair;
-          const int k = (int)(vt % npair);
-          if (t < JS) gj[t] = pair_index(nblk, k, r, t);
-          __syncthreads();
-          for (int e = t; e < JS * JS; e += 256) {
-            const int i = e / JS, j = e % JS;
-            S[i][j] = a.V[(rb * JS + i) * m + gj[j]];
-            Jm[i][j] = a.J[(int64_t)k * JS * JS + e];
-          }
-          __syncthreads();
-          mm64<false>(S, Jm, acc);
-          mm64_store(acc, [&](int i, int j, double v) { a.V[(rb * JS + i) * m + gj[j]] = v; });
-          __syncthreads();
-        }
-      }
-      gb.sync();
+    acc = mmjs<true>(Jm, S);  // T = J_k1^T S
+    __syncthreads();
+    mmjs_store(acc, [&](int i, int j, double v) { S[i][j] = v; });
+    for (int e = t; e < JS * JS; e += 256) Jm[e / JS][e % JS] = a.J[(int64_t)k2 * JS * JS + e];
+    __syncthreads();
+    acc = mmjs<false>(S, Jm);  // T J_k2
+    mmjs_store(acc, [&](int i, int j, double v) { a.A[gi[i] * m + gj[j]] = v; });
+  } else {
+    const int64_t vt = task - ntile_a;
+    const int64_t rb = vt / npair;
+    const int k = (int)(vt % npair);
+    if (t < JS) gj[t] = pair_index(nblk, k, r, t);
+    __syncthreads();
+    for (int e = t; e < JS * JS; e += 256) {
+      const int i = e / JS, j = e % JS;
+      S[i][j] = a.V[(rb * JS + i) * m + gj[j]];
+      Jm[i][j] = a.J[(int64_t)k * JS * JS + e];
     }
-    if (*((volatile int*)&a.flags[sweep]) == 0) {
-      ++sweep;
-      break;
-    }
+    __syncthreads();
+    acc = mmjs<false>(S, Jm);
+    mmjs_store(acc, [&](int i, int j, double v) { a.V[(rb * JS + i) * m + gj[j]] = v; });
   }
-  const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + t;
-  if (gtid == 0) a.sweeps_out[0] = sweep;
-  for (int64_t i = gtid; i < m; i += (int64_t)gridDim.x * blockDim.x) a.evals[i] = a.A[i * m + i];
+}
+
+__global__ void jac_end_sweep(JacArgs a, int sweep) {
+  if (*a.conv) return;
+  a.sweeps_out[0] = sweep + 1;
+  if (a.flags[sweep] == 0) a.conv[0] = 1;
+}
+
+__global__ void jac_evals(const double* __restrict__ A, int64_t m, double* __restrict__ ev) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < m) ev[i] = A[i * m + i];
 }
 
 // A = (G + G^T)/2 padded to m x m (padding: isolated eigenvalue -1), V = I.
@@ -550,14 +566,6 @@ __global__ void eig_finalize(const double* __restrict__ ev, const double* __rest
   if (sig2) sig2[rank] = si;
 }
 
-int coop_blocks(const void* fn, int threads, size_t shmem, int want) {
-  int per_cu = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, shmem) != hipSuccess ||
-      per_cu < 1)
-    per_cu = 1;
-  int cap = per_cu * num_cus();
-  return want < cap ? want : cap;
-}
 
 }  // namespace
 
@@ -587,19 +595,21 @@ nys_status scale_device_scalar(double* x, double factor, hipStream_t s) {
 
 size_t chol_ws_doubles(int64_t n) { return (size_t)(cdiv(n, NB) * NB * NB); }
 
-nys_status cholesky(const double* M, int64_t n, double* L, double* Dinv, int* info, unsigned* bar,
-                    int* bar_err, hipStream_t s) {
+nys_status cholesky(const double* M, int64_t n, double* L, double* Dinv, int* info, hipStream_t s) {
   hipLaunchKernelGGL(symmetrize_lower, dim3((unsigned)cdiv(n * n, 256)), dim3(256), 0, s, M, n, L);
   NYS_CHECK_LAUNCH();
   NYS_HIP(hipMemsetAsync(info, 0, sizeof(int), s));
-  NYS_HIP(hipMemsetAsync(bar, 0, sizeof(unsigned), s));
-  NYS_HIP(hipMemsetAsync(bar_err, 0, sizeof(int), s));
-  CholArgs a{L, n, Dinv, info, bar, bar_err};
+  CholArgs a{L, n, Dinv, info};
   const int nblk = (int)cdiv(n, NB);
-  const int want = nblk * (nblk + 1) / 2 > 1 ? nblk * (nblk + 1) / 2 : 1;
-  const int g = coop_blocks((const void*)chol_coop, 256, 0, want < 512 ? want : 512);
-  void* args[] = {&a};
-  NYS_HIP(hipLaunchCooperativeKernel((const void*)chol_coop, dim3(g), dim3(256), args, 0, s));
+  for (int kb = 0; kb < nblk; ++kb) {
+    hipLaunchKernelGGL(chol_diag, dim3(1), dim3(256), 0, s, a, kb);
+    const int rem = nblk - kb - 1;
+    if (rem > 0) {
+      hipLaunchKernelGGL(chol_panel, dim3((unsigned)rem), dim3(256), 0, s, a, kb);
+      hipLaunchKernelGGL(chol_trail, dim3((unsigned)(rem * (rem + 1) / 2)), dim3(256), 0, s, a, kb);
+    }
+  }
+  NYS_CHECK_LAUNCH();
   return NYS_OK;
 }
 
@@ -611,7 +621,11 @@ nys_status tri_inverse(const double* L, int64_t n, const double* Dinv, double* X
 
 // one inner sweep per round for large problems (the outer sweeps refine the
 // pairs again); small problems are a single block pair, solved to convergence
-int inner_sweeps_for(int64_t l) { return l <= JS ? 30 : 1; }
+int inner_sweeps_for(int64_t l) {
+  if (l <= JS) return 40;
+  const char* e = std::getenv("NYS_JACOBI_INNER");
+  return e ? std::atoi(e) : 1;
+}
 
 int jac_nblk(int64_t l) {
   int nb = (int)cdiv(l, JB);
@@ -623,28 +637,44 @@ int jac_nblk(int64_t l) {
 size_t eig_ws_doubles(int64_t l) {
   const int64_t nb = jac_nblk(l);
   const int64_t m = nb * JB;
-  return (size_t)(2 * m * m + m + (nb / 2) * JS * JS);
+  return (size_t)(2 * m * m + m + (nb / 2) * JS * JS + 8);
 }
 
 nys_status sym_eig(const double* G, int64_t l, double* work, int* flags, int max_sweeps,
-                   int* sweeps_out, unsigned* bar, int* bar_err, double* T, double* lam,
-                   double* sig2, const double* nu, hipStream_t s) {
+                   int* sweeps_out, int* conv, double* T, double* lam, double* sig2, const double* nu,
+                   hipStream_t s) {
   const int nb = jac_nblk(l);
   const int64_t m = (int64_t)nb * JB;
   double* A = work;
   double* V = work + m * m;
   double* ev = work + 2 * m * m;
   double* J = ev + m;
+  double* floor = J + (int64_t)(nb / 2) * JS * JS;
   hipLaunchKernelGGL(jacobi_init, dim3((unsigned)cdiv(m * m, 256)), dim3(256), 0, s, G, l, m, A, V);
   NYS_CHECK_LAUNCH();
   NYS_HIP(hipMemsetAsync(flags, 0, sizeof(int) * max_sweeps, s));
-  NYS_HIP(hipMemsetAsync(bar, 0, sizeof(unsigned), s));
-  NYS_HIP(hipMemsetAsync(bar_err, 0, sizeof(int), s));
-  JacArgs a{A, V, J, m, nb, max_sweeps, inner_sweeps_for(l), flags, sweeps_out, ev, bar, bar_err};
-  const int64_t tasks = (int64_t)(nb / 2) * (nb / 2) + (m / JS) * (nb / 2);
-  const int g = coop_blocks((const void*)jacobi_block_coop, 256, 0, (int)(tasks < 256 ? tasks : 256));
-  void* args[] = {&a};
-  NYS_HIP(hipLaunchCooperativeKernel((const void*)jacobi_block_coop, dim3(g), dim3(256), args, 0, s));
+  NYS_HIP(hipMemsetAsync(conv, 0, sizeof(int), s));
+  NYS_HIP(hipMemsetAsync(sweeps_out, 0, sizeof(int), s));
+  hipLaunchKernelGGL(jac_floor, dim3(1), dim3(256), 0, s, A, m, floor);
+  NYS_CHECK_LAUNCH();
+  JacArgs a{A, V, J, m, nb, inner_sweeps_for(l), flags, conv, sweeps_out, floor};
+  const int npair = nb / 2;
+  const int64_t tasks = (int64_t)npair * npair + (m / JS) * npair;
+  for (int sweep = 0; sweep < max_sweeps; ++sweep) {
+    for (int64_t r = 0; r < nb - 1; ++r) {
+      hipLaunchKernelGGL(jac_phase1, dim3((unsigned)npair), dim3(256), 0, s, a, r, sweep);
+      hipLaunchKernelGGL(jac_phase2, dim3((unsigned)tasks), dim3(256), 0, s, a, r);
+    }
+    hipLaunchKernelGGL(jac_end_sweep, dim3(1), dim3(1), 0, s, a, sweep);
+    NYS_CHECK_LAUNCH();
+    if (sweep >= 5 && (sweep % 3 == 2)) {
+      int c = 0;
+      NYS_HIP(hipMemcpyAsync(&c, conv, sizeof(int), hipMemcpyDeviceToHost, s));
+      NYS_HIP(hipStreamSynchronize(s));
+      if (c) break;
+    }
+  }
+  hipLaunchKernelGGL(jac_evals, dim3((unsigned)cdiv(m, 256)), dim3(256), 0, s, A, m, ev);
   hipLaunchKernelGGL(eig_finalize, dim3((unsigned)cdiv(l, 256)), dim3(256), 0, s, ev, V, l, m,
                      nu, T, lam, sig2);
   NYS_CHECK_LAUNCH();

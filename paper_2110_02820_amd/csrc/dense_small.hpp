@@ -13,19 +13,19 @@ nys_status scale_device_scalar(double* x, double factor, hipStream_t s);
 
 // L L^T = (M + M^T)/2 (lower L, upper part zeroed); Dinv receives the inverses
 // of the diagonal blocks (chol_ws_doubles(n) doubles); *info = 0 or k+1 for a
-// non-positive pivot at column k.  bar/bar_err: device counters.
+// non-positive pivot at column k.
 size_t chol_ws_doubles(int64_t n);
-nys_status cholesky(const double* M, int64_t n, double* L, double* Dinv, int* info, unsigned* bar,
-                    int* bar_err, hipStream_t s);
+nys_status cholesky(const double* M, int64_t n, double* L, double* Dinv, int* info, hipStream_t s);
 // X = L^{-1} (lower, full n x n written) using the diagonal-block inverses.
 nys_status tri_inverse(const double* L, int64_t n, const double* Dinv, double* X, hipStream_t s);
 
 // Eigen-decomposition of the symmetric l x l matrix G = W diag(s) W^T
-// (Jacobi).  Writes T = W[:, perm] diag(1/sqrt(s)) (l x l) with perm sorting s
+// (block Jacobi).  Writes T = W[:, perm] diag(1/sqrt(s)) (l x l) with perm sorting s
 // descending, lam = max(0, s - nu) (descending), sig2 = s (descending, nullable).
 size_t eig_ws_doubles(int64_t l);
+// flags: max_sweeps ints; sweeps_out, conv: device ints.
 nys_status sym_eig(const double* G, int64_t l, double* work, int* flags, int max_sweeps,
-                   int* sweeps_out, unsigned* bar, int* bar_err, double* T, double* lam,
-                   double* sig2, const double* nu, hipStream_t s);
+                   int* sweeps_out, int* conv, double* T, double* lam, double* sig2, const double* nu,
+                   hipStream_t s);
 
 }  // namespace nys

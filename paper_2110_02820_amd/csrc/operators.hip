@@ -257,7 +257,7 @@ template <typename TD, int DMAX>
 __global__ __launch_bounds__(256) void rbf_kv_f64(const TD* __restrict__ X, int64_t n, int d,
                                                   int64_t ld, double c2, const double* __restrict__ P,
                                                   int64_t ldp, int64_t k, double* __restrict__ out,
-                                                  int64_t ldo, int64_t pts_per_split,
+                                                  int64_t ldo, int64_t pts_per_split, double scale,
                                                   const int* __restrict__ skip) {
   if (skip && *skip) return;
   __shared__ double Xi[RB_ROWS][DMAX + 1];
@@ -337,13 +337,13 @@ __global__ __launch_bounds__(256) void rbf_kv_f64(const TD* __restrict__ X, int6
         // f64 MFMA accumulator element qq of lane l holds row 4 qq + l/16
         const int64_t gi = i0 + wm * 32 + a * 16 + 4 * qq + (lane >> 4);
         const int64_t gc = cb + wn * 32 + b * 16 + (lane & 15);
-        if (gi < n && gc < k) o[gi * ldo + gc] = acc[a][b][qq];
+        if (gi < n && gc < k) o[gi * ldo + gc] = scale * acc[a][b][qq];
       }
 }
 
 // out[i][c] = sum_s part[s][i][c] (+ mu_c P[i][c]) for n x k
 __global__ void reduce_splits_mu(const double* __restrict__ part, int ns, int64_t n, int64_t k,
-                                 const double* __restrict__ P, int64_t ldp,
+                                 double scale, const double* __restrict__ P, int64_t ldp,
                                  const double* __restrict__ mu, int64_t nrhs,
                                  double* __restrict__ out, int64_t ldo,
                                  const int* __restrict__ skip) {
@@ -353,6 +353,7 @@ __global__ void reduce_splits_mu(const double* __restrict__ part, int ns, int64_
   const int64_t i = idx / k, c = idx % k;
   double s = 0.0;
   for (int q = 0; q < ns; ++q) s += part[((int64_t)q * n + i) * k + c];
+  s *= scale;
   if (mu) s += mu[c / nrhs] * P[i * ldp + c];
   out[i * ldo + c] = s;
 }
@@ -386,7 +387,7 @@ nys_status rbf_apply_f64_t(const OpDesc& op, const double* P, int64_t k, int64_t
 #undef L1
     NYS_CHECK_LAUNCH();
     hipLaunchKernelGGL(reduce_splits_mu, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, s, scratch,
-                       (int)ns, n, (int64_t)1, P, ldp, mu_dev, nrhs, V, ldv, op.skip);
+                       (int)ns, n, (int64_t)1, op.scale, P, ldp, mu_dev, nrhs, V, ldv, op.skip);
     NYS_CHECK_LAUNCH();
     return NYS_OK;
   }
@@ -399,7 +400,7 @@ nys_status rbf_apply_f64_t(const OpDesc& op, const double* P, int64_t k, int64_t
   dim3 grid((unsigned)nrb, (unsigned)ncb, (unsigned)ns);
   double* o = ns > 1 ? scratch : V;
   const int64_t ldo = ns > 1 ? k : ldv;
-#define L2(DM) hipLaunchKernelGGL((rbf_kv_f64<TD, DM>), grid, dim3(256), 0, s, X, n, d, op.ld, c2, P, ldp, k, o, ldo, pps, op.skip)
+#define L2(DM) hipLaunchKernelGGL((rbf_kv_f64<TD, DM>), grid, dim3(256), 0, s, X, n, d, op.ld, c2, P, ldp, k, o, ldo, pps, ns > 1 ? 1.0 : op.scale, op.skip)
   if (dm == 8) L2(8); else if (dm == 16) L2(16); else if (dm == 32) L2(32); else L2(64);
 #undef L2
   NYS_CHECK_LAUNCH();
@@ -410,7 +411,7 @@ nys_status rbf_apply_f64_t(const OpDesc& op, const double* P, int64_t k, int64_t
                          P, ldp, n, k, mu_dev, nrhs, op.skip);
     } else {
       hipLaunchKernelGGL(reduce_splits_mu, dim3((unsigned)cdiv(n * k, 256)), dim3(256), 0, s,
-                         scratch, (int)ns, n, k, P, ldp, mu_dev, nrhs, V, ldv, op.skip);
+                         scratch, (int)ns, n, k, op.scale, P, ldp, mu_dev, nrhs, V, ldv, op.skip);
     }
     NYS_CHECK_LAUNCH();
   }
@@ -418,8 +419,8 @@ nys_status rbf_apply_f64_t(const OpDesc& op, const double* P, int64_t k, int64_t
 }
 
 template <typename TD, typename TA>
-nys_status xtx_apply_t(const OpDesc& op, const TA* p, TA mu, TA* v, TA* scratch,
-                       size_t scratch_elems, hipStream_t s) {
+nys_status xtx_partials_t(const OpDesc& op, const TA* p, TA* scratch, size_t scratch_elems, int* ng_out,
+                          hipStream_t s) {
   const TD* X = static_cast<const TD*>(op.data);
   const int64_t m = op.rows, n = op.n;
   constexpr int E = Vec16<TD>::E;
@@ -450,8 +451,18 @@ nys_status xtx_apply_t(const OpDesc& op, const TA* p, TA mu, TA* v, TA* scratch,
   }
 #undef LX
   NYS_CHECK_LAUNCH();
+  *ng_out = (int)ng;
+  return NYS_OK;
+}
+
+template <typename TD, typename TA>
+nys_status xtx_apply_t(const OpDesc& op, const TA* p, TA mu, TA* v, TA* scratch,
+                       size_t scratch_elems, hipStream_t s) {
+  int ng = 0;
+  NYS_TRY((xtx_partials_t<TD, TA>(op, p, scratch, scratch_elems, &ng, s)));
+  const int64_t n = op.n;
   hipLaunchKernelGGL((reduce_cols<TA, TA>), dim3((unsigned)cdiv(n, 32)), dim3(256), 0, s, scratch,
-                     (int)ng, n, TA(op.scale), p, mu, v, op.skip);
+                     ng, n, TA(op.scale), p, mu, v, op.skip);
   NYS_CHECK_LAUNCH();
   return NYS_OK;
 }
@@ -481,7 +492,7 @@ nys_status rbf_rect_t(const TD* Xr, int64_t nr, int64_t ldr, const TD* Xc, int64
 #undef L3
   NYS_CHECK_LAUNCH();
   hipLaunchKernelGGL(reduce_splits_mu, dim3((unsigned)cdiv(nr, 256)), dim3(256), 0, s, scratch,
-                     (int)ns, nr, (int64_t)1, (const double*)nullptr, (int64_t)1,
+                     (int)ns, nr, (int64_t)1, 1.0, (const double*)nullptr, (int64_t)1,
                      (const double*)nullptr, (int64_t)1, out, (int64_t)1, (const int*)nullptr);
   NYS_CHECK_LAUNCH();
   return NYS_OK;
@@ -595,6 +606,60 @@ nys_status op_matvec(const OpDesc& op, const TA* p, TA mu, TA* v, TA* scratch, s
     return NYS_OK;
   }
   set_error("op_matvec: unsupported operator for this precision");
+  return NYS_ERR_ARG;
+}
+
+// Single vector in partial-sum form: (A p)[j] = scale * sum_{g < ng} part[g][j].
+template <typename TA>
+nys_status op_matvec_partials(const OpDesc& op, const TA* p, TA* part, size_t part_elems, int* ng_out,
+                              hipStream_t s);
+
+template <>
+nys_status op_matvec_partials<double>(const OpDesc& op, const double* p, double* part, size_t part_elems,
+                                      int* ng_out, hipStream_t s) {
+  const int64_t n = op.n;
+  if (op.kind == NYS_OP_XTX) {
+    const int64_t m = op.rows;
+    if (op.dtype == NYS_F64) return xtx_partials_t<double, double>(op, p, part, part_elems, ng_out, s);
+    return xtx_partials_t<float, double>(op, p, part, part_elems, ng_out, s);
+    (void)m;
+  }
+  if (op.kind == NYS_OP_RBF) {
+    const int d = (int)op.cols;
+    const int dm = rbf_dmax(d);
+    if (dm < 0) {
+      set_error("RBF operator: d = %d > 64 not supported", d);
+      return NYS_ERR_ARG;
+    }
+    const double c2 = 1.0 / (2.0 * op.sigma * op.sigma);
+    const int64_t nrb = cdiv(n, RB_ROWS);
+    int64_t ns = cdiv(4 * (num_cus() < 256 ? num_cus() : 256), nrb);
+    if (ns < 1) ns = 1;
+    while (ns > 1 && (size_t)(ns * n) > part_elems) --ns;
+    const int64_t pps = cdiv(cdiv(n, ns), RB_PTS) * RB_PTS;
+    ns = cdiv(n, pps);
+    dim3 grid((unsigned)nrb, (unsigned)ns);
+#define LP(TD_, DM) hipLaunchKernelGGL((rbf_mv_f64<TD_, DM, 0>), grid, dim3(256), 0, s, static_cast<const TD_*>(op.data), n, op.ld, static_cast<const TD_*>(op.data), n, op.ld, d, c2, 0.0, p, part, pps, op.skip)
+#define LPD(TD_) if (dm == 8) LP(TD_, 8); else if (dm == 16) LP(TD_, 16); else if (dm == 32) LP(TD_, 32); else LP(TD_, 64)
+    if (op.dtype == NYS_F64) { LPD(double); } else { LPD(float); }
+#undef LPD
+#undef LP
+    NYS_CHECK_LAUNCH();
+    *ng_out = (int)ns;
+    return NYS_OK;
+  }
+  set_error("op_matvec_partials: operator has no partial form");
+  return NYS_ERR_ARG;
+}
+
+template <>
+nys_status op_matvec_partials<float>(const OpDesc& op, const float* p, float* part, size_t part_elems,
+                                     int* ng_out, hipStream_t s) {
+  if (op.kind == NYS_OP_XTX) {
+    if (op.dtype == NYS_F64) return xtx_partials_t<double, float>(op, p, part, part_elems, ng_out, s);
+    return xtx_partials_t<float, float>(op, p, part, part_elems, ng_out, s);
+  }
+  set_error("op_matvec_partials: float32 form available for X^T X only");
   return NYS_ERR_ARG;
 }
 

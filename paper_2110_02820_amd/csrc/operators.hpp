@@ -29,6 +29,12 @@ template <typename TA>
 nys_status op_matvec(const OpDesc& op, const TA* p, TA mu, TA* v, TA* scratch, size_t scratch_elems,
                      hipStream_t s);
 
+// Single vector in partial-sum form: (A p)[j] = scale * sum_{g < ng} part[g][j]
+// (X^T X: float or double arithmetic; RBF: double).  *ng_out = number of groups.
+template <typename TA>
+nys_status op_matvec_partials(const OpDesc& op, const TA* p, TA* part, size_t part_elems, int* ng_out,
+                              hipStream_t s);
+
 // out (nr) = W p with W = K(Xr, Xc) (mode 0) or dK/dsigma (mode 1), float64
 // arithmetic; Xr: nr x d (ldr), Xc: nc x d (ldc), both of storage `dtype`.
 // scratch: >= 4 * 256 * nr doubles.

@@ -264,6 +264,84 @@ __global__ void cg_direction(int64_t n, int64_t k, const T* __restrict__ Z, T* _
   }
 }
 
+// Single vector, fused: finish the operator product from its partial sums,
+// v = scale * sum_g part[g] + mu p (block: 32 entries x 8 slices of g), then
+// partial p^T v; the last block derives alpha and, when `fuse` is set (small
+// n), also performs x += alpha p, r -= alpha v and the stopping test over the
+// whole vector (saving two launches per iteration).
+template <typename T>
+__global__ __launch_bounds__(NT) void cg_finish_mv(int64_t n, const T* __restrict__ part, int ng, double scale,
+                                                   double mu, const T* __restrict__ P, T* __restrict__ V,
+                                                   double* __restrict__ ppv, CgScalars sc, int par, int fuse,
+                                                   T* __restrict__ X, T* __restrict__ R,
+                                                   double* __restrict__ prr, double tol) {
+  if (*sc.alldone) return;
+  __shared__ T shp[8][33];
+  __shared__ double sh[NT];
+  const int c = threadIdx.x & 31, sl = threadIdx.x >> 5;
+  const int64_t ntiles = cdiv(n, 32);
+  double pvp = 0.0;
+  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const int64_t j = tile * 32 + c;
+    T a0 = T(0), a1 = T(0);
+    if (j < n) {
+      int g = sl;
+      for (; g + 8 < ng; g += 16) {
+        a0 += part[(int64_t)g * n + j];
+        a1 += part[(int64_t)(g + 8) * n + j];
+      }
+      if (g < ng) a0 += part[(int64_t)g * n + j];
+    }
+    __syncthreads();
+    shp[sl][c] = a0 + a1;
+    __syncthreads();
+    if (sl == 0 && j < n) {
+      const T sum = ((shp[0][c] + shp[1][c]) + (shp[2][c] + shp[3][c])) +
+                    ((shp[4][c] + shp[5][c]) + (shp[6][c] + shp[7][c]));
+      const T pj = P[j];
+      const T vj = T(scale) * sum + T(mu) * pj;
+      V[j] = vj;
+      pvp += double(pj) * double(vj);
+    }
+  }
+  const double tot = block_sum(pvp, sh);
+  if (threadIdx.x == 0) ppv[blockIdx.x] = tot;
+  if (!last_block(sc.ctr, gridDim.x)) return;
+  const double pv = block_reduce_col(ppv, gridDim.x, 1, 0, sh);
+  __shared__ double alpha_s;
+  if (threadIdx.x == 0) {
+    double a = 0.0;
+    if (!sc.done[0]) {
+      if (pv > 0.0) {
+        a = sc.rz[par] / pv;
+      } else {
+        sc.status[0] = NYS_ERR_BREAKDOWN;
+        sc.done[0] = 1;
+      }
+    }
+    sc.alpha[0] = a;
+    alpha_s = a;
+  }
+  __syncthreads();
+  if (!fuse) return;
+  const T a = T(alpha_s);
+  double rr = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += NT) {
+    X[i] += a * P[i];
+    const T r = R[i] - a * V[i];
+    R[i] = r;
+    rr += double(r) * double(r);
+  }
+  rr = block_sum(rr, sh);
+  if (threadIdx.x == 0 && !sc.done[0]) {
+    sc.rnorm2[0] = rr;
+    sc.iters[0] += 1;
+    const bool conv = rr <= tol * tol * sc.bnorm2[0];
+    sc.conv[0] = conv ? 1 : 0;
+    if (conv) sc.status[0] = NYS_OK;
+  }
+}
+
 // ---------------------------------------------------------------- apply, k = 1
 
 // C'[j] = ((lam_l + mu)/(lam_j + mu) - 1) (U^T r)[j].  Grid (column blocks of
@@ -284,25 +362,35 @@ __global__ __launch_bounds__(NT) void utr_scale(int64_t n, int64_t l, const TU* 
   const int64_t j = (int64_t)blockIdx.x * 64 + tx;
   const int64_t i0 = (int64_t)blockIdx.y * rows_per_chunk;
   const int64_t i1 = i0 + rows_per_chunk < n ? i0 + rows_per_chunk : n;
-  double a0 = 0.0, a1 = 0.0;
+  // four independent accumulators: several loads in flight per thread
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
   if (j < l) {
     int64_t i = i0 + ty;
-    for (; i + 4 < i1; i += 8) {
+    for (; i + 12 < i1; i += 16) {
       a0 += double(U[i * ldu + j]) * double(r[i]);
       a1 += double(U[(i + 4) * ldu + j]) * double(r[i + 4]);
+      a2 += double(U[(i + 8) * ldu + j]) * double(r[i + 8]);
+      a3 += double(U[(i + 12) * ldu + j]) * double(r[i + 12]);
     }
-    if (i < i1) a0 += double(U[i * ldu + j]) * double(r[i]);
+    for (; i < i1; i += 4) a0 += double(U[i * ldu + j]) * double(r[i]);
   }
-  red[ty][tx] = a0 + a1;
+  red[ty][tx] = (a0 + a1) + (a2 + a3);
   __syncthreads();
   if (ty == 0 && j < l)
     part[(int64_t)blockIdx.y * l + j] = (red[0][tx] + red[1][tx]) + (red[2][tx] + red[3][tx]);
   if (!last_block(ctr + blockIdx.x, gridDim.y)) return;
   // chunk partials: thread (tx, ty) sums chunks q = ty (mod 4), then in order
-  double sp = 0.0;
-  if (j < l)
-    for (unsigned q = ty; q < gridDim.y; q += 4) sp += part[(int64_t)q * l + j];
-  red[ty][tx] = sp;
+  double p0 = 0.0, p1 = 0.0;
+  if (j < l) {
+    unsigned q = ty;
+    for (; q + 4 < gridDim.y; q += 8) {
+      p0 += part[(int64_t)q * l + j];
+      p1 += part[(int64_t)(q + 4) * l + j];
+    }
+    if (q < gridDim.y) p0 += part[(int64_t)q * l + j];
+  }
+  __syncthreads();
+  red[ty][tx] = p0 + p1;
   __syncthreads();
   if (ty == 0 && j < l) {
     const double sum = (red[0][tx] + red[1][tx]) + (red[2][tx] + red[3][tx]);
@@ -317,7 +405,8 @@ template <typename TU, typename T>
 __global__ __launch_bounds__(NT) void uc_rz(int64_t n, int64_t l, const TU* __restrict__ U, int64_t ldu,
                                             const double* __restrict__ Cs, const T* __restrict__ r,
                                             T* __restrict__ z, int64_t rows_per_wave,
-                                            double* __restrict__ prz, CgScalars sc, int par, int mode) {
+                                            double* __restrict__ prz, CgScalars sc, int par, int mode,
+                                            T* __restrict__ Pd) {
   if (mode == 2 && *sc.alldone) return;
   extern __shared__ char smem[];
   T* cs = reinterpret_cast<T*>(smem);
@@ -358,6 +447,15 @@ __global__ __launch_bounds__(NT) void uc_rz(int64_t n, int64_t l, const TU* __re
   if (threadIdx.x == 0) prz[blockIdx.x] = tot;
   if (!last_block(sc.ctr, gridDim.x)) return;
   rz_tail(prz, gridDim.x, 1, sh, sc, par, mode == 1);
+  if (Pd == nullptr) return;
+  // fused direction update (small n): P = Z (set-up) or P = Z + beta P
+  __syncthreads();
+  if (mode == 1) {
+    for (int64_t i = threadIdx.x; i < n; i += NT) Pd[i] = z[i];
+  } else if (!sc.done[0]) {
+    const T b = T(sc.beta[0]);
+    for (int64_t i = threadIdx.x; i < n; i += NT) Pd[i] = z[i] + b * Pd[i];
+  }
 }
 
 // ---------------------------------------------------------------- apply, k > 1
@@ -396,11 +494,10 @@ nys_status utr_launch(const PrecDesc& P, const double* mu_dev, const void* R, bo
                       double* Cs, unsigned* ctr, const int* alldone, hipStream_t s) {
   const int64_t n = P.n, l = P.ell;
   const int64_t cb = cdiv(l, 64);
-  int64_t rc = cdiv(512, cb);
-  if (rc > cdiv(n, 64)) rc = cdiv(n, 64);
-  if (rc < 1) rc = 1;
-  const int64_t rpc = cdiv(n, rc);
-  rc = cdiv(n, rpc);
+  // chunks of >= 64 rows (16 per thread row phase), at most 512 chunks
+  int64_t rpc = cdiv(n, 512);
+  rpc = cdiv(rpc < 64 ? 64 : rpc, 16) * 16;
+  const int64_t rc = cdiv(n, rpc);
   dim3 grid((unsigned)cb, (unsigned)rc);
 #define LU(TU_, T_)                                                                                \
   hipLaunchKernelGGL((utr_scale<TU_, T_>), grid, dim3(NT), 0, s, n, l, static_cast<const TU_*>(P.U), \
@@ -415,7 +512,7 @@ nys_status utr_launch(const PrecDesc& P, const double* mu_dev, const void* R, bo
 }
 
 nys_status uc_launch(const PrecDesc& P, const double* Cs, const void* R, void* Z, bool f32, double* prz,
-                     const CgScalars& sc, int par, int mode, hipStream_t s) {
+                     const CgScalars& sc, int par, int mode, hipStream_t s, void* Pd = nullptr) {
   const int64_t n = P.n, l = P.ell;
   int64_t rpw = cdiv(n, 4 * 512);  // at most 512 workgroups (partial buffer size)
   rpw = cdiv(rpw < 4 ? 4 : rpw, 4) * 4;
@@ -424,7 +521,7 @@ nys_status uc_launch(const PrecDesc& P, const double* Cs, const void* R, void* Z
 #define LC(TU_, T_)                                                                                  \
   hipLaunchKernelGGL((uc_rz<TU_, T_>), dim3((unsigned)nb), dim3(NT), sh, s, n, l,                    \
                      static_cast<const TU_*>(P.U), P.ldu, Cs, static_cast<const T_*>(R),              \
-                     static_cast<T_*>(Z), rpw, prz, sc, par, mode)
+                     static_cast<T_*>(Z), rpw, prz, sc, par, mode, static_cast<T_*>(Pd))
   if (P.dtype == NYS_F64 && !f32) LC(double, double);
   else if (P.dtype == NYS_F64 && f32) LC(double, float);
   else if (P.dtype == NYS_F32 && !f32) LC(float, double);
@@ -540,6 +637,40 @@ nys_status pcg_iteration(int64_t n, int64_t k, const PrecDesc& P, const double* 
   NYS_CHECK_LAUNCH();
   return NYS_OK;
 }
+
+constexpr int64_t kFuseMaxN = 16384;
+
+template <typename T>
+nys_status pcg_iteration_fused(int64_t n, const PrecDesc& P, const double* mu_dev, double mu, const T* part,
+                               int ng, double scale, T* V, T* X, T* R, T* Z, T* Pd, PcgWork& w,
+                               const CgScalars& sc, int par, double tol, hipStream_t s) {
+  const bool f32 = sizeof(T) == 4;
+  const bool fuse = n <= kFuseMaxN;
+  const int64_t nfb = cdiv(n, 32) < 512 ? cdiv(n, 32) : 512;
+  hipLaunchKernelGGL(cg_finish_mv<T>, dim3((unsigned)nfb), dim3(NT), 0, s, n, part, ng, scale, mu, Pd,
+                     V, w.ppv, sc, par, fuse ? 1 : 0, X, R, w.prr, tol);
+  NYS_CHECK_LAUNCH();
+  if (!fuse) {
+    const int64_t g = groups_for(n, 1);
+    hipLaunchKernelGGL(cg_update<T>, dim3((unsigned)g), dim3(NT), 0, s, n, (int64_t)1, Pd, V, X, (int64_t)1, R,
+                       w.prr, cdiv(n, g), tol, sc);
+    NYS_CHECK_LAUNCH();
+  }
+  NYS_TRY(utr_launch(P, mu_dev, R, f32, w.apart, w.Cs, sc.ctr + 1, sc.alldone, s));
+  NYS_TRY(uc_launch(P, w.Cs, R, Z, f32, w.prz, sc, par, 2, s, fuse ? Pd : nullptr));
+  if (!fuse) {
+    hipLaunchKernelGGL(cg_direction<T>, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, s, n, (int64_t)1, Z, Pd, sc, 0);
+    NYS_CHECK_LAUNCH();
+  }
+  return NYS_OK;
+}
+
+template nys_status pcg_iteration_fused<double>(int64_t, const PrecDesc&, const double*, double, const double*, int,
+                                                double, double*, double*, double*, double*, double*, PcgWork&,
+                                                const CgScalars&, int, double, hipStream_t);
+template nys_status pcg_iteration_fused<float>(int64_t, const PrecDesc&, const double*, double, const float*, int,
+                                               double, float*, float*, float*, float*, float*, PcgWork&,
+                                               const CgScalars&, int, double, hipStream_t);
 
 template nys_status pcg_setup<double>(int64_t, int64_t, const PrecDesc&, const double*, int64_t, const double*,
                                       const double*, double*, double*, double*, PcgWork&, const CgScalars&,

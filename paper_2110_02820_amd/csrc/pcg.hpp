@@ -56,4 +56,12 @@ nys_status pcg_iteration(int64_t n, int64_t k, const PrecDesc& P, const double* 
                          const T* V, T* X, int64_t ldx, T* R, T* Z, T* Pd, PcgWork& w, const CgScalars& sc,
                          int par, double tol, hipStream_t s);
 
+// One iteration for a single column whose product (A p) is given in partial
+// form (part: ng x n, A p = scale * sum_g part[g]); fewer launches than
+// pcg_iteration (matvec finish, alpha, update and direction are fused).
+template <typename T>
+nys_status pcg_iteration_fused(int64_t n, const PrecDesc& P, const double* mu_dev, double mu, const T* part,
+                               int ng, double scale, T* V, T* X, T* R, T* Z, T* Pd, PcgWork& w,
+                               const CgScalars& sc, int par, double tol, hipStream_t s);
+
 }  // namespace nys
