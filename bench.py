@@ -70,7 +70,7 @@ def main():
 
     def step(seed, opx, precx, wsx, udtype):
         Om, Y = nys.nys_sketch(opx, ell, seed=seed, prec=precx, ws=wsx)
-        P = nys.nys_factor(Om, Y, dtype=udtype, ws=wsx)
+        P = nys.nys_factor(Om, Y, dtype=udtype, ws=wsx, prec=precx)
         x, info = nys.nys_pcg_solve(opx, P, mu, b, tol=tol, maxit=1000, prec=precx, ws=wsx, inner_tol=1e-4)
         return x, info
 
@@ -86,7 +86,7 @@ def main():
             Om, Y = nys.nys_sketch(opx, ell, seed=20211002 + i, prec=precx, ws=wsx)
             torch.cuda.synchronize()
             bb = time.perf_counter()
-            P = nys.nys_factor(Om, Y, dtype=udtype, ws=wsx)
+            P = nys.nys_factor(Om, Y, dtype=udtype, ws=wsx, prec=precx)
             torch.cuda.synchronize()
             c = time.perf_counter()
             x, info = nys.nys_pcg_solve(opx, P, mu, b, tol=tol, maxit=1000, prec=precx, ws=wsx, inner_tol=1e-4)

@@ -135,17 +135,25 @@ nys_status nys_sketch(const nys_operator* A, int64_t ell, uint64_t seed, const d
 /* Factor (same algorithm, steps 4-9): nu = eps(||Y||_F) (spacing of the
  * float64 number), Y_nu = Y + nu Omega, C = chol(Omega^T Y_nu), B = Y_nu C^{-1},
  * [U, Sigma] = thin SVD of B, lam = max(0, Sigma^2 - nu), descending.
+ * prec: arithmetic of the sketch that produced Y.  For a reduced-precision
+ * sketch (relative error up to u = 2^-20 for float32 tiles, 2^-15 for bf16x3
+ * tiles) the shift is raised to max(eps(||Y||_F), u ||Y||_F) so that the core
+ * matrix stays positive definite; the shift is removed again from lam.
  * Y is overwritten.  P: P->n, P->ell, P->U, P->ldu, P->dtype, P->lam set by
  * the caller; P->nu is written (host).  A failed Cholesky is retried with
  * nu <- 10 nu up to three times, then NYS_ERR_NOT_PSD.  Synchronises stream. */
-nys_status nys_factor(const double* Omega, double* Y, nys_precond* P, void* ws, size_t ws_bytes,
-                      void* stream);
+nys_status nys_factor(const double* Omega, double* Y, nys_precond* P, int32_t prec, void* ws,
+                      size_t ws_bytes, void* stream);
 
-/* Z = (A + mu I) V for k columns (row-major n x k).  dtype NYS_F64 computes in
- * float64 (float32 operator data is promoted exactly); NYS_F32 computes in
- * float32.  Used for right-hand sides and true residuals. */
+/* Z = (A + mu I) V for k columns (row-major n x k).  prec NYS_PREC_FP64
+ * computes in float64 (float32 operator data is promoted exactly; V, Z
+ * float64).  Other modes compute in float32 with float32 V, Z: X^T X and
+ * dense operators for one contiguous vector; RBF operators for any k, with
+ * the Gram tiles in float32 (NYS_PREC_FP32, NYS_PREC_FP32_REFINE64) or split
+ * into three bf16 products (NYS_PREC_BF16X3_REFINE64), d <= 32.  Used for
+ * right-hand sides, true residuals and tests of the product kernels. */
 nys_status nys_op_apply(const nys_operator* A, double mu, const void* V, int64_t k, int64_t ldv,
-                        void* Z, int64_t ldz, int32_t dtype, void* ws, size_t ws_bytes, void* stream);
+                        void* Z, int64_t ldz, int32_t prec, void* ws, size_t ws_bytes, void* stream);
 
 /* Z = P^{-1} R with eq. (NysPre):
  *   P^{-1} = (lam_l + mu) U (Lambda + mu I)^{-1} U^T + (I - U U^T),

@@ -76,7 +76,7 @@ def lib():
         L.nys_workspace_size.argtypes = [P(_Operator), i64, i64, i32]
         L.nys_gaussian.argtypes = [ctypes.c_uint64, i64, i64, vp, i64, vp]
         L.nys_sketch.argtypes = [P(_Operator), i64, ctypes.c_uint64, vp, vp, vp, i32, vp, sz, vp]
-        L.nys_factor.argtypes = [vp, vp, P(_Precond), vp, sz, vp]
+        L.nys_factor.argtypes = [vp, vp, P(_Precond), i32, vp, sz, vp]
         L.nys_op_apply.argtypes = [P(_Operator), dbl, vp, i64, i64, vp, i64, i32, vp, sz, vp]
         L.nys_precond_apply.argtypes = [P(_Precond), dbl, vp, i64, i64, vp, i64, vp, sz, vp]
         L.nys_pcg_solve.argtypes = [P(_Operator), P(_Precond), P(dbl), i64, vp, i64, i64, vp, i64,
@@ -208,23 +208,31 @@ def nys_sketch(op: Operator, ell: int, seed: int = 0, omega0: Optional[torch.Ten
 
 
 def nys_factor(Omega: torch.Tensor, Y: torch.Tensor, dtype=torch.float64,
-               ws: Optional[torch.Tensor] = None, op: Optional[Operator] = None) -> Precond:
+               ws: Optional[torch.Tensor] = None, op: Optional[Operator] = None,
+               prec: int = NYS_PREC_FP64) -> Precond:
+    """Shifted Cholesky + SVD factorisation of a sketch; prec is the arithmetic
+    the sketch was computed in (it sets the minimum shift)."""
     n, ell = Y.shape
     U = torch.empty(n, ell, dtype=dtype, device=Y.device)
     lam = torch.empty(ell, dtype=torch.float64, device=Y.device)
     p = _Precond(n, ell, _ptr(U), ell, NYS_F64 if dtype == torch.float64 else NYS_F32, 0, _ptr(lam), 0.0)
     if ws is None:
         ws = _ws_shape(n, ell, 1, Y.device) if op is None else workspace(op, ell)
-    _check(lib().nys_factor(_ptr(Omega), _ptr(Y), ctypes.byref(p), _ptr(ws), ws.numel(), _stream()))
+    _check(lib().nys_factor(_ptr(Omega), _ptr(Y), ctypes.byref(p), prec, _ptr(ws), ws.numel(), _stream()))
     return Precond(U, lam, p.nu)
 
 
-def nys_op_apply(op: Operator, mu: float, V: torch.Tensor, ws: Optional[torch.Tensor] = None) -> torch.Tensor:
+def nys_op_apply(op: Operator, mu: float, V: torch.Tensor, ws: Optional[torch.Tensor] = None,
+                 prec: Optional[int] = None) -> torch.Tensor:
+    """(A + mu I) V.  float64 V computes in float64; float32 V in float32 (RBF:
+    Gram tiles in float32, or bf16x3 with prec=NYS_PREC_BF16X3_REFINE64)."""
     V2 = V.reshape(V.shape[0], -1).contiguous()
     k = V2.shape[1]
     Z = torch.empty_like(V2)
-    w = _ws(op, 1, k, NYS_PREC_FP64, ws)
-    _check(lib().nys_op_apply(ctypes.byref(op.c()), float(mu), _ptr(V2), k, k, _ptr(Z), k, _dt(V2), _ptr(w),
+    if prec is None:
+        prec = NYS_PREC_FP64 if V2.dtype == torch.float64 else NYS_PREC_FP32
+    w = _ws(op, 1, k, prec, ws)
+    _check(lib().nys_op_apply(ctypes.byref(op.c()), float(mu), _ptr(V2), k, k, _ptr(Z), k, prec, _ptr(w),
                               w.numel(), _stream()))
     return Z.reshape(V.shape)
 

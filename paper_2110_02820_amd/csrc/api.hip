@@ -13,6 +13,7 @@
 #include "gemm.hpp"
 #include "operators.hpp"
 #include "pcg.hpp"
+#include "rbf_lowp.hpp"
 #include "rng.hpp"
 
 namespace nys {
@@ -130,11 +131,16 @@ struct SketchWs {
   size_t opscr_elems;
   float *Om32, *T32, *Y32, *f32scr;
   size_t f32scr_elems;
+  void* lowp_buf;
 };
 
 bool sketch_f32(const OpDesc& op, int prec) {
   return prec != NYS_PREC_FP64 && op.kind == NYS_OP_XTX && op.dtype == NYS_F32;
 }
+
+bool rbf_lowp_mode(const OpDesc& op, int prec) { return prec != NYS_PREC_FP64 && op.kind == NYS_OP_RBF; }
+
+int rbf_gram(int prec) { return prec == NYS_PREC_BF16X3_REFINE64 ? RBF_GRAM_BF16X3 : RBF_GRAM_F32; }
 
 void carve_sketch(Arena& a, const OpDesc& op, int64_t l, int prec, SketchWs& w) {
   carve_core(a, l, w.c);
@@ -142,6 +148,14 @@ void carve_sketch(Arena& a, const OpDesc& op, int64_t l, int prec, SketchWs& w) 
   w.opscr = a.take<double>(w.opscr_elems);
   w.Om32 = w.T32 = w.Y32 = w.f32scr = nullptr;
   w.f32scr_elems = 0;
+  w.lowp_buf = nullptr;
+  if (rbf_lowp_mode(op, prec)) {
+    w.Om32 = a.take<float>(op.n * l);
+    w.Y32 = a.take<float>(op.n * l);
+    w.f32scr_elems = rbf_lowp_kv_scratch(op.n, l);
+    w.f32scr = a.take<float>(w.f32scr_elems);
+    w.lowp_buf = a.take<char>(rbf_lowp_bytes(op.n));
+  }
   if (sketch_f32(op, prec)) {
     w.Om32 = a.take<float>(op.n * l);
     w.T32 = a.take<float>(op.rows * l);
@@ -207,6 +221,8 @@ struct SolveWs {
   PcgBufs<float> f;
   double *mu, *R64, *V64, *X64, *B64, *dots;
   bool has_f;
+  void* lowp_buf;
+  RbfLowp L;
 };
 
 void carve_solve(Arena& a, const OpDesc& op, int64_t l, int64_t k, int prec, SolveWs& w) {
@@ -220,6 +236,7 @@ void carve_solve(Arena& a, const OpDesc& op, int64_t l, int64_t k, int prec, Sol
   carve_pcg<double>(a, op, l, k, w.d);
   w.has_f = prec != NYS_PREC_FP64;
   if (w.has_f) carve_pcg<float>(a, op, l, k, w.f);
+  w.lowp_buf = rbf_lowp_mode(op, prec) ? a.take<char>(rbf_lowp_bytes(op.n)) : nullptr;
 }
 
 // ---------------------------------------------------------------- small kernels
@@ -376,7 +393,9 @@ nys_status matvec<float>(const OpDesc& op, const float* P, int64_t k, const doub
   (void)nrhs;
   if (k == 1 && (op.kind == NYS_OP_XTX || op.kind == NYS_OP_DENSE))
     return op_matvec<float>(op, P, (float)mu_host, V, b.opscr, b.opscr_elems, s);
-  set_error("float32 arithmetic is available for single-column X^T X and dense operators");
+  if (op.kind == NYS_OP_RBF && op.lowp)
+    return rbf_lowp_kv(*op.lowp, op.gram, P, k, k, mu_dev, nrhs, V, k, b.opscr, b.opscr_elems, op.skip, s);
+  set_error("float32 arithmetic is available for X^T X, dense and prepared RBF operators (k = 1 for X^T X)");
   return NYS_ERR_ARG;
 }
 
@@ -405,7 +424,8 @@ nys_status pcg_run(const OpDesc& op0, const PrecDesc& P, int64_t k, int64_t nrhs
   NYS_TRY(pcg_setup<T>(n, k, P, mu_dev, nrhs, B, b.V, b.R, b.Z, b.P, b.w, b.sc, tol, s));
   op.skip = b.sc.alldone;
   // single column with a partial-sum operator product: fused iteration
-  const bool fused = k == 1 && (op.kind == NYS_OP_XTX || (op.kind == NYS_OP_RBF && sizeof(T) == 8));
+  const bool fused =
+      k == 1 && (op.kind == NYS_OP_XTX || (op.kind == NYS_OP_RBF && (sizeof(T) == 8 || op.lowp != nullptr)));
   int it = 0;
   int alldone_h = 0;
   NYS_HIP(hipMemcpyAsync(&alldone_h, b.sc.alldone, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -489,6 +509,13 @@ nys_status solve_impl(const OpDesc& op, const PrecDesc& P, const double* mu, int
   std::vector<double> relres(k, 0.0);
   int refine_steps = 0, total = 0;
   const double mu0 = mu[0];
+  // operator for the float32 inner solves (prepared points for the RBF kernels)
+  OpDesc opf = op;
+  if (rbf_lowp_mode(op, prec)) {
+    NYS_TRY(rbf_lowp_prepare(op, w.lowp_buf, w.L, s));
+    opf.lowp = &w.L;
+    opf.gram = rbf_gram(prec);
+  }
   if (prec == NYS_PREC_FP64) {
     PcgResult r;
     NYS_TRY(pcg_run<double>(op, P, k, nrhs, w.mu, mu0, w.B64, w.X64, false, tol, maxit, check, w.d, r, s));
@@ -503,7 +530,7 @@ nys_status solve_impl(const OpDesc& op, const PrecDesc& P, const double* mu, int
                        k, w.f.X, k);
     NYS_CHECK_LAUNCH();
     PcgResult r;
-    NYS_TRY(pcg_run<float>(op, P, k, nrhs, w.mu, mu0, w.f.B, w.f.X, false, tol, maxit, check, w.f, r, s));
+    NYS_TRY(pcg_run<float>(opf, P, k, nrhs, w.mu, mu0, w.f.B, w.f.X, false, tol, maxit, check, w.f, r, s));
     hipLaunchKernelGGL((gather_cols<float, double>), dim3(nblk(n * k)), dim3(256), 0, s, n, k, w.f.X, k,
                        k, w.X64, k);
     NYS_CHECK_LAUNCH();
@@ -524,7 +551,7 @@ nys_status solve_impl(const OpDesc& op, const PrecDesc& P, const double* mu, int
                          k, k, w.f.B, k);
       NYS_CHECK_LAUNCH();
       PcgResult r;
-      NYS_TRY(pcg_run<float>(op, P, k, nrhs, w.mu, mu0, w.f.B, w.f.X, true, itol, maxit, check, w.f, r,
+      NYS_TRY(pcg_run<float>(opf, P, k, nrhs, w.mu, mu0, w.f.B, w.f.X, true, itol, maxit, check, w.f, r,
                              s));
       hipLaunchKernelGGL(add_to<float>, dim3(nblk(n * k)), dim3(256), 0, s, w.X64, w.f.X, n * k);
       NYS_CHECK_LAUNCH();
@@ -577,10 +604,8 @@ nys_status check_solve_common(const OpDesc& op, const PrecDesc& P, const double*
     NYS_ARG(std::isfinite(mu[i]) && mu[i] >= 0.0, "mu[%lld] must be finite and >= 0", (long long)i);
     NYS_ARG(lam_l + mu[i] > 0.0, "lam_l + mu must be > 0 (mu = 0 needs a positive lam_l)");
   }
-  if (o->prec != NYS_PREC_FP64 && op.kind == NYS_OP_RBF) {
-    set_error("reduced-precision modes for the RBF operator are not available in this build");
-    return NYS_ERR_ARG;
-  }
+  if (o->prec != NYS_PREC_FP64 && op.kind == NYS_OP_RBF)
+    NYS_ARG(op.cols <= 32, "reduced-precision RBF modes need d <= 32");
   return NYS_OK;
 }
 
@@ -615,7 +640,7 @@ size_t nys_workspace_size(const nys_operator* A, int64_t ell, int64_t ncols, int
     Arena a(nullptr, 0);
     SolveWs w;
     carve_solve(a, op, ell, ncols, prec, w);
-    size_t extra = (size_t)(4 * 256) * (size_t)op.n * sizeof(double) + 4096;
+    size_t extra = (size_t)(4 * 256) * (size_t)op.n * sizeof(double) + rbf_lowp_bytes(op.n) + 4096;
     best = a.off + extra > best ? a.off + extra : best;
   }
   return best + 256;
@@ -650,7 +675,20 @@ nys_status nys_sketch(const nys_operator* A, int64_t ell, uint64_t seed, const d
   else NYS_TRY(gaussian(seed, n, l, Omega, l, s));
   int info[2] = {0, 0};
   NYS_TRY(cholqr2(Omega, Y, n, l, w.c, info, s));
-  if (sketch_f32(op, prec)) {
+  if (rbf_lowp_mode(op, prec)) {
+    NYS_ARG(op.cols <= 32, "reduced-precision RBF modes need d <= 32");
+    // Y = K Omega with the reduced-precision Gram tiles, float32 accumulation
+    RbfLowp L;
+    NYS_TRY(rbf_lowp_prepare(op, w.lowp_buf, L, s));
+    hipLaunchKernelGGL((gather_cols<double, float>), dim3(nblk(n * l)), dim3(256), 0, s, n, l, Omega, l,
+                       l, w.Om32, l);
+    NYS_CHECK_LAUNCH();
+    NYS_TRY(rbf_lowp_kv(L, rbf_gram(prec), w.Om32, l, l, nullptr, 1, w.Y32, l, w.f32scr, w.f32scr_elems, nullptr,
+                        s));
+    hipLaunchKernelGGL((gather_cols<float, double>), dim3(nblk(n * l)), dim3(256), 0, s, n, l, w.Y32, l,
+                       l, Y, l);
+    NYS_CHECK_LAUNCH();
+  } else if (sketch_f32(op, prec)) {
     // Y = X^T (X Omega) in float32 MFMA arithmetic
     hipLaunchKernelGGL((gather_cols<double, float>), dim3(nblk(n * l)), dim3(256), 0, s, n, l, Omega, l,
                        l, w.Om32, l);
@@ -674,7 +712,7 @@ nys_status nys_sketch(const nys_operator* A, int64_t ell, uint64_t seed, const d
   return NYS_OK;
 }
 
-nys_status nys_factor(const double* Omega, double* Y, nys_precond* P, void* ws, size_t ws_bytes,
+nys_status nys_factor(const double* Omega, double* Y, nys_precond* P, int32_t prec, void* ws, size_t ws_bytes,
                       void* stream) {
   NYS_ARG(P != nullptr && Omega != nullptr && Y != nullptr, "nys_factor: NULL argument");
   PrecDesc pd;
@@ -689,8 +727,13 @@ nys_status nys_factor(const double* Omega, double* Y, nys_precond* P, void* ws, 
   }
   hipStream_t s = S(stream);
   Core& c = w.c;
-  // nu = eps(||Y||_F);  Y_nu = Y + nu Omega
-  NYS_TRY(frob_shift(Y, n * l, c.part, c.nu, s));
+  // nu = eps(||Y||_F) (float64 sketch); a sketch computed in reduced
+  // precision carries relative errors up to u_rel, so the shift is raised to
+  // u_rel ||Y||_F, which keeps Omega^T Y_nu positive definite
+  NYS_ARG(prec >= NYS_PREC_FP64 && prec <= NYS_PREC_BF16X3_REFINE64, "unknown precision mode");
+  const double u_rel = prec == NYS_PREC_FP64 ? 0.0 : prec == NYS_PREC_BF16X3_REFINE64 ? 3.0517578125e-05
+                                                                                      : 9.5367431640625e-07;
+  NYS_TRY(frob_shift(Y, n * l, c.part, c.nu, u_rel, s));
   NYS_TRY(add_shift(Y, Omega, n * l, c.nu, 1.0, s));
   int info = 0;
   for (int attempt = 0; attempt <= 3; ++attempt) {
@@ -742,29 +785,38 @@ nys_status nys_factor(const double* Omega, double* Y, nys_precond* P, void* ws, 
 }
 
 nys_status nys_op_apply(const nys_operator* A, double mu, const void* V, int64_t k, int64_t ldv,
-                        void* Z, int64_t ldz, int32_t dtype, void* ws, size_t ws_bytes, void* stream) {
+                        void* Z, int64_t ldz, int32_t prec, void* ws, size_t ws_bytes, void* stream) {
   OpDesc op;
   NYS_TRY(check_op(A, op));
   NYS_ARG(V && Z && k >= 1 && ldv >= k && ldz >= k, "nys_op_apply: invalid vectors");
   NYS_ARG(std::isfinite(mu), "mu must be finite");
-  NYS_ARG(dtype == NYS_F64 || (dtype == NYS_F32 && k == 1 && ldv == 1 && ldz == 1 &&
-                               (op.kind == NYS_OP_XTX || op.kind == NYS_OP_DENSE)),
-          "nys_op_apply: float32 is available for one X^T X or dense vector");
+  NYS_ARG(prec >= NYS_PREC_FP64 && prec <= NYS_PREC_BF16X3_REFINE64, "unknown precision mode");
+  const bool f32 = prec != NYS_PREC_FP64;
+  NYS_ARG(!f32 || op.kind == NYS_OP_RBF || (k == 1 && ldv == 1 && ldz == 1),
+          "nys_op_apply: float32 products of X^T X / dense operators take one contiguous vector");
+  NYS_ARG(!f32 || op.kind != NYS_OP_RBF || op.cols <= 32, "reduced-precision RBF products need d <= 32");
   Arena a(ws, ws_bytes);
   double* mu_dev = a.take<double>(1);
   const size_t se = op_scratch_elems(op, k);
   double* scr = a.take<double>(se);
+  void* lowp_buf = (f32 && op.kind == NYS_OP_RBF) ? a.take<char>(rbf_lowp_bytes(op.n)) : nullptr;
   if (!ws || !a.ok()) {
     set_error("workspace too small: need %zu bytes", a.off);
     return NYS_ERR_WORKSPACE;
   }
   hipStream_t s = S(stream);
-  if (dtype == NYS_F32)
+  NYS_TRY(set_mu(mu_dev, &mu, 1, s));
+  if (f32 && op.kind == NYS_OP_RBF) {
+    RbfLowp L;
+    NYS_TRY(rbf_lowp_prepare(op, lowp_buf, L, s));
+    return rbf_lowp_kv(L, rbf_gram(prec), static_cast<const float*>(V), ldv, k, mu_dev, k, static_cast<float*>(Z),
+                       ldz, reinterpret_cast<float*>(scr), se, nullptr, s);
+  }
+  if (f32)
     return op_matvec<float>(op, static_cast<const float*>(V), (float)mu, static_cast<float*>(Z),
                             reinterpret_cast<float*>(scr), se, s);
   if (k == 1 && ldv == 1 && ldz == 1 && (op.kind == NYS_OP_XTX || op.kind == NYS_OP_DENSE))
     return op_matvec<double>(op, static_cast<const double*>(V), mu, static_cast<double*>(Z), scr, se, s);
-  NYS_TRY(set_mu(mu_dev, &mu, 1, s));
   return op_apply_f64(op, static_cast<const double*>(V), k, ldv, mu_dev, k, static_cast<double*>(Z), ldz,
                       scr, se, s);
 }

@@ -50,7 +50,7 @@ __global__ void sumsq_partial(const double* __restrict__ Y, int64_t count,
 }
 
 // nu = spacing of ||Y||_F: for |x| = f 2^e (0.5 <= f < 1), 2^(e - 53).
-__global__ void finalize_nu(const double* __restrict__ part, int np, double* __restrict__ nu) {
+__global__ void finalize_nu(const double* __restrict__ part, int np, double u_rel, double* __restrict__ nu) {
   __shared__ double sh[16];
   double s = 0.0;
   for (int i = threadIdx.x; i < np; i += blockDim.x) s += part[i];
@@ -59,7 +59,8 @@ __global__ void finalize_nu(const double* __restrict__ part, int np, double* __r
     const double nrm = sqrt(s);
     int e = 0;
     frexp(nrm, &e);
-    nu[0] = (nrm > 0.0) ? ldexp(1.0, e - 53) : 4.9406564584124654e-324;
+    const double eps_nrm = (nrm > 0.0) ? ldexp(1.0, e - 53) : 4.9406564584124654e-324;
+    nu[0] = fmax(eps_nrm, u_rel * nrm);
   }
 }
 
@@ -569,11 +570,11 @@ __global__ void eig_finalize(const double* __restrict__ ev, const double* __rest
 
 }  // namespace
 
-nys_status frob_shift(const double* Y, int64_t count, double* part, double* nu, hipStream_t s) {
+nys_status frob_shift(const double* Y, int64_t count, double* part, double* nu, double u_rel, hipStream_t s) {
   const int nb = 1024;
   hipLaunchKernelGGL(sumsq_partial, dim3(nb), dim3(256), 0, s, Y, count, part);
   NYS_CHECK_LAUNCH();
-  hipLaunchKernelGGL(finalize_nu, dim3(1), dim3(256), 0, s, part, nb, nu);
+  hipLaunchKernelGGL(finalize_nu, dim3(1), dim3(256), 0, s, part, nb, u_rel, nu);
   NYS_CHECK_LAUNCH();
   return NYS_OK;
 }

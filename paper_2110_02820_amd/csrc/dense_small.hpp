@@ -3,8 +3,9 @@
 
 namespace nys {
 
-// nu <- eps(||Y||_F) for `count` contiguous entries; `part` holds frob_partials() doubles.
-nys_status frob_shift(const double* Y, int64_t count, double* part, double* nu, hipStream_t s);
+// nu <- max(eps(||Y||_F), u_rel ||Y||_F) for `count` contiguous entries;
+// `part` holds frob_partials() doubles.
+nys_status frob_shift(const double* Y, int64_t count, double* part, double* nu, double u_rel, hipStream_t s);
 size_t frob_partials();
 // Y += factor * nu * Omega  (nu read on the device)
 nys_status add_shift(double* Y, const double* Om, int64_t count, const double* nu, double factor,

@@ -16,6 +16,7 @@
 //               (the sketch A Omega, block PCG).
 #include "operators.hpp"
 #include "gemm.hpp"
+#include "rbf_lowp.hpp"
 
 namespace nys {
 
@@ -655,11 +656,13 @@ nys_status op_matvec_partials<double>(const OpDesc& op, const double* p, double*
 template <>
 nys_status op_matvec_partials<float>(const OpDesc& op, const float* p, float* part, size_t part_elems,
                                      int* ng_out, hipStream_t s) {
+  if (op.kind == NYS_OP_RBF && op.lowp)
+    return rbf_lowp_mv_partials(*op.lowp, op.gram, p, part, part_elems, ng_out, op.skip, s);
   if (op.kind == NYS_OP_XTX) {
     if (op.dtype == NYS_F64) return xtx_partials_t<double, float>(op, p, part, part_elems, ng_out, s);
     return xtx_partials_t<float, float>(op, p, part, part_elems, ng_out, s);
   }
-  set_error("op_matvec_partials: float32 form available for X^T X only");
+  set_error("op_matvec_partials: float32 form needs X^T X or a prepared RBF operator");
   return NYS_ERR_ARG;
 }
 

@@ -3,6 +3,8 @@
 
 namespace nys {
 
+struct RbfLowp;
+
 // Validated copy of a nys_operator.
 struct OpDesc {
   int kind;
@@ -12,6 +14,8 @@ struct OpDesc {
   int64_t rows, cols, ld;
   double sigma, scale;
   const int* skip = nullptr;  // device flag: kernels return at once when *skip != 0
+  const RbfLowp* lowp = nullptr;  // prepared points for reduced-precision RBF products
+  int gram = 0;                   // RBF_GRAM_BF16X3 or RBF_GRAM_F32 (with lowp)
 };
 
 // Scratch (in elements of the arithmetic type) used by one operator product

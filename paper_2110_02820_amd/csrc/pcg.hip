@@ -531,7 +531,21 @@ nys_status uc_launch(const PrecDesc& P, const double* Cs, const void* R, void* Z
   return NYS_OK;
 }
 
-// Block apply Z = R + U (f .* (U^T R)) through the MFMA GEMM (float64 vectors).
+// Block apply Z = R + U (f .* (U^T R)) through the MFMA GEMM.  float64
+// vectors take U in either precision; float32 vectors need a float32 U.
+template <typename T>
+__global__ void apply_scale_blk_t(int64_t l, int64_t k, const T* __restrict__ C, const double* __restrict__ lam,
+                                  const double* __restrict__ mu, int64_t nrhs, T* __restrict__ Cs,
+                                  const int* __restrict__ done, const int* __restrict__ alldone) {
+  if (alldone && *alldone) return;
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= l * k) return;
+  const int64_t j = idx / k, c = idx % k;
+  const double m = mu[c / nrhs];
+  const double f = (lam[l - 1] + m) / (lam[j] + m) - 1.0;
+  Cs[idx] = (done && done[c]) ? T(0) : T(f * double(C[idx]));
+}
+
 nys_status apply_block(const PrecDesc& P, const double* mu_dev, int64_t nrhs, const double* R, double* Z,
                        int64_t k, const int* done, const int* alldone, double* part, size_t part_elems,
                        double* C, double* Cs, hipStream_t s) {
@@ -555,6 +569,40 @@ nys_status apply_block(const PrecDesc& P, const double* mu_dev, int64_t nrhs, co
     NYS_TRY((gemm<double, float, double>(false, false, n, k, l, 1.0, static_cast<const float*>(P.U), P.ldu,
                                          Cs, k, 1.0, Z, k, part, part_elems, s, alldone)));
   return NYS_OK;
+}
+
+nys_status apply_block_f32(const PrecDesc& P, const double* mu_dev, int64_t nrhs, const float* R, float* Z,
+                           int64_t k, const int* done, const int* alldone, double* part, size_t part_elems,
+                           double* Cbuf, double* Csbuf, hipStream_t s) {
+  const int64_t n = P.n, l = P.ell;
+  if (P.dtype != NYS_F32) {
+    set_error("float32 block preconditioner apply needs a float32 U");
+    return NYS_ERR_ARG;
+  }
+  const float* U = static_cast<const float*>(P.U);
+  float* C = reinterpret_cast<float*>(Cbuf);
+  float* Cs = reinterpret_cast<float*>(Csbuf);
+  float* fpart = reinterpret_cast<float*>(part);
+  NYS_TRY((gemm<float, float, float>(true, false, l, k, n, 1.0f, U, P.ldu, R, k, 0.0f, C, k, fpart, part_elems, s,
+                                     alldone)));
+  hipLaunchKernelGGL(apply_scale_blk_t<float>, dim3((unsigned)cdiv(l * k, 256)), dim3(256), 0, s, l, k, C, P.lam,
+                     mu_dev, nrhs, Cs, done, alldone);
+  NYS_CHECK_LAUNCH();
+  hipLaunchKernelGGL(copy_vec<float>, dim3((unsigned)cdiv(n * k, 256)), dim3(256), 0, s, n * k, R, Z, alldone);
+  NYS_CHECK_LAUNCH();
+  NYS_TRY((gemm<float, float, float>(false, false, n, k, l, 1.0f, U, P.ldu, Cs, k, 1.0f, Z, k, fpart, part_elems, s,
+                                     alldone)));
+  return NYS_OK;
+}
+
+template <typename T>
+nys_status apply_block_t(const PrecDesc& P, const double* mu_dev, int64_t nrhs, const T* R, T* Z, int64_t k,
+                         const int* done, const int* alldone, PcgWork& w, hipStream_t s) {
+  if (sizeof(T) == 8)
+    return apply_block(P, mu_dev, nrhs, reinterpret_cast<const double*>(R), reinterpret_cast<double*>(Z), k, done,
+                       alldone, w.apart, w.apart_elems, w.Ct, w.Cs, s);
+  return apply_block_f32(P, mu_dev, nrhs, reinterpret_cast<const float*>(R), reinterpret_cast<float*>(Z), k, done,
+                         alldone, w.apart, w.apart_elems, w.Ct, w.Cs, s);
 }
 
 }  // namespace
@@ -594,12 +642,7 @@ nys_status pcg_setup(int64_t n, int64_t k, const PrecDesc& P, const double* mu_d
     NYS_TRY(utr_launch(P, mu_dev, R, f32, w.apart, w.Cs, sc.ctr + 1, nullptr, s));
     NYS_TRY(uc_launch(P, w.Cs, R, Z, f32, w.prz, sc, 0, 1, s));
   } else {
-    if (f32) {
-      set_error("float32 block preconditioner apply is not available; use k = 1 or float64");
-      return NYS_ERR_ARG;
-    }
-    NYS_TRY(apply_block(P, mu_dev, nrhs, reinterpret_cast<const double*>(R), reinterpret_cast<double*>(Z), k,
-                        nullptr, nullptr, w.apart, w.apart_elems, w.Ct, w.Cs, s));
+    NYS_TRY(apply_block_t<T>(P, mu_dev, nrhs, R, Z, k, nullptr, nullptr, w, s));
     hipLaunchKernelGGL(cg_rz<T>, dim3((unsigned)ng), dim3(NT), 0, s, n, k, R, Z, w.prz, rpw, sc, 0, 1);
     NYS_CHECK_LAUNCH();
   }
@@ -624,12 +667,7 @@ nys_status pcg_iteration(int64_t n, int64_t k, const PrecDesc& P, const double* 
     NYS_TRY(utr_launch(P, mu_dev, R, f32, w.apart, w.Cs, sc.ctr + 1, sc.alldone, s));
     NYS_TRY(uc_launch(P, w.Cs, R, Z, f32, w.prz, sc, par, 2, s));
   } else {
-    if (f32) {
-      set_error("float32 block preconditioner apply is not available; use k = 1 or float64");
-      return NYS_ERR_ARG;
-    }
-    NYS_TRY(apply_block(P, mu_dev, nrhs, reinterpret_cast<const double*>(R), reinterpret_cast<double*>(Z), k,
-                        sc.done, sc.alldone, w.apart, w.apart_elems, w.Ct, w.Cs, s));
+    NYS_TRY(apply_block_t<T>(P, mu_dev, nrhs, R, Z, k, sc.done, sc.alldone, w, s));
     hipLaunchKernelGGL(cg_rz<T>, dim3((unsigned)ng), dim3(NT), 0, s, n, k, R, Z, w.prz, rpw, sc, par, 0);
     NYS_CHECK_LAUNCH();
   }

@@ -1,0 +1,387 @@
+// Reduced-precision Gaussian-kernel products on MFMA (gfx950).
+//
+// K_ij = exp(-||x_i - x_j||^2 / (2 sigma^2)) is evaluated tile by tile and
+// never stored (kernel ridge regression operator).  The Gram entries x_i^T x_j
+// come from MFMA in one of two modes:
+//   * BF16X3: each coordinate is split into bf16 hi + lo parts (round to
+//     nearest even) and x^T y ~ hi.hi + hi.lo + lo.hi, three
+//     v_mfma_f32_16x16x32_bf16 per 16 x 16 tile, float32 accumulation;
+//   * F32:    v_mfma_f32_16x16x4f32 on the float32 coordinates.
+// With s = log2(e) / (2 sigma^2) and h_i = s ||x_i||^2, the exponent is
+// log2 K_ij = 2 s x_i^T x_j - h_i - h_j.  The row term is folded into the
+// MFMA accumulator input (C = -h_i / (2 s)), so each kernel entry costs one
+// FMA, one v_exp_f32 and one FMA with the vector.  Coordinates are padded to
+// 32 (one bf16 MFMA step, eight f32 steps); rows are padded to a multiple of
+// 256 with zeros, so operand loads never leave the prepared arrays.
+#include "rbf_lowp.hpp"
+
+namespace nys {
+
+namespace {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ unsigned short bf16_rne(float x) {
+  unsigned u = __float_as_uint(x);
+  if ((u & 0x7f800000u) == 0x7f800000u) return (unsigned short)(u >> 16);  // inf / nan
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (unsigned short)(u >> 16);
+}
+__device__ __forceinline__ float bf16_to_f(unsigned short h) { return __uint_as_float((unsigned)h << 16); }
+
+// Xhi, Xlo: npad x 32 bf16; X32: npad x 32 float; hs[i] = s ||x_i||^2 (float,
+// from the float64 norm of the stored coordinates).  Padding rows are zero.
+template <typename TD>
+__global__ void rbf_prepare(const TD* __restrict__ X, int64_t n, int64_t d, int64_t ld, int64_t npad, double s,
+                            unsigned short* __restrict__ Xhi, unsigned short* __restrict__ Xlo,
+                            float* __restrict__ X32, float* __restrict__ hs) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= npad) return;
+  double nrm = 0.0;
+  for (int k = 0; k < 32; ++k) {
+    const double v = (i < n && k < d) ? double(X[i * ld + k]) : 0.0;
+    nrm += v * v;
+    const float f = (float)v;
+    const unsigned short hi = bf16_rne(f);
+    const unsigned short lo = bf16_rne(f - bf16_to_f(hi));
+    Xhi[i * 32 + k] = hi;
+    Xlo[i * 32 + k] = lo;
+    X32[i * 32 + k] = f;
+  }
+  hs[i] = (float)(s * nrm);
+}
+
+template <int MODE>
+struct Operand;
+
+// BF16X3: lane l holds row (l % 16), coordinates 8 (l / 16) .. + 7
+template <>
+struct Operand<0> {
+  bf8 hi, lo;
+  __device__ __forceinline__ void load(const RbfLowp& L, int64_t row, int lane) {
+    const int64_t off = row * 32 + 8 * (lane >> 4);
+    hi = *reinterpret_cast<const bf8*>(L.Xhi + off);
+    lo = *reinterpret_cast<const bf8*>(L.Xlo + off);
+  }
+};
+// F32: lane l holds row (l % 16), coordinates 4 ks + l / 16 for ks = 0..7
+template <>
+struct Operand<1> {
+  float v[8];
+  __device__ __forceinline__ void load(const RbfLowp& L, int64_t row, int lane) {
+    const float* p = L.X32 + row * 32 + (lane >> 4);
+#pragma unroll
+    for (int ks = 0; ks < 8; ++ks) v[ks] = p[4 * ks];
+  }
+};
+
+// D = A B^T + C for one 16 x 16 tile (rows of a, points of b).
+__device__ __forceinline__ f4 gram_tile(const Operand<0>& a, const Operand<0>& b, f4 c) {
+  f4 d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.hi, b.hi, c, 0, 0, 0);
+  d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.hi, b.lo, d, 0, 0, 0);
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.lo, b.hi, d, 0, 0, 0);
+}
+__device__ __forceinline__ f4 gram_tile(const Operand<1>& a, const Operand<1>& b, f4 c) {
+  f4 d = c;
+#pragma unroll
+  for (int ks = 0; ks < 8; ++ks) d = __builtin_amdgcn_mfma_f32_16x16x4f32(a.v[ks], b.v[ks], d, 0, 0, 0);
+  return d;
+}
+
+// One vector: part[split][i] = sum_{j in split} K_ij p_j.  Block = 4 waves,
+// wave w owns rows rb*256 + w*64 .. + 63 (four 16-row fragments); the lanes
+// of a wave walk the points of the split 16 at a time.  Accumulator element
+// q of lane l belongs to row 4 (l/16) + q of a fragment and column l % 16.
+template <int MODE>
+__global__ __launch_bounds__(256) void rbf_mv_lowp(RbfLowp L, const float* __restrict__ p, float* __restrict__ part,
+                                                   int64_t pts_per_split, const int* __restrict__ skip) {
+  if (skip && *skip) return;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t n = L.n;
+  const int64_t row0 = (int64_t)blockIdx.x * 256 + wave * 64;
+  const float two_s = L.two_s;
+  Operand<MODE> a[4];
+  f4 cinit[4], acc[4];
+#pragma unroll
+  for (int f = 0; f < 4; ++f) {
+    a[f].load(L, row0 + f * 16 + (lane & 15), lane);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      cinit[f][q] = -L.hs[row0 + f * 16 + 4 * (lane >> 4) + q] / two_s;
+      acc[f][q] = 0.0f;
+    }
+  }
+  const int64_t j0 = (int64_t)blockIdx.y * pts_per_split;
+  int64_t j1 = j0 + pts_per_split;
+  if (j1 > n) j1 = n;
+  for (int64_t jt = j0; jt < j1; jt += 16) {
+    const int64_t j = jt + (lane & 15);
+    Operand<MODE> b;
+    b.load(L, j, lane);  // rows beyond n are zero padding
+    const float hj = L.hs[j];
+    const float pj = (j < j1) ? p[j] : 0.0f;
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+      const f4 dg = gram_tile(a[f], b, cinit[f]);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const float e = __builtin_amdgcn_exp2f(fmaf(two_s, dg[q], -hj));
+        acc[f][q] = fmaf(e, pj, acc[f][q]);
+      }
+    }
+  }
+  // sum over the 16 columns held by lanes with the same l / 16
+#pragma unroll
+  for (int f = 0; f < 4; ++f)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      float v = acc[f][q];
+      v += __shfl_xor(v, 1, 64);
+      v += __shfl_xor(v, 2, 64);
+      v += __shfl_xor(v, 4, 64);
+      v += __shfl_xor(v, 8, 64);
+      const int64_t row = row0 + f * 16 + 4 * (lane >> 4) + q;
+      if ((lane & 15) == 0 && row < n) part[(int64_t)blockIdx.y * n + row] = v;
+    }
+}
+
+// Block of columns: V[I, cb*64 .. +63] = scale * K_IJ P_J (+ mu_c P) over all J,
+// float32.  Block = 4 waves, 64 rows x 64 output columns; per point tile of
+// 32: stage 1 forms K (64 x 32, wave w rows w*16..) with the Gram MFMA and
+// exp, splits it into bf16 hi/lo in LDS; stage 2 multiplies K (hi/lo) by the
+// P tile (hi/lo, staged transposed in LDS) with three bf16 MFMAs per tile.
+template <int MODE>
+struct KvStage2;
+
+// BF16X3 second stage: K and P split into bf16 hi/lo in LDS, three bf16 MFMAs
+template <>
+struct KvStage2<0> {
+  unsigned short Khi[64][40], Klo[64][40];  // [row][point]
+  unsigned short Phi[64][40], Plo[64][40];  // [col][point]
+  __device__ __forceinline__ void put_p(int pt, int cc, float v) {
+    const unsigned short hi = bf16_rne(v);
+    Phi[cc][pt] = hi;
+    Plo[cc][pt] = bf16_rne(v - bf16_to_f(hi));
+  }
+  __device__ __forceinline__ void put_k(int r, int pc, float e) {
+    const unsigned short hi = bf16_rne(e);
+    Khi[r][pc] = hi;
+    Klo[r][pc] = bf16_rne(e - bf16_to_f(hi));
+  }
+  __device__ __forceinline__ void mac(int wave, int lane, f4 acc[4]) {
+    const int r = wave * 16 + (lane & 15);
+    const bf8 khi = *reinterpret_cast<const bf8*>(&Khi[r][8 * (lane >> 4)]);
+    const bf8 klo = *reinterpret_cast<const bf8*>(&Klo[r][8 * (lane >> 4)]);
+#pragma unroll
+    for (int cf = 0; cf < 4; ++cf) {
+      const int cc = cf * 16 + (lane & 15);
+      const bf8 phi = *reinterpret_cast<const bf8*>(&Phi[cc][8 * (lane >> 4)]);
+      const bf8 plo = *reinterpret_cast<const bf8*>(&Plo[cc][8 * (lane >> 4)]);
+      acc[cf] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(khi, phi, acc[cf], 0, 0, 0);
+      acc[cf] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(khi, plo, acc[cf], 0, 0, 0);
+      acc[cf] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(klo, phi, acc[cf], 0, 0, 0);
+    }
+  }
+};
+
+// F32 second stage: K and P as float in LDS, v_mfma_f32_16x16x4f32
+template <>
+struct KvStage2<1> {
+  float Kf[64][33];  // [row][point]
+  float Pf[32][65];  // [point][col]
+  __device__ __forceinline__ void put_p(int pt, int cc, float v) { Pf[pt][cc] = v; }
+  __device__ __forceinline__ void put_k(int r, int pc, float e) { Kf[r][pc] = e; }
+  __device__ __forceinline__ void mac(int wave, int lane, f4 acc[4]) {
+    const int r = wave * 16 + (lane & 15);
+#pragma unroll
+    for (int ks = 0; ks < 8; ++ks) {
+      const float av = Kf[r][4 * ks + (lane >> 4)];
+#pragma unroll
+      for (int cf = 0; cf < 4; ++cf)
+        acc[cf] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, Pf[4 * ks + (lane >> 4)][cf * 16 + (lane & 15)], acc[cf],
+                                                       0, 0, 0);
+    }
+  }
+};
+
+// Block of columns: V[I, cb*64 .. +63] = oscale * K_IJ P_J over the points of
+// split z, float32.  Block = 4 waves, 64 rows x 64 output columns; per point
+// tile of 32: stage 1 forms K (wave w: rows w*16 .. +15) with the Gram MFMA and
+// exp into LDS; stage 2 multiplies K by the P tile staged in LDS.
+template <int MODE>
+__global__ __launch_bounds__(256) void rbf_kv_lowp(RbfLowp L, const float* __restrict__ P, int64_t ldp, int64_t k,
+                                                   float* __restrict__ out, int64_t ldo, int64_t pts_per_split,
+                                                   float oscale, const int* __restrict__ skip) {
+  if (skip && *skip) return;
+  __shared__ __attribute__((aligned(16))) KvStage2<MODE> st;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int64_t n = L.n;
+  const int64_t i0 = (int64_t)blockIdx.x * 64;
+  const int64_t c0 = (int64_t)blockIdx.y * 64;
+  const float two_s = L.two_s;
+  Operand<MODE> a;
+  a.load(L, i0 + wave * 16 + (lane & 15), lane);
+  f4 cinit;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) cinit[q] = -L.hs[i0 + wave * 16 + 4 * (lane >> 4) + q] / two_s;
+  f4 acc[4];
+#pragma unroll
+  for (int cf = 0; cf < 4; ++cf) acc[cf] = f4{0, 0, 0, 0};
+  const int64_t j0 = (int64_t)blockIdx.z * pts_per_split;
+  int64_t j1 = j0 + pts_per_split;
+  if (j1 > n) j1 = n;
+  for (int64_t jt = j0; jt < j1; jt += 32) {
+    __syncthreads();
+    // P tile (32 points x 64 cols)
+    for (int e = t; e < 32 * 64; e += 256) {
+      const int pt = e >> 6, cc = e & 63;
+      const int64_t j = jt + pt, c = c0 + cc;
+      st.put_p(pt, cc, (j < j1 && c < k) ? P[j * ldp + c] : 0.0f);
+    }
+    // stage 1: K rows wave*16 .. +15, points jt .. jt+31 (two 16-point tiles)
+#pragma unroll
+    for (int pf = 0; pf < 2; ++pf) {
+      const int64_t j = jt + pf * 16 + (lane & 15);
+      Operand<MODE> b;
+      b.load(L, j, lane);
+      const float hj = L.hs[j];
+      const f4 dg = gram_tile(a, b, cinit);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const float e = (j < j1) ? __builtin_amdgcn_exp2f(fmaf(two_s, dg[q], -hj)) : 0.0f;
+        st.put_k(wave * 16 + 4 * (lane >> 4) + q, pf * 16 + (lane & 15), e);
+      }
+    }
+    __syncthreads();
+    st.mac(wave, lane, acc);
+  }
+  float* o = out + (int64_t)blockIdx.z * n * ldo;
+#pragma unroll
+  for (int cf = 0; cf < 4; ++cf)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int64_t row = i0 + wave * 16 + 4 * (lane >> 4) + q;
+      const int64_t col = c0 + cf * 16 + (lane & 15);
+      if (row < n && col < k) o[row * ldo + col] = oscale * acc[cf][q];
+    }
+}
+
+// V = scale * sum_z part[z] + mu_c P  (n x k float), fixed order over z
+__global__ void rbf_lowp_finish(const float* __restrict__ part, int nz, int64_t n, int64_t k, float scale,
+                                const float* __restrict__ P, int64_t ldp, const double* __restrict__ mu,
+                                int64_t nrhs, float* __restrict__ V, int64_t ldv, const int* __restrict__ skip) {
+  if (skip && *skip) return;
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= n * k) return;
+  const int64_t i = idx / k, c = idx % k;
+  float s = 0.0f;
+  for (int z = 0; z < nz; ++z) s += part[((int64_t)z * n + i) * k + c];
+  s *= scale;
+  if (mu) s += float(mu[c / nrhs]) * P[i * ldp + c];
+  V[i * ldv + c] = s;
+}
+
+}  // namespace
+
+size_t rbf_lowp_bytes(int64_t n) {
+  const int64_t npad = cdiv(n, 256) * 256;
+  return (size_t)npad * 32 * (2 + 2 + 4) + (size_t)npad * 4 + 1024;
+}
+
+nys_status rbf_lowp_prepare(const OpDesc& op, void* buf, RbfLowp& L, hipStream_t s) {
+  const int64_t n = op.n, d = op.cols;
+  if (d > 32) {
+    set_error("reduced-precision RBF path supports d <= 32 (got %lld)", (long long)d);
+    return NYS_ERR_ARG;
+  }
+  const int64_t npad = cdiv(n, 256) * 256;
+  char* b = static_cast<char*>(buf);
+  L.n = n;
+  L.npad = npad;
+  L.Xhi = reinterpret_cast<unsigned short*>(b);
+  L.Xlo = L.Xhi + npad * 32;
+  L.X32 = reinterpret_cast<float*>(L.Xlo + npad * 32);
+  L.hs = L.X32 + npad * 32;
+  const double sc = 1.4426950408889634 / (2.0 * op.sigma * op.sigma);  // log2(e) / (2 sigma^2)
+  L.two_s = (float)(2.0 * sc);
+  L.scale = (float)op.scale;
+  if (op.dtype == NYS_F64)
+    hipLaunchKernelGGL(rbf_prepare<double>, dim3((unsigned)cdiv(npad, 256)), dim3(256), 0, s,
+                       static_cast<const double*>(op.data), n, d, op.ld, npad, sc, L.Xhi, L.Xlo, L.X32, L.hs);
+  else
+    hipLaunchKernelGGL(rbf_prepare<float>, dim3((unsigned)cdiv(npad, 256)), dim3(256), 0, s,
+                       static_cast<const float*>(op.data), n, d, op.ld, npad, sc, L.Xhi, L.Xlo, L.X32, L.hs);
+  NYS_CHECK_LAUNCH();
+  return NYS_OK;
+}
+
+nys_status rbf_lowp_mv_partials(const RbfLowp& L, int mode, const float* p, float* part, size_t part_elems,
+                                int* ng_out, const int* skip, hipStream_t s) {
+  const int64_t n = L.n;
+  const int64_t nrb = cdiv(n, 256);
+  const int cus = num_cus() < 256 ? num_cus() : 256;
+  int64_t ns = cdiv(4 * cus, nrb);
+  if (ns < 1) ns = 1;
+  while (ns > 1 && (size_t)(ns * n) > part_elems) --ns;
+  const int64_t pps = cdiv(cdiv(n, ns), 16) * 16;
+  ns = cdiv(n, pps);
+  dim3 grid((unsigned)nrb, (unsigned)ns);
+  if (mode == 0)
+    hipLaunchKernelGGL(rbf_mv_lowp<0>, grid, dim3(256), 0, s, L, p, part, pps, skip);
+  else
+    hipLaunchKernelGGL(rbf_mv_lowp<1>, grid, dim3(256), 0, s, L, p, part, pps, skip);
+  NYS_CHECK_LAUNCH();
+  *ng_out = (int)ns;
+  return NYS_OK;
+}
+
+size_t rbf_lowp_kv_scratch(int64_t n, int64_t k) {
+  const int64_t tiles = cdiv(n, 64) * cdiv(k, 64);
+  const int64_t nz = cdiv(2 * 256, tiles);
+  return nz > 1 ? (size_t)nz * (size_t)n * (size_t)k : 0;
+}
+
+// V += mu_c P
+__global__ void rbf_lowp_add_mu(int64_t n, int64_t k, const float* __restrict__ P, int64_t ldp,
+                                const double* __restrict__ mu, int64_t nrhs, float* __restrict__ V, int64_t ldv,
+                                const int* __restrict__ skip) {
+  if (skip && *skip) return;
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= n * k) return;
+  const int64_t i = idx / k, c = idx % k;
+  V[i * ldv + c] += float(mu[c / nrhs]) * P[i * ldp + c];
+}
+
+nys_status rbf_lowp_kv(const RbfLowp& L, int mode, const float* P, int64_t ldp, int64_t k, const double* mu_dev,
+                       int64_t nrhs, float* V, int64_t ldv, float* scratch, size_t scratch_elems, const int* skip,
+                       hipStream_t s) {
+  const int64_t n = L.n;
+  const int64_t tiles = cdiv(n, 64) * cdiv(k, 64);
+  int64_t nz = cdiv(2 * (num_cus() < 256 ? num_cus() : 256), tiles);
+  if (nz < 1) nz = 1;
+  while (nz > 1 && (size_t)(nz * n * k) > scratch_elems) --nz;
+  const int64_t pps = cdiv(cdiv(n, nz), 32) * 32;
+  nz = cdiv(n, pps);
+  dim3 grid((unsigned)cdiv(n, 64), (unsigned)cdiv(k, 64), (unsigned)nz);
+  float* dst = nz > 1 ? scratch : V;
+  const int64_t ldo = nz > 1 ? k : ldv;
+  const float oscale = nz > 1 ? 1.0f : L.scale;
+  if (mode == 0)
+    hipLaunchKernelGGL(rbf_kv_lowp<0>, grid, dim3(256), 0, s, L, P, ldp, k, dst, ldo, pps, oscale, skip);
+  else
+    hipLaunchKernelGGL(rbf_kv_lowp<1>, grid, dim3(256), 0, s, L, P, ldp, k, dst, ldo, pps, oscale, skip);
+  NYS_CHECK_LAUNCH();
+  if (nz > 1) {
+    hipLaunchKernelGGL(rbf_lowp_finish, dim3((unsigned)cdiv(n * k, 256)), dim3(256), 0, s, scratch, (int)nz, n, k,
+                       L.scale, P, ldp, mu_dev, nrhs, V, ldv, skip);
+    NYS_CHECK_LAUNCH();
+  } else if (mu_dev) {
+    hipLaunchKernelGGL(rbf_lowp_add_mu, dim3((unsigned)cdiv(n * k, 256)), dim3(256), 0, s, n, k, P, ldp, mu_dev, nrhs,
+                       V, ldv, skip);
+    NYS_CHECK_LAUNCH();
+  }
+  return NYS_OK;
+}
+
+}  // namespace nys

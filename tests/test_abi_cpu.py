@@ -68,7 +68,7 @@ def test_argument_errors_before_device_use(L):
     assert L.nys_gaussian(1, 0, 5, 1, 5, None) == nys.NYS_ERR_ARG
     # preconditioner with ell > n
     P = nys._Precond(10, 11, 1, 11, 0, 0, 1, 0.0)
-    assert L.nys_factor(1, 1, ctypes.byref(P), 1, 1 << 20, None) == nys.NYS_ERR_ARG
+    assert L.nys_factor(1, 1, ctypes.byref(P), 0, 1, 1 << 20, None) == nys.NYS_ERR_ARG
     # more than 256 simultaneous columns
     P = nys._Precond(100, 10, 1, 10, 0, 0, 1, 0.0)
     mu = (ctypes.c_double * 300)(*([1.0] * 300))

@@ -212,7 +212,7 @@ def test_pcg_xtx_refinement_small():
     b = X.astype(np.float64).T @ w["y"]
     op = nys.Operator.xtx(t32(X))
     Om, Y = nys.nys_sketch(op, 100, omega0=t64(w["omega0"]), prec=nys.NYS_PREC_FP32_REFINE64)
-    P = nys.nys_factor(Om, Y, dtype=torch.float32)
+    P = nys.nys_factor(Om, Y, dtype=torch.float32, prec=nys.NYS_PREC_FP32_REFINE64)
     x, info = nys.nys_pcg_solve(op, P, w["mu"], t64(b), tol=1e-10, maxit=500, prec=nys.NYS_PREC_FP32_REFINE64)
     assert info.status[0] == 0 and info.refine_steps >= 1
     assert oracle.true_relres(op_ref, w["mu"], h(x), b) <= 1e-10
@@ -230,7 +230,7 @@ def test_pcg_fp32_only_path():
     b = X.astype(np.float64).T @ w["y"]
     op = nys.Operator.xtx(t32(X))
     P = nys.nys_factor(*nys.nys_sketch(op, 80, omega0=t64(w["omega0"]), prec=nys.NYS_PREC_FP32),
-                       dtype=torch.float32)
+                       dtype=torch.float32, prec=nys.NYS_PREC_FP32)
     x, info = nys.nys_pcg_solve(op, P, w["mu"], t64(b), tol=1e-5, maxit=500, prec=nys.NYS_PREC_FP32)
     assert oracle.true_relres(oracle.XtXOp(X), w["mu"], h(x), b) <= 1e-5
 
@@ -316,3 +316,83 @@ def test_error_paths_on_device():
     with pytest.raises(nys.NysError) as e:
         nys.nys_sketch(op, 20, omega0=t64(np.zeros((200, 20))))
     assert e.value.status == nys.NYS_ERR_NOT_PSD
+
+
+# ---------------------------------------------------------------- reduced-precision RBF
+
+def _mixture_case(n, d, ell, seed):
+    from workloads import krr_mixture
+    w = krr_mixture(n=n, d=d, ell=ell, seed=seed)
+    op_ref = oracle.RBFOp(w["X"], w["sigma"])
+    b = op_ref.matmat(w["w"]) + w["noise"] * w["eps"]
+    return w, op_ref, b
+
+
+@pytest.mark.parametrize("prec,tol", [(1, 2e-5), (3, 2e-4)])
+@pytest.mark.parametrize("k", [1, 5, 70])
+def test_rbf_lowp_products(prec, tol, k):
+    """float32 Gram (prec 1) and bf16x3 Gram (prec 3) against the float64 oracle.
+    Bounds: float32 exp and accumulation over ~1e3 terms (~1e-6 .. 1e-5);
+    bf16x3 keeps ~16 bits of each coordinate (~1e-4)."""
+    w, op_ref, _ = _mixture_case(1111, 32, 10, 40 + k)
+    op = nys.Operator.rbf(t32(w["X"]), w["sigma"])
+    V = np.random.default_rng(k).standard_normal((1111, k))
+    out = h(nys.nys_op_apply(op, 0.25, t32(V), prec=prec))
+    ref = op_ref.matmat(V) + 0.25 * V
+    assert rel(out, ref) < tol
+
+
+@pytest.mark.parametrize("d", [3, 16])
+def test_rbf_lowp_small_dims(d):
+    rng = np.random.default_rng(60 + d)
+    X = rng.standard_normal((517, d)).astype(np.float32)
+    op = nys.Operator.rbf(t32(X), 1.7)
+    v = rng.standard_normal(517)
+    ref = oracle.RBFOp(X, 1.7).matmat(v)
+    assert rel(h(nys.nys_op_apply(op, 0.0, t32(v), prec=3)), ref) < 2e-4
+    assert rel(h(nys.nys_op_apply(op, 0.0, t32(v), prec=1)), ref) < 2e-5
+
+
+@pytest.mark.parametrize("prec", [2, 3])
+def test_rbf_mixed_precision_solve_reaches_fp64_tolerance(prec):
+    """Reduced-precision inner PCG + float64 refinement: true float64 relative
+    residual <= 1e-10 (the precision form is judged by the float64 oracle)."""
+    n = 3000
+    w, op_ref, b = _mixture_case(n, 32, 200, 41)
+    mu = 1e-6 * n
+    op = nys.Operator.rbf(t32(w["X"]), w["sigma"])
+    Om, Y = nys.nys_sketch(op, 200, omega0=t64(w["omega0"]), prec=prec)
+    P = nys.nys_factor(Om, Y, dtype=torch.float32, prec=prec)
+    x, info = nys.nys_pcg_solve(op, P, mu, t64(b), tol=1e-10, maxit=2000, prec=prec, max_refine=20,
+                                inner_tol=1e-3)
+    assert info.status[0] == 0, info
+    assert oracle.true_relres(op_ref, mu, h(x), b) <= 1e-10
+    xs = oracle.dense_solve(op_ref.dense(), mu, b)
+    assert rel(h(x), xs) < 1e-6
+
+
+def test_rbf_lowp_sketch_close_to_oracle():
+    w, op_ref, _ = _mixture_case(1500, 32, 64, 42)
+    op = nys.Operator.rbf(t32(w["X"]), w["sigma"])
+    for prec, tol in ((1, 1e-5), (3, 1e-3)):
+        Om, Y = nys.nys_sketch(op, 64, omega0=t64(w["omega0"]), prec=prec)
+        Om, Y = h(Om), h(Y)
+        Q = oracle.orthonormalize(w["omega0"])
+        assert rel(Y @ Om.T, op_ref.matmat(Q) @ Q.T) < tol
+
+
+def test_rbf_block_mu_grid_float_refine():
+    """mu grid x right-hand sides in one block solve with float32 block products."""
+    n = 1200
+    w, op_ref, b = _mixture_case(n, 16, 100, 43)
+    B = np.stack([b, np.random.default_rng(44).standard_normal(n)], axis=1)
+    mus = [1e-3 * n, 1e-5 * n]
+    op = nys.Operator.rbf(t32(w["X"]), w["sigma"])
+    Om, Y = nys.nys_sketch(op, 100, omega0=t64(w["omega0"]), prec=2)
+    P = nys.nys_factor(Om, Y, dtype=torch.float32, prec=2)
+    X, info = nys.nys_pcg_solve(op, P, mus, t64(B), tol=1e-10, maxit=3000, prec=2, max_refine=20,
+                                inner_tol=1e-3)
+    X = h(X)
+    for m, mu in enumerate(mus):
+        for r in range(2):
+            assert oracle.true_relres(op_ref, mu, X[:, m * 2 + r], B[:, r]) <= 1e-10
