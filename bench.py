@@ -1,14 +1,20 @@
 """Benchmark: Nystrom PCG solves/s on one MI355X at a true float64 relative
-residual of 1e-10, chosen form (float32 inner PCG + float64 refinement) next
-to the plain float64 GPU path, plus the roofline of the dominant kernel (the
-one-pass X^T X matvec) and the CPU oracle as a baseline.
+residual of 1e-10 for the chosen form next to the plain float64 GPU path,
+with the roofline of the dominant kernel and the CPU oracle as a baseline.
 
-Workload (default): dense ridge regression, X = G diag(j^-1/2) in float32
-(20000 x 4000, G ~ N(0, 1/20000)), A = X^T X, b = X^T y, mu = 1e-4, l = 500.
-One step = one whole solve: Gaussian test matrix, sketch Y = A Omega, shifted
-Cholesky + SVD factorisation, and PCG with refinement to 1e-10.
+Default workload ("ridge"): dense ridge regression, X = G diag(j^-1/2) stored
+in float32 (20000 x 4000, G ~ N(0, 1/20000)), A = X^T X, b = X^T y, mu = 1e-4,
+l = 500; chosen form = float32 inner PCG + float64 residual refinement.  One
+step = one whole solve: Gaussian test matrix, sketch Y = A Omega, shifted
+Cholesky + SVD factorisation, PCG to 1e-10.
 
-python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-plain] [--no-cpu-baseline]
+Other workloads (--workload): krr_small (n = 2048, d = 8, l = 100, float64),
+krr (n = 1e5, d = 32, l = 1000, bf16x3 Gram tiles + refinement), batched
+(one RBF sketch, 32 mu x 8 right-hand sides, plus 64 ragged ridge problems),
+diff (validation-loss gradient through the RBF solve).
+
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+                [--no-plain] [--no-cpu-baseline]
 """
 from __future__ import annotations
 
@@ -25,6 +31,12 @@ sys.path.insert(0, ROOT)
 
 METRIC = "PCG solves/s + matvec %roofline at rel-res 1e-10, chosen vs plain FP64 GPU"
 HBM_PEAK_GBS = 8000.0
+# v_exp_f32 issue rate: 256 CUs x 4 SIMDs x 4 lanes/clk (quarter rate) x 2.4 GHz
+EXP_PEAK_GPS = 256 * 4 * 4 * 2.4
+
+
+def log(msg):
+    print("# " + msg, file=sys.stderr, flush=True)
 
 
 def parse():
@@ -32,13 +44,403 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--m", type=int, default=20000)
-    ap.add_argument("--n", type=int, default=4000)
-    ap.add_argument("--ell", type=int, default=500)
+    ap.add_argument("--workload", default="ridge",
+                    choices=["ridge", "krr_small", "krr", "batched", "diff"])
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--matvec-reps", type=int, default=30)
+    ap.add_argument("--n", type=int, default=0, help="override the system size (reduced runs)")
+    ap.add_argument("--kernel-only", action="store_true",
+                    help="ridge: only the X^T X product (and a 256 MiB device copy as the counter "
+                         "calibration), for hardware-counter runs")
     return ap.parse_args()
+
+
+class Timer:
+    def __init__(self, torch):
+        self.torch = torch
+        self.t = {}
+
+    def lap(self, key, t0):
+        self.torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        self.t[key] = self.t.get(key, 0.0) + (t1 - t0)
+        return t1
+
+
+def full_solve(nys, torch, op, ell, seed, prec, udtype, mus, B, ws, tol, timer, **kw):
+    t = time.perf_counter()
+    Om, Y = nys.nys_sketch(op, ell, seed=seed, prec=prec, ws=ws)
+    t = timer.lap("sketch", t)
+    P = nys.nys_factor(Om, Y, dtype=udtype, ws=ws, prec=prec)
+    del Om, Y
+    t = timer.lap("factor", t)
+    X, info = nys.nys_pcg_solve(op, P, mus, B, tol=tol, prec=prec, ws=ws, **kw)
+    timer.lap("pcg", t)
+    return X, info, P
+
+
+def kernel_avg_ms(torch, fn, reps):
+    for _ in range(2):
+        fn()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def cores_used():
+    try:
+        from threadpoolctl import threadpool_info
+        return max([i.get("num_threads", 0) for i in threadpool_info()] + [1])
+    except Exception:  # pragma: no cover
+        return os.cpu_count()
+
+
+def base_record(args, value, ms, dtype, config, extra):
+    out = {"metric": METRIC, "value": value, "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": dtype, "data": "synthetic", "config": config}
+    out.update(extra)
+    return out
+
+
+# --------------------------------------------------------------------------- ridge (default)
+
+def run_ridge(args, nys, torch):
+    from workloads import ridge_dense
+    dev = "cuda:0"
+    m, n, ell = 20000, (args.n or 4000), 500
+    w = ridge_dense(m=m, n=n, ell=ell, with_omega=False)
+    X32h = w["X"]
+    b_h = X32h.astype(np.float64).T @ w["y"]  # input synthesis (host, float64)
+    mu, tol = w["mu"], 1e-10
+    X32 = torch.as_tensor(X32h, device=dev)
+    b = torch.as_tensor(b_h, device=dev)
+    op = nys.Operator.xtx(X32)
+    prec = nys.NYS_PREC_FP32_REFINE64
+    ws = nys.workspace(op, ell, 1, prec)
+    kw = dict(maxit=1000, inner_tol=1e-4)
+
+    def timed(opx, precx, wsx, udtype, steps, warmup, label):
+        for i in range(warmup):
+            full_solve(nys, torch, opx, ell, 1000 + i, precx, udtype, mu, b, wsx, tol, Timer(torch), **kw)
+        tm = Timer(torch)
+        infos = []
+        t = time.perf_counter()
+        for i in range(steps):
+            a = time.perf_counter()
+            _, info, _ = full_solve(nys, torch, opx, ell, 20211002 + i, precx, udtype, mu, b, wsx, tol, tm, **kw)
+            infos.append(info)
+            log("%s step %d: %.2f ms, iters %d, refine %d, relres %.2e" %
+                (label, i, 1e3 * (time.perf_counter() - a), info.iters[0], info.refine_steps, info.relres[0]))
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t
+        return el, {k: 1e3 * v / steps for k, v in tm.t.items()}, infos
+
+    el, phases, infos = timed(op, prec, ws, torch.float32, args.steps, args.warmup, "chosen")
+    v32 = torch.randn(n, dtype=torch.float32, device=dev)
+    wsm = nys.workspace(op, 1, 1, nys.NYS_PREC_FP64)
+    mv_ms = kernel_avg_ms(torch, lambda: nys.nys_op_apply(op, mu, v32, ws=wsm), args.matvec_reps)
+    alg_bytes = m * n * 4 + 2 * n * 4  # X once + p in + v out
+    achieved = alg_bytes / (mv_ms * 1e-3) / 1e9
+    out = base_record(
+        args, args.steps / el, 1e3 * el / args.steps, "f32+f64",
+        {"workload": "ridge regression A = X^T X, X %dx%d float32 = G diag(j^-1/2), mu=1e-4, l=%d, b = X^T y, "
+                     "tol 1e-10 (true float64 residual)" % (m, n, ell),
+         "precision": "float32 inner PCG + float64 residual refinement; float64 core factorisation",
+         "step": "Gaussian Omega + sketch + factor + PCG solve"},
+        {"correct": all(i.relres[0] <= tol and i.status[0] == 0 for i in infos),
+         "relres": max(i.relres[0] for i in infos), "iters": infos[-1].iters[0],
+         "refine_steps": infos[-1].refine_steps, "phase_ms": phases,
+         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                      "kernel": "one X^T X product: xtx_fused<float,float> + reduce_cols",
+                      "avg_ms": mv_ms, "alg_bytes": alg_bytes}})
+    if not args.no_plain:
+        X64 = X32.double()
+        op64 = nys.Operator.xtx(X64)
+        ws64 = nys.workspace(op64, ell, 1, nys.NYS_PREC_FP64)
+        n64 = max(1, min(args.steps, 3))
+        el64, ph64, inf64 = timed(op64, nys.NYS_PREC_FP64, ws64, torch.float64, n64, 1, "plain")
+        out["plain_fp64"] = {"value": n64 / el64, "unit": "solves/s", "ms_per_step": 1e3 * el64 / n64,
+                             "phase_ms": ph64, "iters": inf64[-1].iters[0], "relres": inf64[-1].relres[0],
+                             "correct": all(i.relres[0] <= tol for i in inf64)}
+        out["speedup_vs_plain_fp64"] = out["value"] / out["plain_fp64"]["value"]
+        del X64, op64, ws64
+    if not args.no_cpu_baseline:
+        import oracle
+        from workloads import gaussian_test_matrix
+        opr = oracle.XtXOp(X32h)
+        om0 = gaussian_test_matrix(n, ell, 7)
+        t = time.perf_counter()
+        r = oracle.randomized_nystrom(opr, om0)
+        o = oracle.nystrom_pcg(opr.matmat, b_h, mu, lambda v: oracle.precond_inv_apply(r["U"], r["lam"], mu, v),
+                               tol=tol, maxit=1000)
+        el = time.perf_counter() - t
+        out["cpu_baseline"] = {"value": 1.0 / el, "unit": "solves/s", "cores": cores_used(), "kind": "oracle",
+                               "sample": "one full solve of the same workload (sketch + factor + PCG to 1e-10), "
+                                         "numpy float64", "seconds": el, "iters": o["iters"]}
+    return out
+
+
+def run_ridge_kernel(args, nys, torch):
+    """The dominant kernel alone: float32 (X^T X + mu I) p on the ridge workload, then a
+    plain device copy of 256 MiB whose counter readings calibrate FETCH_SIZE / WRITE_SIZE."""
+    from workloads import ridge_dense
+    dev = "cuda:0"
+    m, n = 20000, (args.n or 4000)
+    w = ridge_dense(m=m, n=n, ell=8, with_omega=False)
+    op = nys.Operator.xtx(torch.as_tensor(w["X"], device=dev))
+    v32 = torch.randn(n, dtype=torch.float32, device=dev)
+    wsm = nys.workspace(op, 1, 1, nys.NYS_PREC_FP64)
+    mv_ms = kernel_avg_ms(torch, lambda: nys.nys_op_apply(op, w["mu"], v32, ws=wsm), args.matvec_reps)
+    src = torch.ones(64 << 20, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    cp_ms = kernel_avg_ms(torch, lambda: dst.copy_(src), 10)
+    return {"kernel": "xtx_fused<float,float> + reduce_cols", "avg_ms": mv_ms, "reps": args.matvec_reps + 2,
+            "alg_bytes": m * n * 4 + 2 * n * 4, "copy_bytes_each_way": src.numel() * 4, "copy_avg_ms": cp_ms,
+            "copy_reps": 12}
+
+
+# --------------------------------------------------------------------------- RBF helpers
+
+def rbf_rhs(nys, torch, op, w, dev):
+    """b = K w + 0.01 eps on the device (float64 product of the stored points)."""
+    wv = torch.as_tensor(w["w"], device=dev)
+    Kw = nys.nys_op_apply(op, 0.0, wv)
+    return Kw + w["noise"] * torch.as_tensor(w["eps"], device=dev)
+
+
+def rbf_cpu_sample(w, ell, nvec=1):
+    """The float64 CPU oracle on a bounded sample of the RBF products: one
+    2048-row block of K (the oracle's own block size) times l columns and
+    times nvec columns.  Returns the extrapolated whole-matrix times
+    (n / 2048 blocks) for the sketch product and for one PCG product."""
+    import oracle
+    opr = oracle.RBFOp(w["X"], w["sigma"])
+    n = opr.n
+    blk = min(2048, n)
+    rng = np.random.default_rng(3)
+    V = rng.standard_normal((n, ell))
+    v = rng.standard_normal((n, nvec))
+    idx = np.arange(blk)
+    t = time.perf_counter()
+    opr.rows(idx) @ V
+    t_sk = (time.perf_counter() - t) * n / blk
+    t = time.perf_counter()
+    opr.rows(idx) @ v
+    t_mv = (time.perf_counter() - t) * n / blk
+    return t_sk, t_mv
+
+
+def run_krr(args, nys, torch, small=False):
+    from workloads import krr_mixture, krr_small
+    dev = "cuda:0"
+    if small:
+        n, d, ell = (args.n or 2048), 8, 100
+        w = krr_small(n=n, d=d, ell=ell)
+        X = torch.as_tensor(w["X"], dtype=torch.float64, device=dev)
+        prec, udtype, label = nys.NYS_PREC_FP64, torch.float64, "f64"
+        mu = w["mu"]
+        kw = dict(maxit=5000, check_every=16)
+    else:
+        n, d, ell = (args.n or 100000), 32, 1000
+        w = krr_mixture(n=n, d=d, ell=ell, with_omega=False)
+        X = torch.as_tensor(w["X"], device=dev)
+        prec, udtype, label = nys.NYS_PREC_BF16X3_REFINE64, torch.float32, "bf16x3+f32+f64"
+        mu = w["mu"]
+        kw = dict(maxit=5000, max_refine=40, inner_tol=1e-2, check_every=16)
+    tol = 1e-10
+    op = nys.Operator.rbf(X, w["sigma"])
+    b = rbf_rhs(nys, torch, op, w, dev)
+    ws = nys.workspace(op, ell, 1, prec)
+    for i in range(args.warmup):
+        full_solve(nys, torch, op, ell, 1000 + i, prec, udtype, mu, b, ws, tol, Timer(torch), **kw)
+    tm = Timer(torch)
+    infos = []
+    t = time.perf_counter()
+    for i in range(args.steps):
+        a = time.perf_counter()
+        _, info, _ = full_solve(nys, torch, op, ell, 20211003 + i, prec, udtype, mu, b, ws, tol, tm, **kw)
+        infos.append(info)
+        log("krr step %d: %.1f ms iters %d refine %d relres %.2e" % (i, 1e3 * (time.perf_counter() - a),
+                                                                     info.iters[0], info.refine_steps,
+                                                                     info.relres[0]))
+    el = time.perf_counter() - t
+    # dominant kernel: one single-vector product in the chosen arithmetic
+    if small:
+        v = torch.randn(n, dtype=torch.float64, device=dev)
+        mv_ms = kernel_avg_ms(torch, lambda: nys.nys_op_apply(op, mu, v), args.matvec_reps)
+        ev = n * n / (mv_ms * 1e-3) / 1e9
+        roof = {"bound": "alu", "achieved": ev, "peak": 78.6e3 / 64, "unit": "G kernel entries/s",
+                "frac": ev / (78.6e3 / 64), "traffic": None,
+                "kernel": "rbf_mv_f64 (float64 Gram + exp per entry, ~64 float64 flops)", "avg_ms": mv_ms}
+    else:
+        v = torch.randn(n, dtype=torch.float32, device=dev)
+        mv_ms = kernel_avg_ms(torch, lambda: nys.nys_op_apply(op, mu, v, prec=prec), args.matvec_reps)
+        ev = n * n / (mv_ms * 1e-3) / 1e9
+        roof = {"bound": "alu", "achieved": ev, "peak": EXP_PEAK_GPS, "unit": "G kernel entries/s",
+                "frac": ev / EXP_PEAK_GPS, "traffic": None,
+                "kernel": "rbf_mv_lowp<bf16x3>: one v_exp_f32 per kernel entry", "avg_ms": mv_ms}
+    out = base_record(
+        args, args.steps / el, 1e3 * el / args.steps, label,
+        {"workload": ("kernel ridge regression, RBF n=%d d=%d sigma=sqrt(d), mu=%g, l=%d, tol 1e-10"
+                      % (n, d, mu, ell)),
+         "precision": "float64" if small else "bf16x3 Gram tiles on MFMA, float32 inner PCG, float64 refinement",
+         "step": "Gaussian Omega + sketch + factor + PCG solve"},
+        {"correct": all(i.relres[0] <= tol and i.status[0] == 0 for i in infos),
+         "relres": max(i.relres[0] for i in infos), "iters": infos[-1].iters[0],
+         "refine_steps": infos[-1].refine_steps,
+         "phase_ms": {k: 1e3 * v / args.steps for k, v in tm.t.items()}, "roofline": roof})
+    if not args.no_plain and not small:
+        ws64 = nys.workspace(op, ell, 1, nys.NYS_PREC_FP64)
+        tm64 = Timer(torch)
+        t = time.perf_counter()
+        _, inf64, _ = full_solve(nys, torch, op, ell, 7, nys.NYS_PREC_FP64, torch.float64, mu, b, ws64, tol, tm64,
+                                 maxit=5000, check_every=16)
+        el64 = time.perf_counter() - t
+        out["plain_fp64"] = {"value": 1.0 / el64, "unit": "solves/s", "ms_per_step": 1e3 * el64,
+                             "phase_ms": {k: 1e3 * v for k, v in tm64.t.items()}, "iters": inf64.iters[0],
+                             "relres": inf64.relres[0], "correct": inf64.relres[0] <= tol}
+        out["speedup_vs_plain_fp64"] = out["value"] / out["plain_fp64"]["value"]
+    if not args.no_cpu_baseline:
+        t_sk, t_mv = rbf_cpu_sample(w, ell)
+        it = infos[-1].total_iters or infos[-1].iters[0]
+        est = t_sk + it * t_mv
+        out["cpu_baseline"] = {"value": 1.0 / est, "unit": "solves/s", "cores": cores_used(), "kind": "oracle",
+                               "sample": "oracle RBF row block (2048 rows of K) times l columns and times one "
+                                         "column, scaled by n/2048; solve = sketch product + %d PCG products "
+                                         "(the GPU run's count); factorisation not counted, so the CPU figure "
+                                         "is an upper bound" % it,
+                               "seconds_est": est}
+    return out
+
+
+# --------------------------------------------------------------------------- batched
+
+def run_batched(args, nys, torch):
+    from workloads import batched_cv
+    dev = "cuda:0"
+    n = args.n or 50000
+    log("generating the batched workload (n=%d, 64 ragged problems)" % n)
+    w = batched_cv(n=n, with_omega=False, with_ragged=True)
+    log("inputs ready")
+    tol = 1e-10
+    X = torch.as_tensor(w["X"], device=dev)
+    op = nys.Operator.rbf(X, w["sigma"])
+    B = torch.as_tensor(w["B"], device=dev)
+    mus = [float(m) for m in w["mus"]]
+    ell = w["ell"]
+    prec = nys.NYS_PREC_FP32_REFINE64
+    ws = nys.workspace(op, ell, len(mus) * B.shape[1], prec)
+    rag = w["ragged"]
+    rops, rbs = [], []
+    for p in rag:
+        Xk = torch.as_tensor(p["X"], device=dev)
+        rops.append(nys.Operator.xtx(Xk))
+        rbs.append(torch.as_tensor(p["X"].astype(np.float64).T @ p["y"], device=dev))
+
+    def step(seed):
+        tm = Timer(torch)
+        t = time.perf_counter()
+        Xs, info, _ = full_solve(nys, torch, op, ell, seed, prec, torch.float32, mus, B, ws, tol, tm, maxit=5000,
+                                 max_refine=40, inner_tol=1e-3, check_every=16)
+        log("block solve: %s, iters max %d, refine %d" % ({k: round(1e3 * v, 1) for k, v in tm.t.items()},
+                                                          max(info.iters), info.refine_steps))
+        t = time.perf_counter()
+        Ps = []
+        for k, (o, p) in enumerate(zip(rops, rag)):
+            Om, Y = nys.nys_sketch(o, p["ell"], seed=seed + k, prec=prec)
+            Ps.append(nys.nys_factor(Om, Y, dtype=torch.float32, prec=prec))
+        tm.lap("ragged_factor", t)
+        log("ragged sketches + factors: %.1f ms" % (1e3 * tm.t["ragged_factor"]))
+        t = time.perf_counter()
+        Xr, rinfo = nys.nys_pcg_solve_ragged(rops, Ps, [p["mu"] for p in rag], rbs, tol=tol, prec=prec,
+                                             maxit=1000)
+        tm.lap("ragged_pcg", t)
+        return info, rinfo, tm
+
+    for i in range(args.warmup):
+        step(100 + i)
+    t = time.perf_counter()
+    infos = []
+    tms = []
+    for i in range(args.steps):
+        info, rinfo, tm = step(20211004 + i)
+        infos.append((info, rinfo))
+        tms.append(tm)
+        log("batched step %d: %s; block iters max %d; ragged relres max %.2e" %
+            (i, {k: round(1e3 * v, 1) for k, v in tm.t.items()}, max(info.iters), max(rinfo.relres)))
+    el = time.perf_counter() - t
+    nsolves = len(mus) * B.shape[1] + len(rag)
+    ok = all(max(a.relres) <= tol and max(r.relres) <= tol for a, r in infos)
+    phases = {k: 1e3 * sum(tm.t.get(k, 0.0) for tm in tms) / args.steps for k in tms[0].t}
+    return base_record(
+        args, nsolves * args.steps / el, 1e3 * el / args.steps, "f32+f64",
+        {"workload": "batched cross-validation: RBF n=%d d=16 l=%d, 32 mu x 8 rhs in one block solve, plus 64 "
+                     "ragged ridge problems (n_k = m_k/4, m_k in [1000, 20000])" % (n, ell),
+         "precision": "float32 inner PCG + float64 refinement", "step": "all 320 solves incl. sketches"},
+        {"correct": ok, "phase_ms": phases, "solves_per_step": nsolves,
+         "block_iters_max": max(infos[-1][0].iters), "block_refine": infos[-1][0].refine_steps})
+
+
+# --------------------------------------------------------------------------- differentiation
+
+def run_diff(args, nys, torch):
+    import oracle  # noqa: F401  (only the checker below uses it)
+    from workloads import differentiation
+    dev = "cuda:0"
+    n = args.n or 100000
+    w = differentiation(n=n, nval=max(1000, n // 10), with_omega=False)
+    log("inputs ready")
+    X = torch.as_tensor(w["X"], device=dev)
+    Xv = torch.as_tensor(w["Xval"], device=dev)
+    op = nys.Operator.rbf(X, w["sigma"])
+    b = rbf_rhs(nys, torch, op, w, dev)
+    wv = torch.as_tensor(w["w"], device=dev)
+    yv = nys.nys_rbf_cross(op, Xv, wv) + w["noise"] * torch.as_tensor(w["eps_val"], device=dev)
+    ell, mu, tol = w["ell"], w["mu"], 1e-10
+    prec = nys.NYS_PREC_BF16X3_REFINE64
+    ws = nys.workspace(op, ell, 1, prec)
+
+    def step(seed):
+        tm = Timer(torch)
+        x, info, P = full_solve(nys, torch, op, ell, seed, prec, torch.float32, mu, b, ws, tol, tm, maxit=5000,
+                                max_refine=40, inner_tol=1e-2, check_every=16)
+        log("forward solve: %s, iters %d" % ({k: round(1e3 * v, 1) for k, v in tm.t.items()}, info.iters[0]))
+        t = time.perf_counter()
+        rv = nys.nys_rbf_cross(op, Xv, x) - yv
+        L = float((rv * rv).sum())
+        gx = 2.0 * nys.nys_rbf_cross(op, Xv, rv, transpose=True)
+        _, dsig_explicit = nys.nys_rbf_cross(op, Xv, rv, wvec=x)
+        g = nys.nys_pcg_backward(op, P, mu, x, gx, want_sigma=True, tol=tol, prec=prec, ws=ws, maxit=5000,
+                                 max_refine=40, inner_tol=1e-2, check_every=16)
+        tm.lap("backward", t)
+        return L, g, 2.0 * dsig_explicit + g["gsigma"], info, tm
+
+    for i in range(args.warmup):
+        step(200 + i)
+    t = time.perf_counter()
+    tms = []
+    for i in range(args.steps):
+        L, g, gs, info, tm = step(20211005 + i)
+        tms.append(tm)
+        log("diff step %d: L=%.6e dL/dmu=%.6e dL/dsigma=%.6e %s" % (i, L, g["gmu"], gs,
+                                                                   {k: round(1e3 * v, 1) for k, v in tm.t.items()}))
+    el = time.perf_counter() - t
+    return base_record(
+        args, args.steps / el, 1e3 * el / args.steps, "bf16x3+f32+f64",
+        {"workload": "validation loss L = ||K_val x - y_val||^2 through the RBF solve, n=%d, nval=%d, d=16, l=%d"
+                     % (n, Xv.shape[0], ell),
+         "precision": "bf16x3 Gram tiles, float32 inner PCG, float64 refinement and gradient reductions",
+         "step": "forward solve + loss + adjoint solve with the same preconditioner + dL/dmu, dL/dsigma, dL/db"},
+        {"unit_note": "value = loss-and-gradient evaluations per second",
+         "phase_ms": {k: 1e3 * sum(tm.t.get(k, 0.0) for tm in tms) / args.steps for k in tms[0].t},
+         "L": L, "dL_dmu": g["gmu"], "dL_dsigma": gs})
 
 
 def main():
@@ -50,134 +452,12 @@ def main():
     import torch
 
     import paper_2110_02820_amd as nys
-    from workloads import ridge_dense
-
     assert torch.cuda.is_available(), "bench.py needs a GPU"
-    dev = "cuda:0"
     torch.cuda.set_device(0)
-    t0 = time.time()
-    w = ridge_dense(m=args.m, n=args.n, ell=args.ell, with_omega=False)
-    X32h = w["X"]
-    # b = X^T y (input synthesis on the host, float64)
-    b_h = X32h.astype(np.float64).T @ w["y"]
-    mu, ell, tol = w["mu"], args.ell, 1e-10
-    X32 = torch.as_tensor(X32h, device=dev)
-    b = torch.as_tensor(b_h, device=dev)
-    op = nys.Operator.xtx(X32)
-    prec = nys.NYS_PREC_FP32_REFINE64
-    ws = nys.workspace(op, ell, 1, prec)
-    print("# inputs ready in %.1fs" % (time.time() - t0), file=sys.stderr, flush=True)
-
-    def step(seed, opx, precx, wsx, udtype):
-        Om, Y = nys.nys_sketch(opx, ell, seed=seed, prec=precx, ws=wsx)
-        P = nys.nys_factor(Om, Y, dtype=udtype, ws=wsx, prec=precx)
-        x, info = nys.nys_pcg_solve(opx, P, mu, b, tol=tol, maxit=1000, prec=precx, ws=wsx, inner_tol=1e-4)
-        return x, info
-
-    def timed(opx, precx, wsx, udtype, steps, warmup, label):
-        for i in range(warmup):
-            step(1000 + i, opx, precx, wsx, udtype)
-        torch.cuda.synchronize()
-        ph = {"sketch": 0.0, "factor": 0.0, "pcg": 0.0}
-        infos = []
-        t = time.perf_counter()
-        for i in range(steps):
-            a = time.perf_counter()
-            Om, Y = nys.nys_sketch(opx, ell, seed=20211002 + i, prec=precx, ws=wsx)
-            torch.cuda.synchronize()
-            bb = time.perf_counter()
-            P = nys.nys_factor(Om, Y, dtype=udtype, ws=wsx, prec=precx)
-            torch.cuda.synchronize()
-            c = time.perf_counter()
-            x, info = nys.nys_pcg_solve(opx, P, mu, b, tol=tol, maxit=1000, prec=precx, ws=wsx, inner_tol=1e-4)
-            torch.cuda.synchronize()
-            d = time.perf_counter()
-            ph["sketch"] += bb - a
-            ph["factor"] += c - bb
-            ph["pcg"] += d - c
-            infos.append(info)
-            print("# %s step %d: %.2f ms, iters %d, refine %d, relres %.2e" %
-                  (label, i, 1e3 * (d - a), info.iters[0], info.refine_steps, info.relres[0]),
-                  file=sys.stderr, flush=True)
-        torch.cuda.synchronize()
-        el = time.perf_counter() - t
-        return el, {k: 1e3 * v / steps for k, v in ph.items()}, infos
-
-    el, phases, infos = timed(op, prec, ws, torch.float32, args.steps, args.warmup, "chosen")
-    ok = all(i.relres[0] <= tol and i.status[0] == 0 for i in infos)
-    ms = 1e3 * el / args.steps
-
-    # roofline of the dominant kernel: the one-pass float32 X^T X matvec
-    v32 = torch.randn(args.n, dtype=torch.float32, device=dev)
-    wsm = nys.workspace(op, 1, 1, nys.NYS_PREC_FP64)
-    for _ in range(3):
-        nys.nys_op_apply(op, mu, v32, ws=wsm)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(args.matvec_reps):
-        nys.nys_op_apply(op, mu, v32, ws=wsm)
-    e1.record()
-    torch.cuda.synchronize()
-    mv_ms = e0.elapsed_time(e1) / args.matvec_reps
-    alg_bytes = args.m * args.n * 4 + 2 * args.n * 4  # X once + p in + v out
-    achieved = alg_bytes / (mv_ms * 1e-3) / 1e9
-
-    out = {
-        "metric": METRIC, "value": args.steps / el, "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
-        "config": {"workload": "ridge regression A = X^T X, X %dx%d float32 = G diag(j^-1/2), mu=1e-4, "
-                               "l=%d, b = X^T y, tol 1e-10 (true float64 residual)" % (args.m, args.n, ell),
-                   "precision": "float32 inner PCG + float64 residual refinement; float64 core factorisation",
-                   "step": "Gaussian Omega + sketch + factor + PCG solve"},
-        "correct": ok,
-        "relres": max(i.relres[0] for i in infos),
-        "iters": infos[-1].iters[0], "refine_steps": infos[-1].refine_steps,
-        "phase_ms": phases,
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "xtx_fused<float,float> + reduce_cols (one X^T X matvec)",
-                     "avg_ms": mv_ms, "alg_bytes": alg_bytes},
-    }
-
-    if not args.no_plain:
-        X64 = X32.double()
-        op64 = nys.Operator.xtx(X64)
-        ws64 = nys.workspace(op64, ell, 1, nys.NYS_PREC_FP64)
-        el64, ph64, inf64 = timed(op64, nys.NYS_PREC_FP64, ws64, torch.float64, max(1, min(args.steps, 3)), 1,
-                                  "plain")
-        n64 = max(1, min(args.steps, 3))
-        out["plain_fp64"] = {"value": n64 / el64, "unit": "solves/s", "ms_per_step": 1e3 * el64 / n64,
-                             "phase_ms": ph64, "iters": inf64[-1].iters[0], "relres": inf64[-1].relres[0],
-                             "correct": all(i.relres[0] <= tol for i in inf64)}
-        out["speedup_vs_plain_fp64"] = out["value"] / out["plain_fp64"]["value"]
-        del X64, op64, ws64
-
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(w, b_h, mu, ell, tol)
+    fn = {"ridge": run_ridge_kernel if args.kernel_only else run_ridge, "krr_small": lambda a, n, t: run_krr(a, n, t, small=True), "krr": run_krr,
+          "batched": run_batched, "diff": run_diff}[args.workload]
+    out = fn(args, nys, torch)
     print(json.dumps(out), flush=True)
-
-
-def cpu_baseline(w, b_h, mu, ell, tol):
-    """The float64 CPU oracle, unchanged, on one full solve of the same workload."""
-    import oracle
-    from workloads import gaussian_test_matrix
-    try:
-        from threadpoolctl import threadpool_info
-        cores = max([i.get("num_threads", 0) for i in threadpool_info()] + [1])
-    except Exception:  # pragma: no cover
-        cores = os.cpu_count()
-    X = w["X"]
-    opr = oracle.XtXOp(X)
-    om0 = gaussian_test_matrix(X.shape[1], ell, 7)
-    t = time.perf_counter()
-    r = oracle.randomized_nystrom(opr, om0)
-    out = oracle.nystrom_pcg(opr.matmat, b_h, mu, lambda v: oracle.precond_inv_apply(r["U"], r["lam"], mu, v),
-                             tol=tol, maxit=1000)
-    el = time.perf_counter() - t
-    return {"value": 1.0 / el, "unit": "solves/s", "cores": cores, "kind": "oracle",
-            "sample": "one full solve of the same workload (sketch + factor + PCG to 1e-10), numpy float64",
-            "seconds": el, "iters": out["iters"]}
 
 
 if __name__ == "__main__":

@@ -320,7 +320,8 @@ def nys_pcg_solve_ragged(ops: Sequence[Operator], Ps: Sequence[Precond], mus: Se
 
 def nys_pcg_backward(op: Operator, P: Precond, mu: float, x: torch.Tensor, gx: torch.Tensor,
                      want_sigma: bool = False, want_X: bool = False, tol: float = 1e-10, maxit: int = 500,
-                     prec: int = NYS_PREC_FP64, ws: Optional[torch.Tensor] = None):
+                     prec: int = NYS_PREC_FP64, max_refine: int = 10, check_every: int = 8,
+                     inner_tol: float = 1e-4, ws: Optional[torch.Tensor] = None):
     """Adjoint solve with the same preconditioner.  Returns dict(gb, gmu, gsigma, gX, info)."""
     x = x.reshape(-1).contiguous().to(torch.float64)
     gx = gx.reshape(-1).contiguous().to(torch.float64)
@@ -333,7 +334,7 @@ def nys_pcg_backward(op: Operator, P: Precond, mu: float, x: torch.Tensor, gx: t
     rr = (ctypes.c_double * 1)()
     st = (ctypes.c_int32 * 1)()
     info = _Info(it, rr, st, 0, 0)
-    o = _opts(tol, maxit, prec, 10, 8, 1e-4)
+    o = _opts(tol, maxit, prec, max_refine, check_every, inner_tol)
     code = lib().nys_pcg_backward(ctypes.byref(op.c()), ctypes.byref(P.c()), float(mu), _ptr(x), _ptr(gx),
                                   _ptr(gb), ctypes.byref(gmu), ctypes.byref(gsig) if want_sigma else None,
                                   _ptr(gX), ctypes.byref(o), ctypes.byref(info), _ptr(w), w.numel(), _stream())

@@ -27,6 +27,12 @@ void set_error(const char* fmt, ...) {
   va_end(ap);
 }
 
+// Diagnostics on stderr (Jacobi sweeps, refinement progress) when NYS_VERBOSE is set.
+bool verbose() {
+  static const bool v = std::getenv("NYS_VERBOSE") != nullptr;
+  return v;
+}
+
 int num_cus() {
   static int cached[64] = {0};
   int dev = 0;
@@ -562,6 +568,13 @@ nys_status solve_impl(const OpDesc& op, const PrecDesc& P, const double* mu, int
       total += r.sweeps;
       ++refine_steps;
       NYS_TRY(true_residual(op, k, nrhs, w.mu, mu, w, relres, s));
+      if (verbose()) {
+        double worst = 0.0;
+        for (int64_t c = 0; c < k; ++c) worst = relres[c] > worst ? relres[c] : worst;
+        std::fprintf(stderr, "[nyspcg] refinement %d: inner iterations %d, max relres %.3e\n", refine_steps,
+                     r.sweeps, worst);
+        std::fflush(stderr);
+      }
     }
     for (int64_t c = 0; c < k; ++c)
       if (status[c] != NYS_ERR_BREAKDOWN) status[c] = relres[c] <= tol ? NYS_OK : NYS_NOT_CONVERGED;
@@ -777,7 +790,7 @@ nys_status nys_factor(const double* Omega, double* Y, nys_precond* P, int32_t pr
   NYS_HIP(hipMemcpyAsync(&nu, c.nu, sizeof(double), hipMemcpyDeviceToHost, s));
   NYS_HIP(hipMemcpyAsync(&sweeps, c.sweeps, sizeof(int), hipMemcpyDeviceToHost, s));
   NYS_HIP(hipStreamSynchronize(s));
-  if (std::getenv("NYS_VERBOSE"))
+  if (verbose())
     std::fprintf(stderr, "[nyspcg] factor n=%lld l=%lld nu=%.3e jacobi_sweeps=%d\n", (long long)n,
                  (long long)l, nu, sweeps);
   P->nu = nu;
@@ -805,17 +818,22 @@ nys_status nys_op_apply(const nys_operator* A, double mu, const void* V, int64_t
     return NYS_ERR_WORKSPACE;
   }
   hipStream_t s = S(stream);
-  NYS_TRY(set_mu(mu_dev, &mu, 1, s));
+  const bool one = k == 1 && ldv == 1 && ldz == 1;
+  // single-vector X^T X / dense products take mu by value; the others read it from the device
+  if (!(one && op.kind != NYS_OP_RBF)) NYS_TRY(set_mu(mu_dev, &mu, 1, s));
   if (f32 && op.kind == NYS_OP_RBF) {
     RbfLowp L;
     NYS_TRY(rbf_lowp_prepare(op, lowp_buf, L, s));
+    if (one)
+      return rbf_lowp_mv(L, rbf_gram(prec), static_cast<const float*>(V), mu_dev, static_cast<float*>(Z),
+                         reinterpret_cast<float*>(scr), 2 * se, s);
     return rbf_lowp_kv(L, rbf_gram(prec), static_cast<const float*>(V), ldv, k, mu_dev, k, static_cast<float*>(Z),
                        ldz, reinterpret_cast<float*>(scr), se, nullptr, s);
   }
   if (f32)
     return op_matvec<float>(op, static_cast<const float*>(V), (float)mu, static_cast<float*>(Z),
                             reinterpret_cast<float*>(scr), se, s);
-  if (k == 1 && ldv == 1 && ldz == 1 && (op.kind == NYS_OP_XTX || op.kind == NYS_OP_DENSE))
+  if (one && (op.kind == NYS_OP_XTX || op.kind == NYS_OP_DENSE))
     return op_matvec<double>(op, static_cast<const double*>(V), mu, static_cast<double*>(Z), scr, se, s);
   return op_apply_f64(op, static_cast<const double*>(V), k, ldv, mu_dev, k, static_cast<double*>(Z), ldz,
                       scr, se, s);

@@ -1,12 +1,15 @@
 // Small dense float64 linear algebra on the l x l core of the Nystrom
 // factorisation (Section 2.2, algorithm "Randomized Nystrom Approximation",
-// steps 4-9), all on the device:
-//   * shift nu = eps(||Y||_F) and Y_nu = Y + nu Omega
-//   * Cholesky factorisation (blocked, right-looking, cooperative launch)
+// steps 4-9), all on the device and stream-ordered (no host round trips
+// except the convergence polls of the eigensolver):
+//   * shift nu = eps(||Y||_F) (raised for reduced-precision sketches) and
+//     Y_nu = Y + nu Omega
+//   * blocked right-looking Cholesky, one launch per block step
+//     (diagonal block, panel, trailing update)
 //   * inverse of the lower-triangular factor (independent column-block chains)
-//   * symmetric eigensolver: cyclic two-sided Jacobi with the round-robin
-//     parallel ordering (every round rotates m/2 disjoint pairs), cooperative
-//     launch with one grid barrier per round
+//   * symmetric eigensolver: block two-sided Jacobi with the round-robin
+//     ordering of block pairs; each round solves the 32 x 32 subproblems in
+//     LDS and applies the rotations to the off-diagonal tiles on FP64 MFMA
 //   * descending sort of the eigenvalues and the scaled eigenvector matrix
 #include <cstdlib>
 
@@ -622,11 +625,7 @@ nys_status tri_inverse(const double* L, int64_t n, const double* Dinv, double* X
 
 // one inner sweep per round for large problems (the outer sweeps refine the
 // pairs again); small problems are a single block pair, solved to convergence
-int inner_sweeps_for(int64_t l) {
-  if (l <= JS) return 40;
-  const char* e = std::getenv("NYS_JACOBI_INNER");
-  return e ? std::atoi(e) : 1;
-}
+int inner_sweeps_for(int64_t l) { return l <= JS ? 40 : 1; }
 
 int jac_nblk(int64_t l) {
   int nb = (int)cdiv(l, JB);

@@ -336,6 +336,16 @@ nys_status rbf_lowp_mv_partials(const RbfLowp& L, int mode, const float* p, floa
   return NYS_OK;
 }
 
+nys_status rbf_lowp_mv(const RbfLowp& L, int mode, const float* p, const double* mu_dev, float* v, float* part,
+                       size_t part_elems, hipStream_t s) {
+  int ns = 0;
+  NYS_TRY(rbf_lowp_mv_partials(L, mode, p, part, part_elems, &ns, nullptr, s));
+  hipLaunchKernelGGL(rbf_lowp_finish, dim3((unsigned)cdiv(L.n, 256)), dim3(256), 0, s, part, ns, L.n, (int64_t)1,
+                     L.scale, p, (int64_t)1, mu_dev, (int64_t)1, v, (int64_t)1, (const int*)nullptr);
+  NYS_CHECK_LAUNCH();
+  return NYS_OK;
+}
+
 size_t rbf_lowp_kv_scratch(int64_t n, int64_t k) {
   const int64_t tiles = cdiv(n, 64) * cdiv(k, 64);
   const int64_t nz = cdiv(2 * 256, tiles);

@@ -24,6 +24,10 @@ nys_status rbf_lowp_prepare(const OpDesc& op, void* buf, RbfLowp& L, hipStream_t
 nys_status rbf_lowp_mv_partials(const RbfLowp& L, int mode, const float* p, float* part, size_t part_elems,
                                 int* ng_out, const int* skip, hipStream_t s);
 
+// v = scale K p + mu p for one contiguous vector (part: the partial buffer above).
+nys_status rbf_lowp_mv(const RbfLowp& L, int mode, const float* p, const double* mu_dev, float* v, float* part,
+                       size_t part_elems, hipStream_t s);
+
 // V = scale K P (+ mu_c P) for k columns, float32 (scratch: rbf_lowp_kv_scratch).
 size_t rbf_lowp_kv_scratch(int64_t n, int64_t k);
 nys_status rbf_lowp_kv(const RbfLowp& L, int mode, const float* P, int64_t ldp, int64_t k, const double* mu_dev,
