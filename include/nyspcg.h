@@ -205,11 +205,17 @@ nys_status nys_pcg_backward(const nys_operator* A, const nys_precond* P, double 
                             size_t ws_bytes, void* stream);
 
 /* Rectangular RBF products for losses on held-out points (validation set Xv,
- * nv x d; training points X of A, n x d):
- *   transpose = 0:  out (nv) = K(Xv, X) v,        v (n)
- *   transpose = 1:  out (n)  = K(Xv, X)^T v,      v (nv)
- * and, when dsig_out != NULL (host), *dsig_out = u^T (dK(Xv,X)/dsigma) w for
- * u = v (nv) and w = wvec (n).  All float64. */
+ * nv x d, same storage type as the data of A; training points X of A, n x d).
+ * All vectors are device float64.
+ *   wvec == NULL, transpose = 0:  out (nv) = K(Xv, X) v,       v has n entries
+ *   wvec == NULL, transpose = 1:  out (n)  = K(Xv, X)^T v,     v has nv entries
+ *   wvec != NULL (transpose must be 0; dsig_out, host, must be non-NULL):
+ *       out (nv) = (dK(Xv, X)/dsigma) wvec,  wvec has n entries,
+ *       *dsig_out = v^T out,                 v has nv entries,
+ *   with dK_ij/dsigma = K_ij |xv_i - x_j|^2 / sigma^3 (the explicit sigma
+ *   dependence of a validation loss).  The call reads exactly these lengths;
+ *   shorter buffers are undefined behaviour.  Synchronises the stream only in
+ *   the wvec form. */
 nys_status nys_rbf_cross(const nys_operator* A, const void* Xv, int64_t nv, int64_t ldxv,
                          int32_t transpose, const double* v, double* out, const double* wvec,
                          double* dsig_out, void* ws, size_t ws_bytes, void* stream);

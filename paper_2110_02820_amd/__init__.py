@@ -345,14 +345,20 @@ def nys_pcg_backward(op: Operator, P: Precond, mu: float, x: torch.Tensor, gx: t
 
 def nys_rbf_cross(op: Operator, Xv: torch.Tensor, v: torch.Tensor, transpose: bool = False,
                   wvec: Optional[torch.Tensor] = None, ws: Optional[torch.Tensor] = None):
-    """K(Xv, X) v (transpose=False) or K(Xv, X)^T v; with wvec also v^T (dK(Xv,X)/dsigma) wvec."""
+    """K(Xv, X) v (transpose=False, v: n), K(Xv, X)^T v (transpose=True, v: nv), or with
+    wvec (n): (out, v^T out) for out = (dK(Xv, X)/dsigma) wvec and v of length nv."""
     Xv = Xv.contiguous()
     v = v.reshape(-1).contiguous().to(torch.float64)
     nv = Xv.shape[0]
+    want = nv if (transpose or wvec is not None) else op.n
+    if v.numel() != want:
+        raise ValueError("nys_rbf_cross: v has %d entries, expected %d" % (v.numel(), want))
+    if wvec is not None and (transpose or wvec.numel() != op.n):
+        raise ValueError("nys_rbf_cross: wvec needs n = %d entries and transpose=False" % op.n)
     out = torch.empty(op.n if transpose else nv, dtype=torch.float64, device=v.device)
     dsig = ctypes.c_double(0.0)
     if ws is None:
-        ws = torch.empty(8 * 1024 * max(op.n, nv) + 16 * nv + 8192, dtype=torch.uint8, device=v.device)
+        ws = torch.empty(8 * 1024 * max(op.n, nv) + 8192, dtype=torch.uint8, device=v.device)
     wv = None if wvec is None else wvec.reshape(-1).contiguous().to(torch.float64)
     _check(lib().nys_rbf_cross(ctypes.byref(op.c()), _ptr(Xv), nv, Xv.stride(0), 1 if transpose else 0, _ptr(v),
                                _ptr(out), _ptr(wv), ctypes.byref(dsig) if wv is not None else None, _ptr(ws),

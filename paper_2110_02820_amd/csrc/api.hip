@@ -184,6 +184,9 @@ void carve_factor(Arena& a, int64_t n, int64_t l, FactorWs& w) {
 template <typename T>
 struct PcgBufs {
   T *V, *R, *Z, *P, *X, *B;
+  T* Xw;       // working copy of the active columns of X once columns are compacted
+  double* mu;  // per-column mu of the active columns
+  int *cidx, *cmap;  // compaction: kept columns (old positions), original column of each active column
   PcgWork w;
   CgScalars sc;
   T* opscr;
@@ -199,6 +202,10 @@ void carve_pcg(Arena& a, const OpDesc& op, int64_t l, int64_t k, PcgBufs<T>& b) 
   b.P = a.take<T>(n * k);
   b.X = a.take<T>(n * k);
   b.B = a.take<T>(n * k);
+  b.Xw = k > 1 ? a.take<T>(n * k) : nullptr;
+  b.mu = a.take<double>(k);
+  b.cidx = a.take<int>(k);
+  b.cmap = a.take<int>(k);
   b.w.pb = a.take<double>(kMaxGroups * k);
   b.w.prr = a.take<double>(kMaxGroups * k);
   b.w.ppv = a.take<double>(kMaxGroups * k);
@@ -226,6 +233,8 @@ struct SolveWs {
   PcgBufs<double> d;
   PcgBufs<float> f;
   double *mu, *R64, *V64, *X64, *B64, *dots;
+  double* mu_act;  // mu of the columns still refined
+  int* omap;       // original column of each refined column
   bool has_f;
   void* lowp_buf;
   RbfLowp L;
@@ -234,6 +243,8 @@ struct SolveWs {
 void carve_solve(Arena& a, const OpDesc& op, int64_t l, int64_t k, int prec, SolveWs& w) {
   const int64_t n = op.n;
   w.mu = a.take<double>(k);
+  w.mu_act = a.take<double>(k);
+  w.omap = a.take<int>(k);
   w.dots = a.take<double>(kMaxGroups * k + 2 * k);
   w.R64 = a.take<double>(n * k);
   w.V64 = a.take<double>(n * k);
@@ -283,12 +294,6 @@ __global__ void residual_norms(int64_t n, int64_t k, const double* __restrict__ 
   }
 }
 
-__global__ void fill_values(double* __restrict__ dst, int64_t count, double v0, double v1,
-                            double v2, double v3) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < count) dst[i] = (i == 0) ? v0 : (i == 1) ? v1 : (i == 2) ? v2 : v3;
-}
-
 template <typename T>
 __global__ void zero_fill(T* __restrict__ p, int64_t count) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -334,7 +339,93 @@ __global__ void gemv_rows(const TS* __restrict__ X, int64_t m, int64_t n, int64_
   if (lane == 0) out[row] = s;
 }
 
+// Up to 256 column indices passed by value (no host-to-device copy).
+struct ColList {
+  int v[256];
+};
+
+__global__ void set_indices(int* __restrict__ dst, int64_t count, ColList l) {
+  const int i = threadIdx.x;
+  if (i < count) dst[i] = l.v[i];
+}
+
+// dst (n x knew) = columns idx[0..knew) of src (n x kold)
+template <typename TS, typename TD>
+__global__ void gather_idx(int64_t n, int64_t kold, const TS* __restrict__ src, const int* __restrict__ idx,
+                           int64_t knew, TD* __restrict__ dst) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n * knew) return;
+  const int64_t i = t / knew, j = t % knew;
+  dst[t] = TD(src[i * kold + idx[j]]);
+}
+
+// dst (n x kfull) columns map[j] (+)= src (n x ksub) column j
+template <typename TS, bool ADD>
+__global__ void scatter_idx(int64_t n, int64_t ksub, const TS* __restrict__ src, const int* __restrict__ map,
+                            int64_t kfull, double* __restrict__ dst) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n * ksub) return;
+  const int64_t i = t / ksub, j = t % ksub;
+  double* d = dst + i * kfull + map[j];
+  if (ADD) *d += double(src[t]);
+  else *d = double(src[t]);
+}
+
+template <typename T>
+__global__ void scatter_idx_same(int64_t n, int64_t ksub, const T* __restrict__ src, const int* __restrict__ map,
+                                 int64_t kfull, T* __restrict__ dst) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n * ksub) return;
+  const int64_t i = t / ksub, j = t % ksub;
+  dst[i * kfull + map[j]] = src[t];
+}
+
+// Keep the per-column CG scalars (and mu) of columns idx[0..knew), one
+// workgroup: every kept value is read into registers before any is written.
+__global__ void compact_scalars(CgScalars sc, double* __restrict__ mu, int64_t kold, const int* __restrict__ idx,
+                                int64_t knew) {
+  const int t = threadIdx.x;
+  double r0 = 0, r1 = 0, bn = 0, rn = 0, al = 0, be = 0, m = 0;
+  int dn = 0, cv = 0, it = 0, st = 0;
+  if (t < knew) {
+    const int j = idx[t];
+    r0 = sc.rz[j];
+    r1 = sc.rz[kold + j];
+    bn = sc.bnorm2[j];
+    rn = sc.rnorm2[j];
+    al = sc.alpha[j];
+    be = sc.beta[j];
+    m = mu[j];
+    dn = sc.done[j];
+    cv = sc.conv[j];
+    it = sc.iters[j];
+    st = sc.status[j];
+  }
+  __syncthreads();
+  if (t < knew) {
+    sc.rz[t] = r0;
+    sc.rz[knew + t] = r1;
+    sc.bnorm2[t] = bn;
+    sc.rnorm2[t] = rn;
+    sc.alpha[t] = al;
+    sc.beta[t] = be;
+    mu[t] = m;
+    sc.done[t] = dn;
+    sc.conv[t] = cv;
+    sc.iters[t] = it;
+    sc.status[t] = st;
+  }
+}
+
 unsigned nblk(int64_t count) { return (unsigned)(count > 0 ? cdiv(count, 256) : 1); }
+
+nys_status upload_indices(int* dst, const std::vector<int>& v, hipStream_t s) {
+  ColList l{};
+  for (size_t i = 0; i < v.size() && i < 256; ++i) l.v[i] = v[i];
+  hipLaunchKernelGGL(set_indices, dim3(1), dim3(256), 0, s, dst, (int64_t)v.size(), l);
+  NYS_CHECK_LAUNCH();
+  return NYS_OK;
+}
 
 template <typename T>
 nys_status zero(T* p, int64_t count, hipStream_t s) {
@@ -344,12 +435,23 @@ nys_status zero(T* p, int64_t count, hipStream_t s) {
   return NYS_OK;
 }
 
+// Up to 256 values passed by value (no host-to-device copy, so the call is
+// safe inside stream capture and needs no pinned memory).
+struct ValList {
+  double v[256];
+};
+
+__global__ void set_values(double* __restrict__ dst, int64_t count, ValList l) {
+  const int i = threadIdx.x;
+  if (i < count) dst[i] = l.v[i];
+}
+
 nys_status set_mu(double* mu_dev, const double* mu, int64_t nmu, hipStream_t s) {
-  for (int64_t i = 0; i < nmu; i += 4) {
-    double v[4] = {0, 0, 0, 0};
-    for (int j = 0; j < 4 && i + j < nmu; ++j) v[j] = mu[i + j];
-    const int64_t cnt = (nmu - i) < 4 ? (nmu - i) : 4;
-    hipLaunchKernelGGL(fill_values, dim3(1), dim3(64), 0, s, mu_dev + i, cnt, v[0], v[1], v[2], v[3]);
+  for (int64_t i = 0; i < nmu; i += 256) {
+    ValList l{};
+    const int64_t cnt = (nmu - i) < 256 ? (nmu - i) : 256;
+    for (int64_t j = 0; j < cnt; ++j) l.v[j] = mu[i + j];
+    hipLaunchKernelGGL(set_values, dim3(1), dim3(256), 0, s, mu_dev + i, cnt, l);
     NYS_CHECK_LAUNCH();
   }
   return NYS_OK;
@@ -411,72 +513,144 @@ struct PcgResult {
   int sweeps = 0;
 };
 
-// Left-preconditioned CG (algorithm "Nystrom PCG") on k columns.  B (n x k,
-// ld = k) and X (n x k, ld = k, in: x0 unless x0_zero) are arrays of type T.
+// Left-preconditioned CG (algorithm "Nystrom PCG") on k independent columns,
+// column c with its own mu (mu_dev / mu_host, k entries).  B (n x k, ld = k)
+// and X (n x k, ld = k, in: x0 unless x0_zero) are arrays of type T.
+//
+// Columns that have met the stopping test are compacted away at the
+// convergence polls (every check_every iterations): the active columns of X,
+// R, the direction and the per-column scalars are gathered to the front, so
+// the block products and the preconditioner apply only pay for the columns
+// still iterating.  Each column follows exactly the recurrence it would follow
+// alone; results are scattered back to the original column order.
 template <typename T>
-nys_status pcg_run(const OpDesc& op0, const PrecDesc& P, int64_t k, int64_t nrhs,
-                   const double* mu_dev, double mu_host, const T* B, T* X, bool x0_zero, double tol,
-                   int maxit, int check_every, PcgBufs<T>& b, PcgResult& res, hipStream_t s) {
+nys_status pcg_run(const OpDesc& op0, const PrecDesc& P, int64_t k, const double* mu_dev,
+                   const std::vector<double>& mu_host, const T* B, T* X, bool x0_zero, double tol, int maxit,
+                   int check_every, PcgBufs<T>& b, PcgResult& res, hipStream_t s) {
   const int64_t n = op0.n;
   OpDesc op = op0;
   op.skip = nullptr;
+  NYS_HIP(hipMemcpyAsync(b.mu, mu_dev, sizeof(double) * k, hipMemcpyDeviceToDevice, s));
   NYS_HIP(hipMemsetAsync(b.sc.ctr, 0, sizeof(unsigned) * 64, s));
   if (x0_zero) {
     NYS_TRY(zero<T>(X, n * k, s));
     NYS_TRY(zero<T>(b.V, n * k, s));
   } else {
-    NYS_TRY(matvec<T>(op, X, k, mu_dev, nrhs, mu_host, b.V, b, s));
+    NYS_TRY(matvec<T>(op, X, k, b.mu, 1, mu_host[0], b.V, b, s));
   }
-  NYS_TRY(pcg_setup<T>(n, k, P, mu_dev, nrhs, B, b.V, b.R, b.Z, b.P, b.w, b.sc, tol, s));
+  NYS_TRY(pcg_setup<T>(n, k, P, b.mu, 1, B, b.V, b.R, b.Z, b.P, b.w, b.sc, tol, s));
   op.skip = b.sc.alldone;
-  // single column with a partial-sum operator product: fused iteration
-  const bool fused =
-      k == 1 && (op.kind == NYS_OP_XTX || (op.kind == NYS_OP_RBF && (sizeof(T) == 8 || op.lowp != nullptr)));
+  res.iters.assign(k, 0);
+  res.status.assign(k, 0);
+  res.rnorm2.assign(k, 0.0);
+  res.bnorm2.assign(k, 0.0);
+  // current column c is original column map[c]; Xc holds the active columns
+  std::vector<int> map(k);
+  for (int64_t c = 0; c < k; ++c) map[c] = (int)c;
+  int64_t kc = k;
+  T* Xc = X;
+  bool compacted = false;
+  std::vector<int> hi(k), hs(k), hd(k);
+  std::vector<double> hr(k), hb(k);
+  auto harvest = [&](int64_t kk, bool only_done) -> nys_status {
+    NYS_HIP(hipMemcpyAsync(hi.data(), b.sc.iters, sizeof(int) * kk, hipMemcpyDeviceToHost, s));
+    NYS_HIP(hipMemcpyAsync(hs.data(), b.sc.status, sizeof(int) * kk, hipMemcpyDeviceToHost, s));
+    NYS_HIP(hipMemcpyAsync(hr.data(), b.sc.rnorm2, sizeof(double) * kk, hipMemcpyDeviceToHost, s));
+    NYS_HIP(hipMemcpyAsync(hb.data(), b.sc.bnorm2, sizeof(double) * kk, hipMemcpyDeviceToHost, s));
+    NYS_HIP(hipStreamSynchronize(s));
+    for (int64_t c = 0; c < kk; ++c) {
+      if (only_done && !hd[c]) continue;
+      res.iters[map[c]] = hi[c];
+      res.status[map[c]] = hs[c];
+      res.rnorm2[map[c]] = hr[c];
+      res.bnorm2[map[c]] = hb[c];
+    }
+    return NYS_OK;
+  };
   int it = 0;
   int alldone_h = 0;
   NYS_HIP(hipMemcpyAsync(&alldone_h, b.sc.alldone, sizeof(int), hipMemcpyDeviceToHost, s));
   NYS_HIP(hipStreamSynchronize(s));
   while (!alldone_h && it < maxit) {
     const int par = it & 1;
+    // single column with a partial-sum operator product: fused iteration
+    const bool fused = kc == 1 && (op.kind == NYS_OP_XTX ||
+                                   (op.kind == NYS_OP_RBF && (sizeof(T) == 8 || op.lowp != nullptr)));
     if (fused) {
       int ng = 0;
       NYS_TRY(op_matvec_partials<T>(op, b.P, b.opscr, b.opscr_elems, &ng, s));
-      NYS_TRY(pcg_iteration_fused<T>(n, P, mu_dev, mu_host, b.opscr, ng, op.scale, b.V, X, b.R, b.Z, b.P, b.w,
-                                     b.sc, par, tol, s));
+      NYS_TRY(pcg_iteration_fused<T>(n, P, b.mu, mu_host[map[0]], b.opscr, ng, op.scale, b.V, Xc, b.R, b.Z,
+                                     b.P, b.w, b.sc, par, tol, s));
     } else {
-      NYS_TRY(matvec<T>(op, b.P, k, mu_dev, nrhs, mu_host, b.V, b, s));
-      NYS_TRY(pcg_iteration<T>(n, k, P, mu_dev, nrhs, b.V, X, k, b.R, b.Z, b.P, b.w, b.sc, par, tol, s));
+      NYS_TRY(matvec<T>(op, b.P, kc, b.mu, 1, mu_host[map[0]], b.V, b, s));
+      NYS_TRY(pcg_iteration<T>(n, kc, P, b.mu, 1, b.V, Xc, kc, b.R, b.Z, b.P, b.w, b.sc, par, tol, s));
     }
     ++it;
     if (it % check_every == 0 || it == maxit) {
       NYS_HIP(hipMemcpyAsync(&alldone_h, b.sc.alldone, sizeof(int), hipMemcpyDeviceToHost, s));
+      if (kc > 1) NYS_HIP(hipMemcpyAsync(hd.data(), b.sc.done, sizeof(int) * kc, hipMemcpyDeviceToHost, s));
       NYS_HIP(hipStreamSynchronize(s));
+      if (kc > 1 && !alldone_h && it < maxit) {
+        std::vector<int> keep;
+        for (int64_t c = 0; c < kc; ++c)
+          if (!hd[c]) keep.push_back((int)c);
+        const int64_t kn = (int64_t)keep.size();
+        if (kn > 0 && kn < kc) {
+          NYS_TRY(harvest(kc, true));
+          NYS_TRY(upload_indices(b.cidx, keep, s));
+          if (!compacted) {
+            // X keeps every column (the finished ones are final); work on a copy
+            hipLaunchKernelGGL((gather_idx<T, T>), dim3(nblk(n * kn)), dim3(256), 0, s, n, kc, X, b.cidx, kn,
+                               b.Xw);
+            NYS_CHECK_LAUNCH();
+            Xc = b.Xw;
+            compacted = true;
+          } else {
+            NYS_TRY(upload_indices(b.cmap, map, s));
+            hipLaunchKernelGGL(scatter_idx_same<T>, dim3(nblk(n * kc)), dim3(256), 0, s, n, kc, Xc, b.cmap, k, X);
+            hipLaunchKernelGGL((gather_idx<T, T>), dim3(nblk(n * kn)), dim3(256), 0, s, n, kc, Xc, b.cidx, kn,
+                               b.V);
+            NYS_CHECK_LAUNCH();
+            NYS_HIP(hipMemcpyAsync(Xc, b.V, sizeof(T) * n * kn, hipMemcpyDeviceToDevice, s));
+          }
+          hipLaunchKernelGGL((gather_idx<T, T>), dim3(nblk(n * kn)), dim3(256), 0, s, n, kc, b.R, b.cidx, kn, b.V);
+          NYS_CHECK_LAUNCH();
+          NYS_HIP(hipMemcpyAsync(b.R, b.V, sizeof(T) * n * kn, hipMemcpyDeviceToDevice, s));
+          hipLaunchKernelGGL((gather_idx<T, T>), dim3(nblk(n * kn)), dim3(256), 0, s, n, kc, b.P, b.cidx, kn, b.V);
+          NYS_CHECK_LAUNCH();
+          NYS_HIP(hipMemcpyAsync(b.P, b.V, sizeof(T) * n * kn, hipMemcpyDeviceToDevice, s));
+          hipLaunchKernelGGL(compact_scalars, dim3(1), dim3(256), 0, s, b.sc, b.mu, kc, b.cidx, kn);
+          NYS_CHECK_LAUNCH();
+          std::vector<int> nm(kn);
+          for (int64_t j = 0; j < kn; ++j) nm[j] = map[keep[j]];
+          map.swap(nm);
+          kc = kn;
+        }
+      }
     }
   }
-  res.iters.assign(k, 0);
-  res.status.assign(k, 0);
-  res.rnorm2.assign(k, 0.0);
-  res.bnorm2.assign(k, 0.0);
-  NYS_HIP(hipMemcpyAsync(res.iters.data(), b.sc.iters, sizeof(int) * k, hipMemcpyDeviceToHost, s));
-  NYS_HIP(hipMemcpyAsync(res.status.data(), b.sc.status, sizeof(int) * k, hipMemcpyDeviceToHost, s));
-  NYS_HIP(hipMemcpyAsync(res.rnorm2.data(), b.sc.rnorm2, sizeof(double) * k, hipMemcpyDeviceToHost, s));
-  NYS_HIP(hipMemcpyAsync(res.bnorm2.data(), b.sc.bnorm2, sizeof(double) * k, hipMemcpyDeviceToHost, s));
-  NYS_HIP(hipStreamSynchronize(s));
+  for (int64_t c = 0; c < kc; ++c) hd[c] = 1;
+  NYS_TRY(harvest(kc, false));
+  if (compacted) {
+    NYS_TRY(upload_indices(b.cmap, map, s));
+    hipLaunchKernelGGL(scatter_idx_same<T>, dim3(nblk(n * kc)), dim3(256), 0, s, n, kc, Xc, b.cmap, k, X);
+    NYS_CHECK_LAUNCH();
+  }
   res.sweeps = it;
   return NYS_OK;
 }
 
-// R64 = B64 - (A + mu I) X64 in float64; returns per-column relative residuals.
-nys_status true_residual(const OpDesc& op, int64_t k, int64_t nrhs, const double* mu_dev,
-                         const double* mu_host, SolveWs& w, std::vector<double>& relres,
-                         hipStream_t s) {
+// R64 = B64 - (A + mu_c I) X64 in float64 (mu_dev: one mu per column);
+// returns per-column relative residuals.
+nys_status true_residual(const OpDesc& op, int64_t k, const double* mu_dev, double mu0, SolveWs& w,
+                         std::vector<double>& relres, hipStream_t s) {
   const int64_t n = op.n;
   OpDesc o = op;
   o.skip = nullptr;
   if (k == 1 && (op.kind == NYS_OP_XTX || op.kind == NYS_OP_DENSE))
-    NYS_TRY(op_matvec<double>(o, w.X64, mu_host[0], w.V64, w.d.opscr, w.d.opscr_elems, s));
+    NYS_TRY(op_matvec<double>(o, w.X64, mu0, w.V64, w.d.opscr, w.d.opscr_elems, s));
   else
-    NYS_TRY(op_apply_f64(o, w.X64, k, k, mu_dev, nrhs, w.V64, k, w.d.opscr, w.d.opscr_elems, s));
+    NYS_TRY(op_apply_f64(o, w.X64, k, k, mu_dev, 1, w.V64, k, w.d.opscr, w.d.opscr_elems, s));
   const int g = 64;
   hipLaunchKernelGGL(residual_norms, dim3(g), dim3(256), 0, s, n, k, w.B64, w.V64, w.R64, w.dots);
   NYS_CHECK_LAUNCH();
@@ -503,7 +677,10 @@ nys_status solve_impl(const OpDesc& op, const PrecDesc& P, const double* mu, int
   const int maxit = o->maxit > 0 ? o->maxit : 500;
   const int check = o->check_every > 0 ? o->check_every : 8;
   const int prec = o->prec;
-  NYS_TRY(set_mu(w.mu, mu, nmu, s));
+  // one mu per column: column c = m * nrhs + r solves with mu[m]
+  std::vector<double> mu_col(k);
+  for (int64_t c = 0; c < k; ++c) mu_col[c] = mu[c / nrhs];
+  NYS_TRY(set_mu(w.mu, mu_col.data(), k, s));
   // contiguous float64 copies of B (expanded over the mu grid) and X
   hipLaunchKernelGGL((gather_cols<double, double>), dim3(nblk(n * k)), dim3(256), 0, s, n, k, B, ldb,
                      nrhs, w.B64, k);
@@ -514,7 +691,6 @@ nys_status solve_impl(const OpDesc& op, const PrecDesc& P, const double* mu, int
   std::vector<int> iters(k, 0), status(k, NYS_NOT_CONVERGED);
   std::vector<double> relres(k, 0.0);
   int refine_steps = 0, total = 0;
-  const double mu0 = mu[0];
   // operator for the float32 inner solves (prepared points for the RBF kernels)
   OpDesc opf = op;
   if (rbf_lowp_mode(op, prec)) {
@@ -524,11 +700,11 @@ nys_status solve_impl(const OpDesc& op, const PrecDesc& P, const double* mu, int
   }
   if (prec == NYS_PREC_FP64) {
     PcgResult r;
-    NYS_TRY(pcg_run<double>(op, P, k, nrhs, w.mu, mu0, w.B64, w.X64, false, tol, maxit, check, w.d, r, s));
+    NYS_TRY(pcg_run<double>(op, P, k, w.mu, mu_col, w.B64, w.X64, false, tol, maxit, check, w.d, r, s));
     iters = r.iters;
     status = r.status;
     total = r.sweeps;
-    NYS_TRY(true_residual(op, k, nrhs, w.mu, mu, w, relres, s));
+    NYS_TRY(true_residual(op, k, w.mu, mu_col[0], w, relres, s));
   } else if (prec == NYS_PREC_FP32) {
     hipLaunchKernelGGL((gather_cols<double, float>), dim3(nblk(n * k)), dim3(256), 0, s, n, k, w.B64, k,
                        k, w.f.B, k);
@@ -536,43 +712,53 @@ nys_status solve_impl(const OpDesc& op, const PrecDesc& P, const double* mu, int
                        k, w.f.X, k);
     NYS_CHECK_LAUNCH();
     PcgResult r;
-    NYS_TRY(pcg_run<float>(opf, P, k, nrhs, w.mu, mu0, w.f.B, w.f.X, false, tol, maxit, check, w.f, r, s));
+    NYS_TRY(pcg_run<float>(opf, P, k, w.mu, mu_col, w.f.B, w.f.X, false, tol, maxit, check, w.f, r, s));
     hipLaunchKernelGGL((gather_cols<float, double>), dim3(nblk(n * k)), dim3(256), 0, s, n, k, w.f.X, k,
                        k, w.X64, k);
     NYS_CHECK_LAUNCH();
     iters = r.iters;
     status = r.status;
     total = r.sweeps;
-    NYS_TRY(true_residual(op, k, nrhs, w.mu, mu, w, relres, s));
+    NYS_TRY(true_residual(op, k, w.mu, mu_col[0], w, relres, s));
   } else {
-    // iterative refinement: float64 residual and update, float32 inner PCG
+    // iterative refinement: float64 residual and update, float32 inner PCG on
+    // the columns that have not yet met the tolerance
     const int max_ref = o->max_refine > 0 ? o->max_refine : 10;
     const double itol = o->inner_tol > 0 ? o->inner_tol : 1e-4;
-    NYS_TRY(true_residual(op, k, nrhs, w.mu, mu, w, relres, s));
+    NYS_TRY(true_residual(op, k, w.mu, mu_col[0], w, relres, s));
     for (int step = 0; step < max_ref; ++step) {
-      bool all = true;
-      for (int64_t c = 0; c < k; ++c) all = all && relres[c] <= tol;
-      if (all) break;
-      hipLaunchKernelGGL((gather_cols<double, float>), dim3(nblk(n * k)), dim3(256), 0, s, n, k, w.R64,
-                         k, k, w.f.B, k);
+      std::vector<int> act;
+      std::vector<double> mu_act;
+      for (int64_t c = 0; c < k; ++c)
+        if (!(relres[c] <= tol)) {
+          act.push_back((int)c);
+          mu_act.push_back(mu_col[c]);
+        }
+      const int64_t ka = (int64_t)act.size();
+      if (ka == 0) break;
+      NYS_TRY(upload_indices(w.omap, act, s));
+      hipLaunchKernelGGL((gather_idx<double, float>), dim3(nblk(n * ka)), dim3(256), 0, s, n, k, w.R64, w.omap,
+                         ka, w.f.B);
+      hipLaunchKernelGGL((gather_idx<double, double>), dim3(1), dim3(256), 0, s, (int64_t)1, k, w.mu, w.omap, ka,
+                         w.mu_act);
       NYS_CHECK_LAUNCH();
       PcgResult r;
-      NYS_TRY(pcg_run<float>(opf, P, k, nrhs, w.mu, mu0, w.f.B, w.f.X, true, itol, maxit, check, w.f, r,
-                             s));
-      hipLaunchKernelGGL(add_to<float>, dim3(nblk(n * k)), dim3(256), 0, s, w.X64, w.f.X, n * k);
+      NYS_TRY(pcg_run<float>(opf, P, ka, w.mu_act, mu_act, w.f.B, w.f.X, true, itol, maxit, check, w.f, r, s));
+      hipLaunchKernelGGL((scatter_idx<float, true>), dim3(nblk(n * ka)), dim3(256), 0, s, n, ka, w.f.X, w.omap, k,
+                         w.X64);
       NYS_CHECK_LAUNCH();
-      for (int64_t c = 0; c < k; ++c) {
-        iters[c] += r.iters[c];
-        if (r.status[c] == NYS_ERR_BREAKDOWN) status[c] = NYS_ERR_BREAKDOWN;
+      for (int64_t j = 0; j < ka; ++j) {
+        iters[act[j]] += r.iters[j];
+        if (r.status[j] == NYS_ERR_BREAKDOWN) status[act[j]] = NYS_ERR_BREAKDOWN;
       }
       total += r.sweeps;
       ++refine_steps;
-      NYS_TRY(true_residual(op, k, nrhs, w.mu, mu, w, relres, s));
+      NYS_TRY(true_residual(op, k, w.mu, mu_col[0], w, relres, s));
       if (verbose()) {
         double worst = 0.0;
         for (int64_t c = 0; c < k; ++c) worst = relres[c] > worst ? relres[c] : worst;
-        std::fprintf(stderr, "[nyspcg] refinement %d: inner iterations %d, max relres %.3e\n", refine_steps,
-                     r.sweeps, worst);
+        std::fprintf(stderr, "[nyspcg] refinement %d: %lld columns, inner iterations %d, max relres %.3e\n",
+                     refine_steps, (long long)ka, r.sweeps, worst);
         std::fflush(stderr);
       }
     }
@@ -653,7 +839,10 @@ size_t nys_workspace_size(const nys_operator* A, int64_t ell, int64_t ncols, int
     Arena a(nullptr, 0);
     SolveWs w;
     carve_solve(a, op, ell, ncols, prec, w);
-    size_t extra = (size_t)(4 * 256) * (size_t)op.n * sizeof(double) + rbf_lowp_bytes(op.n) + 4096;
+    // the adjoint's extra buffers: two row vectors, dot partials and the dK/dsigma partials
+    const int64_t rmax = op.rows > op.n ? op.rows : op.n;
+    size_t extra = (size_t)(4 * 256) * (size_t)op.n * sizeof(double) + 2 * (size_t)rmax * sizeof(double) +
+                   rbf_lowp_bytes(op.n) + 8192 + 4 * 256;
     best = a.off + extra > best ? a.off + extra : best;
   }
   return best + 256;
@@ -1014,30 +1203,22 @@ nys_status nys_rbf_cross(const nys_operator* A, const void* Xv, int64_t nv, int6
   NYS_ARG(op.kind == NYS_OP_RBF, "nys_rbf_cross needs an RBF operator");
   NYS_ARG(Xv && nv >= 1 && ldxv >= op.cols && v && out, "nys_rbf_cross: invalid arguments");
   const int64_t n = op.n;
-  const int64_t nr = transpose ? n : nv;
   Arena a(ws, ws_bytes);
   const size_t se = (size_t)(4 * 256) * (size_t)(n > nv ? n : nv);
   double* scr = a.take<double>(se);
-  double* tmp = a.take<double>(nv);
   double* part = a.take<double>(256);
   if (!ws || !a.ok()) {
     set_error("workspace too small: need %zu bytes", a.off);
     return NYS_ERR_WORKSPACE;
   }
   hipStream_t s = S(stream);
-  if (!transpose)
-    NYS_TRY(rbf_rect_mv(Xv, nv, ldxv, op.data, n, op.ld, (int)op.cols, op.dtype, op.sigma, 0, v, out, scr,
+  if (wvec || dsig_out) {
+    NYS_ARG(wvec != nullptr && dsig_out != nullptr && !transpose,
+            "nys_rbf_cross: the dK/dsigma form needs wvec, dsig_out and transpose = 0");
+    // out = (dK(Xv, X)/dsigma) wvec (nv), then v^T out
+    NYS_TRY(rbf_rect_mv(Xv, nv, ldxv, op.data, n, op.ld, (int)op.cols, op.dtype, op.sigma, 1, wvec, out, scr,
                         se, s));
-  else
-    NYS_TRY(rbf_rect_mv(op.data, n, op.ld, Xv, nv, ldxv, (int)op.cols, op.dtype, op.sigma, 0, v, out, scr,
-                        se, s));
-  (void)nr;
-  if (dsig_out) {
-    NYS_ARG(wvec != nullptr && !transpose, "nys_rbf_cross: dsig_out needs wvec and transpose = 0");
-    // u^T (dK(Xv, X)/dsigma) w with u = v (nv), w = wvec (n)
-    NYS_TRY(rbf_rect_mv(Xv, nv, ldxv, op.data, n, op.ld, (int)op.cols, op.dtype, op.sigma, 1, wvec, tmp,
-                        scr, se, s));
-    hipLaunchKernelGGL(dot_partial, dim3(256), dim3(256), 0, s, v, tmp, nv, part);
+    hipLaunchKernelGGL(dot_partial, dim3(256), dim3(256), 0, s, v, out, nv, part);
     NYS_CHECK_LAUNCH();
     std::vector<double> h(256);
     NYS_HIP(hipMemcpyAsync(h.data(), part, sizeof(double) * 256, hipMemcpyDeviceToHost, s));
@@ -1045,8 +1226,11 @@ nys_status nys_rbf_cross(const nys_operator* A, const void* Xv, int64_t nv, int6
     double d = 0.0;
     for (int i = 0; i < 256; ++i) d += h[i];
     *dsig_out = d;
+    return NYS_OK;
   }
-  return NYS_OK;
+  if (!transpose)
+    return rbf_rect_mv(Xv, nv, ldxv, op.data, n, op.ld, (int)op.cols, op.dtype, op.sigma, 0, v, out, scr, se, s);
+  return rbf_rect_mv(op.data, n, op.ld, Xv, nv, ldxv, (int)op.cols, op.dtype, op.sigma, 0, v, out, scr, se, s);
 }
 
 }  // extern "C"

@@ -280,9 +280,14 @@ def test_rbf_cross_products():
     np.testing.assert_allclose(out, Kv @ u, rtol=1e-12, atol=1e-12)
     out_t = h(nys.nys_rbf_cross(op, t64(Xv), t64(v), transpose=True))
     np.testing.assert_allclose(out_t, Kv.T @ v, rtol=1e-12, atol=1e-12)
-    _, ds = nys.nys_rbf_cross(op, t64(Xv), t64(v), wvec=t64(u))
+    # dK/dsigma form: v has nv entries, wvec n entries (a regression case: the
+    # call must not read v as an n-vector)
+    dv, ds = nys.nys_rbf_cross(op, t64(Xv), t64(v), wvec=t64(u))
     d2 = ((Xv[:, None, :] - Xtr[None, :, :]) ** 2).sum(-1)
+    np.testing.assert_allclose(h(dv), (Kv * d2 / 4.0 ** 3) @ u, rtol=1e-11, atol=1e-13)
     assert ds == pytest.approx(float(v @ ((Kv * d2 / 4.0 ** 3) @ u)), rel=1e-11)
+    with pytest.raises(ValueError):
+        nys.nys_rbf_cross(op, t64(Xv), t64(u), wvec=t64(u))
 
 
 def test_determinism_bitwise():
@@ -396,3 +401,39 @@ def test_rbf_block_mu_grid_float_refine():
     for m, mu in enumerate(mus):
         for r in range(2):
             assert oracle.true_relres(op_ref, mu, X[:, m * 2 + r], B[:, r]) <= 1e-10
+
+
+@pytest.mark.parametrize("kind,check_every", [("rbf", 1), ("rbf", 8), ("xtx", 4)])
+def test_block_column_compaction(kind, check_every):
+    """A wide mu grid makes columns finish at very different iterations; the
+    block solve drops finished columns from the products at each poll.  Every
+    column must still reach the tolerance (oracle residual) in the iteration
+    count of its own single-column solve, and land at that solve's x."""
+    if kind == "rbf":
+        w, op_ref, b = _krr(500, 30, 45)
+        op = nys.Operator.rbf(t64(w["X"]), w["sigma"])
+        ell, om0 = 30, w["omega0"]
+    else:
+        w = ridge_dense(m=1500, n=400, ell=40, seed=46)
+        op_ref = oracle.XtXOp(w["X"])
+        b = w["X"].astype(np.float64).T @ w["y"]
+        op = nys.Operator.xtx(t64(w["X"].astype(np.float64)))
+        ell, om0 = 40, w["omega0"]
+    n = op_ref.n
+    rng = np.random.default_rng(47)
+    B = np.stack([b] + [rng.standard_normal(n) for _ in range(3)], axis=1)
+    mus = list(np.logspace(-5, 0, 10))
+    P = nys.nys_factor(*nys.nys_sketch(op, ell, omega0=t64(om0)))
+    X, info = nys.nys_pcg_solve(op, P, mus, t64(B), tol=1e-10, maxit=4000, check_every=check_every)
+    X = h(X)
+    assert len(set(info.iters)) > 3  # columns really finish at different points
+    for m, mu in enumerate(mus):
+        for r in range(B.shape[1]):
+            c = m * B.shape[1] + r
+            assert info.status[c] == 0
+            assert oracle.true_relres(op_ref, mu, X[:, c], B[:, r]) <= 1e-10
+            if (m + r) % 7 == 0:  # a spread of single-column comparisons
+                x1, i1 = nys.nys_pcg_solve(op, P, mu, t64(B[:, r]), tol=1e-10, maxit=4000)
+                assert abs(i1.iters[0] - info.iters[c]) <= max(2, info.iters[c] // 20)
+                kappa = 1.0 + 10.0 / mu
+                assert rel(X[:, c], h(x1)) <= 1e-9 * kappa
