@@ -35,6 +35,30 @@ HBM_PEAK_GBS = 8000.0
 EXP_PEAK_GPS = 256 * 4 * 4 * 2.4
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "xtx_fused_ridge_20000x4000_pmc.txt")
+XTX_SOURCE = os.path.join(ROOT, "paper_2110_02820_amd", "csrc", "xtx.hip")
+
+
+def measured_traffic():
+    """HBM bytes per launch of the float32 X^T X product, from the committed
+    FETCH_SIZE / WRITE_SIZE counter summary; None when the summary is missing or
+    the kernel source has changed since the counters were taken."""
+    import hashlib
+    try:
+        with open(TRAFFIC_FILE) as f:
+            kv = dict(line.split(":", 1) for line in f if ":" in line and not line.startswith("#"))
+        with open(XTX_SOURCE, "rb") as f:
+            sha = hashlib.sha256(f.read()).hexdigest()
+    except OSError:
+        return None
+    if kv.get("kernel_source_sha256", "").strip() != sha:
+        return None
+    try:
+        return float(kv["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 def log(msg):
     print("# " + msg, file=sys.stderr, flush=True)
 
@@ -157,7 +181,7 @@ def run_ridge(args, nys, torch):
          "relres": max(i.relres[0] for i in infos), "iters": infos[-1].iters[0],
          "refine_steps": infos[-1].refine_steps, "phase_ms": phases,
          "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
                       "kernel": "one X^T X product: xtx_fused<float,float> + reduce_cols",
                       "avg_ms": mv_ms, "alg_bytes": alg_bytes}})
     if not args.no_plain:

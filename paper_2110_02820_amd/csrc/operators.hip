@@ -2,19 +2,15 @@
 // touched only through products), gfx950.
 //
 //  * dense    : row-per-wave GEMV (k = 1) or the MFMA GEMM (k > 1)
-//  * X^T X    : one pass over X per product (Section 1.4 ridge normal
-//               equations).  Each workgroup owns a contiguous range of rows of
-//               X, keeps R rows in registers, forms t_r = x_r^T p with a block
-//               reduction and immediately accumulates t_r x_r into a per-
-//               workgroup partial of X^T t held in registers.  X is read from
-//               HBM exactly once; a second kernel sums the partials in fixed
-//               order (deterministic) and adds mu p.
+//  * X^T X    : one pass over X per single-vector product (xtx.hip); MFMA
+//               GEMMs X^T (X P) for blocks of columns
 //  * RBF      : K_ij = exp(-||x_i - x_j||^2 / (2 sigma^2)) evaluated tile by
 //               tile and never stored (Section 6.3 kernel ridge regression).
 //               float64 forms: a VALU kernel for one vector, and an MFMA
 //               (v_mfma_f64_16x16x4f64) kernel for blocks of columns
 //               (the sketch A Omega, block PCG).
 #include "operators.hpp"
+#include "xtx.hpp"
 #include "gemm.hpp"
 #include "rbf_lowp.hpp"
 
@@ -49,142 +45,6 @@ __global__ void add_mu(T* __restrict__ V, int64_t ldv, const T* __restrict__ P, 
   if (idx >= n * k) return;
   const int64_t i = idx / k, c = idx % k;
   V[i * ldv + c] += T(mu[c / nrhs]) * P[i * ldp + c];
-}
-
-// ------------------------------------------------------------- X^T X
-
-template <typename TD>
-struct Vec16;
-template <>
-struct Vec16<float> {
-  typedef float4 type;
-  static constexpr int E = 4;
-  static __device__ __forceinline__ float get(const float4& v, int e) {
-    return e == 0 ? v.x : e == 1 ? v.y : e == 2 ? v.z : v.w;
-  }
-};
-template <>
-struct Vec16<double> {
-  typedef double2 type;
-  static constexpr int E = 2;
-  static __device__ __forceinline__ double get(const double2& v, int e) { return e == 0 ? v.x : v.y; }
-};
-// one element per load: rows that are not 16-byte aligned
-template <typename TD>
-struct Vec1 {
-  typedef TD type;
-  static constexpr int E = 1;
-  static __device__ __forceinline__ TD get(const TD& v, int) { return v; }
-};
-
-// part[g][j] = sum over rows r of this workgroup of (x_r^T p) x_r[j]
-// (accumulated in TA).  Requires n <= 256 * NV * E and 16-byte aligned rows.
-template <typename TD, typename TA, typename VP, int NV, int R>
-__global__ __launch_bounds__(256) void xtx_fused(const TD* __restrict__ X, int64_t m, int64_t n,
-                                                 int64_t ld, const TA* __restrict__ p,
-                                                 TA* __restrict__ part, int64_t rows_per_wg,
-                                                 const int* __restrict__ skip) {
-  if (skip && *skip) return;
-  typedef typename VP::type VT;
-  constexpr int E = VP::E;
-  __shared__ TA red[2][4][R];
-  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-  TA pr[NV][E];
-  TA acc[NV][E];
-#pragma unroll
-  for (int v = 0; v < NV; ++v)
-#pragma unroll
-    for (int e = 0; e < E; ++e) {
-      const int64_t col = ((int64_t)v * 256 + t) * E + e;
-      pr[v][e] = col < n ? p[col] : TA(0);
-      acc[v][e] = TA(0);
-    }
-  const int64_t r0 = (int64_t)blockIdx.x * rows_per_wg;
-  const int64_t r1 = (r0 + rows_per_wg < m) ? r0 + rows_per_wg : m;
-  const int64_t nvec = n / E;  // full vectors per row
-  int buf = 0;
-  for (int64_t rb = r0; rb < r1; rb += R) {
-    VT xr[R][NV];
-#pragma unroll
-    for (int r = 0; r < R; ++r)
-#pragma unroll
-      for (int v = 0; v < NV; ++v) {
-        const int64_t vi = (int64_t)v * 256 + t;
-        if (rb + r < r1 && vi < nvec) {
-          xr[r][v] = *reinterpret_cast<const VT*>(X + (rb + r) * ld + vi * E);
-        } else {
-          VT z;
-          for (int e = 0; e < E; ++e) reinterpret_cast<TD*>(&z)[e] = TD(0);
-          // tail elements of a row whose length is not a multiple of E
-          if (rb + r < r1 && vi == nvec)
-            for (int e = 0; e < E; ++e)
-              if (vi * E + e < n) reinterpret_cast<TD*>(&z)[e] = X[(rb + r) * ld + vi * E + e];
-          xr[r][v] = z;
-        }
-      }
-    TA d[R];
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      TA s = TA(0);
-#pragma unroll
-      for (int v = 0; v < NV; ++v)
-#pragma unroll
-        for (int e = 0; e < E; ++e) s += TA(VP::get(xr[r][v], e)) * pr[v][e];
-      d[r] = wave_sum(s);
-    }
-    if (lane == 0) {
-#pragma unroll
-      for (int r = 0; r < R; ++r) red[buf][wave][r] = d[r];
-    }
-    __syncthreads();
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const TA tr = red[buf][0][r] + red[buf][1][r] + red[buf][2][r] + red[buf][3][r];
-#pragma unroll
-      for (int v = 0; v < NV; ++v)
-#pragma unroll
-        for (int e = 0; e < E; ++e) acc[v][e] += tr * TA(VP::get(xr[r][v], e));
-    }
-    buf ^= 1;  // the other buffer is free: its readers passed this barrier
-  }
-  TA* out = part + (int64_t)blockIdx.x * n;
-#pragma unroll
-  for (int v = 0; v < NV; ++v)
-#pragma unroll
-    for (int e = 0; e < E; ++e) {
-      const int64_t col = ((int64_t)v * 256 + t) * E + e;
-      if (col < n) out[col] = acc[v][e];
-    }
-}
-
-// out[j] = alpha * sum_g part[g][j] + beta * y[j].  Block = 32 columns x 8
-// slices of g; each thread sums its slice with two accumulators, then the
-// slices are combined in order in LDS (fixed order: deterministic).
-template <typename TA, typename TO>
-__global__ __launch_bounds__(256) void reduce_cols(const TA* __restrict__ part, int ng, int64_t n, TA alpha,
-                                                   const TO* __restrict__ y, TA beta, TO* __restrict__ out,
-                                                   const int* __restrict__ skip) {
-  if (skip && *skip) return;
-  __shared__ TA sh[8][33];
-  const int c = threadIdx.x & 31, sl = threadIdx.x >> 5;
-  const int64_t j = (int64_t)blockIdx.x * 32 + c;
-  TA a0 = TA(0), a1 = TA(0);
-  if (j < n) {
-    int g = sl;
-    for (; g + 8 < ng; g += 16) {
-      a0 += part[(int64_t)g * n + j];
-      a1 += part[(int64_t)(g + 8) * n + j];
-    }
-    if (g < ng) a0 += part[(int64_t)g * n + j];
-  }
-  sh[sl][c] = a0 + a1;
-  __syncthreads();
-  if (sl == 0 && j < n) {
-    TA s = ((sh[0][c] + sh[1][c]) + (sh[2][c] + sh[3][c])) + ((sh[4][c] + sh[5][c]) + (sh[6][c] + sh[7][c]));
-    TA o = alpha * s;
-    if (y) o += beta * TA(y[j]);
-    out[j] = TO(o);
-  }
 }
 
 // ------------------------------------------------------------- RBF, float64
@@ -419,55 +279,6 @@ nys_status rbf_apply_f64_t(const OpDesc& op, const double* P, int64_t k, int64_t
   return NYS_OK;
 }
 
-template <typename TD, typename TA>
-nys_status xtx_partials_t(const OpDesc& op, const TA* p, TA* scratch, size_t scratch_elems, int* ng_out,
-                          hipStream_t s) {
-  const TD* X = static_cast<const TD*>(op.data);
-  const int64_t m = op.rows, n = op.n;
-  constexpr int E = Vec16<TD>::E;
-  const bool aligned = (op.ld % E == 0) && ((uintptr_t)X % 16 == 0);
-  const int64_t need_nv = aligned ? cdiv(n, 256 * E) : cdiv(n, 256);
-  int64_t ng = (num_cus() < 256 ? num_cus() : 256);
-  const int64_t R = 4;
-  if (ng > cdiv(m, R)) ng = cdiv(m, R);
-  if (ng < 1) ng = 1;
-  while (ng > 1 && (size_t)(ng * n) > scratch_elems) ng /= 2;
-  int64_t rpw = cdiv(cdiv(m, ng), R) * R;
-  ng = cdiv(m, rpw);
-  if ((aligned && need_nv > 8) || (!aligned && need_nv > 32)) {
-    set_error("X^T X operator: n = %lld too large for the one-pass kernel", (long long)n);
-    return NYS_ERR_ARG;
-  }
-#define LX(VP_, NV, RR) hipLaunchKernelGGL((xtx_fused<TD, TA, VP_, NV, RR>), dim3((unsigned)ng), dim3(256), 0, s, X, m, n, op.ld, p, scratch, rpw, op.skip)
-  if (aligned) {
-    if (need_nv <= 1) LX(Vec16<TD>, 1, 4);
-    else if (need_nv <= 2) LX(Vec16<TD>, 2, 4);
-    else if (need_nv <= 4) LX(Vec16<TD>, 4, 4);
-    else LX(Vec16<TD>, 8, 2);
-  } else {
-    if (need_nv <= 4) LX(Vec1<TD>, 4, 4);
-    else if (need_nv <= 8) LX(Vec1<TD>, 8, 4);
-    else if (need_nv <= 16) LX(Vec1<TD>, 16, 4);
-    else LX(Vec1<TD>, 32, 2);
-  }
-#undef LX
-  NYS_CHECK_LAUNCH();
-  *ng_out = (int)ng;
-  return NYS_OK;
-}
-
-template <typename TD, typename TA>
-nys_status xtx_apply_t(const OpDesc& op, const TA* p, TA mu, TA* v, TA* scratch,
-                       size_t scratch_elems, hipStream_t s) {
-  int ng = 0;
-  NYS_TRY((xtx_partials_t<TD, TA>(op, p, scratch, scratch_elems, &ng, s)));
-  const int64_t n = op.n;
-  hipLaunchKernelGGL((reduce_cols<TA, TA>), dim3((unsigned)cdiv(n, 32)), dim3(256), 0, s, scratch,
-                     ng, n, TA(op.scale), p, mu, v, op.skip);
-  NYS_CHECK_LAUNCH();
-  return NYS_OK;
-}
-
 template <typename TD>
 nys_status rbf_rect_t(const TD* Xr, int64_t nr, int64_t ldr, const TD* Xc, int64_t nc, int64_t ldc,
                       int d, double sigma, int mode, const double* p, double* out, double* scratch,
@@ -551,8 +362,8 @@ nys_status op_apply_f64(const OpDesc& op, const double* P, int64_t k, int64_t ld
   if (op.kind == NYS_OP_XTX) {
     if (k == 1 && ldp == 1 && ldv == 1 && !mu_dev) {
       if (op.dtype == NYS_F64)
-        return xtx_apply_t<double, double>(op, P, 0.0, V, scratch, scratch_elems, s);
-      return xtx_apply_t<float, double>(op, P, 0.0, V, scratch, scratch_elems, s);
+        return xtx_apply<double, double>(op, P, 0.0, V, scratch, scratch_elems, s);
+      return xtx_apply<float, double>(op, P, 0.0, V, scratch, scratch_elems, s);
     }
     // T = X P (m x k) then V = scale X^T T
     double* T = scratch;
@@ -593,8 +404,8 @@ nys_status op_matvec(const OpDesc& op, const TA* p, TA mu, TA* v, TA* scratch, s
                      hipStream_t s) {
   const int64_t n = op.n;
   if (op.kind == NYS_OP_XTX) {
-    if (op.dtype == NYS_F64) return xtx_apply_t<double, TA>(op, p, mu, v, scratch, scratch_elems, s);
-    return xtx_apply_t<float, TA>(op, p, mu, v, scratch, scratch_elems, s);
+    if (op.dtype == NYS_F64) return xtx_apply<double, TA>(op, p, mu, v, scratch, scratch_elems, s);
+    return xtx_apply<float, TA>(op, p, mu, v, scratch, scratch_elems, s);
   }
   if (op.kind == NYS_OP_DENSE) {
     if (op.dtype == NYS_F64)
@@ -621,8 +432,8 @@ nys_status op_matvec_partials<double>(const OpDesc& op, const double* p, double*
   const int64_t n = op.n;
   if (op.kind == NYS_OP_XTX) {
     const int64_t m = op.rows;
-    if (op.dtype == NYS_F64) return xtx_partials_t<double, double>(op, p, part, part_elems, ng_out, s);
-    return xtx_partials_t<float, double>(op, p, part, part_elems, ng_out, s);
+    if (op.dtype == NYS_F64) return xtx_partials<double, double>(op, p, part, part_elems, ng_out, s);
+    return xtx_partials<float, double>(op, p, part, part_elems, ng_out, s);
     (void)m;
   }
   if (op.kind == NYS_OP_RBF) {
@@ -659,8 +470,8 @@ nys_status op_matvec_partials<float>(const OpDesc& op, const float* p, float* pa
   if (op.kind == NYS_OP_RBF && op.lowp)
     return rbf_lowp_mv_partials(*op.lowp, op.gram, p, part, part_elems, ng_out, op.skip, s);
   if (op.kind == NYS_OP_XTX) {
-    if (op.dtype == NYS_F64) return xtx_partials_t<double, float>(op, p, part, part_elems, ng_out, s);
-    return xtx_partials_t<float, float>(op, p, part, part_elems, ng_out, s);
+    if (op.dtype == NYS_F64) return xtx_partials<double, float>(op, p, part, part_elems, ng_out, s);
+    return xtx_partials<float, float>(op, p, part, part_elems, ng_out, s);
   }
   set_error("op_matvec_partials: float32 form needs X^T X or a prepared RBF operator");
   return NYS_ERR_ARG;
