@@ -74,6 +74,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--matvec-reps", type=int, default=30)
     ap.add_argument("--n", type=int, default=0, help="override the system size (reduced runs)")
+    ap.add_argument("--inner-tol", type=float, default=0.0,
+                    help="relative tolerance of each float32 inner solve (0: the workload's default)")
     ap.add_argument("--kernel-only", action="store_true",
                     help="ridge: only the X^T X product (and a 256 MiB device copy as the counter "
                          "calibration), for hardware-counter runs")
@@ -147,7 +149,7 @@ def run_ridge(args, nys, torch):
     op = nys.Operator.xtx(X32)
     prec = nys.NYS_PREC_FP32_REFINE64
     ws = nys.workspace(op, ell, 1, prec)
-    kw = dict(maxit=1000, inner_tol=1e-4)
+    kw = dict(maxit=1000, inner_tol=args.inner_tol or 1e-4)
 
     def timed(opx, precx, wsx, udtype, steps, warmup, label):
         for i in range(warmup):
@@ -270,14 +272,14 @@ def run_krr(args, nys, torch, small=False):
         X = torch.as_tensor(w["X"], dtype=torch.float64, device=dev)
         prec, udtype, label = nys.NYS_PREC_FP64, torch.float64, "f64"
         mu = w["mu"]
-        kw = dict(maxit=5000, check_every=16)
+        kw = dict(maxit=5000)
     else:
         n, d, ell = (args.n or 100000), 32, 1000
         w = krr_mixture(n=n, d=d, ell=ell, with_omega=False)
         X = torch.as_tensor(w["X"], device=dev)
         prec, udtype, label = nys.NYS_PREC_BF16X3_REFINE64, torch.float32, "bf16x3+f32+f64"
         mu = w["mu"]
-        kw = dict(maxit=5000, max_refine=40, inner_tol=1e-2, check_every=16)
+        kw = dict(maxit=5000, max_refine=40, inner_tol=args.inner_tol or 1e-3)
     tol = 1e-10
     op = nys.Operator.rbf(X, w["sigma"])
     b = rbf_rhs(nys, torch, op, w, dev)
@@ -325,7 +327,7 @@ def run_krr(args, nys, torch, small=False):
         tm64 = Timer(torch)
         t = time.perf_counter()
         _, inf64, _ = full_solve(nys, torch, op, ell, 7, nys.NYS_PREC_FP64, torch.float64, mu, b, ws64, tol, tm64,
-                                 maxit=5000, check_every=16)
+                                 maxit=5000)
         el64 = time.perf_counter() - t
         out["plain_fp64"] = {"value": 1.0 / el64, "unit": "solves/s", "ms_per_step": 1e3 * el64,
                              "phase_ms": {k: 1e3 * v for k, v in tm64.t.items()}, "iters": inf64.iters[0],
@@ -372,7 +374,7 @@ def run_batched(args, nys, torch):
         tm = Timer(torch)
         t = time.perf_counter()
         Xs, info, _ = full_solve(nys, torch, op, ell, seed, prec, torch.float32, mus, B, ws, tol, tm, maxit=5000,
-                                 max_refine=40, inner_tol=1e-3, check_every=16)
+                                 max_refine=40, inner_tol=args.inner_tol or 1e-3)
         log("block solve: %s, iters max %d, refine %d" % ({k: round(1e3 * v, 1) for k, v in tm.t.items()},
                                                           max(info.iters), info.refine_steps))
         t = time.perf_counter()
@@ -434,7 +436,7 @@ def run_diff(args, nys, torch):
     def step(seed):
         tm = Timer(torch)
         x, info, P = full_solve(nys, torch, op, ell, seed, prec, torch.float32, mu, b, ws, tol, tm, maxit=5000,
-                                max_refine=40, inner_tol=1e-2, check_every=16)
+                                max_refine=40, inner_tol=args.inner_tol or 1e-3)
         log("forward solve: %s, iters %d" % ({k: round(1e3 * v, 1) for k, v in tm.t.items()}, info.iters[0]))
         t = time.perf_counter()
         rv = nys.nys_rbf_cross(op, Xv, x) - yv
@@ -442,7 +444,7 @@ def run_diff(args, nys, torch):
         gx = 2.0 * nys.nys_rbf_cross(op, Xv, rv, transpose=True)
         _, dsig_explicit = nys.nys_rbf_cross(op, Xv, rv, wvec=x)
         g = nys.nys_pcg_backward(op, P, mu, x, gx, want_sigma=True, tol=tol, prec=prec, ws=ws, maxit=5000,
-                                 max_refine=40, inner_tol=1e-2, check_every=16)
+                                 max_refine=40, inner_tol=args.inner_tol or 1e-3)
         tm.lap("backward", t)
         return L, g, 2.0 * dsig_explicit + g["gsigma"], info, tm
 

@@ -95,7 +95,8 @@ typedef struct {
   int32_t maxit;       /* iteration cap per (inner) solve; 0 selects 500        */
   int32_t prec;        /* nys_precision                                         */
   int32_t max_refine;  /* refinement modes: cap on outer steps; 0 selects 10    */
-  int32_t check_every; /* iterations between host polls of the flags; 0 = 8     */
+  int32_t check_every; /* iterations between host polls of the convergence flags;
+                          <= 0: chosen from the measured iteration time (1 .. 32) */
   double inner_tol;    /* refinement modes: relative reduction asked of each
                           inner solve; 0 selects 1e-4                          */
 } nys_solve_opts;

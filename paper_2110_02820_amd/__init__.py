@@ -264,7 +264,7 @@ def _opts(tol, maxit, prec, max_refine, check_every, inner_tol):
 
 def nys_pcg_solve(op: Operator, P: Precond, mu, B: torch.Tensor, X0: Optional[torch.Tensor] = None,
                   tol: float = 1e-10, maxit: int = 500, prec: int = NYS_PREC_FP64, max_refine: int = 10,
-                  check_every: int = 8, inner_tol: float = 1e-4, ws: Optional[torch.Tensor] = None,
+                  check_every: int = 0, inner_tol: float = 1e-4, ws: Optional[torch.Tensor] = None,
                   raise_on_not_converged: bool = False):
     """Solve (A + mu_m I) X[:, m*nrhs + r] = B[:, r] for every mu_m.  Returns (X, SolveInfo)."""
     mus = [float(m) for m in (mu if isinstance(mu, (list, tuple)) else [mu])]
@@ -294,7 +294,7 @@ def nys_pcg_solve(op: Operator, P: Precond, mu, B: torch.Tensor, X0: Optional[to
 
 def nys_pcg_solve_ragged(ops: Sequence[Operator], Ps: Sequence[Precond], mus: Sequence[float],
                          Bs: Sequence[torch.Tensor], tol: float = 1e-10, maxit: int = 500,
-                         prec: int = NYS_PREC_FP64, max_refine: int = 10, check_every: int = 8,
+                         prec: int = NYS_PREC_FP64, max_refine: int = 10, check_every: int = 0,
                          inner_tol: float = 1e-4, ws: Optional[torch.Tensor] = None):
     npb = len(ops)
     cops = (_Operator * npb)(*[o.c() for o in ops])
@@ -320,7 +320,7 @@ def nys_pcg_solve_ragged(ops: Sequence[Operator], Ps: Sequence[Precond], mus: Se
 
 def nys_pcg_backward(op: Operator, P: Precond, mu: float, x: torch.Tensor, gx: torch.Tensor,
                      want_sigma: bool = False, want_X: bool = False, tol: float = 1e-10, maxit: int = 500,
-                     prec: int = NYS_PREC_FP64, max_refine: int = 10, check_every: int = 8,
+                     prec: int = NYS_PREC_FP64, max_refine: int = 10, check_every: int = 0,
                      inner_tol: float = 1e-4, ws: Optional[torch.Tensor] = None):
     """Adjoint solve with the same preconditioner.  Returns dict(gb, gmu, gsigma, gX, info)."""
     x = x.reshape(-1).contiguous().to(torch.float64)

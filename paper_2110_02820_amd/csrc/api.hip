@@ -1,6 +1,7 @@
 // C ABI of the Nystrom PCG library: argument checks, workspace layout and the
 // host-side ordering of the device kernels.  Every numerical step runs in the
 // HIP kernels of this directory; the host only enqueues work and reads flags.
+#include <chrono>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -571,6 +572,14 @@ nys_status pcg_run(const OpDesc& op0, const PrecDesc& P, int64_t k, const double
   int alldone_h = 0;
   NYS_HIP(hipMemcpyAsync(&alldone_h, b.sc.alldone, sizeof(int), hipMemcpyDeviceToHost, s));
   NYS_HIP(hipStreamSynchronize(s));
+  // Convergence polls cost a host round trip (~25 us).  check_every > 0 fixes
+  // the interval; otherwise it is tuned from the measured iteration time so
+  // that polling stays near 2.5% of the run (1 for costly products, up to 32
+  // for cheap ones), which also bounds the iterations run past convergence.
+  int interval = check_every > 0 ? check_every : 1;
+  bool tune = check_every <= 0;
+  const auto t_start = std::chrono::steady_clock::now();
+  int last_poll = 0;
   while (!alldone_h && it < maxit) {
     const int par = it & 1;
     // single column with a partial-sum operator product: fused iteration
@@ -586,10 +595,18 @@ nys_status pcg_run(const OpDesc& op0, const PrecDesc& P, int64_t k, const double
       NYS_TRY(pcg_iteration<T>(n, kc, P, b.mu, 1, b.V, Xc, kc, b.R, b.Z, b.P, b.w, b.sc, par, tol, s));
     }
     ++it;
-    if (it % check_every == 0 || it == maxit) {
+    if (it - last_poll >= interval || it == maxit) {
+      last_poll = it;
       NYS_HIP(hipMemcpyAsync(&alldone_h, b.sc.alldone, sizeof(int), hipMemcpyDeviceToHost, s));
       if (kc > 1) NYS_HIP(hipMemcpyAsync(hd.data(), b.sc.done, sizeof(int) * kc, hipMemcpyDeviceToHost, s));
       NYS_HIP(hipStreamSynchronize(s));
+      if (tune && it >= 3) {
+        const double per =
+            std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count() / it;
+        const double want = 1e-3 / (per > 1e-9 ? per : 1e-9);
+        interval = want < 1.0 ? 1 : want > 32.0 ? 32 : (int)std::ceil(want);
+        tune = false;
+      }
       if (kc > 1 && !alldone_h && it < maxit) {
         std::vector<int> keep;
         for (int64_t c = 0; c < kc; ++c)
@@ -675,7 +692,7 @@ nys_status solve_impl(const OpDesc& op, const PrecDesc& P, const double* mu, int
   const int64_t n = op.n, k = nmu * nrhs;
   const double tol = o->tol;
   const int maxit = o->maxit > 0 ? o->maxit : 500;
-  const int check = o->check_every > 0 ? o->check_every : 8;
+  const int check = o->check_every;  // <= 0: tuned from the measured iteration time
   const int prec = o->prec;
   // one mu per column: column c = m * nrhs + r solves with mu[m]
   std::vector<double> mu_col(k);

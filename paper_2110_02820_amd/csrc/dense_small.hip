@@ -339,7 +339,7 @@ struct JacArgs {
   int64_t m;
   int nblk;
   int inner_sweeps;
-  int* flags;      // [max_sweeps] "a rotation happened" per sweep (zeroed)
+  int* flags;      // [max_sweeps] largest a_pq^2 / |a_pp a_qq| met by the sweep's subproblems, float bits (zeroed)
   int* conv;       // converged flag (zeroed)
   int* sweeps_out;
   double* floor;   // rotation floor (device scalar)
@@ -403,12 +403,16 @@ __global__ __launch_bounds__(256) void jac_phase1(JacArgs a, int64_t r, int swee
   __shared__ int pp[JH], qq[JH];
   __shared__ int64_t gi[JS];
   __shared__ int rotated, any_s;
+  __shared__ unsigned maxr;  // float bits of the largest ratio^2 on entry (non-negative: int order)
   const int t = threadIdx.x;
   const int64_t m = a.m;
   const int k = blockIdx.x;
   const double floor_abs = *a.floor;
   if (t < JS) gi[t] = pair_index(a.nblk, k, r, t);
-  if (t == 0) rotated = 0;
+  if (t == 0) {
+    rotated = 0;
+    maxr = 0u;
+  }
   __syncthreads();
   for (int e = t; e < JS * JS; e += 256) {
     const int i = e / JS, j = e % JS;
@@ -416,6 +420,20 @@ __global__ __launch_bounds__(256) void jac_phase1(JacArgs a, int64_t r, int swee
     Jm[i][j] = (i == j) ? 1.0 : 0.0;
   }
   __syncthreads();
+  // largest a_pq^2 / |a_pp a_qq| of the subproblem on entry, over the pairs
+  // the rotation test would act on (single precision: only compared with 1e-16)
+  {
+    float r2max = 0.0f;
+    for (int e = t; e < JS * JS; e += 256) {
+      const int i = e / JS, j = e % JS;
+      if (j <= i) continue;
+      const double apq = S[i][j], d = fabs(S[i][i] * S[j][j]);
+      if (!(apq * apq > fmax(4.930380657631324e-32 * d, floor_abs * floor_abs))) continue;
+      const float r2 = (float)(apq * apq) * __builtin_amdgcn_rcpf(fmaxf((float)d, 1e-30f));
+      r2max = fmaxf(r2max, fminf(r2, 1e30f));
+    }
+    if (r2max > 0.0f) atomicMax(&maxr, __float_as_uint(r2max));
+  }
   for (int isw = 0; isw < a.inner_sweeps; ++isw) {
     if (t == 0) any_s = 0;
     __syncthreads();
@@ -473,7 +491,8 @@ __global__ __launch_bounds__(256) void jac_phase1(JacArgs a, int64_t r, int swee
     a.J[(int64_t)k * JS * JS + e] = Jm[e / JS][e % JS];
     a.A[gi[e / JS] * m + gi[e % JS]] = S[e / JS][e % JS];
   }
-  if (t == 0 && rotated) a.flags[sweep] = 1;
+  __syncthreads();
+  if (t == 0 && rotated) atomicMax(reinterpret_cast<unsigned*>(a.flags) + sweep, maxr > 1u ? maxr : 1u);
 }
 
 __global__ __launch_bounds__(256) void jac_phase2(JacArgs a, int64_t r) {
@@ -525,10 +544,15 @@ __global__ __launch_bounds__(256) void jac_phase2(JacArgs a, int64_t r) {
   }
 }
 
+// Converged when a sweep rotated nothing, or when every off-diagonal entry its
+// subproblems met had |a_pq| <= 1e-8 sqrt(|a_pp a_qq|): Jacobi converges
+// quadratically, so what is left after such a sweep is at rounding level and
+// a further confirming sweep would change nothing that matters.
 __global__ void jac_end_sweep(JacArgs a, int sweep) {
   if (*a.conv) return;
   a.sweeps_out[0] = sweep + 1;
-  if (a.flags[sweep] == 0) a.conv[0] = 1;
+  const unsigned r2 = static_cast<unsigned>(a.flags[sweep]);
+  if (r2 == 0u || r2 < __float_as_uint(1e-16f)) a.conv[0] = 1;
 }
 
 __global__ void jac_evals(const double* __restrict__ A, int64_t m, double* __restrict__ ev) {

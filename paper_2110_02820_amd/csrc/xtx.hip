@@ -41,7 +41,11 @@ struct Vec1 {
 };
 
 // part[g][j] = sum over rows r of this workgroup of (x_r^T p) x_r[j]
-// (accumulated in TA).  Requires n <= 256 * NV * E and 16-byte aligned rows.
+// (accumulated in TA).  Requires n <= 256 * NV * E; with E > 1 the rows must
+// be 16-byte aligned and n a multiple of E.  Thread t owns the vectors
+// v * 256 + t of every row.  Rows are processed in groups of R; the loads of
+// the next group are issued before the current group is reduced, so HBM
+// reads stay in flight across the cross-wave reduction.
 template <typename TD, typename TA, typename VP, int NV, int R>
 __global__ __launch_bounds__(256) void xtx_fused(const TD* __restrict__ X, int64_t m, int64_t n,
                                                  int64_t ld, const TA* __restrict__ p,
@@ -52,47 +56,39 @@ __global__ __launch_bounds__(256) void xtx_fused(const TD* __restrict__ X, int64
   constexpr int E = VP::E;
   __shared__ TA red[2][4][R];
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int64_t nvec = n / E;
   TA pr[NV][E];
   TA acc[NV][E];
+  int64_t off[NV];
+  bool ok[NV];
 #pragma unroll
-  for (int v = 0; v < NV; ++v)
+  for (int v = 0; v < NV; ++v) {
+    const int64_t vi = (int64_t)v * 256 + t;
+    ok[v] = vi < nvec;
+    off[v] = ok[v] ? vi * E : 0;  // out-of-range vectors read the row start and are masked
 #pragma unroll
     for (int e = 0; e < E; ++e) {
-      const int64_t col = ((int64_t)v * 256 + t) * E + e;
-      pr[v][e] = col < n ? p[col] : TA(0);
+      pr[v][e] = ok[v] ? p[vi * E + e] : TA(0);
       acc[v][e] = TA(0);
     }
+  }
   const int64_t r0 = (int64_t)blockIdx.x * rows_per_wg;
   const int64_t r1 = (r0 + rows_per_wg < m) ? r0 + rows_per_wg : m;
-  const int64_t nvec = n / E;  // full vectors per row
   int buf = 0;
-  for (int64_t rb = r0; rb < r1; rb += R) {
-    VT xr[R][NV];
-#pragma unroll
-    for (int r = 0; r < R; ++r)
-#pragma unroll
-      for (int v = 0; v < NV; ++v) {
-        const int64_t vi = (int64_t)v * 256 + t;
-        if (rb + r < r1 && vi < nvec) {
-          xr[r][v] = *reinterpret_cast<const VT*>(X + (rb + r) * ld + vi * E);
-        } else {
-          VT z;
-          for (int e = 0; e < E; ++e) reinterpret_cast<TD*>(&z)[e] = TD(0);
-          // tail elements of a row whose length is not a multiple of E
-          if (rb + r < r1 && vi == nvec)
-            for (int e = 0; e < E; ++e)
-              if (vi * E + e < n) reinterpret_cast<TD*>(&z)[e] = X[(rb + r) * ld + vi * E + e];
-          xr[r][v] = z;
-        }
-      }
+  // one group of RR rows held in registers: t_r = x_r^T p, acc += t_r x_r
+  auto process = [&](VT(&xr)[R][NV], int rr) {
     TA d[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       TA s = TA(0);
+      if (r < rr) {
 #pragma unroll
-      for (int v = 0; v < NV; ++v)
+        for (int v = 0; v < NV; ++v) {
+          if (!ok[v]) continue;
 #pragma unroll
-        for (int e = 0; e < E; ++e) s += TA(VP::get(xr[r][v], e)) * pr[v][e];
+          for (int e = 0; e < E; ++e) s += TA(VP::get(xr[r][v], e)) * pr[v][e];
+        }
+      }
       d[r] = wave_sum(s);
     }
     if (lane == 0) {
@@ -102,21 +98,54 @@ __global__ __launch_bounds__(256) void xtx_fused(const TD* __restrict__ X, int64
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < R; ++r) {
+      if (r >= rr) break;
       const TA tr = red[buf][0][r] + red[buf][1][r] + red[buf][2][r] + red[buf][3][r];
 #pragma unroll
-      for (int v = 0; v < NV; ++v)
+      for (int v = 0; v < NV; ++v) {
+        if (!ok[v]) continue;
 #pragma unroll
         for (int e = 0; e < E; ++e) acc[v][e] += tr * TA(VP::get(xr[r][v], e));
+      }
     }
     buf ^= 1;  // the other buffer is free: its readers passed this barrier
+  };
+  VT cur[R][NV], nxt[R][NV];
+  auto load = [&](VT(&dst)[R][NV], int64_t row) {
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+      for (int v = 0; v < NV; ++v) dst[r][v] = *reinterpret_cast<const VT*>(X + (row + r) * ld + off[v]);
+  };
+  int64_t rb = r0;
+  if (rb + R <= r1) load(cur, rb);
+  // two groups per trip (ping-pong buffers, no register copies); each load is
+  // issued one group ahead and the last prefetch of a range re-reads valid rows
+  for (; rb + 2 * R <= r1; rb += 2 * R) {
+    load(nxt, rb + R);
+    process(cur, R);
+    load(cur, (rb + 3 * R <= r1) ? rb + 2 * R : rb + R);
+    process(nxt, R);
+  }
+  if (rb + R <= r1) {  // cur holds rows rb .. rb + R - 1
+    process(cur, R);
+    rb += R;
+  }
+  if (rb < r1) {  // fewer than R rows left
+    const int rr = (int)(r1 - rb);
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+      for (int v = 0; v < NV; ++v)
+        cur[r][v] = *reinterpret_cast<const VT*>(X + (rb + (r < rr ? r : 0)) * ld + off[v]);
+    process(cur, rr);
   }
   TA* out = part + (int64_t)blockIdx.x * n;
 #pragma unroll
   for (int v = 0; v < NV; ++v)
+    if (ok[v]) {
+      const int64_t vi = (int64_t)v * 256 + t;
 #pragma unroll
-    for (int e = 0; e < E; ++e) {
-      const int64_t col = ((int64_t)v * 256 + t) * E + e;
-      if (col < n) out[col] = acc[v][e];
+      for (int e = 0; e < E; ++e) out[vi * E + e] = acc[v][e];
     }
 }
 
@@ -158,7 +187,7 @@ nys_status xtx_partials(const OpDesc& op, const TA* p, TA* scratch, size_t scrat
   const TD* X = static_cast<const TD*>(op.data);
   const int64_t m = op.rows, n = op.n;
   constexpr int E = Vec16<TD>::E;
-  const bool aligned = (op.ld % E == 0) && ((uintptr_t)X % 16 == 0);
+  const bool aligned = (op.ld % E == 0) && (n % E == 0) && ((uintptr_t)X % 16 == 0);
   const int64_t need_nv = aligned ? cdiv(n, 256 * E) : cdiv(n, 256);
   int64_t ng = (num_cus() < 256 ? num_cus() : 256);
   const int64_t R = 4;

@@ -430,8 +430,11 @@ def test_block_column_compaction(kind, check_every):
     for m, mu in enumerate(mus):
         for r in range(B.shape[1]):
             c = m * B.shape[1] + r
-            assert info.status[c] == 0
-            assert oracle.true_relres(op_ref, mu, X[:, c], B[:, r]) <= 1e-10
+            assert info.status[c] == 0 and info.relres[c] <= 1e-10
+            # the oracle re-evaluates the residual; at mu = 1e-5 the product
+            # K x carries rounding of order eps ||K|| ||x|| (~1e-12 of ||b||),
+            # so the two float64 evaluations may straddle 1e-10 by that much
+            assert oracle.true_relres(op_ref, mu, X[:, c], B[:, r]) <= 1.02e-10
             if (m + r) % 7 == 0:  # a spread of single-column comparisons
                 x1, i1 = nys.nys_pcg_solve(op, P, mu, t64(B[:, r]), tol=1e-10, maxit=4000)
                 assert abs(i1.iters[0] - info.iters[c]) <= max(2, info.iters[c] // 20)
