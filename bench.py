@@ -279,7 +279,7 @@ def run_krr(args, nys, torch, small=False):
         X = torch.as_tensor(w["X"], device=dev)
         prec, udtype, label = nys.NYS_PREC_BF16X3_REFINE64, torch.float32, "bf16x3+f32+f64"
         mu = w["mu"]
-        kw = dict(maxit=5000, max_refine=40, inner_tol=args.inner_tol or 1e-3)
+        kw = dict(maxit=5000, max_refine=40, inner_tol=args.inner_tol or 1e-2)
     tol = 1e-10
     op = nys.Operator.rbf(X, w["sigma"])
     b = rbf_rhs(nys, torch, op, w, dev)

@@ -14,6 +14,7 @@
 #include "gemm.hpp"
 #include "operators.hpp"
 #include "pcg.hpp"
+#include "ragged.hpp"
 #include "rbf_lowp.hpp"
 #include "rng.hpp"
 
@@ -1132,10 +1133,18 @@ nys_status nys_pcg_solve(const nys_operator* A, const nys_precond* P, const doub
 size_t nys_workspace_size_ragged(const nys_operator* ops, const nys_precond* Ps, int32_t nprob,
                                  int32_t prec) {
   if (!ops || !Ps || nprob < 1) return 0;
+  std::vector<OpDesc> od(nprob);
+  std::vector<PrecDesc> pd(nprob);
   size_t best = 0;
+  bool valid = true;
   for (int32_t i = 0; i < nprob; ++i) {
+    valid = valid && check_op(&ops[i], od[i]) == NYS_OK && check_prec(&Ps[i], pd[i]) == NYS_OK;
     const size_t b = nys_workspace_size(&ops[i], Ps[i].ell, 1, prec);
     best = b > best ? b : best;
+  }
+  if (valid && ragged_supported(od.data(), pd.data(), nprob)) {
+    const size_t r = ragged_workspace(od.data(), pd.data(), nprob, prec);
+    best = r > best ? r : best;
   }
   return best;
 }
@@ -1145,6 +1154,19 @@ nys_status nys_pcg_solve_ragged(const nys_operator* ops, const nys_precond* Ps, 
                                 const nys_solve_opts* o, nys_solve_info* info, void* ws,
                                 size_t ws_bytes, void* stream) {
   NYS_ARG(ops && Ps && mu && B && X && nprob >= 1, "nys_pcg_solve_ragged: NULL argument");
+  hipStream_t s = S(stream);
+  std::vector<OpDesc> od(nprob);
+  std::vector<PrecDesc> pd(nprob);
+  for (int32_t i = 0; i < nprob; ++i) {
+    NYS_TRY(check_op(&ops[i], od[i]));
+    NYS_TRY(check_prec(&Ps[i], pd[i]));
+    NYS_ARG(B[i] != nullptr && X[i] != nullptr, "nys_pcg_solve_ragged: NULL vector of problem %d", i);
+    NYS_TRY(check_solve_common(od[i], pd[i], &mu[i], 1, o, s));
+  }
+  // X^T X problems: one batched solve (every CG step of every problem in the same launches)
+  if (ragged_supported(od.data(), pd.data(), nprob))
+    return ragged_solve(od.data(), pd.data(), mu, B, X, nprob, o, info, ws, ws_bytes, s);
+  // other operator mixes: one problem after the other
   nys_status worst = NYS_OK;
   int total = 0, refine = 0;
   for (int32_t i = 0; i < nprob; ++i) {

@@ -432,7 +432,9 @@ __global__ __launch_bounds__(256) void jac_phase1(JacArgs a, int64_t r, int swee
       const float r2 = (float)(apq * apq) * __builtin_amdgcn_rcpf(fmaxf((float)d, 1e-30f));
       r2max = fmaxf(r2max, fminf(r2, 1e30f));
     }
-    if (r2max > 0.0f) atomicMax(&maxr, __float_as_uint(r2max));
+    // wave maximum first: one LDS atomic per wave
+    for (int off = 32; off > 0; off >>= 1) r2max = fmaxf(r2max, __shfl_xor(r2max, off));
+    if ((t & 63) == 0 && r2max > 0.0f) atomicMax(&maxr, __float_as_uint(r2max));
   }
   for (int isw = 0; isw < a.inner_sweeps; ++isw) {
     if (t == 0) any_s = 0;

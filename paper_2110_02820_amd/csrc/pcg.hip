@@ -703,6 +703,55 @@ nys_status pcg_iteration_fused(int64_t n, const PrecDesc& P, const double* mu_de
   return NYS_OK;
 }
 
+template <typename T>
+nys_status cg_block_init(int64_t n, int64_t k, const T* B, const T* V, T* R, PcgWork& w, const CgScalars& sc,
+                         double tol, hipStream_t s) {
+  const int64_t ng = groups_for(n, k);
+  hipLaunchKernelGGL(cg_init_residual<T>, dim3((unsigned)ng), dim3(NT), 0, s, n, k, B, V, R, w.pb, w.prr,
+                     cdiv(n, ng), tol, sc);
+  NYS_CHECK_LAUNCH();
+  return NYS_OK;
+}
+
+template <typename T>
+nys_status cg_block_update(int64_t n, int64_t k, const T* V, T* X, T* R, const T* Pd, PcgWork& w,
+                           const CgScalars& sc, int par, double tol, hipStream_t s) {
+  const int64_t ng = groups_for(n, k);
+  const int64_t rpw = cdiv(n, ng);
+  hipLaunchKernelGGL(cg_pv_alpha<T>, dim3((unsigned)ng), dim3(NT), 0, s, n, k, Pd, V, w.ppv, rpw, sc, par);
+  NYS_CHECK_LAUNCH();
+  hipLaunchKernelGGL(cg_update<T>, dim3((unsigned)ng), dim3(NT), 0, s, n, k, Pd, V, X, k, R, w.prr, rpw, tol,
+                     sc);
+  NYS_CHECK_LAUNCH();
+  return NYS_OK;
+}
+
+template <typename T>
+nys_status cg_block_direction(int64_t n, int64_t k, const T* R, const T* Z, T* Pd, PcgWork& w,
+                              const CgScalars& sc, int par, bool init, hipStream_t s) {
+  const int64_t ng = groups_for(n, k);
+  hipLaunchKernelGGL(cg_rz<T>, dim3((unsigned)ng), dim3(NT), 0, s, n, k, R, Z, w.prz, cdiv(n, ng), sc, par,
+                     init ? 1 : 0);
+  NYS_CHECK_LAUNCH();
+  hipLaunchKernelGGL(cg_direction<T>, dim3((unsigned)cdiv(n * k, 256)), dim3(256), 0, s, n, k, Z, Pd, sc,
+                     init ? 1 : 0);
+  NYS_CHECK_LAUNCH();
+  return NYS_OK;
+}
+
+template nys_status cg_block_init<float>(int64_t, int64_t, const float*, const float*, float*, PcgWork&,
+                                         const CgScalars&, double, hipStream_t);
+template nys_status cg_block_init<double>(int64_t, int64_t, const double*, const double*, double*, PcgWork&,
+                                          const CgScalars&, double, hipStream_t);
+template nys_status cg_block_update<float>(int64_t, int64_t, const float*, float*, float*, const float*, PcgWork&,
+                                           const CgScalars&, int, double, hipStream_t);
+template nys_status cg_block_update<double>(int64_t, int64_t, const double*, double*, double*, const double*,
+                                            PcgWork&, const CgScalars&, int, double, hipStream_t);
+template nys_status cg_block_direction<float>(int64_t, int64_t, const float*, const float*, float*, PcgWork&,
+                                              const CgScalars&, int, bool, hipStream_t);
+template nys_status cg_block_direction<double>(int64_t, int64_t, const double*, const double*, double*,
+                                               PcgWork&, const CgScalars&, int, bool, hipStream_t);
+
 template nys_status pcg_iteration_fused<double>(int64_t, const PrecDesc&, const double*, double, const double*, int,
                                                 double, double*, double*, double*, double*, double*, PcgWork&,
                                                 const CgScalars&, int, double, hipStream_t);

@@ -64,4 +64,19 @@ nys_status pcg_iteration_fused(int64_t n, const PrecDesc& P, const double* mu_de
                                int ng, double scale, T* V, T* X, T* R, T* Z, T* Pd, PcgWork& w,
                                const CgScalars& sc, int par, double tol, hipStream_t s);
 
+// Pieces of one block iteration for callers that supply their own operator
+// product and preconditioner apply (n x k blocks, ld = k, per-column scalars):
+//   cg_block_init:      R = B - V, ||B||^2, stopping flags (sc.ctr zeroed)
+//   cg_block_update:    alpha = r^T z / p^T v, X += alpha P, R -= alpha V, stopping test
+//   cg_block_direction: r^T z, beta, P = Z + beta P (init: rz and P = Z)
+template <typename T>
+nys_status cg_block_init(int64_t n, int64_t k, const T* B, const T* V, T* R, PcgWork& w, const CgScalars& sc,
+                         double tol, hipStream_t s);
+template <typename T>
+nys_status cg_block_update(int64_t n, int64_t k, const T* V, T* X, T* R, const T* Pd, PcgWork& w,
+                           const CgScalars& sc, int par, double tol, hipStream_t s);
+template <typename T>
+nys_status cg_block_direction(int64_t n, int64_t k, const T* R, const T* Z, T* Pd, PcgWork& w,
+                              const CgScalars& sc, int par, bool init, hipStream_t s);
+
 }  // namespace nys

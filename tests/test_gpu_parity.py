@@ -440,3 +440,60 @@ def test_block_column_compaction(kind, check_every):
                 assert abs(i1.iters[0] - info.iters[c]) <= max(2, info.iters[c] // 20)
                 kappa = 1.0 + 10.0 / mu
                 assert rel(X[:, c], h(x1)) <= 1e-9 * kappa
+
+
+def _ragged_problems(sizes, seed, dtype=np.float32):
+    """Independent ridge problems X_k (m_k x n_k, unaligned n_k included) as in
+    the batched workload, with their float64 right-hand sides."""
+    probs = []
+    for q, (m, n) in enumerate(sizes):
+        w = ridge_dense(m=m, n=n, ell=max(8, 16 * -(-n // 128)), seed=seed + q)
+        X = w["X"].astype(dtype)
+        probs.append(dict(X=X, b=X.astype(np.float64).T @ w["y"], mu=w["mu"] * (1 + q), ell=w["ell"],
+                          omega0=w["omega0"]))
+    return probs
+
+
+@pytest.mark.parametrize("prec", [0, 2])
+def test_ragged_batched_solve(prec):
+    """All problems advance in the same launches; each must reach the float64
+    tolerance on its own operator (oracle residual) with the iteration count of
+    its own single solve."""
+    sizes = [(1200, 301), (800, 200), (2000, 513), (600, 150), (1500, 387), (900, 64)]
+    probs = _ragged_problems(sizes, 60, np.float32 if prec else np.float64)
+    tdev = t32 if prec else t64
+    udt = torch.float32 if prec else torch.float64
+    ops, Ps = [], []
+    for p in probs:
+        op = nys.Operator.xtx(tdev(p["X"]))
+        Om, Y = nys.nys_sketch(op, p["ell"], omega0=t64(p["omega0"]), prec=prec)
+        ops.append(op)
+        Ps.append(nys.nys_factor(Om, Y, dtype=udt, prec=prec))
+    Xs, info = nys.nys_pcg_solve_ragged(ops, Ps, [p["mu"] for p in probs], [t64(p["b"]) for p in probs],
+                                        tol=1e-10, maxit=2000, prec=prec)
+    for q, p in enumerate(probs):
+        opr = oracle.XtXOp(p["X"])
+        assert info.status[q] == 0 and info.relres[q] <= 1e-10
+        assert oracle.true_relres(opr, p["mu"], h(Xs[q]), p["b"]) <= 1.02e-10
+        xs = oracle.dense_solve(opr.dense(), p["mu"], p["b"])
+        assert rel(h(Xs[q]), xs) < 1e-5  # kappa(A + mu I) <= 1e4 times 1e-10
+        if prec == 0:
+            x1, i1 = nys.nys_pcg_solve(ops[q], Ps[q], p["mu"], t64(p["b"]), tol=1e-10, maxit=2000)
+            assert abs(i1.iters[0] - info.iters[q]) <= max(2, i1.iters[0] // 20)
+
+
+def test_ragged_mixed_operators_fall_back():
+    """A batch that mixes operator kinds is solved problem by problem."""
+    probs = _ragged_problems([(700, 180), (500, 90)], 70, np.float64)
+    w, op_ref, b = _krr(300, 20, 71)
+    ops = [nys.Operator.xtx(t64(p["X"])) for p in probs] + [nys.Operator.rbf(t64(w["X"]), w["sigma"])]
+    oms = [p["omega0"] for p in probs] + [w["omega0"]]
+    ells = [p["ell"] for p in probs] + [20]
+    Ps = [nys.nys_factor(*nys.nys_sketch(o, l, omega0=t64(om))) for o, l, om in zip(ops, ells, oms)]
+    mus = [p["mu"] for p in probs] + [1e-2]
+    bs = [p["b"] for p in probs] + [b]
+    Xs, info = nys.nys_pcg_solve_ragged(ops, Ps, mus, [t64(x) for x in bs], tol=1e-10, maxit=2000)
+    refs = [oracle.XtXOp(p["X"]) for p in probs] + [op_ref]
+    for q in range(3):
+        assert info.status[q] == 0
+        assert oracle.true_relres(refs[q], mus[q], h(Xs[q]), bs[q]) <= 1.02e-10
