@@ -361,6 +361,8 @@ def run_batched(args, nys, torch):
     B = torch.as_tensor(w["B"], device=dev)
     mus = [float(m) for m in w["mus"]]
     ell = w["ell"]
+    # float32 Gram tiles: at the smallest mu of the grid (n 1e-8) the bf16x3
+    # perturbation of K exceeds mu and K + mu I is no longer definite
     prec = nys.NYS_PREC_FP32_REFINE64
     ws = nys.workspace(op, ell, len(mus) * B.shape[1], prec)
     rag = w["ragged"]
@@ -409,7 +411,8 @@ def run_batched(args, nys, torch):
         args, nsolves * args.steps / el, 1e3 * el / args.steps, "f32+f64",
         {"workload": "batched cross-validation: RBF n=%d d=16 l=%d, 32 mu x 8 rhs in one block solve, plus 64 "
                      "ragged ridge problems (n_k = m_k/4, m_k in [1000, 20000])" % (n, ell),
-         "precision": "float32 inner PCG + float64 refinement", "step": "all 320 solves incl. sketches"},
+         "precision": "float32 Gram tiles (RBF) / float32 data (ridge), float32 inner PCG, float64 refinement",
+         "step": "all 320 solves incl. sketches"},
         {"correct": ok, "phase_ms": phases, "solves_per_step": nsolves,
          "block_iters_max": max(infos[-1][0].iters), "block_refine": infos[-1][0].refine_steps})
 

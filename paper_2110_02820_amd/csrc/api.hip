@@ -461,12 +461,18 @@ nys_status set_mu(double* mu_dev, const double* mu, int64_t nmu, hipStream_t s) 
 
 // ---------------------------------------------------------------- CholQR
 
-// Omega <- Omega C^{-1} with C^T C = Omega^T Omega, using tmp (n x l); twice.
-nys_status cholqr2(double* Om, double* tmp, int64_t n, int64_t l, Core& c, int* info_host,
-                   hipStream_t s) {
+// Omega <- Omega C^{-1} with C^T C = Omega^T Omega (CholeskyQR), using tmp
+// (n x l).  One pass leaves ||Q^T Q - I|| of order kappa(Omega)^2 u; a Gaussian
+// n x l matrix with n >= 3 l has kappa <= (sqrt(3) + 1)/(sqrt(3) - 1) ~ 3.7
+// with overwhelming probability, so one pass is orthonormal to ~1e-15 there;
+// squarer test matrices, and any caller-supplied matrix, get a second pass.
+nys_status cholqr(double* Om, double* tmp, int64_t n, int64_t l, bool gaussian, Core& c, int* info_host,
+                  hipStream_t s) {
+  const int passes = gaussian && n >= 3 * l ? 1 : 2;
+  info_host[0] = info_host[1] = 0;
   double* src = Om;
   double* dst = tmp;
-  for (int pass = 0; pass < 2; ++pass) {
+  for (int pass = 0; pass < passes; ++pass) {
     NYS_TRY((gemm<double, double, double>(true, false, l, l, n, 1.0, src, l, src, l, 0.0, c.G, l,
                                           c.gscr, c.gscr_elems, s)));
     NYS_TRY(cholesky(c.G, l, c.L, c.Dinv, c.info, s));
@@ -478,7 +484,8 @@ nys_status cholqr2(double* Om, double* tmp, int64_t n, int64_t l, Core& c, int* 
     src = dst;
     dst = t;
   }
-  return NYS_OK;  // after two passes the result is back in Om
+  if (src != Om) NYS_HIP(hipMemcpyAsync(Om, src, sizeof(double) * n * l, hipMemcpyDeviceToDevice, s));
+  return NYS_OK;
 }
 
 // ---------------------------------------------------------------- PCG core
@@ -780,14 +787,23 @@ nys_status solve_impl(const OpDesc& op, const PrecDesc& P, const double* mu, int
     const int max_ref = o->max_refine > 0 ? o->max_refine : 10;
     const double itol = o->inner_tol > 0 ? o->inner_tol : 1e-4;
     NYS_TRY(true_residual(op, k, w.mu, mu_col[0], w, relres, s));
+    std::vector<double> prev(relres);
     for (int step = 0; step < max_ref; ++step) {
       std::vector<int> act;
       std::vector<double> mu_act;
-      for (int64_t c = 0; c < k; ++c)
+      for (int64_t c = 0; c < k; ++c) {
+        // a column whose inner solve broke down, whose residual grew (the
+        // reduced-precision operator is not positive definite at this mu) or
+        // stagnated (less than a 2x reduction: the float64 residual is at its
+        // rounding floor) is not refined further; it is reported as not
+        // converged unless it already meets tol
+        if (step > 0 && (status[c] == NYS_ERR_BREAKDOWN || !(relres[c] <= 0.5 * prev[c]))) continue;
         if (!(relres[c] <= tol)) {
           act.push_back((int)c);
           mu_act.push_back(mu_col[c]);
         }
+      }
+      prev = relres;
       const int64_t ka = (int64_t)act.size();
       if (ka == 0) break;
       NYS_TRY(upload_indices(w.omap, act, s));
@@ -930,7 +946,7 @@ nys_status nys_sketch(const nys_operator* A, int64_t ell, uint64_t seed, const d
   if (omega0) NYS_HIP(hipMemcpyAsync(Omega, omega0, sizeof(double) * n * l, hipMemcpyDeviceToDevice, s));
   else NYS_TRY(gaussian(seed, n, l, Omega, l, s));
   int info[2] = {0, 0};
-  NYS_TRY(cholqr2(Omega, Y, n, l, w.c, info, s));
+  NYS_TRY(cholqr(Omega, Y, n, l, omega0 == nullptr, w.c, info, s));
   if (rbf_lowp_mode(op, prec)) {
     NYS_ARG(op.cols <= 32, "reduced-precision RBF modes need d <= 32");
     // Y = K Omega with the reduced-precision Gram tiles, float32 accumulation

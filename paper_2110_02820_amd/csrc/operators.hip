@@ -78,7 +78,9 @@ __global__ __launch_bounds__(256) void rbf_mv_f64(const TD* __restrict__ Xr, int
   }
   const int64_t j0 = (int64_t)blockIdx.y * pts_per_split;
   const int64_t j1 = (j0 + pts_per_split < nc) ? j0 + pts_per_split : nc;
-  double acc = 0.0;
+  // compensated (Kahan) sum over the points of this split: the float64
+  // residual of a refinement step must stay accurate when x is large
+  double acc = 0.0, comp = 0.0;
   for (int64_t jt = j0; jt < j1; jt += RB_PTS) {
     __syncthreads();
     for (int e = t; e < RB_PTS * DMAX; e += 256) {
@@ -100,10 +102,13 @@ __global__ __launch_bounds__(256) void rbf_mv_f64(const TD* __restrict__ Xr, int
       for (int k = 0; k < DMAX; ++k) g += xi[k] * Xs[jj][k];
       const double d2 = fmax(ni + Ns[jj] - 2.0 * g, 0.0);
       const double kv = exp(-d2 * c2);
-      acc += (MODE == 0 ? kv : kv * d2 * inv_s3) * Ps[jj];
+      const double y = (MODE == 0 ? kv : kv * d2 * inv_s3) * Ps[jj] - comp;
+      const double ts = acc + y;
+      comp = (ts - acc) - y;
+      acc = ts;
     }
   }
-  Red[q][il] = acc;
+  Red[q][il] = acc - comp;
   __syncthreads();
   if (q == 0 && i < nr)
     part[(int64_t)blockIdx.y * nr + i] = Red[0][il] + Red[1][il] + Red[2][il] + Red[3][il];
@@ -142,11 +147,16 @@ __global__ __launch_bounds__(256) void rbf_kv_f64(const TD* __restrict__ X, int6
     for (int kk = 0; kk < DMAX; ++kk) s += Xi[t][kk] * Xi[t][kk];
     Ni[t] = s;
   }
-  d4 acc[2][2];
+  // the per-tile MFMA products are summed over tiles with a compensation term
+  // (TwoSum), so long point ranges keep float64 accuracy
+  d4 acc[2][2], cmp[2][2];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b) acc[a][b] = d4{0, 0, 0, 0};
+    for (int b = 0; b < 2; ++b) {
+      acc[a][b] = d4{0, 0, 0, 0};
+      cmp[a][b] = d4{0, 0, 0, 0};
+    }
   for (int64_t jt = j0; jt < j1; jt += RB_PTS) {
     __syncthreads();
     for (int e = t; e < RB_PTS * DMAX; e += 256) {
@@ -174,7 +184,12 @@ __global__ __launch_bounds__(256) void rbf_kv_f64(const TD* __restrict__ X, int6
       Ks[jj][ii] = (jt + jj < j1) ? exp(-d2 * c2) : 0.0;
     }
     __syncthreads();
-    // acc(64 rows x 64 cols) += K(64 x 64 pts) * P(64 pts x 64 cols)
+    // tile(64 rows x 64 cols) = K(64 x 64 pts) * P(64 pts x 64 cols), then acc += tile
+    d4 tl[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) tl[a][b] = d4{0, 0, 0, 0};
 #pragma unroll 4
     for (int kk = 0; kk < RB_PTS; kk += 4) {
       const int kq = kk + (lane >> 4);
@@ -182,12 +197,29 @@ __global__ __launch_bounds__(256) void rbf_kv_f64(const TD* __restrict__ X, int6
       const double a1 = Ks[kq][wm * 32 + 16 + (lane & 15)];
       const double b0 = Ps[kq][wn * 32 + (lane & 15)];
       const double b1 = Ps[kq][wn * 32 + 16 + (lane & 15)];
-      acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
-      acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
-      acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
-      acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+      tl[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, tl[0][0], 0, 0, 0);
+      tl[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, tl[0][1], 0, 0, 0);
+      tl[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, tl[1][0], 0, 0, 0);
+      tl[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, tl[1][1], 0, 0, 0);
     }
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int qq = 0; qq < 4; ++qq) {
+          const double x = acc[a][b][qq], y = tl[a][b][qq];
+          const double sm = x + y, bb = sm - x;
+          cmp[a][b][qq] += (x - (sm - bb)) + (y - bb);
+          acc[a][b][qq] = sm;
+        }
   }
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int qq = 0; qq < 4; ++qq) acc[a][b][qq] += cmp[a][b][qq];
   double* o = out + (int64_t)blockIdx.z * n * ldo;
 #pragma unroll
   for (int a = 0; a < 2; ++a)

@@ -633,6 +633,10 @@ nys_status ragged_solve(const OpDesc* ops, const PrecDesc* pds, const double* mu
   NYS_HIP(hipMemcpyAsync(w.bsrc, B, sizeof(double*) * k, hipMemcpyHostToDevice, s));
   NYS_HIP(hipMemcpyAsync(w.xdst, X, sizeof(double*) * k, hipMemcpyHostToDevice, s));
   NYS_HIP(hipStreamSynchronize(s));
+  // the product kernels write rows < n_c only: the padded rows of V64 (and so
+  // of every residual) must start, and stay, at zero
+  hipLaunchKernelGGL(rag_zero<double>, dim3(nb256(nk)), dim3(NT), 0, s, nk, w.V64);
+  hipLaunchKernelGGL(rag_zero<double>, dim3(nb256(nk)), dim3(NT), 0, s, nk, w.R64);
   hipLaunchKernelGGL((rag_pack<double, double>), dim3(nb256(p.nmax), (unsigned)k), dim3(NT), 0, s, w.tab, k, p.nmax,
                      w.bsrc, w.B64);
   hipLaunchKernelGGL((rag_pack<double, double>), dim3(nb256(p.nmax), (unsigned)k), dim3(NT), 0, s, w.tab, k, p.nmax,
@@ -645,17 +649,20 @@ nys_status ragged_solve(const OpDesc* ops, const PrecDesc* pds, const double* mu
   const bool f64 = o->prec == NYS_PREC_FP64;
   const int max_steps = f64 ? 4 : (o->max_refine > 0 ? o->max_refine : 10);
   const double itol = o->inner_tol > 0 ? o->inner_tol : 1e-4;
+  std::vector<double> prev(relres);
   for (int step = 0; step < max_steps; ++step) {
     std::vector<int> act(k, 0);
     double worst = 0.0;
     int nact = 0;
     for (int64_t c = 0; c < k; ++c)
-      if (!(relres[c] <= tol) && status[c] != NYS_ERR_BREAKDOWN) {
+      // as in the single solve: stop refining a problem whose residual grew or stalled
+      if (!(relres[c] <= tol) && status[c] != NYS_ERR_BREAKDOWN && (step == 0 || relres[c] <= 0.5 * prev[c])) {
         act[c] = 1;
         ++nact;
         worst = std::max(worst, relres[c]);
       }
     if (nact == 0 || !std::isfinite(worst)) break;
+    prev = relres;
     RagResult r;
     if (f64) {
       // first pass: the solve itself (tol relative to b, as the residual is b
@@ -695,7 +702,6 @@ nys_status ragged_solve(const OpDesc* ops, const PrecDesc* pds, const double* mu
   }
   if (worst == NYS_ERR_BREAKDOWN) set_error("PCG breakdown: p^T (A + mu I) p <= 0");
   else if (worst == NYS_NOT_CONVERGED) set_error("PCG did not reach the tolerance within maxit");
-  (void)nk;
   return worst;
 }
 

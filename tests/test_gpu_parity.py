@@ -117,7 +117,12 @@ def test_factor_matches_oracle(n, ell):
     P = nys.nys_factor(Om, Y)
     ref = oracle.randomized_nystrom(oracle.DenseOp(A), om0)
     U, lam = h(P.U), h(P.lam)
-    np.testing.assert_allclose(U.T @ U, np.eye(ell), atol=1e-11)
+    # U = B W S^{-1/2} from the eigenpairs (W, S) of B^T B: an off-diagonal e_ij
+    # left by the eigensolver shows in U^T U as e_ij / sqrt(s_i s_j); entries
+    # below 1e-14 max(s) are not rotated, so the bound grows for tiny s.
+    s2 = lam + P.nu
+    bound = 1e-13 + 4e-14 * s2.max() / np.sqrt(np.outer(s2, s2))
+    assert np.all(np.abs(U.T @ U - np.eye(ell)) <= bound)
     assert np.all(np.diff(lam) <= 0)
     np.testing.assert_allclose(lam, ref["lam"], rtol=1e-9, atol=1e-12 * ref["lam"][0])
     Ah = (U * lam) @ U.T
@@ -497,3 +502,16 @@ def test_ragged_mixed_operators_fall_back():
     for q in range(3):
         assert info.status[q] == 0
         assert oracle.true_relres(refs[q], mus[q], h(Xs[q]), bs[q]) <= 1.02e-10
+
+
+@pytest.mark.parametrize("n,ell", [(1500, 500), (1400, 500), (200, 64)])
+def test_sketch_device_gaussian_orthonormal(n, ell):
+    """The device test matrix is orthonormalised by one CholeskyQR pass when
+    n >= 3 l (Gaussian, well conditioned) and by two otherwise; either way
+    Omega^T Omega = I and Y = A Omega."""
+    A = spectrum_psd(1.0 / np.arange(1, n + 1) ** 2, 80 + n)
+    op = nys.Operator.dense(t64(A))
+    Om, Y = nys.nys_sketch(op, ell, seed=17)
+    Om, Y = h(Om), h(Y)
+    assert np.linalg.norm(Om.T @ Om - np.eye(ell), 2) < 1e-13
+    assert np.linalg.norm(Y - A @ Om) <= 1e-12 * np.linalg.norm(Y)
