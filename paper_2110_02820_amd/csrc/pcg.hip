@@ -283,17 +283,21 @@ __global__ __launch_bounds__(NT) void cg_finish_mv(int64_t n, const T* __restric
   double pvp = 0.0;
   for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     const int64_t j = tile * 32 + c;
-    T a0 = T(0), a1 = T(0);
-    if (j < n) {
-      int g = sl;
-      for (; g + 8 < ng; g += 16) {
-        a0 += part[(int64_t)g * n + j];
-        a1 += part[(int64_t)(g + 8) * n + j];
+    const int64_t jc = j < n ? j : n - 1;
+    T a0 = T(0);
+    // slice sl: groups sl, sl + 8, ...; eight loads in flight per pass, summed in order
+    for (int g0 = sl; g0 < ng; g0 += 64) {
+      T v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int g = g0 + 8 * u;
+        v[u] = g < ng ? part[(int64_t)g * n + jc] : T(0);
       }
-      if (g < ng) a0 += part[(int64_t)g * n + j];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) a0 += v[u];
     }
     __syncthreads();
-    shp[sl][c] = a0 + a1;
+    shp[sl][c] = a0;
     __syncthreads();
     if (sl == 0 && j < n) {
       const T sum = ((shp[0][c] + shp[1][c]) + (shp[2][c] + shp[3][c])) +
@@ -326,11 +330,27 @@ __global__ __launch_bounds__(NT) void cg_finish_mv(int64_t n, const T* __restric
   if (!fuse) return;
   const T a = T(alpha_s);
   double rr = 0.0;
-  for (int64_t i = threadIdx.x; i < n; i += NT) {
-    X[i] += a * P[i];
-    const T r = R[i] - a * V[i];
-    R[i] = r;
-    rr += double(r) * double(r);
+  for (int64_t i0 = threadIdx.x; i0 < n; i0 += 4 * NT) {  // loads of four entries in flight
+    T xv[4], pv4[4], rv[4], vv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int64_t i = i0 + (int64_t)u * NT;
+      const int64_t ic = i < n ? i : n - 1;
+      xv[u] = X[ic];
+      pv4[u] = P[ic];
+      rv[u] = R[ic];
+      vv[u] = V[ic];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int64_t i = i0 + (int64_t)u * NT;
+      if (i < n) {
+        X[i] = xv[u] + a * pv4[u];
+        const T r = rv[u] - a * vv[u];
+        R[i] = r;
+        rr += double(r) * double(r);
+      }
+    }
   }
   rr = block_sum(rr, sh);
   if (threadIdx.x == 0 && !sc.done[0]) {
@@ -344,96 +364,114 @@ __global__ __launch_bounds__(NT) void cg_finish_mv(int64_t n, const T* __restric
 
 // ---------------------------------------------------------------- apply, k = 1
 
-// C'[j] = ((lam_l + mu)/(lam_j + mu) - 1) (U^T r)[j].  Grid (column blocks of
-// 64, row chunks); thread (tx, ty): column tx of the block, rows ty (mod 4).
-// The last row chunk of each column block to finish sums the chunk partials
-// in chunk order.
-template <typename TU, typename T>
-__global__ __launch_bounds__(NT) void utr_scale(int64_t n, int64_t l, const TU* __restrict__ U,
-                                                int64_t ldu, const T* __restrict__ r,
-                                                double* __restrict__ part, int64_t rows_per_chunk,
-                                                const double* __restrict__ lam,
-                                                const double* __restrict__ mu, double* __restrict__ Cs,
-                                                unsigned* __restrict__ ctr,
-                                                const int* __restrict__ alldone) {
+// Partial U^T r: part[chunk][j].  Grid (column blocks of 64, row chunks);
+// thread (tx, ty): column tx of the block, rows ty (mod 4) of the chunk, RU
+// loads in flight at a time.
+template <typename TU, typename T, int RU>
+__global__ __launch_bounds__(NT) void utr_part(int64_t n, int64_t l, const TU* __restrict__ U, int64_t ldu,
+                                               const T* __restrict__ r, double* __restrict__ part,
+                                               int64_t rows_per_chunk, const int* __restrict__ alldone) {
   if (alldone && *alldone) return;
   __shared__ double red[4][64];
   const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
   const int64_t j = (int64_t)blockIdx.x * 64 + tx;
   const int64_t i0 = (int64_t)blockIdx.y * rows_per_chunk;
   const int64_t i1 = i0 + rows_per_chunk < n ? i0 + rows_per_chunk : n;
-  // four independent accumulators: several loads in flight per thread
-  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-  if (j < l) {
-    int64_t i = i0 + ty;
-    for (; i + 12 < i1; i += 16) {
-      a0 += double(U[i * ldu + j]) * double(r[i]);
-      a1 += double(U[(i + 4) * ldu + j]) * double(r[i + 4]);
-      a2 += double(U[(i + 8) * ldu + j]) * double(r[i + 8]);
-      a3 += double(U[(i + 12) * ldu + j]) * double(r[i + 12]);
+  const int64_t jc = j < l ? j : l - 1;
+  double acc = 0.0;
+  for (int64_t ib = i0 + ty; ib < i1; ib += 4 * RU) {
+    double uv[RU], rv[RU];
+#pragma unroll
+    for (int u = 0; u < RU; ++u) {
+      const int64_t i = ib + 4 * u;
+      const int64_t ic = i < i1 ? i : i1 - 1;
+      uv[u] = double(U[ic * ldu + jc]);
+      rv[u] = i < i1 ? double(r[ic]) : 0.0;
     }
-    for (; i < i1; i += 4) a0 += double(U[i * ldu + j]) * double(r[i]);
+#pragma unroll
+    for (int u = 0; u < RU; ++u) acc += uv[u] * rv[u];
   }
-  red[ty][tx] = (a0 + a1) + (a2 + a3);
+  red[ty][tx] = j < l ? acc : 0.0;
   __syncthreads();
   if (ty == 0 && j < l)
     part[(int64_t)blockIdx.y * l + j] = (red[0][tx] + red[1][tx]) + (red[2][tx] + red[3][tx]);
-  if (!last_block(ctr + blockIdx.x, gridDim.y)) return;
-  // chunk partials: thread (tx, ty) sums chunks q = ty (mod 4), then in order
-  double p0 = 0.0, p1 = 0.0;
-  if (j < l) {
-    unsigned q = ty;
-    for (; q + 4 < gridDim.y; q += 8) {
-      p0 += part[(int64_t)q * l + j];
-      p1 += part[(int64_t)(q + 4) * l + j];
-    }
-    if (q < gridDim.y) p0 += part[(int64_t)q * l + j];
+}
+
+// C'[j] = ((lam_l + mu)/(lam_j + mu) - 1) sum_chunk part[chunk][j].  One wave
+// per 16 columns; lane q takes chunks q, q + 64, ... (16 loads in flight per
+// pass) and a fixed shuffle tree adds the lanes (deterministic).
+__global__ __launch_bounds__(NT) void utr_final(int64_t l, int nch, const double* __restrict__ part,
+                                                const double* __restrict__ lam, const double* __restrict__ mu,
+                                                double* __restrict__ Cs, const int* __restrict__ alldone) {
+  if (alldone && *alldone) return;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t jb = ((int64_t)blockIdx.x * 4 + wave) * 16;
+  double sums[16];
+#pragma unroll
+  for (int cc = 0; cc < 16; ++cc) sums[cc] = 0.0;
+  for (int q0 = 0; q0 < nch; q0 += 64) {
+    const int q = q0 + lane;
+#pragma unroll
+    for (int cc = 0; cc < 16; ++cc)
+      if (q < nch && jb + cc < l) sums[cc] += part[(int64_t)q * l + jb + cc];
   }
-  __syncthreads();
-  red[ty][tx] = p0 + p1;
-  __syncthreads();
-  if (ty == 0 && j < l) {
-    const double sum = (red[0][tx] + red[1][tx]) + (red[2][tx] + red[3][tx]);
-    const double m = mu[0];
-    Cs[j] = ((lam[l - 1] + m) / (lam[j] + m) - 1.0) * sum;
+#pragma unroll
+  for (int cc = 0; cc < 16; ++cc) sums[cc] = wave_sum(sums[cc]);
+  if (lane < 16) {
+    double tot = sums[0];
+#pragma unroll
+    for (int cc = 1; cc < 16; ++cc)
+      if (lane == cc) tot = sums[cc];
+    const int64_t jj = jb + lane;
+    if (jj < l) {
+      const double m = mu[0];
+      Cs[jj] = ((lam[l - 1] + m) / (lam[jj] + m) - 1.0) * tot;
+    }
   }
 }
 
-// z_i = r_i + sum_j U[i][j] C'[j] (one wave per row).  mode 0: plain apply;
-// mode 1: also r^T z for the set-up; mode 2: r^T z, beta and flags.
-template <typename TU, typename T>
+// z_i = r_i + sum_j U[i][j] C'[j]: one wave per group of four rows, whose
+// 4 x NJ loads per lane (columns lane + 64 jj, l <= 64 NJ) are issued together.
+// mode 0: plain apply; mode 1: also r^T z for the set-up; mode 2: r^T z,
+// beta and flags.
+template <typename TU, typename T, int NJ>
 __global__ __launch_bounds__(NT) void uc_rz(int64_t n, int64_t l, const TU* __restrict__ U, int64_t ldu,
                                             const double* __restrict__ Cs, const T* __restrict__ r,
                                             T* __restrict__ z, int64_t rows_per_wave,
                                             double* __restrict__ prz, CgScalars sc, int par, int mode,
                                             T* __restrict__ Pd) {
   if (mode == 2 && *sc.alldone) return;
-  extern __shared__ char smem[];
-  T* cs = reinterpret_cast<T*>(smem);
   __shared__ double sh[NT];
-  for (int64_t j = threadIdx.x; j < l; j += NT) cs[j] = T(Cs[j]);
-  __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  T cs[NJ];
+#pragma unroll
+  for (int jj = 0; jj < NJ; ++jj) {
+    const int64_t j = lane + 64 * jj;
+    cs[jj] = j < l ? T(Cs[j]) : T(0);
+  }
   const int64_t w0 = ((int64_t)blockIdx.x * 4 + wave) * rows_per_wave;
   const int64_t w1 = w0 + rows_per_wave < n ? w0 + rows_per_wave : n;
   double rzp = 0.0;
   for (int64_t ib = w0; ib < w1; ib += 4) {
-    // four rows at once: independent loads in flight
-    T s0 = T(0), s1 = T(0), s2 = T(0), s3 = T(0);
     const int64_t nr = (w1 - ib) < 4 ? (w1 - ib) : 4;
-    const TU* u0 = U + ib * ldu;
-    for (int64_t j = lane; j < l; j += 64) {
-      const T c = cs[j];
-      s0 += T(u0[j]) * c;
-      if (nr > 1) s1 += T(u0[ldu + j]) * c;
-      if (nr > 2) s2 += T(u0[2 * ldu + j]) * c;
-      if (nr > 3) s3 += T(u0[3 * ldu + j]) * c;
+    TU u[4][NJ];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int64_t row = ib + (q < nr ? q : 0);
+#pragma unroll
+      for (int jj = 0; jj < NJ; ++jj) {
+        const int64_t j = lane + 64 * jj;
+        u[q][jj] = U[row * ldu + (j < l ? j : l - 1)];
+      }
     }
-    s0 = wave_sum(s0);
-    s1 = wave_sum(s1);
-    s2 = wave_sum(s2);
-    s3 = wave_sum(s3);
-    const T sv[4] = {s0, s1, s2, s3};
+    T sv[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      T acc = T(0);
+#pragma unroll
+      for (int jj = 0; jj < NJ; ++jj) acc += T(u[q][jj]) * cs[jj];  // cs = 0 past l
+      sv[q] = wave_sum(acc);
+    }
     for (int q = 0; q < nr; ++q) {
       const T ri = r[ib + q];
       const T zi = ri + sv[q];
@@ -450,11 +488,23 @@ __global__ __launch_bounds__(NT) void uc_rz(int64_t n, int64_t l, const TU* __re
   if (Pd == nullptr) return;
   // fused direction update (small n): P = Z (set-up) or P = Z + beta P
   __syncthreads();
-  if (mode == 1) {
-    for (int64_t i = threadIdx.x; i < n; i += NT) Pd[i] = z[i];
-  } else if (!sc.done[0]) {
-    const T b = T(sc.beta[0]);
-    for (int64_t i = threadIdx.x; i < n; i += NT) Pd[i] = z[i] + b * Pd[i];
+  const T b = mode == 1 ? T(0) : T(sc.beta[0]);
+  if (mode == 1 || !sc.done[0]) {
+    for (int64_t i0 = threadIdx.x; i0 < n; i0 += 4 * NT) {  // loads of four entries in flight
+      T zv[4], pv4[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int64_t i = i0 + (int64_t)u * NT;
+        const int64_t ic = i < n ? i : n - 1;
+        zv[u] = z[ic];
+        pv4[u] = mode == 1 ? T(0) : Pd[ic];  // set-up: P = Z (P not read: it is uninitialised)
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int64_t i = i0 + (int64_t)u * NT;
+        if (i < n) Pd[i] = zv[u] + b * pv4[u];
+      }
+    }
   }
 }
 
@@ -492,41 +542,64 @@ int64_t groups_for(int64_t n, int64_t k) {
 // k = 1: Cs = scaled U^T r.
 nys_status utr_launch(const PrecDesc& P, const double* mu_dev, const void* R, bool f32, double* part,
                       double* Cs, unsigned* ctr, const int* alldone, hipStream_t s) {
+  (void)ctr;
   const int64_t n = P.n, l = P.ell;
   const int64_t cb = cdiv(l, 64);
-  // chunks of >= 64 rows (16 per thread row phase), at most 512 chunks
+  // chunks of 32 rows (8 loads per thread, all in flight), at most 512 chunks
   int64_t rpc = cdiv(n, 512);
-  rpc = cdiv(rpc < 64 ? 64 : rpc, 16) * 16;
+  rpc = cdiv(rpc < 32 ? 32 : rpc, 32) * 32;
   const int64_t rc = cdiv(n, rpc);
   dim3 grid((unsigned)cb, (unsigned)rc);
-#define LU(TU_, T_)                                                                                \
-  hipLaunchKernelGGL((utr_scale<TU_, T_>), grid, dim3(NT), 0, s, n, l, static_cast<const TU_*>(P.U), \
-                     P.ldu, static_cast<const T_*>(R), part, rpc, P.lam, mu_dev, Cs, ctr, alldone)
+#define LU(TU_, T_)                                                                                  \
+  hipLaunchKernelGGL((utr_part<TU_, T_, 8>), grid, dim3(NT), 0, s, n, l, static_cast<const TU_*>(P.U), \
+                     P.ldu, static_cast<const T_*>(R), part, rpc, alldone)
   if (P.dtype == NYS_F64 && !f32) LU(double, double);
   else if (P.dtype == NYS_F64 && f32) LU(double, float);
   else if (P.dtype == NYS_F32 && !f32) LU(float, double);
   else LU(float, float);
 #undef LU
   NYS_CHECK_LAUNCH();
+  hipLaunchKernelGGL(utr_final, dim3((unsigned)cdiv(l, 64)), dim3(NT), 0, s, l, (int)rc, part, P.lam, mu_dev, Cs,
+                     alldone);
+  NYS_CHECK_LAUNCH();
   return NYS_OK;
+}
+
+template <typename TU, typename T>
+void uc_dispatch(int64_t n, int64_t l, const TU* U, int64_t ldu, const double* Cs, const T* R, T* Z,
+                 int64_t rpw, double* prz, const CgScalars& sc, int par, int mode, T* Pd, unsigned nb,
+                 hipStream_t s) {
+#define LC(NJ) hipLaunchKernelGGL((uc_rz<TU, T, NJ>), dim3(nb), dim3(NT), 0, s, n, l, U, ldu, Cs, R, Z, rpw, prz, sc, par, mode, Pd)
+  if (l <= 128) LC(2);
+  else if (l <= 256) LC(4);
+  else if (l <= 512) LC(8);
+  else if (l <= 1024) LC(16);
+  else LC(32);
+#undef LC
 }
 
 nys_status uc_launch(const PrecDesc& P, const double* Cs, const void* R, void* Z, bool f32, double* prz,
                      const CgScalars& sc, int par, int mode, hipStream_t s, void* Pd = nullptr) {
   const int64_t n = P.n, l = P.ell;
+  if (l > 2048) {
+    set_error("preconditioner apply: l = %lld > 2048 not supported", (long long)l);
+    return NYS_ERR_ARG;
+  }
   int64_t rpw = cdiv(n, 4 * 512);  // at most 512 workgroups (partial buffer size)
   rpw = cdiv(rpw < 4 ? 4 : rpw, 4) * 4;
-  const int64_t nb = cdiv(cdiv(n, rpw), 4);
-  const size_t sh = (size_t)l * (f32 ? 4 : 8);
-#define LC(TU_, T_)                                                                                  \
-  hipLaunchKernelGGL((uc_rz<TU_, T_>), dim3((unsigned)nb), dim3(NT), sh, s, n, l,                    \
-                     static_cast<const TU_*>(P.U), P.ldu, Cs, static_cast<const T_*>(R),              \
-                     static_cast<T_*>(Z), rpw, prz, sc, par, mode, static_cast<T_*>(Pd))
-  if (P.dtype == NYS_F64 && !f32) LC(double, double);
-  else if (P.dtype == NYS_F64 && f32) LC(double, float);
-  else if (P.dtype == NYS_F32 && !f32) LC(float, double);
-  else LC(float, float);
-#undef LC
+  const unsigned nb = (unsigned)cdiv(cdiv(n, rpw), 4);
+  if (P.dtype == NYS_F64 && !f32)
+    uc_dispatch<double, double>(n, l, static_cast<const double*>(P.U), P.ldu, Cs, static_cast<const double*>(R),
+                                static_cast<double*>(Z), rpw, prz, sc, par, mode, static_cast<double*>(Pd), nb, s);
+  else if (P.dtype == NYS_F64 && f32)
+    uc_dispatch<double, float>(n, l, static_cast<const double*>(P.U), P.ldu, Cs, static_cast<const float*>(R),
+                               static_cast<float*>(Z), rpw, prz, sc, par, mode, static_cast<float*>(Pd), nb, s);
+  else if (P.dtype == NYS_F32 && !f32)
+    uc_dispatch<float, double>(n, l, static_cast<const float*>(P.U), P.ldu, Cs, static_cast<const double*>(R),
+                               static_cast<double*>(Z), rpw, prz, sc, par, mode, static_cast<double*>(Pd), nb, s);
+  else
+    uc_dispatch<float, float>(n, l, static_cast<const float*>(P.U), P.ldu, Cs, static_cast<const float*>(R),
+                              static_cast<float*>(Z), rpw, prz, sc, par, mode, static_cast<float*>(Pd), nb, s);
   NYS_CHECK_LAUNCH();
   return NYS_OK;
 }
