@@ -373,6 +373,36 @@ __device__ __forceinline__ bool jacobi_rot(double app, double aqq, double apq, d
   return true;
 }
 
+// Branch-free rotation for the subproblem rounds, same test as jacobi_rot.
+// Only the rotation's exact orthogonality matters for the accuracy of the
+// eigenvectors; its angle only has to annihilate a_pq well enough for the
+// sweeps to converge.  So tau = (a_qq - a_pp) / (2 a_pq) is formed in float64,
+// t = sign(tau) / (|tau| + sqrt(1 + tau^2)) in float32 (relative error
+// ~1e-7: the rotated a_pq drops by that factor, and later sweeps remove the
+// rest), and c = 1/sqrt(1 + t^2), s = t c in float64 from that t, which keeps
+// c^2 + s^2 = 1 to float64 rounding.  Short dependent chain: one float64
+// reciprocal and one float64 reciprocal square root.
+__device__ __forceinline__ bool jacobi_rot_bf(double app, double aqq, double apq, double floor_abs, double& c,
+                                              double& s) {
+  const double thr2 = fmax(4.930380657631324e-32 * fabs(app * aqq), floor_abs * floor_abs);
+  const bool did = (apq * apq > thr2) && !(fabs(apq) < 1e-300);
+  const double tau = (aqq - app) * 0.5 * frcp(did ? apq : 1.0);
+  const float tf = (float)tau;  // |tau| beyond float range: t rounds to 0 (angle < 1e-38)
+  const float at = fabsf(tf);
+  float t;
+  if (at > 1e15f) {
+    t = 0.5f * __builtin_amdgcn_rcpf(at);
+  } else {
+    const float h = fmaf(at, at, 1.0f);
+    t = __builtin_amdgcn_rcpf(at + h * __builtin_amdgcn_rsqf(h));
+  }
+  const double td = (double)(tf < 0.0f ? -t : t);
+  const double cc = frsq(fma(td, td, 1.0));
+  c = did ? cc : 1.0;
+  s = did ? td * cc : 0.0;
+  return did;
+}
+
 // Block two-sided Jacobi.  The m x m matrix (m = nblk * JB, nblk even) is cut
 // into JB x JB blocks; a round pairs the blocks by the round-robin schedule.
 // Phase 1 (one workgroup per block pair (P, Q)): load the JS x JS subproblem
@@ -522,25 +552,20 @@ __global__ __launch_bounds__(256) void jac_phase1(JacArgs a, int64_t r, int swee
       double(*So)[JS + 1] = Sb[cur ^ 1];
       const int p1 = rr_js(k1, ir), q1 = rr_js(JS - 1 - k1, ir);
       const int p2 = rr_js(k2, ir), q2 = rr_js(JS - 1 - k2, ir);
+      // both rotations, interleaved (pair k2 == k1 on the diagonal blocks gives the same one twice)
       double c1, s1, c2, s2;
-      bool did = jacobi_rot(Si[p1][p1], Si[q1][q1], Si[p1][q1], floor_abs, c1, s1);
-      if (k1 == k2) {
-        c2 = c1;
-        s2 = s1;
-      } else {
-        did = jacobi_rot(Si[p2][p2], Si[q2][q2], Si[p2][q2], floor_abs, c2, s2) || did;
-      }
-      if (did) any_s = 1;
+      const bool d1 = jacobi_rot_bf(Si[p1][p1], Si[q1][q1], Si[p1][q1], floor_abs, c1, s1);
+      const bool d2 = jacobi_rot_bf(Si[p2][p2], Si[q2][q2], Si[p2][q2], floor_abs, c2, s2);
+      if (d1 || d2) any_s = 1;
       // S <- R^T S R on the 2 x 2 block (rows pair k1, columns pair k2)
       const double app = Si[p1][p2], apq = Si[p1][q2], aqp = Si[q1][p2], aqq = Si[q1][q2];
       const double bpp = c1 * app - s1 * aqp, bpq = c1 * apq - s1 * aqq;
       const double bqp = s1 * app + c1 * aqp, bqq = s1 * apq + c1 * aqq;
-      double npp = c2 * bpp - s2 * bpq, npq = s2 * bpp + c2 * bpq;
-      double nqp = c2 * bqp - s2 * bqq, nqq = s2 * bqp + c2 * bqq;
-      if (k1 == k2) {
-        npq = 0.0;
-        nqp = 0.0;
-      }
+      // (on the diagonal blocks the rotated a_pq is kept as computed, not
+      // set to zero: the float32 tangent leaves a small remainder that later
+      // rounds remove, and S must stay equal to J^T A J)
+      const double npp = c2 * bpp - s2 * bpq, npq = s2 * bpp + c2 * bpq;
+      const double nqp = c2 * bqp - s2 * bqq, nqq = s2 * bqp + c2 * bqq;
       So[p1][p2] = npp;
       So[p1][q2] = npq;
       So[q1][p2] = nqp;
