@@ -376,7 +376,7 @@ def run_batched(args, nys, torch):
         tm = Timer(torch)
         t = time.perf_counter()
         Xs, info, _ = full_solve(nys, torch, op, ell, seed, prec, torch.float32, mus, B, ws, tol, tm, maxit=5000,
-                                 max_refine=40, inner_tol=args.inner_tol or 1e-3)
+                                 max_refine=40, inner_tol=args.inner_tol or 1e-2)
         log("block solve: %s, iters max %d, refine %d" % ({k: round(1e3 * v, 1) for k, v in tm.t.items()},
                                                           max(info.iters), info.refine_steps))
         t = time.perf_counter()

@@ -151,14 +151,14 @@ __global__ __launch_bounds__(256) void rbf_mv_lowp(RbfLowp L, const float* __res
 // 32: stage 1 forms K (64 x 32, wave w rows w*16..) with the Gram MFMA and
 // exp, splits it into bf16 hi/lo in LDS; stage 2 multiplies K (hi/lo) by the
 // P tile (hi/lo, staged transposed in LDS) with three bf16 MFMAs per tile.
-template <int MODE>
+template <int MODE, int CF>
 struct KvStage2;
 
 // BF16X3 second stage: K and P split into bf16 hi/lo in LDS, three bf16 MFMAs
-template <>
-struct KvStage2<0> {
-  unsigned short Khi[64][40], Klo[64][40];  // [row][point]
-  unsigned short Phi[64][40], Plo[64][40];  // [col][point]
+template <int CF>
+struct KvStage2<0, CF> {
+  unsigned short Khi[64][40], Klo[64][40];            // [row][point]
+  unsigned short Phi[16 * CF][40], Plo[16 * CF][40];  // [col][point]
   __device__ __forceinline__ void put_p(int pt, int cc, float v) {
     const unsigned short hi = bf16_rne(v);
     Phi[cc][pt] = hi;
@@ -169,12 +169,12 @@ struct KvStage2<0> {
     Khi[r][pc] = hi;
     Klo[r][pc] = bf16_rne(e - bf16_to_f(hi));
   }
-  __device__ __forceinline__ void mac(int wave, int lane, f4 acc[4]) {
+  __device__ __forceinline__ void mac(int wave, int lane, f4 (&acc)[CF]) {
     const int r = wave * 16 + (lane & 15);
     const bf8 khi = *reinterpret_cast<const bf8*>(&Khi[r][8 * (lane >> 4)]);
     const bf8 klo = *reinterpret_cast<const bf8*>(&Klo[r][8 * (lane >> 4)]);
 #pragma unroll
-    for (int cf = 0; cf < 4; ++cf) {
+    for (int cf = 0; cf < CF; ++cf) {
       const int cc = cf * 16 + (lane & 15);
       const bf8 phi = *reinterpret_cast<const bf8*>(&Phi[cc][8 * (lane >> 4)]);
       const bf8 plo = *reinterpret_cast<const bf8*>(&Plo[cc][8 * (lane >> 4)]);
@@ -186,79 +186,98 @@ struct KvStage2<0> {
 };
 
 // F32 second stage: K and P as float in LDS, v_mfma_f32_16x16x4f32
-template <>
-struct KvStage2<1> {
-  float Kf[64][33];  // [row][point]
-  float Pf[32][65];  // [point][col]
+template <int CF>
+struct KvStage2<1, CF> {
+  float Kf[64][33];           // [row][point]
+  float Pf[32][16 * CF + 1];  // [point][col]
   __device__ __forceinline__ void put_p(int pt, int cc, float v) { Pf[pt][cc] = v; }
   __device__ __forceinline__ void put_k(int r, int pc, float e) { Kf[r][pc] = e; }
-  __device__ __forceinline__ void mac(int wave, int lane, f4 acc[4]) {
+  __device__ __forceinline__ void mac(int wave, int lane, f4 (&acc)[CF]) {
     const int r = wave * 16 + (lane & 15);
 #pragma unroll
     for (int ks = 0; ks < 8; ++ks) {
       const float av = Kf[r][4 * ks + (lane >> 4)];
 #pragma unroll
-      for (int cf = 0; cf < 4; ++cf)
+      for (int cf = 0; cf < CF; ++cf)
         acc[cf] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, Pf[4 * ks + (lane >> 4)][cf * 16 + (lane & 15)], acc[cf],
                                                        0, 0, 0);
     }
   }
 };
 
-// Block of columns: V[I, cb*64 .. +63] = oscale * K_IJ P_J over the points of
-// split z, float32.  Block = 4 waves, 64 rows x 64 output columns; per point
-// tile of 32: stage 1 forms K (wave w: rows w*16 .. +15) with the Gram MFMA and
-// exp into LDS; stage 2 multiplies K by the P tile staged in LDS.
-template <int MODE>
+// Block of columns: V[I, cb*16CF .. +16CF-1] = oscale * K_IJ P_J over the points
+// of split z, float32.  Block = 4 waves, 64 rows x 16 CF output columns; per
+// point tile of 32: stage 1 forms K (wave w: rows w*16 .. +15) with the Gram
+// MFMA and exp into LDS; stage 2 multiplies K by the P tile staged in LDS.
+// The P tile and the point operands of the next tile are loaded into
+// registers while the current tile is multiplied.
+template <int MODE, int CF>
 __global__ __launch_bounds__(256) void rbf_kv_lowp(RbfLowp L, const float* __restrict__ P, int64_t ldp, int64_t k,
                                                    float* __restrict__ out, int64_t ldo, int64_t pts_per_split,
                                                    float oscale, const int* __restrict__ skip) {
   if (skip && *skip) return;
-  __shared__ __attribute__((aligned(16))) KvStage2<MODE> st;
+  constexpr int NC = 16 * CF;               // output columns of the block
+  constexpr int PE = 32 * NC / 256;         // P tile entries per thread
+  __shared__ __attribute__((aligned(16))) KvStage2<MODE, CF> st;
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int64_t n = L.n;
   const int64_t i0 = (int64_t)blockIdx.x * 64;
-  const int64_t c0 = (int64_t)blockIdx.y * 64;
+  const int64_t c0 = (int64_t)blockIdx.y * NC;
   const float two_s = L.two_s;
   Operand<MODE> a;
   a.load(L, i0 + wave * 16 + (lane & 15), lane);
   f4 cinit;
 #pragma unroll
   for (int q = 0; q < 4; ++q) cinit[q] = -L.hs[i0 + wave * 16 + 4 * (lane >> 4) + q] / two_s;
-  f4 acc[4];
+  f4 acc[CF];
 #pragma unroll
-  for (int cf = 0; cf < 4; ++cf) acc[cf] = f4{0, 0, 0, 0};
+  for (int cf = 0; cf < CF; ++cf) acc[cf] = f4{0, 0, 0, 0};
   const int64_t j0 = (int64_t)blockIdx.z * pts_per_split;
   int64_t j1 = j0 + pts_per_split;
   if (j1 > n) j1 = n;
+  // registers for the next tile: P entries and the two 16-point operands
+  float pr[PE];
+  Operand<MODE> b0, b1;
+  float h0 = 0.0f, h1 = 0.0f;
+  auto fetch = [&](int64_t jt) {
+#pragma unroll
+    for (int u = 0; u < PE; ++u) {
+      const int e = t + 256 * u, pt = e / NC, cc = e % NC;
+      const int64_t j = jt + pt, c = c0 + cc;
+      pr[u] = (j < j1 && c < k) ? P[j * ldp + c] : 0.0f;
+    }
+    // rows jt .. jt + 31 lie inside the padded operand arrays (jt < n, npad a multiple of 256)
+    b0.load(L, jt + (lane & 15), lane);
+    b1.load(L, jt + 16 + (lane & 15), lane);
+    h0 = L.hs[jt + (lane & 15)];
+    h1 = L.hs[jt + 16 + (lane & 15)];
+  };
+  if (j0 < j1) fetch(j0);
   for (int64_t jt = j0; jt < j1; jt += 32) {
     __syncthreads();
-    // P tile (32 points x 64 cols)
-    for (int e = t; e < 32 * 64; e += 256) {
-      const int pt = e >> 6, cc = e & 63;
-      const int64_t j = jt + pt, c = c0 + cc;
-      st.put_p(pt, cc, (j < j1 && c < k) ? P[j * ldp + c] : 0.0f);
+#pragma unroll
+    for (int u = 0; u < PE; ++u) {
+      const int e = t + 256 * u;
+      st.put_p(e / NC, e % NC, pr[u]);
     }
     // stage 1: K rows wave*16 .. +15, points jt .. jt+31 (two 16-point tiles)
+    const f4 dg0 = gram_tile(a, b0, cinit);
+    const f4 dg1 = gram_tile(a, b1, cinit);
+    const int64_t ja = jt + (lane & 15), jb = jt + 16 + (lane & 15);
 #pragma unroll
-    for (int pf = 0; pf < 2; ++pf) {
-      const int64_t j = jt + pf * 16 + (lane & 15);
-      Operand<MODE> b;
-      b.load(L, j, lane);
-      const float hj = L.hs[j];
-      const f4 dg = gram_tile(a, b, cinit);
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const float e = (j < j1) ? __builtin_amdgcn_exp2f(fmaf(two_s, dg[q], -hj)) : 0.0f;
-        st.put_k(wave * 16 + 4 * (lane >> 4) + q, pf * 16 + (lane & 15), e);
-      }
+    for (int q = 0; q < 4; ++q) {
+      const float e0 = (ja < j1) ? __builtin_amdgcn_exp2f(fmaf(two_s, dg0[q], -h0)) : 0.0f;
+      const float e1 = (jb < j1) ? __builtin_amdgcn_exp2f(fmaf(two_s, dg1[q], -h1)) : 0.0f;
+      st.put_k(wave * 16 + 4 * (lane >> 4) + q, (lane & 15), e0);
+      st.put_k(wave * 16 + 4 * (lane >> 4) + q, 16 + (lane & 15), e1);
     }
     __syncthreads();
+    if (jt + 32 < j1) fetch(jt + 32);  // in flight during stage 2
     st.mac(wave, lane, acc);
   }
   float* o = out + (int64_t)blockIdx.z * n * ldo;
 #pragma unroll
-  for (int cf = 0; cf < 4; ++cf)
+  for (int cf = 0; cf < CF; ++cf)
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int64_t row = i0 + wave * 16 + 4 * (lane >> 4) + q;
@@ -347,7 +366,7 @@ nys_status rbf_lowp_mv(const RbfLowp& L, int mode, const float* p, const double*
 }
 
 size_t rbf_lowp_kv_scratch(int64_t n, int64_t k) {
-  const int64_t tiles = cdiv(n, 64) * cdiv(k, 64);
+  const int64_t tiles = cdiv(n, 64) * cdiv(k, k > 64 ? (int64_t)128 : (int64_t)64);
   const int64_t nz = cdiv(2 * 256, tiles);
   return nz > 1 ? (size_t)nz * (size_t)n * (size_t)k : 0;
 }
@@ -367,20 +386,26 @@ nys_status rbf_lowp_kv(const RbfLowp& L, int mode, const float* P, int64_t ldp, 
                        int64_t nrhs, float* V, int64_t ldv, float* scratch, size_t scratch_elems, const int* skip,
                        hipStream_t s) {
   const int64_t n = L.n;
-  const int64_t tiles = cdiv(n, 64) * cdiv(k, 64);
+  // 128 output columns per block when there are more than 64 (half the
+  // Gram / exp recomputation and twice the MFMA work per staged tile)
+  const int64_t nc = k > 64 ? 128 : 64;
+  const int64_t tiles = cdiv(n, 64) * cdiv(k, nc);
   int64_t nz = cdiv(2 * (num_cus() < 256 ? num_cus() : 256), tiles);
   if (nz < 1) nz = 1;
   while (nz > 1 && (size_t)(nz * n * k) > scratch_elems) --nz;
   const int64_t pps = cdiv(cdiv(n, nz), 32) * 32;
   nz = cdiv(n, pps);
-  dim3 grid((unsigned)cdiv(n, 64), (unsigned)cdiv(k, 64), (unsigned)nz);
+  dim3 grid((unsigned)cdiv(n, 64), (unsigned)cdiv(k, nc), (unsigned)nz);
   float* dst = nz > 1 ? scratch : V;
   const int64_t ldo = nz > 1 ? k : ldv;
   const float oscale = nz > 1 ? 1.0f : L.scale;
-  if (mode == 0)
-    hipLaunchKernelGGL(rbf_kv_lowp<0>, grid, dim3(256), 0, s, L, P, ldp, k, dst, ldo, pps, oscale, skip);
-  else
-    hipLaunchKernelGGL(rbf_kv_lowp<1>, grid, dim3(256), 0, s, L, P, ldp, k, dst, ldo, pps, oscale, skip);
+#define KV(M, CF) hipLaunchKernelGGL((rbf_kv_lowp<M, CF>), grid, dim3(256), 0, s, L, P, ldp, k, dst, ldo, pps, oscale, skip)
+  if (mode == 0) {
+    if (nc == 128) KV(0, 8); else KV(0, 4);
+  } else {
+    if (nc == 128) KV(1, 8); else KV(1, 4);
+  }
+#undef KV
   NYS_CHECK_LAUNCH();
   if (nz > 1) {
     hipLaunchKernelGGL(rbf_lowp_finish, dim3((unsigned)cdiv(n * k, 256)), dim3(256), 0, s, scratch, (int)nz, n, k,
