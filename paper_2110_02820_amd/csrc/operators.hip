@@ -353,7 +353,9 @@ size_t op_scratch_elems(const OpDesc& op, int64_t k) {
     const size_t one = (size_t)(4 * 256) * (size_t)op.n;
     const int64_t tiles = cdiv(op.n, RB_ROWS) * cdiv(k, 64);
     const int64_t ns = cdiv(2 * 256, tiles);
-    const size_t blk = ns > 1 ? (size_t)ns * (size_t)op.n * (size_t)k : 0;
+    size_t blk = ns > 1 ? (size_t)ns * (size_t)op.n * (size_t)k : 0;
+    const size_t lowp = rbf_lowp_kv_scratch(op.n, k);  // float elements: fits in as many doubles
+    blk = blk > lowp ? blk : lowp;
     return one > blk ? one : blk;
   }
   return gemm_scratch_elems(op.n, k);

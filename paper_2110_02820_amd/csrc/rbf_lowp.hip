@@ -82,11 +82,16 @@ __device__ __forceinline__ f4 gram_tile(const Operand<0>& a, const Operand<0>& b
   d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.hi, b.lo, d, 0, 0, 0);
   return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.lo, b.hi, d, 0, 0, 0);
 }
-__device__ __forceinline__ f4 gram_tile(const Operand<1>& a, const Operand<1>& b, f4 c) {
+// (float32: only the ksteps coordinate groups that hold data; ksteps is uniform)
+__device__ __forceinline__ f4 gram_tile(const Operand<1>& a, const Operand<1>& b, f4 c, int ksteps = 8) {
   f4 d = c;
 #pragma unroll
-  for (int ks = 0; ks < 8; ++ks) d = __builtin_amdgcn_mfma_f32_16x16x4f32(a.v[ks], b.v[ks], d, 0, 0, 0);
+  for (int ks = 0; ks < 8; ++ks)
+    if (ks < ksteps) d = __builtin_amdgcn_mfma_f32_16x16x4f32(a.v[ks], b.v[ks], d, 0, 0, 0);
   return d;
+}
+__device__ __forceinline__ f4 gram_tile(const Operand<0>& a, const Operand<0>& b, f4 c, int) {
+  return gram_tile(a, b, c);
 }
 
 // One vector: part[split][i] = sum_{j in split} K_ij p_j.  Block = 4 waves,
@@ -123,7 +128,7 @@ __global__ __launch_bounds__(256) void rbf_mv_lowp(RbfLowp L, const float* __res
     const float pj = (j < j1) ? p[j] : 0.0f;
 #pragma unroll
     for (int f = 0; f < 4; ++f) {
-      const f4 dg = gram_tile(a[f], b, cinit[f]);
+      const f4 dg = gram_tile(a[f], b, cinit[f], L.ksteps);
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const float e = __builtin_amdgcn_exp2f(fmaf(two_s, dg[q], -hj));
@@ -261,8 +266,8 @@ __global__ __launch_bounds__(256) void rbf_kv_lowp(RbfLowp L, const float* __res
       st.put_p(e / NC, e % NC, pr[u]);
     }
     // stage 1: K rows wave*16 .. +15, points jt .. jt+31 (two 16-point tiles)
-    const f4 dg0 = gram_tile(a, b0, cinit);
-    const f4 dg1 = gram_tile(a, b1, cinit);
+    const f4 dg0 = gram_tile(a, b0, cinit, L.ksteps);
+    const f4 dg1 = gram_tile(a, b1, cinit, L.ksteps);
     const int64_t ja = jt + (lane & 15), jb = jt + 16 + (lane & 15);
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
@@ -325,6 +330,7 @@ nys_status rbf_lowp_prepare(const OpDesc& op, void* buf, RbfLowp& L, hipStream_t
   const double sc = 1.4426950408889634 / (2.0 * op.sigma * op.sigma);  // log2(e) / (2 sigma^2)
   L.two_s = (float)(2.0 * sc);
   L.scale = (float)op.scale;
+  L.ksteps = (int)cdiv(d, (int64_t)4);
   if (op.dtype == NYS_F64)
     hipLaunchKernelGGL(rbf_prepare<double>, dim3((unsigned)cdiv(npad, 256)), dim3(256), 0, s,
                        static_cast<const double*>(op.data), n, d, op.ld, npad, sc, L.Xhi, L.Xlo, L.X32, L.hs);
@@ -340,7 +346,7 @@ nys_status rbf_lowp_mv_partials(const RbfLowp& L, int mode, const float* p, floa
   const int64_t n = L.n;
   const int64_t nrb = cdiv(n, 256);
   const int cus = num_cus() < 256 ? num_cus() : 256;
-  int64_t ns = cdiv(4 * cus, nrb);
+  int64_t ns = cdiv(8 * cus, nrb);  // about eight blocks per compute unit
   if (ns < 1) ns = 1;
   while (ns > 1 && (size_t)(ns * n) > part_elems) --ns;
   const int64_t pps = cdiv(cdiv(n, ns), 16) * 16;
@@ -367,7 +373,7 @@ nys_status rbf_lowp_mv(const RbfLowp& L, int mode, const float* p, const double*
 
 size_t rbf_lowp_kv_scratch(int64_t n, int64_t k) {
   const int64_t tiles = cdiv(n, 64) * cdiv(k, k > 64 ? (int64_t)128 : (int64_t)64);
-  const int64_t nz = cdiv(2 * 256, tiles);
+  const int64_t nz = cdiv(8 * 256, tiles);
   return nz > 1 ? (size_t)nz * (size_t)n * (size_t)k : 0;
 }
 
@@ -390,7 +396,9 @@ nys_status rbf_lowp_kv(const RbfLowp& L, int mode, const float* P, int64_t ldp, 
   // Gram / exp recomputation and twice the MFMA work per staged tile)
   const int64_t nc = k > 64 ? 128 : 64;
   const int64_t tiles = cdiv(n, 64) * cdiv(k, nc);
-  int64_t nz = cdiv(2 * (num_cus() < 256 ? num_cus() : 256), tiles);
+  // about eight blocks per compute unit: the per-tile chain (loads, LDS,
+  // barriers, MFMA) is latency-bound with fewer waves per SIMD
+  int64_t nz = cdiv(8 * (num_cus() < 256 ? num_cus() : 256), tiles);
   if (nz < 1) nz = 1;
   while (nz > 1 && (size_t)(nz * n * k) > scratch_elems) --nz;
   const int64_t pps = cdiv(cdiv(n, nz), 32) * 32;

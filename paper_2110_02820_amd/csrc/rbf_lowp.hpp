@@ -13,6 +13,7 @@ struct RbfLowp {
   float* hs;            // npad: log2(e) ||x_i||^2 / (2 sigma^2)
   float two_s;          // log2(e) / sigma^2
   float scale;          // operator scale
+  int ksteps;           // float32 Gram: 4-coordinate MFMA steps that cover d (<= 8)
 };
 
 enum { RBF_GRAM_BF16X3 = 0, RBF_GRAM_F32 = 1 };
