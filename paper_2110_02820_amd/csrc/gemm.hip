@@ -9,7 +9,8 @@
 // four 16 x 16 MFMA tiles; the K loop stages 16-deep slabs of A and B through
 // LDS.  When the output has too few tiles to fill 256 CUs, K is split across
 // workgroups (grid z) and a second kernel sums the partial tiles in a fixed
-// order, so results are deterministic.
+// order, so results are deterministic.  Large products with 16-byte aligned
+// operands use 128 x 128 tiles instead (gemm_large).
 #include "gemm.hpp"
 
 namespace nys {
@@ -128,6 +129,155 @@ __global__ __launch_bounds__(NT) void gemm_kernel(int64_t M, int64_t N, int64_t 
       }
 }
 
+// 16-byte vector of storage elements.
+template <typename TS>
+struct Vec16B;
+template <>
+struct Vec16B<float> {
+  typedef float4 type;
+  static constexpr int E = 4;
+};
+template <>
+struct Vec16B<double> {
+  typedef double2 type;
+  static constexpr int E = 2;
+};
+template <typename TS>
+__device__ __forceinline__ TS vget(const typename Vec16B<TS>::type& v, int u);
+template <>
+__device__ __forceinline__ float vget<float>(const float4& v, int u) {
+  return u == 0 ? v.x : u == 1 ? v.y : u == 2 ? v.z : v.w;
+}
+template <>
+__device__ __forceinline__ double vget<double>(const double2& v, int u) {
+  return u == 0 ? v.x : v.y;
+}
+
+constexpr int LM = 128, LN = 128, LK = 16, LPAD = 16;
+
+// Large tiles: a 256-thread workgroup computes a 128 x 128 tile, each wave a
+// 64 x 64 block of 4 x 4 MFMA tiles, from 16-deep slabs of A and B loaded with
+// 16-byte vector loads; the next slab is held in registers while the current
+// one is multiplied out of LDS.  Requires the contiguous dimension of each
+// operand to be a multiple of the vector width and 16-byte aligned rows
+// (checked on the host).  Tiles are numbered so that the workgroups that
+// share a row block of A run on the same XCD (blocks are dealt to the XCDs
+// round-robin): grid = 8 * ceil(tiles / 8) in x, split-K in y.
+template <typename TC, typename TAs, typename TBs, bool TA, bool TB>
+__global__ __launch_bounds__(NT) void gemm_large(int64_t M, int64_t N, int64_t K, int64_t kchunk,
+                                                 TC alpha, const TAs* __restrict__ A, int64_t lda,
+                                                 const TBs* __restrict__ B, int64_t ldb, TC beta,
+                                                 TC* __restrict__ C, int64_t ldc,
+                                                 TC* __restrict__ part, const int* __restrict__ skip) {
+  if (skip && *skip) return;
+  typedef typename Vec16B<TAs>::type VA;
+  typedef typename Vec16B<TBs>::type VB;
+  constexpr int EA = Vec16B<TAs>::E, EB = Vec16B<TBs>::E;
+  constexpr int NVA = LM * LK / EA / NT, NVB = LN * LK / EB / NT;
+  __shared__ TC As[LK][LM + LPAD];
+  __shared__ TC Bs[LK][LN + LPAD];
+  const int64_t mt = (M + LM - 1) / LM, nt = (N + LN - 1) / LN, tiles = mt * nt;
+  const int64_t per = (int64_t)gridDim.x / 8;
+  const int64_t tile = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
+  if (tile >= tiles) return;
+  const int64_t m0 = (tile / nt) * LM, n0 = (tile % nt) * LN;
+  const int t = threadIdx.x;
+  const int lane = t & 63, wave = t >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int64_t kb = (int64_t)blockIdx.y * kchunk;
+  const int64_t ke = (kb + kchunk < K) ? kb + kchunk : K;
+
+  VA ra[NVA];
+  VB rb[NVB];
+  auto load = [&](int64_t k0) {
+#pragma unroll
+    for (int r = 0; r < NVA; ++r) {
+      const int e = t + r * NT;
+      int64_t gm, gk;
+      if (!TA) { gm = m0 + e / (LK / EA); gk = k0 + (e % (LK / EA)) * EA; }
+      else { gk = k0 + e / (LM / EA); gm = m0 + (e % (LM / EA)) * EA; }
+      const bool ok = gm < M && gk < ke;
+      ra[r] = ok ? *reinterpret_cast<const VA*>(TA ? A + gk * lda + gm : A + gm * lda + gk) : VA{};
+    }
+#pragma unroll
+    for (int r = 0; r < NVB; ++r) {
+      const int e = t + r * NT;
+      int64_t gn, gk;
+      if (TB) { gn = n0 + e / (LK / EB); gk = k0 + (e % (LK / EB)) * EB; }
+      else { gk = k0 + e / (LN / EB); gn = n0 + (e % (LN / EB)) * EB; }
+      const bool ok = gn < N && gk < ke;
+      rb[r] = ok ? *reinterpret_cast<const VB*>(TB ? B + gn * ldb + gk : B + gk * ldb + gn) : VB{};
+    }
+  };
+  auto store = [&]() {
+#pragma unroll
+    for (int r = 0; r < NVA; ++r) {
+      const int e = t + r * NT;
+#pragma unroll
+      for (int u = 0; u < EA; ++u) {
+        if (!TA) As[(e % (LK / EA)) * EA + u][e / (LK / EA)] = TC(vget<TAs>(ra[r], u));
+        else As[e / (LM / EA)][(e % (LM / EA)) * EA + u] = TC(vget<TAs>(ra[r], u));
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < NVB; ++r) {
+      const int e = t + r * NT;
+#pragma unroll
+      for (int u = 0; u < EB; ++u) {
+        if (TB) Bs[(e % (LK / EB)) * EB + u][e / (LK / EB)] = TC(vget<TBs>(rb[r], u));
+        else Bs[e / (LN / EB)][(e % (LN / EB)) * EB + u] = TC(vget<TBs>(rb[r], u));
+      }
+    }
+  };
+
+  typename Mfma<TC>::acc_t acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = typename Mfma<TC>::acc_t{0, 0, 0, 0};
+
+  if (kb < ke) load(kb);
+  for (int64_t k0 = kb; k0 < ke; k0 += LK) {
+    __syncthreads();
+    store();
+    __syncthreads();
+    if (k0 + LK < ke) load(k0 + LK);
+#pragma unroll
+    for (int ks = 0; ks < LK; ks += 4) {
+      const int kk = ks + (lane >> 4);
+      TC a[4], b[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) a[i] = As[kk][wm * 64 + i * 16 + (lane & 15)];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) b[j] = Bs[kk][wn * 64 + j * 16 + (lane & 15)];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = Mfma<TC>::op(a[i], b[j], acc[i][j]);
+    }
+  }
+
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int64_t gm = m0 + wm * 64 + i * 16 + Mfma<TC>::row(lane, q);
+        const int64_t gn = n0 + wn * 64 + j * 16 + (lane & 15);
+        if (gm < M && gn < N) {
+          const TC v = acc[i][j][q];
+          if (part) {
+            part[((int64_t)blockIdx.y * M + gm) * N + gn] = v;
+          } else {
+            TC o = alpha * v;
+            if (beta != TC(0)) o += beta * C[gm * ldc + gn];
+            C[gm * ldc + gn] = o;
+          }
+        }
+      }
+}
+
 template <typename TC>
 __global__ void splitk_reduce(int64_t M, int64_t N, int nz, TC alpha, const TC* __restrict__ part,
                               TC beta, TC* __restrict__ C, int64_t ldc, const int* __restrict__ skip) {
@@ -149,7 +299,43 @@ nys_status gemm(bool ta, bool tb, int64_t M, int64_t N, int64_t K, TC alpha, con
                 int64_t lda, const TBs* B, int64_t ldb, TC beta, TC* C, int64_t ldc, TC* scratch,
                 size_t scratch_elems, hipStream_t s, const int* skip) {
   if (M <= 0 || N <= 0) return NYS_OK;
+  // large problems whose operands allow 16-byte loads: 128 x 128 tiles
+  constexpr int EA = 16 / sizeof(TAs), EB = 16 / sizeof(TBs);
+  const bool vec_a = (lda % EA == 0) && ((uintptr_t)A % 16 == 0) && ((ta ? M : K) % EA == 0);
+  const bool vec_b = (ldb % EB == 0) && ((uintptr_t)B % 16 == 0) && ((tb ? K : N) % EB == 0);
+  if (vec_a && vec_b && M >= LM && N >= 64 && K >= 4 * LK && (double)M * N * K >= 1.0e9) {
+    const int64_t lt = cdiv(M, LM) * cdiv(N, LN);
+    const int64_t target = 2 * (int64_t)(num_cus() < 256 ? num_cus() : 256);
+    int64_t nz = 1;
+    if (lt < target) {
+      nz = cdiv(target, lt);
+      nz = nz < cdiv(K, 16 * LK) ? nz : cdiv(K, 16 * LK);
+      while (nz > 1 && (size_t)(nz * M * N) > scratch_elems) --nz;
+      if (nz > 64) nz = 64;
+    }
+    const int64_t kchunk = cdiv(cdiv(K, nz), LK) * LK;
+    nz = cdiv(K, kchunk);
+    dim3 grid((unsigned)(8 * cdiv(lt, 8)), (unsigned)nz);
+    TC* part = nz > 1 ? scratch : nullptr;
+#define NYS_GEMM_LARGE(TA_, TB_)                                                              \
+  hipLaunchKernelGGL((gemm_large<TC, TAs, TBs, TA_, TB_>), grid, dim3(NT), 0, s, M, N, K,    \
+                     kchunk, alpha, A, lda, B, ldb, beta, C, ldc, part, skip)
+    if (!ta && !tb) NYS_GEMM_LARGE(false, false);
+    else if (!ta && tb) NYS_GEMM_LARGE(false, true);
+    else if (ta && !tb) NYS_GEMM_LARGE(true, false);
+    else NYS_GEMM_LARGE(true, true);
+#undef NYS_GEMM_LARGE
+    NYS_CHECK_LAUNCH();
+    if (nz > 1) {
+      const int64_t tot = M * N;
+      hipLaunchKernelGGL(splitk_reduce<TC>, dim3((unsigned)cdiv(tot, 256)), dim3(256), 0, s, M, N,
+                         (int)nz, alpha, part, beta, C, ldc, skip);
+      NYS_CHECK_LAUNCH();
+    }
+    return NYS_OK;
+  }
   const int64_t tiles = cdiv(M, BM) * cdiv(N, BN);
+
   const int64_t target = 2 * (int64_t)(num_cus() < 256 ? num_cus() : 256);
   int64_t nz = 1;
   if (tiles < target && K > 4 * BK) {

@@ -52,69 +52,114 @@ __global__ void add_mu(T* __restrict__ V, int64_t ldv, const T* __restrict__ P, 
 constexpr int RB_ROWS = 64;   // rows per workgroup
 constexpr int RB_PTS = 64;    // points per staged tile
 
-// One vector, rectangular: part[s][i] = sum_{j in split s} W_ij p_j with
-// W = K(Xr, Xc) (MODE 0) or W = dK/dsigma = K .* D2 / sigma^3 (MODE 1).
-// Thread (il, q): row il of the block, points j = q (mod 4) of every tile.
-template <typename TD, int DMAX, int MODE>
-__global__ __launch_bounds__(256) void rbf_mv_f64(const TD* __restrict__ Xr, int64_t nr, int64_t ldr,
-                                                  const TD* __restrict__ Xc, int64_t nc, int64_t ldc,
-                                                  int d, double c2, double inv_s3,
-                                                  const double* __restrict__ p,
-                                                  double* __restrict__ part, int64_t pts_per_split,
-                                                  const int* __restrict__ skip) {
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+// One vector, rectangular, float64, Gram on the matrix cores (d <= 4 KS):
+// part[s][i] = sum_{j in split s} W_ij p_j with W = K(Xr, Xc) (MODE 0) or
+// dK/dsigma (MODE 1).  Wave w of the block owns rows i0 + 16 w .. + 15 and
+// forms x_i^T y_j for 16 points at a time with KS v_mfma_f64_16x16x4f64
+// (operand lane l: row / point l % 16, coordinate 4 ks + l / 16; result lane l,
+// element q: row 4 q + l / 16, point l % 16), so the vector units only do
+// the exponential and the compensated accumulation.
+template <typename TD, int KS, int MODE>
+__global__ __launch_bounds__(256) void rbf_mv_f64m(const TD* __restrict__ Xr, int64_t nr, int64_t ldr,
+                                                   const TD* __restrict__ Xc, int64_t nc, int64_t ldc, int d,
+                                                   double c2, double inv_s3, const double* __restrict__ p,
+                                                   double* __restrict__ part, int64_t pts_per_split,
+                                                   const int* __restrict__ skip) {
   if (skip && *skip) return;
-  __shared__ double Xs[RB_PTS][DMAX + 1];
+  constexpr int DW = 4 * KS;
+  __shared__ double Xs[RB_PTS][DW + 1];
   __shared__ double Ns[RB_PTS];
   __shared__ double Ps[RB_PTS];
-  __shared__ double Red[4][RB_ROWS];
-  const int t = threadIdx.x, il = t & 63, q = t >> 6;
-  const int64_t i = (int64_t)blockIdx.x * RB_ROWS + il;
-  double xi[DMAX];
-  double ni = 0.0;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int64_t i0 = (int64_t)blockIdx.x * RB_ROWS + wave * 16;
+  // row operand and the norms of this lane's four output rows
+  double a[KS];
+  double nrm = 0.0;
+  {
+    const int64_t r = i0 + (lane & 15);
 #pragma unroll
-  for (int k = 0; k < DMAX; ++k) {
-    xi[k] = (i < nr && k < d) ? double(Xr[i * ldr + k]) : 0.0;
-    ni += xi[k] * xi[k];
+    for (int ks = 0; ks < KS; ++ks) {
+      const int kk = 4 * ks + (lane >> 4);
+      a[ks] = (r < nr && kk < d) ? double(Xr[r * ldr + kk]) : 0.0;
+      nrm += a[ks] * a[ks];
+    }
   }
+  nrm += __shfl_xor(nrm, 16, 64);
+  nrm += __shfl_xor(nrm, 32, 64);  // every lane: ||x||^2 of row l % 16
+  double ni[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) ni[q] = __shfl(nrm, 4 * q + (lane >> 4), 64);
   const int64_t j0 = (int64_t)blockIdx.y * pts_per_split;
   const int64_t j1 = (j0 + pts_per_split < nc) ? j0 + pts_per_split : nc;
-  // compensated (Kahan) sum over the points of this split: the float64
-  // residual of a refinement step must stay accurate when x is large
-  double acc = 0.0, comp = 0.0;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0}, cmp[4] = {0.0, 0.0, 0.0, 0.0};
   for (int64_t jt = j0; jt < j1; jt += RB_PTS) {
     __syncthreads();
-    for (int e = t; e < RB_PTS * DMAX; e += 256) {
-      const int jj = e / DMAX, k = e % DMAX;
-      const int64_t j = jt + jj;
-      Xs[jj][k] = (j < j1 && k < d) ? double(Xc[j * ldc + k]) : 0.0;
+    {
+      double v[RB_PTS * DW / 256];
+#pragma unroll
+      for (int u = 0; u < RB_PTS * DW / 256; ++u) {
+        const int e = t + 256 * u, jj = e / DW, kk = e % DW;
+        const int64_t j = jt + jj;
+        v[u] = (j < j1 && kk < d) ? double(Xc[j * ldc + kk]) : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < RB_PTS * DW / 256; ++u) {
+        const int e = t + 256 * u;
+        Xs[e / DW][e % DW] = v[u];
+      }
     }
+    if (t < RB_PTS) Ps[t] = (jt + t < j1) ? p[jt + t] : 0.0;
     __syncthreads();
     if (t < RB_PTS) {
-      double s = 0.0;
-      for (int k = 0; k < DMAX; ++k) s += Xs[t][k] * Xs[t][k];
-      Ns[t] = s;
-      Ps[t] = (jt + t < j1) ? p[jt + t] : 0.0;
+      double sn = 0.0;
+#pragma unroll
+      for (int kk = 0; kk < DW; ++kk) sn += Xs[t][kk] * Xs[t][kk];
+      Ns[t] = sn;
     }
     __syncthreads();
-    for (int jj = q; jj < RB_PTS; jj += 4) {
-      double g = 0.0;
 #pragma unroll
-      for (int k = 0; k < DMAX; ++k) g += xi[k] * Xs[jj][k];
-      const double d2 = fmax(ni + Ns[jj] - 2.0 * g, 0.0);
-      const double kv = exp(-d2 * c2);
-      const double y = (MODE == 0 ? kv : kv * d2 * inv_s3) * Ps[jj] - comp;
-      const double ts = acc + y;
-      comp = (ts - acc) - y;
-      acc = ts;
+    for (int st = 0; st < RB_PTS / 16; ++st) {
+      const int pt = st * 16 + (lane & 15);
+      d4 g = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks) g = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ks], Xs[pt][4 * ks + (lane >> 4)], g, 0, 0, 0);
+      const double nj = Ns[pt], pj = Ps[pt];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const double d2 = fmax(ni[q] + nj - 2.0 * g[q], 0.0);
+        const double kv = exp(-d2 * c2);
+        const double y = (MODE == 0 ? kv : kv * d2 * inv_s3) * pj - cmp[q];
+        const double ts = acc[q] + y;
+        cmp[q] = (ts - acc[q]) - y;
+        acc[q] = ts;
+      }
     }
   }
-  Red[q][il] = acc - comp;
-  __syncthreads();
-  if (q == 0 && i < nr)
-    part[(int64_t)blockIdx.y * nr + i] = Red[0][il] + Red[1][il] + Red[2][il] + Red[3][il];
+  // rows 4 q + l / 16: add the 16 lanes (points) of each group in a fixed tree
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    double v = acc[q] - cmp[q];
+    for (int o = 1; o < 16; o <<= 1) v += __shfl_xor(v, o, 64);
+    const int64_t row = i0 + 4 * q + (lane >> 4);
+    if ((lane & 15) == 0 && row < nr) part[(int64_t)blockIdx.y * nr + row] = v;
+  }
 }
 
-typedef double d4 __attribute__((ext_vector_type(4)));
+// Launches rbf_mv_f64m with the fewest coordinate steps that cover d (<= 64).
+template <typename TD, int MODE>
+void launch_rbf_mv_f64(dim3 grid, hipStream_t s, const TD* Xr, int64_t nr, int64_t ldr, const TD* Xc,
+                       int64_t nc, int64_t ldc, int d, double c2, double is3, const double* p,
+                       double* part, int64_t pps, const int* skip) {
+#define LM(KS) hipLaunchKernelGGL((rbf_mv_f64m<TD, KS, MODE>), grid, dim3(256), 0, s, Xr, nr, ldr, Xc, nc, ldc, d, c2, is3, p, part, pps, skip)
+  if (d <= 4) LM(1);
+  else if (d <= 8) LM(2);
+  else if (d <= 16) LM(4);
+  else if (d <= 32) LM(8);
+  else LM(16);
+#undef LM
+}
 
 // Block of columns: V[I, c0:c0+64] (+)= K_IJ P[J, c0:c0+64] with MFMA f64.
 // Grid: (row blocks, column chunks of 64, point splits).  Output partials
@@ -275,9 +320,7 @@ nys_status rbf_apply_f64_t(const OpDesc& op, const double* P, int64_t k, int64_t
     const int64_t pps = cdiv(cdiv(n, ns), RB_PTS) * RB_PTS;
     ns = cdiv(n, pps);
     dim3 grid((unsigned)nrb, (unsigned)ns);
-#define L1(DM) hipLaunchKernelGGL((rbf_mv_f64<TD, DM, 0>), grid, dim3(256), 0, s, X, n, op.ld, X, n, op.ld, d, c2, 0.0, P, scratch, pps, op.skip)
-    if (dm == 8) L1(8); else if (dm == 16) L1(16); else if (dm == 32) L1(32); else L1(64);
-#undef L1
+    launch_rbf_mv_f64<TD, 0>(grid, s, X, n, op.ld, X, n, op.ld, d, c2, 0.0, P, scratch, pps, op.skip);
     NYS_CHECK_LAUNCH();
     hipLaunchKernelGGL(reduce_splits_mu, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, s, scratch,
                        (int)ns, n, (int64_t)1, op.scale, P, ldp, mu_dev, nrhs, V, ldv, op.skip);
@@ -329,11 +372,10 @@ nys_status rbf_rect_t(const TD* Xr, int64_t nr, int64_t ldr, const TD* Xc, int64
   const int64_t pps = cdiv(cdiv(nc, ns), RB_PTS) * RB_PTS;
   ns = cdiv(nc, pps);
   dim3 grid((unsigned)nrb, (unsigned)ns);
-#define L3(DM, MD) hipLaunchKernelGGL((rbf_mv_f64<TD, DM, MD>), grid, dim3(256), 0, s, Xr, nr, ldr, Xc, nc, ldc, d, c2, is3, p, scratch, pps, (const int*)nullptr)
-#define L3D(MD) if (dm == 8) L3(8, MD); else if (dm == 16) L3(16, MD); else if (dm == 32) L3(32, MD); else L3(64, MD)
-  if (mode == 0) { L3D(0); } else { L3D(1); }
-#undef L3D
-#undef L3
+  if (mode == 0)
+    launch_rbf_mv_f64<TD, 0>(grid, s, Xr, nr, ldr, Xc, nc, ldc, d, c2, is3, p, scratch, pps, nullptr);
+  else
+    launch_rbf_mv_f64<TD, 1>(grid, s, Xr, nr, ldr, Xc, nc, ldc, d, c2, is3, p, scratch, pps, nullptr);
   NYS_CHECK_LAUNCH();
   hipLaunchKernelGGL(reduce_splits_mu, dim3((unsigned)cdiv(nr, 256)), dim3(256), 0, s, scratch,
                      (int)ns, nr, (int64_t)1, 1.0, (const double*)nullptr, (int64_t)1,
@@ -485,11 +527,13 @@ nys_status op_matvec_partials<double>(const OpDesc& op, const double* p, double*
     const int64_t pps = cdiv(cdiv(n, ns), RB_PTS) * RB_PTS;
     ns = cdiv(n, pps);
     dim3 grid((unsigned)nrb, (unsigned)ns);
-#define LP(TD_, DM) hipLaunchKernelGGL((rbf_mv_f64<TD_, DM, 0>), grid, dim3(256), 0, s, static_cast<const TD_*>(op.data), n, op.ld, static_cast<const TD_*>(op.data), n, op.ld, d, c2, 0.0, p, part, pps, op.skip)
-#define LPD(TD_) if (dm == 8) LP(TD_, 8); else if (dm == 16) LP(TD_, 16); else if (dm == 32) LP(TD_, 32); else LP(TD_, 64)
-    if (op.dtype == NYS_F64) { LPD(double); } else { LPD(float); }
-#undef LPD
-#undef LP
+    if (op.dtype == NYS_F64) {
+      const double* X = static_cast<const double*>(op.data);
+      launch_rbf_mv_f64<double, 0>(grid, s, X, n, op.ld, X, n, op.ld, d, c2, 0.0, p, part, pps, op.skip);
+    } else {
+      const float* X = static_cast<const float*>(op.data);
+      launch_rbf_mv_f64<float, 0>(grid, s, X, n, op.ld, X, n, op.ld, d, c2, 0.0, p, part, pps, op.skip);
+    }
     NYS_CHECK_LAUNCH();
     *ng_out = (int)ns;
     return NYS_OK;

@@ -264,6 +264,58 @@ __global__ void cg_direction(int64_t n, int64_t k, const T* __restrict__ Z, T* _
   }
 }
 
+// x += a p, r -= a v over a whole vector by one workgroup, UN entries per
+// thread in flight per pass; returns this thread's part of ||r||^2 (entries in
+// increasing order, so the sum does not depend on UN).
+template <typename T, int UN>
+__device__ __forceinline__ double update_xr(int64_t n, T a, const T* __restrict__ P, const T* __restrict__ V,
+                                            T* __restrict__ X, T* __restrict__ R) {
+  double rr = 0.0;
+  for (int64_t i0 = threadIdx.x; i0 < n; i0 += UN * NT) {
+    T xv[UN], pv[UN], rv[UN], vv[UN];
+#pragma unroll
+    for (int u = 0; u < UN; ++u) {
+      const int64_t i = i0 + (int64_t)u * NT;
+      const int64_t ic = i < n ? i : n - 1;
+      xv[u] = X[ic];
+      pv[u] = P[ic];
+      rv[u] = R[ic];
+      vv[u] = V[ic];
+    }
+#pragma unroll
+    for (int u = 0; u < UN; ++u) {
+      const int64_t i = i0 + (int64_t)u * NT;
+      if (i < n) {
+        X[i] = xv[u] + a * pv[u];
+        const T r = rv[u] - a * vv[u];
+        R[i] = r;
+        rr += double(r) * double(r);
+      }
+    }
+  }
+  return rr;
+}
+
+// P = Z + b P over a whole vector by one workgroup (set-up: P = Z, P not read).
+template <typename T, int UN>
+__device__ __forceinline__ void update_dir(int64_t n, T b, bool setup, const T* __restrict__ Z, T* __restrict__ P) {
+  for (int64_t i0 = threadIdx.x; i0 < n; i0 += UN * NT) {
+    T zv[UN], pv[UN];
+#pragma unroll
+    for (int u = 0; u < UN; ++u) {
+      const int64_t i = i0 + (int64_t)u * NT;
+      const int64_t ic = i < n ? i : n - 1;
+      zv[u] = Z[ic];
+      pv[u] = setup ? T(0) : P[ic];
+    }
+#pragma unroll
+    for (int u = 0; u < UN; ++u) {
+      const int64_t i = i0 + (int64_t)u * NT;
+      if (i < n) P[i] = zv[u] + b * pv[u];
+    }
+  }
+}
+
 // Single vector, fused: finish the operator product from its partial sums,
 // v = scale * sum_g part[g] + mu p (block: 32 entries x 8 slices of g), then
 // partial p^T v; the last block derives alpha and, when `fuse` is set (small
@@ -285,16 +337,17 @@ __global__ __launch_bounds__(NT) void cg_finish_mv(int64_t n, const T* __restric
     const int64_t j = tile * 32 + c;
     const int64_t jc = j < n ? j : n - 1;
     T a0 = T(0);
-    // slice sl: groups sl, sl + 8, ...; eight loads in flight per pass, summed in order
-    for (int g0 = sl; g0 < ng; g0 += 64) {
-      T v[8];
+    // slice sl: groups sl, sl + 8, ...; 32 loads in flight per pass (one pass
+    // for ng <= 256), summed in group order
+    for (int g0 = sl; g0 < ng; g0 += 256) {
+      T v[32];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
+      for (int u = 0; u < 32; ++u) {
         const int g = g0 + 8 * u;
         v[u] = g < ng ? part[(int64_t)g * n + jc] : T(0);
       }
 #pragma unroll
-      for (int u = 0; u < 8; ++u) a0 += v[u];
+      for (int u = 0; u < 32; ++u) a0 += v[u];
     }
     __syncthreads();
     shp[sl][c] = a0;
@@ -329,29 +382,7 @@ __global__ __launch_bounds__(NT) void cg_finish_mv(int64_t n, const T* __restric
   __syncthreads();
   if (!fuse) return;
   const T a = T(alpha_s);
-  double rr = 0.0;
-  for (int64_t i0 = threadIdx.x; i0 < n; i0 += 4 * NT) {  // loads of four entries in flight
-    T xv[4], pv4[4], rv[4], vv[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int64_t i = i0 + (int64_t)u * NT;
-      const int64_t ic = i < n ? i : n - 1;
-      xv[u] = X[ic];
-      pv4[u] = P[ic];
-      rv[u] = R[ic];
-      vv[u] = V[ic];
-    }
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int64_t i = i0 + (int64_t)u * NT;
-      if (i < n) {
-        X[i] = xv[u] + a * pv4[u];
-        const T r = rv[u] - a * vv[u];
-        R[i] = r;
-        rr += double(r) * double(r);
-      }
-    }
-  }
+  double rr = n <= 16 * NT ? update_xr<T, 16>(n, a, P, V, X, R) : update_xr<T, 4>(n, a, P, V, X, R);
   rr = block_sum(rr, sh);
   if (threadIdx.x == 0 && !sc.done[0]) {
     sc.rnorm2[0] = rr;
@@ -397,36 +428,34 @@ __global__ __launch_bounds__(NT) void utr_part(int64_t n, int64_t l, const TU* _
     part[(int64_t)blockIdx.y * l + j] = (red[0][tx] + red[1][tx]) + (red[2][tx] + red[3][tx]);
 }
 
-// C'[j] = ((lam_l + mu)/(lam_j + mu) - 1) sum_chunk part[chunk][j].  One wave
-// per 16 columns; lane q takes chunks q, q + 64, ... (16 loads in flight per
-// pass) and a fixed shuffle tree adds the lanes (deterministic).
+// C'[j] = ((lam_l + mu)/(lam_j + mu) - 1) sum_chunk part[chunk][j].  Thread
+// (tx, ty): column tx of the block of 64, chunks ty, ty + 4, ... (up to 32
+// loads in flight per pass); the four slices are added in a fixed order.
 __global__ __launch_bounds__(NT) void utr_final(int64_t l, int nch, const double* __restrict__ part,
                                                 const double* __restrict__ lam, const double* __restrict__ mu,
                                                 double* __restrict__ Cs, const int* __restrict__ alldone) {
   if (alldone && *alldone) return;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int64_t jb = ((int64_t)blockIdx.x * 4 + wave) * 16;
-  double sums[16];
+  __shared__ double red[4][64];
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  const int64_t j = (int64_t)blockIdx.x * 64 + tx;
+  const int64_t jc = j < l ? j : l - 1;
+  double acc = 0.0;
+  for (int q0 = ty; q0 < nch; q0 += 4 * 32) {
+    double v[32];
 #pragma unroll
-  for (int cc = 0; cc < 16; ++cc) sums[cc] = 0.0;
-  for (int q0 = 0; q0 < nch; q0 += 64) {
-    const int q = q0 + lane;
-#pragma unroll
-    for (int cc = 0; cc < 16; ++cc)
-      if (q < nch && jb + cc < l) sums[cc] += part[(int64_t)q * l + jb + cc];
-  }
-#pragma unroll
-  for (int cc = 0; cc < 16; ++cc) sums[cc] = wave_sum(sums[cc]);
-  if (lane < 16) {
-    double tot = sums[0];
-#pragma unroll
-    for (int cc = 1; cc < 16; ++cc)
-      if (lane == cc) tot = sums[cc];
-    const int64_t jj = jb + lane;
-    if (jj < l) {
-      const double m = mu[0];
-      Cs[jj] = ((lam[l - 1] + m) / (lam[jj] + m) - 1.0) * tot;
+    for (int u = 0; u < 32; ++u) {
+      const int q = q0 + 4 * u;
+      v[u] = q < nch ? part[(int64_t)q * l + jc] : 0.0;
     }
+#pragma unroll
+    for (int u = 0; u < 32; ++u) acc += v[u];
+  }
+  red[ty][tx] = acc;
+  __syncthreads();
+  if (ty == 0 && j < l) {
+    const double tot = (red[0][tx] + red[1][tx]) + (red[2][tx] + red[3][tx]);
+    const double m = mu[0];
+    Cs[j] = ((lam[l - 1] + m) / (lam[j] + m) - 1.0) * tot;
   }
 }
 
@@ -455,6 +484,9 @@ __global__ __launch_bounds__(NT) void uc_rz(int64_t n, int64_t l, const TU* __re
   for (int64_t ib = w0; ib < w1; ib += 4) {
     const int64_t nr = (w1 - ib) < 4 ? (w1 - ib) : 4;
     TU u[4][NJ];
+    T rv[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) rv[q] = r[ib + (q < nr ? q : 0)];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int64_t row = ib + (q < nr ? q : 0);
@@ -472,11 +504,13 @@ __global__ __launch_bounds__(NT) void uc_rz(int64_t n, int64_t l, const TU* __re
       for (int jj = 0; jj < NJ; ++jj) acc += T(u[q][jj]) * cs[jj];  // cs = 0 past l
       sv[q] = wave_sum(acc);
     }
-    for (int q = 0; q < nr; ++q) {
-      const T ri = r[ib + q];
-      const T zi = ri + sv[q];
-      if (lane == q) z[ib + q] = zi;
-      rzp += double(ri) * double(zi);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      if (q < nr) {
+        const T zi = rv[q] + sv[q];
+        if (lane == q) z[ib + q] = zi;
+        rzp += double(rv[q]) * double(zi);
+      }
     }
   }
   if (mode == 0) return;
@@ -489,22 +523,9 @@ __global__ __launch_bounds__(NT) void uc_rz(int64_t n, int64_t l, const TU* __re
   // fused direction update (small n): P = Z (set-up) or P = Z + beta P
   __syncthreads();
   const T b = mode == 1 ? T(0) : T(sc.beta[0]);
-  if (mode == 1 || !sc.done[0]) {
-    for (int64_t i0 = threadIdx.x; i0 < n; i0 += 4 * NT) {  // loads of four entries in flight
-      T zv[4], pv4[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int64_t i = i0 + (int64_t)u * NT;
-        const int64_t ic = i < n ? i : n - 1;
-        zv[u] = z[ic];
-        pv4[u] = mode == 1 ? T(0) : Pd[ic];  // set-up: P = Z (P not read: it is uninitialised)
-      }
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int64_t i = i0 + (int64_t)u * NT;
-        if (i < n) Pd[i] = zv[u] + b * pv4[u];
-      }
-    }
+  if (mode == 1 || !sc.done[0]) {  // set-up: P = Z (P not read: it is uninitialised)
+    if (n <= 16 * NT) update_dir<T, 16>(n, b, mode == 1, z, Pd);
+    else update_dir<T, 4>(n, b, mode == 1, z, Pd);
   }
 }
 

@@ -71,6 +71,37 @@ def test_op_apply(kind, k):
     np.testing.assert_allclose(out, ref.matmat(V) + mu * V, rtol=1e-12, atol=1e-12)
 
 
+@pytest.mark.parametrize("case", ["dense64", "xtx32_f64", "xtx32_sketch_f32"])
+def test_large_tile_products(case):
+    """Products of at least 1e9 multiply-adds with 16-byte aligned operands take
+    the 128 x 128 tile GEMM (split-K when the output has few tiles); the sizes
+    leave ragged tiles in every dimension."""
+    rng = np.random.default_rng(7)
+    if case == "dense64":
+        n, k = 2050, 250
+        A = rng.standard_normal((n, n))
+        A = A + A.T
+        V = rng.standard_normal((n, k))
+        out = h(nys.nys_op_apply(nys.Operator.dense(t64(A)), 0.25, t64(V)))
+        assert rel(out, A @ V + 0.25 * V) < 1e-13
+    elif case == "xtx32_f64":
+        X = rng.standard_normal((4001, 1204)).astype(np.float32)
+        V = rng.standard_normal((1204, 210))
+        out = h(nys.nys_op_apply(nys.Operator.xtx(t32(X), scale=0.5), 0.25, t64(V)))
+        ref = oracle.XtXOp(X.astype(np.float64), 0.5).matmat(V) + 0.25 * V
+        assert rel(out, ref) < 1e-13
+    else:
+        X = rng.standard_normal((4001, 1204)).astype(np.float32)
+        om0 = rng.standard_normal((1204, 212))
+        op = nys.Operator.xtx(t32(X))
+        Om, Y = nys.nys_sketch(op, 212, omega0=t64(om0), prec=nys.NYS_PREC_FP32_REFINE64)
+        Om, Y = h(Om), h(Y)
+        Q = oracle.orthonormalize(om0)
+        ref = oracle.XtXOp(X.astype(np.float64)).matmat(Q)
+        # float32 products over K = 4001 and 1204 terms: relative error ~1e-6
+        assert rel(Y @ Om.T, ref @ Q.T) < 2e-5
+
+
 @pytest.mark.parametrize("d", [1, 8, 33])
 def test_rbf_single_vector_dims(d):
     rng = np.random.default_rng(200 + d)
