@@ -94,10 +94,19 @@ struct CholArgs {
   int* info;        // 0 = ok, k+1 = non-positive pivot at column k
 };
 
-// Unblocked Cholesky + inverse of one NB x NB diagonal block in LDS.
-__device__ void factor_diag_block(CholArgs a, int kb, double (*T)[NB + 1], double (*Ti)[NB + 1]) {
-  // restrict-qualified views of the global arrays: the tile loads may then be
-  // issued together, ahead of the LDS stores
+// Blocked right-looking Cholesky, one launch per step (the stream orders
+// them): diagonal block (one wave), panel below it, trailing update.
+
+// Cholesky + inverse of one NB x NB diagonal block by one wave: lane i keeps
+// row i of the factor in registers (left-looking: column j is A[i][j] -
+// sum_{k<j} L[i][k] L[j][k], row j read back from LDS as a broadcast), then
+// lane j forms column j of L^{-1} by forward substitution.  Lanes 32..63
+// repeat lanes 0..31 and store nothing.
+__global__ __launch_bounds__(64) void chol_diag(CholArgs a, int kb) {
+  if (*((volatile int*)a.info) != 0) return;
+  __shared__ double T[NB][NB + 1];
+  __shared__ double Piv;
+  __shared__ double Ys[NB];  // 1 / L[j][j]
   double* __restrict__ Lg = a.L;
   double* __restrict__ Dg = a.Dinv;
   const int64_t n = a.n;
@@ -105,76 +114,74 @@ __device__ void factor_diag_block(CholArgs a, int kb, double (*T)[NB + 1], doubl
   const int nbk = (int)((n - base) < NB ? (n - base) : NB);
   const int t = threadIdx.x;
   {
-    double v[NB * NB / 256];
+    double v[NB * NB / 64];
 #pragma unroll
-    for (int u = 0; u < NB * NB / 256; ++u) {
-      const int e = t + 256 * u, i = e / NB, j = e % NB;
+    for (int u = 0; u < NB * NB / 64; ++u) {
+      const int e = t + 64 * u, i = e / NB, j = e % NB;
       v[u] = (i < nbk && j < nbk && j <= i) ? Lg[(base + i) * n + base + j] : (i == j ? 1.0 : 0.0);
     }
 #pragma unroll
-    for (int u = 0; u < NB * NB / 256; ++u) {
-      const int e = t + 256 * u, i = e / NB, j = e % NB;
-      T[i][j] = v[u];  // padding outside the matrix: identity
-      Ti[i][j] = 0.0;
+    for (int u = 0; u < NB * NB / 64; ++u) {
+      const int e = t + 64 * u;
+      T[e / NB][e % NB] = v[u];  // padding outside the matrix: identity
     }
   }
   __syncthreads();
-  __shared__ int bad;
-  if (t == 0) bad = 0;
+  const int i = t & (NB - 1);
+  const bool own = t < NB;
+  double r[NB];
+#pragma unroll
+  for (int j = 0; j < NB; ++j) r[j] = (j <= i) ? T[i][j] : 0.0;
   __syncthreads();
-  __shared__ double rinv;
-  for (int k = 0; k < NB; ++k) {
-    if (t == 0) {
-      const double d = T[k][k];
-      if (!(d > 0.0) || !isfinite(d)) {
-        bad = 1;
-        if (k < nbk && atomicCAS(a.info, 0, (int)(base + k + 1)) == 0) {}
-        T[k][k] = 1.0;
-        rinv = 1.0;
-      } else {
-        const double y = frsq(d);  // 1 / sqrt(d)
-        T[k][k] = d * y;
-        rinv = y;
-      }
+  // from here T[j][k], k < j, holds the finished factor entry L[j][k]
+  int bad = -1;
+#pragma unroll
+  for (int j = 0; j < NB; ++j) {
+    double s0 = r[j], s1 = 0.0;
+#pragma unroll
+    for (int k = 0; k < j; k += 2) {
+      s0 -= r[k] * T[j][k];
+      if (k + 1 < j) s1 -= r[k + 1] * T[j][k + 1];
     }
+    const double sj = s0 + s1;
+    if (own && i == j) Piv = sj;
     __syncthreads();
-    const double ri = rinv;
-    for (int i = k + 1 + t; i < NB; i += blockDim.x) T[i][k] *= ri;
-    __syncthreads();
-    #pragma unroll
-    for (int e = t; e < NB * NB; e += 256) {
-      const int i = e / NB, j = e % NB;
-      if (i > k && j > k && j <= i) T[i][j] -= T[i][k] * T[j][k];
+    double d = Piv;
+    double yj;
+    if (!(d > 0.0) || !isfinite(d)) {
+      if (bad < 0) bad = j;
+      d = 1.0;
+      yj = 1.0;
+    } else {
+      yj = frsq(d);  // 1 / sqrt(d)
     }
+    r[j] = (i == j) ? d * yj : (i > j ? sj * yj : 0.0);
+    if (own) T[i][j] = r[j];
+    if (t == 0) Ys[j] = yj;
     __syncthreads();
   }
-  // inverse of the lower factor, row by row: Ti[i][j] = (delta_ij - sum_{k<i}
-  // T[i][k] Ti[k][j]) / T[i][i], the NB columns j in parallel
-  for (int i = 0; i < NB; ++i) {
-    if (t < NB) {
-      const int j = t;
-      double sacc = (i == j) ? 1.0 : 0.0;
-      for (int k = j; k < i; ++k) sacc -= T[i][k] * Ti[k][j];
-      Ti[i][j] = (j <= i) ? sacc * frcp(T[i][i]) : 0.0;
+  if (bad >= 0 && bad < nbk && t == 0) atomicCAS(a.info, 0, (int)(base + bad + 1));
+  if (own) {
+#pragma unroll
+    for (int j = 0; j < NB; ++j)
+      if (i < nbk && j < nbk) Lg[(base + i) * n + base + j] = r[j];
+  }
+  // column i of the inverse: x[m] = (delta_mi - sum_{k<m} L[m][k] x[k]) / L[m][m]
+  double x[NB];
+#pragma unroll
+  for (int m = 0; m < NB; ++m) {
+    double s0 = (m == i) ? 1.0 : 0.0, s1 = 0.0;
+#pragma unroll
+    for (int k = 0; k < m; k += 2) {
+      s0 -= T[m][k] * x[k];
+      if (k + 1 < m) s1 -= T[m][k + 1] * x[k + 1];
     }
-    __syncthreads();
+    x[m] = (s0 + s1) * Ys[m];
   }
-  #pragma unroll
-  for (int e = t; e < NB * NB; e += 256) {
-    const int i = e / NB, j = e % NB;
-    if (i < nbk && j < nbk) Lg[(base + i) * n + base + j] = (j <= i) ? T[i][j] : 0.0;
-    Dg[(int64_t)kb * NB * NB + e] = Ti[i][j];
+  if (own) {
+#pragma unroll
+    for (int m = 0; m < NB; ++m) Dg[(int64_t)kb * NB * NB + m * NB + i] = x[m];
   }
-  (void)bad;
-}
-
-// Blocked right-looking Cholesky, one launch per step (the stream orders
-// them): diagonal block (one workgroup), panel below it, trailing update.
-__global__ __launch_bounds__(256) void chol_diag(CholArgs a, int kb) {
-  if (*((volatile int*)a.info) != 0) return;
-  __shared__ double T[NB][NB + 1];
-  __shared__ double Ti[NB][NB + 1];
-  factor_diag_block(a, kb, T, Ti);
 }
 
 // L[ib,kb] = A[ib,kb] * Dinv_kb^T for ib = kb + 1 + blockIdx.x
@@ -267,73 +274,88 @@ __global__ __launch_bounds__(256) void chol_trail(CholArgs a, int kb) {
 
 // ---------------------------------------------------------------- L^{-1}
 
-// One workgroup per column block jb: X[jb][jb] = Dinv_jb and, for ib > jb,
-// X[ib][jb] = -Dinv_ib * sum_{kb=jb}^{ib-1} L[ib][kb] X[kb][jb].
-__global__ __launch_bounds__(256) void trinv_blocks(const double* __restrict__ L, int64_t n,
-                                                    const double* __restrict__ Dinv,
-                                                    double* __restrict__ X) {
-  __shared__ double Acc[NB][NB + 1];
-  __shared__ double Lt[NB][NB + 1];
-  __shared__ double Xt[NB][NB + 1];
-  const int nblk = (int)cdiv(n, NB);
-  const int jb = blockIdx.x;
+// L^{-1} by recursive doubling over the diagonal blocks.  With X11, X22 the
+// inverses of two neighbouring diagonal blocks of size bs and L21 the block
+// below the first, the inverse of the pair is [X11 0; X21 X22] with
+// X21 = -X22 (L21 X11).  Level bs = NB, 2 NB, ... doubles the inverted blocks;
+// each level is two launches (T = L21 X11, then X21 = -X22 T), parallel over
+// pairs and 32 x 32 output tiles.  T is kept in the mirror block X12 of the
+// strict upper triangle, which is cleared at the end; only block-lower tiles
+// of X11 and X22 are read, so stale T blocks are never used.
+
+// X = 0 except the diagonal blocks (Dinv).
+__global__ void trinv_init(int64_t n, const double* __restrict__ Dinv, double* __restrict__ X) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= n * n) return;
+  const int64_t i = idx / n, j = idx % n;
+  const int64_t bi = i / NB, bj = j / NB;
+  X[idx] = (bi == bj) ? Dinv[bi * NB * NB + (i % NB) * NB + (j % NB)] : 0.0;
+}
+
+// phase 0: T = L21 X11 (stored at X12); phase 1: X21 = -X22 T.
+// Grid: (tiles per pair (bs/NB)^2, pairs).  256 threads, 4 outputs each.
+__global__ __launch_bounds__(256) void trinv_level(const double* __restrict__ L, int64_t n, double* X,
+                                                   int64_t bs, int phase) {
+  __shared__ double As[NB][NB + 1];
+  __shared__ double Bs[NB][NB + 1];
+  const int64_t tb = bs / NB;
+  const int64_t ti = blockIdx.x / tb, tj = blockIdx.x % tb;
+  const int64_t o1 = (int64_t)blockIdx.y * 2 * bs, o2 = o1 + bs;  // offsets of blocks 1 and 2
+  if (o2 >= n) return;
   const int t = threadIdx.x;
-  const int64_t c0 = (int64_t)jb * NB;
-  // zero the strictly-upper column blocks of this column block
-  for (int64_t r = t; r < c0; r += blockDim.x)
-    for (int j = 0; j < NB && c0 + j < n; ++j) X[r * n + c0 + j] = 0.0;
-  // diagonal block
-  #pragma unroll
-  for (int e = t; e < NB * NB; e += 256) {
-    const int i = e / NB, j = e % NB;
-    if (c0 + i < n && c0 + j < n) X[(c0 + i) * n + c0 + j] = Dinv[(int64_t)jb * NB * NB + e];
-  }
-  __threadfence_block();
-  __syncthreads();
-  for (int ib = jb + 1; ib < nblk; ++ib) {
-    const int64_t r0 = (int64_t)ib * NB;
-    #pragma unroll
-    for (int e = t; e < NB * NB; e += 256) Acc[e / NB][e % NB] = 0.0;
+  const int ci = t >> 3, cj0 = (t & 7) * 4;  // row ci, columns cj0 .. cj0 + 3 of the tile
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  // phase 0: sum over k-blocks kb >= tj (X11 block-lower); phase 1: kb <= ti (X22 block-lower)
+  const int64_t kb0 = phase == 0 ? tj : 0, kb1 = phase == 0 ? tb : ti + 1;
+  for (int64_t kb = kb0; kb < kb1; ++kb) {
     __syncthreads();
-    for (int kb = jb; kb < ib; ++kb) {
-      const int64_t k0 = (int64_t)kb * NB;
-      {
-        double v[NB * NB / 256], w[NB * NB / 256];
+    double va[4], vb[4];
 #pragma unroll
-        for (int u = 0; u < NB * NB / 256; ++u) {
-          const int e = t + 256 * u, i = e / NB, j = e % NB;
-          v[u] = (r0 + i < n && k0 + j < n) ? L[(r0 + i) * n + k0 + j] : 0.0;
-          w[u] = (k0 + i < n && c0 + j < n) ? X[(k0 + i) * n + c0 + j] : 0.0;
-        }
-#pragma unroll
-        for (int u = 0; u < NB * NB / 256; ++u) {
-          const int e = t + 256 * u;
-          Lt[e / NB][e % NB] = v[u];
-          Xt[e / NB][e % NB] = w[u];
-        }
+    for (int u = 0; u < 4; ++u) {
+      const int e = t + 256 * u, r = e / NB, c = e % NB;
+      int64_t ar, ac, br, bc;
+      const double* Ap;
+      if (phase == 0) {  // A = L21 tile (ti, kb), B = X11 tile (kb, tj)
+        ar = o2 + ti * NB + r; ac = o1 + kb * NB + c; Ap = L;
+        br = o1 + kb * NB + r; bc = o1 + tj * NB + c;
+      } else {           // A = X22 tile (ti, kb), B = T tile (kb, tj) at X12 (transposed position)
+        ar = o2 + ti * NB + r; ac = o2 + kb * NB + c; Ap = X;
+        br = o1 + tj * NB + c; bc = o2 + kb * NB + r;
       }
-      __syncthreads();
-      #pragma unroll
-      for (int e = t; e < NB * NB; e += 256) {
-        const int i = e / NB, j = e % NB;
-        double s = 0.0;
+      va[u] = (ar < n && ac < n) ? Ap[ar * n + ac] : 0.0;
+      vb[u] = (br < n && bc < n) ? X[br * n + bc] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int e = t + 256 * u;
+      As[e / NB][e % NB] = va[u];
+      Bs[e / NB][e % NB] = vb[u];
+    }
+    __syncthreads();
 #pragma unroll 8
-        for (int k = 0; k < NB; ++k) s += Lt[i][k] * Xt[k][j];
-        Acc[i][j] += s;
-      }
-      __syncthreads();
+    for (int k = 0; k < NB; ++k) {
+      const double av = As[ci][k];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) acc[q] += av * Bs[k][cj0 + q];
     }
-    const double* Di = Dinv + (int64_t)ib * NB * NB;
-    #pragma unroll
-    for (int e = t; e < NB * NB; e += 256) {
-      const int i = e / NB, j = e % NB;
-      double s = 0.0;
-      for (int k = 0; k <= i; ++k) s += Di[i * NB + k] * Acc[k][j];
-      if (r0 + i < n && c0 + j < n) X[(r0 + i) * n + c0 + j] = -s;
-    }
-    __threadfence_block();
-    __syncthreads();
   }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int64_t r = ti * NB + ci, c = tj * NB + cj0 + q;
+    if (phase == 0) {  // T[r][c] -> X[o1 + c][o2 + r]
+      if (o1 + c < n && o2 + r < n) X[(o1 + c) * n + o2 + r] = acc[q];
+    } else {
+      if (o2 + r < n && o1 + c < n) X[(o2 + r) * n + o1 + c] = -acc[q];
+    }
+  }
+}
+
+// zero the strict upper triangle
+__global__ void trinv_clear_upper(int64_t n, double* __restrict__ X) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= n * n) return;
+  const int64_t i = idx / n, j = idx % n;
+  if (j > i && j / NB != i / NB) X[idx] = 0.0;
 }
 
 // ---------------------------------------------------------------- Jacobi
@@ -762,7 +784,7 @@ nys_status cholesky(const double* M, int64_t n, double* L, double* Dinv, int* in
   CholArgs a{L, n, Dinv, info};
   const int nblk = (int)cdiv(n, NB);
   for (int kb = 0; kb < nblk; ++kb) {
-    hipLaunchKernelGGL(chol_diag, dim3(1), dim3(256), 0, s, a, kb);
+    hipLaunchKernelGGL(chol_diag, dim3(1), dim3(64), 0, s, a, kb);
     const int rem = nblk - kb - 1;
     if (rem > 0) {
       hipLaunchKernelGGL(chol_panel, dim3((unsigned)rem), dim3(256), 0, s, a, kb);
@@ -774,7 +796,17 @@ nys_status cholesky(const double* M, int64_t n, double* L, double* Dinv, int* in
 }
 
 nys_status tri_inverse(const double* L, int64_t n, const double* Dinv, double* X, hipStream_t s) {
-  hipLaunchKernelGGL(trinv_blocks, dim3((unsigned)cdiv(n, NB)), dim3(256), 0, s, L, n, Dinv, X);
+  const unsigned ne = (unsigned)cdiv(n * n, 256);
+  hipLaunchKernelGGL(trinv_init, dim3(ne), dim3(256), 0, s, n, Dinv, X);
+  NYS_CHECK_LAUNCH();
+  for (int64_t bs = NB; bs < n; bs *= 2) {
+    const int64_t tb = bs / NB;
+    dim3 grid((unsigned)(tb * tb), (unsigned)cdiv(n, 2 * bs));
+    hipLaunchKernelGGL(trinv_level, grid, dim3(256), 0, s, L, n, X, bs, 0);
+    hipLaunchKernelGGL(trinv_level, grid, dim3(256), 0, s, L, n, X, bs, 1);
+    NYS_CHECK_LAUNCH();
+  }
+  hipLaunchKernelGGL(trinv_clear_upper, dim3(ne), dim3(256), 0, s, n, X);
   NYS_CHECK_LAUNCH();
   return NYS_OK;
 }
