@@ -428,7 +428,8 @@ __device__ __forceinline__ bool jacobi_rot_bf(double app, double aqq, double apq
 // Block two-sided Jacobi.  The m x m matrix (m = nblk * JB, nblk even) is cut
 // into JB x JB blocks; a round pairs the blocks by the round-robin schedule.
 // Phase 1 (one workgroup per block pair (P, Q)): load the JS x JS subproblem
-// [A_PP A_PQ; A_QP A_QQ] into LDS, run a cyclic Jacobi sweep on it, keep the
+// [A_PP A_PQ; A_QP A_QQ] into LDS, rotate its index pairs (all of them in the
+// first round of a sweep, only the P-Q pairs in later rounds), keep the
 // accumulated rotation J_k and write the rotated subproblem back.  Phase 2
 // (one workgroup per tile): A <- J^T A J on the off-diagonal pair tiles
 // (J_k^T A_kk' J_k') and V <- V J.  Phases are separate launches on the
@@ -565,15 +566,33 @@ __global__ __launch_bounds__(256) void jac_phase1(JacArgs a, int64_t r, int swee
     if ((t & 63) == 0 && r2max > 0.0f) atomicMax(&maxr, __float_as_uint(r2max));
   }
   const int k1 = t >> 4, k2 = t & 15;
+  // Inner ordering.  The first round of a sweep runs a full round-robin sweep
+  // over the JS indices of each pair, which also covers the pairs inside
+  // every block (each block is in exactly one pair of that round).  Later
+  // rounds only pair an index of P with one of Q: JB inner rounds, round ir
+  // pairing P's i with Q's (i + ir) mod JB, so every pair of indices of the
+  // matrix is still rotated once per sweep, with half the inner rounds.
+  const bool cross = r > 0 && a.inner_sweeps == 1;
+  const int nround = cross ? JB : JS - 1;
   int cur = 0;
   for (int isw = 0; isw < a.inner_sweeps; ++isw) {
     if (t == 0) any_s = 0;
     __syncthreads();
-    for (int ir = 0; ir < JS - 1; ++ir) {
+    for (int ir = 0; ir < nround; ++ir) {
       double(*Si)[JS + 1] = Sb[cur];
       double(*So)[JS + 1] = Sb[cur ^ 1];
-      const int p1 = rr_js(k1, ir), q1 = rr_js(JS - 1 - k1, ir);
-      const int p2 = rr_js(k2, ir), q2 = rr_js(JS - 1 - k2, ir);
+      int p1, q1, p2, q2;
+      if (cross) {
+        p1 = k1;
+        q1 = JB + ((k1 + ir) & (JB - 1));
+        p2 = k2;
+        q2 = JB + ((k2 + ir) & (JB - 1));
+      } else {
+        p1 = rr_js(k1, ir);
+        q1 = rr_js(JS - 1 - k1, ir);
+        p2 = rr_js(k2, ir);
+        q2 = rr_js(JS - 1 - k2, ir);
+      }
       // both rotations, interleaved (pair k2 == k1 on the diagonal blocks gives the same one twice)
       double c1, s1, c2, s2;
       const bool d1 = jacobi_rot_bf(Si[p1][p1], Si[q1][q1], Si[p1][q1], floor_abs, c1, s1);
