@@ -364,8 +364,12 @@ constexpr int JB = 16;       // Jacobi block size
 constexpr int JS = 2 * JB;   // order of one block-pair subproblem
 constexpr int JH = JS / 2;   // rotation pairs per inner round
 
-__device__ __forceinline__ int64_t rr_index(int64_t pos, int64_t r, int64_t m) {
-  return pos == 0 ? 0 : 1 + ((pos - 1 + r) % (m - 1));
+// Position pos of round r of the round-robin schedule over m slots (pos, r < m):
+// slot 0 stays, the others rotate.  32-bit, no division.
+__device__ __forceinline__ int rr_index(int pos, int r, int m) {
+  int x = pos - 1 + r;
+  if (x >= m - 1) x -= m - 1;
+  return pos == 0 ? 0 : 1 + x;
 }
 
 // Rotation (c, s) with J_pp = c, J_pq = s, J_qp = -s, J_qq = c that zeroes
@@ -398,26 +402,27 @@ __device__ __forceinline__ bool jacobi_rot(double app, double aqq, double apq, d
 // Branch-free rotation for the subproblem rounds, same test as jacobi_rot.
 // Only the rotation's exact orthogonality matters for the accuracy of the
 // eigenvectors; its angle only has to annihilate a_pq well enough for the
-// sweeps to converge.  So tau = (a_qq - a_pp) / (2 a_pq) is formed in float64,
-// t = sign(tau) / (|tau| + sqrt(1 + tau^2)) in float32 (relative error
-// ~1e-7: the rotated a_pq drops by that factor, and later sweeps remove the
-// rest), and c = 1/sqrt(1 + t^2), s = t c in float64 from that t, which keeps
-// c^2 + s^2 = 1 to float64 rounding.  Short dependent chain: one float64
-// reciprocal and one float64 reciprocal square root.
+// sweeps to converge.  So tau = (a_qq - a_pp) / (2 a_pq) is formed in float64
+// (hardware reciprocal + one Newton step: relative error far below float32's),
+// t = sign(tau) / (|tau| + sqrt(1 + tau^2)) in float32 (relative error ~1e-7:
+// the rotated a_pq drops by that factor, and later sweeps remove the rest),
+// and c = 1/sqrt(1 + t^2), s = t c in float64 from that t, which keeps
+// c^2 + s^2 = 1 to float64 rounding.  No branches, so the two rotations a
+// thread needs are computed interleaved.
 __device__ __forceinline__ bool jacobi_rot_bf(double app, double aqq, double apq, double floor_abs, double& c,
                                               double& s) {
   const double thr2 = fmax(4.930380657631324e-32 * fabs(app * aqq), floor_abs * floor_abs);
   const bool did = (apq * apq > thr2) && !(fabs(apq) < 1e-300);
-  const double tau = (aqq - app) * 0.5 * frcp(did ? apq : 1.0);
+  const double x = did ? apq : 1.0;
+  double rx = __builtin_amdgcn_rcp(x);
+  rx = fma(rx, fma(-x, rx, 1.0), rx);
+  const double tau = (aqq - app) * 0.5 * rx;
   const float tf = (float)tau;  // |tau| beyond float range: t rounds to 0 (angle < 1e-38)
   const float at = fabsf(tf);
-  float t;
-  if (at > 1e15f) {
-    t = 0.5f * __builtin_amdgcn_rcpf(at);
-  } else {
-    const float h = fmaf(at, at, 1.0f);
-    t = __builtin_amdgcn_rcpf(at + h * __builtin_amdgcn_rsqf(h));
-  }
+  const float h = fmaf(at, at, 1.0f);
+  const float t_small = __builtin_amdgcn_rcpf(at + h * __builtin_amdgcn_rsqf(h));
+  const float t_big = 0.5f * __builtin_amdgcn_rcpf(at);  // |tau| > 1e15: t = 1 / (2 |tau|)
+  const float t = at > 1e15f ? t_big : t_small;
   const double td = (double)(tf < 0.0f ? -t : t);
   const double cc = frsq(fma(td, td, 1.0));
   c = did ? cc : 1.0;
@@ -450,8 +455,8 @@ struct JacArgs {
 };
 
 __device__ __forceinline__ int64_t pair_index(int nblk, int k, int64_t r, int t) {
-  const int64_t blk = (t < JB) ? rr_index(k, r, nblk) : rr_index(nblk - 1 - k, r, nblk);
-  return blk * JB + (t & (JB - 1));
+  const int blk = (t < JB) ? rr_index(k, (int)r, nblk) : rr_index(nblk - 1 - k, (int)r, nblk);
+  return (int64_t)blk * JB + (t & (JB - 1));
 }
 
 typedef double jd4 __attribute__((ext_vector_type(4)));
@@ -515,7 +520,6 @@ __device__ __forceinline__ int rr_js(int pos, int ir) {
 // pair k derives it from the same entries, so they agree), and S is double
 // buffered, so an inner round costs one barrier.
 __global__ __launch_bounds__(256) void jac_phase1(JacArgs a, int64_t r, int sweep) {
-  if (*a.conv) return;
   double* __restrict__ Ag = a.A;
   double* __restrict__ Jg = a.J;
   __shared__ double Sb[2][JS][JS + 1];
@@ -526,19 +530,23 @@ __global__ __launch_bounds__(256) void jac_phase1(JacArgs a, int64_t r, int swee
   const int t = threadIdx.x;
   const int64_t m = a.m;
   const int k = blockIdx.x;
-  const double floor_abs = *a.floor;
-  if (t < JS) gi[t] = pair_index(a.nblk, k, r, t);
-  if (t == 0) {
-    rotated = 0;
-    maxr = 0u;
-  }
-  __syncthreads();
-    {  // issue the four loads of this thread before storing any of them
+  double floor_abs;
+  {
+    // the subproblem loads (in bounds whatever the flags say), the floor and
+    // the converged flag are issued together: one memory latency, not three
+    floor_abs = *a.floor;
     double v[JS * JS / 256];
 #pragma unroll
     for (int u = 0; u < JS * JS / 256; ++u) {
       const int e = t + 256 * u;
-      v[u] = Ag[gi[e / JS] * m + gi[e % JS]];
+      v[u] = Ag[pair_index(a.nblk, k, r, e / JS) * m + pair_index(a.nblk, k, r, e % JS)];
+    }
+    const int done = *a.conv;
+    if (done) return;
+    if (t < JS) gi[t] = pair_index(a.nblk, k, r, t);
+    if (t == 0) {
+      rotated = 0;
+      maxr = 0u;
     }
 #pragma unroll
     for (int u = 0; u < JS * JS / 256; ++u) {
@@ -593,33 +601,38 @@ __global__ __launch_bounds__(256) void jac_phase1(JacArgs a, int64_t r, int swee
         p2 = rr_js(k2, ir);
         q2 = rr_js(JS - 1 - k2, ir);
       }
-      // both rotations, interleaved (pair k2 == k1 on the diagonal blocks gives the same one twice)
-      double c1, s1, c2, s2;
-      const bool d1 = jacobi_rot_bf(Si[p1][p1], Si[q1][q1], Si[p1][q1], floor_abs, c1, s1);
-      const bool d2 = jacobi_rot_bf(Si[p2][p2], Si[q2][q2], Si[p2][q2], floor_abs, c2, s2);
-      if (d1 || d2) any_s = 1;
-      // S <- R^T S R on the 2 x 2 block (rows pair k1, columns pair k2)
+      // every LDS read of the round first: the entries of both rotations, the
+      // 2 x 2 block (rows pair k1, columns pair k2) and this thread's J entries
+      const double r1pp = Si[p1][p1], r1qq = Si[q1][q1], r1pq = Si[p1][q1];
+      const double r2pp = Si[p2][p2], r2qq = Si[q2][q2], r2pq = Si[p2][q2];
       const double app = Si[p1][p2], apq = Si[p1][q2], aqp = Si[q1][p2], aqq = Si[q1][q2];
+      double jp[2], jq[2];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        jp[h] = Jm[k1 + h * JH][p2];
+        jq[h] = Jm[k1 + h * JH][q2];
+      }
+      // both rotations (pair k2 == k1 on the diagonal blocks gives the same one twice)
+      double c1, s1, c2, s2;
+      const bool d1 = jacobi_rot_bf(r1pp, r1qq, r1pq, floor_abs, c1, s1);
+      const bool d2 = jacobi_rot_bf(r2pp, r2qq, r2pq, floor_abs, c2, s2);
+      if (d1 || d2) any_s = 1;
+      // S <- R^T S R on the 2 x 2 block
       const double bpp = c1 * app - s1 * aqp, bpq = c1 * apq - s1 * aqq;
       const double bqp = s1 * app + c1 * aqp, bqq = s1 * apq + c1 * aqq;
       // (on the diagonal blocks the rotated a_pq is kept as computed, not
       // set to zero: the float32 tangent leaves a small remainder that later
       // rounds remove, and S must stay equal to J^T A J)
-      const double npp = c2 * bpp - s2 * bpq, npq = s2 * bpp + c2 * bpq;
-      const double nqp = c2 * bqp - s2 * bqq, nqq = s2 * bqp + c2 * bqq;
-      So[p1][p2] = npp;
-      So[p1][q2] = npq;
-      So[q1][p2] = nqp;
-      So[q1][q2] = nqq;
-      // Jm <- Jm R: rows k1 and k1 + 16, columns of pair k2 (only this thread touches them)
-      if (s2 != 0.0) {
+      So[p1][p2] = c2 * bpp - s2 * bpq;
+      So[p1][q2] = s2 * bpp + c2 * bpq;
+      So[q1][p2] = c2 * bqp - s2 * bqq;
+      So[q1][q2] = s2 * bqp + c2 * bqq;
+      // Jm <- Jm R: rows k1 and k1 + 16, columns of pair k2 (only this thread
+      // touches them in this round; the identity rotation leaves them as they are)
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-          const int i = k1 + h * JH;
-          const double vp = Jm[i][p2], vq = Jm[i][q2];
-          Jm[i][p2] = c2 * vp - s2 * vq;
-          Jm[i][q2] = s2 * vp + c2 * vq;
-        }
+      for (int h = 0; h < 2; ++h) {
+        Jm[k1 + h * JH][p2] = c2 * jp[h] - s2 * jq[h];
+        Jm[k1 + h * JH][q2] = s2 * jp[h] + c2 * jq[h];
       }
       __syncthreads();
       cur ^= 1;
@@ -639,7 +652,6 @@ __global__ __launch_bounds__(256) void jac_phase1(JacArgs a, int64_t r, int swee
 }
 
 __global__ __launch_bounds__(256) void jac_phase2(JacArgs a, int64_t r) {
-  if (*a.conv) return;
   double* __restrict__ Ag = a.A;
   double* __restrict__ Vg = a.V;
   const double* __restrict__ Jg = a.J;
@@ -655,37 +667,32 @@ __global__ __launch_bounds__(256) void jac_phase2(JacArgs a, int64_t r) {
   if (task < ntile_a) {
     const int k1 = (int)(task / npair), k2 = (int)(task % npair);
     if (k1 == k2) return;  // written by phase 1
+    // the tile, both rotations and the converged flag in one round of loads
+    double v[JS * JS / 256], w[JS * JS / 256], w2[JS * JS / 256];
+#pragma unroll
+    for (int u = 0; u < JS * JS / 256; ++u) {
+      const int e = t + 256 * u;
+      v[u] = Ag[pair_index(nblk, k1, r, e / JS) * m + pair_index(nblk, k2, r, e % JS)];
+      w[u] = Jg[(int64_t)k1 * JS * JS + e];
+      w2[u] = Jg[(int64_t)k2 * JS * JS + e];
+    }
+    if (*a.conv) return;
     if (t < JS) {
       gi[t] = pair_index(nblk, k1, r, t);
       gj[t] = pair_index(nblk, k2, r, t);
     }
-    __syncthreads();
-        {
-      double v[JS * JS / 256], w[JS * JS / 256];
 #pragma unroll
-      for (int u = 0; u < JS * JS / 256; ++u) {
-        const int e = t + 256 * u;
-        v[u] = Ag[gi[e / JS] * m + gj[e % JS]];
-        w[u] = Jg[(int64_t)k1 * JS * JS + e];
-      }
-#pragma unroll
-      for (int u = 0; u < JS * JS / 256; ++u) {
-        const int e = t + 256 * u;
-        S[e / JS][e % JS] = v[u];
-        Jm[e / JS][e % JS] = w[u];
-      }
+    for (int u = 0; u < JS * JS / 256; ++u) {
+      const int e = t + 256 * u;
+      S[e / JS][e % JS] = v[u];
+      Jm[e / JS][e % JS] = w[u];
     }
     __syncthreads();
     acc = mmjs<true>(Jm, S);  // T = J_k1^T S
     __syncthreads();
     mmjs_store(acc, [&](int i, int j, double v) { S[i][j] = v; });
-        {
-      double w[JS * JS / 256];
 #pragma unroll
-      for (int u = 0; u < JS * JS / 256; ++u) w[u] = Jg[(int64_t)k2 * JS * JS + t + 256 * u];
-#pragma unroll
-      for (int u = 0; u < JS * JS / 256; ++u) Jm[(t + 256 * u) / JS][(t + 256 * u) % JS] = w[u];
-    }
+    for (int u = 0; u < JS * JS / 256; ++u) Jm[(t + 256 * u) / JS][(t + 256 * u) % JS] = w2[u];
     __syncthreads();
     acc = mmjs<false>(S, Jm);  // T J_k2
     mmjs_store(acc, [&](int i, int j, double v) { Ag[gi[i] * m + gj[j]] = v; });
@@ -693,16 +700,16 @@ __global__ __launch_bounds__(256) void jac_phase2(JacArgs a, int64_t r) {
     const int64_t vt = task - ntile_a;
     const int64_t rb = vt / npair;
     const int k = (int)(vt % npair);
-    if (t < JS) gj[t] = pair_index(nblk, k, r, t);
-    __syncthreads();
-        {
+    {
       double v[JS * JS / 256], w[JS * JS / 256];
 #pragma unroll
       for (int u = 0; u < JS * JS / 256; ++u) {
         const int e = t + 256 * u;
-        v[u] = Vg[(rb * JS + e / JS) * m + gj[e % JS]];
+        v[u] = Vg[(rb * JS + e / JS) * m + pair_index(nblk, k, r, e % JS)];
         w[u] = Jg[(int64_t)k * JS * JS + e];
       }
+      if (*a.conv) return;
+      if (t < JS) gj[t] = pair_index(nblk, k, r, t);
 #pragma unroll
       for (int u = 0; u < JS * JS / 256; ++u) {
         const int e = t + 256 * u;
@@ -721,11 +728,15 @@ __global__ __launch_bounds__(256) void jac_phase2(JacArgs a, int64_t r) {
 // makes rounding-level rotations, and the off-diagonal it leaves (which sets
 // the orthogonality of U = B W S^{-1/2}) is at that level too, so a further
 // confirming sweep would change nothing that matters.
-__global__ void jac_end_sweep(JacArgs a, int sweep) {
-  if (*a.conv) return;
-  a.sweeps_out[0] = sweep + 1;
-  const unsigned r2 = static_cast<unsigned>(a.flags[sweep]);
-  if (r2 == 0u || r2 < __float_as_uint(1e-28f)) a.conv[0] = 1;
+// host_conv (host memory visible to the device, may be null) receives the
+// flag for the host's sweep loop.
+__global__ void jac_end_sweep(JacArgs a, int sweep, int* host_conv) {
+  if (!*a.conv) {
+    a.sweeps_out[0] = sweep + 1;
+    const unsigned r2 = static_cast<unsigned>(a.flags[sweep]);
+    if (r2 == 0u || r2 < __float_as_uint(1e-28f)) a.conv[0] = 1;
+  }
+  if (host_conv) *(volatile int*)host_conv = a.conv[0];
 }
 
 __global__ void jac_evals(const double* __restrict__ A, int64_t m, double* __restrict__ ev) {
@@ -847,6 +858,19 @@ size_t eig_ws_doubles(int64_t l) {
   return (size_t)(2 * m * m + m + (nb / 2) * JS * JS + 8);
 }
 
+// A few bytes of pinned host memory per host thread, kept for the life of
+// the process (null if it cannot be had).
+int* pinned_flag() {
+  static thread_local int* p = nullptr;
+  static thread_local bool tried = false;
+  if (!tried) {
+    tried = true;
+    void* q = nullptr;
+    if (hipHostMalloc(&q, 64, hipHostMallocDefault) == hipSuccess) p = static_cast<int*>(q);
+  }
+  return p;
+}
+
 nys_status sym_eig(const double* G, int64_t l, double* work, int* flags, int max_sweeps,
                    int* sweeps_out, int* conv, double* T, double* lam, double* sig2, const double* nu,
                    hipStream_t s) {
@@ -867,20 +891,55 @@ nys_status sym_eig(const double* G, int64_t l, double* work, int* flags, int max
   JacArgs a{A, V, J, m, nb, inner_sweeps_for(l), flags, conv, sweeps_out, floor};
   const int npair = nb / 2;
   const int64_t tasks = (int64_t)npair * npair + (m / JS) * npair;
+  // Convergence is read one sweep behind: the flag of sweep s - 1 (written to
+  // pinned host memory by its end-of-sweep kernel) is awaited while sweep s
+  // runs, so the GPU never idles on the poll and at most one sweep of
+  // early-returning launches follows convergence.  Without pinned memory the
+  // flag is copied and the stream synchronised every third sweep.
+  int* hconv = pinned_flag();
+  hipEvent_t evs[2] = {nullptr, nullptr};
+  if (hconv) {
+    *(volatile int*)hconv = 0;
+    for (int e = 0; e < 2; ++e)
+      if (hipEventCreateWithFlags(&evs[e], hipEventDisableTiming) != hipSuccess) evs[e] = nullptr;
+    if (!evs[0] || !evs[1]) hconv = nullptr;
+  }
+  nys_status st = NYS_OK;
   for (int sweep = 0; sweep < max_sweeps; ++sweep) {
     for (int64_t r = 0; r < nb - 1; ++r) {
       hipLaunchKernelGGL(jac_phase1, dim3((unsigned)npair), dim3(256), 0, s, a, r, sweep);
       hipLaunchKernelGGL(jac_phase2, dim3((unsigned)tasks), dim3(256), 0, s, a, r);
     }
-    hipLaunchKernelGGL(jac_end_sweep, dim3(1), dim3(1), 0, s, a, sweep);
-    NYS_CHECK_LAUNCH();
-    if (sweep >= 5 && (sweep % 3 == 2)) {
+    hipLaunchKernelGGL(jac_end_sweep, dim3(1), dim3(1), 0, s, a, sweep, hconv);
+    if (hipGetLastError() != hipSuccess) {
+      set_error("sym_eig: kernel launch failed");
+      st = NYS_ERR_DEVICE;
+      break;
+    }
+    if (hconv) {
+      if (hipEventRecord(evs[sweep & 1], s) != hipSuccess) {
+        set_error("sym_eig: event record failed");
+        st = NYS_ERR_DEVICE;
+        break;
+      }
+      if (sweep >= 6) {
+        if (hipEventSynchronize(evs[(sweep - 1) & 1]) != hipSuccess) {
+          set_error("sym_eig: event wait failed");
+          st = NYS_ERR_DEVICE;
+          break;
+        }
+        if (*(volatile int*)hconv) break;
+      }
+    } else if (sweep >= 5 && (sweep % 3 == 2)) {
       int c = 0;
       NYS_HIP(hipMemcpyAsync(&c, conv, sizeof(int), hipMemcpyDeviceToHost, s));
       NYS_HIP(hipStreamSynchronize(s));
       if (c) break;
     }
   }
+  for (int e = 0; e < 2; ++e)
+    if (evs[e]) (void)hipEventDestroy(evs[e]);
+  if (st != NYS_OK) return st;
   hipLaunchKernelGGL(jac_evals, dim3((unsigned)cdiv(m, 256)), dim3(256), 0, s, A, m, ev);
   hipLaunchKernelGGL(eig_finalize, dim3((unsigned)cdiv(l, 256)), dim3(256), 0, s, ev, V, l, m,
                      nu, T, lam, sig2);

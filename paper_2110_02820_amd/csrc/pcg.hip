@@ -327,7 +327,9 @@ __global__ __launch_bounds__(NT) void cg_finish_mv(int64_t n, const T* __restric
                                                    double* __restrict__ ppv, CgScalars sc, int par, int fuse,
                                                    T* __restrict__ X, T* __restrict__ R,
                                                    double* __restrict__ prr, double tol) {
-  if (*sc.alldone) return;
+  // the flag is read with the first partial loads (one memory latency) and
+  // tested before anything is stored; every block has at least one tile
+  const int skip_all = *sc.alldone;
   __shared__ T shp[8][33];
   __shared__ double sh[NT];
   const int c = threadIdx.x & 31, sl = threadIdx.x >> 5;
@@ -349,6 +351,7 @@ __global__ __launch_bounds__(NT) void cg_finish_mv(int64_t n, const T* __restric
 #pragma unroll
       for (int u = 0; u < 32; ++u) a0 += v[u];
     }
+    if (skip_all) return;
     __syncthreads();
     shp[sl][c] = a0;
     __syncthreads();
@@ -402,7 +405,7 @@ template <typename TU, typename T, int RU>
 __global__ __launch_bounds__(NT) void utr_part(int64_t n, int64_t l, const TU* __restrict__ U, int64_t ldu,
                                                const T* __restrict__ r, double* __restrict__ part,
                                                int64_t rows_per_chunk, const int* __restrict__ alldone) {
-  if (alldone && *alldone) return;
+  const int skip_all = alldone ? *alldone : 0;  // tested once the first loads are issued
   __shared__ double red[4][64];
   const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
   const int64_t j = (int64_t)blockIdx.x * 64 + tx;
@@ -419,9 +422,11 @@ __global__ __launch_bounds__(NT) void utr_part(int64_t n, int64_t l, const TU* _
       uv[u] = double(U[ic * ldu + jc]);
       rv[u] = i < i1 ? double(r[ic]) : 0.0;
     }
+    if (skip_all) return;
 #pragma unroll
     for (int u = 0; u < RU; ++u) acc += uv[u] * rv[u];
   }
+  if (skip_all) return;
   red[ty][tx] = j < l ? acc : 0.0;
   __syncthreads();
   if (ty == 0 && j < l)
@@ -434,7 +439,7 @@ __global__ __launch_bounds__(NT) void utr_part(int64_t n, int64_t l, const TU* _
 __global__ __launch_bounds__(NT) void utr_final(int64_t l, int nch, const double* __restrict__ part,
                                                 const double* __restrict__ lam, const double* __restrict__ mu,
                                                 double* __restrict__ Cs, const int* __restrict__ alldone) {
-  if (alldone && *alldone) return;
+  const int skip_all = alldone ? *alldone : 0;  // tested once the first loads are issued
   __shared__ double red[4][64];
   const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
   const int64_t j = (int64_t)blockIdx.x * 64 + tx;
@@ -447,9 +452,11 @@ __global__ __launch_bounds__(NT) void utr_final(int64_t l, int nch, const double
       const int q = q0 + 4 * u;
       v[u] = q < nch ? part[(int64_t)q * l + jc] : 0.0;
     }
+    if (skip_all) return;
 #pragma unroll
     for (int u = 0; u < 32; ++u) acc += v[u];
   }
+  if (skip_all) return;
   red[ty][tx] = acc;
   __syncthreads();
   if (ty == 0 && j < l) {
@@ -469,7 +476,8 @@ __global__ __launch_bounds__(NT) void uc_rz(int64_t n, int64_t l, const TU* __re
                                             T* __restrict__ z, int64_t rows_per_wave,
                                             double* __restrict__ prz, CgScalars sc, int par, int mode,
                                             T* __restrict__ Pd) {
-  if (mode == 2 && *sc.alldone) return;
+  // the flag is read with the first loads and tested before anything is stored
+  const int skip_all = mode == 2 ? *sc.alldone : 0;
   __shared__ double sh[NT];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   T cs[NJ];
@@ -496,6 +504,7 @@ __global__ __launch_bounds__(NT) void uc_rz(int64_t n, int64_t l, const TU* __re
         u[q][jj] = U[row * ldu + (j < l ? j : l - 1)];
       }
     }
+    if (skip_all) return;
     T sv[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
@@ -513,7 +522,7 @@ __global__ __launch_bounds__(NT) void uc_rz(int64_t n, int64_t l, const TU* __re
       }
     }
   }
-  if (mode == 0) return;
+  if (mode == 0 || skip_all) return;
   // every lane of a wave holds the same rzp; lane 0 contributes it
   const double tot = block_sum(lane == 0 ? rzp : 0.0, sh);
   if (threadIdx.x == 0) prz[blockIdx.x] = tot;

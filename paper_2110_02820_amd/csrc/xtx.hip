@@ -51,7 +51,7 @@ __global__ __launch_bounds__(256) void xtx_fused(const TD* __restrict__ X, int64
                                                  int64_t ld, const TA* __restrict__ p,
                                                  TA* __restrict__ part, int64_t rows_per_wg,
                                                  const int* __restrict__ skip) {
-  if (skip && *skip) return;
+  const int sk = skip ? *skip : 0;  // tested once the first loads are issued
   typedef typename VP::type VT;
   constexpr int E = VP::E;
   __shared__ TA red[2][4][R];
@@ -118,6 +118,7 @@ __global__ __launch_bounds__(256) void xtx_fused(const TD* __restrict__ X, int64
   };
   int64_t rb = r0;
   if (rb + R <= r1) load(cur, rb);
+  if (sk) return;
   // two groups per trip (ping-pong buffers, no register copies); each load is
   // issued one group ahead and the last prefetch of a range re-reads valid rows
   for (; rb + 2 * R <= r1; rb += 2 * R) {
