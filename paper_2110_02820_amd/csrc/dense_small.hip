@@ -432,27 +432,47 @@ __device__ __forceinline__ bool jacobi_rot_bf(double app, double aqq, double apq
 
 // Block two-sided Jacobi.  The m x m matrix (m = nblk * JB, nblk even) is cut
 // into JB x JB blocks; a round pairs the blocks by the round-robin schedule.
-// Phase 1 (one workgroup per block pair (P, Q)): load the JS x JS subproblem
-// [A_PP A_PQ; A_QP A_QQ] into LDS, rotate its index pairs (all of them in the
+// Phase 1 (one workgroup per block pair (P, Q)): form the JS x JS subproblem
+// [A_PP A_PQ; A_QP A_QQ] in LDS, rotate its index pairs (all of them in the
 // first round of a sweep, only the P-Q pairs in later rounds), keep the
-// accumulated rotation J_k and write the rotated subproblem back.  Phase 2
-// (one workgroup per tile): A <- J^T A J on the off-diagonal pair tiles
-// (J_k^T A_kk' J_k') and V <- V J.  Phases are separate launches on the
-// stream (the kernel boundary orders them); nblk - 1 rounds make a sweep.
-// Every kernel returns at once when the converged flag is set, so the host
-// may enqueue whole sweeps and poll the flag only now and then.
+// accumulated rotation J_k and write the rotated subproblem.  Phase 2 (one
+// workgroup per tile): A <- J^T A J on the off-diagonal pair tiles
+// (J_k^T A_kk' J_k') and V <- V J.
+//
+// One launch per round g runs phase 1 of round g and phase 2 of round g - 1
+// side by side.  A^(g) (the matrix entering round g) lives in buffer g mod 3:
+// phase 2 of round g - 1 writes its off-diagonal tiles from A^(g-1), phase 1
+// of round g - 1 wrote its pair tiles the launch before, and phase 1 of
+// round g, which cannot wait for phase 2, forms each block of its subproblem
+// that phase 2 is still producing from A^(g-1) and the two rotations of round
+// g - 1 itself (a 16 x 16 block of J^T T J).  Rotations are double buffered.
+// A round whose index reaches conv_round (set when a sweep converges) does
+// nothing, so the host may enqueue whole sweeps and poll the flag now and then.
 struct JacArgs {
-  double* A;       // m x m
-  double* V;       // m x m eigenvectors (columns)
-  double* J;       // (nblk/2) x JS x JS rotations of the current round
+  double* A[3];     // m x m each: A^(g) in A[g % 3]
+  double* V;        // m x m eigenvectors (columns), updated in place
+  double* J[2];     // (nblk/2) x JS x JS rotations of round g in J[g % 2]
   int64_t m;
   int nblk;
   int inner_sweeps;
-  int* flags;      // [max_sweeps] largest a_pq^2 / |a_pp a_qq| met by the sweep's subproblems, float bits (zeroed)
-  int* conv;       // converged flag (zeroed)
+  int* flags;       // [max_sweeps] largest a_pq^2 / |a_pp a_qq| met by the sweep's subproblems, float bits (zeroed)
+  int* conv;        // converged flag (zeroed)
+  int* conv_round;  // first round not to run (INT_MAX-like until convergence)
   int* sweeps_out;
-  double* floor;   // rotation floor (device scalar)
+  double* floor;    // rotation floor (device scalar)
 };
+
+// Pair k and half h (0: first block, 1: second) of block X in round r.
+__device__ __forceinline__ void locate_block(int X, int r, int nblk, int& k, int& h) {
+  int pos = 0;
+  if (X != 0) {
+    int x = X - 1 - r;
+    if (x < 0) x += nblk - 1;
+    pos = 1 + x;
+  }
+  h = pos < nblk / 2 ? 0 : 1;
+  k = h ? nblk - 1 - pos : pos;
+}
 
 __device__ __forceinline__ int64_t pair_index(int nblk, int k, int64_t r, int t) {
   const int blk = (t < JB) ? rr_index(k, (int)r, nblk) : rr_index(nblk - 1 - k, (int)r, nblk);
@@ -519,39 +539,86 @@ __device__ __forceinline__ int rr_js(int pos, int ir) {
 // It computes the two rotations it needs itself (every thread that needs
 // pair k derives it from the same entries, so they agree), and S is double
 // buffered, so an inner round costs one barrier.
-__global__ __launch_bounds__(256) void jac_phase1(JacArgs a, int64_t r, int sweep) {
-  double* __restrict__ Ag = a.A;
-  double* __restrict__ Jg = a.J;
+__device__ void phase1_task(const JacArgs& a, int64_t g, int k) {
+  const int nb = a.nblk, R = nb - 1;
+  const int r = (int)(g % R), sweep = (int)(g / R);
+  const double* __restrict__ Ain = a.A[g % 3];         // A^(g): pair tiles of round g - 1
+  const double* __restrict__ Aold = a.A[(g + 2) % 3];  // A^(g-1)
+  double* __restrict__ Aout = a.A[(g + 1) % 3];        // A^(g+1): pair tiles of this round
+  const double* __restrict__ Jold = a.J[(g + 1) % 2];  // rotations of round g - 1
+  double* __restrict__ Jg = a.J[g % 2];
   __shared__ double Sb[2][JS][JS + 1];
   __shared__ double Jm[JS][JS + 1];
   __shared__ int64_t gi[JS];
   __shared__ int rotated, any_s;
   __shared__ unsigned maxr;  // float bits of the largest ratio^2 on entry (non-negative: int order)
-  const int t = threadIdx.x;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int64_t m = a.m;
-  const int k = blockIdx.x;
   double floor_abs;
   {
-    // the subproblem loads (in bounds whatever the flags say), the floor and
-    // the converged flag are issued together: one memory latency, not three
+    // wave w forms block (w / 2, w % 2) of the subproblem: read from A^(g)
+    // when its two blocks were one pair of round g - 1 (or g == 0), else as
+    // J_kX^T T J_kY restricted to the two halves, T the tile of A^(g-1) and
+    // J of round g - 1.  Lane l holds entries (4 q + l / 16, l % 16), the
+    // f64 MFMA result layout.  The loads, the floor and the round limit are
+    // issued together (in bounds whatever the limit says).
+    const int P = rr_index(k, r, nb), Q = rr_index(nb - 1 - k, r, nb);
+    const int bx = wave >> 1, by = wave & 1;
+    const int X = bx ? Q : P, Y = by ? Q : P;
     floor_abs = *a.floor;
-    double v[JS * JS / 256];
-#pragma unroll
-    for (int u = 0; u < JS * JS / 256; ++u) {
-      const int e = t + 256 * u;
-      v[u] = Ag[pair_index(a.nblk, k, r, e / JS) * m + pair_index(a.nblk, k, r, e % JS)];
+    const int cr = *a.conv_round;
+    int kX = 0, hX = 0, kY = 0, hY = 0;
+    const int rp = g > 0 ? (int)((g - 1) % R) : 0;
+    bool direct = g == 0;
+    if (!direct) {
+      locate_block(X, rp, nb, kX, hX);
+      locate_block(Y, rp, nb, kY, hY);
+      direct = kX == kY;
     }
-    const int done = *a.conv;
-    if (done) return;
-    if (t < JS) gi[t] = pair_index(a.nblk, k, r, t);
+    double blk[4];
+    if (direct) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        blk[q] = Ain[((int64_t)X * JB + 4 * q + (lane >> 4)) * m + (int64_t)Y * JB + (lane & 15)];
+    } else {
+      double ta[2][JS / 4], jy[JS / 4], jx[JS / 4];
+#pragma unroll
+      for (int ks = 0; ks < JS / 4; ++ks) {
+        const int kk = 4 * ks + (lane >> 4);
+        const int64_t col = pair_index(nb, kY, rp, kk);
+#pragma unroll
+        for (int rt = 0; rt < 2; ++rt) ta[rt][ks] = Aold[pair_index(nb, kX, rp, rt * 16 + (lane & 15)) * m + col];
+        jy[ks] = Jold[(int64_t)kY * JS * JS + kk * JS + hY * JB + (lane & 15)];
+        jx[ks] = Jold[(int64_t)kX * JS * JS + kk * JS + hX * JB + (lane & 15)];
+      }
+      // W = T J_kY[:, half hY] (32 x 16, two row tiles), then J_kX[:, half hX]^T W;
+      // W's result registers are the second product's B operand as they stand
+      jd4 w0 = jd4{0, 0, 0, 0}, w1 = jd4{0, 0, 0, 0};
+#pragma unroll
+      for (int ks = 0; ks < JS / 4; ++ks) {
+        w0 = __builtin_amdgcn_mfma_f64_16x16x4f64(ta[0][ks], jy[ks], w0, 0, 0, 0);
+        w1 = __builtin_amdgcn_mfma_f64_16x16x4f64(ta[1][ks], jy[ks], w1, 0, 0, 0);
+      }
+      jd4 o = jd4{0, 0, 0, 0};
+#pragma unroll
+      for (int ks = 0; ks < JS / 4; ++ks) {
+        const double bw = ks < 4 ? w0[ks & 3] : w1[ks & 3];
+        o = __builtin_amdgcn_mfma_f64_16x16x4f64(jx[ks], bw, o, 0, 0, 0);
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) blk[q] = o[q];
+    }
+    if (g >= cr) return;
+    if (t < JS) gi[t] = pair_index(nb, k, r, t);
     if (t == 0) {
       rotated = 0;
       maxr = 0u;
     }
 #pragma unroll
+    for (int q = 0; q < 4; ++q) Sb[0][bx * JB + 4 * q + (lane >> 4)][by * JB + (lane & 15)] = blk[q];
+#pragma unroll
     for (int u = 0; u < JS * JS / 256; ++u) {
       const int e = t + 256 * u, i = e / JS, j = e % JS;
-      Sb[0][i][j] = v[u];
       Jm[i][j] = (i == j) ? 1.0 : 0.0;
     }
   }
@@ -645,16 +712,19 @@ __global__ __launch_bounds__(256) void jac_phase1(JacArgs a, int64_t r, int swee
   #pragma unroll
   for (int e = t; e < JS * JS; e += 256) {
     Jg[(int64_t)k * JS * JS + e] = Jm[e / JS][e % JS];
-    Ag[gi[e / JS] * m + gi[e % JS]] = Sb[cur][e / JS][e % JS];
+    Aout[gi[e / JS] * m + gi[e % JS]] = Sb[cur][e / JS][e % JS];
   }
   __syncthreads();
   if (t == 0 && rotated) atomicMax(reinterpret_cast<unsigned*>(a.flags) + sweep, maxr > 1u ? maxr : 1u);
 }
 
-__global__ __launch_bounds__(256) void jac_phase2(JacArgs a, int64_t r) {
-  double* __restrict__ Ag = a.A;
+// Phase 2 of round g - 1: A^(g) off-diagonal pair tiles from A^(g-1); V <- V J.
+__device__ void phase2_task(const JacArgs& a, int64_t g, int64_t task) {
+  const int r = (int)((g - 1) % (a.nblk - 1));
+  const double* __restrict__ Ag = a.A[(g + 2) % 3];
+  double* __restrict__ An = a.A[g % 3];
   double* __restrict__ Vg = a.V;
-  const double* __restrict__ Jg = a.J;
+  const double* __restrict__ Jg = a.J[(g + 1) % 2];
   __shared__ double S[JS][JS + 1];
   __shared__ double Jm[JS][JS + 1];
   __shared__ int64_t gi[JS], gj[JS];
@@ -662,7 +732,6 @@ __global__ __launch_bounds__(256) void jac_phase2(JacArgs a, int64_t r) {
   const int64_t m = a.m;
   const int nblk = a.nblk, npair = nblk / 2;
   const int64_t ntile_a = (int64_t)npair * npair;
-  const int64_t task = blockIdx.x;
   jd4 acc;
   if (task < ntile_a) {
     const int k1 = (int)(task / npair), k2 = (int)(task % npair);
@@ -676,7 +745,7 @@ __global__ __launch_bounds__(256) void jac_phase2(JacArgs a, int64_t r) {
       w[u] = Jg[(int64_t)k1 * JS * JS + e];
       w2[u] = Jg[(int64_t)k2 * JS * JS + e];
     }
-    if (*a.conv) return;
+    if (g - 1 >= *a.conv_round) return;
     if (t < JS) {
       gi[t] = pair_index(nblk, k1, r, t);
       gj[t] = pair_index(nblk, k2, r, t);
@@ -695,7 +764,7 @@ __global__ __launch_bounds__(256) void jac_phase2(JacArgs a, int64_t r) {
     for (int u = 0; u < JS * JS / 256; ++u) Jm[(t + 256 * u) / JS][(t + 256 * u) % JS] = w2[u];
     __syncthreads();
     acc = mmjs<false>(S, Jm);  // T J_k2
-    mmjs_store(acc, [&](int i, int j, double v) { Ag[gi[i] * m + gj[j]] = v; });
+    mmjs_store(acc, [&](int i, int j, double v) { An[gi[i] * m + gj[j]] = v; });
   } else {
     const int64_t vt = task - ntile_a;
     const int64_t rb = vt / npair;
@@ -708,7 +777,7 @@ __global__ __launch_bounds__(256) void jac_phase2(JacArgs a, int64_t r) {
         v[u] = Vg[(rb * JS + e / JS) * m + pair_index(nblk, k, r, e % JS)];
         w[u] = Jg[(int64_t)k * JS * JS + e];
       }
-      if (*a.conv) return;
+      if (g - 1 >= *a.conv_round) return;
       if (t < JS) gj[t] = pair_index(nblk, k, r, t);
 #pragma unroll
       for (int u = 0; u < JS * JS / 256; ++u) {
@@ -734,14 +803,36 @@ __global__ void jac_end_sweep(JacArgs a, int sweep, int* host_conv) {
   if (!*a.conv) {
     a.sweeps_out[0] = sweep + 1;
     const unsigned r2 = static_cast<unsigned>(a.flags[sweep]);
-    if (r2 == 0u || r2 < __float_as_uint(1e-28f)) a.conv[0] = 1;
+    if (r2 == 0u || r2 < __float_as_uint(1e-28f)) {
+      a.conv[0] = 1;
+      a.conv_round[0] = (sweep + 1) * (a.nblk - 1);
+    }
   }
   if (host_conv) *(volatile int*)host_conv = a.conv[0];
 }
 
-__global__ void jac_evals(const double* __restrict__ A, int64_t m, double* __restrict__ ev) {
+// Round g: blocks [0, nblk/2) run phase 1 of round g (when with_phase1), the
+// rest phase 2 of round g - 1 (when g > 0).
+__global__ __launch_bounds__(256) void jac_round(JacArgs a, int64_t g, int with_phase1) {
+  int64_t b = blockIdx.x;
+  if (with_phase1) {
+    if (b < a.nblk / 2) {
+      phase1_task(a, g, (int)b);
+      return;
+    }
+    b -= a.nblk / 2;
+  }
+  phase2_task(a, g, b);
+}
+
+// Diagonal of the final matrix A^(ge), ge = rounds run (all launched rounds
+// up to the converged one).
+__global__ void jac_evals(JacArgs a, int64_t glaunched, double* __restrict__ ev) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < m) ev[i] = A[i * m + i];
+  const int64_t cr = *a.conv_round;
+  const int64_t ge = cr < glaunched ? cr : glaunched;
+  const double* A = a.A[ge % 3];
+  if (i < a.m) ev[i] = A[i * a.m + i];
 }
 
 // A = (G + G^T)/2 padded to m x m (padding: isolated eigenvalue -1), V = I.
@@ -855,7 +946,7 @@ int jac_nblk(int64_t l) {
 size_t eig_ws_doubles(int64_t l) {
   const int64_t nb = jac_nblk(l);
   const int64_t m = nb * JB;
-  return (size_t)(2 * m * m + m + (nb / 2) * JS * JS + 8);
+  return (size_t)(4 * m * m + m + 2 * (nb / 2) * JS * JS + 8);
 }
 
 // A few bytes of pinned host memory per host thread, kept for the life of
@@ -876,21 +967,26 @@ nys_status sym_eig(const double* G, int64_t l, double* work, int* flags, int max
                    hipStream_t s) {
   const int nb = jac_nblk(l);
   const int64_t m = (int64_t)nb * JB;
-  double* A = work;
-  double* V = work + m * m;
-  double* ev = work + 2 * m * m;
-  double* J = ev + m;
-  double* floor = J + (int64_t)(nb / 2) * JS * JS;
-  hipLaunchKernelGGL(jacobi_init, dim3((unsigned)cdiv(m * m, 256)), dim3(256), 0, s, G, l, m, A, V);
+  double* A0 = work;
+  double* V = work + 3 * m * m;
+  double* ev = work + 4 * m * m;
+  double* J0 = ev + m;
+  double* J1 = J0 + (int64_t)(nb / 2) * JS * JS;
+  double* floor = J1 + (int64_t)(nb / 2) * JS * JS;
+  int* conv_round = reinterpret_cast<int*>(floor + 1);
+  hipLaunchKernelGGL(jacobi_init, dim3((unsigned)cdiv(m * m, 256)), dim3(256), 0, s, G, l, m, A0, V);
   NYS_CHECK_LAUNCH();
   NYS_HIP(hipMemsetAsync(flags, 0, sizeof(int) * max_sweeps, s));
   NYS_HIP(hipMemsetAsync(conv, 0, sizeof(int), s));
+  NYS_HIP(hipMemsetAsync(conv_round, 0x7f, sizeof(int), s));  // 0x7f7f7f7f: no limit yet
   NYS_HIP(hipMemsetAsync(sweeps_out, 0, sizeof(int), s));
-  hipLaunchKernelGGL(jac_floor, dim3(1), dim3(256), 0, s, A, m, floor);
+  hipLaunchKernelGGL(jac_floor, dim3(1), dim3(256), 0, s, A0, m, floor);
   NYS_CHECK_LAUNCH();
-  JacArgs a{A, V, J, m, nb, inner_sweeps_for(l), flags, conv, sweeps_out, floor};
+  JacArgs a{{A0, A0 + m * m, A0 + 2 * m * m}, V, {J0, J1}, m, nb, inner_sweeps_for(l), flags, conv,
+            conv_round, sweeps_out, floor};
   const int npair = nb / 2;
   const int64_t tasks = (int64_t)npair * npair + (m / JS) * npair;
+  int64_t g = 0;
   // Convergence is read one sweep behind: the flag of sweep s - 1 (written to
   // pinned host memory by its end-of-sweep kernel) is awaited while sweep s
   // runs, so the GPU never idles on the poll and at most one sweep of
@@ -906,10 +1002,8 @@ nys_status sym_eig(const double* G, int64_t l, double* work, int* flags, int max
   }
   nys_status st = NYS_OK;
   for (int sweep = 0; sweep < max_sweeps; ++sweep) {
-    for (int64_t r = 0; r < nb - 1; ++r) {
-      hipLaunchKernelGGL(jac_phase1, dim3((unsigned)npair), dim3(256), 0, s, a, r, sweep);
-      hipLaunchKernelGGL(jac_phase2, dim3((unsigned)tasks), dim3(256), 0, s, a, r);
-    }
+    for (int64_t r = 0; r < nb - 1; ++r, ++g)
+      hipLaunchKernelGGL(jac_round, dim3((unsigned)(npair + (g > 0 ? tasks : 0))), dim3(256), 0, s, a, g, 1);
     hipLaunchKernelGGL(jac_end_sweep, dim3(1), dim3(1), 0, s, a, sweep, hconv);
     if (hipGetLastError() != hipSuccess) {
       set_error("sym_eig: kernel launch failed");
@@ -940,7 +1034,9 @@ nys_status sym_eig(const double* G, int64_t l, double* work, int* flags, int max
   for (int e = 0; e < 2; ++e)
     if (evs[e]) (void)hipEventDestroy(evs[e]);
   if (st != NYS_OK) return st;
-  hipLaunchKernelGGL(jac_evals, dim3((unsigned)cdiv(m, 256)), dim3(256), 0, s, A, m, ev);
+  // phase 2 of the last round that ran (a no-op if a later launch did it)
+  hipLaunchKernelGGL(jac_round, dim3((unsigned)tasks), dim3(256), 0, s, a, g, 0);
+  hipLaunchKernelGGL(jac_evals, dim3((unsigned)cdiv(m, 256)), dim3(256), 0, s, a, g, ev);
   hipLaunchKernelGGL(eig_finalize, dim3((unsigned)cdiv(l, 256)), dim3(256), 0, s, ev, V, l, m,
                      nu, T, lam, sig2);
   NYS_CHECK_LAUNCH();
