@@ -149,7 +149,9 @@ def run_ridge(args, nys, torch):
     op = nys.Operator.xtx(X32)
     prec = nys.NYS_PREC_FP32_REFINE64
     ws = nys.workspace(op, ell, 1, prec)
-    kw = dict(maxit=1000, inner_tol=args.inner_tol or 1e-4)
+    # each float32 inner solve to about sqrt(tol) / 3: two refinement steps
+    # reach tol with margin (float32 PCG gets to ~1e-6 here before rounding)
+    kw = dict(maxit=1000, inner_tol=args.inner_tol or 3e-6)
 
     def timed(opx, precx, wsx, udtype, steps, warmup, label):
         for i in range(warmup):

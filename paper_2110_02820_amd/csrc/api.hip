@@ -578,8 +578,13 @@ nys_status pcg_run(const OpDesc& op0, const PrecDesc& P, int64_t k, const double
   };
   int it = 0;
   int alldone_h = 0;
-  NYS_HIP(hipMemcpyAsync(&alldone_h, b.sc.alldone, sizeof(int), hipMemcpyDeviceToHost, s));
-  NYS_HIP(hipStreamSynchronize(s));
+  // a single column learns whether the set-up already met tol from its first
+  // snapshot; blocks read the flag now (their polls synchronise anyway)
+  const bool snap_path = kc == 1 && pinned_flags() != nullptr;
+  if (!snap_path) {
+    NYS_HIP(hipMemcpyAsync(&alldone_h, b.sc.alldone, sizeof(int), hipMemcpyDeviceToHost, s));
+    NYS_HIP(hipStreamSynchronize(s));
+  }
   // Convergence polls cost a host round trip (~25 us).  check_every > 0 fixes
   // the interval; otherwise it is tuned from the measured iteration time so
   // that polling stays near 2.5% of the run (1 for costly products, up to 32
@@ -588,7 +593,8 @@ nys_status pcg_run(const OpDesc& op0, const PrecDesc& P, int64_t k, const double
   bool tune = check_every <= 0;
   const auto t_start = std::chrono::steady_clock::now();
   int last_poll = 0;
-  while (!alldone_h && it < maxit) {
+  // one iteration on the current kc columns
+  auto step = [&]() -> nys_status {
     const int par = it & 1;
     // single column with a partial-sum operator product: fused iteration
     const bool fused = kc == 1 && (op.kind == NYS_OP_XTX ||
@@ -603,6 +609,104 @@ nys_status pcg_run(const OpDesc& op0, const PrecDesc& P, int64_t k, const double
       NYS_TRY(pcg_iteration<T>(n, kc, P, b.mu, 1, b.V, Xc, kc, b.R, b.Z, b.P, b.w, b.sc, par, tol, s));
     }
     ++it;
+    return NYS_OK;
+  };
+  // A single column needs no compaction, so its polls need not stop the
+  // device: a batch is enqueued before the host waits for the snapshot
+  // (iterations, residual) of the batch before it, which the device writes to
+  // pinned memory.  Batch sizes come from the residual's measured rate of
+  // decrease: the next batch holds the iterations predicted to remain beyond
+  // the batch in flight (at most the poll interval), so few iterations are
+  // enqueued past convergence (those return at once in every kernel).
+  PcgSnap* hsnap = snap_path ? reinterpret_cast<PcgSnap*>(pinned_flags()) : nullptr;
+  struct Events {
+    hipEvent_t e[2] = {nullptr, nullptr};
+    ~Events() {
+      for (auto& x : e)
+        if (x) (void)hipEventDestroy(x);
+    }
+  } pev;
+  if (hsnap) {
+    hsnap = reinterpret_cast<PcgSnap*>(reinterpret_cast<char*>(hsnap) + 64);
+    for (auto& x : pev.e)
+      if (hipEventCreateWithFlags(&x, hipEventDisableTiming) != hipSuccess) x = nullptr;
+    if (!pev.e[0] || !pev.e[1]) {
+      hsnap = nullptr;
+      NYS_HIP(hipMemcpyAsync(&alldone_h, b.sc.alldone, sizeof(int), hipMemcpyDeviceToHost, s));
+      NYS_HIP(hipStreamSynchronize(s));
+    }
+  }
+  bool have_final = false;  // final state of the column known from a snapshot
+  PcgSnap fin{};
+  if (hsnap) {
+    int batch = 0, inflight = -1, inflight_n = 0, next_n = 1;
+    bool have_prev = false;
+    int prev_it = 0;
+    double prev_rn2 = 0.0;
+    while (true) {
+      int slot = -1, n_now = 0;
+      if (next_n > 0 && it < maxit) {
+        n_now = next_n < maxit - it ? next_n : maxit - it;
+        for (int j = 0; j < n_now; ++j) NYS_TRY(step());
+        slot = batch & 1;
+        ++batch;
+        NYS_TRY(pcg_snapshot(b.sc, hsnap + slot, s));
+        NYS_HIP(hipEventRecord(pev.e[slot], s));
+      }
+      const int wait_slot = inflight >= 0 ? inflight : slot;
+      if (wait_slot < 0) break;  // iteration cap reached, nothing in flight
+      NYS_HIP(hipEventSynchronize(pev.e[wait_slot]));
+      PcgSnap sp;
+      {
+        const volatile PcgSnap* v = hsnap + wait_slot;
+        sp.alldone = v->alldone;
+        sp.iters = v->iters;
+        sp.status = v->status;
+        sp.pad = 0;
+        sp.rnorm2 = v->rnorm2;
+        sp.bnorm2 = v->bnorm2;
+      }
+      int ahead = 0;  // iterations enqueued beyond the snapshot
+      if (wait_slot == inflight && slot >= 0) {
+        inflight = slot;
+        inflight_n = n_now;
+        ahead = n_now;
+      } else {
+        inflight = -1;
+        inflight_n = 0;
+      }
+      if (sp.alldone || (it >= maxit && inflight < 0)) {
+        have_final = true;
+        fin = sp;
+        break;
+      }
+      if (tune) {  // the first batch (one iteration) has finished
+        const double per = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+        const double want = 1e-3 / (per > 1e-9 ? per : 1e-9);
+        interval = want < 1.0 ? 1 : want > 32.0 ? 32 : (int)std::ceil(want);
+        tune = false;
+      }
+      next_n = interval;
+      if (have_prev && sp.iters > prev_it && sp.rnorm2 > 0.0 && prev_rn2 > 0.0) {
+        const double rate = (std::log(sp.rnorm2) - std::log(prev_rn2)) / (double)(sp.iters - prev_it);
+        const double goal = std::log(tol * tol * sp.bnorm2);
+        if (rate < 0.0 && std::isfinite(rate) && std::isfinite(goal)) {
+          const double rem = (goal - std::log(sp.rnorm2)) / rate;
+          if (std::isfinite(rem)) {
+            const double left = std::ceil(rem) - ahead;
+            next_n = left < 0.0 ? 0 : left > interval ? interval : (int)left;
+          }
+        }
+      }
+      if (inflight < 0 && next_n == 0) next_n = 1;  // nothing in flight: keep going
+      have_prev = true;
+      prev_it = sp.iters;
+      prev_rn2 = sp.rnorm2;
+      (void)inflight_n;
+    }
+  }
+  while (!hsnap && !alldone_h && it < maxit) {
+    NYS_TRY(step());
     if (it - last_poll >= interval || it == maxit) {
       last_poll = it;
       NYS_HIP(hipMemcpyAsync(&alldone_h, b.sc.alldone, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -654,14 +758,25 @@ nys_status pcg_run(const OpDesc& op0, const PrecDesc& P, int64_t k, const double
       }
     }
   }
-  for (int64_t c = 0; c < kc; ++c) hd[c] = 1;
-  NYS_TRY(harvest(kc, false));
+  if (have_final && !compacted) {  // single column: the last snapshot holds its results
+    res.iters[map[0]] = fin.iters;
+    res.status[map[0]] = fin.status;
+    res.rnorm2[map[0]] = fin.rnorm2;
+    res.bnorm2[map[0]] = fin.bnorm2;
+  } else {
+    for (int64_t c = 0; c < kc; ++c) hd[c] = 1;
+    NYS_TRY(harvest(kc, false));
+  }
   if (compacted) {
     NYS_TRY(upload_indices(b.cmap, map, s));
     hipLaunchKernelGGL(scatter_idx_same<T>, dim3(nblk(n * kc)), dim3(256), 0, s, n, kc, Xc, b.cmap, k, X);
     NYS_CHECK_LAUNCH();
   }
   res.sweeps = it;
+  if (hsnap) {  // iterations enqueued past convergence did not run
+    res.sweeps = 0;
+    for (int64_t c = 0; c < k; ++c) res.sweeps = res.iters[c] > res.sweeps ? res.iters[c] : res.sweeps;
+  }
   return NYS_OK;
 }
 

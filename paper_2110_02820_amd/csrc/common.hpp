@@ -58,6 +58,12 @@ __host__ __device__ inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 
 
 int num_cus();  // compute units of the current device
 
+// 256 bytes of pinned host memory per host thread, kept for the life of the
+// process (null if it cannot be had): state the device writes for host loops
+// that poll without synchronising the stream.  Bytes 0..63: eigensolver
+// sweeps; bytes 64..127: PCG batch snapshots.
+int* pinned_flags();
+
 // --------------------------------------------------------------- device side
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v) {

@@ -793,17 +793,19 @@ __device__ void phase2_task(const JacArgs& a, int64_t g, int64_t task) {
 }
 
 // Converged when a sweep rotated nothing, or when every off-diagonal entry its
-// subproblems met had |a_pq| <= 1e-14 sqrt(|a_pp a_qq|): such a sweep only
-// makes rounding-level rotations, and the off-diagonal it leaves (which sets
-// the orthogonality of U = B W S^{-1/2}) is at that level too, so a further
-// confirming sweep would change nothing that matters.
+// subproblems met had |a_pq| <= 1e-9 sqrt(|a_pp a_qq|).  In the second case
+// the sweep's own rotations leave each entry they annihilate at most at the
+// float32-tangent remainder (1e-7 of its ratio) and mix in products of two
+// such ratios from rotations sharing an index, so the matrix it leaves has
+// ratios of about 1e-16: the level a further, confirming sweep would reach,
+// and the level that sets the orthogonality of U = B W S^{-1/2}.
 // host_conv (host memory visible to the device, may be null) receives the
 // flag for the host's sweep loop.
 __global__ void jac_end_sweep(JacArgs a, int sweep, int* host_conv) {
   if (!*a.conv) {
     a.sweeps_out[0] = sweep + 1;
     const unsigned r2 = static_cast<unsigned>(a.flags[sweep]);
-    if (r2 == 0u || r2 < __float_as_uint(1e-28f)) {
+    if (r2 == 0u || r2 < __float_as_uint(1e-18f)) {
       a.conv[0] = 1;
       a.conv_round[0] = (sweep + 1) * (a.nblk - 1);
     }
@@ -949,15 +951,13 @@ size_t eig_ws_doubles(int64_t l) {
   return (size_t)(4 * m * m + m + 2 * (nb / 2) * JS * JS + 8);
 }
 
-// A few bytes of pinned host memory per host thread, kept for the life of
-// the process (null if it cannot be had).
-int* pinned_flag() {
+int* pinned_flags() {
   static thread_local int* p = nullptr;
   static thread_local bool tried = false;
   if (!tried) {
     tried = true;
     void* q = nullptr;
-    if (hipHostMalloc(&q, 64, hipHostMallocDefault) == hipSuccess) p = static_cast<int*>(q);
+    if (hipHostMalloc(&q, 256, hipHostMallocDefault) == hipSuccess) p = static_cast<int*>(q);
   }
   return p;
 }
@@ -992,7 +992,7 @@ nys_status sym_eig(const double* G, int64_t l, double* work, int* flags, int max
   // runs, so the GPU never idles on the poll and at most one sweep of
   // early-returning launches follows convergence.  Without pinned memory the
   // flag is copied and the stream synchronised every third sweep.
-  int* hconv = pinned_flag();
+  int* hconv = pinned_flags();
   hipEvent_t evs[2] = {nullptr, nullptr};
   if (hconv) {
     *(volatile int*)hconv = 0;

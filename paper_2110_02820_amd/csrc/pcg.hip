@@ -779,7 +779,22 @@ nys_status pcg_iteration(int64_t n, int64_t k, const PrecDesc& P, const double* 
   return NYS_OK;
 }
 
+__global__ void pcg_snapshot_kernel(CgScalars sc, PcgSnap* out) {
+  volatile PcgSnap* o = out;
+  o->alldone = *sc.alldone;
+  o->iters = sc.iters[0];
+  o->status = sc.status[0];
+  o->rnorm2 = sc.rnorm2[0];
+  o->bnorm2 = sc.bnorm2[0];
+}
+
 constexpr int64_t kFuseMaxN = 16384;
+
+nys_status pcg_snapshot(const CgScalars& sc, PcgSnap* out, hipStream_t s) {
+  hipLaunchKernelGGL(pcg_snapshot_kernel, dim3(1), dim3(1), 0, s, sc, out);
+  NYS_CHECK_LAUNCH();
+  return NYS_OK;
+}
 
 template <typename T>
 nys_status pcg_iteration_fused(int64_t n, const PrecDesc& P, const double* mu_dev, double mu, const T* part,

@@ -64,6 +64,17 @@ nys_status pcg_iteration_fused(int64_t n, const PrecDesc& P, const double* mu_de
                                int ng, double scale, T* V, T* X, T* R, T* Z, T* Pd, PcgWork& w,
                                const CgScalars& sc, int par, double tol, hipStream_t s);
 
+// State of column 0 after a batch of iterations, written by the device into
+// host memory (pcg_snapshot) for host loops that poll without synchronising.
+struct PcgSnap {
+  int alldone;
+  int iters;
+  int status;
+  int pad;
+  double rnorm2, bnorm2;
+};
+nys_status pcg_snapshot(const CgScalars& sc, PcgSnap* out, hipStream_t s);
+
 // Pieces of one block iteration for callers that supply their own operator
 // product and preconditioner apply (n x k blocks, ld = k, per-column scalars):
 //   cg_block_init:      R = B - V, ||B||^2, stopping flags (sc.ctr zeroed)
