@@ -304,9 +304,12 @@ def run_krr(args, nys, torch, small=False):
         v = torch.randn(n, dtype=torch.float64, device=dev)
         mv_ms = kernel_avg_ms(torch, lambda: nys.nys_op_apply(op, mu, v), args.matvec_reps)
         ev = n * n / (mv_ms * 1e-3) / 1e9
+        # Gram on f64 MFMA; per entry the vector units spend ~32 float64
+        # operations (exp, distance, compensated sum): 78.6 TFLOP/s / 64
         roof = {"bound": "alu", "achieved": ev, "peak": 78.6e3 / 64, "unit": "G kernel entries/s",
                 "frac": ev / (78.6e3 / 64), "traffic": None,
-                "kernel": "rbf_mv_f64 (float64 Gram + exp per entry, ~64 float64 flops)", "avg_ms": mv_ms}
+                "kernel": "rbf_mv_f64m (f64 MFMA Gram; float64 exp + compensated sum, ~32 float64 ops "
+                          "per entry)", "avg_ms": mv_ms}
     else:
         v = torch.randn(n, dtype=torch.float32, device=dev)
         mv_ms = kernel_avg_ms(torch, lambda: nys.nys_op_apply(op, mu, v, prec=prec), args.matvec_reps)

@@ -13,6 +13,9 @@
  *     dimension counted in elements.  The library never allocates or frees
  *     device memory: each call takes a workspace (ws, ws_bytes) sized by
  *     nys_workspace_size(); a too-small workspace returns NYS_ERR_WORKSPACE.
+ *     Its only allocation is 256 bytes of pinned host memory per calling host
+ *     thread, made once and kept until the process ends, into which the
+ *     device writes the flags that nys_factor and nys_pcg_solve* poll.
  *   - `stream` is the caller's hipStream_t (NULL = default stream).  Work is
  *     enqueued on it in order.  nys_factor and nys_pcg_solve* synchronise that
  *     stream to read convergence and failure flags; the other calls do not.
