@@ -1,6 +1,7 @@
 // C ABI of the Nystrom PCG library: argument checks, workspace layout and the
 // host-side ordering of the device kernels.  Every numerical step runs in the
 // HIP kernels of this directory; the host only enqueues work and reads flags.
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstdarg>
@@ -33,6 +34,40 @@ void set_error(const char* fmt, ...) {
 bool verbose() {
   static const bool v = std::getenv("NYS_VERBOSE") != nullptr;
   return v;
+}
+
+int next_pinned_seq() {
+  static thread_local int seq = 0;
+  seq = seq >= 0x3fffffff ? 1 : seq + 1;
+  return seq;
+}
+
+bool wait_pinned(const volatile int* seq, int expect, hipStream_t s, int alt) {
+  const auto seen = [&]() {
+    const int v = *seq;
+    return v == expect || (alt != 0 && v == alt);
+  };
+  const auto t0 = std::chrono::steady_clock::now();
+  for (unsigned spin = 0;; ++spin) {
+    if (seen()) {
+      std::atomic_thread_fence(std::memory_order_acquire);
+      return true;
+    }
+    if ((spin & 1023u) == 1023u &&
+        std::chrono::steady_clock::now() - t0 > std::chrono::seconds(2))
+      break;
+  }
+  const hipError_t e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    set_error("stream failed while waiting for a device flag: %s", hipGetErrorString(e));
+    return false;
+  }
+  if (seen()) {
+    std::atomic_thread_fence(std::memory_order_acquire);
+    return true;
+  }
+  set_error("device flag not written (expected sequence %d, found %d)", expect, *seq);
+  return false;
 }
 
 int num_cus() {
@@ -618,28 +653,12 @@ nys_status pcg_run(const OpDesc& op0, const PrecDesc& P, int64_t k, const double
   // decrease: the next batch holds the iterations predicted to remain beyond
   // the batch in flight (at most the poll interval), so few iterations are
   // enqueued past convergence (those return at once in every kernel).
-  PcgSnap* hsnap = snap_path ? reinterpret_cast<PcgSnap*>(pinned_flags()) : nullptr;
-  struct Events {
-    hipEvent_t e[2] = {nullptr, nullptr};
-    ~Events() {
-      for (auto& x : e)
-        if (x) (void)hipEventDestroy(x);
-    }
-  } pev;
-  if (hsnap) {
-    hsnap = reinterpret_cast<PcgSnap*>(reinterpret_cast<char*>(hsnap) + 64);
-    for (auto& x : pev.e)
-      if (hipEventCreateWithFlags(&x, hipEventDisableTiming) != hipSuccess) x = nullptr;
-    if (!pev.e[0] || !pev.e[1]) {
-      hsnap = nullptr;
-      NYS_HIP(hipMemcpyAsync(&alldone_h, b.sc.alldone, sizeof(int), hipMemcpyDeviceToHost, s));
-      NYS_HIP(hipStreamSynchronize(s));
-    }
-  }
+  PcgSnap* hsnap = snap_path ? reinterpret_cast<PcgSnap*>(reinterpret_cast<char*>(pinned_flags()) + 64) : nullptr;
   bool have_final = false;  // final state of the column known from a snapshot
   PcgSnap fin{};
   if (hsnap) {
     int batch = 0, inflight = -1, inflight_n = 0, next_n = 1;
+    int seqs[2] = {0, 0};
     bool have_prev = false;
     int prev_it = 0;
     double prev_rn2 = 0.0;
@@ -650,19 +669,19 @@ nys_status pcg_run(const OpDesc& op0, const PrecDesc& P, int64_t k, const double
         for (int j = 0; j < n_now; ++j) NYS_TRY(step());
         slot = batch & 1;
         ++batch;
-        NYS_TRY(pcg_snapshot(b.sc, hsnap + slot, s));
-        NYS_HIP(hipEventRecord(pev.e[slot], s));
+        seqs[slot] = next_pinned_seq();
+        NYS_TRY(pcg_snapshot(b.sc, hsnap + slot, seqs[slot], s));
       }
       const int wait_slot = inflight >= 0 ? inflight : slot;
       if (wait_slot < 0) break;  // iteration cap reached, nothing in flight
-      NYS_HIP(hipEventSynchronize(pev.e[wait_slot]));
+      if (!wait_pinned(&hsnap[wait_slot].seq, seqs[wait_slot], s)) return NYS_ERR_DEVICE;
       PcgSnap sp;
       {
         const volatile PcgSnap* v = hsnap + wait_slot;
         sp.alldone = v->alldone;
         sp.iters = v->iters;
         sp.status = v->status;
-        sp.pad = 0;
+        sp.seq = v->seq;
         sp.rnorm2 = v->rnorm2;
         sp.bnorm2 = v->bnorm2;
       }

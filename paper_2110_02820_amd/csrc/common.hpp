@@ -64,6 +64,16 @@ int num_cus();  // compute units of the current device
 // sweeps; bytes 64..127: PCG batch snapshots.
 int* pinned_flags();
 
+// Next value of a per-thread sequence that tags what the device writes into
+// pinned memory, so a host loop can tell a fresh write from an older one.
+int next_pinned_seq();
+
+// Wait until *seq is expect or alt (alt = 0: expect only), written by a
+// kernel on stream s.  Spins on the host; after ~2 s without the value it
+// synchronises the stream and looks once more.  False (message set) if the
+// value never came or the stream failed.
+bool wait_pinned(const volatile int* seq, int expect, hipStream_t s, int alt = 0);
+
 // --------------------------------------------------------------- device side
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v) {

@@ -800,8 +800,8 @@ __device__ void phase2_task(const JacArgs& a, int64_t g, int64_t task) {
 // ratios of about 1e-16: the level a further, confirming sweep would reach,
 // and the level that sets the orthogonality of U = B W S^{-1/2}.
 // host_conv (host memory visible to the device, may be null) receives the
-// flag for the host's sweep loop.
-__global__ void jac_end_sweep(JacArgs a, int sweep, int* host_conv) {
+// flag for the host's sweep loop in [0] and then the sequence tag in [1].
+__global__ void jac_end_sweep(JacArgs a, int sweep, int* host_conv, int seq) {
   if (!*a.conv) {
     a.sweeps_out[0] = sweep + 1;
     const unsigned r2 = static_cast<unsigned>(a.flags[sweep]);
@@ -810,7 +810,11 @@ __global__ void jac_end_sweep(JacArgs a, int sweep, int* host_conv) {
       a.conv_round[0] = (sweep + 1) * (a.nblk - 1);
     }
   }
-  if (host_conv) *(volatile int*)host_conv = a.conv[0];
+  if (host_conv) {
+    host_conv[0] = a.conv[0];
+    __threadfence_system();
+    ((volatile int*)host_conv)[1] = seq;
+  }
 }
 
 // Round g: blocks [0, nblk/2) run phase 1 of round g (when with_phase1), the
@@ -988,41 +992,33 @@ nys_status sym_eig(const double* G, int64_t l, double* work, int* flags, int max
   const int64_t tasks = (int64_t)npair * npair + (m / JS) * npair;
   int64_t g = 0;
   // Convergence is read one sweep behind: the flag of sweep s - 1 (written to
-  // pinned host memory by its end-of-sweep kernel) is awaited while sweep s
-  // runs, so the GPU never idles on the poll and at most one sweep of
-  // early-returning launches follows convergence.  Without pinned memory the
-  // flag is copied and the stream synchronised every third sweep.
-  int* hconv = pinned_flags();
-  hipEvent_t evs[2] = {nullptr, nullptr};
-  if (hconv) {
-    *(volatile int*)hconv = 0;
-    for (int e = 0; e < 2; ++e)
-      if (hipEventCreateWithFlags(&evs[e], hipEventDisableTiming) != hipSuccess) evs[e] = nullptr;
-    if (!evs[0] || !evs[1]) hconv = nullptr;
-  }
+  // pinned host memory with a sequence tag by its end-of-sweep kernel) is
+  // awaited while sweep s runs, so the GPU never idles on the poll and at
+  // most one sweep of early-returning launches follows convergence.  Without
+  // pinned memory the flag is copied and the stream synchronised every third
+  // sweep.
+  int* hpin = pinned_flags();  // [0] converged flag, [1] sequence tag
+  int seqs[2] = {0, 0};
   nys_status st = NYS_OK;
   for (int sweep = 0; sweep < max_sweeps; ++sweep) {
     for (int64_t r = 0; r < nb - 1; ++r, ++g)
       hipLaunchKernelGGL(jac_round, dim3((unsigned)(npair + (g > 0 ? tasks : 0))), dim3(256), 0, s, a, g, 1);
-    hipLaunchKernelGGL(jac_end_sweep, dim3(1), dim3(1), 0, s, a, sweep, hconv);
+    seqs[sweep & 1] = hpin ? next_pinned_seq() : 0;
+    hipLaunchKernelGGL(jac_end_sweep, dim3(1), dim3(1), 0, s, a, sweep, hpin, seqs[sweep & 1]);
     if (hipGetLastError() != hipSuccess) {
       set_error("sym_eig: kernel launch failed");
       st = NYS_ERR_DEVICE;
       break;
     }
-    if (hconv) {
-      if (hipEventRecord(evs[sweep & 1], s) != hipSuccess) {
-        set_error("sym_eig: event record failed");
-        st = NYS_ERR_DEVICE;
-        break;
-      }
+    if (hpin) {
       if (sweep >= 6) {
-        if (hipEventSynchronize(evs[(sweep - 1) & 1]) != hipSuccess) {
-          set_error("sym_eig: event wait failed");
+        // the tag slot holds the latest sweep's tag; sweep s - 1's or later
+        // means sweep s - 1 has ended (tags increase within the call)
+        if (!wait_pinned(hpin + 1, seqs[(sweep - 1) & 1], s, seqs[sweep & 1])) {
           st = NYS_ERR_DEVICE;
           break;
         }
-        if (*(volatile int*)hconv) break;
+        if (*(volatile int*)hpin) break;
       }
     } else if (sweep >= 5 && (sweep % 3 == 2)) {
       int c = 0;
@@ -1031,8 +1027,6 @@ nys_status sym_eig(const double* G, int64_t l, double* work, int* flags, int max
       if (c) break;
     }
   }
-  for (int e = 0; e < 2; ++e)
-    if (evs[e]) (void)hipEventDestroy(evs[e]);
   if (st != NYS_OK) return st;
   // phase 2 of the last round that ran (a no-op if a later launch did it)
   hipLaunchKernelGGL(jac_round, dim3((unsigned)tasks), dim3(256), 0, s, a, g, 0);

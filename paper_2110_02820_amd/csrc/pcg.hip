@@ -779,19 +779,21 @@ nys_status pcg_iteration(int64_t n, int64_t k, const PrecDesc& P, const double* 
   return NYS_OK;
 }
 
-__global__ void pcg_snapshot_kernel(CgScalars sc, PcgSnap* out) {
+__global__ void pcg_snapshot_kernel(CgScalars sc, PcgSnap* out, int seq) {
   volatile PcgSnap* o = out;
   o->alldone = *sc.alldone;
   o->iters = sc.iters[0];
   o->status = sc.status[0];
   o->rnorm2 = sc.rnorm2[0];
   o->bnorm2 = sc.bnorm2[0];
+  __threadfence_system();
+  o->seq = seq;
 }
 
 constexpr int64_t kFuseMaxN = 16384;
 
-nys_status pcg_snapshot(const CgScalars& sc, PcgSnap* out, hipStream_t s) {
-  hipLaunchKernelGGL(pcg_snapshot_kernel, dim3(1), dim3(1), 0, s, sc, out);
+nys_status pcg_snapshot(const CgScalars& sc, PcgSnap* out, int seq, hipStream_t s) {
+  hipLaunchKernelGGL(pcg_snapshot_kernel, dim3(1), dim3(1), 0, s, sc, out, seq);
   NYS_CHECK_LAUNCH();
   return NYS_OK;
 }

@@ -67,13 +67,13 @@ nys_status pcg_iteration_fused(int64_t n, const PrecDesc& P, const double* mu_de
 // State of column 0 after a batch of iterations, written by the device into
 // host memory (pcg_snapshot) for host loops that poll without synchronising.
 struct PcgSnap {
+  int seq;  // written last: the tag the host waits for
   int alldone;
   int iters;
   int status;
-  int pad;
   double rnorm2, bnorm2;
 };
-nys_status pcg_snapshot(const CgScalars& sc, PcgSnap* out, hipStream_t s);
+nys_status pcg_snapshot(const CgScalars& sc, PcgSnap* out, int seq, hipStream_t s);
 
 // Pieces of one block iteration for callers that supply their own operator
 // product and preconditioner apply (n x k blocks, ld = k, per-column scalars):
