@@ -363,6 +363,7 @@ __global__ void trinv_clear_upper(int64_t n, double* __restrict__ X) {
 constexpr int JB = 16;       // Jacobi block size
 constexpr int JS = 2 * JB;   // order of one block-pair subproblem
 constexpr int JH = JS / 2;   // rotation pairs per inner round
+constexpr int JSS = JS;      // LDS row stride of the subproblem rounds (power of two: shift addressing)
 
 // Position pos of round r of the round-robin schedule over m slots (pos, r < m):
 // slot 0 stays, the others rotate.  32-bit, no division.
@@ -403,7 +404,7 @@ __device__ __forceinline__ bool jacobi_rot(double app, double aqq, double apq, d
 // Only the rotation's exact orthogonality matters for the accuracy of the
 // eigenvectors; its angle only has to annihilate a_pq well enough for the
 // sweeps to converge.  So tau = (a_qq - a_pp) / (2 a_pq) is formed in float64
-// (hardware reciprocal + one Newton step: relative error far below float32's),
+// with the hardware reciprocal (relative error ~2^-24, below float32 rounding),
 // t = sign(tau) / (|tau| + sqrt(1 + tau^2)) in float32 (relative error ~1e-7:
 // the rotated a_pq drops by that factor, and later sweeps remove the rest),
 // and c = 1/sqrt(1 + t^2), s = t c in float64 from that t, which keeps
@@ -413,10 +414,9 @@ __device__ __forceinline__ bool jacobi_rot_bf(double app, double aqq, double apq
                                               double& s) {
   const double thr2 = fmax(4.930380657631324e-32 * fabs(app * aqq), floor_abs * floor_abs);
   const bool did = (apq * apq > thr2) && !(fabs(apq) < 1e-300);
-  const double x = did ? apq : 1.0;
-  double rx = __builtin_amdgcn_rcp(x);
-  rx = fma(rx, fma(-x, rx, 1.0), rx);
-  const double tau = (aqq - app) * 0.5 * rx;
+  // hardware reciprocal alone (relative error ~2^-24, measured): tau is only
+  // needed to float32 accuracy
+  const double tau = (aqq - app) * 0.5 * __builtin_amdgcn_rcp(did ? apq : 1.0);
   const float tf = (float)tau;  // |tau| beyond float range: t rounds to 0 (angle < 1e-38)
   const float at = fabsf(tf);
   const float h = fmaf(at, at, 1.0f);
@@ -532,6 +532,70 @@ __device__ __forceinline__ int rr_js(int pos, int ir) {
   return 1 + (x >= JS - 1 ? x - (JS - 1) : x);
 }
 
+// Inner rounds of one subproblem (see phase1_task): thread (k1, k2) updates the
+// 2 x 2 block (rows of pair k1, columns of pair k2) of S = Sb[cur] into
+// Sb[cur ^ 1] and its J entries, one barrier per round.  CROSS: round ir
+// pairs i with JB + (i + ir) mod JB; else the round-robin over JS indices.
+template <bool CROSS>
+__device__ __forceinline__ void jac_inner(double (*Sb)[JS][JSS], double (*Jm)[JSS], int k1, int k2,
+                                          int nround, double floor_abs, int& cur, bool& any_local,
+                                          float& r2loc) {
+  for (int ir = 0; ir < nround; ++ir) {
+    double(*Si)[JSS] = Sb[cur];
+    double(*So)[JSS] = Sb[cur ^ 1];
+    int p1, q1, p2, q2;
+    if (CROSS) {
+      p1 = k1;
+      q1 = JB + ((k1 + ir) & (JB - 1));
+      p2 = k2;
+      q2 = JB + ((k2 + ir) & (JB - 1));
+    } else {
+      p1 = rr_js(k1, ir);
+      q1 = rr_js(JS - 1 - k1, ir);
+      p2 = rr_js(k2, ir);
+      q2 = rr_js(JS - 1 - k2, ir);
+    }
+    // every LDS read of the round first: the entries of both rotations, the
+    // 2 x 2 block and this thread's J entries
+    const double r1pp = Si[p1][p1], r1qq = Si[q1][q1], r1pq = Si[p1][q1];
+    const double r2pp = Si[p2][p2], r2qq = Si[q2][q2], r2pq = Si[p2][q2];
+    const double app = Si[p1][p2], apq = Si[p1][q2], aqp = Si[q1][p2], aqq = Si[q1][q2];
+    double jp[2], jq[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      jp[h] = Jm[k1 + h * JH][p2];
+      jq[h] = Jm[k1 + h * JH][q2];
+    }
+    // both rotations (pair k2 == k1 on the diagonal blocks gives the same one twice)
+    double c1, s1, c2, s2;
+    const bool d1 = jacobi_rot_bf(r1pp, r1qq, r1pq, floor_abs, c1, s1);
+    const bool d2 = jacobi_rot_bf(r2pp, r2qq, r2pq, floor_abs, c2, s2);
+    any_local |= d1 || d2;
+    if (k2 == 0 && d1) {
+      const float r2 = (float)(r1pq * r1pq) * __builtin_amdgcn_rcpf(fmaxf((float)fabs(r1pp * r1qq), 1e-30f));
+      r2loc = fmaxf(r2loc, fminf(r2, 1e30f));
+    }
+    // S <- R^T S R on the 2 x 2 block (on the diagonal blocks the rotated
+    // a_pq is kept as computed, not set to zero: the float32 tangent leaves a
+    // small remainder that later rounds remove, and S must stay J^T A J)
+    const double bpp = c1 * app - s1 * aqp, bpq = c1 * apq - s1 * aqq;
+    const double bqp = s1 * app + c1 * aqp, bqq = s1 * apq + c1 * aqq;
+    So[p1][p2] = c2 * bpp - s2 * bpq;
+    So[p1][q2] = s2 * bpp + c2 * bpq;
+    So[q1][p2] = c2 * bqp - s2 * bqq;
+    So[q1][q2] = s2 * bqp + c2 * bqq;
+    // Jm <- Jm R: rows k1 and k1 + 16, columns of pair k2 (only this thread
+    // touches them in this round; the identity rotation leaves them as they are)
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      Jm[k1 + h * JH][p2] = c2 * jp[h] - s2 * jq[h];
+      Jm[k1 + h * JH][q2] = s2 * jp[h] + c2 * jq[h];
+    }
+    __syncthreads();
+    cur ^= 1;
+  }
+}
+
 // One block pair per workgroup: solve its JS x JS subproblem (inner cyclic
 // sweeps in LDS) and store the accumulated rotation J and the rotated block.
 // Thread (k1, k2) = (t / 16, t % 16) owns the 2 x 2 block (rows of rotation
@@ -547,8 +611,8 @@ __device__ void phase1_task(const JacArgs& a, int64_t g, int k) {
   double* __restrict__ Aout = a.A[(g + 1) % 3];        // A^(g+1): pair tiles of this round
   const double* __restrict__ Jold = a.J[(g + 1) % 2];  // rotations of round g - 1
   double* __restrict__ Jg = a.J[g % 2];
-  __shared__ double Sb[2][JS][JS + 1];
-  __shared__ double Jm[JS][JS + 1];
+  __shared__ double Sb[2][JS][JSS];
+  __shared__ double Jm[JS][JSS];
   __shared__ int64_t gi[JS];
   __shared__ int rotated, any_s;
   __shared__ unsigned maxr;  // float bits of the largest ratio^2 on entry (non-negative: int order)
@@ -623,23 +687,6 @@ __device__ void phase1_task(const JacArgs& a, int64_t g, int k) {
     }
   }
   __syncthreads();
-  // largest a_pq^2 / |a_pp a_qq| of the subproblem on entry, over the pairs
-  // the rotation test would act on (single precision: only compared with 1e-16)
-  {
-    float r2max = 0.0f;
-    #pragma unroll
-    for (int e = t; e < JS * JS; e += 256) {
-      const int i = e / JS, j = e % JS;
-      if (j <= i) continue;
-      const double apq = Sb[0][i][j], d = fabs(Sb[0][i][i] * Sb[0][j][j]);
-      if (!(apq * apq > fmax(4.930380657631324e-32 * d, floor_abs * floor_abs))) continue;
-      const float r2 = (float)(apq * apq) * __builtin_amdgcn_rcpf(fmaxf((float)d, 1e-30f));
-      r2max = fmaxf(r2max, fminf(r2, 1e30f));
-    }
-    // wave maximum first: one LDS atomic per wave
-    for (int off = 32; off > 0; off >>= 1) r2max = fmaxf(r2max, __shfl_xor(r2max, off));
-    if ((t & 63) == 0 && r2max > 0.0f) atomicMax(&maxr, __float_as_uint(r2max));
-  }
   const int k1 = t >> 4, k2 = t & 15;
   // Inner ordering.  The first round of a sweep runs a full round-robin sweep
   // over the JS indices of each pair, which also covers the pairs inside
@@ -647,68 +694,32 @@ __device__ void phase1_task(const JacArgs& a, int64_t g, int k) {
   // rounds only pair an index of P with one of Q: JB inner rounds, round ir
   // pairing P's i with Q's (i + ir) mod JB, so every pair of indices of the
   // matrix is still rotated once per sweep, with half the inner rounds.
+  // Every pair's ratio a_pq^2 / |a_pp a_qq| is taken when it is rotated (by
+  // the threads with k2 == 0, which own each row rotation once), so the
+  // sweep's maximum covers every pair once.
   const bool cross = r > 0 && a.inner_sweeps == 1;
-  const int nround = cross ? JB : JS - 1;
   int cur = 0;
+  float r2loc = 0.0f;
   for (int isw = 0; isw < a.inner_sweeps; ++isw) {
     if (t == 0) any_s = 0;
     __syncthreads();
-    for (int ir = 0; ir < nround; ++ir) {
-      double(*Si)[JS + 1] = Sb[cur];
-      double(*So)[JS + 1] = Sb[cur ^ 1];
-      int p1, q1, p2, q2;
-      if (cross) {
-        p1 = k1;
-        q1 = JB + ((k1 + ir) & (JB - 1));
-        p2 = k2;
-        q2 = JB + ((k2 + ir) & (JB - 1));
-      } else {
-        p1 = rr_js(k1, ir);
-        q1 = rr_js(JS - 1 - k1, ir);
-        p2 = rr_js(k2, ir);
-        q2 = rr_js(JS - 1 - k2, ir);
-      }
-      // every LDS read of the round first: the entries of both rotations, the
-      // 2 x 2 block (rows pair k1, columns pair k2) and this thread's J entries
-      const double r1pp = Si[p1][p1], r1qq = Si[q1][q1], r1pq = Si[p1][q1];
-      const double r2pp = Si[p2][p2], r2qq = Si[q2][q2], r2pq = Si[p2][q2];
-      const double app = Si[p1][p2], apq = Si[p1][q2], aqp = Si[q1][p2], aqq = Si[q1][q2];
-      double jp[2], jq[2];
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        jp[h] = Jm[k1 + h * JH][p2];
-        jq[h] = Jm[k1 + h * JH][q2];
-      }
-      // both rotations (pair k2 == k1 on the diagonal blocks gives the same one twice)
-      double c1, s1, c2, s2;
-      const bool d1 = jacobi_rot_bf(r1pp, r1qq, r1pq, floor_abs, c1, s1);
-      const bool d2 = jacobi_rot_bf(r2pp, r2qq, r2pq, floor_abs, c2, s2);
-      if (d1 || d2) any_s = 1;
-      // S <- R^T S R on the 2 x 2 block
-      const double bpp = c1 * app - s1 * aqp, bpq = c1 * apq - s1 * aqq;
-      const double bqp = s1 * app + c1 * aqp, bqq = s1 * apq + c1 * aqq;
-      // (on the diagonal blocks the rotated a_pq is kept as computed, not
-      // set to zero: the float32 tangent leaves a small remainder that later
-      // rounds remove, and S must stay equal to J^T A J)
-      So[p1][p2] = c2 * bpp - s2 * bpq;
-      So[p1][q2] = s2 * bpp + c2 * bpq;
-      So[q1][p2] = c2 * bqp - s2 * bqq;
-      So[q1][q2] = s2 * bqp + c2 * bqq;
-      // Jm <- Jm R: rows k1 and k1 + 16, columns of pair k2 (only this thread
-      // touches them in this round; the identity rotation leaves them as they are)
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        Jm[k1 + h * JH][p2] = c2 * jp[h] - s2 * jq[h];
-        Jm[k1 + h * JH][q2] = s2 * jp[h] + c2 * jq[h];
-      }
-      __syncthreads();
-      cur ^= 1;
-    }
+    bool any_local = false;
+    if (cross)
+      jac_inner<true>(Sb, Jm, k1, k2, JB, floor_abs, cur, any_local, r2loc);
+    else
+      jac_inner<false>(Sb, Jm, k1, k2, JS - 1, floor_abs, cur, any_local, r2loc);
+    if (any_local) any_s = 1;
+    __syncthreads();
     if (any_s) rotated = 1;
     __syncthreads();
     if (!any_s) break;
     __syncthreads();
   }
+  {  // wave maximum of the rotated ratios first: one LDS atomic per wave
+    for (int off = 32; off > 0; off >>= 1) r2loc = fmaxf(r2loc, __shfl_xor(r2loc, off));
+    if ((t & 63) == 0 && r2loc > 0.0f) atomicMax(&maxr, __float_as_uint(r2loc));
+  }
+  __syncthreads();
   #pragma unroll
   for (int e = t; e < JS * JS; e += 256) {
     Jg[(int64_t)k * JS * JS + e] = Jm[e / JS][e % JS];
