@@ -363,7 +363,7 @@ __global__ void trinv_clear_upper(int64_t n, double* __restrict__ X) {
 constexpr int JB = 16;       // Jacobi block size
 constexpr int JS = 2 * JB;   // order of one block-pair subproblem
 constexpr int JH = JS / 2;   // rotation pairs per inner round
-constexpr int JSS = JS;      // LDS row stride of the subproblem rounds (power of two: shift addressing)
+constexpr int JSS = JS + 16;  // LDS row stride of the subproblem rounds
 
 // Position pos of round r of the round-robin schedule over m slots (pos, r < m):
 // slot 0 stays, the others rotate.  32-bit, no division.
