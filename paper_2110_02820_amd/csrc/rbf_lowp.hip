@@ -15,6 +15,8 @@
 // 256 with zeros, so operand loads never leave the prepared arrays.
 #include "rbf_lowp.hpp"
 
+#include <type_traits>
+
 namespace nys {
 
 namespace {
@@ -22,11 +24,9 @@ namespace {
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 
+// float -> bf16, round to nearest even (one v_cvt_pk_bf16_f32 on gfx950)
 __device__ __forceinline__ unsigned short bf16_rne(float x) {
-  unsigned u = __float_as_uint(x);
-  if ((u & 0x7f800000u) == 0x7f800000u) return (unsigned short)(u >> 16);  // inf / nan
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return (unsigned short)(u >> 16);
+  return __builtin_bit_cast(unsigned short, (__bf16)x);
 }
 __device__ __forceinline__ float bf16_to_f(unsigned short h) { return __uint_as_float((unsigned)h << 16); }
 
@@ -164,10 +164,9 @@ template <int CF>
 struct KvStage2<0, CF> {
   unsigned short Khi[64][40], Klo[64][40];            // [row][point]
   unsigned short Phi[16 * CF][40], Plo[16 * CF][40];  // [col][point]
-  __device__ __forceinline__ void put_p(int pt, int cc, float v) {
-    const unsigned short hi = bf16_rne(v);
-    Phi[cc][pt] = hi;
-    Plo[cc][pt] = bf16_rne(v - bf16_to_f(hi));
+  // 8 points (part) of column cc, already split (half 0: hi, 1: lo)
+  __device__ __forceinline__ void put_p16(int half, int cc, int part, uint4 v) {
+    *reinterpret_cast<uint4*>(half ? &Plo[cc][8 * part] : &Phi[cc][8 * part]) = v;
   }
   __device__ __forceinline__ void put_k(int r, int pc, float e) {
     const unsigned short hi = bf16_rne(e);
@@ -210,6 +209,33 @@ struct KvStage2<1, CF> {
   }
 };
 
+// P (n x k float, row-major) -> bf16 hi / lo, transposed: Pq[half][c][j] for
+// c < kq, j < npad (zero outside n x k), so a tile's 8-point runs of one
+// column are 16-byte chunks.  32 x 32 tiles through LDS.
+__global__ __launch_bounds__(256) void split_p_bf16(const float* __restrict__ P, int64_t ldp, int64_t n,
+                                                    int64_t k, int64_t kq, int64_t npad,
+                                                    unsigned short* __restrict__ Pq) {
+  __shared__ float tl[32][33];
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  const int64_t j0 = (int64_t)blockIdx.x * 32, c0 = (int64_t)blockIdx.y * 32;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int64_t j = j0 + ty + 8 * u, c = c0 + tx;
+    tl[ty + 8 * u][tx] = (j < n && c < k) ? P[j * ldp + c] : 0.0f;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int64_t c = c0 + ty + 8 * u, j = j0 + tx;
+    if (c < kq && j < npad) {
+      const float v = tl[tx][ty + 8 * u];
+      const unsigned short hi = bf16_rne(v);
+      Pq[c * npad + j] = hi;
+      Pq[(kq + c) * npad + j] = bf16_rne(v - bf16_to_f(hi));
+    }
+  }
+}
+
 // Block of columns: V[I, cb*16CF .. +16CF-1] = oscale * K_IJ P_J over the points
 // of split z, float32.  Block = 4 waves, 64 rows x 16 CF output columns; per
 // point tile of 32: stage 1 forms K (wave w: rows w*16 .. +15) with the Gram
@@ -218,11 +244,14 @@ struct KvStage2<1, CF> {
 // registers while the current tile is multiplied.
 template <int MODE, int CF>
 __global__ __launch_bounds__(256) void rbf_kv_lowp(RbfLowp L, const float* __restrict__ P, int64_t ldp, int64_t k,
+                                                   const uint4* __restrict__ Pq, int64_t ldq,
                                                    float* __restrict__ out, int64_t ldo, int64_t pts_per_split,
                                                    float oscale, const int* __restrict__ skip) {
   if (skip && *skip) return;
   constexpr int NC = 16 * CF;               // output columns of the block
-  constexpr int PE = 32 * NC / 256;         // P tile entries per thread
+  // P tile per thread: MODE 1 float entries; MODE 0 16-byte chunks of the
+  // pre-split bf16 hi / lo columns (8 points per chunk)
+  constexpr int PE = MODE == 0 ? 2 * NC * 4 / 256 : 32 * NC / 256;
   __shared__ __attribute__((aligned(16))) KvStage2<MODE, CF> st;
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int64_t n = L.n;
@@ -241,15 +270,23 @@ __global__ __launch_bounds__(256) void rbf_kv_lowp(RbfLowp L, const float* __res
   int64_t j1 = j0 + pts_per_split;
   if (j1 > n) j1 = n;
   // registers for the next tile: P entries and the two 16-point operands
-  float pr[PE];
+  typedef typename std::conditional<MODE == 0, uint4, float>::type PT;
+  PT pr[PE];
   Operand<MODE> b0, b1;
   float h0 = 0.0f, h1 = 0.0f;
   auto fetch = [&](int64_t jt) {
 #pragma unroll
     for (int u = 0; u < PE; ++u) {
-      const int e = t + 256 * u, pt = e / NC, cc = e % NC;
-      const int64_t j = jt + pt, c = c0 + cc;
-      pr[u] = (j < j1 && c < k) ? P[j * ldp + c] : 0.0f;
+      const int e = t + 256 * u;
+      if constexpr (MODE == 0) {
+        // chunk (half, column, part): Pq holds [half][column][point / 8], ldq chunks per column
+        const int part = e & 3, cc = (e >> 2) % NC, half = (e >> 2) / NC;
+        pr[u] = Pq[((int64_t)half * L.kq + c0 + cc) * ldq + (jt >> 3) + part];
+      } else {
+        const int pt = e / NC, cc = e % NC;
+        const int64_t j = jt + pt, c = c0 + cc;
+        pr[u] = (j < j1 && c < k) ? P[j * ldp + c] : 0.0f;
+      }
     }
     // rows jt .. jt + 31 lie inside the padded operand arrays (jt < n, npad a multiple of 256)
     b0.load(L, jt + (lane & 15), lane);
@@ -263,7 +300,10 @@ __global__ __launch_bounds__(256) void rbf_kv_lowp(RbfLowp L, const float* __res
 #pragma unroll
     for (int u = 0; u < PE; ++u) {
       const int e = t + 256 * u;
-      st.put_p(e / NC, e % NC, pr[u]);
+      if constexpr (MODE == 0)
+        st.put_p16((e >> 2) / NC, (e >> 2) % NC, e & 3, pr[u]);
+      else
+        st.put_p(e / NC, e % NC, pr[u]);
     }
     // stage 1: K rows wave*16 .. +15, points jt .. jt+31 (two 16-point tiles)
     const f4 dg0 = gram_tile(a, b0, cinit, L.ksteps);
@@ -371,10 +411,16 @@ nys_status rbf_lowp_mv(const RbfLowp& L, int mode, const float* p, const double*
   return NYS_OK;
 }
 
+// float elements of the pre-split bf16 P (hi and lo: kq x npad bf16 each)
+size_t kv_split_elems(int64_t n, int64_t k) {
+  const int64_t nc = k > 64 ? 128 : 64;
+  return (size_t)(cdiv(k, nc) * nc) * (size_t)(cdiv(n, 256) * 256);
+}
+
 size_t rbf_lowp_kv_scratch(int64_t n, int64_t k) {
   const int64_t tiles = cdiv(n, 64) * cdiv(k, k > 64 ? (int64_t)128 : (int64_t)64);
   const int64_t nz = cdiv(8 * 256, tiles);
-  return nz > 1 ? (size_t)nz * (size_t)n * (size_t)k : 0;
+  return kv_split_elems(n, k) + (nz > 1 ? (size_t)nz * (size_t)n * (size_t)k : 0);
 }
 
 // V += mu_c P
@@ -395,6 +441,22 @@ nys_status rbf_lowp_kv(const RbfLowp& L, int mode, const float* P, int64_t ldp, 
   // 128 output columns per block when there are more than 64 (half the
   // Gram / exp recomputation and twice the MFMA work per staged tile)
   const int64_t nc = k > 64 ? 128 : 64;
+  // bf16 products read P split once into hi / lo (front of the scratch)
+  const size_t se = kv_split_elems(n, k);
+  if (scratch_elems < se) {
+    set_error("rbf_lowp_kv: scratch of %zu floats < %zu", scratch_elems, se);
+    return NYS_ERR_WORKSPACE;
+  }
+  RbfLowp Lq = L;
+  Lq.kq = cdiv(k, nc) * nc;
+  const uint4* Pq = reinterpret_cast<const uint4*>(scratch);
+  if (mode == 0) {
+    hipLaunchKernelGGL(split_p_bf16, dim3((unsigned)cdiv(L.npad, 32), (unsigned)cdiv(Lq.kq, 32)), dim3(256), 0, s,
+                       P, ldp, n, k, Lq.kq, L.npad, reinterpret_cast<unsigned short*>(scratch));
+    NYS_CHECK_LAUNCH();
+  }
+  scratch += se;
+  scratch_elems -= se;
   const int64_t tiles = cdiv(n, 64) * cdiv(k, nc);
   // about eight blocks per compute unit: the per-tile chain (loads, LDS,
   // barriers, MFMA) is latency-bound with fewer waves per SIMD
@@ -407,7 +469,7 @@ nys_status rbf_lowp_kv(const RbfLowp& L, int mode, const float* P, int64_t ldp, 
   float* dst = nz > 1 ? scratch : V;
   const int64_t ldo = nz > 1 ? k : ldv;
   const float oscale = nz > 1 ? 1.0f : L.scale;
-#define KV(M, CF) hipLaunchKernelGGL((rbf_kv_lowp<M, CF>), grid, dim3(256), 0, s, L, P, ldp, k, dst, ldo, pps, oscale, skip)
+#define KV(M, CF) hipLaunchKernelGGL((rbf_kv_lowp<M, CF>), grid, dim3(256), 0, s, Lq, P, ldp, k, Pq, Lq.npad / 8, dst, ldo, pps, oscale, skip)
   if (mode == 0) {
     if (nc == 128) KV(0, 8); else KV(0, 4);
   } else {

@@ -14,6 +14,7 @@ struct RbfLowp {
   float two_s;          // log2(e) / sigma^2
   float scale;          // operator scale
   int ksteps;           // float32 Gram: 4-coordinate MFMA steps that cover d (<= 8)
+  int64_t kq;           // columns of the pre-split P of a K P call (set per call)
 };
 
 enum { RBF_GRAM_BF16X3 = 0, RBF_GRAM_F32 = 1 };
