@@ -164,9 +164,9 @@ template <int CF>
 struct KvStage2<0, CF> {
   unsigned short Khi[64][40], Klo[64][40];            // [row][point]
   unsigned short Phi[16 * CF][40], Plo[16 * CF][40];  // [col][point]
-  // 8 points (part) of column cc, already split (half 0: hi, 1: lo)
-  __device__ __forceinline__ void put_p16(int half, int cc, int part, uint4 v) {
-    *reinterpret_cast<uint4*>(half ? &Plo[cc][8 * part] : &Phi[cc][8 * part]) = v;
+  // 8 points (part) of column cc, already split (piece 0: hi, 1: lo)
+  __device__ __forceinline__ void put_p16(int piece, int cc, int part, uint4 v) {
+    *reinterpret_cast<uint4*>(piece ? &Plo[cc][8 * part] : &Phi[cc][8 * part]) = v;
   }
   __device__ __forceinline__ void put_k(int r, int pc, float e) {
     const unsigned short hi = bf16_rne(e);
@@ -189,29 +189,64 @@ struct KvStage2<0, CF> {
   }
 };
 
-// F32 second stage: K and P as float in LDS, v_mfma_f32_16x16x4f32
+// F32 second stage: K and P each split exactly into three bf16 pieces
+// (8 + 8 + 8 significant bits = the float32 significand), and K P formed from
+// all nine piece products with v_mfma_f32_16x16x32_bf16 and float32
+// accumulation: every piece product is exact, so the result carries the
+// rounding of a float32 product (the same class as v_mfma_f32_16x16x4f32)
+// at 9 x 16 instead of 8 x 32 MFMA cycles per 16 x 16 x 32 step.
+__device__ __forceinline__ void split3(float v, unsigned short& h0, unsigned short& h1, unsigned short& h2) {
+  h0 = bf16_rne(v);
+  const float r1 = v - bf16_to_f(h0);
+  h1 = bf16_rne(r1);
+  h2 = bf16_rne(r1 - bf16_to_f(h1));
+}
+
 template <int CF>
 struct KvStage2<1, CF> {
-  float Kf[64][33];           // [row][point]
-  float Pf[32][16 * CF + 1];  // [point][col]
-  __device__ __forceinline__ void put_p(int pt, int cc, float v) { Pf[pt][cc] = v; }
-  __device__ __forceinline__ void put_k(int r, int pc, float e) { Kf[r][pc] = e; }
+  unsigned short Kp[3][64][40];       // [piece][row][point]
+  unsigned short Pp[3][16 * CF][40];  // [piece][col][point]
+  __device__ __forceinline__ void put_p16(int piece, int cc, int part, uint4 v) {
+    *reinterpret_cast<uint4*>(&Pp[piece][cc][8 * part]) = v;
+  }
+  __device__ __forceinline__ void put_k(int r, int pc, float e) {
+    unsigned short h0, h1, h2;
+    split3(e, h0, h1, h2);
+    Kp[0][r][pc] = h0;
+    Kp[1][r][pc] = h1;
+    Kp[2][r][pc] = h2;
+  }
   __device__ __forceinline__ void mac(int wave, int lane, f4 (&acc)[CF]) {
     const int r = wave * 16 + (lane & 15);
+    bf8 kk[3];
 #pragma unroll
-    for (int ks = 0; ks < 8; ++ks) {
-      const float av = Kf[r][4 * ks + (lane >> 4)];
+    for (int q = 0; q < 3; ++q) kk[q] = *reinterpret_cast<const bf8*>(&Kp[q][r][8 * (lane >> 4)]);
 #pragma unroll
-      for (int cf = 0; cf < CF; ++cf)
-        acc[cf] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, Pf[4 * ks + (lane >> 4)][cf * 16 + (lane & 15)], acc[cf],
-                                                       0, 0, 0);
+    for (int cf = 0; cf < CF; ++cf) {
+      const int cc = cf * 16 + (lane & 15);
+      bf8 pp[3];
+#pragma unroll
+      for (int q = 0; q < 3; ++q) pp[q] = *reinterpret_cast<const bf8*>(&Pp[q][cc][8 * (lane >> 4)]);
+      // smallest products first
+      f4 c = acc[cf];
+      c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(kk[2], pp[2], c, 0, 0, 0);
+      c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(kk[1], pp[2], c, 0, 0, 0);
+      c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(kk[2], pp[1], c, 0, 0, 0);
+      c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(kk[0], pp[2], c, 0, 0, 0);
+      c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(kk[1], pp[1], c, 0, 0, 0);
+      c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(kk[2], pp[0], c, 0, 0, 0);
+      c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(kk[0], pp[1], c, 0, 0, 0);
+      c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(kk[1], pp[0], c, 0, 0, 0);
+      acc[cf] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(kk[0], pp[0], c, 0, 0, 0);
     }
   }
 };
 
-// P (n x k float, row-major) -> bf16 hi / lo, transposed: Pq[half][c][j] for
-// c < kq, j < npad (zero outside n x k), so a tile's 8-point runs of one
-// column are 16-byte chunks.  32 x 32 tiles through LDS.
+// P (n x k float, row-major) -> NP bf16 pieces (2: hi, lo; 3: the exact
+// three-piece split), transposed: Pq[piece][c][j] for c < kq, j < npad (zero
+// outside n x k), so a tile's 8-point runs of one column are 16-byte chunks.
+// 32 x 32 tiles through LDS.
+template <int NP>
 __global__ __launch_bounds__(256) void split_p_bf16(const float* __restrict__ P, int64_t ldp, int64_t n,
                                                     int64_t k, int64_t kq, int64_t npad,
                                                     unsigned short* __restrict__ Pq) {
@@ -229,9 +264,17 @@ __global__ __launch_bounds__(256) void split_p_bf16(const float* __restrict__ P,
     const int64_t c = c0 + ty + 8 * u, j = j0 + tx;
     if (c < kq && j < npad) {
       const float v = tl[tx][ty + 8 * u];
-      const unsigned short hi = bf16_rne(v);
-      Pq[c * npad + j] = hi;
-      Pq[(kq + c) * npad + j] = bf16_rne(v - bf16_to_f(hi));
+      if (NP == 2) {
+        const unsigned short hi = bf16_rne(v);
+        Pq[c * npad + j] = hi;
+        Pq[(kq + c) * npad + j] = bf16_rne(v - bf16_to_f(hi));
+      } else {
+        unsigned short h0, h1, h2;
+        split3(v, h0, h1, h2);
+        Pq[c * npad + j] = h0;
+        Pq[(kq + c) * npad + j] = h1;
+        Pq[(2 * kq + c) * npad + j] = h2;
+      }
     }
   }
 }
@@ -249,9 +292,10 @@ __global__ __launch_bounds__(256) void rbf_kv_lowp(RbfLowp L, const float* __res
                                                    float oscale, const int* __restrict__ skip) {
   if (skip && *skip) return;
   constexpr int NC = 16 * CF;               // output columns of the block
-  // P tile per thread: MODE 1 float entries; MODE 0 16-byte chunks of the
-  // pre-split bf16 hi / lo columns (8 points per chunk)
-  constexpr int PE = MODE == 0 ? 2 * NC * 4 / 256 : 32 * NC / 256;
+  // P tile per thread: 16-byte chunks (8 points of one column) of the
+  // pre-split bf16 pieces, NPC pieces (MODE 0: hi / lo; MODE 1: three)
+  constexpr int NPC = MODE == 0 ? 2 : 3;
+  constexpr int PE = NPC * NC * 4 / 256;
   __shared__ __attribute__((aligned(16))) KvStage2<MODE, CF> st;
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int64_t n = L.n;
@@ -270,23 +314,16 @@ __global__ __launch_bounds__(256) void rbf_kv_lowp(RbfLowp L, const float* __res
   int64_t j1 = j0 + pts_per_split;
   if (j1 > n) j1 = n;
   // registers for the next tile: P entries and the two 16-point operands
-  typedef typename std::conditional<MODE == 0, uint4, float>::type PT;
-  PT pr[PE];
+  uint4 pr[PE];
   Operand<MODE> b0, b1;
   float h0 = 0.0f, h1 = 0.0f;
   auto fetch = [&](int64_t jt) {
 #pragma unroll
     for (int u = 0; u < PE; ++u) {
       const int e = t + 256 * u;
-      if constexpr (MODE == 0) {
-        // chunk (half, column, part): Pq holds [half][column][point / 8], ldq chunks per column
-        const int part = e & 3, cc = (e >> 2) % NC, half = (e >> 2) / NC;
-        pr[u] = Pq[((int64_t)half * L.kq + c0 + cc) * ldq + (jt >> 3) + part];
-      } else {
-        const int pt = e / NC, cc = e % NC;
-        const int64_t j = jt + pt, c = c0 + cc;
-        pr[u] = (j < j1 && c < k) ? P[j * ldp + c] : 0.0f;
-      }
+      // chunk (piece, column, part): Pq holds [piece][column][point / 8], ldq chunks per column
+      const int part = e & 3, cc = (e >> 2) % NC, piece = (e >> 2) / NC;
+      pr[u] = Pq[((int64_t)piece * L.kq + c0 + cc) * ldq + (jt >> 3) + part];
     }
     // rows jt .. jt + 31 lie inside the padded operand arrays (jt < n, npad a multiple of 256)
     b0.load(L, jt + (lane & 15), lane);
@@ -300,10 +337,7 @@ __global__ __launch_bounds__(256) void rbf_kv_lowp(RbfLowp L, const float* __res
 #pragma unroll
     for (int u = 0; u < PE; ++u) {
       const int e = t + 256 * u;
-      if constexpr (MODE == 0)
-        st.put_p16((e >> 2) / NC, (e >> 2) % NC, e & 3, pr[u]);
-      else
-        st.put_p(e / NC, e % NC, pr[u]);
+      st.put_p16((e >> 2) / NC, (e >> 2) % NC, e & 3, pr[u]);
     }
     // stage 1: K rows wave*16 .. +15, points jt .. jt+31 (two 16-point tiles)
     const f4 dg0 = gram_tile(a, b0, cinit, L.ksteps);
@@ -411,10 +445,10 @@ nys_status rbf_lowp_mv(const RbfLowp& L, int mode, const float* p, const double*
   return NYS_OK;
 }
 
-// float elements of the pre-split bf16 P (hi and lo: kq x npad bf16 each)
+// float elements of the pre-split bf16 P (up to three pieces of kq x npad bf16)
 size_t kv_split_elems(int64_t n, int64_t k) {
   const int64_t nc = k > 64 ? 128 : 64;
-  return (size_t)(cdiv(k, nc) * nc) * (size_t)(cdiv(n, 256) * 256);
+  return 3 * (size_t)(cdiv(k, nc) * nc) * (size_t)(cdiv(n, 256) * 256) / 2;
 }
 
 size_t rbf_lowp_kv_scratch(int64_t n, int64_t k) {
@@ -441,7 +475,7 @@ nys_status rbf_lowp_kv(const RbfLowp& L, int mode, const float* P, int64_t ldp, 
   // 128 output columns per block when there are more than 64 (half the
   // Gram / exp recomputation and twice the MFMA work per staged tile)
   const int64_t nc = k > 64 ? 128 : 64;
-  // bf16 products read P split once into hi / lo (front of the scratch)
+  // the bf16 products read P split once into pieces (front of the scratch)
   const size_t se = kv_split_elems(n, k);
   if (scratch_elems < se) {
     set_error("rbf_lowp_kv: scratch of %zu floats < %zu", scratch_elems, se);
@@ -450,9 +484,13 @@ nys_status rbf_lowp_kv(const RbfLowp& L, int mode, const float* P, int64_t ldp, 
   RbfLowp Lq = L;
   Lq.kq = cdiv(k, nc) * nc;
   const uint4* Pq = reinterpret_cast<const uint4*>(scratch);
-  if (mode == 0) {
-    hipLaunchKernelGGL(split_p_bf16, dim3((unsigned)cdiv(L.npad, 32), (unsigned)cdiv(Lq.kq, 32)), dim3(256), 0, s,
-                       P, ldp, n, k, Lq.kq, L.npad, reinterpret_cast<unsigned short*>(scratch));
+  {
+    const dim3 sg((unsigned)cdiv(L.npad, 32), (unsigned)cdiv(Lq.kq, 32));
+    unsigned short* q = reinterpret_cast<unsigned short*>(scratch);
+    if (mode == 0)
+      hipLaunchKernelGGL(split_p_bf16<2>, sg, dim3(256), 0, s, P, ldp, n, k, Lq.kq, L.npad, q);
+    else
+      hipLaunchKernelGGL(split_p_bf16<3>, sg, dim3(256), 0, s, P, ldp, n, k, Lq.kq, L.npad, q);
     NYS_CHECK_LAUNCH();
   }
   scratch += se;
