@@ -76,6 +76,8 @@ def parse():
     ap.add_argument("--n", type=int, default=0, help="override the system size (reduced runs)")
     ap.add_argument("--inner-tol", type=float, default=0.0,
                     help="relative tolerance of each float32 inner solve (0: the workload's default)")
+    ap.add_argument("--prec", default="", choices=["", "fp32_refine64", "bf16x3_refine64"],
+                    help="ridge: precision mode of the chosen form (empty: the workload's default)")
     ap.add_argument("--kernel-only", action="store_true",
                     help="ridge: only the X^T X product (and a 256 MiB device copy as the counter "
                          "calibration), for hardware-counter runs")
@@ -147,7 +149,10 @@ def run_ridge(args, nys, torch):
     X32 = torch.as_tensor(X32h, device=dev)
     b = torch.as_tensor(b_h, device=dev)
     op = nys.Operator.xtx(X32)
-    prec = nys.NYS_PREC_FP32_REFINE64
+    # default: sketch products on bf16 MFMA (hi/lo split; the preconditioner
+    # needs no more), float32 inner PCG, float64 refinement and factorisation
+    bf = args.prec != "fp32_refine64"
+    prec = nys.NYS_PREC_BF16X3_REFINE64 if bf else nys.NYS_PREC_FP32_REFINE64
     ws = nys.workspace(op, ell, 1, prec)
     # each float32 inner solve to about sqrt(tol) / 3: two refinement steps
     # reach tol with margin (float32 PCG gets to ~1e-6 here before rounding)
@@ -176,10 +181,11 @@ def run_ridge(args, nys, torch):
     alg_bytes = m * n * 4 + 2 * n * 4  # X once + p in + v out
     achieved = alg_bytes / (mv_ms * 1e-3) / 1e9
     out = base_record(
-        args, args.steps / el, 1e3 * el / args.steps, "f32+f64",
+        args, args.steps / el, 1e3 * el / args.steps, "bf16x3+f32+f64" if bf else "f32+f64",
         {"workload": "ridge regression A = X^T X, X %dx%d float32 = G diag(j^-1/2), mu=1e-4, l=%d, b = X^T y, "
                      "tol 1e-10 (true float64 residual)" % (m, n, ell),
-         "precision": "float32 inner PCG + float64 residual refinement; float64 core factorisation",
+         "precision": ("sketch products on bf16 MFMA (hi/lo split), " if bf else "float32 sketch products, ") +
+                      "float32 inner PCG + float64 residual refinement; float64 core factorisation",
          "step": "Gaussian Omega + sketch + factor + PCG solve"},
         {"correct": all(i.relres[0] <= tol and i.status[0] == 0 for i in infos),
          "relres": max(i.relres[0] for i in infos), "iters": infos[-1].iters[0],

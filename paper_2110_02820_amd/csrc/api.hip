@@ -1095,15 +1095,22 @@ nys_status nys_sketch(const nys_operator* A, int64_t ell, uint64_t seed, const d
                        l, Y, l);
     NYS_CHECK_LAUNCH();
   } else if (sketch_f32(op, prec)) {
-    // Y = X^T (X Omega) in float32 MFMA arithmetic
+    // Y = X^T (X Omega): float32 MFMA, or bf16 MFMA on the hi/lo split (bf16x3 mode)
     hipLaunchKernelGGL((gather_cols<double, float>), dim3(nblk(n * l)), dim3(256), 0, s, n, l, Omega, l,
                        l, w.Om32, l);
     NYS_CHECK_LAUNCH();
     const float* X = static_cast<const float*>(op.data);
-    NYS_TRY((gemm<float, float, float>(false, false, op.rows, l, n, 1.0f, X, op.ld, w.Om32, l, 0.0f,
-                                       w.T32, l, w.f32scr, w.f32scr_elems, s)));
-    NYS_TRY((gemm<float, float, float>(true, false, n, l, op.rows, (float)op.scale, X, op.ld, w.T32, l,
-                                       0.0f, w.Y32, l, w.f32scr, w.f32scr_elems, s)));
+    if (prec == NYS_PREC_BF16X3_REFINE64) {  // products on bf16 MFMA (hi/lo split)
+      NYS_TRY(gemm_bf16x3(false, false, op.rows, l, n, 1.0f, X, op.ld, w.Om32, l, 0.0f, w.T32, l, w.f32scr,
+                          w.f32scr_elems, s));
+      NYS_TRY(gemm_bf16x3(true, false, n, l, op.rows, (float)op.scale, X, op.ld, w.T32, l, 0.0f, w.Y32, l,
+                          w.f32scr, w.f32scr_elems, s));
+    } else {
+      NYS_TRY((gemm<float, float, float>(false, false, op.rows, l, n, 1.0f, X, op.ld, w.Om32, l, 0.0f,
+                                         w.T32, l, w.f32scr, w.f32scr_elems, s)));
+      NYS_TRY((gemm<float, float, float>(true, false, n, l, op.rows, (float)op.scale, X, op.ld, w.T32, l,
+                                         0.0f, w.Y32, l, w.f32scr, w.f32scr_elems, s)));
+    }
     hipLaunchKernelGGL((gather_cols<float, double>), dim3(nblk(n * l)), dim3(256), 0, s, n, l, w.Y32, l,
                        l, Y, l);
     NYS_CHECK_LAUNCH();

@@ -278,6 +278,144 @@ __global__ __launch_bounds__(NT) void gemm_large(int64_t M, int64_t N, int64_t K
       }
 }
 
+// float32 operands, products on bf16 MFMA with the three-product split:
+// a = a_hi + a_lo, b = b_hi + b_lo (bf16, round to nearest even) and
+// a b ~ a_hi b_hi + a_hi b_lo + a_lo b_hi, float32 accumulation (relative
+// error ~2^-16 per product).  128 x 128 tiles, 4 waves of 64 x 64, 32-deep
+// slabs (one v_mfma_f32_16x16x32_bf16 step), split in registers on the way
+// into LDS as [row][k] (A) and [column][k] (B) so that each lane reads its
+// 8 consecutive k with one 16-byte load; the next slab is loaded while the
+// current one is multiplied.  Tile numbering and split-K as in gemm_large.
+typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
+typedef __bf16 bf4v __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ void split_bf16x4(const float (&v)[4], bf4v& hi, bf4v& lo) {
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const __bf16 h = (__bf16)v[u];
+    hi[u] = h;
+    lo[u] = (__bf16)(v[u] - (float)h);
+  }
+}
+
+constexpr int XK = 32, XPAD = 40;
+
+template <bool TA, bool TB>
+__global__ __launch_bounds__(NT) void gemm_bf16x3(int64_t M, int64_t N, int64_t K, int64_t kchunk, float alpha,
+                                                  const float* __restrict__ A, int64_t lda,
+                                                  const float* __restrict__ B, int64_t ldb, float beta,
+                                                  float* __restrict__ C, int64_t ldc, float* __restrict__ part,
+                                                  const int* __restrict__ skip) {
+  if (skip && *skip) return;
+  __shared__ __attribute__((aligned(16))) __bf16 Ah[LM][XPAD], Al[LM][XPAD], Bh[LN][XPAD], Bl[LN][XPAD];
+  const int64_t mt = (M + LM - 1) / LM, nt = (N + LN - 1) / LN, tiles = mt * nt;
+  const int64_t per = (int64_t)gridDim.x / 8;
+  const int64_t tile = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
+  if (tile >= tiles) return;
+  const int64_t m0 = (tile / nt) * LM, n0 = (tile % nt) * LN;
+  const int t = threadIdx.x;
+  const int lane = t & 63, wave = t >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int64_t kb = (int64_t)blockIdx.y * kchunk;
+  const int64_t ke = (kb + kchunk < K) ? kb + kchunk : K;
+  // each thread stages 4 runs of 4 consecutive k for A and for B (128 x 32 each)
+  float ra[4][4], rb[4][4];
+  auto load = [&](int64_t k0) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int e = t + NT * r;
+      // A run: row (e % 128) when A is transposed, else row e / 8; k offset 4 * (e / 128) or 4 * (e % 8)
+      const int row = TA ? (e & (LM - 1)) : (e >> 3);
+      const int kq = TA ? (e >> 7) : (e & 7);
+      const int64_t gm = m0 + row, gk = k0 + 4 * kq;
+      if (!TA && gm < M && gk + 3 < ke) {
+        const float4 v = *reinterpret_cast<const float4*>(A + gm * lda + gk);
+        ra[r][0] = v.x; ra[r][1] = v.y; ra[r][2] = v.z; ra[r][3] = v.w;
+      } else {
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          ra[r][u] = (gm < M && gk + u < ke) ? (TA ? A[(gk + u) * lda + gm] : A[gm * lda + gk + u]) : 0.0f;
+      }
+      const int col = TB ? (e >> 3) : (e & (LN - 1));
+      const int kqb = TB ? (e & 7) : (e >> 7);
+      const int64_t gn = n0 + col, gkb = k0 + 4 * kqb;
+      if (TB && gn < N && gkb + 3 < ke) {
+        const float4 v = *reinterpret_cast<const float4*>(B + gn * ldb + gkb);
+        rb[r][0] = v.x; rb[r][1] = v.y; rb[r][2] = v.z; rb[r][3] = v.w;
+      } else {
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          rb[r][u] = (gn < N && gkb + u < ke) ? (TB ? B[gn * ldb + gkb + u] : B[(gkb + u) * ldb + gn]) : 0.0f;
+      }
+    }
+  };
+  auto store = [&]() {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int e = t + NT * r;
+      const int row = TA ? (e & (LM - 1)) : (e >> 3);
+      const int kq = TA ? (e >> 7) : (e & 7);
+      bf4v h, l;
+      split_bf16x4(ra[r], h, l);
+      *reinterpret_cast<bf4v*>(&Ah[row][4 * kq]) = h;
+      *reinterpret_cast<bf4v*>(&Al[row][4 * kq]) = l;
+      const int col = TB ? (e >> 3) : (e & (LN - 1));
+      const int kqb = TB ? (e & 7) : (e >> 7);
+      split_bf16x4(rb[r], h, l);
+      *reinterpret_cast<bf4v*>(&Bh[col][4 * kqb]) = h;
+      *reinterpret_cast<bf4v*>(&Bl[col][4 * kqb]) = l;
+    }
+  };
+  f4 acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = f4{0, 0, 0, 0};
+  if (kb < ke) load(kb);
+  for (int64_t k0 = kb; k0 < ke; k0 += XK) {
+    __syncthreads();
+    store();
+    __syncthreads();
+    if (k0 + XK < ke) load(k0 + XK);
+    const int ks = 8 * (lane >> 4);
+    bf8v ah[4], al[4], bh[4], bl[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      ah[i] = *reinterpret_cast<const bf8v*>(&Ah[wm * 64 + i * 16 + (lane & 15)][ks]);
+      al[i] = *reinterpret_cast<const bf8v*>(&Al[wm * 64 + i * 16 + (lane & 15)][ks]);
+      bh[i] = *reinterpret_cast<const bf8v*>(&Bh[wn * 64 + i * 16 + (lane & 15)][ks]);
+      bl[i] = *reinterpret_cast<const bf8v*>(&Bl[wn * 64 + i * 16 + (lane & 15)][ks]);
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        f4 c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], c, 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], c, 0, 0, 0);
+      }
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int64_t gm = m0 + wm * 64 + i * 16 + 4 * (lane >> 4) + q;
+        const int64_t gn = n0 + wn * 64 + j * 16 + (lane & 15);
+        if (gm < M && gn < N) {
+          const float v = acc[i][j][q];
+          if (part) {
+            part[((int64_t)blockIdx.y * M + gm) * N + gn] = v;
+          } else {
+            float o = alpha * v;
+            if (beta != 0.0f) o += beta * C[gm * ldc + gn];
+            C[gm * ldc + gn] = o;
+          }
+        }
+      }
+}
+
 template <typename TC>
 __global__ void splitk_reduce(int64_t M, int64_t N, int nz, TC alpha, const TC* __restrict__ part,
                               TC beta, TC* __restrict__ C, int64_t ldc, const int* __restrict__ skip) {
@@ -388,5 +526,44 @@ template nys_status gemm<float, float, float>(bool, bool, int64_t, int64_t, int6
 template nys_status gemm<float, float, double>(bool, bool, int64_t, int64_t, int64_t, float,
                                                const float*, int64_t, const double*, int64_t, float,
                                                float*, int64_t, float*, size_t, hipStream_t, const int*);
+
+nys_status gemm_bf16x3(bool ta, bool tb, int64_t M, int64_t N, int64_t K, float alpha, const float* A, int64_t lda,
+                       const float* B, int64_t ldb, float beta, float* C, int64_t ldc, float* scratch,
+                       size_t scratch_elems, hipStream_t s) {
+  if (M <= 0 || N <= 0) return NYS_OK;
+  // float4 loads along k need 16-byte aligned rows
+  const bool vec_a = ta || ((lda % 4 == 0) && ((uintptr_t)A % 16 == 0));
+  const bool vec_b = !tb || ((ldb % 4 == 0) && ((uintptr_t)B % 16 == 0));
+  if (!vec_a || !vec_b || K % 4 != 0)
+    return gemm<float, float, float>(ta, tb, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, scratch, scratch_elems, s);
+  const int64_t lt = cdiv(M, LM) * cdiv(N, LN);
+  const int64_t target = 2 * (int64_t)(num_cus() < 256 ? num_cus() : 256);
+  int64_t nz = 1;
+  if (lt < target) {
+    nz = cdiv(target, lt);
+    nz = nz < cdiv(K, 8 * XK) ? nz : cdiv(K, 8 * XK);
+    while (nz > 1 && (size_t)(nz * M * N) > scratch_elems) --nz;
+    if (nz > 64) nz = 64;
+  }
+  const int64_t kchunk = cdiv(cdiv(K, nz), XK) * XK;
+  nz = cdiv(K, kchunk);
+  dim3 grid((unsigned)(8 * cdiv(lt, 8)), (unsigned)nz);
+  float* part = nz > 1 ? scratch : nullptr;
+#define NYS_GEMM_B3(TA_, TB_)                                                                             \
+  hipLaunchKernelGGL((gemm_bf16x3<TA_, TB_>), grid, dim3(NT), 0, s, M, N, K, kchunk, alpha, A, lda, B, ldb, beta, \
+                     C, ldc, part, (const int*)nullptr)
+  if (!ta && !tb) NYS_GEMM_B3(false, false);
+  else if (!ta && tb) NYS_GEMM_B3(false, true);
+  else if (ta && !tb) NYS_GEMM_B3(true, false);
+  else NYS_GEMM_B3(true, true);
+#undef NYS_GEMM_B3
+  NYS_CHECK_LAUNCH();
+  if (nz > 1) {
+    hipLaunchKernelGGL(splitk_reduce<float>, dim3((unsigned)cdiv(M * N, 256)), dim3(256), 0, s, M, N, (int)nz,
+                       alpha, part, beta, C, ldc, (const int*)nullptr);
+    NYS_CHECK_LAUNCH();
+  }
+  return NYS_OK;
+}
 
 }  // namespace nys

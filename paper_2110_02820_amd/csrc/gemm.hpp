@@ -11,6 +11,14 @@ nys_status gemm(bool ta, bool tb, int64_t M, int64_t N, int64_t K, TC alpha, con
                 int64_t lda, const TBs* B, int64_t ldb, TC beta, TC* C, int64_t ldc, TC* scratch,
                 size_t scratch_elems, hipStream_t s, const int* skip = nullptr);
 
+// C = alpha op(A) op(B) + beta C for float32 operands with the products on
+// bf16 MFMA (hi/lo three-product split, relative error ~2^-16 per product,
+// float32 accumulation).  Same scratch rule as gemm(); shapes whose rows
+// cannot take 16-byte loads fall back to gemm<float>.
+nys_status gemm_bf16x3(bool ta, bool tb, int64_t M, int64_t N, int64_t K, float alpha, const float* A, int64_t lda,
+                       const float* B, int64_t ldb, float beta, float* C, int64_t ldc, float* scratch,
+                       size_t scratch_elems, hipStream_t s);
+
 // Scratch that lets gemm() split K for an M x N output.
 // gemm() splits K only when the output has fewer than 512 tiles of 64 x 64.
 inline size_t gemm_scratch_elems(int64_t M, int64_t N) {
