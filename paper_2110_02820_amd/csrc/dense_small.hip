@@ -5,11 +5,13 @@
 //   * shift nu = eps(||Y||_F) (raised for reduced-precision sketches) and
 //     Y_nu = Y + nu Omega
 //   * blocked right-looking Cholesky, one launch per block step
-//     (diagonal block, panel, trailing update)
-//   * inverse of the lower-triangular factor (independent column-block chains)
+//     (diagonal block by one wave, panel, trailing update)
+//   * inverse of the lower-triangular factor by recursive doubling over
+//     block pairs
 //   * symmetric eigensolver: block two-sided Jacobi with the round-robin
-//     ordering of block pairs; each round solves the 32 x 32 subproblems in
-//     LDS and applies the rotations to the off-diagonal tiles on FP64 MFMA
+//     ordering of block pairs; one launch per round solves the 32 x 32
+//     subproblems in LDS and applies the previous round's rotations to the
+//     off-diagonal tiles on FP64 MFMA
 //   * descending sort of the eigenvalues and the scaled eigenvector matrix
 #include <cstdlib>
 

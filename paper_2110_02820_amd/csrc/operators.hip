@@ -6,9 +6,9 @@
 //               GEMMs X^T (X P) for blocks of columns
 //  * RBF      : K_ij = exp(-||x_i - x_j||^2 / (2 sigma^2)) evaluated tile by
 //               tile and never stored (Section 6.3 kernel ridge regression).
-//               float64 forms: a VALU kernel for one vector, and an MFMA
-//               (v_mfma_f64_16x16x4f64) kernel for blocks of columns
-//               (the sketch A Omega, block PCG).
+//               float64 forms, both with the Gram on v_mfma_f64_16x16x4f64:
+//               one vector (exp and compensated sum on the vector units),
+//               and blocks of columns (the sketch A Omega, block PCG).
 #include "operators.hpp"
 #include "xtx.hpp"
 #include "gemm.hpp"
