@@ -869,10 +869,11 @@ __global__ void jacobi_init(const double* __restrict__ G, int64_t l, int64_t m,
 
 // Sort eigenvalues descending (rank by counting; ties by index) and build
 //   T[:, rank(i)] = V[:, i] / sqrt(s_i),   lam[rank(i)] = max(0, s_i - nu).
-__global__ void eig_finalize(const double* __restrict__ ev, const double* __restrict__ V,
-                             int64_t l, int64_t m, const double* __restrict__ nu,
-                             double* __restrict__ T, double* __restrict__ lam,
-                             double* __restrict__ sig2) {
+// Rank of eigenvalue i in descending order (ties by index), lam, sig2 and the
+// column scale 1/sqrt(s_i); one thread per eigenvalue.
+__global__ void eig_rank(const double* __restrict__ ev, int64_t l, const double* __restrict__ nu,
+                         int* __restrict__ rank_out, double* __restrict__ inv_out, double* __restrict__ lam,
+                         double* __restrict__ sig2) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= l) return;
   const double si = ev[i];
@@ -881,13 +882,22 @@ __global__ void eig_finalize(const double* __restrict__ ev, const double* __rest
     const double sj = ev[j];
     rank += (sj > si) || (sj == si && j < i);
   }
-  const double inv = (si > 0.0) ? 1.0 / sqrt(si) : 0.0;
-  for (int64_t r = 0; r < l; ++r) T[r * l + rank] = V[r * m + i] * inv;
+  rank_out[i] = (int)rank;
+  inv_out[i] = (si > 0.0) ? 1.0 / sqrt(si) : 0.0;
   const double sh = nu ? nu[0] : 0.0;
   lam[rank] = fmax(0.0, si - sh);
   if (sig2) sig2[rank] = si;
 }
 
+// T[r][rank_i] = V[r][i] / sqrt(s_i): the eigenvectors in descending order,
+// scaled; one thread per entry.
+__global__ void eig_permute(const double* __restrict__ V, int64_t l, int64_t m, const int* __restrict__ rank,
+                            const double* __restrict__ inv, double* __restrict__ T) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= l * l) return;
+  const int64_t r = idx / l, i = idx % l;
+  T[r * l + rank[i]] = V[r * m + i] * inv[i];
+}
 
 }  // namespace
 
@@ -965,7 +975,7 @@ int jac_nblk(int64_t l) {
 size_t eig_ws_doubles(int64_t l) {
   const int64_t nb = jac_nblk(l);
   const int64_t m = nb * JB;
-  return (size_t)(4 * m * m + m + 2 * (nb / 2) * JS * JS + 8);
+  return (size_t)(4 * m * m + m + 2 * (nb / 2) * JS * JS + 2 * m + 8);
 }
 
 int* pinned_flags() {
@@ -1044,8 +1054,10 @@ nys_status sym_eig(const double* G, int64_t l, double* work, int* flags, int max
   // phase 2 of the last round that ran (a no-op if a later launch did it)
   hipLaunchKernelGGL(jac_round, dim3((unsigned)tasks), dim3(256), 0, s, a, g, 0);
   hipLaunchKernelGGL(jac_evals, dim3((unsigned)cdiv(m, 256)), dim3(256), 0, s, a, g, ev);
-  hipLaunchKernelGGL(eig_finalize, dim3((unsigned)cdiv(l, 256)), dim3(256), 0, s, ev, V, l, m,
-                     nu, T, lam, sig2);
+  int* rk = reinterpret_cast<int*>(floor + 2);
+  double* inv = floor + 2 + cdiv(m, 2);
+  hipLaunchKernelGGL(eig_rank, dim3((unsigned)cdiv(l, 256)), dim3(256), 0, s, ev, l, nu, rk, inv, lam, sig2);
+  hipLaunchKernelGGL(eig_permute, dim3((unsigned)cdiv(l * l, 256)), dim3(256), 0, s, V, l, m, rk, inv, T);
   NYS_CHECK_LAUNCH();
   return NYS_OK;
 }
