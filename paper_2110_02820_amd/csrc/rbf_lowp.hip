@@ -365,6 +365,91 @@ __global__ __launch_bounds__(256) void rbf_kv_lowp(RbfLowp L, const float* __res
     }
 }
 
+// Few columns (k <= 64): out[I, c0 .. c0 + 16 CF - 1] = oscale * K_IJ P_J over
+// the points of split z, in registers only.  Each wave owns F fragments of 16
+// rows and walks the points 16 at a time.  The Gram tile is formed transposed
+// (points as the MFMA row index, rows as the column index), so lane l holds
+// K[point 4 (l/16) + q][row l % 16] for q = 0..3: for each q this is exactly
+// the B operand of v_mfma_f32_16x16x4f32 over the four points {4 g + q}, and
+// the matching A operand is P[point 4 g + q][column l % 16].  K P is therefore
+// four float32 MFMAs per 16 x 16 tile and 16 columns, with no LDS, no barrier
+// and no conversion of K.  Pz: P copied to npad x kq floats, zero outside
+// n x k (so tail points and columns contribute exact zeros).
+template <int MODE, int CF, int F>
+__global__ __launch_bounds__(256) void rbf_kv_reg(RbfLowp L, const float* __restrict__ Pz, int64_t kq, int64_t k,
+                                                  float* __restrict__ out, int64_t ldo, int64_t pts_per_split,
+                                                  float oscale, const int* __restrict__ skip) {
+  if (skip && *skip) return;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int g = lane >> 4, r = lane & 15;
+  const int64_t n = L.n;
+  const int64_t i0 = ((int64_t)blockIdx.x * 4 + wave) * (16 * F);
+  const int64_t c0 = (int64_t)blockIdx.y * (16 * CF);
+  const float two_s = L.two_s;
+  // rows i0 + 16 f + r: operands and the row term folded into the accumulator
+  Operand<MODE> a[F];
+  f4 crow[F];
+#pragma unroll
+  for (int f = 0; f < F; ++f) {
+    a[f].load(L, i0 + 16 * f + r, lane);
+    const float c = -L.hs[i0 + 16 * f + r] / two_s;
+    crow[f] = f4{c, c, c, c};
+  }
+  f4 acc[F][CF];
+#pragma unroll
+  for (int f = 0; f < F; ++f)
+#pragma unroll
+    for (int cf = 0; cf < CF; ++cf) acc[f][cf] = f4{0, 0, 0, 0};
+  const int64_t j0 = (int64_t)blockIdx.z * pts_per_split;
+  int64_t j1 = j0 + pts_per_split;
+  if (j1 > n) j1 = n;
+  for (int64_t jt = j0; jt < j1; jt += 16) {
+    // points jt .. jt + 15 lie inside the padded arrays (jt < n, npad a multiple of 256)
+    Operand<MODE> b;
+    b.load(L, jt + r, lane);
+    const f4 hj = *reinterpret_cast<const f4*>(L.hs + jt + 4 * g);
+    float pv[CF][4];
+#pragma unroll
+    for (int cf = 0; cf < CF; ++cf)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) pv[cf][q] = Pz[(jt + 4 * g + q) * kq + c0 + 16 * cf + r];
+#pragma unroll
+    for (int f = 0; f < F; ++f) {
+      const f4 dg = gram_tile(b, a[f], crow[f], L.ksteps);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const float e = __builtin_amdgcn_exp2f(fmaf(two_s, dg[q], -hj[q]));
+#pragma unroll
+        for (int cf = 0; cf < CF; ++cf)
+          acc[f][cf] = __builtin_amdgcn_mfma_f32_16x16x4f32(pv[cf][q], e, acc[f][cf], 0, 0, 0);
+      }
+    }
+  }
+  // lane l holds out[row 16 f + l % 16][column 16 cf + 4 (l / 16) + q]
+  float* o = out + (int64_t)blockIdx.z * n * ldo;
+#pragma unroll
+  for (int f = 0; f < F; ++f) {
+    const int64_t row = i0 + 16 * f + r;
+    if (row >= n) continue;
+#pragma unroll
+    for (int cf = 0; cf < CF; ++cf)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int64_t col = c0 + 16 * cf + 4 * g + q;
+        if (col < k) o[row * ldo + col] = oscale * acc[f][cf][q];
+      }
+  }
+}
+
+// Pz[j][c] = P[j][c] for j < n, c < k; zero elsewhere (npad x kq)
+__global__ void pad_p(const float* __restrict__ P, int64_t ldp, int64_t n, int64_t k, int64_t npad, int64_t kq,
+                      float* __restrict__ Pz) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= npad * kq) return;
+  const int64_t j = idx / kq, c = idx % kq;
+  Pz[idx] = (j < n && c < k) ? P[j * ldp + c] : 0.0f;
+}
+
 // V = scale * sum_z part[z] + mu_c P  (n x k float), fixed order over z
 __global__ void rbf_lowp_finish(const float* __restrict__ part, int nz, int64_t n, int64_t k, float scale,
                                 const float* __restrict__ P, int64_t ldp, const double* __restrict__ mu,
@@ -445,16 +530,42 @@ nys_status rbf_lowp_mv(const RbfLowp& L, int mode, const float* p, const double*
   return NYS_OK;
 }
 
-// float elements of the pre-split bf16 P (up to three pieces of kq x npad bf16)
-size_t kv_split_elems(int64_t n, int64_t k) {
-  const int64_t nc = k > 64 ? 128 : 64;
-  return 3 * (size_t)(cdiv(k, nc) * nc) * (size_t)(cdiv(n, 256) * 256) / 2;
+// Launch plan of V = K P.  k <= 64: the register kernel, 16 CF columns and
+// 4 waves x 16 F rows per block, P copied zero-padded to npad x kq floats.
+// k > 64: the LDS kernel, 64 rows x nc columns per block, P pre-split into
+// bf16 pieces (up to three pieces of kq x npad bf16).
+struct KvPlan {
+  bool reg;
+  int cf, f;
+  int64_t nc, kq, rows, tiles;
+  size_t prep_elems;  // float elements of the prepared P
+};
+
+KvPlan kv_plan(int64_t n, int64_t k) {
+  KvPlan p{};
+  const int64_t npad = cdiv(n, 256) * 256;
+  p.reg = k <= 64;
+  if (p.reg) {
+    p.cf = k <= 16 ? 1 : k <= 32 ? 2 : 4;
+    p.f = p.cf == 4 ? 2 : 4;
+    p.nc = 16 * p.cf;
+    p.rows = 64 * p.f;
+  } else {
+    p.cf = 8;
+    p.f = 1;
+    p.nc = 128;
+    p.rows = 64;
+  }
+  p.kq = cdiv(k, p.nc) * p.nc;
+  p.tiles = cdiv(n, p.rows) * cdiv(k, p.nc);
+  p.prep_elems = p.reg ? (size_t)npad * (size_t)p.kq : 3 * (size_t)p.kq * (size_t)npad / 2;
+  return p;
 }
 
 size_t rbf_lowp_kv_scratch(int64_t n, int64_t k) {
-  const int64_t tiles = cdiv(n, 64) * cdiv(k, k > 64 ? (int64_t)128 : (int64_t)64);
-  const int64_t nz = cdiv(8 * 256, tiles);
-  return kv_split_elems(n, k) + (nz > 1 ? (size_t)nz * (size_t)n * (size_t)k : 0);
+  const KvPlan p = kv_plan(n, k);
+  const int64_t nz = cdiv(8 * 256, p.tiles);
+  return p.prep_elems + (nz > 1 ? (size_t)nz * (size_t)n * (size_t)k : 0);
 }
 
 // V += mu_c P
@@ -472,19 +583,24 @@ nys_status rbf_lowp_kv(const RbfLowp& L, int mode, const float* P, int64_t ldp, 
                        int64_t nrhs, float* V, int64_t ldv, float* scratch, size_t scratch_elems, const int* skip,
                        hipStream_t s) {
   const int64_t n = L.n;
-  // 128 output columns per block when there are more than 64 (half the
-  // Gram / exp recomputation and twice the MFMA work per staged tile)
-  const int64_t nc = k > 64 ? 128 : 64;
-  // the bf16 products read P split once into pieces (front of the scratch)
-  const size_t se = kv_split_elems(n, k);
+  const KvPlan pl = kv_plan(n, k);
+  const int64_t nc = pl.nc;
+  // the kernels read P prepared once (front of the scratch): zero-padded
+  // float32 for the register kernel, split into bf16 pieces for the LDS kernel
+  const size_t se = pl.prep_elems;
   if (scratch_elems < se) {
     set_error("rbf_lowp_kv: scratch of %zu floats < %zu", scratch_elems, se);
     return NYS_ERR_WORKSPACE;
   }
   RbfLowp Lq = L;
-  Lq.kq = cdiv(k, nc) * nc;
+  Lq.kq = pl.kq;
   const uint4* Pq = reinterpret_cast<const uint4*>(scratch);
-  {
+  const float* Pz = scratch;
+  if (pl.reg) {
+    hipLaunchKernelGGL(pad_p, dim3((unsigned)cdiv(L.npad * pl.kq, 256)), dim3(256), 0, s, P, ldp, n, k, L.npad,
+                       pl.kq, scratch);
+    NYS_CHECK_LAUNCH();
+  } else {
     const dim3 sg((unsigned)cdiv(L.npad, 32), (unsigned)cdiv(Lq.kq, 32));
     unsigned short* q = reinterpret_cast<unsigned short*>(scratch);
     if (mode == 0)
@@ -495,7 +611,7 @@ nys_status rbf_lowp_kv(const RbfLowp& L, int mode, const float* P, int64_t ldp, 
   }
   scratch += se;
   scratch_elems -= se;
-  const int64_t tiles = cdiv(n, 64) * cdiv(k, nc);
+  const int64_t tiles = pl.tiles;
   // about eight blocks per compute unit: the per-tile chain (loads, LDS,
   // barriers, MFMA) is latency-bound with fewer waves per SIMD
   int64_t nz = cdiv(8 * (num_cus() < 256 ? num_cus() : 256), tiles);
@@ -503,17 +619,24 @@ nys_status rbf_lowp_kv(const RbfLowp& L, int mode, const float* P, int64_t ldp, 
   while (nz > 1 && (size_t)(nz * n * k) > scratch_elems) --nz;
   const int64_t pps = cdiv(cdiv(n, nz), 32) * 32;
   nz = cdiv(n, pps);
-  dim3 grid((unsigned)cdiv(n, 64), (unsigned)cdiv(k, nc), (unsigned)nz);
+  dim3 grid((unsigned)cdiv(n, pl.rows), (unsigned)cdiv(k, nc), (unsigned)nz);
   float* dst = nz > 1 ? scratch : V;
   const int64_t ldo = nz > 1 ? k : ldv;
   const float oscale = nz > 1 ? 1.0f : L.scale;
-#define KV(M, CF) hipLaunchKernelGGL((rbf_kv_lowp<M, CF>), grid, dim3(256), 0, s, Lq, P, ldp, k, Pq, Lq.npad / 8, dst, ldo, pps, oscale, skip)
-  if (mode == 0) {
-    if (nc == 128) KV(0, 8); else KV(0, 4);
+  if (pl.reg) {
+#define KR(M, CF, F) \
+  hipLaunchKernelGGL((rbf_kv_reg<M, CF, F>), grid, dim3(256), 0, s, Lq, Pz, pl.kq, k, dst, ldo, pps, oscale, skip)
+    if (mode == 0) {
+      if (pl.cf == 1) KR(0, 1, 4); else if (pl.cf == 2) KR(0, 2, 4); else KR(0, 4, 2);
+    } else {
+      if (pl.cf == 1) KR(1, 1, 4); else if (pl.cf == 2) KR(1, 2, 4); else KR(1, 4, 2);
+    }
+#undef KR
   } else {
-    if (nc == 128) KV(1, 8); else KV(1, 4);
-  }
+#define KV(M, CF) hipLaunchKernelGGL((rbf_kv_lowp<M, CF>), grid, dim3(256), 0, s, Lq, P, ldp, k, Pq, Lq.npad / 8, dst, ldo, pps, oscale, skip)
+    if (mode == 0) KV(0, 8); else KV(1, 8);
 #undef KV
+  }
   NYS_CHECK_LAUNCH();
   if (nz > 1) {
     hipLaunchKernelGGL(rbf_lowp_finish, dim3((unsigned)cdiv(n * k, 256)), dim3(256), 0, s, scratch, (int)nz, n, k,

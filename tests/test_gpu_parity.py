@@ -373,11 +373,13 @@ def _mixture_case(n, d, ell, seed):
 
 
 @pytest.mark.parametrize("prec,tol", [(1, 2e-5), (3, 2e-4)])
-@pytest.mark.parametrize("k", [1, 5, 70])
+@pytest.mark.parametrize("k", [1, 5, 20, 40, 70])
 def test_rbf_lowp_products(prec, tol, k):
     """float32 Gram (prec 1) and bf16x3 Gram (prec 3) against the float64 oracle.
     Bounds: float32 exp and accumulation over ~1e3 terms (~1e-6 .. 1e-5);
-    bf16x3 keeps ~16 bits of each coordinate (~1e-4)."""
+    bf16x3 keeps ~16 bits of each coordinate (~1e-4).  k covers the one-vector
+    kernel, the register kernel's 16, 32 and 64 column blocks (ragged) and the
+    LDS kernel."""
     w, op_ref, _ = _mixture_case(1111, 32, 10, 40 + k)
     op = nys.Operator.rbf(t32(w["X"]), w["sigma"])
     V = np.random.default_rng(k).standard_normal((1111, k))
@@ -395,6 +397,10 @@ def test_rbf_lowp_small_dims(d):
     ref = oracle.RBFOp(X, 1.7).matmat(v)
     assert rel(h(nys.nys_op_apply(op, 0.0, t32(v), prec=3)), ref) < 2e-4
     assert rel(h(nys.nys_op_apply(op, 0.0, t32(v), prec=1)), ref) < 2e-5
+    V = rng.standard_normal((517, 3))
+    ref = oracle.RBFOp(X, 1.7).matmat(V)
+    assert rel(h(nys.nys_op_apply(op, 0.0, t32(V), prec=3)), ref) < 2e-4
+    assert rel(h(nys.nys_op_apply(op, 0.0, t32(V), prec=1)), ref) < 2e-5
 
 
 @pytest.mark.parametrize("prec", [2, 3])
