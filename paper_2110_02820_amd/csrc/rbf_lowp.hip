@@ -66,6 +66,7 @@ struct Operand<0> {
   }
 };
 // F32: lane l holds row (l % 16), coordinates 4 ks + l / 16 for ks = 0..7
+// (the loads of the groups a kernel's Gram does not use are dead code)
 template <>
 struct Operand<1> {
   float v[8];
@@ -82,23 +83,29 @@ __device__ __forceinline__ f4 gram_tile(const Operand<0>& a, const Operand<0>& b
   d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.hi, b.lo, d, 0, 0, 0);
   return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.lo, b.hi, d, 0, 0, 0);
 }
-// (float32: only the ksteps coordinate groups that hold data; ksteps is uniform)
-__device__ __forceinline__ f4 gram_tile(const Operand<1>& a, const Operand<1>& b, f4 c, int ksteps = 8) {
+// (float32: the first KS coordinate groups, KS a compile-time count that
+// covers d, so the MFMA chain is straight-line code; operand registers of the
+// groups beyond KS are never loaded)
+template <int KS>
+__device__ __forceinline__ f4 gram_tile(const Operand<1>& a, const Operand<1>& b, f4 c) {
   f4 d = c;
 #pragma unroll
-  for (int ks = 0; ks < 8; ++ks)
-    if (ks < ksteps) d = __builtin_amdgcn_mfma_f32_16x16x4f32(a.v[ks], b.v[ks], d, 0, 0, 0);
+  for (int ks = 0; ks < KS; ++ks) d = __builtin_amdgcn_mfma_f32_16x16x4f32(a.v[ks], b.v[ks], d, 0, 0, 0);
   return d;
 }
-__device__ __forceinline__ f4 gram_tile(const Operand<0>& a, const Operand<0>& b, f4 c, int) {
+template <int KS>
+__device__ __forceinline__ f4 gram_tile(const Operand<0>& a, const Operand<0>& b, f4 c) {
   return gram_tile(a, b, c);
 }
+// float32 Gram steps for d coordinates: 2, 4 or 8 groups of four (the padded
+// coordinates are zero); the bf16x3 Gram always takes one 32-wide step
+__host__ __device__ constexpr int ks_for(int ksteps) { return ksteps <= 2 ? 2 : ksteps <= 4 ? 4 : 8; }
 
 // One vector: part[split][i] = sum_{j in split} K_ij p_j.  Block = 4 waves,
 // wave w owns rows rb*256 + w*64 .. + 63 (four 16-row fragments); the lanes
 // of a wave walk the points of the split 16 at a time.  Accumulator element
 // q of lane l belongs to row 4 (l/16) + q of a fragment and column l % 16.
-template <int MODE>
+template <int MODE, int KS>
 __global__ __launch_bounds__(256) void rbf_mv_lowp(RbfLowp L, const float* __restrict__ p, float* __restrict__ part,
                                                    int64_t pts_per_split, const int* __restrict__ skip) {
   if (skip && *skip) return;
@@ -128,7 +135,7 @@ __global__ __launch_bounds__(256) void rbf_mv_lowp(RbfLowp L, const float* __res
     const float pj = (j < j1) ? p[j] : 0.0f;
 #pragma unroll
     for (int f = 0; f < 4; ++f) {
-      const f4 dg = gram_tile(a[f], b, cinit[f], L.ksteps);
+      const f4 dg = gram_tile<KS>(a[f], b, cinit[f]);
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const float e = __builtin_amdgcn_exp2f(fmaf(two_s, dg[q], -hj));
@@ -242,11 +249,17 @@ struct KvStage2<1, CF> {
   }
 };
 
+// Storage position of point jj (0..31) of a 32-point step in the register
+// kernel's order: position 8 g + t holds point 4 g + t (t < 4) or
+// 16 + 4 g + t - 4 (t >= 4), the points lane group g holds after the
+// transposed Gram tiles.
+__device__ __forceinline__ int kv_perm(int jj) { return 8 * ((jj & 15) >> 2) + 4 * (jj >> 4) + (jj & 3); }
+
 // P (n x k float, row-major) -> NP bf16 pieces (2: hi, lo; 3: the exact
 // three-piece split), transposed: Pq[piece][c][j] for c < kq, j < npad (zero
 // outside n x k), so a tile's 8-point runs of one column are 16-byte chunks.
 // 32 x 32 tiles through LDS.
-template <int NP>
+template <int NP, bool PERM>
 __global__ __launch_bounds__(256) void split_p_bf16(const float* __restrict__ P, int64_t ldp, int64_t n,
                                                     int64_t k, int64_t kq, int64_t npad,
                                                     unsigned short* __restrict__ Pq) {
@@ -261,7 +274,8 @@ __global__ __launch_bounds__(256) void split_p_bf16(const float* __restrict__ P,
   __syncthreads();
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
-    const int64_t c = c0 + ty + 8 * u, j = j0 + tx;
+    const int64_t c = c0 + ty + 8 * u;
+    const int64_t j = j0 + (PERM ? kv_perm(tx) : tx);
     if (c < kq && j < npad) {
       const float v = tl[tx][ty + 8 * u];
       if (NP == 2) {
@@ -285,7 +299,7 @@ __global__ __launch_bounds__(256) void split_p_bf16(const float* __restrict__ P,
 // MFMA and exp into LDS; stage 2 multiplies K by the P tile staged in LDS.
 // The P tile and the point operands of the next tile are loaded into
 // registers while the current tile is multiplied.
-template <int MODE, int CF>
+template <int MODE, int CF, int KS>
 __global__ __launch_bounds__(256) void rbf_kv_lowp(RbfLowp L, const float* __restrict__ P, int64_t ldp, int64_t k,
                                                    const uint4* __restrict__ Pq, int64_t ldq,
                                                    float* __restrict__ out, int64_t ldo, int64_t pts_per_split,
@@ -340,8 +354,8 @@ __global__ __launch_bounds__(256) void rbf_kv_lowp(RbfLowp L, const float* __res
       st.put_p16((e >> 2) / NC, (e >> 2) % NC, e & 3, pr[u]);
     }
     // stage 1: K rows wave*16 .. +15, points jt .. jt+31 (two 16-point tiles)
-    const f4 dg0 = gram_tile(a, b0, cinit, L.ksteps);
-    const f4 dg1 = gram_tile(a, b1, cinit, L.ksteps);
+    const f4 dg0 = gram_tile<KS>(a, b0, cinit);
+    const f4 dg1 = gram_tile<KS>(a, b1, cinit);
     const int64_t ja = jt + (lane & 15), jb = jt + 16 + (lane & 15);
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
@@ -365,8 +379,8 @@ __global__ __launch_bounds__(256) void rbf_kv_lowp(RbfLowp L, const float* __res
     }
 }
 
-// Few columns (k <= 64): out[I, c0 .. c0 + 16 CF - 1] = oscale * K_IJ P_J over
-// the points of split z, in registers only.  Each wave owns F fragments of 16
+// Float32 mode, few columns (k <= 64): out[I, c0 .. c0 + 16 CF - 1] =
+// oscale * K_IJ P_J over the points of split z, in registers only.  Each wave owns F fragments of 16
 // rows and walks the points 16 at a time.  The Gram tile is formed transposed
 // (points as the MFMA row index, rows as the column index), so lane l holds
 // K[point 4 (l/16) + q][row l % 16] for q = 0..3: for each q this is exactly
@@ -375,8 +389,8 @@ __global__ __launch_bounds__(256) void rbf_kv_lowp(RbfLowp L, const float* __res
 // four float32 MFMAs per 16 x 16 tile and 16 columns, with no LDS, no barrier
 // and no conversion of K.  Pz: P copied to npad x kq floats, zero outside
 // n x k (so tail points and columns contribute exact zeros).
-template <int MODE, int CF, int F>
-__global__ __launch_bounds__(256) void rbf_kv_reg(RbfLowp L, const float* __restrict__ Pz, int64_t kq, int64_t k,
+template <int CF, int F, int KS>
+__global__ __launch_bounds__(256) void rbf_kv_reg32(RbfLowp L, const float* __restrict__ Pz, int64_t kq, int64_t k,
                                                   float* __restrict__ out, int64_t ldo, int64_t pts_per_split,
                                                   float oscale, const int* __restrict__ skip) {
   if (skip && *skip) return;
@@ -387,7 +401,7 @@ __global__ __launch_bounds__(256) void rbf_kv_reg(RbfLowp L, const float* __rest
   const int64_t c0 = (int64_t)blockIdx.y * (16 * CF);
   const float two_s = L.two_s;
   // rows i0 + 16 f + r: operands and the row term folded into the accumulator
-  Operand<MODE> a[F];
+  Operand<1> a[F];
   f4 crow[F];
 #pragma unroll
   for (int f = 0; f < F; ++f) {
@@ -405,7 +419,7 @@ __global__ __launch_bounds__(256) void rbf_kv_reg(RbfLowp L, const float* __rest
   if (j1 > n) j1 = n;
   for (int64_t jt = j0; jt < j1; jt += 16) {
     // points jt .. jt + 15 lie inside the padded arrays (jt < n, npad a multiple of 256)
-    Operand<MODE> b;
+    Operand<1> b;
     b.load(L, jt + r, lane);
     const f4 hj = *reinterpret_cast<const f4*>(L.hs + jt + 4 * g);
     float pv[CF][4];
@@ -415,7 +429,7 @@ __global__ __launch_bounds__(256) void rbf_kv_reg(RbfLowp L, const float* __rest
       for (int q = 0; q < 4; ++q) pv[cf][q] = Pz[(jt + 4 * g + q) * kq + c0 + 16 * cf + r];
 #pragma unroll
     for (int f = 0; f < F; ++f) {
-      const f4 dg = gram_tile(b, a[f], crow[f], L.ksteps);
+      const f4 dg = gram_tile<KS>(b, a[f], crow[f]);
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const float e = __builtin_amdgcn_exp2f(fmaf(two_s, dg[q], -hj[q]));
@@ -448,6 +462,111 @@ __global__ void pad_p(const float* __restrict__ P, int64_t ldp, int64_t n, int64
   if (idx >= npad * kq) return;
   const int64_t j = idx / kq, c = idx % kq;
   Pz[idx] = (j < n && c < k) ? P[j * ldp + c] : 0.0f;
+}
+
+// bf16x3 mode, few columns (k <= 64), in registers only:
+// out[I, c0 .. c0 + 16 CF - 1] = oscale * K_IJ P_J over the points of split z.  Each wave owns F fragments of 16 rows and walks the
+// points 32 at a time.  The Gram tiles are formed transposed (points as the
+// MFMA row index, rows as the column index), so after the exp lane l holds
+// K[point 4 g + q][row l % 16] and K[point 16 + 4 g + q][row l % 16],
+// g = l / 16, q = 0..3.  These eight values are the lane's k-slice of the B
+// operand of v_mfma_f32_16x16x32_bf16 when the 32 points of the step are taken
+// in the order of kv_perm below; P is pre-split into bf16 pieces stored in
+// that order (split_p_bf16 with PERM), so the A operand (P transposed) is one
+// 16-byte load per piece.  K is split into bf16 hi + lo in registers and
+// K P ~ hi.hi + hi.lo + lo.hi (three MFMAs per 32 points and 16 columns), as
+// in the LDS kernel's bf16x3 mode.  No LDS, no barrier, float32 accumulation.
+// (For the float32 mode the three-piece split of K costs more VALU time than
+// the float32 MFMAs it saves: rbf_kv_reg32 above multiplies K unsplit.)
+__device__ __forceinline__ void split_k(const float (&e)[8], bf8 (&kb)[2]) {
+#pragma unroll
+  for (int t = 0; t < 8; ++t) {
+    const __bf16 h = (__bf16)e[t];
+    kb[0][t] = h;
+    kb[1][t] = (__bf16)(e[t] - (float)h);
+  }
+}
+// acc += P^T K over one 32-point step (A: P pieces, B: K pieces), smallest first
+__device__ __forceinline__ f4 kp_products(const bf8 (&pp)[2], const bf8 (&kb)[2], f4 c) {
+  c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(pp[1], kb[0], c, 0, 0, 0);
+  c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(pp[0], kb[1], c, 0, 0, 0);
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(pp[0], kb[0], c, 0, 0, 0);
+}
+template <int CF, int F>
+__global__ __launch_bounds__(256) void rbf_kv_reg(RbfLowp L, const uint4* __restrict__ Pq, int64_t ldq, int64_t k,
+                                                  float* __restrict__ out, int64_t ldo, int64_t pts_per_split,
+                                                  float oscale, const int* __restrict__ skip) {
+  if (skip && *skip) return;
+  constexpr int NP = 2;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int g = lane >> 4, r = lane & 15;
+  const int64_t n = L.n;
+  const int64_t i0 = ((int64_t)blockIdx.x * 4 + wave) * (16 * F);
+  const int64_t c0 = (int64_t)blockIdx.y * (16 * CF);
+  const float two_s = L.two_s;
+  // rows i0 + 16 f + r: operands and the row term folded into the accumulator
+  Operand<0> a[F];
+  f4 crow[F];
+#pragma unroll
+  for (int f = 0; f < F; ++f) {
+    a[f].load(L, i0 + 16 * f + r, lane);
+    const float c = -L.hs[i0 + 16 * f + r] / two_s;
+    crow[f] = f4{c, c, c, c};
+  }
+  f4 acc[F][CF];
+#pragma unroll
+  for (int f = 0; f < F; ++f)
+#pragma unroll
+    for (int cf = 0; cf < CF; ++cf) acc[f][cf] = f4{0, 0, 0, 0};
+  const int64_t j0 = (int64_t)blockIdx.z * pts_per_split;
+  int64_t j1 = j0 + pts_per_split;
+  if (j1 > n) j1 = n;
+  for (int64_t jt = j0; jt < j1; jt += 32) {
+    // points jt .. jt + 31 lie inside the padded arrays (jt < n, npad a
+    // multiple of 256); P pieces are zero for points >= n
+    Operand<0> b0, b1;
+    b0.load(L, jt + r, lane);
+    b1.load(L, jt + 16 + r, lane);
+    const f4 h0 = *reinterpret_cast<const f4*>(L.hs + jt + 4 * g);
+    const f4 h1 = *reinterpret_cast<const f4*>(L.hs + jt + 16 + 4 * g);
+    bf8 kb[F][NP];
+#pragma unroll
+    for (int f = 0; f < F; ++f) {
+      const f4 d0 = gram_tile(b0, a[f], crow[f]);
+      const f4 d1 = gram_tile(b1, a[f], crow[f]);
+      float e[8];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        e[q] = __builtin_amdgcn_exp2f(fmaf(two_s, d0[q], -h0[q]));
+        e[4 + q] = __builtin_amdgcn_exp2f(fmaf(two_s, d1[q], -h1[q]));
+      }
+      split_k(e, kb[f]);
+    }
+#pragma unroll
+    for (int cf = 0; cf < CF; ++cf) {
+      // column c0 + 16 cf + r, positions 8 g .. 8 g + 7 of the step
+      bf8 pp[NP];
+#pragma unroll
+      for (int pc = 0; pc < NP; ++pc)
+        pp[pc] = __builtin_bit_cast(bf8, Pq[((int64_t)pc * L.kq + c0 + 16 * cf + r) * ldq + (jt >> 3) + g]);
+#pragma unroll
+      for (int f = 0; f < F; ++f) acc[f][cf] = kp_products(pp, kb[f], acc[f][cf]);
+    }
+  }
+  // lane l holds out[row 16 f + l % 16][column 16 cf + 4 (l / 16) + q]
+  float* o = out + (int64_t)blockIdx.z * n * ldo;
+#pragma unroll
+  for (int f = 0; f < F; ++f) {
+    const int64_t row = i0 + 16 * f + r;
+    if (row >= n) continue;
+#pragma unroll
+    for (int cf = 0; cf < CF; ++cf)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int64_t col = c0 + 16 * cf + 4 * g + q;
+        if (col < k) o[row * ldo + col] = oscale * acc[f][cf][q];
+      }
+  }
 }
 
 // V = scale * sum_z part[z] + mu_c P  (n x k float), fixed order over z
@@ -512,9 +631,13 @@ nys_status rbf_lowp_mv_partials(const RbfLowp& L, int mode, const float* p, floa
   ns = cdiv(n, pps);
   dim3 grid((unsigned)nrb, (unsigned)ns);
   if (mode == 0)
-    hipLaunchKernelGGL(rbf_mv_lowp<0>, grid, dim3(256), 0, s, L, p, part, pps, skip);
+    hipLaunchKernelGGL((rbf_mv_lowp<0, 1>), grid, dim3(256), 0, s, L, p, part, pps, skip);
   else
-    hipLaunchKernelGGL(rbf_mv_lowp<1>, grid, dim3(256), 0, s, L, p, part, pps, skip);
+    switch (ks_for(L.ksteps)) {
+      case 2: hipLaunchKernelGGL((rbf_mv_lowp<1, 2>), grid, dim3(256), 0, s, L, p, part, pps, skip); break;
+      case 4: hipLaunchKernelGGL((rbf_mv_lowp<1, 4>), grid, dim3(256), 0, s, L, p, part, pps, skip); break;
+      default: hipLaunchKernelGGL((rbf_mv_lowp<1, 8>), grid, dim3(256), 0, s, L, p, part, pps, skip); break;
+    }
   NYS_CHECK_LAUNCH();
   *ng_out = (int)ns;
   return NYS_OK;
@@ -530,10 +653,11 @@ nys_status rbf_lowp_mv(const RbfLowp& L, int mode, const float* p, const double*
   return NYS_OK;
 }
 
-// Launch plan of V = K P.  k <= 64: the register kernel, 16 CF columns and
-// 4 waves x 16 F rows per block, P copied zero-padded to npad x kq floats.
-// k > 64: the LDS kernel, 64 rows x nc columns per block, P pre-split into
-// bf16 pieces (up to three pieces of kq x npad bf16).
+// Launch plan of V = K P.  k <= 64: a register kernel with 16 CF columns and
+// 4 waves x 16 F rows per block (bf16x3 mode: rbf_kv_reg on P pre-split in
+// the point order of a step; float32 mode: rbf_kv_reg32 on P zero-padded to
+// npad x kq floats).  k > 64: the LDS kernel, 64 rows x 128 columns per
+// block, P pre-split into bf16 pieces.
 struct KvPlan {
   bool reg;
   int cf, f;
@@ -541,13 +665,13 @@ struct KvPlan {
   size_t prep_elems;  // float elements of the prepared P
 };
 
-KvPlan kv_plan(int64_t n, int64_t k) {
+KvPlan kv_plan(int64_t n, int64_t k, int mode) {
   KvPlan p{};
   const int64_t npad = cdiv(n, 256) * 256;
   p.reg = k <= 64;
   if (p.reg) {
     p.cf = k <= 16 ? 1 : k <= 32 ? 2 : 4;
-    p.f = p.cf == 4 ? 2 : 4;
+    p.f = mode == RBF_GRAM_F32 && p.cf < 4 ? 4 : 2;
     p.nc = 16 * p.cf;
     p.rows = 64 * p.f;
   } else {
@@ -558,14 +682,22 @@ KvPlan kv_plan(int64_t n, int64_t k) {
   }
   p.kq = cdiv(k, p.nc) * p.nc;
   p.tiles = cdiv(n, p.rows) * cdiv(k, p.nc);
-  p.prep_elems = p.reg ? (size_t)npad * (size_t)p.kq : 3 * (size_t)p.kq * (size_t)npad / 2;
+  if (p.reg && mode == RBF_GRAM_F32)
+    p.prep_elems = (size_t)npad * (size_t)p.kq;
+  else
+    p.prep_elems = (mode == RBF_GRAM_F32 ? 3 : 2) * (size_t)p.kq * (size_t)npad / 2;
   return p;
 }
 
 size_t rbf_lowp_kv_scratch(int64_t n, int64_t k) {
-  const KvPlan p = kv_plan(n, k);
-  const int64_t nz = cdiv(8 * 256, p.tiles);
-  return p.prep_elems + (nz > 1 ? (size_t)nz * (size_t)n * (size_t)k : 0);
+  size_t m = 0;
+  for (int mode = 0; mode < 2; ++mode) {
+    const KvPlan p = kv_plan(n, k, mode);
+    const int64_t nz = cdiv(8 * 256, p.tiles);
+    const size_t e = p.prep_elems + (nz > 1 ? (size_t)nz * (size_t)n * (size_t)k : 0);
+    m = e > m ? e : m;
+  }
+  return m;
 }
 
 // V += mu_c P
@@ -583,10 +715,9 @@ nys_status rbf_lowp_kv(const RbfLowp& L, int mode, const float* P, int64_t ldp, 
                        int64_t nrhs, float* V, int64_t ldv, float* scratch, size_t scratch_elems, const int* skip,
                        hipStream_t s) {
   const int64_t n = L.n;
-  const KvPlan pl = kv_plan(n, k);
+  const KvPlan pl = kv_plan(n, k, mode);
   const int64_t nc = pl.nc;
-  // the kernels read P prepared once (front of the scratch): zero-padded
-  // float32 for the register kernel, split into bf16 pieces for the LDS kernel
+  // the kernels read P split once into bf16 pieces (front of the scratch)
   const size_t se = pl.prep_elems;
   if (scratch_elems < se) {
     set_error("rbf_lowp_kv: scratch of %zu floats < %zu", scratch_elems, se);
@@ -596,17 +727,21 @@ nys_status rbf_lowp_kv(const RbfLowp& L, int mode, const float* P, int64_t ldp, 
   Lq.kq = pl.kq;
   const uint4* Pq = reinterpret_cast<const uint4*>(scratch);
   const float* Pz = scratch;
-  if (pl.reg) {
+  if (pl.reg && mode == RBF_GRAM_F32) {
     hipLaunchKernelGGL(pad_p, dim3((unsigned)cdiv(L.npad * pl.kq, 256)), dim3(256), 0, s, P, ldp, n, k, L.npad,
                        pl.kq, scratch);
     NYS_CHECK_LAUNCH();
   } else {
     const dim3 sg((unsigned)cdiv(L.npad, 32), (unsigned)cdiv(Lq.kq, 32));
     unsigned short* q = reinterpret_cast<unsigned short*>(scratch);
-    if (mode == 0)
-      hipLaunchKernelGGL(split_p_bf16<2>, sg, dim3(256), 0, s, P, ldp, n, k, Lq.kq, L.npad, q);
-    else
-      hipLaunchKernelGGL(split_p_bf16<3>, sg, dim3(256), 0, s, P, ldp, n, k, Lq.kq, L.npad, q);
+    if (pl.reg) {
+      hipLaunchKernelGGL((split_p_bf16<2, true>), sg, dim3(256), 0, s, P, ldp, n, k, Lq.kq, L.npad, q);
+    } else {
+      if (mode == 0)
+        hipLaunchKernelGGL((split_p_bf16<2, false>), sg, dim3(256), 0, s, P, ldp, n, k, Lq.kq, L.npad, q);
+      else
+        hipLaunchKernelGGL((split_p_bf16<3, false>), sg, dim3(256), 0, s, P, ldp, n, k, Lq.kq, L.npad, q);
+    }
     NYS_CHECK_LAUNCH();
   }
   scratch += se;
@@ -623,18 +758,25 @@ nys_status rbf_lowp_kv(const RbfLowp& L, int mode, const float* P, int64_t ldp, 
   float* dst = nz > 1 ? scratch : V;
   const int64_t ldo = nz > 1 ? k : ldv;
   const float oscale = nz > 1 ? 1.0f : L.scale;
+  const int kss = ks_for(L.ksteps);
   if (pl.reg) {
-#define KR(M, CF, F) \
-  hipLaunchKernelGGL((rbf_kv_reg<M, CF, F>), grid, dim3(256), 0, s, Lq, Pz, pl.kq, k, dst, ldo, pps, oscale, skip)
-    if (mode == 0) {
-      if (pl.cf == 1) KR(0, 1, 4); else if (pl.cf == 2) KR(0, 2, 4); else KR(0, 4, 2);
+#define KR(CF) \
+  hipLaunchKernelGGL((rbf_kv_reg<CF, 2>), grid, dim3(256), 0, s, Lq, Pq, Lq.npad / 8, k, dst, ldo, pps, oscale, skip)
+#define K32(CF, F, KS) \
+  hipLaunchKernelGGL((rbf_kv_reg32<CF, F, KS>), grid, dim3(256), 0, s, Lq, Pz, pl.kq, k, dst, ldo, pps, oscale, skip)
+#define K32S(CF, F) \
+  do { if (kss == 2) K32(CF, F, 2); else if (kss == 4) K32(CF, F, 4); else K32(CF, F, 8); } while (0)
+    if (mode == RBF_GRAM_BF16X3) {
+      if (pl.cf == 1) KR(1); else if (pl.cf == 2) KR(2); else KR(4);
     } else {
-      if (pl.cf == 1) KR(1, 1, 4); else if (pl.cf == 2) KR(1, 2, 4); else KR(1, 4, 2);
+      if (pl.cf == 1) K32S(1, 4); else if (pl.cf == 2) K32S(2, 4); else K32S(4, 2);
     }
+#undef K32S
+#undef K32
 #undef KR
   } else {
-#define KV(M, CF) hipLaunchKernelGGL((rbf_kv_lowp<M, CF>), grid, dim3(256), 0, s, Lq, P, ldp, k, Pq, Lq.npad / 8, dst, ldo, pps, oscale, skip)
-    if (mode == 0) KV(0, 8); else KV(1, 8);
+#define KV(M, KS) hipLaunchKernelGGL((rbf_kv_lowp<M, 8, KS>), grid, dim3(256), 0, s, Lq, P, ldp, k, Pq, Lq.npad / 8, dst, ldo, pps, oscale, skip)
+    if (mode == 0) KV(0, 1); else if (kss == 2) KV(1, 2); else if (kss == 4) KV(1, 4); else KV(1, 8);
 #undef KV
   }
   NYS_CHECK_LAUNCH();
