@@ -19,6 +19,12 @@ Pinned parts (tests/test_oracle_*.py):
                       iteration counts for rank(A) < l and rank(A) = l,
                       CG iteration bound with the exact condition number
   power            -- power estimate against the exact spectral norm of E
+  adaptive         -- the base algorithm when no doubling is allowed, the closed
+                      form of the Nystrom approximation on the concatenated test
+                      matrix, the first doubling stage whose exact ||E|| meets the
+                      tolerance, the l_max cap, Strategy 2's stopping stage, and
+                      the theorem's bound on the final sketch size (frequency
+                      over seeds)
   grad             -- central finite differences of dense solves and a closed form
   philox           -- Random123 known-answer vectors
 Parity unpinned: none of the functions above is unpinned; the mixed-precision
@@ -26,9 +32,10 @@ forms have no oracle of their own (they are judged by this FP64 oracle's true
 residual).
 """
 from .operators import DenseOp, XtXOp, RBFOp, rbf_kernel_block  # noqa: F401
-from .nystrom import orthonormalize, matlab_eps, randomized_nystrom  # noqa: F401
+from .nystrom import orthonormalize, matlab_eps, randomized_nystrom, nystrom_factor  # noqa: F401
 from .precond import precond_inv_apply, precond_matrix, precond_inv_matrix  # noqa: F401
 from .pcg import nystrom_pcg, true_relres, dense_solve  # noqa: F401
 from .power import rand_pow_err_est  # noqa: F401
+from .adaptive import ada_rand_nystrom, effective_dimension  # noqa: F401
 from .grad import adjoint_gradients  # noqa: F401
 from .philox import philox4x32_10, gaussian_philox  # noqa: F401

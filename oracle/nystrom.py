@@ -56,8 +56,14 @@ def randomized_nystrom(op, omega0: np.ndarray, shift: str = "fro", use_qr: bool 
     ``nu`` fixes the shift instead of computing it (used by tests that make the
     shift large enough to observe)."""
     Omega = orthonormalize(omega0) if use_qr else np.asarray(omega0, dtype=np.float64)
-    n = Omega.shape[0]
     Y = op.matmat(Omega)
+    return nystrom_factor(Omega, Y, shift=shift, max_retry=max_retry, nu=nu)
+
+
+def nystrom_factor(Omega: np.ndarray, Y: np.ndarray, shift: str = "fro", max_retry: int = 3, nu=None) -> dict:
+    """Steps 4-9 of the algorithm on a given test matrix Omega and sketch
+    Y = A Omega (the adaptive variant calls them on concatenated sketches)."""
+    n = Omega.shape[0]
     if nu is not None:
         nu = float(nu)
     elif shift == "fro":
