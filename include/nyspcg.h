@@ -224,6 +224,59 @@ nys_status nys_rbf_cross(const nys_operator* A, const void* Xv, int64_t nv, int6
                          int32_t transpose, const double* v, double* out, const double* wvec,
                          double* dsig_out, void* ws, size_t ws_bytes, void* stream);
 
+/* ---- Adaptive rank selection (Section "Adaptive rank selection") ---- */
+
+/* Stopping criteria of nys_nystrom_adaptive. */
+typedef enum {
+  NYS_ADA_ERR = 0,      /* Strategy 1: estimate of ||E|| <= tau mu                   */
+  NYS_ADA_ERR_LAM = 1,  /* Strategy 1 with the theorem's second condition:
+                           ||E|| estimate <= tau mu and lam_l <= tau mu / 11        */
+  NYS_ADA_RATIO = 2     /* Strategy 2: lam_l <= tau mu (no power estimate)           */
+} nys_ada_criterion;
+
+/* Bytes of workspace for nys_nystrom_adaptive with sketch sizes up to ell_max
+ * (also enough for nys_power_err_est with P->ell <= ell_max). */
+size_t nys_workspace_size_adaptive(const nys_operator* A, int64_t ell_max, int32_t prec);
+
+/* Randomized power estimate of ||E||, E = A - U diag(lam) U^T (Appendix,
+ * algorithm "Randomized Power method for estimating ||E||"):
+ *   v0 = g / ||g||; q times: v = A v0 - U (lam .* (U^T v0)), E = v0^T v,
+ *   v0 = v / ||v||.
+ * g: device float64 n, the random start vector (an input; nys_gaussian draws
+ * one).  *est (host) receives the last E, a lower bound of ||E|| that
+ * approaches it as q grows.  prec: NYS_PREC_FP64 forms A v0 in float64; the
+ * other modes form it as nys_op_apply does in that mode (from a float32 copy of
+ * v0); everything else is float64.  ws: nys_workspace_size_adaptive(A, P->ell,
+ * prec) bytes suffice.  Errors: NYS_ERR_ARG (q < 1, shapes).  Synchronises. */
+nys_status nys_power_err_est(const nys_operator* A, const nys_precond* P, int32_t q, const double* g,
+                             double* est, int32_t prec, void* ws, size_t ws_bytes, void* stream);
+
+/* Adaptive randomized Nystrom approximation (Appendix, algorithm "Adaptive
+ * Randomized Nystrom Approximation"; Strategy 2 with criterion NYS_ADA_RATIO).
+ * Starting from ell0 columns, the sketch size doubles (each new block of test
+ * columns is drawn, orthonormalised on its own and sketched; the earlier
+ * blocks and their sketch are kept) until the criterion holds with
+ * tol = tau mu; a doubling past ell_max is cut to ell_max, and that last
+ * approximation is returned without an estimate.  Every stage is factored as
+ * nys_factor does.  Random draws: block j (j = 0, 1, ...) is
+ * nys_gaussian(seed + 2j), the start vector of the j-th estimate
+ * nys_gaussian(seed + 2j + 1, n, 1).
+ * Omega, Y: device float64 n x ld (ld >= ell_max), written: on return their
+ *   first P->ell columns hold the accepted test matrix and sketch.
+ * P: caller sets n, U (capacity n x ldu, ldu >= ell_max), ldu, dtype and lam
+ *   (capacity ell_max); the call sets P->ell (the chosen sketch size), P->nu
+ *   and fills U, lam.
+ * *err_out (host): the estimate of ||E|| for the returned approximation (NaN
+ *   for NYS_ADA_RATIO and when ell_max was reached).
+ * Returns NYS_OK when the criterion held, NYS_NOT_CONVERGED when ell_max was
+ * reached first (U, lam then hold the rank-ell_max approximation), or an
+ * error of nys_sketch / nys_factor.  ws: nys_workspace_size_adaptive(A,
+ * ell_max, prec) bytes.  Synchronises the stream. */
+nys_status nys_nystrom_adaptive(const nys_operator* A, int64_t ell0, int64_t ell_max, int32_t q, double tau,
+                                double mu, int32_t criterion, uint64_t seed, double* Omega, double* Y,
+                                int64_t ld, nys_precond* P, double* err_out, int32_t prec, void* ws,
+                                size_t ws_bytes, void* stream);
+
 /* Message for the last non-OK status returned on this thread. */
 const char* nys_last_error(void);
 

@@ -24,10 +24,12 @@ NYS_ERR_ARG, NYS_ERR_NOT_PSD, NYS_ERR_BREAKDOWN, NYS_ERR_DEVICE, NYS_ERR_WORKSPA
 NYS_F64, NYS_F32 = 0, 1
 NYS_PREC_FP64, NYS_PREC_FP32, NYS_PREC_FP32_REFINE64, NYS_PREC_BF16X3_REFINE64 = 0, 1, 2, 3
 NYS_OP_DENSE, NYS_OP_XTX, NYS_OP_RBF = 0, 1, 2
+NYS_ADA_ERR, NYS_ADA_ERR_LAM, NYS_ADA_RATIO = 0, 1, 2
 
 EXPORTED = ["nys_workspace_size", "nys_gaussian", "nys_sketch", "nys_factor", "nys_op_apply",
             "nys_precond_apply", "nys_pcg_solve", "nys_workspace_size_ragged", "nys_pcg_solve_ragged",
-            "nys_pcg_backward", "nys_rbf_cross", "nys_last_error", "nys_version"]
+            "nys_pcg_backward", "nys_rbf_cross", "nys_workspace_size_adaptive", "nys_power_err_est",
+            "nys_nystrom_adaptive", "nys_last_error", "nys_version"]
 
 
 class NysError(RuntimeError):
@@ -88,8 +90,14 @@ def lib():
         L.nys_pcg_backward.argtypes = [P(_Operator), P(_Precond), dbl, vp, vp, vp, P(dbl), P(dbl), vp,
                                        P(_Opts), P(_Info), vp, sz, vp]
         L.nys_rbf_cross.argtypes = [P(_Operator), vp, i64, i64, i32, vp, vp, vp, P(dbl), vp, sz, vp]
+        L.nys_workspace_size_adaptive.restype = sz
+        L.nys_workspace_size_adaptive.argtypes = [P(_Operator), i64, i32]
+        L.nys_power_err_est.argtypes = [P(_Operator), P(_Precond), i32, vp, P(dbl), i32, vp, sz, vp]
+        L.nys_nystrom_adaptive.argtypes = [P(_Operator), i64, i64, i32, dbl, dbl, i32, ctypes.c_uint64, vp, vp,
+                                           i64, P(_Precond), P(dbl), i32, vp, sz, vp]
         for f in ("nys_gaussian", "nys_sketch", "nys_factor", "nys_op_apply", "nys_precond_apply",
-                  "nys_pcg_solve", "nys_pcg_solve_ragged", "nys_pcg_backward", "nys_rbf_cross"):
+                  "nys_pcg_solve", "nys_pcg_solve_ragged", "nys_pcg_backward", "nys_rbf_cross",
+                  "nys_power_err_est", "nys_nystrom_adaptive"):
             getattr(L, f).restype = ctypes.c_int
         L.nys_last_error.restype = ctypes.c_char_p
         L.nys_version.restype = ctypes.c_char_p
@@ -220,6 +228,51 @@ def nys_factor(Omega: torch.Tensor, Y: torch.Tensor, dtype=torch.float64,
         ws = _ws_shape(n, ell, 1, Y.device) if op is None else workspace(op, ell)
     _check(lib().nys_factor(_ptr(Omega), _ptr(Y), ctypes.byref(p), prec, _ptr(ws), ws.numel(), _stream()))
     return Precond(U, lam, p.nu)
+
+
+def workspace_adaptive(op: Operator, ell_max: int, prec: int = NYS_PREC_FP64) -> torch.Tensor:
+    nb = lib().nys_workspace_size_adaptive(ctypes.byref(op.c()), ell_max, prec)
+    if nb == 0:
+        raise NysError(NYS_ERR_ARG, "invalid operator for workspace sizing")
+    return torch.empty(nb, dtype=torch.uint8, device=op.data.device)
+
+
+def nys_power_err_est(op: Operator, P: Precond, q: int, g: Optional[torch.Tensor] = None, seed: int = 0,
+                      prec: int = NYS_PREC_FP64, ws: Optional[torch.Tensor] = None) -> float:
+    """Randomized power estimate of ||A - U diag(lam) U^T|| after q steps from
+    the start vector g (drawn with nys_gaussian(seed, n, 1) when None)."""
+    if g is None:
+        g = nys_gaussian(seed, op.n, 1, device=op.data.device)
+    g = g.to(device=op.data.device, dtype=torch.float64).contiguous()
+    w = ws if ws is not None else workspace_adaptive(op, P.U.shape[1], prec)
+    est = ctypes.c_double(0.0)
+    _check(lib().nys_power_err_est(ctypes.byref(op.c()), ctypes.byref(P.c()), q, _ptr(g), ctypes.byref(est), prec,
+                                   _ptr(w), w.numel(), _stream()))
+    return est.value
+
+
+def nys_nystrom_adaptive(op: Operator, ell0: int, ell_max: int, mu: float, tau: float = 44.0, q: int = 10,
+                         criterion: int = NYS_ADA_ERR, seed: int = 0, prec: int = NYS_PREC_FP64,
+                         dtype=torch.float64, ws: Optional[torch.Tensor] = None):
+    """Adaptive rank selection: doubles the sketch size from ell0 until the
+    criterion holds with tol = tau * mu (or ell_max is reached).  Returns
+    (Precond, info) with info = {"ell", "err", "capped", "Omega", "Y"}."""
+    dev = op.data.device
+    n = op.n
+    Om = torch.empty(n, ell_max, dtype=torch.float64, device=dev)
+    Y = torch.empty(n, ell_max, dtype=torch.float64, device=dev)
+    U = torch.empty(n, ell_max, dtype=dtype, device=dev)
+    lam = torch.empty(ell_max, dtype=torch.float64, device=dev)
+    p = _Precond(n, ell_max, _ptr(U), ell_max, NYS_F64 if dtype == torch.float64 else NYS_F32, 0, _ptr(lam), 0.0)
+    w = ws if ws is not None else workspace_adaptive(op, ell_max, prec)
+    err = ctypes.c_double(0.0)
+    st = _check(lib().nys_nystrom_adaptive(ctypes.byref(op.c()), ell0, ell_max, q, float(tau), float(mu), criterion,
+                                           seed, _ptr(Om), _ptr(Y), ell_max, ctypes.byref(p), ctypes.byref(err),
+                                           prec, _ptr(w), w.numel(), _stream()), allow_not_converged=True)
+    ell = int(p.ell)
+    P = Precond(U[:, :ell].contiguous(), lam[:ell].clone(), p.nu)
+    return P, {"ell": ell, "err": err.value, "capped": st == NYS_NOT_CONVERGED,
+               "Omega": Om[:, :ell], "Y": Y[:, :ell]}
 
 
 def nys_op_apply(op: Operator, mu: float, V: torch.Tensor, ws: Optional[torch.Tensor] = None,
