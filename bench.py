@@ -11,7 +11,8 @@ Cholesky + SVD factorisation, PCG to 1e-10.
 Other workloads (--workload): krr_small (n = 2048, d = 8, l = 100, float64),
 krr (n = 1e5, d = 32, l = 1000, bf16x3 Gram tiles + refinement), batched
 (one RBF sketch, 32 mu x 8 right-hand sides, plus 64 ragged ridge problems),
-diff (validation-loss gradient through the RBF solve).
+diff (validation-loss gradient through the RBF solve), adaptive (the ridge
+system with the sketch size chosen by adaptive rank selection).
 
 python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
                 [--no-plain] [--no-cpu-baseline]
@@ -69,7 +70,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="ridge",
-                    choices=["ridge", "krr_small", "krr", "batched", "diff"])
+                    choices=["ridge", "krr_small", "krr", "batched", "diff", "adaptive"])
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--matvec-reps", type=int, default=30)
@@ -238,6 +239,79 @@ def run_ridge_kernel(args, nys, torch):
     return {"kernel": "xtx_fused<float,float> + reduce_cols", "avg_ms": mv_ms, "reps": args.matvec_reps + 2,
             "alg_bytes": m * n * 4 + 2 * n * 4, "copy_bytes_each_way": src.numel() * 4, "copy_avg_ms": cp_ms,
             "copy_reps": 12}
+
+
+# --------------------------------------------------------------------------- adaptive rank
+
+def run_adaptive(args, nys, torch):
+    """The ridge system with l chosen by adaptive rank selection (Strategy 1
+    with the theorem's two conditions, tau = 44 as in its corollary, q = 10
+    power steps), l0 = 64 doubling up to l_max = 2048, then the PCG solve."""
+    from workloads import ridge_dense
+    dev = "cuda:0"
+    m, n = 20000, (args.n or 4000)
+    l0, lmax, tau, q = 64, min(2048, n), 44.0, 10
+    w = ridge_dense(m=m, n=n, ell=8, with_omega=False)
+    X32h = w["X"]
+    b_h = X32h.astype(np.float64).T @ w["y"]
+    mu, tol = w["mu"], 1e-10
+    op = nys.Operator.xtx(torch.as_tensor(X32h, device=dev))
+    b = torch.as_tensor(b_h, device=dev)
+    prec = nys.NYS_PREC_BF16X3_REFINE64
+    wsa = nys.workspace_adaptive(op, lmax, prec)
+    kw = dict(maxit=1000, inner_tol=args.inner_tol or 3e-6)
+    wss = {}
+
+    def step(seed):
+        tm = Timer(torch)
+        t = time.perf_counter()
+        P, info = nys.nys_nystrom_adaptive(op, l0, lmax, mu, tau=tau, q=q, criterion=nys.NYS_ADA_ERR_LAM,
+                                           seed=seed, prec=prec, dtype=torch.float32, ws=wsa)
+        t = tm.lap("adaptive_nystrom", t)
+        ell = info["ell"]
+        if ell not in wss:
+            wss[ell] = nys.workspace(op, ell, 1, prec)
+        X, sinfo = nys.nys_pcg_solve(op, P, mu, b, tol=tol, prec=prec, ws=wss[ell], **kw)
+        tm.lap("pcg", t)
+        return info, sinfo, tm
+
+    for i in range(args.warmup):
+        step(1000 + i)
+    t = time.perf_counter()
+    runs = []
+    for i in range(args.steps):
+        info, sinfo, tm = step(20211002 + i)
+        runs.append((info, sinfo, tm))
+        log("adaptive step %d: l=%d E=%.3e capped=%s iters %d relres %.2e %s" %
+            (i, info["ell"], info["err"], info["capped"], sinfo.iters[0], sinfo.relres[0],
+             {k: round(1e3 * v, 2) for k, v in tm.t.items()}))
+    el = time.perf_counter() - t
+    out = base_record(
+        args, args.steps / el, 1e3 * el / args.steps, "bf16x3+f32+f64",
+        {"workload": "ridge regression A = X^T X, X %dx%d float32 = G diag(j^-1/2), mu=1e-4, b = X^T y, tol 1e-10; "
+                     "l by adaptive rank selection: l0=%d doubling to l_max=%d until ||E|| <= tau mu and "
+                     "lam_l <= tau mu / 11, tau=%g, q=%d power steps" % (m, n, l0, lmax, tau, q),
+         "precision": "sketch products on bf16 MFMA (hi/lo split), float32 power-step products and inner PCG, "
+                      "float64 refinement and core factorisations",
+         "step": "adaptive sketch/factor/estimate stages + PCG solve"},
+        {"correct": all(s.relres[0] <= tol and s.status[0] == 0 for _, s, _ in runs),
+         "ell": runs[-1][0]["ell"], "err_estimate": runs[-1][0]["err"], "capped": runs[-1][0]["capped"],
+         "iters": runs[-1][1].iters[0], "refine_steps": runs[-1][1].refine_steps,
+         "phase_ms": {k: 1e3 * sum(r[2].t.get(k, 0.0) for r in runs) / args.steps for k in runs[0][2].t}})
+    if not args.no_cpu_baseline:
+        import oracle
+        opr = oracle.XtXOp(X32h)
+        db = lambda j, mm: oracle.gaussian_philox(7 + 2 * j, n, mm)
+        dg = lambda j: oracle.gaussian_philox(8 + 2 * j, n, 1)[:, 0]
+        t = time.perf_counter()
+        r = oracle.ada_rand_nystrom(opr, l0, lmax, q, tau, mu, db, dg, criterion="err_lam")
+        o = oracle.nystrom_pcg(opr.matmat, b_h, mu, lambda v: oracle.precond_inv_apply(r["U"], r["lam"], mu, v),
+                               tol=tol, maxit=1000)
+        el = time.perf_counter() - t
+        out["cpu_baseline"] = {"value": 1.0 / el, "unit": "solves/s", "cores": cores_used(), "kind": "oracle",
+                               "sample": "one full adaptive solve of the same workload (stages + PCG to 1e-10), "
+                                         "numpy float64", "seconds": el, "ell": r["ell"], "iters": o["iters"]}
+    return out
 
 
 # --------------------------------------------------------------------------- RBF helpers
@@ -495,7 +569,7 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     fn = {"ridge": run_ridge_kernel if args.kernel_only else run_ridge, "krr_small": lambda a, n, t: run_krr(a, n, t, small=True), "krr": run_krr,
-          "batched": run_batched, "diff": run_diff}[args.workload]
+          "batched": run_batched, "diff": run_diff, "adaptive": run_adaptive}[args.workload]
     out = fn(args, nys, torch)
     print(json.dumps(out), flush=True)
 
