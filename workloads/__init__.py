@@ -15,6 +15,7 @@ l = 1000); no dataset item is reproduced.
 """
 from .synth import (  # noqa: F401
     gaussian_test_matrix,
+    column_sample,
     krr_small,
     ridge_dense,
     krr_mixture,

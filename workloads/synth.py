@@ -14,6 +14,12 @@ def gaussian_test_matrix(n: int, ell: int, seed: int) -> np.ndarray:
     return rng.standard_normal((n, ell))
 
 
+def column_sample(n: int, ell: int, seed: int) -> np.ndarray:
+    """ell distinct column indices drawn uniformly from 0..n-1 (int64)."""
+    rng = np.random.default_rng(seed)
+    return rng.choice(n, size=ell, replace=False).astype(np.int64)
+
+
 def krr_small(n: int = 2048, d: int = 8, ell: int = 100, seed: int = 20211001) -> dict:
     """Kernel ridge regression, small: points i.i.d. N(0, I_d), sigma = sqrt(d).
 
