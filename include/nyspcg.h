@@ -224,6 +224,27 @@ nys_status nys_rbf_cross(const nys_operator* A, const void* Xv, int64_t nv, int6
                          int32_t transpose, const double* v, double* out, const double* wvec,
                          double* dsig_out, void* ws, size_t ws_bytes, void* stream);
 
+/* ---- Sketch from sampled columns (Section "Random projection versus
+ * column sampling"; the paper's kernel ridge regression experiments) ---- */
+
+/* Bytes of workspace for nys_sketch_columns with ell sampled columns. */
+size_t nys_workspace_size_columns(const nys_operator* A, int64_t ell);
+
+/* Column-sampling sketch: Omega = I[:, S] (a test matrix with 1-sparse
+ * columns; already orthonormal, so the QR step of the base algorithm leaves
+ * it as it is) and Y = A Omega = A[:, S], for the ell indices S = idx
+ * (device int64, distinct, in [0, n); drawn by the caller, e.g. uniformly
+ * without replacement).  RBF operators evaluate the ell kernel columns
+ * directly (O(n ell d) work instead of ell products), dense operators gather
+ * them, X^T X operators form scale X^T X[:, S] with one GEMM.  All float64
+ * (float32 operator data is promoted exactly).  Omega_out, Y_out: device
+ * float64 n x ell (ld = ell); pass them to nys_factor (prec NYS_PREC_FP64) to
+ * complete the approximation.  Errors: NYS_ERR_ARG (indices out of range or
+ * repeated, ell outside [1, n], bad operator).  Synchronises the stream once
+ * (index check). */
+nys_status nys_sketch_columns(const nys_operator* A, int64_t ell, const int64_t* idx, double* Omega_out,
+                              double* Y_out, void* ws, size_t ws_bytes, void* stream);
+
 /* ---- Adaptive rank selection (Section "Adaptive rank selection") ---- */
 
 /* Stopping criteria of nys_nystrom_adaptive. */

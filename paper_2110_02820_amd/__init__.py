@@ -29,7 +29,8 @@ NYS_ADA_ERR, NYS_ADA_ERR_LAM, NYS_ADA_RATIO = 0, 1, 2
 EXPORTED = ["nys_workspace_size", "nys_gaussian", "nys_sketch", "nys_factor", "nys_op_apply",
             "nys_precond_apply", "nys_pcg_solve", "nys_workspace_size_ragged", "nys_pcg_solve_ragged",
             "nys_pcg_backward", "nys_rbf_cross", "nys_workspace_size_adaptive", "nys_power_err_est",
-            "nys_nystrom_adaptive", "nys_last_error", "nys_version"]
+            "nys_nystrom_adaptive", "nys_workspace_size_columns", "nys_sketch_columns", "nys_last_error",
+            "nys_version"]
 
 
 class NysError(RuntimeError):
@@ -95,9 +96,12 @@ def lib():
         L.nys_power_err_est.argtypes = [P(_Operator), P(_Precond), i32, vp, P(dbl), i32, vp, sz, vp]
         L.nys_nystrom_adaptive.argtypes = [P(_Operator), i64, i64, i32, dbl, dbl, i32, ctypes.c_uint64, vp, vp,
                                            i64, P(_Precond), P(dbl), i32, vp, sz, vp]
+        L.nys_workspace_size_columns.restype = sz
+        L.nys_workspace_size_columns.argtypes = [P(_Operator), i64]
+        L.nys_sketch_columns.argtypes = [P(_Operator), i64, vp, vp, vp, vp, sz, vp]
         for f in ("nys_gaussian", "nys_sketch", "nys_factor", "nys_op_apply", "nys_precond_apply",
                   "nys_pcg_solve", "nys_pcg_solve_ragged", "nys_pcg_backward", "nys_rbf_cross",
-                  "nys_power_err_est", "nys_nystrom_adaptive"):
+                  "nys_power_err_est", "nys_nystrom_adaptive", "nys_sketch_columns"):
             getattr(L, f).restype = ctypes.c_int
         L.nys_last_error.restype = ctypes.c_char_p
         L.nys_version.restype = ctypes.c_char_p
@@ -228,6 +232,24 @@ def nys_factor(Omega: torch.Tensor, Y: torch.Tensor, dtype=torch.float64,
         ws = _ws_shape(n, ell, 1, Y.device) if op is None else workspace(op, ell)
     _check(lib().nys_factor(_ptr(Omega), _ptr(Y), ctypes.byref(p), prec, _ptr(ws), ws.numel(), _stream()))
     return Precond(U, lam, p.nu)
+
+
+def nys_sketch_columns(op: Operator, idx, ws: Optional[torch.Tensor] = None):
+    """Column-sampling sketch: Omega = I[:, idx], Y = A[:, idx] (float64).
+    idx: ell distinct indices (any int sequence or tensor)."""
+    dev = op.data.device
+    idx_t = torch.as_tensor(idx, dtype=torch.int64).to(dev).contiguous()
+    ell = idx_t.numel()
+    Om = torch.empty(op.n, ell, dtype=torch.float64, device=dev)
+    Y = torch.empty(op.n, ell, dtype=torch.float64, device=dev)
+    if ws is None:
+        nb = lib().nys_workspace_size_columns(ctypes.byref(op.c()), ell)
+        if nb == 0:
+            raise NysError(NYS_ERR_ARG, "invalid operator for workspace sizing")
+        ws = torch.empty(nb, dtype=torch.uint8, device=dev)
+    _check(lib().nys_sketch_columns(ctypes.byref(op.c()), ell, _ptr(idx_t), _ptr(Om), _ptr(Y), _ptr(ws),
+                                    ws.numel(), _stream()))
+    return Om, Y
 
 
 def workspace_adaptive(op: Operator, ell_max: int, prec: int = NYS_PREC_FP64) -> torch.Tensor:
