@@ -70,7 +70,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="ridge",
-                    choices=["ridge", "krr_small", "krr", "batched", "diff", "adaptive"])
+                    choices=["ridge", "krr_small", "krr", "krr_cols", "batched", "diff", "adaptive"])
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--matvec-reps", type=int, default=30)
@@ -97,11 +97,18 @@ class Timer:
         return t1
 
 
-def full_solve(nys, torch, op, ell, seed, prec, udtype, mus, B, ws, tol, timer, **kw):
+def full_solve(nys, torch, op, ell, seed, prec, udtype, mus, B, ws, tol, timer, cols=None, **kw):
+    """cols = (device index tensor, workspace): column-sampling sketch instead
+    of the Gaussian one (its Y is float64, so the factor takes the float64 shift)."""
     t = time.perf_counter()
-    Om, Y = nys.nys_sketch(op, ell, seed=seed, prec=prec, ws=ws)
+    if cols is None:
+        Om, Y = nys.nys_sketch(op, ell, seed=seed, prec=prec, ws=ws)
+        fprec = prec
+    else:
+        Om, Y = nys.nys_sketch_columns(op, cols[0], ws=cols[1])
+        fprec = nys.NYS_PREC_FP64
     t = timer.lap("sketch", t)
-    P = nys.nys_factor(Om, Y, dtype=udtype, ws=ws, prec=prec)
+    P = nys.nys_factor(Om, Y, dtype=udtype, ws=ws, prec=fprec)
     del Om, Y
     t = timer.lap("factor", t)
     X, info = nys.nys_pcg_solve(op, P, mus, B, tol=tol, prec=prec, ws=ws, **kw)
@@ -345,8 +352,8 @@ def rbf_cpu_sample(w, ell, nvec=1):
     return t_sk, t_mv
 
 
-def run_krr(args, nys, torch, small=False):
-    from workloads import krr_mixture, krr_small
+def run_krr(args, nys, torch, small=False, columns=False):
+    from workloads import column_sample, krr_mixture, krr_small
     dev = "cuda:0"
     if small:
         n, d, ell = (args.n or 2048), 8, 100
@@ -366,14 +373,24 @@ def run_krr(args, nys, torch, small=False):
     op = nys.Operator.rbf(X, w["sigma"])
     b = rbf_rhs(nys, torch, op, w, dev)
     ws = nys.workspace(op, ell, 1, prec)
+    # column sampling: the index sets are inputs, drawn and uploaded before the timed steps
+    cols = {}
+    if columns:
+        import ctypes
+        wsc = torch.empty(nys.lib().nys_workspace_size_columns(ctypes.byref(op.c()), ell), dtype=torch.uint8,
+                          device=dev)
+        for sd in [1000 + i for i in range(args.warmup)] + [20211003 + i for i in range(args.steps)]:
+            cols[sd] = (torch.as_tensor(column_sample(n, ell, sd), device=dev), wsc)
     for i in range(args.warmup):
-        full_solve(nys, torch, op, ell, 1000 + i, prec, udtype, mu, b, ws, tol, Timer(torch), **kw)
+        full_solve(nys, torch, op, ell, 1000 + i, prec, udtype, mu, b, ws, tol, Timer(torch),
+                   cols=cols.get(1000 + i), **kw)
     tm = Timer(torch)
     infos = []
     t = time.perf_counter()
     for i in range(args.steps):
         a = time.perf_counter()
-        _, info, _ = full_solve(nys, torch, op, ell, 20211003 + i, prec, udtype, mu, b, ws, tol, tm, **kw)
+        _, info, _ = full_solve(nys, torch, op, ell, 20211003 + i, prec, udtype, mu, b, ws, tol, tm,
+                                cols=cols.get(20211003 + i), **kw)
         infos.append(info)
         log("krr step %d: %.1f ms iters %d refine %d relres %.2e" % (i, 1e3 * (time.perf_counter() - a),
                                                                      info.iters[0], info.refine_steps,
@@ -399,15 +416,16 @@ def run_krr(args, nys, torch, small=False):
                 "kernel": "rbf_mv_lowp<bf16x3>: one v_exp_f32 per kernel entry", "avg_ms": mv_ms}
     out = base_record(
         args, args.steps / el, 1e3 * el / args.steps, label,
-        {"workload": ("kernel ridge regression, RBF n=%d d=%d sigma=sqrt(d), mu=%g, l=%d, tol 1e-10"
-                      % (n, d, mu, ell)),
+        {"workload": ("kernel ridge regression, RBF n=%d d=%d sigma=sqrt(d), mu=%g, l=%d, tol 1e-10%s"
+                      % (n, d, mu, ell, "; sketch from l uniformly sampled kernel columns" if columns else "")),
          "precision": "float64" if small else "bf16x3 Gram tiles on MFMA, float32 inner PCG, float64 refinement",
-         "step": "Gaussian Omega + sketch + factor + PCG solve"},
+         "step": ("sampled kernel columns" if columns else "Gaussian Omega + sketch") +
+                 " + factor + PCG solve"},
         {"correct": all(i.relres[0] <= tol and i.status[0] == 0 for i in infos),
          "relres": max(i.relres[0] for i in infos), "iters": infos[-1].iters[0],
          "refine_steps": infos[-1].refine_steps,
          "phase_ms": {k: 1e3 * v / args.steps for k, v in tm.t.items()}, "roofline": roof})
-    if not args.no_plain and not small:
+    if not args.no_plain and not small and not columns:
         ws64 = nys.workspace(op, ell, 1, nys.NYS_PREC_FP64)
         tm64 = Timer(torch)
         t = time.perf_counter()
@@ -421,12 +439,18 @@ def run_krr(args, nys, torch, small=False):
     if not args.no_cpu_baseline:
         t_sk, t_mv = rbf_cpu_sample(w, ell)
         it = infos[-1].total_iters or infos[-1].iters[0]
+        if columns:
+            import oracle
+            t = time.perf_counter()
+            oracle.RBFOp(w["X"], w["sigma"]).rows(column_sample(n, ell, 5))
+            t_sk = time.perf_counter() - t
         est = t_sk + it * t_mv
         out["cpu_baseline"] = {"value": 1.0 / est, "unit": "solves/s", "cores": cores_used(), "kind": "oracle",
-                               "sample": "oracle RBF row block (2048 rows of K) times l columns and times one "
-                                         "column, scaled by n/2048; solve = sketch product + %d PCG products "
-                                         "(the GPU run's count); factorisation not counted, so the CPU figure "
-                                         "is an upper bound" % it,
+                               "sample": ("oracle kernel rows at the l sampled points (the column sketch)"
+                                          if columns else "oracle RBF row block (2048 rows of K) times l columns") +
+                                         " and a 2048-row block times one column, scaled by n/2048; solve = sketch "
+                                         "+ %d PCG products (the GPU run's count); factorisation not counted, so "
+                                         "the CPU figure is an upper bound" % it,
                                "seconds_est": est}
     return out
 
@@ -568,7 +592,9 @@ def main():
     import paper_2110_02820_amd as nys
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
-    fn = {"ridge": run_ridge_kernel if args.kernel_only else run_ridge, "krr_small": lambda a, n, t: run_krr(a, n, t, small=True), "krr": run_krr,
+    fn = {"ridge": run_ridge_kernel if args.kernel_only else run_ridge,
+          "krr_small": lambda a, n, t: run_krr(a, n, t, small=True), "krr": run_krr,
+          "krr_cols": lambda a, n, t: run_krr(a, n, t, columns=True),
           "batched": run_batched, "diff": run_diff, "adaptive": run_adaptive}[args.workload]
     out = fn(args, nys, torch)
     print(json.dumps(out), flush=True)
