@@ -28,6 +28,9 @@ Pinned parts (tests/test_oracle_*.py):
   columns          -- the column Nystrom formula A(:,S) A(S,S)^{-1} A(S,:), exact
                       recovery of a rank-r matrix from r independent columns,
                       interpolation of A on the sampled rows and columns
+  sketch_solve     -- a dense solve of the proxy system (LAPACK), the exact
+                      solution when rank(A) <= l, the theorem's bound on the
+                      expected relative error (mean over seeds)
   grad             -- central finite differences of dense solves and a closed form
   philox           -- Random123 known-answer vectors
 Parity unpinned: none of the functions above is unpinned; the mixed-precision
@@ -41,5 +44,6 @@ from .pcg import nystrom_pcg, true_relres, dense_solve  # noqa: F401
 from .power import rand_pow_err_est  # noqa: F401
 from .adaptive import ada_rand_nystrom, effective_dimension  # noqa: F401
 from .columns import column_nystrom, selection_matrix  # noqa: F401
+from .sketch_solve import nystrom_sketch_solve  # noqa: F401
 from .grad import adjoint_gradients  # noqa: F401
 from .philox import philox4x32_10, gaussian_philox  # noqa: F401
