@@ -245,6 +245,22 @@ size_t nys_workspace_size_columns(const nys_operator* A, int64_t ell);
 nys_status nys_sketch_columns(const nys_operator* A, int64_t ell, const int64_t* idx, double* Omega_out,
                               double* Y_out, void* ws, size_t ws_bytes, void* stream);
 
+/* ---- Nystrom sketch-and-solve (Section "Nystrom sketch-and-solve") ---- */
+
+/* Bytes of workspace for nys_sketch_solve with n x ell U and k columns. */
+size_t nys_workspace_size_sketch_solve(int64_t n, int64_t ell, int64_t k);
+
+/* Solves the proxy system (A_hat + mu I) X = B, A_hat = U diag(lam) U^T, by
+ * the Woodbury form of the lemma on approximate regularized inversion, eq.
+ * (Woodbury): X = U (Lambda + mu I)^{-1} U^T B + (1/mu)(I - U U^T) B.  The
+ * paper's point is that this is NOT a solve of (A + mu I) X = B: its error is
+ * set by how well A_hat approximates A against mu (theorem on sketch-and-solve),
+ * unlike nys_pcg_solve.  B, X: device float64 n x k (ldb, ldx >= k), must not
+ * alias; mu > 0.  U float64 or float32 (promoted).  ws:
+ * nys_workspace_size_sketch_solve(n, ell, k) bytes.  Errors: NYS_ERR_ARG. */
+nys_status nys_sketch_solve(const nys_precond* P, double mu, const double* B, int64_t k, int64_t ldb, double* X,
+                            int64_t ldx, void* ws, size_t ws_bytes, void* stream);
+
 /* ---- Adaptive rank selection (Section "Adaptive rank selection") ---- */
 
 /* Stopping criteria of nys_nystrom_adaptive. */

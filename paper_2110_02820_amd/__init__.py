@@ -29,8 +29,8 @@ NYS_ADA_ERR, NYS_ADA_ERR_LAM, NYS_ADA_RATIO = 0, 1, 2
 EXPORTED = ["nys_workspace_size", "nys_gaussian", "nys_sketch", "nys_factor", "nys_op_apply",
             "nys_precond_apply", "nys_pcg_solve", "nys_workspace_size_ragged", "nys_pcg_solve_ragged",
             "nys_pcg_backward", "nys_rbf_cross", "nys_workspace_size_adaptive", "nys_power_err_est",
-            "nys_nystrom_adaptive", "nys_workspace_size_columns", "nys_sketch_columns", "nys_last_error",
-            "nys_version"]
+            "nys_nystrom_adaptive", "nys_workspace_size_columns", "nys_sketch_columns",
+            "nys_workspace_size_sketch_solve", "nys_sketch_solve", "nys_last_error", "nys_version"]
 
 
 class NysError(RuntimeError):
@@ -99,9 +99,12 @@ def lib():
         L.nys_workspace_size_columns.restype = sz
         L.nys_workspace_size_columns.argtypes = [P(_Operator), i64]
         L.nys_sketch_columns.argtypes = [P(_Operator), i64, vp, vp, vp, vp, sz, vp]
+        L.nys_workspace_size_sketch_solve.restype = sz
+        L.nys_workspace_size_sketch_solve.argtypes = [i64, i64, i64]
+        L.nys_sketch_solve.argtypes = [P(_Precond), dbl, vp, i64, i64, vp, i64, vp, sz, vp]
         for f in ("nys_gaussian", "nys_sketch", "nys_factor", "nys_op_apply", "nys_precond_apply",
                   "nys_pcg_solve", "nys_pcg_solve_ragged", "nys_pcg_backward", "nys_rbf_cross",
-                  "nys_power_err_est", "nys_nystrom_adaptive", "nys_sketch_columns"):
+                  "nys_power_err_est", "nys_nystrom_adaptive", "nys_sketch_columns", "nys_sketch_solve"):
             getattr(L, f).restype = ctypes.c_int
         L.nys_last_error.restype = ctypes.c_char_p
         L.nys_version.restype = ctypes.c_char_p
@@ -232,6 +235,20 @@ def nys_factor(Omega: torch.Tensor, Y: torch.Tensor, dtype=torch.float64,
         ws = _ws_shape(n, ell, 1, Y.device) if op is None else workspace(op, ell)
     _check(lib().nys_factor(_ptr(Omega), _ptr(Y), ctypes.byref(p), prec, _ptr(ws), ws.numel(), _stream()))
     return Precond(U, lam, p.nu)
+
+
+def nys_sketch_solve(P: Precond, mu: float, B: torch.Tensor, ws: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Nystrom sketch-and-solve: (U diag(lam) U^T + mu I)^{-1} B (Woodbury);
+    an approximation of (A + mu I)^{-1} B only as good as A_hat is."""
+    B2 = B.reshape(B.shape[0], -1).to(torch.float64).contiguous()
+    n, k = B2.shape
+    X = torch.empty_like(B2)
+    if ws is None:
+        ws = torch.empty(lib().nys_workspace_size_sketch_solve(n, P.U.shape[1], k), dtype=torch.uint8,
+                         device=B2.device)
+    _check(lib().nys_sketch_solve(ctypes.byref(P.c()), float(mu), _ptr(B2), k, k, _ptr(X), k, _ptr(ws), ws.numel(),
+                                  _stream()))
+    return X.reshape(B.shape)
 
 
 def nys_sketch_columns(op: Operator, idx, ws: Optional[torch.Tensor] = None):
