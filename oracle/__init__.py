@@ -31,6 +31,10 @@ Pinned parts (tests/test_oracle_*.py):
   sketch_solve     -- a dense solve of the proxy system (LAPACK), the exact
                       solution when rank(A) <= l, the theorem's bound on the
                       expected relative error (mean over seeds)
+  block_pcg        -- scipy cg iterates for one column, the Galerkin property of
+                      block CG on the block Krylov space (explicit projection),
+                      termination near ceil(n / s) steps (dimension of the block
+                      Krylov space), a LAPACK solve
   grad             -- central finite differences of dense solves and a closed form
   philox           -- Random123 known-answer vectors
 Parity unpinned: none of the functions above is unpinned; the mixed-precision
@@ -45,5 +49,6 @@ from .power import rand_pow_err_est  # noqa: F401
 from .adaptive import ada_rand_nystrom, effective_dimension  # noqa: F401
 from .columns import column_nystrom, selection_matrix  # noqa: F401
 from .sketch_solve import nystrom_sketch_solve  # noqa: F401
+from .block_pcg import block_nystrom_pcg  # noqa: F401
 from .grad import adjoint_gradients  # noqa: F401
 from .philox import philox4x32_10, gaussian_philox  # noqa: F401
