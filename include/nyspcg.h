@@ -245,6 +245,31 @@ size_t nys_workspace_size_columns(const nys_operator* A, int64_t ell);
 nys_status nys_sketch_columns(const nys_operator* A, int64_t ell, const int64_t* idx, double* Omega_out,
                               double* Y_out, void* ws, size_t ws_bytes, void* stream);
 
+/* ---- Block Nystrom PCG (Section "Block Nystrom PCG") ---- */
+
+/* Bytes of workspace for nys_block_pcg_solve with preconditioner rank ell and
+ * s right-hand sides (1 <= s <= 64; 0 otherwise). */
+size_t nys_workspace_size_block(const nys_operator* A, int64_t ell, int64_t s);
+
+/* Coupled block PCG for (A + mu I) X = B with s right-hand sides sharing mu:
+ * O'Leary's preconditioned block CG recurrences (alpha = (D^T A_mu D)^{-1}
+ * Z^T R, beta = (Z^T R)_old^{-1} (Z^T R)_new, s x s Cholesky solves) with the
+ * Nystrom preconditioner of eq. (NysPre), after Feng, Owen and Peric's
+ * orthogonalisation of B (thin QR B = Q T0 by CholeskyQR2; the block iteration
+ * solves for Q and X = Xt T0).  Unlike nys_pcg_solve, whose columns are
+ * independent, the columns share one block Krylov space.  Float64 only
+ * (o->prec must be NYS_PREC_FP64); X0 = 0 (X is output only).  Stops when
+ * every column's residual (the recursive residual mapped back through T0)
+ * meets o->tol relative to its column of B, checked every o->check_every
+ * iterations (<= 0: every iteration).  B: device float64 n x s (ldb), full
+ * column rank, else NYS_ERR_ARG.  info arrays: s entries (iters = the block's
+ * iteration count).  Returns NYS_OK, NYS_NOT_CONVERGED (cap) or
+ * NYS_ERR_BREAKDOWN (an s x s system lost definiteness before convergence).
+ * Synchronises the stream at every check. */
+nys_status nys_block_pcg_solve(const nys_operator* A, const nys_precond* P, double mu, const double* B, int64_t s,
+                               int64_t ldb, double* X, int64_t ldx, const nys_solve_opts* o, nys_solve_info* info,
+                               void* ws, size_t ws_bytes, void* stream);
+
 /* ---- Nystrom sketch-and-solve (Section "Nystrom sketch-and-solve") ---- */
 
 /* Bytes of workspace for nys_sketch_solve with n x ell U and k columns. */

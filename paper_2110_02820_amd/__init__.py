@@ -30,7 +30,8 @@ EXPORTED = ["nys_workspace_size", "nys_gaussian", "nys_sketch", "nys_factor", "n
             "nys_precond_apply", "nys_pcg_solve", "nys_workspace_size_ragged", "nys_pcg_solve_ragged",
             "nys_pcg_backward", "nys_rbf_cross", "nys_workspace_size_adaptive", "nys_power_err_est",
             "nys_nystrom_adaptive", "nys_workspace_size_columns", "nys_sketch_columns",
-            "nys_workspace_size_sketch_solve", "nys_sketch_solve", "nys_last_error", "nys_version"]
+            "nys_workspace_size_sketch_solve", "nys_sketch_solve", "nys_workspace_size_block",
+            "nys_block_pcg_solve", "nys_last_error", "nys_version"]
 
 
 class NysError(RuntimeError):
@@ -102,9 +103,14 @@ def lib():
         L.nys_workspace_size_sketch_solve.restype = sz
         L.nys_workspace_size_sketch_solve.argtypes = [i64, i64, i64]
         L.nys_sketch_solve.argtypes = [P(_Precond), dbl, vp, i64, i64, vp, i64, vp, sz, vp]
+        L.nys_workspace_size_block.restype = sz
+        L.nys_workspace_size_block.argtypes = [P(_Operator), i64, i64]
+        L.nys_block_pcg_solve.argtypes = [P(_Operator), P(_Precond), dbl, vp, i64, i64, vp, i64, P(_Opts), P(_Info),
+                                          vp, sz, vp]
         for f in ("nys_gaussian", "nys_sketch", "nys_factor", "nys_op_apply", "nys_precond_apply",
                   "nys_pcg_solve", "nys_pcg_solve_ragged", "nys_pcg_backward", "nys_rbf_cross",
-                  "nys_power_err_est", "nys_nystrom_adaptive", "nys_sketch_columns", "nys_sketch_solve"):
+                  "nys_power_err_est", "nys_nystrom_adaptive", "nys_sketch_columns", "nys_sketch_solve",
+                  "nys_block_pcg_solve"):
             getattr(L, f).restype = ctypes.c_int
         L.nys_last_error.restype = ctypes.c_char_p
         L.nys_version.restype = ctypes.c_char_p
@@ -382,6 +388,29 @@ def nys_pcg_solve(op: Operator, P: Precond, mu, B: torch.Tensor, X0: Optional[to
     if B.dim() == 1 and k == 1:
         X = X.reshape(-1)
     return X, si
+
+
+def nys_block_pcg_solve(op: Operator, P: Precond, mu: float, B: torch.Tensor, tol: float = 1e-10, maxit: int = 500,
+                        check_every: int = 0, ws: Optional[torch.Tensor] = None, raise_on_not_converged: bool = False):
+    """Coupled block PCG (O'Leary) for (A + mu I) X = B, float64, s <= 64
+    columns sharing one block Krylov space.  Returns (X, SolveInfo)."""
+    B2 = B.reshape(B.shape[0], -1).contiguous().to(torch.float64)
+    n, s = B2.shape
+    X = torch.empty_like(B2)
+    if ws is None:
+        nb = lib().nys_workspace_size_block(ctypes.byref(op.c()), P.U.shape[1], s)
+        if nb == 0:
+            raise NysError(NYS_ERR_ARG, "block PCG: 1 <= s <= 64 columns and a valid operator are required")
+        ws = torch.empty(nb, dtype=torch.uint8, device=B2.device)
+    it = (ctypes.c_int32 * s)()
+    rr = (ctypes.c_double * s)()
+    st = (ctypes.c_int32 * s)()
+    info = _Info(it, rr, st, 0, 0)
+    o = _opts(tol, maxit, NYS_PREC_FP64, 0, check_every, 0.0)
+    code = lib().nys_block_pcg_solve(ctypes.byref(op.c()), ctypes.byref(P.c()), float(mu), _ptr(B2), s, s, _ptr(X), s,
+                                     ctypes.byref(o), ctypes.byref(info), _ptr(ws), ws.numel(), _stream())
+    _check(code, allow_not_converged=not raise_on_not_converged)
+    return X.reshape(B.shape), SolveInfo(list(it), list(rr), list(st), info.refine_steps, info.total_iters, code)
 
 
 def nys_pcg_solve_ragged(ops: Sequence[Operator], Ps: Sequence[Precond], mus: Sequence[float],
