@@ -14,7 +14,8 @@ krr (n = 1e5, d = 32, l = 1000, bf16x3 Gram tiles + refinement), batched
 diff (validation-loss gradient through the RBF solve), adaptive (the ridge
 system with the sketch size chosen by adaptive rank selection), sketch_solve
 (Nystrom sketch-and-solve on the krr_small system: its accuracy and rate
-against PCG's).
+against PCG's), block (coupled block PCG on 8 right-hand sides of the
+krr_small system against the independent-column solve).
 
 python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
                 [--no-plain] [--no-cpu-baseline]
@@ -73,7 +74,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="ridge",
                     choices=["ridge", "krr_small", "krr", "krr_cols", "batched", "diff", "adaptive",
-                             "sketch_solve"])
+                             "sketch_solve", "block"])
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--matvec-reps", type=int, default=30)
@@ -377,6 +378,63 @@ def run_sketch_solve(args, nys, torch):
          "sketch_and_solve_reaches_tol": any(v["relres"] <= tol for v in res.values())})
 
 
+# --------------------------------------------------------------------------- block PCG
+
+def run_block(args, nys, torch):
+    """Coupled block Nystrom PCG (O'Leary) for 8 right-hand sides sharing mu
+    on the krr_small system (n = 2048, d = 8, l = 100, mu = 1e-3), float64,
+    next to the same 8 columns solved independently (nys_pcg_solve)."""
+    from workloads import krr_small
+    dev = "cuda:0"
+    n, s, ell = (args.n or 2048), 8, 100
+    w = krr_small(n=n, d=8, ell=ell)
+    X = torch.as_tensor(w["X"], dtype=torch.float64, device=dev)
+    op = nys.Operator.rbf(X, w["sigma"])
+    mu, tol = w["mu"], 1e-10
+    B = torch.as_tensor(np.random.default_rng(20211006).standard_normal((n, s)), device=dev)
+    ws = nys.workspace(op, ell, s, nys.NYS_PREC_FP64)
+    import ctypes
+    wsb = torch.empty(nys.lib().nys_workspace_size_block(ctypes.byref(op.c()), ell, s), dtype=torch.uint8,
+                      device=dev)
+
+    def one(seed, block, tm):
+        t = time.perf_counter()
+        Om, Y = nys.nys_sketch(op, ell, seed=seed, ws=ws)
+        P = nys.nys_factor(Om, Y, ws=ws)
+        t = tm.lap("sketch_factor", t)
+        if block:
+            Xs, info = nys.nys_block_pcg_solve(op, P, mu, B, tol=tol, maxit=5000, ws=wsb)
+        else:
+            Xs, info = nys.nys_pcg_solve(op, P, mu, B, tol=tol, maxit=5000, ws=ws)
+        tm.lap("pcg", t)
+        return Xs, info
+
+    out = {}
+    for block in (True, False):
+        for i in range(args.warmup):
+            one(1000 + i, block, Timer(torch))
+        tm = Timer(torch)
+        t = time.perf_counter()
+        for i in range(args.steps):
+            Xs, info = one(20211001 + i, block, tm)
+        el = time.perf_counter() - t
+        R = B - nys.nys_op_apply(op, mu, Xs)
+        rel = (torch.linalg.norm(R, dim=0) / torch.linalg.norm(B, dim=0)).max().item()
+        out[block] = {"solves_per_s": s * args.steps / el, "ms_per_step": 1e3 * el / args.steps,
+                      "iters": max(info.iters), "true_relres_max": rel,
+                      "phase_ms": {k: 1e3 * v / args.steps for k, v in tm.t.items()}}
+        log("%s: %.2f ms per 8 solves, iters %d, relres %.2e" % ("block" if block else "independent",
+                                                                  1e3 * el / args.steps, max(info.iters), rel))
+    b = out[True]
+    return base_record(
+        args, b["solves_per_s"], b["ms_per_step"], "f64",
+        {"workload": "coupled block PCG: RBF n=%d d=8 sigma=sqrt(8), mu=1e-3, l=%d, 8 right-hand sides N(0,1), "
+                     "tol 1e-10" % (n, ell),
+         "precision": "float64",
+         "step": "Gaussian Omega + sketch + factor + block PCG for all 8 columns"},
+        {"correct": b["true_relres_max"] <= 1.01 * tol, "block": b, "independent_columns": out[False]})
+
+
 # --------------------------------------------------------------------------- RBF helpers
 
 def rbf_rhs(nys, torch, op, w, dev):
@@ -652,7 +710,7 @@ def main():
           "krr_small": lambda a, n, t: run_krr(a, n, t, small=True), "krr": run_krr,
           "krr_cols": lambda a, n, t: run_krr(a, n, t, columns=True),
           "batched": run_batched, "diff": run_diff, "adaptive": run_adaptive,
-          "sketch_solve": run_sketch_solve}[args.workload]
+          "sketch_solve": run_sketch_solve, "block": run_block}[args.workload]
     out = fn(args, nys, torch)
     print(json.dumps(out), flush=True)
 

@@ -261,7 +261,8 @@ size_t nys_workspace_size_block(const nys_operator* A, int64_t ell, int64_t s);
  * (o->prec must be NYS_PREC_FP64); X0 = 0 (X is output only).  Stops when
  * every column's residual (the recursive residual mapped back through T0)
  * meets o->tol relative to its column of B, checked every o->check_every
- * iterations (<= 0: every iteration).  B: device float64 n x s (ldb), full
+ * iterations (<= 0: every 8), so the count can pass the first converged step
+ * by up to check_every - 1.  B: device float64 n x s (ldb), full
  * column rank, else NYS_ERR_ARG.  info arrays: s entries (iters = the block's
  * iteration count).  Returns NYS_OK, NYS_NOT_CONVERGED (cap) or
  * NYS_ERR_BREAKDOWN (an s x s system lost definiteness before convergence).

@@ -199,7 +199,8 @@ nys_status nys_block_pcg_solve(const nys_operator* A, const nys_precond* P, doub
   const int64_t n = A->n;
   NYS_ARG(s <= n, "more right-hand sides than unknowns");
   const int maxit = o->maxit > 0 ? o->maxit : 500;
-  const int every = o->check_every > 0 ? o->check_every : 1;
+  // host checks synchronise the stream: every 8 steps unless asked otherwise
+  const int every = o->check_every > 0 ? o->check_every : 8;
   const size_t base = nys_workspace_size(A, P->ell, s, NYS_PREC_FP64);
   NYS_ARG(base > 0, "nys_block_pcg_solve: invalid operator");
   Arena a(ws, ws_bytes);

@@ -56,7 +56,7 @@ def test_block_solve_converges_like_the_oracle(udtype):
     want = oracle.block_nystrom_pcg(ref.matmat, B, mu, Pi, tol=1e-10, maxit=1000)
     assert want["converged"]
     P = nys.Precond(dev(U, udtype), dev(r["lam"]))
-    X, info = nys.nys_block_pcg_solve(op, P, mu, dev(B), tol=1e-10, maxit=1000)
+    X, info = nys.nys_block_pcg_solve(op, P, mu, dev(B), tol=1e-10, maxit=1000, check_every=1)
     assert info.code == nys.NYS_OK and all(st == 0 for st in info.status)
     # ~90 block steps: rounding may move the step that crosses 1e-10 by one or two
     assert abs(info.iters[0] - want["iters"]) <= 2
