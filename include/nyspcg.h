@@ -340,6 +340,17 @@ nys_status nys_nystrom_adaptive(const nys_operator* A, int64_t ell0, int64_t ell
                                 int64_t ld, nys_precond* P, double* err_out, int32_t prec, void* ws,
                                 size_t ws_bytes, void* stream);
 
+/* Measurement hook.  nys_timing_begin enables, for calls made afterwards on
+ * the calling host thread, HIP events recorded on the launch stream
+ * immediately before and after each launch of the one-pass X^T X product
+ * kernel (the dominant kernel of the ridge solve).  nys_timing_end waits for
+ * the recorded events, returns the mean launch duration in milliseconds and
+ * the number of launches timed, releases the events and disables timing.
+ * Timing costs two event records per launch; it is off by default.
+ * Errors: NYS_ERR_ARG (end without begin), NYS_ERR_DEVICE (event failure). */
+nys_status nys_timing_begin(void);
+nys_status nys_timing_end(double* avg_ms, int64_t* launches);
+
 /* Message for the last non-OK status returned on this thread. */
 const char* nys_last_error(void);
 

@@ -31,7 +31,7 @@ EXPORTED = ["nys_workspace_size", "nys_gaussian", "nys_sketch", "nys_factor", "n
             "nys_pcg_backward", "nys_rbf_cross", "nys_workspace_size_adaptive", "nys_power_err_est",
             "nys_nystrom_adaptive", "nys_workspace_size_columns", "nys_sketch_columns",
             "nys_workspace_size_sketch_solve", "nys_sketch_solve", "nys_workspace_size_block",
-            "nys_block_pcg_solve", "nys_last_error", "nys_version"]
+            "nys_block_pcg_solve", "nys_timing_begin", "nys_timing_end", "nys_last_error", "nys_version"]
 
 
 class NysError(RuntimeError):
@@ -103,6 +103,8 @@ def lib():
         L.nys_workspace_size_sketch_solve.restype = sz
         L.nys_workspace_size_sketch_solve.argtypes = [i64, i64, i64]
         L.nys_sketch_solve.argtypes = [P(_Precond), dbl, vp, i64, i64, vp, i64, vp, sz, vp]
+        L.nys_timing_begin.argtypes = []
+        L.nys_timing_end.argtypes = [P(dbl), P(i64)]
         L.nys_workspace_size_block.restype = sz
         L.nys_workspace_size_block.argtypes = [P(_Operator), i64, i64]
         L.nys_block_pcg_solve.argtypes = [P(_Operator), P(_Precond), dbl, vp, i64, i64, vp, i64, P(_Opts), P(_Info),
@@ -110,7 +112,7 @@ def lib():
         for f in ("nys_gaussian", "nys_sketch", "nys_factor", "nys_op_apply", "nys_precond_apply",
                   "nys_pcg_solve", "nys_pcg_solve_ragged", "nys_pcg_backward", "nys_rbf_cross",
                   "nys_power_err_est", "nys_nystrom_adaptive", "nys_sketch_columns", "nys_sketch_solve",
-                  "nys_block_pcg_solve"):
+                  "nys_block_pcg_solve", "nys_timing_begin", "nys_timing_end"):
             getattr(L, f).restype = ctypes.c_int
         L.nys_last_error.restype = ctypes.c_char_p
         L.nys_version.restype = ctypes.c_char_p
@@ -388,6 +390,19 @@ def nys_pcg_solve(op: Operator, P: Precond, mu, B: torch.Tensor, X0: Optional[to
     if B.dim() == 1 and k == 1:
         X = X.reshape(-1)
     return X, si
+
+
+def timing_begin() -> None:
+    """Start timing launches of the X^T X product kernel with HIP events."""
+    _check(lib().nys_timing_begin())
+
+
+def timing_end():
+    """Stop timing; returns (mean launch duration in ms, launches timed)."""
+    avg = ctypes.c_double(0.0)
+    cnt = ctypes.c_int64(0)
+    _check(lib().nys_timing_end(ctypes.byref(avg), ctypes.byref(cnt)))
+    return avg.value, cnt.value
 
 
 def nys_block_pcg_solve(op: Operator, P: Precond, mu: float, B: torch.Tensor, tol: float = 1e-10, maxit: int = 500,

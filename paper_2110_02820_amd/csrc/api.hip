@@ -70,6 +70,38 @@ bool wait_pinned(const volatile int* seq, int expect, hipStream_t s, int alt) {
   return false;
 }
 
+// Launch timing of the X^T X product kernel (nys_timing_begin / _end):
+// while enabled, each launch is bracketed by two HIP events recorded on the
+// stream it is launched on.  Host thread of the caller only.
+namespace {
+struct LaunchTimer {
+  bool on = false;
+  std::vector<hipEvent_t> ev;  // start, end, start, end, ...
+};
+thread_local LaunchTimer g_timer;
+
+void record(hipStream_t s) {
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) {
+    g_timer.on = false;  // no event: give up timing, never the launch
+    return;
+  }
+  if (hipEventRecord(e, s) != hipSuccess) {
+    (void)hipEventDestroy(e);
+    g_timer.on = false;
+    return;
+  }
+  g_timer.ev.push_back(e);
+}
+}  // namespace
+
+void timing_mark_begin(hipStream_t s) {
+  if (g_timer.on) record(s);
+}
+void timing_mark_end(hipStream_t s) {
+  if (g_timer.on) record(s);
+}
+
 int num_cus() {
   static int cached[64] = {0};
   int dev = 0;
@@ -1022,6 +1054,41 @@ extern "C" {
 const char* nys_last_error(void) { return g_err; }
 
 const char* nys_version(void) { return "nyspcg 0.1 (gfx950)"; }
+
+nys_status nys_timing_begin(void) {
+  for (hipEvent_t e : g_timer.ev) (void)hipEventDestroy(e);
+  g_timer.ev.clear();
+  g_timer.on = true;
+  return NYS_OK;
+}
+
+nys_status nys_timing_end(double* avg_ms, int64_t* launches) {
+  NYS_ARG(avg_ms != nullptr && launches != nullptr, "nys_timing_end: NULL argument");
+  const bool was_on = g_timer.on;
+  g_timer.on = false;
+  double total = 0.0;
+  int64_t count = 0;
+  nys_status st = NYS_OK;
+  const size_t pairs = g_timer.ev.size() / 2;
+  for (size_t i = 0; i < pairs && st == NYS_OK; ++i) {
+    hipEvent_t a = g_timer.ev[2 * i], b = g_timer.ev[2 * i + 1];
+    float ms = 0.0f;
+    if (hipEventSynchronize(b) != hipSuccess || hipEventElapsedTime(&ms, a, b) != hipSuccess) {
+      set_error("nys_timing_end: event timing failed");
+      st = NYS_ERR_DEVICE;
+      break;
+    }
+    total += ms;
+    ++count;
+  }
+  for (hipEvent_t e : g_timer.ev) (void)hipEventDestroy(e);
+  g_timer.ev.clear();
+  if (st != NYS_OK) return st;
+  NYS_ARG(was_on, "nys_timing_end without nys_timing_begin (or event creation failed)");
+  *launches = count;
+  *avg_ms = count ? total / (double)count : 0.0;
+  return NYS_OK;
+}
 
 size_t nys_workspace_size(const nys_operator* A, int64_t ell, int64_t ncols, int32_t prec) {
   OpDesc op;

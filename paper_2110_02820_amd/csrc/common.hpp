@@ -58,6 +58,11 @@ __host__ __device__ inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 
 
 int num_cus();  // compute units of the current device
 
+// Measurement hook around the launch of the X^T X product kernel: records a
+// HIP event on s when nys_timing_begin() has enabled timing on this thread.
+void timing_mark_begin(hipStream_t s);
+void timing_mark_end(hipStream_t s);
+
 // 256 bytes of pinned host memory per host thread, kept for the life of the
 // process (null if it cannot be had): state the device writes for host loops
 // that poll without synchronising the stream.  Bytes 0..63: eigensolver

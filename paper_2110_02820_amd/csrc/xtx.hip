@@ -202,6 +202,7 @@ nys_status xtx_partials(const OpDesc& op, const TA* p, TA* scratch, size_t scrat
     return NYS_ERR_ARG;
   }
 #define LX(VP_, NV, RR) hipLaunchKernelGGL((xtx_fused<TD, TA, VP_, NV, RR>), dim3((unsigned)ng), dim3(256), 0, s, X, m, n, op.ld, p, scratch, rpw, op.skip)
+  timing_mark_begin(s);
   if (aligned) {
     if (need_nv <= 1) LX(Vec16<TD>, 1, 4);
     else if (need_nv <= 2) LX(Vec16<TD>, 2, 4);
@@ -215,6 +216,7 @@ nys_status xtx_partials(const OpDesc& op, const TA* p, TA* scratch, size_t scrat
   }
 #undef LX
   NYS_CHECK_LAUNCH();
+  timing_mark_end(s);
   *ng_out = (int)ng;
   return NYS_OK;
 }
