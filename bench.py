@@ -490,7 +490,7 @@ def run_krr(args, nys, torch, small=False, columns=False):
         X = torch.as_tensor(w["X"], device=dev)
         prec, udtype, label = nys.NYS_PREC_BF16X3_REFINE64, torch.float32, "bf16x3+f32+f64"
         mu = w["mu"]
-        kw = dict(maxit=5000, max_refine=40, inner_tol=args.inner_tol or 1e-2)
+        kw = dict(maxit=5000, max_refine=40, inner_tol=args.inner_tol or 3e-3)
     tol = 1e-10
     op = nys.Operator.rbf(X, w["sigma"])
     b = rbf_rhs(nys, torch, op, w, dev)
@@ -607,7 +607,7 @@ def run_batched(args, nys, torch):
         tm = Timer(torch)
         t = time.perf_counter()
         Xs, info, _ = full_solve(nys, torch, op, ell, seed, prec, torch.float32, mus, B, ws, tol, tm, maxit=5000,
-                                 max_refine=40, inner_tol=args.inner_tol or 1e-2)
+                                 max_refine=40, inner_tol=args.inner_tol or 3e-2)
         log("block solve: %s, iters max %d, refine %d" % ({k: round(1e3 * v, 1) for k, v in tm.t.items()},
                                                           max(info.iters), info.refine_steps))
         t = time.perf_counter()
@@ -670,7 +670,7 @@ def run_diff(args, nys, torch):
     def step(seed):
         tm = Timer(torch)
         x, info, P = full_solve(nys, torch, op, ell, seed, prec, torch.float32, mu, b, ws, tol, tm, maxit=5000,
-                                max_refine=40, inner_tol=args.inner_tol or 1e-3)
+                                max_refine=40, inner_tol=args.inner_tol or 3e-2)
         log("forward solve: %s, iters %d" % ({k: round(1e3 * v, 1) for k, v in tm.t.items()}, info.iters[0]))
         t = time.perf_counter()
         rv = nys.nys_rbf_cross(op, Xv, x) - yv
@@ -678,7 +678,7 @@ def run_diff(args, nys, torch):
         gx = 2.0 * nys.nys_rbf_cross(op, Xv, rv, transpose=True)
         _, dsig_explicit = nys.nys_rbf_cross(op, Xv, rv, wvec=x)
         g = nys.nys_pcg_backward(op, P, mu, x, gx, want_sigma=True, tol=tol, prec=prec, ws=ws, maxit=5000,
-                                 max_refine=40, inner_tol=args.inner_tol or 1e-3)
+                                 max_refine=40, inner_tol=args.inner_tol or 3e-2)
         tm.lap("backward", t)
         return L, g, 2.0 * dsig_explicit + g["gsigma"], info, tm
 
@@ -686,9 +686,11 @@ def run_diff(args, nys, torch):
         step(200 + i)
     t = time.perf_counter()
     tms = []
+    runs = []
     for i in range(args.steps):
         L, g, gs, info, tm = step(20211005 + i)
         tms.append(tm)
+        runs.append((info, g["info"]))
         log("diff step %d: L=%.6e dL/dmu=%.6e dL/dsigma=%.6e %s" % (i, L, g["gmu"], gs,
                                                                    {k: round(1e3 * v, 1) for k, v in tm.t.items()}))
     el = time.perf_counter() - t
@@ -699,6 +701,10 @@ def run_diff(args, nys, torch):
          "precision": "bf16x3 Gram tiles, float32 inner PCG, float64 refinement and gradient reductions",
          "step": "forward solve + loss + adjoint solve with the same preconditioner + dL/dmu, dL/dsigma, dL/db"},
         {"unit_note": "value = loss-and-gradient evaluations per second",
+         "correct": all(f.status[0] == 0 and f.relres[0] <= tol and a.status[0] == 0 and a.relres[0] <= tol
+                        for f, a in runs),
+         "relres_forward": max(f.relres[0] for f, _ in runs), "relres_adjoint": max(a.relres[0] for _, a in runs),
+         "refine_steps": [runs[-1][0].refine_steps, runs[-1][1].refine_steps],
          "phase_ms": {k: 1e3 * sum(tm.t.get(k, 0.0) for tm in tms) / args.steps for k in tms[0].t},
          "L": L, "dL_dmu": g["gmu"], "dL_dsigma": gs})
 
