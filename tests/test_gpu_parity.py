@@ -373,13 +373,13 @@ def _mixture_case(n, d, ell, seed):
 
 
 @pytest.mark.parametrize("prec,tol", [(1, 2e-5), (3, 2e-4)])
-@pytest.mark.parametrize("k", [1, 5, 20, 40, 70])
+@pytest.mark.parametrize("k", [1, 5, 20, 40, 70, 150])
 def test_rbf_lowp_products(prec, tol, k):
     """float32 Gram (prec 1) and bf16x3 Gram (prec 3) against the float64 oracle.
     Bounds: float32 exp and accumulation over ~1e3 terms (~1e-6 .. 1e-5);
     bf16x3 keeps ~16 bits of each coordinate (~1e-4).  k covers the one-vector
     kernel, the register kernel's 16, 32 and 64 column blocks (ragged) and the
-    LDS kernel."""
+    LDS kernel's 128 and (bf16x3 mode) 256 column blocks."""
     w, op_ref, _ = _mixture_case(1111, 32, 10, 40 + k)
     op = nys.Operator.rbf(t32(w["X"]), w["sigma"])
     V = np.random.default_rng(k).standard_normal((1111, k))
