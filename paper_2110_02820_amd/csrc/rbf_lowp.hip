@@ -675,10 +675,9 @@ KvPlan kv_plan(int64_t n, int64_t k, int mode) {
     p.nc = 16 * p.cf;
     p.rows = 64 * p.f;
   } else {
-    // bf16x3 mode past 128 columns: 256 columns per block halve the Gram /
-    // exp / split work per column (the float32 mode's three-piece tiles do
-    // not fit twice as many columns in LDS and registers)
-    p.cf = (mode == RBF_GRAM_BF16X3 && k > 128) ? 16 : 8;
+    // past 128 columns: 256 columns per block halve the Gram / exp / split
+    // work per column (two workgroups per CU instead of three)
+    p.cf = k > 128 ? 16 : 8;
     p.f = 1;
     p.nc = 16 * p.cf;
     p.rows = 64;
@@ -781,6 +780,8 @@ nys_status rbf_lowp_kv(const RbfLowp& L, int mode, const float* P, int64_t ldp, 
 #define KV(M, CF, KS) hipLaunchKernelGGL((rbf_kv_lowp<M, CF, KS>), grid, dim3(256), 0, s, Lq, P, ldp, k, Pq, Lq.npad / 8, dst, ldo, pps, oscale, skip)
     if (mode == 0) {
       if (pl.cf == 16) KV(0, 16, 1); else KV(0, 8, 1);
+    } else if (pl.cf == 16) {
+      if (kss == 2) KV(1, 16, 2); else if (kss == 4) KV(1, 16, 4); else KV(1, 16, 8);
     } else if (kss == 2) KV(1, 8, 2); else if (kss == 4) KV(1, 8, 4); else KV(1, 8, 8);
 #undef KV
   }
