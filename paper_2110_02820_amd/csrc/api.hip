@@ -1240,8 +1240,9 @@ nys_status nys_factor(const double* Omega, double* Y, nys_precond* P, int32_t pr
   // thin SVD of B through B^T B = W S W^T:  U = B W S^{-1/2}, lam = max(0, S - nu)
   NYS_TRY((gemm<double, double, double>(true, false, l, l, n, 1.0, w.B, l, w.B, l, 0.0, c.G, l, c.gscr,
                                         c.gscr_elems, s)));
+  // eigenvectors kept in float32 need off-diagonal ratios ~1e-8, not ~1e-16
   NYS_TRY(sym_eig(c.G, l, c.eig, c.flags, kMaxSweeps, c.sweeps, c.conv, c.T, P->lam, c.sig2,
-                  c.nu, s));
+                  c.nu, s, P->dtype == NYS_F32 ? 1e-4 : 1e-9));
   if (P->dtype == NYS_F64) {
     NYS_TRY((gemm<double, double, double>(false, false, n, l, l, 1.0, w.B, l, c.T, l, 0.0,
                                           static_cast<double*>(P->U), P->ldu, c.gscr, c.gscr_elems, s)));

@@ -462,6 +462,7 @@ struct JacArgs {
   int* conv_round;  // first round not to run (INT_MAX-like until convergence)
   int* sweeps_out;
   double* floor;    // rotation floor (device scalar)
+  float conv_r2;    // a sweep whose largest ratio^2 stays below this is the last
 };
 
 // Pair k and half h (0: first block, 1: second) of block X in round r.
@@ -806,19 +807,21 @@ __device__ void phase2_task(const JacArgs& a, int64_t g, int64_t task) {
 }
 
 // Converged when a sweep rotated nothing, or when every off-diagonal entry its
-// subproblems met had |a_pq| <= 1e-9 sqrt(|a_pp a_qq|).  In the second case
-// the sweep's own rotations leave each entry they annihilate at most at the
-// float32-tangent remainder (1e-7 of its ratio) and mix in products of two
-// such ratios from rotations sharing an index, so the matrix it leaves has
-// ratios of about 1e-16: the level a further, confirming sweep would reach,
-// and the level that sets the orthogonality of U = B W S^{-1/2}.
+// subproblems met had |a_pq| <= c sqrt(|a_pp a_qq|), c^2 = conv_r2.  In the
+// second case the sweep's own rotations leave each entry they annihilate at
+// most at the float32-tangent remainder (1e-7 of its ratio) and mix in
+// products of two such ratios from rotations sharing an index, so the matrix
+// it leaves has ratios of about max(c^2, 1e-7 c): with c = 1e-9 about 1e-16,
+// the level a further, confirming sweep would reach; with c = 1e-4 about 1e-8,
+// below the rounding of a float32 U.  These ratios set the orthogonality of
+// U = B W S^{-1/2}.
 // host_conv (host memory visible to the device, may be null) receives the
 // flag for the host's sweep loop in [0] and then the sequence tag in [1].
 __global__ void jac_end_sweep(JacArgs a, int sweep, int* host_conv, int seq) {
   if (!*a.conv) {
     a.sweeps_out[0] = sweep + 1;
     const unsigned r2 = static_cast<unsigned>(a.flags[sweep]);
-    if (r2 == 0u || r2 < __float_as_uint(1e-18f)) {
+    if (r2 == 0u || r2 < __float_as_uint(a.conv_r2)) {
       a.conv[0] = 1;
       a.conv_round[0] = (sweep + 1) * (a.nblk - 1);
     }
@@ -991,7 +994,7 @@ int* pinned_flags() {
 
 nys_status sym_eig(const double* G, int64_t l, double* work, int* flags, int max_sweeps,
                    int* sweeps_out, int* conv, double* T, double* lam, double* sig2, const double* nu,
-                   hipStream_t s) {
+                   hipStream_t s, double conv_ratio) {
   const int nb = jac_nblk(l);
   const int64_t m = (int64_t)nb * JB;
   double* A0 = work;
@@ -1010,7 +1013,7 @@ nys_status sym_eig(const double* G, int64_t l, double* work, int* flags, int max
   hipLaunchKernelGGL(jac_floor, dim3(1), dim3(256), 0, s, A0, m, floor);
   NYS_CHECK_LAUNCH();
   JacArgs a{{A0, A0 + m * m, A0 + 2 * m * m}, V, {J0, J1}, m, nb, inner_sweeps_for(l), flags, conv,
-            conv_round, sweeps_out, floor};
+            conv_round, sweeps_out, floor, (float)(conv_ratio * conv_ratio)};
   const int npair = nb / 2;
   const int64_t tasks = (int64_t)npair * npair + (m / JS) * npair;
   int64_t g = 0;

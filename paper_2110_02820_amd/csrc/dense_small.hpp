@@ -24,9 +24,12 @@ nys_status tri_inverse(const double* L, int64_t n, const double* Dinv, double* X
 // (block Jacobi).  Writes T = W[:, perm] diag(1/sqrt(s)) (l x l) with perm sorting s
 // descending, lam = max(0, s - nu) (descending), sig2 = s (descending, nullable).
 size_t eig_ws_doubles(int64_t l);
-// flags: max_sweeps ints; sweeps_out, conv: device ints.
+// flags: max_sweeps ints; sweeps_out, conv: device ints.  conv_ratio: the
+// sweep in which no rotated pair had |a_pq| / sqrt(|a_pp a_qq|) above it is
+// the last (1e-9 leaves off-diagonal ratios ~1e-16; 1e-4 leaves ~1e-8, enough
+// for eigenvectors that are stored in float32).
 nys_status sym_eig(const double* G, int64_t l, double* work, int* flags, int max_sweeps,
                    int* sweeps_out, int* conv, double* T, double* lam, double* sig2, const double* nu,
-                   hipStream_t s);
+                   hipStream_t s, double conv_ratio = 1e-9);
 
 }  // namespace nys
