@@ -1,0 +1,127 @@
+"""Parity at the benchmark's full sizes and launch configurations, on outputs
+the CPU oracle can compute one by one: sampled entries of the operator
+products, and sampled rows (or, where the oracle affords it, all rows) of the
+float64 residual of the solves.
+
+Inputs come from the seeded generators in ``workloads``; the oracle never
+receives a value the device computed except the solution whose residual it
+checks.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle  # noqa: E402
+from workloads import batched_cv, krr_mixture, ridge_dense  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2110_02820_amd as nys  # noqa: E402
+
+DEV = "cuda"
+
+
+def dev(a, dtype=torch.float64):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device=DEV)
+
+
+def h(t):
+    return t.detach().double().cpu().numpy()
+
+
+def test_ridge_20000x4000_products_and_solve():
+    """Ridge regression, X 20000 x 4000 float32, mu = 1e-4, l = 500.
+    Product: float32 (X^T X + mu I) v, the kernel the benchmark's roofline
+    times; bound 5e-5 = float32 rounding (6e-8) times the ~sqrt(4000) +
+    sqrt(20000) terms of the two accumulations, with margin.  Solve: the
+    benchmark's chosen form, judged by the oracle's float64 true residual."""
+    w = ridge_dense(m=20000, n=4000, ell=500, with_omega=False)
+    X = w["X"]
+    Xd = X.astype(np.float64)
+    mu = w["mu"]
+    op = nys.Operator.xtx(dev(X, torch.float32))
+    rng = np.random.default_rng(71)
+    v = rng.standard_normal(4000).astype(np.float32)
+    z = h(nys.nys_op_apply(op, mu, dev(v, torch.float32)))
+    idx = rng.choice(4000, size=48, replace=False)
+    Xv = Xd @ v.astype(np.float64)
+    want = Xd[:, idx].T @ Xv + mu * v[idx].astype(np.float64)
+    assert np.linalg.norm(z[idx] - want) <= 5e-5 * np.linalg.norm(want)
+    # the float64 product of the same data (refinement residuals): float64 rounding
+    z64 = h(nys.nys_op_apply(op, mu, dev(v.astype(np.float64))))
+    assert np.linalg.norm(z64[idx] - want) <= 1e-12 * np.linalg.norm(want)
+    # the benchmark's solve: bf16x3 sketch products, float32 PCG, float64 refinement
+    b = Xd.T @ w["y"]
+    prec = nys.NYS_PREC_BF16X3_REFINE64
+    Om, Y = nys.nys_sketch(op, 500, seed=20211002, prec=prec)
+    P = nys.nys_factor(Om, Y, dtype=torch.float32, prec=prec)
+    x, info = nys.nys_pcg_solve(op, P, mu, dev(b), tol=1e-10, prec=prec, maxit=1000, inner_tol=3e-6)
+    assert info.status[0] == 0
+    assert oracle.true_relres(oracle.XtXOp(X), mu, h(x), b) <= 1e-10
+
+
+def test_krr_100000x32_products_and_sampled_residual():
+    """Kernel ridge regression, n = 1e5, d = 32, sigma = sqrt(32), mu = 0.1,
+    l = 1000.  Sampled rows of K v: bf16x3 Gram tiles (the benchmark's timed
+    kernel; bound 2e-4 from the ~16 bits kept of each coordinate) and float64
+    (1e-12).  Solve with the benchmark's chosen form; each sampled residual
+    entry is bounded by the whole residual's norm, so |r_i| <= 1e-10 ||b||."""
+    w = krr_mixture(n=100000, d=32, ell=1000, with_omega=False)
+    X = w["X"]
+    Xd = X.astype(np.float64)
+    mu, sigma = w["mu"], w["sigma"]
+    op = nys.Operator.rbf(dev(X, torch.float32), sigma)
+    rng = np.random.default_rng(72)
+    v = rng.standard_normal(100000)
+    idx = rng.choice(100000, size=24, replace=False)
+    rows = oracle.rbf_kernel_block(Xd[idx], Xd, sigma)
+    want = rows @ v + mu * v[idx]
+    z3 = h(nys.nys_op_apply(op, mu, dev(v, torch.float32), prec=nys.NYS_PREC_BF16X3_REFINE64))
+    want32 = rows @ v.astype(np.float32).astype(np.float64) + mu * v[idx].astype(np.float32)
+    assert np.linalg.norm(z3[idx] - want32) <= 2e-4 * np.linalg.norm(want32)
+    z64 = h(nys.nys_op_apply(op, mu, dev(v)))
+    assert np.linalg.norm(z64[idx] - want) <= 1e-12 * np.linalg.norm(want)
+    # solve: right-hand side from the generator's noise draw (b = eps), bf16x3 form
+    b = w["eps"]
+    prec = nys.NYS_PREC_BF16X3_REFINE64
+    Om, Y = nys.nys_sketch(op, 1000, seed=20211003, prec=prec)
+    P = nys.nys_factor(Om, Y, dtype=torch.float32, prec=prec)
+    x, info = nys.nys_pcg_solve(op, P, mu, dev(b), tol=1e-10, prec=prec, maxit=5000, max_refine=40,
+                                inner_tol=3e-3)
+    assert info.status[0] == 0 and info.relres[0] <= 1e-10
+    xh = h(x)
+    ridx = rng.choice(100000, size=64, replace=False)
+    r = b[ridx] - (oracle.rbf_kernel_block(Xd[ridx], Xd, sigma) @ xh + mu * xh[ridx])
+    assert np.abs(r).max() <= 1e-10 * np.linalg.norm(b)
+
+
+def test_batched_50000x16_mu_grid_sampled_residuals():
+    """Batched cross-validation: one sketch (n = 5e4, d = 16, l = 800, float32
+    Gram tiles) for 32 mu x 8 right-hand sides in one block solve.  Every
+    column must meet 1e-10 (the library's float64 residual); for the smallest
+    and largest mu the oracle checks sampled residual rows against it."""
+    w = batched_cv(n=50000, d=16, ell=800, with_omega=False, with_ragged=False)
+    X = w["X"]
+    Xd = X.astype(np.float64)
+    sigma, mus, B = w["sigma"], [float(m) for m in w["mus"]], w["B"]
+    op = nys.Operator.rbf(dev(X, torch.float32), sigma)
+    prec = nys.NYS_PREC_FP32_REFINE64
+    Om, Y = nys.nys_sketch(op, 800, seed=20211004, prec=prec)
+    P = nys.nys_factor(Om, Y, dtype=torch.float32, prec=prec)
+    Xs, info = nys.nys_pcg_solve(op, P, mus, dev(B), tol=1e-10, prec=prec, maxit=5000, max_refine=40,
+                                 inner_tol=3e-2)
+    assert all(s == 0 for s in info.status) and max(info.relres) <= 1e-10
+    Xh = h(Xs)
+    rng = np.random.default_rng(73)
+    ridx = rng.choice(50000, size=32, replace=False)
+    rows = oracle.rbf_kernel_block(Xd[ridx], Xd, sigma)
+    nrhs = B.shape[1]
+    for m in (0, len(mus) - 1):
+        for c in (0, nrhs - 1):
+            col = m * nrhs + c
+            r = B[ridx, c] - (rows @ Xh[:, col] + mus[m] * Xh[ridx, col])
+            assert np.abs(r).max() <= 1e-10 * np.linalg.norm(B[:, c])
