@@ -125,3 +125,41 @@ def test_batched_50000x16_mu_grid_sampled_residuals():
             col = m * nrhs + c
             r = B[ridx, c] - (rows @ Xh[:, col] + mus[m] * Xh[ridx, col])
             assert np.abs(r).max() <= 1e-10 * np.linalg.norm(B[:, c])
+
+
+def test_differentiation_100000x16_adjoint_sampled_residual():
+    """Differentiation workload (n = 1e5, d = 16, sigma = 4, mu = 0.1,
+    l = 1000): the adjoint solve (A + mu I) lambda = g reuses the forward
+    preconditioner; both solves meet 1e-10 and the oracle checks sampled
+    residual rows of each.  dL/dmu = -lambda^T x and dL/db = lambda are then
+    the implicit-function formulas (pinned on small systems by the oracle
+    tests)."""
+    from workloads import differentiation
+    w = differentiation(n=100000, nval=10000, with_omega=False)
+    X = w["X"]
+    Xd = X.astype(np.float64)
+    mu, sigma = w["mu"], w["sigma"]
+    op = nys.Operator.rbf(dev(X, torch.float32), sigma)
+    prec = nys.NYS_PREC_BF16X3_REFINE64
+    b = w["eps"]
+    g = w["w"]  # a seeded loss gradient dL/dx
+    Om, Y = nys.nys_sketch(op, 1000, seed=20211005, prec=prec)
+    P = nys.nys_factor(Om, Y, dtype=torch.float32, prec=prec)
+    x, info = nys.nys_pcg_solve(op, P, mu, dev(b), tol=1e-10, prec=prec, maxit=5000, max_refine=40,
+                                inner_tol=3e-2)
+    assert info.status[0] == 0 and info.relres[0] <= 1e-10
+    out = nys.nys_pcg_backward(op, P, mu, x, dev(g), tol=1e-10, prec=prec, maxit=5000, max_refine=40,
+                               inner_tol=3e-2)
+    assert out["info"].status[0] == 0 and out["info"].relres[0] <= 1e-10
+    lam = h(out["gb"])
+    xh = h(x)
+    # float64 dot products in two summation orders: their difference is bounded
+    # by n u |lam| |x| (no relative bound: lam^T x may cancel)
+    assert abs(out["gmu"] + float(lam @ xh)) <= 1e-11 * np.linalg.norm(lam) * np.linalg.norm(xh)
+    rng = np.random.default_rng(74)
+    ridx = rng.choice(100000, size=48, replace=False)
+    rows = oracle.rbf_kernel_block(Xd[ridx], Xd, sigma)
+    r = b[ridx] - (rows @ xh + mu * xh[ridx])
+    assert np.abs(r).max() <= 1e-10 * np.linalg.norm(b)
+    ra = g[ridx] - (rows @ lam + mu * lam[ridx])
+    assert np.abs(ra).max() <= 1e-10 * np.linalg.norm(g)
