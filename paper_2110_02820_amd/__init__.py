@@ -72,7 +72,7 @@ def lib():
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
-            raise RuntimeError("libnyspcg.so is not built: run __graft_entry__.build()")
+            raise RuntimeError("libnyspcg.so is not built: run python -m paper_2110_02820_amd._build")
         L = ctypes.CDLL(LIB_PATH)
         vp, i64, i32, dbl, sz = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_double, ctypes.c_size_t
         P = ctypes.POINTER

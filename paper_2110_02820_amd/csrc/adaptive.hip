@@ -2,8 +2,8 @@
 // power estimate of ||E|| = ||A - U diag(lam) U^T|| (Appendix, algorithm
 // "Randomized Power method for estimating ||E||") and the sketch-doubling
 // driver (Section "Adaptive rank selection", Strategies 1 and 2; Appendix,
-// algorithm "Adaptive Randomized Nystrom Approximation").  The driver is host
-// control over the library's own entry points (sketch, factor, operator
+// algorithm "Adaptive Randomized Nystrom Approximation").  The doubling loop
+// is host control over the library's own entry points (sketch, factor, operator
 // product); the estimate's vector work runs in the kernels below and the
 // library GEMM.
 #include <cmath>
