@@ -51,6 +51,7 @@ __global__ void add_mu(T* __restrict__ V, int64_t ldv, const T* __restrict__ P, 
 
 constexpr int RB_ROWS = 64;   // rows per workgroup
 constexpr int RB_PTS = 64;    // points per staged tile
+constexpr int KV_PTS = 16;    // points per staged tile of the block product
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
@@ -172,10 +173,10 @@ __global__ __launch_bounds__(256) void rbf_kv_f64(const TD* __restrict__ X, int6
                                                   const int* __restrict__ skip) {
   if (skip && *skip) return;
   __shared__ double Xi[RB_ROWS][DMAX + 1];
-  __shared__ double Xj[RB_PTS][DMAX + 1];
-  __shared__ double Ni[RB_ROWS], Nj[RB_PTS];
-  __shared__ double Ks[RB_PTS][RB_ROWS + 2];  // Ks[j][i]
-  __shared__ double Ps[RB_PTS][64 + 2];       // Ps[j][c]
+  __shared__ double Xj[KV_PTS][DMAX + 1];
+  __shared__ double Ni[RB_ROWS], Nj[KV_PTS];
+  __shared__ double Ks[KV_PTS][RB_ROWS + 2];  // Ks[j][i]
+  __shared__ double Ps[KV_PTS][64 + 2];       // Ps[j][c]
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int wm = wave >> 1, wn = wave & 1;
   const int64_t i0 = (int64_t)blockIdx.x * RB_ROWS;
@@ -202,31 +203,42 @@ __global__ __launch_bounds__(256) void rbf_kv_f64(const TD* __restrict__ X, int6
       acc[a][b] = d4{0, 0, 0, 0};
       cmp[a][b] = d4{0, 0, 0, 0};
     }
-  for (int64_t jt = j0; jt < j1; jt += RB_PTS) {
+  for (int64_t jt = j0; jt < j1; jt += KV_PTS) {
     __syncthreads();
-    for (int e = t; e < RB_PTS * DMAX; e += 256) {
+    for (int e = t; e < KV_PTS * DMAX; e += 256) {
       const int jj = e / DMAX, kk = e % DMAX;
       Xj[jj][kk] = (jt + jj < j1 && kk < d) ? double(X[(jt + jj) * ld + kk]) : 0.0;
     }
-    for (int e = t; e < RB_PTS * 64; e += 256) {
+    for (int e = t; e < KV_PTS * 64; e += 256) {
       const int jj = e / 64, cc = e % 64;
       Ps[jj][cc] = (jt + jj < j1 && cb + cc < k) ? P[(jt + jj) * ldp + cb + cc] : 0.0;
     }
     __syncthreads();
-    if (t < RB_PTS) {
+    if (t < KV_PTS) {
       double s = 0.0;
       for (int kk = 0; kk < DMAX; ++kk) s += Xj[t][kk] * Xj[t][kk];
       Nj[t] = s;
     }
     __syncthreads();
-    // kernel tile: 16 entries per thread
-    for (int e = t; e < RB_ROWS * RB_PTS; e += 256) {
-      const int ii = e / RB_PTS, jj = e % RB_PTS;
-      double g = 0.0;
+    // kernel tile: wave w forms rows w*16 .. +15 against the 64 points, the
+    // Gram entries on f64 MFMA (row operand from Xi, point operand from Xj;
+    // accumulator element q of lane l: row 4 q + l/16, point l % 16)
 #pragma unroll
-      for (int kk = 0; kk < DMAX; ++kk) g += Xi[ii][kk] * Xj[jj][kk];
-      const double d2 = fmax(Ni[ii] + Nj[jj] - 2.0 * g, 0.0);
-      Ks[jj][ii] = (jt + jj < j1) ? exp(-d2 * c2) : 0.0;
+    for (int st = 0; st < KV_PTS / 16; ++st) {
+      const int pt = st * 16 + (lane & 15);
+      d4 g = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int ks = 0; ks < DMAX / 4; ++ks)
+        g = __builtin_amdgcn_mfma_f64_16x16x4f64(Xi[wave * 16 + (lane & 15)][4 * ks + (lane >> 4)],
+                                                 Xj[pt][4 * ks + (lane >> 4)], g, 0, 0, 0);
+      const double nj = Nj[pt];
+      const bool in = jt + pt < j1;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int ii = wave * 16 + 4 * q + (lane >> 4);
+        const double d2 = fmax(Ni[ii] + nj - 2.0 * g[q], 0.0);
+        Ks[pt][ii] = in ? exp(-d2 * c2) : 0.0;
+      }
     }
     __syncthreads();
     // tile(64 rows x 64 cols) = K(64 x 64 pts) * P(64 pts x 64 cols), then acc += tile
@@ -236,7 +248,7 @@ __global__ __launch_bounds__(256) void rbf_kv_f64(const TD* __restrict__ X, int6
 #pragma unroll
       for (int b = 0; b < 2; ++b) tl[a][b] = d4{0, 0, 0, 0};
 #pragma unroll 4
-    for (int kk = 0; kk < RB_PTS; kk += 4) {
+    for (int kk = 0; kk < KV_PTS; kk += 4) {
       const int kq = kk + (lane >> 4);
       const double a0 = Ks[kq][wm * 32 + (lane & 15)];
       const double a1 = Ks[kq][wm * 32 + 16 + (lane & 15)];
