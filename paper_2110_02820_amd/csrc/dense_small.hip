@@ -96,39 +96,26 @@ struct CholArgs {
   int* info;        // 0 = ok, k+1 = non-positive pivot at column k
 };
 
-// Blocked right-looking Cholesky, one launch per step (the stream orders
-// them): diagonal block (one wave), panel below it, trailing update.
+// Blocked right-looking Cholesky with one launch per step.  Launch kb
+// updates the trailing matrix with the panel of block column kb and factors
+// diagonal block kb + 1 in the same workgroup that updated it; the
+// sub-diagonal blocks keep their Schur-complement values A[ib][kb] until one
+// last launch turns them all into L[ib][kb] = A[ib][kb] L_kk^{-T}.
 
-// Cholesky + inverse of one NB x NB diagonal block by one wave: lane i keeps
-// row i of the factor in registers (left-looking: column j is A[i][j] -
-// sum_{k<j} L[i][k] L[j][k], row j read back from LDS as a broadcast), then
-// lane j forms column j of L^{-1} by forward substitution.  Lanes 32..63
-// repeat lanes 0..31 and store nothing.
-__global__ __launch_bounds__(64) void chol_diag(CholArgs a, int kb) {
-  if (*((volatile int*)a.info) != 0) return;
-  __shared__ double T[NB][NB + 1];
-  __shared__ double Piv;
-  __shared__ double Ys[NB];  // 1 / L[j][j]
+// Cholesky + inverse of one NB x NB diagonal block held in T (lower part,
+// identity outside the matrix): thread t works on row i = t mod NB and keeps
+// it in registers (left-looking: column j is A[i][j] - sum_{k<j} L[i][k]
+// L[j][k], row j read back from LDS as a broadcast); then it forms column i
+// of L^{-1} by forward substitution.  Threads t >= NB repeat threads t mod NB
+// and store nothing, so any block size that is a multiple of NB works.
+__device__ __forceinline__ void diag_factor(const CholArgs& a, int kb, double (*T)[NB + 1], double* Piv,
+                                            double* Ys) {
   double* __restrict__ Lg = a.L;
   double* __restrict__ Dg = a.Dinv;
   const int64_t n = a.n;
   const int64_t base = (int64_t)kb * NB;
   const int nbk = (int)((n - base) < NB ? (n - base) : NB);
   const int t = threadIdx.x;
-  {
-    double v[NB * NB / 64];
-#pragma unroll
-    for (int u = 0; u < NB * NB / 64; ++u) {
-      const int e = t + 64 * u, i = e / NB, j = e % NB;
-      v[u] = (i < nbk && j < nbk && j <= i) ? Lg[(base + i) * n + base + j] : (i == j ? 1.0 : 0.0);
-    }
-#pragma unroll
-    for (int u = 0; u < NB * NB / 64; ++u) {
-      const int e = t + 64 * u;
-      T[e / NB][e % NB] = v[u];  // padding outside the matrix: identity
-    }
-  }
-  __syncthreads();
   const int i = t & (NB - 1);
   const bool own = t < NB;
   double r[NB];
@@ -146,9 +133,9 @@ __global__ __launch_bounds__(64) void chol_diag(CholArgs a, int kb) {
       if (k + 1 < j) s1 -= r[k + 1] * T[j][k + 1];
     }
     const double sj = s0 + s1;
-    if (own && i == j) Piv = sj;
+    if (own && i == j) *Piv = sj;
     __syncthreads();
-    double d = Piv;
+    double d = *Piv;
     double yj;
     if (!(d > 0.0) || !isfinite(d)) {
       if (bad < 0) bad = j;
@@ -186,15 +173,144 @@ __global__ __launch_bounds__(64) void chol_diag(CholArgs a, int kb) {
   }
 }
 
-// L[ib,kb] = A[ib,kb] * Dinv_kb^T for ib = kb + 1 + blockIdx.x
-__global__ __launch_bounds__(256) void chol_panel(CholArgs a, int kb) {
+// Diagonal block kb by one wave (the first block; later ones are factored
+// inside chol_step).
+__global__ __launch_bounds__(64) void chol_diag(CholArgs a, int kb) {
   if (*((volatile int*)a.info) != 0) return;
   __shared__ double T[NB][NB + 1];
+  __shared__ double Piv;
+  __shared__ double Ys[NB];  // 1 / L[j][j]
+  const int64_t n = a.n;
+  const int64_t base = (int64_t)kb * NB;
+  const int nbk = (int)((n - base) < NB ? (n - base) : NB);
+  const int t = threadIdx.x;
+  double v[NB * NB / 64];
+#pragma unroll
+  for (int u = 0; u < NB * NB / 64; ++u) {
+    const int e = t + 64 * u, i = e / NB, j = e % NB;
+    v[u] = (i < nbk && j < nbk && j <= i) ? a.L[(base + i) * n + base + j] : (i == j ? 1.0 : 0.0);
+  }
+#pragma unroll
+  for (int u = 0; u < NB * NB / 64; ++u) {
+    const int e = t + 64 * u;
+    T[e / NB][e % NB] = v[u];  // padding outside the matrix: identity
+  }
+  __syncthreads();
+  diag_factor(a, kb, T, &Piv, Ys);
+}
+
+// Row and column (ii >= jj) of lower-triangle tile number tt.
+__device__ __forceinline__ void tri_tile(int tt, int& ii, int& jj) {
+  ii = (int)((sqrt(8.0 * tt + 1.0) - 1.0) * 0.5);
+  while ((ii + 1) * (ii + 2) / 2 <= tt) ++ii;
+  while (ii * (ii + 1) / 2 > tt) --ii;
+  jj = tt - ii * (ii + 1) / 2;
+}
+
+// Step kb, tile (ib, jb) with kb < jb <= ib, one workgroup each:
+// A[ib][jb] -= L[ib][kb] L[jb][kb]^T, where the workgroup forms the panel
+// blocks it needs itself, L[xb][kb] = A[xb][kb] Dinv_kb^T (column kb still
+// holds Schur-complement values in this launch).  The workgroup of tile
+// (kb + 1, kb + 1), which no other workgroup of the launch reads or writes,
+// then factors and inverts that block.
+__global__ __launch_bounds__(256) void chol_step(CholArgs a, int kb) {
+  __shared__ double Pi[NB][NB + 1], Pj[NB][NB + 1], Di[NB][NB + 1], T[NB][NB + 1];
+  __shared__ double Piv;
+  __shared__ double Ys[NB];
+  __shared__ int stop;
+  const int64_t n = a.n;
+  const int t = threadIdx.x;
+  int ii, jj;
+  tri_tile((int)blockIdx.x, ii, jj);
+  const int ib = kb + 1 + ii, jb = kb + 1 + jj;
+  const int64_t c0 = (int64_t)kb * NB, cj = (int64_t)jb * NB;
+  double* __restrict__ Lg = a.L;
+  if (t == 0) stop = *((volatile int*)a.info);  // read once: the flag may change during the launch
+  {
+    double vi[NB * NB / 256], vj[NB * NB / 256], vd[NB * NB / 256], vt[NB * NB / 256];
+#pragma unroll
+    for (int u = 0; u < NB * NB / 256; ++u) {
+      const int e = t + 256 * u, i = e / NB, k = e % NB;
+      const int64_t ri = (int64_t)ib * NB + i, rj = cj + i;
+      vi[u] = ri < n ? Lg[ri * n + c0 + k] : 0.0;
+      vj[u] = rj < n ? Lg[rj * n + c0 + k] : 0.0;
+      vd[u] = a.Dinv[c0 * NB + e];
+      vt[u] = (ri < n && cj + k < n) ? Lg[ri * n + cj + k] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < NB * NB / 256; ++u) {
+      const int e = t + 256 * u;
+      Pi[e / NB][e % NB] = vi[u];
+      Pj[e / NB][e % NB] = vj[u];
+      Di[e / NB][e % NB] = vd[u];
+      T[e / NB][e % NB] = vt[u];
+    }
+  }
+  __syncthreads();
+  if (stop != 0) return;  // the same value for every thread
+  {  // panel blocks: P <- P Dinv^T (Dinv lower triangular)
+    double pi[NB * NB / 256], pj[NB * NB / 256];
+#pragma unroll
+    for (int u = 0; u < NB * NB / 256; ++u) {
+      const int e = t + 256 * u, i = e / NB, j = e % NB;
+      double si = 0.0, sj = 0.0;
+      for (int k = 0; k <= j; ++k) {
+        si += Pi[i][k] * Di[j][k];
+        sj += Pj[i][k] * Di[j][k];
+      }
+      pi[u] = si;
+      pj[u] = sj;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < NB * NB / 256; ++u) {
+      const int e = t + 256 * u;
+      Pi[e / NB][e % NB] = pi[u];
+      Pj[e / NB][e % NB] = pj[u];
+    }
+  }
+  __syncthreads();
+  const bool diag_next = ii == 0;  // tile (kb + 1, kb + 1)
+  const int nbk = (int)((n - cj) < NB ? (n - cj) : NB);
+  double upd[NB * NB / 256];
+#pragma unroll
+  for (int u = 0; u < NB * NB / 256; ++u) {
+    const int e = t + 256 * u, i = e / NB, j = e % NB;
+    double sacc = 0.0;
+#pragma unroll 8
+    for (int k = 0; k < NB; ++k) sacc += Pi[i][k] * Pj[j][k];
+    upd[u] = T[i][j] - sacc;
+  }
+  if (!diag_next) {
+#pragma unroll
+    for (int u = 0; u < NB * NB / 256; ++u) {
+      const int e = t + 256 * u, i = e / NB, j = e % NB;
+      const int64_t gi = (int64_t)ib * NB + i, gj = cj + j;
+      if (gi < n && gj < n && gj <= gi) Lg[gi * n + gj] = upd[u];
+    }
+    return;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < NB * NB / 256; ++u) {
+    const int e = t + 256 * u, i = e / NB, j = e % NB;
+    T[i][j] = (i < nbk && j < nbk && j <= i) ? upd[u] : (i == j ? 1.0 : 0.0);
+  }
+  __syncthreads();
+  diag_factor(a, jb, T, &Piv, Ys);
+}
+
+// All sub-diagonal blocks: L[ib][kb] = A[ib][kb] Dinv_kb^T, one workgroup
+// per block (strict lower-triangle tile number tt).
+__global__ __launch_bounds__(256) void chol_panels(CholArgs a) {
+  if (*((volatile int*)a.info) != 0) return;
   __shared__ double Ti[NB][NB + 1];
   __shared__ double Lb[NB][NB + 1];
   const int64_t n = a.n;
   const int t = threadIdx.x;
-  const int ib = kb + 1 + blockIdx.x;
+  int ii, kb;
+  tri_tile((int)blockIdx.x, ii, kb);
+  const int ib = ii + 1;
   double* __restrict__ Lg = a.L;
   const double* __restrict__ Di = a.Dinv + (int64_t)kb * NB * NB;
   const int64_t r0 = (int64_t)ib * NB, c0 = (int64_t)kb * NB;
@@ -203,7 +319,7 @@ __global__ __launch_bounds__(256) void chol_panel(CholArgs a, int kb) {
 #pragma unroll
     for (int u = 0; u < NB * NB / 256; ++u) {
       const int e = t + 256 * u, i = e / NB, j = e % NB;
-      v[u] = (r0 + i < n && c0 + j < n) ? Lg[(r0 + i) * n + c0 + j] : 0.0;
+      v[u] = (r0 + i < n) ? Lg[(r0 + i) * n + c0 + j] : 0.0;
       w[u] = Di[e];
     }
 #pragma unroll
@@ -214,63 +330,12 @@ __global__ __launch_bounds__(256) void chol_panel(CholArgs a, int kb) {
     }
   }
   __syncthreads();
-  #pragma unroll
-  for (int e = t; e < NB * NB; e += 256) {
-    const int i = e / NB, j = e % NB;
+#pragma unroll
+  for (int u = 0; u < NB * NB / 256; ++u) {
+    const int e = t + 256 * u, i = e / NB, j = e % NB;
     double sacc = 0.0;
     for (int k = 0; k <= j; ++k) sacc += Lb[i][k] * Ti[j][k];
-    T[i][j] = sacc;
-  }
-  __syncthreads();
-  #pragma unroll
-  for (int e = t; e < NB * NB; e += 256) {
-    const int i = e / NB, j = e % NB;
-    if (r0 + i < n && c0 + j < n) Lg[(r0 + i) * n + c0 + j] = T[i][j];
-  }
-}
-
-// A[ib,jb] -= L[ib,kb] L[jb,kb]^T for kb < jb <= ib, one tile per workgroup
-__global__ __launch_bounds__(256) void chol_trail(CholArgs a, int kb) {
-  if (*((volatile int*)a.info) != 0) return;
-  __shared__ double T[NB][NB + 1];
-  __shared__ double Lb[NB][NB + 1];
-  const int64_t n = a.n;
-  const int t = threadIdx.x;
-  const int tt = blockIdx.x;
-  int ii = (int)((sqrt(8.0 * tt + 1.0) - 1.0) * 0.5);
-  while ((ii + 1) * (ii + 2) / 2 <= tt) ++ii;
-  while (ii * (ii + 1) / 2 > tt) --ii;
-  const int jj = tt - ii * (ii + 1) / 2;
-  const int ib = kb + 1 + ii, jb = kb + 1 + jj;
-  const int64_t c0 = (int64_t)kb * NB;
-  double* __restrict__ Lg = a.L;
-  {
-    double v[NB * NB / 256], w[NB * NB / 256];
-#pragma unroll
-    for (int u = 0; u < NB * NB / 256; ++u) {
-      const int e = t + 256 * u, i = e / NB, k = e % NB;
-      const int64_t ri = (int64_t)ib * NB + i, rj = (int64_t)jb * NB + i;
-      v[u] = (ri < n) ? Lg[ri * n + c0 + k] : 0.0;
-      w[u] = (rj < n) ? Lg[rj * n + c0 + k] : 0.0;
-    }
-#pragma unroll
-    for (int u = 0; u < NB * NB / 256; ++u) {
-      const int e = t + 256 * u;
-      Lb[e / NB][e % NB] = v[u];
-      T[e / NB][e % NB] = w[u];
-    }
-  }
-  __syncthreads();
-  #pragma unroll
-  for (int e = t; e < NB * NB; e += 256) {
-    const int i = e / NB, j = e % NB;
-    const int64_t gi = (int64_t)ib * NB + i, gj = (int64_t)jb * NB + j;
-    if (gi < n && gj < n && gj <= gi) {
-      double sacc = 0.0;
-#pragma unroll 8
-      for (int k = 0; k < NB; ++k) sacc += Lb[i][k] * T[j][k];
-      Lg[gi * n + gj] -= sacc;
-    }
+    if (r0 + i < n) Lg[(r0 + i) * n + c0 + j] = sacc;
   }
 }
 
@@ -936,14 +1001,12 @@ nys_status cholesky(const double* M, int64_t n, double* L, double* Dinv, int* in
   NYS_HIP(hipMemsetAsync(info, 0, sizeof(int), s));
   CholArgs a{L, n, Dinv, info};
   const int nblk = (int)cdiv(n, NB);
-  for (int kb = 0; kb < nblk; ++kb) {
-    hipLaunchKernelGGL(chol_diag, dim3(1), dim3(64), 0, s, a, kb);
+  hipLaunchKernelGGL(chol_diag, dim3(1), dim3(64), 0, s, a, 0);
+  for (int kb = 0; kb + 1 < nblk; ++kb) {
     const int rem = nblk - kb - 1;
-    if (rem > 0) {
-      hipLaunchKernelGGL(chol_panel, dim3((unsigned)rem), dim3(256), 0, s, a, kb);
-      hipLaunchKernelGGL(chol_trail, dim3((unsigned)(rem * (rem + 1) / 2)), dim3(256), 0, s, a, kb);
-    }
+    hipLaunchKernelGGL(chol_step, dim3((unsigned)(rem * (rem + 1) / 2)), dim3(256), 0, s, a, kb);
   }
+  if (nblk > 1) hipLaunchKernelGGL(chol_panels, dim3((unsigned)(nblk * (nblk - 1) / 2)), dim3(256), 0, s, a);
   NYS_CHECK_LAUNCH();
   return NYS_OK;
 }

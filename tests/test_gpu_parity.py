@@ -360,6 +360,13 @@ def test_error_paths_on_device():
     with pytest.raises(nys.NysError) as e:
         nys.nys_sketch(op, 20, omega0=t64(np.zeros((200, 20))))
     assert e.value.status == nys.NYS_ERR_NOT_PSD
+    # zero columns past the first 32 x 32 block: the zero pivot (column 40) is
+    # met by a later step of the blocked Cholesky, not by its first block
+    om_bad = np.random.default_rng(5).standard_normal((200, 70))
+    om_bad[:, 40:] = 0.0
+    with pytest.raises(nys.NysError) as e:
+        nys.nys_sketch(op, 70, omega0=t64(om_bad))
+    assert e.value.status == nys.NYS_ERR_NOT_PSD
 
 
 # ---------------------------------------------------------------- reduced-precision RBF
