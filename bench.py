@@ -712,8 +712,8 @@ def run_diff(args, nys, torch):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build measures the single-GPU path "
-              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        print("bench.py runs on one GPU only: the library has no multi-GPU path; the figure is one "
+              "GPU's throughput (--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
     import torch
 
