@@ -126,12 +126,12 @@ nys_status nys_gaussian(uint64_t seed, int64_t n, int64_t ell, double* out, int6
                         void* stream);
 
 /* Sketch (algorithm "Randomized Nystrom Approximation", steps 1-3):
- * Omega = orth(Omega0) (thin QR factor Q, computed by CholeskyQR2) and
- * Y = A Omega.  omega0: device float64 n x ell (ld = ell) or NULL to draw it
+ * Omega = orth(Omega0) (thin QR factor Q by CholeskyQR: one pass for a drawn
+ * Gaussian with n >= 3 ell, two passes otherwise) and Y = A Omega.  omega0: device float64 n x ell (ld = ell) or NULL to draw it
  * with nys_gaussian(seed).  Omega_out, Y_out: device float64 n x ell (ld = ell).
  * prec selects the arithmetic of Y = A Omega (FP64, FP32 or BF16X3 tiles);
- * Omega is float64 in every mode.  Errors: NYS_ERR_ARG (1 <= ell <= n violated,
- * bad operator), NYS_ERR_NOT_PSD (Omega0 rank deficient). */
+ * Omega is float64 in every mode.  Errors: NYS_ERR_ARG (1 <= ell <= min(n, 2048)
+ * violated, bad operator), NYS_ERR_NOT_PSD (Omega0 rank deficient). */
 nys_status nys_sketch(const nys_operator* A, int64_t ell, uint64_t seed, const double* omega0,
                       double* Omega_out, double* Y_out, int32_t prec, void* ws, size_t ws_bytes,
                       void* stream);
@@ -144,8 +144,10 @@ nys_status nys_sketch(const nys_operator* A, int64_t ell, uint64_t seed, const d
  * tiles) the shift is raised to max(eps(||Y||_F), u ||Y||_F) so that the core
  * matrix stays positive definite; the shift is removed again from lam.
  * Y is overwritten.  P: P->n, P->ell, P->U, P->ldu, P->dtype, P->lam set by
- * the caller; P->nu is written (host).  A failed Cholesky is retried with
- * nu <- 10 nu up to three times, then NYS_ERR_NOT_PSD.  Synchronises stream. */
+ * the caller (1 <= P->ell <= min(n, 2048), else NYS_ERR_ARG; the same bound
+ * holds for every call that takes a preconditioner); P->nu is written (host).
+ * A failed Cholesky is retried with nu <- 10 nu up to three times, then
+ * NYS_ERR_NOT_PSD.  Synchronises stream. */
 nys_status nys_factor(const double* Omega, double* Y, nys_precond* P, int32_t prec, void* ws,
                       size_t ws_bytes, void* stream);
 

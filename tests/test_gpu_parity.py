@@ -360,6 +360,15 @@ def test_error_paths_on_device():
     with pytest.raises(nys.NysError) as e:
         nys.nys_sketch(op, 20, omega0=t64(np.zeros((200, 20))))
     assert e.value.status == nys.NYS_ERR_NOT_PSD
+    # sketch sizes and preconditioner ranks above 2048 are refused up front
+    big = nys.Operator.dense(t64(np.eye(2100)))
+    with pytest.raises(nys.NysError) as e:
+        nys.nys_sketch(big, 2049, seed=1)
+    assert e.value.status == nys.NYS_ERR_ARG
+    Pbig = nys.Precond(t64(np.eye(2100)[:, :2049]), t64(np.ones(2049)))
+    with pytest.raises(nys.NysError) as e:
+        nys.nys_pcg_solve(big, Pbig, 0.5, t64(np.ones(2100)), maxit=5)
+    assert e.value.status == nys.NYS_ERR_ARG
     # zero columns past the first 32 x 32 block: the zero pivot (column 40) is
     # met by a later step of the blocked Cholesky, not by its first block
     om_bad = np.random.default_rng(5).standard_normal((200, 70))
