@@ -12,6 +12,8 @@ textbook formula).
 
 Pinned parts (tests/test_oracle_*.py):
   operators        -- against scipy.spatial.distance / explicit products
+  XtDXOp           -- row-by-row sum of d_i x_i x_i^T, d = 1 reduces to XtXOp,
+                      one-hot d gives the rank-one x_k x_k^T
   nystrom          -- Lemma (Nystrom properties), closed form of eq. (nys-unstable),
                       exact recovery for rank(A) <= l
   precond          -- P P^{-1} = I, spectrum of P^{-1}, Woodbury identity
@@ -41,7 +43,7 @@ Parity unpinned: none of the functions above is unpinned; the mixed-precision
 forms have no oracle of their own (they are judged by this FP64 oracle's true
 residual).
 """
-from .operators import DenseOp, XtXOp, RBFOp, rbf_kernel_block  # noqa: F401
+from .operators import DenseOp, XtXOp, XtDXOp, RBFOp, rbf_kernel_block  # noqa: F401
 from .nystrom import orthonormalize, matlab_eps, randomized_nystrom, nystrom_factor  # noqa: F401
 from .precond import precond_inv_apply, precond_matrix, precond_inv_matrix  # noqa: F401
 from .pcg import nystrom_pcg, true_relres, dense_solve  # noqa: F401

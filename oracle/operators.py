@@ -6,6 +6,11 @@ the method touches A through matvecs).  Three forms:
 * DenseOp  -- an explicit symmetric n x n matrix.
 * XtXOp    -- ridge normal equations, A = scale * X^T X for data X (m x n)
               (Section 1.4, eq. (RidgeRegression); scale absorbs the 1/n factor).
+* XtDXOp   -- weighted normal equations, A = scale * X^T D X with D = diag(d),
+              d >= 0: the data term of the Hessian of a regularised
+              generalised linear model (logistic weights p (1 - p)), the
+              operator of approximate leave-one-out cross-validation
+              (Section 6.2, "Approximate cross-validation").
 * RBFOp    -- Gaussian kernel matrix K_ij = exp(-||x_i - x_j||^2 / (2 sigma^2))
               for points x_i (rows of X, n x d) (Section 6.3, kernel ridge
               regression).  K is never stored whole; row blocks are formed on
@@ -45,6 +50,24 @@ class XtXOp:
 
     def dense(self) -> np.ndarray:
         return self.scale * (self.X.T @ self.X)
+
+
+class XtDXOp:
+    def __init__(self, X: np.ndarray, d: np.ndarray, scale: float = 1.0):
+        self.X = np.asarray(X, dtype=np.float64)
+        self.d = np.asarray(d, dtype=np.float64)
+        self.scale = float(scale)
+        self.n = self.X.shape[1]
+
+    def matmat(self, V: np.ndarray) -> np.ndarray:
+        # A V = scale * X^T (D (X V)): the diagonal weights act between the
+        # two products.
+        XV = self.X @ V
+        DXV = self.d[:, None] * XV if XV.ndim == 2 else self.d * XV
+        return self.scale * (self.X.T @ DXV)
+
+    def dense(self) -> np.ndarray:
+        return self.scale * (self.X.T @ (self.d[:, None] * self.X))
 
 
 def rbf_kernel_block(Xr: np.ndarray, Xc: np.ndarray, sigma: float) -> np.ndarray:
