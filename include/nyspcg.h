@@ -247,6 +247,27 @@ size_t nys_workspace_size_columns(const nys_operator* A, int64_t ell);
 nys_status nys_sketch_columns(const nys_operator* A, int64_t ell, const int64_t* idx, double* Omega_out,
                               double* Y_out, void* ws, size_t ws_bytes, void* stream);
 
+/* ---- Weighted normal equations X^T D X (Section 6.2, "Approximate
+ * cross-validation": the Hessian of a regularised generalised linear model,
+ * e.g. logistic weights d_i = p_i (1 - p_i)) ---- */
+
+/* Bytes of workspace for nys_weight_rows (a device flag). */
+size_t nys_workspace_size_weight_rows(void);
+
+/* Xw = D^{1/2} X for D = diag(d): row i of Xw is sqrt(d_i) times row i of X,
+ * so that an NYS_OP_XTX operator on Xw (rows x cols, leading dimension ldw,
+ * the same dtype) is A = scale X^T D X.  Weights are folded once; every later
+ * product is the one-pass X^T X product.  X, Xw: device, dtype NYS_F64 or
+ * NYS_F32, row-major with leading dimensions ldx, ldw >= cols; Xw may be X
+ * (in place, ldw == ldx) or a buffer that does not overlap it.  d: device
+ * float64, rows entries, each finite and >= 0 (checked on the device before
+ * anything is written).  sqrt(d_i) is rounded to the data type once, so a
+ * float32 Xw carries one more float32 rounding per entry.  Errors:
+ * NYS_ERR_ARG (shapes, dtype, a negative or non-finite weight: X and Xw are
+ * left unchanged), NYS_ERR_WORKSPACE.  Synchronises the stream once. */
+nys_status nys_weight_rows(int64_t rows, int64_t cols, int32_t dtype, const void* X, int64_t ldx,
+                           const double* d, void* Xw, int64_t ldw, void* ws, size_t ws_bytes, void* stream);
+
 /* ---- Block Nystrom PCG (Section "Block Nystrom PCG") ---- */
 
 /* Bytes of workspace for nys_block_pcg_solve with preconditioner rank ell and

@@ -31,7 +31,8 @@ EXPORTED = ["nys_workspace_size", "nys_gaussian", "nys_sketch", "nys_factor", "n
             "nys_pcg_backward", "nys_rbf_cross", "nys_workspace_size_adaptive", "nys_power_err_est",
             "nys_nystrom_adaptive", "nys_workspace_size_columns", "nys_sketch_columns",
             "nys_workspace_size_sketch_solve", "nys_sketch_solve", "nys_workspace_size_block",
-            "nys_block_pcg_solve", "nys_timing_begin", "nys_timing_end", "nys_last_error", "nys_version"]
+            "nys_block_pcg_solve", "nys_workspace_size_weight_rows", "nys_weight_rows", "nys_timing_begin",
+            "nys_timing_end", "nys_last_error", "nys_version"]
 
 
 class NysError(RuntimeError):
@@ -109,10 +110,13 @@ def lib():
         L.nys_workspace_size_block.argtypes = [P(_Operator), i64, i64]
         L.nys_block_pcg_solve.argtypes = [P(_Operator), P(_Precond), dbl, vp, i64, i64, vp, i64, P(_Opts), P(_Info),
                                           vp, sz, vp]
+        L.nys_workspace_size_weight_rows.restype = sz
+        L.nys_workspace_size_weight_rows.argtypes = []
+        L.nys_weight_rows.argtypes = [i64, i64, i32, vp, i64, vp, vp, i64, vp, sz, vp]
         for f in ("nys_gaussian", "nys_sketch", "nys_factor", "nys_op_apply", "nys_precond_apply",
                   "nys_pcg_solve", "nys_pcg_solve_ragged", "nys_pcg_backward", "nys_rbf_cross",
                   "nys_power_err_est", "nys_nystrom_adaptive", "nys_sketch_columns", "nys_sketch_solve",
-                  "nys_block_pcg_solve", "nys_timing_begin", "nys_timing_end"):
+                  "nys_block_pcg_solve", "nys_weight_rows", "nys_timing_begin", "nys_timing_end"):
             getattr(L, f).restype = ctypes.c_int
         L.nys_last_error.restype = ctypes.c_char_p
         L.nys_version.restype = ctypes.c_char_p
@@ -166,6 +170,12 @@ class Operator:
     def xtx(X: torch.Tensor, scale: float = 1.0) -> "Operator":
         X = X.contiguous()
         return Operator(NYS_OP_XTX, X, X.shape[1], scale=scale)
+
+    @staticmethod
+    def xtdx(X: torch.Tensor, d: torch.Tensor, scale: float = 1.0) -> "Operator":
+        """A = scale X^T D X, D = diag(d), d >= 0: the rows are weighted once on
+        the device (nys_weight_rows) and A is the X^T X operator of D^{1/2} X."""
+        return Operator.xtx(nys_weight_rows(X, d), scale)
 
     @staticmethod
     def rbf(X: torch.Tensor, sigma: float, scale: float = 1.0) -> "Operator":
@@ -243,6 +253,24 @@ def nys_factor(Omega: torch.Tensor, Y: torch.Tensor, dtype=torch.float64,
         ws = _ws_shape(n, ell, 1, Y.device) if op is None else workspace(op, ell)
     _check(lib().nys_factor(_ptr(Omega), _ptr(Y), ctypes.byref(p), prec, _ptr(ws), ws.numel(), _stream()))
     return Precond(U, lam, p.nu)
+
+
+def nys_weight_rows(X: torch.Tensor, d: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """D^{1/2} X for weights d >= 0, one per row of X (float64 or float32 X);
+    out may be X itself (in place)."""
+    if X.dim() != 2 or X.stride(1) != 1:
+        raise ValueError("X must be a row-major 2-D tensor")
+    d = d.to(device=X.device, dtype=torch.float64).contiguous()
+    if d.numel() != X.shape[0]:
+        raise ValueError("need one weight per row of X")
+    if out is None:
+        out = torch.empty_like(X, memory_format=torch.contiguous_format)
+    elif out.shape != X.shape or out.dtype != X.dtype or out.device != X.device or out.stride(1) != 1:
+        raise ValueError("out must be a row-major tensor of X's shape, dtype and device")
+    ws = torch.empty(lib().nys_workspace_size_weight_rows(), dtype=torch.uint8, device=X.device)
+    _check(lib().nys_weight_rows(X.shape[0], X.shape[1], _dt(X), _ptr(X), X.stride(0), _ptr(d), _ptr(out),
+                                 out.stride(0), _ptr(ws), ws.numel(), _stream()))
+    return out
 
 
 def nys_sketch_solve(P: Precond, mu: float, B: torch.Tensor, ws: Optional[torch.Tensor] = None) -> torch.Tensor:
