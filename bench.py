@@ -75,7 +75,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="ridge",
                     choices=["ridge", "krr_small", "krr", "krr_cols", "batched", "diff", "adaptive",
-                             "sketch_solve", "block"])
+                             "sketch_solve", "block", "weighted"])
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--matvec-reps", type=int, default=30)
@@ -390,6 +390,55 @@ def run_sketch_solve(args, nys, torch):
         {"correct": info.relres[0] <= tol, "pcg_relres": info.relres[0], "pcg_iters": info.iters[0],
          "sketch_and_solve": {str(k): v for k, v in res.items()},
          "sketch_and_solve_reaches_tol": any(v["relres"] <= tol for v in res.values())})
+
+
+# --------------------------------------------------------------------------- weighted (ALOOCV operator)
+
+def run_weighted(args, nys, torch):
+    """The ALOOCV operator X^T D X + mu I on the ridge data (X 20000 x 4000
+    float32, l = 500, mu = 1e-4) with seeded logistic Hessian weights
+    d = p (1 - p): the weights are folded once (nys_weight_rows, timed with
+    its own roofline), then whole solves in the ridge line's chosen form."""
+    from workloads import logistic_weights, ridge_dense
+    dev = "cuda:0"
+    m, n, ell = 20000, (args.n or 4000), 500
+    w = ridge_dense(m=m, n=n, ell=ell, with_omega=False)
+    d_h = logistic_weights(m)
+    X = torch.as_tensor(w["X"], device=dev)
+    d = torch.as_tensor(d_h, device=dev)
+    # right-hand side X^T D y (input synthesis on the host, float64)
+    b = torch.as_tensor(w["X"].astype(np.float64).T @ (d_h * w["y"]), device=dev)
+    mu, tol = w["mu"], 1e-10
+    Xw = torch.empty_like(X)
+    fold_ms = kernel_avg_ms(torch, lambda: nys.nys_weight_rows(X, d, out=Xw), 10)
+    op = nys.Operator.xtx(Xw)
+    prec = nys.NYS_PREC_BF16X3_REFINE64
+    ws = nys.workspace(op, ell, 1, prec)
+    kw = dict(maxit=1000, inner_tol=3e-6)
+    for i in range(args.warmup):
+        full_solve(nys, torch, op, ell, 1000 + i, prec, torch.float32, mu, b, ws, tol, Timer(torch), **kw)
+    tm = Timer(torch)
+    infos = []
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for i in range(args.steps):
+        _, info, _ = full_solve(nys, torch, op, ell, 20211002 + i, prec, torch.float32, mu, b, ws, tol, tm, **kw)
+        infos.append(info)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t
+    fold_bytes = 2 * m * n * 4 + m * 8
+    fold_gbs = fold_bytes / (fold_ms * 1e-3) / 1e9
+    return base_record(
+        args, args.steps / el, 1e3 * el / args.steps, "bf16x3+f32+f64",
+        {"workload": "ALOOCV operator X^T D X + mu I, X %dx%d float32 (ridge data), d = p(1-p) logistic weights, "
+                     "mu=1e-4, l=%d, tol 1e-10 (true float64 residual of the folded operator)" % (m, n, ell),
+         "precision": "weights folded once (D^{1/2} X, float32); then the ridge line's chosen form",
+         "step": "Gaussian Omega + sketch + factor + PCG solve (folding excluded: once per operator)"},
+        {"correct": all(i.relres[0] <= tol and i.status[0] == 0 for i in infos),
+         "relres": max(i.relres[0] for i in infos), "iters": infos[-1].iters[0],
+         "refine_steps": infos[-1].refine_steps, "phase_ms": {k: 1e3 * v / args.steps for k, v in tm.t.items()},
+         "fold": {"kernel": "check_weights + weight_rows", "ms": fold_ms, "bytes": fold_bytes,
+                  "achieved_gbs": fold_gbs, "frac_of_hbm_peak": fold_gbs / HBM_PEAK_GBS}})
 
 
 # --------------------------------------------------------------------------- block PCG
@@ -730,7 +779,7 @@ def main():
           "krr_small": lambda a, n, t: run_krr(a, n, t, small=True), "krr": run_krr,
           "krr_cols": lambda a, n, t: run_krr(a, n, t, columns=True),
           "batched": run_batched, "diff": run_diff, "adaptive": run_adaptive,
-          "sketch_solve": run_sketch_solve, "block": run_block}[args.workload]
+          "sketch_solve": run_sketch_solve, "block": run_block, "weighted": run_weighted}[args.workload]
     out = fn(args, nys, torch)
     print(json.dumps(out), flush=True)
 

@@ -11,6 +11,7 @@ import pytest
 torch = pytest.importorskip("torch")
 
 import oracle  # noqa: E402
+from workloads import logistic_weights  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 
@@ -34,11 +35,7 @@ def _case(m=1203, n=301, seed=81, dtype=np.float64, decay=False):
     X = rng.standard_normal((m, n)) / np.sqrt(m)
     if decay:
         X = X / np.sqrt(np.arange(1, n + 1))
-    X = X.astype(dtype)
-    p = 1.0 / (1.0 + np.exp(-2.0 * rng.standard_normal(m)))
-    d = p * (1.0 - p)
-    d[::17] = 0.0
-    return X, d
+    return X.astype(dtype), logistic_weights(m, seed + 1000)
 
 
 @pytest.mark.parametrize("dtype", [np.float64, np.float32])
@@ -79,7 +76,7 @@ def test_weighted_solve_meets_tolerance_on_oracle_operator():
     assert info.status[0] == 0
     ref = oracle.XtDXOp(X, d)
     assert oracle.true_relres(ref, mu, h(x), b) <= 1.01e-10
-    # the preconditioner did its work: the oracle's plain CG needs 153
+    # the preconditioner did its work: the oracle's plain CG needs 154
     # iterations here, its Nystrom PCG with the same test matrix 61
     plain = oracle.nystrom_pcg(ref.matmat, b, mu, lambda v: v, tol=1e-10, maxit=2000)
     assert info.iters[0] * 2 <= plain["iters"]

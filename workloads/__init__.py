@@ -23,4 +23,5 @@ from .synth import (  # noqa: F401
     differentiation,
     spectrum_psd,
     lowrank_psd,
+    logistic_weights,
 )

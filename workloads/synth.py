@@ -55,6 +55,19 @@ def ridge_dense(m: int = 20000, n: int = 4000, ell: int = 500, seed: int = 20211
     return dict(kind="xtx", X=X, mu=1e-4, ell=ell, y=y, omega0=omega0, tol=1e-10)
 
 
+def logistic_weights(m: int, seed: int = 20211007, zero_every: int = 17) -> np.ndarray:
+    """Hessian weights of a logistic model, d_i = p_i (1 - p_i) in [0, 1/4],
+    with p_i = 1 / (1 + exp(-2 z_i)), z ~ N(0, 1) (a fitted model's spread of
+    confidences); every zero_every-th weight is 0 (points the model fits with
+    certainty), 0 for none."""
+    z = np.random.default_rng(seed).standard_normal(m)
+    p = 1.0 / (1.0 + np.exp(-2.0 * z))
+    d = p * (1.0 - p)
+    if zero_every > 0:
+        d[::zero_every] = 0.0
+    return d
+
+
 def _mixture(rng, n: int, d: int, k: int = 10):
     means = 2.0 * rng.standard_normal((k, d))
     lab = rng.integers(0, k, n)
