@@ -7,6 +7,7 @@
 // operator of Xw: one pass over the data per product, the same kernels and
 // roofline as unweighted ridge regression.
 #include <cmath>
+#include <cstdint>
 
 #include "common.hpp"
 
@@ -35,6 +36,41 @@ __global__ __launch_bounds__(256) void weight_rows(int64_t cols, const T* X, int
   T* wr = Xw + i * ldw;
   for (int64_t j = threadIdx.x; j < cols; j += 256) wr[j] = s * xr[j];
 }
+
+// The same with 16-byte accesses (float4 / double2) when every row starts on
+// a 16-byte boundary and the columns fill whole vectors; the products are the
+// scalar kernel's, element by element.
+__global__ __launch_bounds__(256) void weight_rows_f4(int64_t cvec, const float* X, int64_t ldx,
+                                                      const double* __restrict__ d, float* Xw, int64_t ldw) {
+  const int64_t i = blockIdx.x;
+  const float s = float(sqrt(d[i]));
+  const float4* xr = reinterpret_cast<const float4*>(X + i * ldx);
+  float4* wr = reinterpret_cast<float4*>(Xw + i * ldw);
+  for (int64_t j = threadIdx.x; j < cvec; j += 256) {
+    float4 v = xr[j];
+    v.x = s * v.x;
+    v.y = s * v.y;
+    v.z = s * v.z;
+    v.w = s * v.w;
+    wr[j] = v;
+  }
+}
+
+__global__ __launch_bounds__(256) void weight_rows_d2(int64_t cvec, const double* X, int64_t ldx,
+                                                      const double* __restrict__ d, double* Xw, int64_t ldw) {
+  const int64_t i = blockIdx.x;
+  const double s = sqrt(d[i]);
+  const double2* xr = reinterpret_cast<const double2*>(X + i * ldx);
+  double2* wr = reinterpret_cast<double2*>(Xw + i * ldw);
+  for (int64_t j = threadIdx.x; j < cvec; j += 256) {
+    double2 v = xr[j];
+    v.x = s * v.x;
+    v.y = s * v.y;
+    wr[j] = v;
+  }
+}
+
+bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
 
 }  // namespace
 }  // namespace nys
@@ -67,9 +103,18 @@ nys_status nys_weight_rows(int64_t rows, int64_t cols, int32_t dtype, const void
   NYS_HIP(hipMemcpyAsync(&bad_h, bad, sizeof(int), hipMemcpyDeviceToHost, s));
   NYS_HIP(hipStreamSynchronize(s));
   NYS_ARG(!bad_h, "nys_weight_rows: weights must be finite and >= 0");
-  if (dtype == NYS_F64)
+  // 16-byte accesses when each row starts 16-byte aligned and holds whole vectors
+  const int w = dtype == NYS_F64 ? 2 : 4;
+  const bool vec = aligned16(X) && aligned16(Xw) && cols % w == 0 && ldx % w == 0 && ldw % w == 0;
+  if (dtype == NYS_F64 && vec)
+    hipLaunchKernelGGL(weight_rows_d2, dim3((unsigned)rows), dim3(256), 0, s, cols / 2,
+                       static_cast<const double*>(X), ldx, d, static_cast<double*>(Xw), ldw);
+  else if (dtype == NYS_F64)
     hipLaunchKernelGGL(weight_rows<double>, dim3((unsigned)rows), dim3(256), 0, s, cols,
                        static_cast<const double*>(X), ldx, d, static_cast<double*>(Xw), ldw);
+  else if (vec)
+    hipLaunchKernelGGL(weight_rows_f4, dim3((unsigned)rows), dim3(256), 0, s, cols / 4,
+                       static_cast<const float*>(X), ldx, d, static_cast<float*>(Xw), ldw);
   else
     hipLaunchKernelGGL(weight_rows<float>, dim3((unsigned)rows), dim3(256), 0, s, cols,
                        static_cast<const float*>(X), ldx, d, static_cast<float*>(Xw), ldw);

@@ -39,8 +39,10 @@ def _case(m=1203, n=301, seed=81, dtype=np.float64, decay=False):
 
 
 @pytest.mark.parametrize("dtype", [np.float64, np.float32])
-def test_weight_rows_folds_square_roots(dtype):
-    X, d = _case(dtype=dtype)
+@pytest.mark.parametrize("n", [301, 64])
+def test_weight_rows_folds_square_roots(dtype, n):
+    """301 columns take the scalar kernel, 64 the 16-byte vector one."""
+    X, d = _case(n=n, dtype=dtype)
     Xw = h(nys.nys_weight_rows(torch.as_tensor(X, device=DEV), torch.as_tensor(d, device=DEV)))
     # one rounding of sqrt(d_i) to the data type, one of the product
     want = np.sqrt(d).astype(dtype)[:, None] * X
