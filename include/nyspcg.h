@@ -19,6 +19,8 @@
  *   - `stream` is the caller's hipStream_t (NULL = default stream).  Work is
  *     enqueued on it in order.  nys_factor and nys_pcg_solve* synchronise that
  *     stream to read convergence and failure flags; the other calls do not.
+ *     nys_pcg_solve with opts.device_info = 1 neither synchronises nor reads
+ *     device memory on the host, so it can be captured into a HIP graph.
  *   - Inputs are never written, except the buffers documented as in/out.
  *   - Errors are returned as nys_status codes; no C++ exception crosses the
  *     ABI.  nys_last_error() returns a message for the last non-OK status of
@@ -60,12 +62,30 @@ typedef enum {
 
 /* The operator A (Section 1.1: A is reached only through products). */
 typedef enum {
-  NYS_OP_DENSE = 0,  /* explicit symmetric A: data is n x n                    */
-  NYS_OP_XTX = 1,    /* ridge normal equations A = scale X^T X (Section 1.4,
-                        eq. (RidgeRegression)): data X is rows x n             */
-  NYS_OP_RBF = 2     /* Gaussian kernel K_ij = exp(-|x_i-x_j|^2/(2 sigma^2))
-                        (Section 6.3): data is n x d, one point per row       */
+  NYS_OP_DENSE = 0,   /* explicit symmetric A: data is n x n                   */
+  NYS_OP_XTX = 1,     /* ridge normal equations A = scale X^T X (Section 1.3,
+                         eq. (RidgeRegression)): data X is rows x n            */
+  NYS_OP_RBF = 2,     /* Gaussian kernel K_ij = exp(-|x_i-x_j|^2/(2 sigma^2))
+                         (kernel ridge regression, Section 6.5): data is n x d,
+                         one point per row                                     */
+  NYS_OP_CALLBACK = 3 /* A given only as a product routine of the caller
+                         (Section 1.1: the method needs nothing but products
+                         with A): `apply` below; data, rows, cols, ld unused   */
 } nys_op_kind;
+
+/* Product routine of an NYS_OP_CALLBACK operator: W = A V for k columns,
+ * V and W row-major n x k blocks (device pointers, leading dimensions ldv and
+ * ldw in elements) of type `dtype` (NYS_F64 or NYS_F32), enqueued on `stream`
+ * (the hipStream_t of the library call; the routine must not synchronise it
+ * when the call is being captured into a graph).  The library applies scale
+ * and the shift itself: it uses scale * W + mu V.  The routine returns 0 on
+ * success; any other value makes the library call return NYS_ERR_DEVICE.  A
+ * routine that does not support NYS_F32 should return nonzero for it: the
+ * float32 inner solves of the reduced-precision modes call it with NYS_F32,
+ * everything else with NYS_F64.  It may be called from inside any library
+ * call that takes the operator, on the calling host thread. */
+typedef int32_t (*nys_apply_fn)(void* ctx, int64_t k, int32_t dtype, const void* V, int64_t ldv, void* W,
+                                int64_t ldw, void* stream);
 
 typedef struct {
   int32_t kind;      /* nys_op_kind                                           */
@@ -77,6 +97,8 @@ typedef struct {
   int64_t ld;        /* leading dimension of data, >= cols                    */
   double sigma;      /* RBF bandwidth (> 0); ignored otherwise                */
   double scale;      /* A = scale * (base operator); must be > 0              */
+  nys_apply_fn apply;/* NYS_OP_CALLBACK: the product routine; NULL otherwise  */
+  void* ctx;         /* NYS_OP_CALLBACK: passed to apply unchanged            */
 } nys_operator;
 
 /* Factored Nystrom approximation A_hat = U diag(lam) U^T (output of the
@@ -102,13 +124,24 @@ typedef struct {
                           <= 0: chosen from the measured iteration time (1 .. 32) */
   double inner_tol;    /* refinement modes: relative reduction asked of each
                           inner solve; 0 selects 1e-4                          */
+  int32_t device_info; /* 0: the call waits for the device and fills the host
+                          arrays of nys_solve_info.  1: nothing is read back and
+                          the stream is never synchronised (graph capture):
+                          the info arrays are DEVICE arrays written by the last
+                          kernels of the call, and the iteration counts are
+                          fixed in advance (see nys_pcg_solve)                  */
+  int32_t pad_;
 } nys_solve_opts;
 
 typedef struct {
-  int32_t* iters;      /* host, one per column: PCG iterations (all inner)      */
-  double* relres;      /* host, one per column: final relative residual (float64
-                          true residual in refinement modes, recursive otherwise) */
-  int32_t* status;     /* host, one per column: nys_status                      */
+  int32_t* iters;      /* host (device when opts.device_info = 1), one per
+                          column: PCG iterations (all inner)                    */
+  double* relres;      /* host (device when opts.device_info = 1), one per
+                          column: final relative residual (float64 true
+                          residual in refinement modes and with device_info,
+                          recursive otherwise)                                  */
+  int32_t* status;     /* host (device when opts.device_info = 1), one per
+                          column: nys_status                                    */
   int32_t refine_steps;/* output: outer refinement steps taken                  */
   int32_t total_iters; /* output: iteration sweeps executed (max over columns)  */
 } nys_solve_info;
@@ -170,13 +203,29 @@ nys_status nys_precond_apply(const nys_precond* P, double mu, const double* R, i
 
 /* Nystrom PCG (Section 5.2, algorithm "Nystrom PCG") for nmu*nrhs independent
  * systems that share A and P: column c = m*nrhs + r solves
- * (A + mu[m] I) x = B[:, r] (Section 5.2.2 block form read as independent
+ * (A + mu[m] I) x = B[:, r] (Section 5.2.3, Block Nystrom PCG, read as independent
  * columns; the mu grid reuses one preconditioner, which does not depend on mu).
  * mu: host array of nmu values >= 0.  B: device float64 n x nrhs (ldb).
  * X: device float64 n x (nmu*nrhs) (ldx); on entry the initial guesses, on exit
  * the solutions.  info: host arrays of nmu*nrhs entries (may be NULL).
  * Returns NYS_OK when every column met tol, NYS_NOT_CONVERGED when some hit
- * the cap, NYS_ERR_BREAKDOWN when p^T v <= 0 occurred. */
+ * the cap, NYS_ERR_BREAKDOWN when p^T v <= 0 occurred.
+ *
+ * Device-info form (o->device_info = 1), for callers that capture the call
+ * into a HIP graph or cannot wait for the device: the host only checks the
+ * arguments and enqueues kernels (no synchronisation, no device-to-host copy,
+ * no memset node).  Every mu must be > 0.  No column is dropped early and
+ * nothing is decided on the host: the float64 and float32 modes run exactly
+ * maxit iterations, the refinement modes exactly max_refine outer steps of
+ * maxit inner iterations each; a column that has met its tolerance (or broken
+ * down) is frozen by device flags, so the remaining iterations change nothing
+ * for it.  In the float64 mode no correction solve follows.  At the end
+ * info->iters / relres / status (device arrays of nmu*nrhs entries; may be
+ * NULL pointers individually) receive the iterations each column ran, its
+ * float64 true relative residual, and NYS_OK (true residual <= tol),
+ * NYS_NOT_CONVERGED or NYS_ERR_BREAKDOWN; info->refine_steps and
+ * info->total_iters (host fields) receive the fixed counts.  The return
+ * value only reports argument errors (NYS_OK once everything is enqueued). */
 nys_status nys_pcg_solve(const nys_operator* A, const nys_precond* P, const double* mu, int64_t nmu,
                          const double* B, int64_t nrhs, int64_t ldb, double* X, int64_t ldx,
                          const nys_solve_opts* o, nys_solve_info* info, void* ws, size_t ws_bytes,
@@ -247,7 +296,7 @@ size_t nys_workspace_size_columns(const nys_operator* A, int64_t ell);
 nys_status nys_sketch_columns(const nys_operator* A, int64_t ell, const int64_t* idx, double* Omega_out,
                               double* Y_out, void* ws, size_t ws_bytes, void* stream);
 
-/* ---- Weighted normal equations X^T D X (Section 6.2, "Approximate
+/* ---- Weighted normal equations X^T D X (Section 6.3, "Approximate
  * cross-validation": the Hessian of a regularised generalised linear model,
  * e.g. logistic weights d_i = p_i (1 - p_i)) ---- */
 

@@ -5,14 +5,14 @@ the method touches A through matvecs).  Three forms:
 
 * DenseOp  -- an explicit symmetric n x n matrix.
 * XtXOp    -- ridge normal equations, A = scale * X^T X for data X (m x n)
-              (Section 1.4, eq. (RidgeRegression); scale absorbs the 1/n factor).
+              (Section 1.3, eq. (RidgeRegression); scale absorbs the 1/n factor).
 * XtDXOp   -- weighted normal equations, A = scale * X^T D X with D = diag(d),
               d >= 0: the data term of the Hessian of a regularised
               generalised linear model (logistic weights p (1 - p)), the
               operator of approximate leave-one-out cross-validation
-              (Section 6.2, "Approximate cross-validation").
+              (Section 6.3, "Approximate cross-validation").
 * RBFOp    -- Gaussian kernel matrix K_ij = exp(-||x_i - x_j||^2 / (2 sigma^2))
-              for points x_i (rows of X, n x d) (Section 6.3, kernel ridge
+              for points x_i (rows of X, n x d) (Section 6.5, kernel ridge
               regression).  K is never stored whole; row blocks are formed on
               demand.
 

@@ -23,7 +23,7 @@ NYS_OK, NYS_NOT_CONVERGED = 0, 1
 NYS_ERR_ARG, NYS_ERR_NOT_PSD, NYS_ERR_BREAKDOWN, NYS_ERR_DEVICE, NYS_ERR_WORKSPACE = -1, -2, -3, -4, -5
 NYS_F64, NYS_F32 = 0, 1
 NYS_PREC_FP64, NYS_PREC_FP32, NYS_PREC_FP32_REFINE64, NYS_PREC_BF16X3_REFINE64 = 0, 1, 2, 3
-NYS_OP_DENSE, NYS_OP_XTX, NYS_OP_RBF = 0, 1, 2
+NYS_OP_DENSE, NYS_OP_XTX, NYS_OP_RBF, NYS_OP_CALLBACK = 0, 1, 2, 3
 NYS_ADA_ERR, NYS_ADA_ERR_LAM, NYS_ADA_RATIO = 0, 1, 2
 
 EXPORTED = ["nys_workspace_size", "nys_gaussian", "nys_sketch", "nys_factor", "nys_op_apply",
@@ -41,10 +41,17 @@ class NysError(RuntimeError):
         self.status = status
 
 
+# nys_apply_fn: int32 (*)(void* ctx, int64 k, int32 dtype, const void* V, int64 ldv, void* W, int64 ldw,
+#                        void* stream)
+APPLY_FN = ctypes.CFUNCTYPE(ctypes.c_int32, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p,
+                            ctypes.c_int64, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p)
+
+
 class _Operator(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("dtype", ctypes.c_int32), ("n", ctypes.c_int64),
                 ("data", ctypes.c_void_p), ("rows", ctypes.c_int64), ("cols", ctypes.c_int64),
-                ("ld", ctypes.c_int64), ("sigma", ctypes.c_double), ("scale", ctypes.c_double)]
+                ("ld", ctypes.c_int64), ("sigma", ctypes.c_double), ("scale", ctypes.c_double),
+                ("apply", APPLY_FN), ("ctx", ctypes.c_void_p)]
 
 
 class _Precond(ctypes.Structure):
@@ -56,7 +63,7 @@ class _Precond(ctypes.Structure):
 class _Opts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("maxit", ctypes.c_int32), ("prec", ctypes.c_int32),
                 ("max_refine", ctypes.c_int32), ("check_every", ctypes.c_int32),
-                ("inner_tol", ctypes.c_double)]
+                ("inner_tol", ctypes.c_double), ("device_info", ctypes.c_int32), ("pad_", ctypes.c_int32)]
 
 
 class _Info(ctypes.Structure):
@@ -152,14 +159,64 @@ def _dt(t: torch.Tensor) -> int:
 
 # --------------------------------------------------------------------------- operators
 
+class _DeviceArray:
+    """A device buffer described by the CUDA array interface, so that torch can
+    view memory the library hands to a product routine without copying it."""
+
+    def __init__(self, ptr: int, rows: int, cols: int, ld: int, dtype: torch.dtype):
+        isz = 8 if dtype == torch.float64 else 4
+        self.__cuda_array_interface__ = {
+            "shape": (rows, cols), "typestr": "<f%d" % isz, "data": (int(ptr), False),
+            "strides": (ld * isz, isz), "version": 2}
+
+
+def device_view(ptr: int, rows: int, cols: int, ld: int, dtype: torch.dtype, device) -> torch.Tensor:
+    """A rows x cols torch view (leading dimension ld) of device memory at ptr."""
+    return torch.as_tensor(_DeviceArray(ptr, rows, cols, ld, dtype), device=device)
+
+
 @dataclass
 class Operator:
-    """A (Section 1.1) as a dense matrix, ridge data X (A = scale X^T X) or RBF points."""
+    """A (Section 1.1) as a dense matrix, ridge data X (A = scale X^T X), RBF
+    points, or a caller's product routine (NYS_OP_CALLBACK)."""
     kind: int
     data: torch.Tensor
     n: int
     sigma: float = 0.0
     scale: float = 1.0
+    fn: Optional[object] = None  # NYS_OP_CALLBACK: the ctypes product routine (kept alive here)
+
+    @staticmethod
+    def callback(apply, n: int, device="cuda", scale: float = 1.0) -> "Operator":
+        """A given only through the product routine
+        apply(k, dtype, V_ptr, ldv, W_ptr, ldw, stream_ptr) -> int, which enqueues
+        W = A V (n x k blocks, NYS_F64 or NYS_F32 entries) on the given stream and
+        returns 0 (the library adds scale and the shift)."""
+        def raw(_ctx, k, dt, V, ldv, W, ldw, stream):
+            try:
+                return int(apply(int(k), int(dt), V, int(ldv), W, int(ldw), stream))
+            except Exception:  # an exception must not cross the C frames
+                return -1
+        fn = APPLY_FN(raw)
+        return Operator(NYS_OP_CALLBACK, torch.empty(1, dtype=torch.float64, device=device), int(n), scale=scale,
+                        fn=fn)
+
+    @staticmethod
+    def from_function(f, n: int, device="cuda", scale: float = 1.0) -> "Operator":
+        """A given as a torch function W = f(V) on n x k device tensors (float64,
+        or float32 in the reduced-precision modes), run on the library call's
+        stream."""
+        dev = torch.device(device)
+
+        def apply(k, dt, V, ldv, W, ldw, stream):
+            dtype = torch.float64 if dt == NYS_F64 else torch.float32
+            st = torch.cuda.ExternalStream(stream, device=dev) if stream else torch.cuda.default_stream(dev)
+            with torch.cuda.stream(st):
+                Vt = device_view(V, n, k, ldv, dtype, dev)
+                Wt = device_view(W, n, k, ldw, dtype, dev)
+                Wt.copy_(f(Vt))
+            return 0
+        return Operator.callback(apply, n, device, scale)
 
     @staticmethod
     def dense(A: torch.Tensor) -> "Operator":
@@ -184,8 +241,11 @@ class Operator:
 
     def c(self) -> _Operator:
         d = self.data
+        if self.kind == NYS_OP_CALLBACK:
+            return _Operator(self.kind, NYS_F64, self.n, None, self.n, self.n, self.n, 0.0, self.scale, self.fn,
+                             None)
         return _Operator(self.kind, _dt(d), self.n, _ptr(d), d.shape[0], d.shape[1], d.stride(0),
-                         self.sigma, self.scale)
+                         self.sigma, self.scale, APPLY_FN(), None)
 
 
 @dataclass
@@ -386,8 +446,8 @@ class SolveInfo:
     code: int
 
 
-def _opts(tol, maxit, prec, max_refine, check_every, inner_tol):
-    return _Opts(tol, maxit, prec, max_refine, check_every, inner_tol)
+def _opts(tol, maxit, prec, max_refine, check_every, inner_tol, device_info=0):
+    return _Opts(tol, maxit, prec, max_refine, check_every, inner_tol, device_info, 0)
 
 
 def nys_pcg_solve(op: Operator, P: Precond, mu, B: torch.Tensor, X0: Optional[torch.Tensor] = None,
@@ -418,6 +478,39 @@ def nys_pcg_solve(op: Operator, P: Precond, mu, B: torch.Tensor, X0: Optional[to
     if B.dim() == 1 and k == 1:
         X = X.reshape(-1)
     return X, si
+
+
+def nys_pcg_solve_device(op: Operator, P: Precond, mu, B: torch.Tensor, X: torch.Tensor, iters: torch.Tensor,
+                         relres: torch.Tensor, status: torch.Tensor, tol: float = 1e-10, maxit: int = 500,
+                         prec: int = NYS_PREC_FP64, max_refine: int = 10, inner_tol: float = 1e-4,
+                         ws: Optional[torch.Tensor] = None):
+    """Device-info form of nys_pcg_solve (opts.device_info = 1): nothing is read
+    back and the stream is never synchronised, so the call can be captured into
+    a graph.  B: n x nrhs float64, X: n x (nmu*nrhs) float64 (in: x0, out: x),
+    both contiguous; iters (int32), relres (float64), status (int32): device
+    tensors of nmu*nrhs entries written by the call's last kernels.  Runs exactly
+    maxit iterations (refinement modes: max_refine steps of maxit).  Returns
+    (refine_steps, total_iters), the fixed counts."""
+    mus = [float(m) for m in (mu if isinstance(mu, (list, tuple)) else [mu])]
+    if B.dtype != torch.float64 or X.dtype != torch.float64 or not B.is_contiguous() or not X.is_contiguous():
+        raise ValueError("B and X must be contiguous float64 device tensors")
+    B2 = B.reshape(B.shape[0], -1)
+    nrhs = B2.shape[1]
+    k = len(mus) * nrhs
+    if X.numel() != B2.shape[0] * k:
+        raise ValueError("X must have n x (nmu * nrhs) entries")
+    for t, dt in ((iters, torch.int32), (relres, torch.float64), (status, torch.int32)):
+        if t.dtype != dt or t.numel() < k or not t.is_cuda:
+            raise ValueError("iters / relres / status: device tensors of int32 / float64 / int32, %d entries" % k)
+    w = _ws(op, P.U.shape[1], k, prec, ws)
+    info = _Info(ctypes.cast(ctypes.c_void_p(iters.data_ptr()), ctypes.POINTER(ctypes.c_int32)),
+                 ctypes.cast(ctypes.c_void_p(relres.data_ptr()), ctypes.POINTER(ctypes.c_double)),
+                 ctypes.cast(ctypes.c_void_p(status.data_ptr()), ctypes.POINTER(ctypes.c_int32)), 0, 0)
+    mu_arr = (ctypes.c_double * len(mus))(*mus)
+    o = _opts(tol, maxit, prec, max_refine, 1, inner_tol, device_info=1)
+    _check(lib().nys_pcg_solve(ctypes.byref(op.c()), ctypes.byref(P.c()), mu_arr, len(mus), _ptr(B2), nrhs, nrhs,
+                               _ptr(X), k, ctypes.byref(o), ctypes.byref(info), _ptr(w), w.numel(), _stream()))
+    return info.refine_steps, info.total_iters
 
 
 def timing_begin() -> None:
@@ -485,7 +578,8 @@ def nys_pcg_solve_ragged(ops: Sequence[Operator], Ps: Sequence[Precond], mus: Se
 def nys_pcg_backward(op: Operator, P: Precond, mu: float, x: torch.Tensor, gx: torch.Tensor,
                      want_sigma: bool = False, want_X: bool = False, tol: float = 1e-10, maxit: int = 500,
                      prec: int = NYS_PREC_FP64, max_refine: int = 10, check_every: int = 0,
-                     inner_tol: float = 1e-4, ws: Optional[torch.Tensor] = None):
+                     inner_tol: float = 1e-4, ws: Optional[torch.Tensor] = None,
+                     raise_on_not_converged: bool = False):
     """Adjoint solve with the same preconditioner.  Returns dict(gb, gmu, gsigma, gX, info)."""
     x = x.reshape(-1).contiguous().to(torch.float64)
     gx = gx.reshape(-1).contiguous().to(torch.float64)
@@ -502,7 +596,7 @@ def nys_pcg_backward(op: Operator, P: Precond, mu: float, x: torch.Tensor, gx: t
     code = lib().nys_pcg_backward(ctypes.byref(op.c()), ctypes.byref(P.c()), float(mu), _ptr(x), _ptr(gx),
                                   _ptr(gb), ctypes.byref(gmu), ctypes.byref(gsig) if want_sigma else None,
                                   _ptr(gX), ctypes.byref(o), ctypes.byref(info), _ptr(w), w.numel(), _stream())
-    _check(code, allow_not_converged=True)
+    _check(code, allow_not_converged=not raise_on_not_converged)
     return dict(gb=gb, gmu=gmu.value, gsigma=gsig.value if want_sigma else None, gX=gX,
                 info=SolveInfo(list(it), list(rr), list(st), info.refine_steps, info.total_iters, code))
 
@@ -530,4 +624,4 @@ def nys_rbf_cross(op: Operator, Xv: torch.Tensor, v: torch.Tensor, transpose: bo
     return (out, dsig.value) if wv is not None else out
 
 
-from .autograd import NystromSolve, nystrom_solve  # noqa: E402,F401
+from .autograd import NystromSolve, RbfCross, nystrom_solve, rbf_cross  # noqa: E402,F401

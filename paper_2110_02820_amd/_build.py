@@ -11,9 +11,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libnyspcg.so")
-SOURCES = ["api.hip", "gemm.hip", "dense_small.hip", "operators.hip", "xtx.hip", "pcg.hip", "ragged.hip", "rng.hip",
-           "rbf_lowp.hip", "adaptive.hip", "columns.hip", "woodbury.hip", "block_pcg.hip",
-           "weighted.hip"]
+# every HIP source of csrc/ goes into the one library
+SOURCES = sorted(f for f in os.listdir(CSRC) if f.endswith(".hip"))
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-I" + INCLUDE, "-I" + CSRC,
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 

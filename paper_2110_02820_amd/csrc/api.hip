@@ -130,12 +130,30 @@ int groups() {
 
 nys_status check_op(const nys_operator* A, OpDesc& o) {
   NYS_ARG(A != nullptr, "operator is NULL");
-  NYS_ARG(A->kind >= NYS_OP_DENSE && A->kind <= NYS_OP_RBF, "unknown operator kind %d", A->kind);
-  NYS_ARG(A->dtype == NYS_F64 || A->dtype == NYS_F32, "operator dtype must be NYS_F64 or NYS_F32");
+  NYS_ARG(A->kind >= NYS_OP_DENSE && A->kind <= NYS_OP_CALLBACK, "unknown operator kind %d", A->kind);
   NYS_ARG(A->n >= 1, "operator dimension n = %lld < 1", (long long)A->n);
+  NYS_ARG(std::isfinite(A->scale) && A->scale > 0.0, "operator scale must be finite and > 0");
+  o.apply = nullptr;
+  o.ctx = nullptr;
+  if (A->kind == NYS_OP_CALLBACK) {
+    NYS_ARG(A->apply != nullptr, "callback operator: apply is NULL");
+    o.kind = A->kind;
+    o.dtype = NYS_F64;
+    o.n = A->n;
+    o.data = nullptr;
+    o.rows = A->n;
+    o.cols = A->n;
+    o.ld = A->n;
+    o.sigma = 0.0;
+    o.scale = A->scale;
+    o.skip = nullptr;
+    o.apply = A->apply;
+    o.ctx = A->ctx;
+    return NYS_OK;
+  }
+  NYS_ARG(A->dtype == NYS_F64 || A->dtype == NYS_F32, "operator dtype must be NYS_F64 or NYS_F32");
   NYS_ARG(A->data != nullptr, "operator data is NULL");
   NYS_ARG(A->ld >= A->cols && A->cols >= 1 && A->rows >= 1, "operator shape/ld invalid");
-  NYS_ARG(std::isfinite(A->scale) && A->scale > 0.0, "operator scale must be finite and > 0");
   if (A->kind == NYS_OP_DENSE) NYS_ARG(A->rows == A->n && A->cols == A->n, "dense operator must be n x n");
   if (A->kind == NYS_OP_XTX) NYS_ARG(A->cols == A->n, "X^T X operator: cols must equal n");
   if (A->kind == NYS_OP_RBF) {
@@ -304,6 +322,9 @@ struct SolveWs {
   double *mu, *R64, *V64, *X64, *B64, *dots;
   double* mu_act;  // mu of the columns still refined
   int* omap;       // original column of each refined column
+  // device-info form: per-column state kept on the device
+  double *relres_d, *prev_d;
+  int *iters_d, *brk_d, *active_d;
   bool has_f;
   void* lowp_buf;
   RbfLowp L;
@@ -315,6 +336,11 @@ void carve_solve(Arena& a, const OpDesc& op, int64_t l, int64_t k, int prec, Sol
   w.mu_act = a.take<double>(k);
   w.omap = a.take<int>(k);
   w.dots = a.take<double>(kMaxGroups * k + 2 * k);
+  w.relres_d = a.take<double>(k);
+  w.prev_d = a.take<double>(k);
+  w.iters_d = a.take<int>(k);
+  w.brk_d = a.take<int>(k);
+  w.active_d = a.take<int>(k);
   w.R64 = a.take<double>(n * k);
   w.V64 = a.take<double>(n * k);
   w.X64 = a.take<double>(n * k);
@@ -361,6 +387,12 @@ __global__ void residual_norms(int64_t n, int64_t k, const double* __restrict__ 
       part[((int64_t)gridDim.x + blockIdx.x) * k + c0] = sb;
     }
   }
+}
+
+template <typename T>
+__global__ void copy_dev(const T* __restrict__ src, T* __restrict__ dst, int64_t count) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) dst[i] = src[i];
 }
 
 template <typename T>
@@ -486,6 +518,74 @@ __global__ void compact_scalars(CgScalars sc, double* __restrict__ mu, int64_t k
   }
 }
 
+// ---- device-info form of the solve: every decision made on the device
+
+// relres[c] = sqrt(sum_g part[g][c] / sum_g part[G + g][c]) (sqrt of the
+// residual norm alone when ||b|| = 0), groups summed in order
+__global__ void relres_from_parts(int64_t k, int ng, const double* __restrict__ part, double* __restrict__ relres) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= k) return;
+  double rr = 0.0, bb = 0.0;
+  for (int q = 0; q < ng; ++q) {
+    rr += part[(int64_t)q * k + c];
+    bb += part[(int64_t)(ng + q) * k + c];
+  }
+  relres[c] = bb > 0.0 ? sqrt(rr / bb) : sqrt(rr);
+}
+
+// Refinement step selection: a column is refined while its true residual
+// exceeds tol, it has not broken down, and the last step at least halved its
+// residual (first step: prev = +inf).  prev <- relres.
+__global__ void refine_select(int64_t k, const double* __restrict__ relres, double* __restrict__ prev,
+                              const int* __restrict__ brk, int* __restrict__ active, double tol) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= k) return;
+  const double r = relres[c];
+  active[c] = (!brk[c] && !(r <= tol) && r <= 0.5 * prev[c]) ? 1 : 0;
+  prev[c] = r;
+}
+
+// inner right-hand sides: column c of R64 (float32) where active, else 0
+__global__ void gather_active(int64_t n, int64_t k, const double* __restrict__ R, const int* __restrict__ active,
+                              float* __restrict__ fB) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n * k) return;
+  fB[t] = active[t % k] ? float(R[t]) : 0.0f;
+}
+
+// iterations and breakdowns of an inner solve added to the column totals
+__global__ void refine_count(int64_t k, CgScalars sc, int* __restrict__ iters, int* __restrict__ brk) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= k) return;
+  iters[c] += sc.iters[c];
+  if (sc.status[c] == NYS_ERR_BREAKDOWN) brk[c] = 1;
+}
+
+__global__ void init_refine_state(int64_t k, double* __restrict__ prev, int* __restrict__ iters,
+                                  int* __restrict__ brk) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= k) return;
+  prev[c] = __builtin_huge_val();
+  iters[c] = 0;
+  brk[c] = 0;
+}
+
+// caller's device info: iterations, true residual, status of every column
+// (iters_src / status_src: a PCG run's scalars, or the refinement totals when
+// brk is given)
+__global__ void write_device_info(int64_t k, const int* __restrict__ iters_src, const int* __restrict__ status_src,
+                                  const int* __restrict__ brk, const double* __restrict__ relres, double tol,
+                                  int32_t* __restrict__ o_iters, double* __restrict__ o_relres,
+                                  int32_t* __restrict__ o_status) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= k) return;
+  const bool broke = brk ? brk[c] != 0 : status_src[c] == NYS_ERR_BREAKDOWN;
+  const double r = relres[c];
+  if (o_iters) o_iters[c] = iters_src[c];
+  if (o_relres) o_relres[c] = r;
+  if (o_status) o_status[c] = broke ? NYS_ERR_BREAKDOWN : (r <= tol ? NYS_OK : NYS_NOT_CONVERGED);
+}
+
 unsigned nblk(int64_t count) { return (unsigned)(count > 0 ? cdiv(count, 256) : 1); }
 
 nys_status upload_indices(int* dst, const std::vector<int>& v, hipStream_t s) {
@@ -573,13 +673,13 @@ nys_status matvec<double>(const OpDesc& op, const double* P, int64_t k, const do
 template <>
 nys_status matvec<float>(const OpDesc& op, const float* P, int64_t k, const double* mu_dev,
                          int64_t nrhs, double mu_host, float* V, PcgBufs<float>& b, hipStream_t s) {
-  (void)mu_dev;
-  (void)nrhs;
+  if (op.kind == NYS_OP_CALLBACK) return callback_apply<float>(op, P, k, k, mu_dev, nrhs, 0.0, V, k, s);
   if (k == 1 && (op.kind == NYS_OP_XTX || op.kind == NYS_OP_DENSE))
     return op_matvec<float>(op, P, (float)mu_host, V, b.opscr, b.opscr_elems, s);
   if (op.kind == NYS_OP_RBF && op.lowp)
     return rbf_lowp_kv(*op.lowp, op.gram, P, k, k, mu_dev, nrhs, V, k, b.opscr, b.opscr_elems, op.skip, s);
-  set_error("float32 arithmetic is available for X^T X, dense and prepared RBF operators (k = 1 for X^T X)");
+  set_error("float32 arithmetic is available for X^T X, dense, callback and prepared RBF operators (k = 1 for "
+            "X^T X)");
   return NYS_ERR_ARG;
 }
 
@@ -599,15 +699,21 @@ struct PcgResult {
 // the block products and the preconditioner apply only pay for the columns
 // still iterating.  Each column follows exactly the recurrence it would follow
 // alone; results are scattered back to the original column order.
+//
+// dev_mode (the device-info form of nys_pcg_solve): nothing is read back and
+// nothing is decided on the host.  Exactly maxit iterations are enqueued on
+// all k columns (a column that has stopped is frozen by its device flags) and
+// res is left empty: the results stay in b.sc.
 template <typename T>
 nys_status pcg_run(const OpDesc& op0, const PrecDesc& P, int64_t k, const double* mu_dev,
                    const std::vector<double>& mu_host, const T* B, T* X, bool x0_zero, double tol, int maxit,
-                   int check_every, PcgBufs<T>& b, PcgResult& res, hipStream_t s) {
+                   int check_every, PcgBufs<T>& b, PcgResult& res, hipStream_t s, bool dev_mode = false) {
   const int64_t n = op0.n;
   OpDesc op = op0;
   op.skip = nullptr;
-  NYS_HIP(hipMemcpyAsync(b.mu, mu_dev, sizeof(double) * k, hipMemcpyDeviceToDevice, s));
-  NYS_HIP(hipMemsetAsync(b.sc.ctr, 0, sizeof(unsigned) * 64, s));
+  hipLaunchKernelGGL(copy_dev<double>, dim3(nblk(k)), dim3(256), 0, s, mu_dev, b.mu, k);
+  NYS_CHECK_LAUNCH();
+  NYS_TRY(zero<unsigned>(b.sc.ctr, 64, s));
   if (x0_zero) {
     NYS_TRY(zero<T>(X, n * k, s));
     NYS_TRY(zero<T>(b.V, n * k, s));
@@ -647,8 +753,8 @@ nys_status pcg_run(const OpDesc& op0, const PrecDesc& P, int64_t k, const double
   int alldone_h = 0;
   // a single column learns whether the set-up already met tol from its first
   // snapshot; blocks read the flag now (their polls synchronise anyway)
-  const bool snap_path = kc == 1 && pinned_flags() != nullptr;
-  if (!snap_path) {
+  const bool snap_path = !dev_mode && kc == 1 && pinned_flags() != nullptr;
+  if (!snap_path && !dev_mode) {
     NYS_HIP(hipMemcpyAsync(&alldone_h, b.sc.alldone, sizeof(int), hipMemcpyDeviceToHost, s));
     NYS_HIP(hipStreamSynchronize(s));
   }
@@ -678,6 +784,11 @@ nys_status pcg_run(const OpDesc& op0, const PrecDesc& P, int64_t k, const double
     ++it;
     return NYS_OK;
   };
+  if (dev_mode) {
+    while (it < maxit) NYS_TRY(step());
+    res.sweeps = it;
+    return NYS_OK;
+  }
   // A single column needs no compaction, so its polls need not stop the
   // device: a batch is enqueued before the host waits for the snapshot
   // (iterations, residual) of the batch before it, which the device writes to
@@ -860,6 +971,89 @@ nys_status true_residual(const OpDesc& op, int64_t k, const double* mu_dev, doub
   return NYS_OK;
 }
 
+// R64 = B64 - (A + mu_c I) X64 and relres_d[c] on the device (no read-back)
+nys_status true_residual_dev(const OpDesc& op, int64_t k, const double* mu_dev, double mu0, SolveWs& w,
+                             hipStream_t s) {
+  const int64_t n = op.n;
+  OpDesc o = op;
+  o.skip = nullptr;
+  if (k == 1 && (op.kind == NYS_OP_XTX || op.kind == NYS_OP_DENSE))
+    NYS_TRY(op_matvec<double>(o, w.X64, mu0, w.V64, w.d.opscr, w.d.opscr_elems, s));
+  else
+    NYS_TRY(op_apply_f64(o, w.X64, k, k, mu_dev, 1, w.V64, k, w.d.opscr, w.d.opscr_elems, s));
+  const int g = 64;
+  hipLaunchKernelGGL(residual_norms, dim3(g), dim3(256), 0, s, n, k, w.B64, w.V64, w.R64, w.dots);
+  hipLaunchKernelGGL(relres_from_parts, dim3(nblk(k)), dim3(256), 0, s, k, g, w.dots, w.relres_d);
+  NYS_CHECK_LAUNCH();
+  return NYS_OK;
+}
+
+// Device-info form of the solve (opts.device_info = 1): fixed iteration
+// counts, device flags for every per-column decision, results written to the
+// caller's device arrays.  Enqueues kernels only.
+nys_status solve_device_info(const OpDesc& op, const OpDesc& opf, const PrecDesc& P,
+                             const std::vector<double>& mu_col, int64_t k, const nys_solve_opts* o,
+                             nys_solve_info* info, SolveWs& w, hipStream_t s) {
+  const int64_t n = op.n;
+  const double tol = o->tol;
+  const int maxit = o->maxit > 0 ? o->maxit : 500;
+  const int prec = o->prec;
+  int32_t* oi = info ? info->iters : nullptr;
+  double* orr = info ? info->relres : nullptr;
+  int32_t* ost = info ? info->status : nullptr;
+  int refine_steps = 0, total = 0;
+  if (prec == NYS_PREC_FP64) {
+    PcgResult r;
+    NYS_TRY(pcg_run<double>(op, P, k, w.mu, mu_col, w.B64, w.X64, false, tol, maxit, 0, w.d, r, s, true));
+    total = r.sweeps;
+    NYS_TRY(true_residual_dev(op, k, w.mu, mu_col[0], w, s));
+    hipLaunchKernelGGL(write_device_info, dim3(nblk(k)), dim3(256), 0, s, k, w.d.sc.iters, w.d.sc.status,
+                       (const int*)nullptr, w.relres_d, tol, oi, orr, ost);
+    NYS_CHECK_LAUNCH();
+  } else if (prec == NYS_PREC_FP32) {
+    hipLaunchKernelGGL((gather_cols<double, float>), dim3(nblk(n * k)), dim3(256), 0, s, n, k, w.B64, k, k, w.f.B, k);
+    hipLaunchKernelGGL((gather_cols<double, float>), dim3(nblk(n * k)), dim3(256), 0, s, n, k, w.X64, k, k, w.f.X, k);
+    NYS_CHECK_LAUNCH();
+    PcgResult r;
+    NYS_TRY(pcg_run<float>(opf, P, k, w.mu, mu_col, w.f.B, w.f.X, false, tol, maxit, 0, w.f, r, s, true));
+    total = r.sweeps;
+    hipLaunchKernelGGL((gather_cols<float, double>), dim3(nblk(n * k)), dim3(256), 0, s, n, k, w.f.X, k, k, w.X64, k);
+    NYS_CHECK_LAUNCH();
+    NYS_TRY(true_residual_dev(op, k, w.mu, mu_col[0], w, s));
+    hipLaunchKernelGGL(write_device_info, dim3(nblk(k)), dim3(256), 0, s, k, w.f.sc.iters, w.f.sc.status,
+                       (const int*)nullptr, w.relres_d, tol, oi, orr, ost);
+    NYS_CHECK_LAUNCH();
+  } else {
+    const int max_ref = o->max_refine > 0 ? o->max_refine : 10;
+    const double itol = o->inner_tol > 0 ? o->inner_tol : 1e-4;
+    hipLaunchKernelGGL(init_refine_state, dim3(nblk(k)), dim3(256), 0, s, k, w.prev_d, w.iters_d, w.brk_d);
+    NYS_CHECK_LAUNCH();
+    NYS_TRY(true_residual_dev(op, k, w.mu, mu_col[0], w, s));
+    for (int step = 0; step < max_ref; ++step) {
+      hipLaunchKernelGGL(refine_select, dim3(nblk(k)), dim3(256), 0, s, k, w.relres_d, w.prev_d, w.brk_d,
+                         w.active_d, tol);
+      hipLaunchKernelGGL(gather_active, dim3(nblk(n * k)), dim3(256), 0, s, n, k, w.R64, w.active_d, w.f.B);
+      NYS_CHECK_LAUNCH();
+      PcgResult r;
+      NYS_TRY(pcg_run<float>(opf, P, k, w.mu, mu_col, w.f.B, w.f.X, true, itol, maxit, 0, w.f, r, s, true));
+      hipLaunchKernelGGL(add_to<float>, dim3(nblk(n * k)), dim3(256), 0, s, w.X64, w.f.X, n * k);
+      hipLaunchKernelGGL(refine_count, dim3(nblk(k)), dim3(256), 0, s, k, w.f.sc, w.iters_d, w.brk_d);
+      NYS_CHECK_LAUNCH();
+      total += r.sweeps;
+      ++refine_steps;
+      NYS_TRY(true_residual_dev(op, k, w.mu, mu_col[0], w, s));
+    }
+    hipLaunchKernelGGL(write_device_info, dim3(nblk(k)), dim3(256), 0, s, k, w.iters_d, (const int*)nullptr,
+                       w.brk_d, w.relres_d, tol, oi, orr, ost);
+    NYS_CHECK_LAUNCH();
+  }
+  if (info) {
+    info->refine_steps = refine_steps;
+    info->total_iters = total;
+  }
+  return NYS_OK;
+}
+
 nys_status solve_impl(const OpDesc& op, const PrecDesc& P, const double* mu, int64_t nmu,
                       const double* B, int64_t nrhs, int64_t ldb, double* X, int64_t ldx,
                       const nys_solve_opts* o, nys_solve_info* info, SolveWs& w, hipStream_t s) {
@@ -888,6 +1082,12 @@ nys_status solve_impl(const OpDesc& op, const PrecDesc& P, const double* mu, int
     NYS_TRY(rbf_lowp_prepare(op, w.lowp_buf, w.L, s));
     opf.lowp = &w.L;
     opf.gram = rbf_gram(prec);
+  }
+  if (o->device_info) {
+    NYS_TRY(solve_device_info(op, opf, P, mu_col, k, o, info, w, s));
+    hipLaunchKernelGGL((gather_cols<double, double>), dim3(nblk(n * k)), dim3(256), 0, s, n, k, w.X64, k, k, X, ldx);
+    NYS_CHECK_LAUNCH();
+    return NYS_OK;
   }
   if (prec == NYS_PREC_FP64) {
     PcgResult r;
@@ -1032,6 +1232,17 @@ nys_status check_solve_common(const OpDesc& op, const PrecDesc& P, const double*
   NYS_ARG(o->prec >= NYS_PREC_FP64 && o->prec <= NYS_PREC_BF16X3_REFINE64, "unknown precision mode");
   NYS_ARG(P.n == op.n, "preconditioner n (%lld) != operator n (%lld)", (long long)P.n, (long long)op.n);
   NYS_ARG(mu != nullptr && nmu >= 1, "mu array is empty");
+  NYS_ARG(o->device_info == 0 || o->device_info == 1, "device_info must be 0 or 1");
+  if (o->device_info) {
+    // nothing is read from the device: mu > 0 keeps lam_l + mu > 0 for the
+    // lam >= 0 that the factorisation returns
+    for (int64_t i = 0; i < nmu; ++i)
+      NYS_ARG(std::isfinite(mu[i]) && mu[i] > 0.0, "device-info solves need every mu finite and > 0 (mu[%lld])",
+              (long long)i);
+    if (o->prec != NYS_PREC_FP64 && op.kind == NYS_OP_RBF)
+      NYS_ARG(op.cols <= 32, "reduced-precision RBF modes need d <= 32");
+    return NYS_OK;
+  }
   double lam_l = 0.0;
   NYS_HIP(hipMemcpyAsync(&lam_l, P.lam + (P.ell - 1), sizeof(double), hipMemcpyDeviceToHost, s));
   NYS_HIP(hipStreamSynchronize(s));
@@ -1273,6 +1484,14 @@ nys_status nys_op_apply(const nys_operator* A, double mu, const void* V, int64_t
   NYS_ARG(std::isfinite(mu), "mu must be finite");
   NYS_ARG(prec >= NYS_PREC_FP64 && prec <= NYS_PREC_BF16X3_REFINE64, "unknown precision mode");
   const bool f32 = prec != NYS_PREC_FP64;
+  hipStream_t s = S(stream);
+  if (op.kind == NYS_OP_CALLBACK) {
+    if (f32)
+      return callback_apply<float>(op, static_cast<const float*>(V), k, ldv, nullptr, 1, mu, static_cast<float*>(Z),
+                                   ldz, s);
+    return callback_apply<double>(op, static_cast<const double*>(V), k, ldv, nullptr, 1, mu, static_cast<double*>(Z),
+                                  ldz, s);
+  }
   NYS_ARG(!f32 || op.kind == NYS_OP_RBF || (k == 1 && ldv == 1 && ldz == 1),
           "nys_op_apply: float32 products of X^T X / dense operators take one contiguous vector");
   NYS_ARG(!f32 || op.kind != NYS_OP_RBF || op.cols <= 32, "reduced-precision RBF products need d <= 32");
@@ -1285,7 +1504,6 @@ nys_status nys_op_apply(const nys_operator* A, double mu, const void* V, int64_t
     set_error("workspace too small: need %zu bytes", a.off);
     return NYS_ERR_WORKSPACE;
   }
-  hipStream_t s = S(stream);
   const bool one = k == 1 && ldv == 1 && ldz == 1;
   // single-vector X^T X / dense products take mu by value; the others read it from the device
   if (!(one && op.kind != NYS_OP_RBF)) NYS_TRY(set_mu(mu_dev, &mu, 1, s));
@@ -1379,6 +1597,7 @@ nys_status nys_pcg_solve_ragged(const nys_operator* ops, const nys_precond* Ps, 
                                 const nys_solve_opts* o, nys_solve_info* info, void* ws,
                                 size_t ws_bytes, void* stream) {
   NYS_ARG(ops && Ps && mu && B && X && nprob >= 1, "nys_pcg_solve_ragged: NULL argument");
+  NYS_ARG(o != nullptr && o->device_info == 0, "nys_pcg_solve_ragged: the device-info form is not available here");
   hipStream_t s = S(stream);
   std::vector<OpDesc> od(nprob);
   std::vector<PrecDesc> pd(nprob);
@@ -1426,6 +1645,7 @@ nys_status nys_pcg_backward(const nys_operator* A, const nys_precond* P, double 
   PrecDesc pd;
   NYS_TRY(check_prec(P, pd));
   NYS_ARG(x && gx && gb, "nys_pcg_backward: NULL vector");
+  NYS_ARG(o != nullptr && o->device_info == 0, "nys_pcg_backward: the device-info form is not available here");
   hipStream_t s = S(stream);
   NYS_TRY(check_solve_common(op, pd, &mu, 1, o, s));
   const int64_t n = op.n;

@@ -191,6 +191,7 @@ nys_status nys_block_pcg_solve(const nys_operator* A, const nys_precond* P, doub
                                void* ws, size_t ws_bytes, void* stream) {
   NYS_ARG(A != nullptr && P != nullptr && B != nullptr && X != nullptr && o != nullptr,
           "nys_block_pcg_solve: NULL argument");
+  NYS_ARG(o == nullptr || o->device_info == 0, "nys_block_pcg_solve: the device-info form is not available here");
   NYS_ARG(s >= 1 && s <= SMAX && ldb >= s && ldx >= s, "need 1 <= s <= %d and ld >= s", SMAX);
   NYS_ARG(P->n == A->n && P->ell >= 1, "preconditioner does not match the operator");
   NYS_ARG(std::isfinite(mu) && mu >= 0.0, "mu must be finite and >= 0");

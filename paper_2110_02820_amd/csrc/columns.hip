@@ -154,7 +154,7 @@ using namespace nys;
 extern "C" {
 
 size_t nys_workspace_size_columns(const nys_operator* A, int64_t ell) {
-  if (A == nullptr || ell < 1 || A->n < 1) return 0;
+  if (A == nullptr || ell < 1 || A->n < 1 || A->kind == NYS_OP_CALLBACK) return 0;
   Arena a(nullptr, 0);
   ColWs w;
   carve_columns(a, A, ell, w);
@@ -165,6 +165,7 @@ nys_status nys_sketch_columns(const nys_operator* A, int64_t ell, const int64_t*
                               double* Y_out, void* ws, size_t ws_bytes, void* stream) {
   NYS_ARG(A != nullptr && idx != nullptr && Omega_out != nullptr && Y_out != nullptr,
           "nys_sketch_columns: NULL argument");
+  NYS_ARG(A->kind != NYS_OP_CALLBACK, "the column-sampling sketch reads entries of A: a callback operator has none");
   NYS_ARG(A->data != nullptr && A->n >= 1 && (A->dtype == NYS_F64 || A->dtype == NYS_F32), "invalid operator");
   NYS_ARG(A->kind == NYS_OP_DENSE || A->kind == NYS_OP_XTX || A->kind == NYS_OP_RBF, "unknown operator kind");
   NYS_ARG(A->scale > 0.0 && std::isfinite(A->scale), "operator scale must be > 0");

@@ -5,7 +5,7 @@
 //  * X^T X    : one pass over X per single-vector product (xtx.hip); MFMA
 //               GEMMs X^T (X P) for blocks of columns
 //  * RBF      : K_ij = exp(-||x_i - x_j||^2 / (2 sigma^2)) evaluated tile by
-//               tile and never stored (Section 6.3 kernel ridge regression).
+//               tile and never stored (Section 6.5 kernel ridge regression).
 //               float64 forms, both with the Gram on v_mfma_f64_16x16x4f64:
 //               one vector (exp and compensated sum on the vector units),
 //               and blocks of columns (the sketch A Omega, block PCG).
@@ -45,6 +45,19 @@ __global__ void add_mu(T* __restrict__ V, int64_t ldv, const T* __restrict__ P, 
   if (idx >= n * k) return;
   const int64_t i = idx / k, c = idx % k;
   V[i * ldv + c] += T(mu[c / nrhs]) * P[i * ldp + c];
+}
+
+// V[i][c] = scale V[i][c] + mu_c P[i][c] (mu from the device array when given,
+// else the value mu_h): the shift of a caller-supplied product
+template <typename T>
+__global__ void scale_shift(T* __restrict__ V, int64_t ldv, const T* __restrict__ P, int64_t ldp, int64_t n,
+                            int64_t k, double scale, const double* __restrict__ mu, double mu_h,
+                            int64_t nrhs) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= n * k) return;
+  const int64_t i = idx / k, c = idx % k;
+  const double m = mu ? mu[c / nrhs] : mu_h;
+  V[i * ldv + c] = T(scale) * V[i * ldv + c] + T(m) * P[i * ldp + c];
 }
 
 // ------------------------------------------------------------- RBF, float64
@@ -398,7 +411,30 @@ nys_status rbf_rect_t(const TD* Xr, int64_t nr, int64_t ldr, const TD* Xc, int64
 
 }  // namespace
 
+template <typename T>
+nys_status callback_apply(const OpDesc& op, const T* P, int64_t k, int64_t ldp, const double* mu_dev,
+                          int64_t nrhs, double mu_host, T* V, int64_t ldv, hipStream_t s) {
+  const int32_t dt = sizeof(T) == 8 ? NYS_F64 : NYS_F32;
+  const int32_t rc = op.apply(op.ctx, k, dt, P, ldp, V, ldv, s);
+  if (rc != 0) {
+    set_error("operator product routine returned %d (k = %lld, dtype %s)", rc, (long long)k,
+              dt == NYS_F64 ? "NYS_F64" : "NYS_F32");
+    return NYS_ERR_DEVICE;
+  }
+  NYS_CHECK_LAUNCH();
+  hipLaunchKernelGGL(scale_shift<T>, dim3((unsigned)cdiv(op.n * k, 256)), dim3(256), 0, s, V, ldv, P, ldp, op.n,
+                     k, op.scale, mu_dev, mu_host, nrhs > 0 ? nrhs : 1);
+  NYS_CHECK_LAUNCH();
+  return NYS_OK;
+}
+
+template nys_status callback_apply<double>(const OpDesc&, const double*, int64_t, int64_t, const double*, int64_t,
+                                           double, double*, int64_t, hipStream_t);
+template nys_status callback_apply<float>(const OpDesc&, const float*, int64_t, int64_t, const double*, int64_t,
+                                          double, float*, int64_t, hipStream_t);
+
 size_t op_scratch_elems(const OpDesc& op, int64_t k) {
+  if (op.kind == NYS_OP_CALLBACK) return 1;
   if (op.kind == NYS_OP_XTX) {
     const size_t t = (size_t)(op.rows * k);
     return (size_t)(2 * 256 * op.n) + t + gemm_scratch_elems(op.rows, k) + gemm_scratch_elems(op.n, k);
@@ -420,6 +456,7 @@ nys_status op_apply_f64(const OpDesc& op, const double* P, int64_t k, int64_t ld
                         const double* mu_dev, int64_t nrhs, double* V, int64_t ldv,
                         double* scratch, size_t scratch_elems, hipStream_t s) {
   const int64_t n = op.n;
+  if (op.kind == NYS_OP_CALLBACK) return callback_apply<double>(op, P, k, ldp, mu_dev, nrhs, 0.0, V, ldv, s);
   if (op.kind == NYS_OP_DENSE) {
     if (k == 1 && ldp == 1 && ldv == 1) {
       // mu is applied by the caller-visible convention: handled by add_mu below
@@ -491,6 +528,7 @@ template <typename TA>
 nys_status op_matvec(const OpDesc& op, const TA* p, TA mu, TA* v, TA* scratch, size_t scratch_elems,
                      hipStream_t s) {
   const int64_t n = op.n;
+  if (op.kind == NYS_OP_CALLBACK) return callback_apply<TA>(op, p, 1, 1, nullptr, 1, double(mu), v, 1, s);
   if (op.kind == NYS_OP_XTX) {
     if (op.dtype == NYS_F64) return xtx_apply<double, TA>(op, p, mu, v, scratch, scratch_elems, s);
     return xtx_apply<float, TA>(op, p, mu, v, scratch, scratch_elems, s);

@@ -16,7 +16,16 @@ struct OpDesc {
   const int* skip = nullptr;  // device flag: kernels return at once when *skip != 0
   const RbfLowp* lowp = nullptr;  // prepared points for reduced-precision RBF products
   int gram = 0;                   // RBF_GRAM_BF16X3 or RBF_GRAM_F32 (with lowp)
+  nys_apply_fn apply = nullptr;   // NYS_OP_CALLBACK: the caller's product routine
+  void* ctx = nullptr;
 };
+
+// NYS_OP_CALLBACK product: V = scale * (caller's A P) + mu_c P_c for k
+// columns of type T (mu_dev: device array indexed by c / nrhs, or nullptr and
+// the value mu_host for every column; neither shifts when both are absent).
+template <typename T>
+nys_status callback_apply(const OpDesc& op, const T* P, int64_t k, int64_t ldp, const double* mu_dev,
+                          int64_t nrhs, double mu_host, T* V, int64_t ldv, hipStream_t s);
 
 // Scratch (in elements of the arithmetic type) used by one operator product
 // with k columns.

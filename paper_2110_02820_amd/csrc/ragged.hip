@@ -1,4 +1,4 @@
-// Ragged batch of ridge problems (Section 1.4, eq. (RidgeRegression), one
+// Ragged batch of ridge problems (Section 1.3, eq. (RidgeRegression), one
 // operator A_c = scale_c X_c^T X_c and one Nystrom preconditioner, eq.
 // (NysPre), per problem) solved together by the PCG of Section 5.2.
 //

@@ -1,7 +1,7 @@
 // Weighted normal equations A = scale X^T D X, D = diag(d), d >= 0: the data
 // term of the Hessian of a regularised generalised linear model (logistic
 // weights p (1 - p)), the operator of approximate leave-one-out
-// cross-validation (Section 6.2, "Approximate cross-validation").  The
+// cross-validation (Section 6.3, "Approximate cross-validation").  The
 // weights are folded into the data once, Xw = D^{1/2} X, so that
 // Xw^T Xw = X^T D X and every later product, sketch and solve is the X^T X
 // operator of Xw: one pass over the data per product, the same kernels and

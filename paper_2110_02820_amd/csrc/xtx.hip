@@ -1,4 +1,4 @@
-// X^T X products for the ridge normal equations (Section 1.4, eq.
+// X^T X products for the ridge normal equations (Section 1.3, eq.
 // (RidgeRegression)), one contiguous vector, gfx950.
 //
 // One pass over X per product: each workgroup owns a contiguous range of rows

@@ -4,6 +4,7 @@ arguments before touching the device."""
 import ctypes
 import os
 import re
+import subprocess
 
 import pytest
 
@@ -39,15 +40,75 @@ def test_library_exports_every_declared_symbol(L):
     assert set(names) == set(nys.EXPORTED)
 
 
-def test_struct_layouts_match_header(L):
+def _c_layout(tmp_path, structs):
+    """sizeof and every field offset of the header's structs, as the C compiler
+    lays them out."""
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "nyspcg.h"', 'int main(void) {']
+    for cname, fields in structs:
+        lines.append('printf("%s size %%zu\\n", sizeof(%s));' % (cname, cname))
+        for f in fields:
+            lines.append('printf("%s %s %%zu\\n", offsetof(%s, %s));' % (cname, f, cname, f))
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout
+    return {tuple(line.split()[:2]): int(line.split()[2]) for line in out.splitlines()}
+
+
+def test_struct_layouts_match_header(L, tmp_path):
     import paper_2110_02820_amd as nys
-    assert ctypes.sizeof(nys._Operator) == 64
-    assert ctypes.sizeof(nys._Precond) == 56
-    assert ctypes.sizeof(nys._Opts) == 32
+    pairs = [("nys_operator", nys._Operator), ("nys_precond", nys._Precond), ("nys_solve_opts", nys._Opts),
+             ("nys_solve_info", nys._Info)]
+    lay = _c_layout(tmp_path, [(c, [f[0] for f in py._fields_]) for c, py in pairs])
+    for cname, py in pairs:
+        assert lay[(cname, "size")] == ctypes.sizeof(py), cname
+        for f in py._fields_:
+            assert lay[(cname, f[0])] == getattr(py, f[0]).offset, (cname, f[0])
 
 
 def _op(nys, kind=0, n=100, rows=100, cols=100, sigma=1.0):
     return nys._Operator(kind, nys.NYS_F64, n, 1, rows, cols, cols, sigma, 1.0)
+
+
+def test_callback_operator_checked_on_host(L):
+    import paper_2110_02820_amd as nys
+    # a callback operator without a routine is refused before any device work
+    op = nys._Operator(nys.NYS_OP_CALLBACK, nys.NYS_F64, 100, None, 0, 0, 0, 0.0, 1.0)
+    assert L.nys_workspace_size(ctypes.byref(op), 10, 1, 0) == 0
+    st = L.nys_sketch(ctypes.byref(op), 10, 0, None, 1, 1, 0, 1, 1 << 20, None)
+    assert st == nys.NYS_ERR_ARG and b"apply" in L.nys_last_error()
+    # with a routine, data / rows / cols / ld are not looked at
+    fn = nys.APPLY_FN(lambda *a: 0)
+    op = nys._Operator(nys.NYS_OP_CALLBACK, nys.NYS_F64, 100, None, 0, 0, 0, 0.0, 1.0, fn, None)
+    assert L.nys_workspace_size(ctypes.byref(op), 10, 1, 0) > 0
+    # the column-sampling sketch has no callback form
+    assert L.nys_workspace_size_columns(ctypes.byref(op), 10) == 0
+    st = L.nys_sketch_columns(ctypes.byref(op), 10, 1, 1, 1, 1, 1 << 20, None)
+    assert st == nys.NYS_ERR_ARG and b"callback" in L.nys_last_error()
+
+
+def test_device_info_form_argument_checks(L):
+    import paper_2110_02820_amd as nys
+    op = _op(nys)
+    P = nys._Precond(100, 10, 1, 10, 0, 0, 1, 0.0)
+    mu = (ctypes.c_double * 2)(1e-3, 0.0)
+    o = nys._Opts(1e-10, 100, 0, 0, 0, 0.0, 1, 0)
+    # mu = 0 is refused in the device-info form (nothing is read back to check lam_l + mu)
+    st = L.nys_pcg_solve(ctypes.byref(op), ctypes.byref(P), mu, 2, 1, 1, 1, 1, 2, ctypes.byref(o), None,
+                         1, 1 << 20, None)
+    assert st == nys.NYS_ERR_ARG and b"mu" in L.nys_last_error()
+    o = nys._Opts(1e-10, 100, 0, 0, 0, 0.0, 2, 0)
+    st = L.nys_pcg_solve(ctypes.byref(op), ctypes.byref(P), mu, 1, 1, 1, 1, 1, 1, ctypes.byref(o), None,
+                         1, 1 << 20, None)
+    assert st == nys.NYS_ERR_ARG and b"device_info" in L.nys_last_error()
+    # the adjoint and the ragged batch synchronise: no device-info form
+    o = nys._Opts(1e-10, 100, 0, 0, 0, 0.0, 1, 0)
+    g = ctypes.c_double(0.0)
+    st = L.nys_pcg_backward(ctypes.byref(op), ctypes.byref(P), 1e-3, 1, 1, 1, ctypes.byref(g), None, None,
+                            ctypes.byref(o), None, 1, 1 << 20, None)
+    assert st == nys.NYS_ERR_ARG and b"device-info" in L.nys_last_error()
 
 
 def test_argument_errors_before_device_use(L):
@@ -72,7 +133,7 @@ def test_argument_errors_before_device_use(L):
     # more than 256 simultaneous columns
     P = nys._Precond(100, 10, 1, 10, 0, 0, 1, 0.0)
     mu = (ctypes.c_double * 300)(*([1.0] * 300))
-    o = nys._Opts(1e-10, 100, 0, 0, 0, 0.0)
+    o = nys._Opts(1e-10, 100, 0, 0, 0, 0.0, 0, 0)
     st = L.nys_pcg_solve(ctypes.byref(op), ctypes.byref(P), mu, 300, 1, 1, 1, 1, 300, ctypes.byref(o), None,
                          1, 1 << 20, None)
     assert st == nys.NYS_ERR_ARG

@@ -1,0 +1,265 @@
+"""The boundary's two call forms beyond the built-in operators:
+
+* NYS_OP_CALLBACK: A reached only through a product routine of the caller
+  (the problem statement of Section 1.1 touches A only through products).
+  The routine here wraps a built-in operator through nys_op_apply, so the
+  results can be compared with the oracle and with the built-in path.
+* the device-info form of nys_pcg_solve (opts.device_info = 1): no host
+  synchronisation, fixed iteration counts, results in device arrays; captured
+  into a HIP graph through torch.cuda.graph and replayed.
+
+Every result is judged by the float64 oracle (true residual, dense solve).
+"""
+import ctypes
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle  # noqa: E402
+from workloads import krr_mixture, krr_small  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2110_02820_amd as nys  # noqa: E402
+
+DEV = "cuda"
+
+
+def t64(a):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=DEV)
+
+
+def t32(a):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float32, device=DEV)
+
+
+def h(t):
+    return t.detach().double().cpu().numpy()
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+def wrap(inner: "nys.Operator", kmax: int, scale: float = 1.0, fail_on_f32: bool = False):
+    """A callback operator whose routine is nys_op_apply on `inner` (mu = 0),
+    float64 products in float64 and float32 products with float32 Gram tiles."""
+    calls = {"f64": 0, "f32": 0}
+    ws = nys.workspace(inner, 1, kmax, nys.NYS_PREC_FP32)
+    ws = torch.empty(max(ws.numel(), nys.workspace(inner, 1, kmax, nys.NYS_PREC_FP64).numel()), dtype=torch.uint8,
+                     device=DEV)
+    cop = inner.c()
+
+    def apply(k, dt, V, ldv, W, ldw, stream):
+        if dt == nys.NYS_F32:
+            if fail_on_f32:
+                return 7
+            calls["f32"] += 1
+            prec = nys.NYS_PREC_FP32
+        else:
+            calls["f64"] += 1
+            prec = nys.NYS_PREC_FP64
+        return nys.lib().nys_op_apply(ctypes.byref(cop), 0.0, V, k, ldv, W, ldw, prec, ws.data_ptr(), ws.numel(),
+                                      stream)
+    return nys.Operator.callback(apply, inner.n, DEV, scale=scale), calls
+
+
+def test_callback_products_match_oracle():
+    w = krr_small(n=700, d=8, ell=30, seed=51)
+    opr = oracle.RBFOp(w["X"], w["sigma"])
+    inner = nys.Operator.rbf(t64(w["X"]), w["sigma"])
+    op, calls = wrap(inner, 64, scale=2.0)
+    V = np.random.default_rng(52).standard_normal((700, 5))
+    out = h(nys.nys_op_apply(op, 0.3, t64(V)))
+    np.testing.assert_allclose(out, 2.0 * opr.matmat(V) + 0.3 * V, rtol=1e-12, atol=1e-12)
+    out1 = h(nys.nys_op_apply(op, 0.3, t64(V[:, 0])))
+    np.testing.assert_allclose(out1, 2.0 * opr.matmat(V[:, 0]) + 0.3 * V[:, 0], rtol=1e-12, atol=1e-12)
+    assert calls["f64"] == 2
+
+
+def test_callback_sketch_factor_solve_fp64():
+    """Sketch, factor and float64 PCG with A known only through the routine:
+    the same approximation as the built-in operator (the sketch is the
+    routine's block product), a solve at true relative residual 1e-10 and the
+    dense solution; the iteration count within 2 of the built-in path's."""
+    w = krr_small(n=900, d=8, ell=60, seed=53)
+    opr = oracle.RBFOp(w["X"], w["sigma"])
+    b = opr.matmat(w["w"]) + w["noise"] * w["eps"]
+    inner = nys.Operator.rbf(t64(w["X"]), w["sigma"])
+    op, calls = wrap(inner, 64)
+    Om, Y = nys.nys_sketch(op, 60, omega0=t64(w["omega0"]))
+    P = nys.nys_factor(Om, Y)
+    ref = oracle.randomized_nystrom(opr, w["omega0"])
+    Ah = (h(P.U) * h(P.lam)) @ h(P.U).T
+    assert rel(Ah, (ref["U"] * ref["lam"]) @ ref["U"].T) < 1e-10
+    x, info = nys.nys_pcg_solve(op, P, w["mu"], t64(b), tol=1e-10, maxit=3000)
+    assert info.status[0] == 0
+    assert oracle.true_relres(opr, w["mu"], h(x), b) <= 1e-10
+    x_in, info_in = nys.nys_pcg_solve(inner, P, w["mu"], t64(b), tol=1e-10, maxit=3000)
+    assert abs(info.iters[0] - info_in.iters[0]) <= 2
+    K = opr.dense()
+    xs = oracle.dense_solve(K, w["mu"], b)
+    kappa = (np.linalg.eigvalsh(K).max() + w["mu"]) / w["mu"]
+    assert rel(h(x), xs) <= kappa * 1e-10
+    assert calls["f64"] > info.iters[0]
+
+
+def test_callback_refinement_uses_float32_products():
+    """float32 inner PCG + float64 refinement: the routine is asked for float32
+    products in the inner solves and float64 ones for the true residuals."""
+    n = 1500
+    w = krr_mixture(n=n, d=16, ell=80, seed=54)
+    opr = oracle.RBFOp(w["X"], w["sigma"])
+    b = opr.matmat(w["w"]) + w["noise"] * w["eps"]
+    inner = nys.Operator.rbf(t32(w["X"]), w["sigma"])
+    op, calls = wrap(inner, 128)
+    P = nys.nys_factor(*nys.nys_sketch(op, 80, omega0=t64(w["omega0"])), dtype=torch.float32)
+    mu = 1e-3 * n
+    x, info = nys.nys_pcg_solve(op, P, mu, t64(b), tol=1e-10, maxit=2000, prec=nys.NYS_PREC_FP32_REFINE64,
+                                inner_tol=1e-3, max_refine=20)
+    assert info.status[0] == 0 and info.refine_steps >= 1
+    assert oracle.true_relres(opr, mu, h(x), b) <= 1e-10
+    assert calls["f32"] > 0 and calls["f64"] >= info.refine_steps + 1
+
+
+def test_callback_failure_is_reported():
+    w = krr_small(n=300, d=8, ell=20, seed=55)
+    inner = nys.Operator.rbf(t64(w["X"]), w["sigma"])
+    op, _ = wrap(inner, 32, fail_on_f32=True)
+    P = nys.nys_factor(*nys.nys_sketch(op, 20, omega0=t64(w["omega0"])), dtype=torch.float32)
+    with pytest.raises(nys.NysError) as e:
+        nys.nys_pcg_solve(op, P, 1e-2, t64(np.ones(300)), prec=nys.NYS_PREC_FP32_REFINE64)
+    assert e.value.status == nys.NYS_ERR_DEVICE
+    assert "returned 7" in str(e.value)
+
+
+def test_operator_from_torch_function():
+    """A torch function as the product routine: device memory handed to the
+    routine is viewed as torch tensors (no copies) on the call's stream."""
+    w = krr_small(n=400, d=8, ell=30, seed=56)
+    opr = oracle.RBFOp(w["X"], w["sigma"])
+    K = t64(opr.dense())
+    op = nys.Operator.from_function(lambda V: K @ V, 400, DEV)
+    b = opr.matmat(w["w"])
+    P = nys.nys_factor(*nys.nys_sketch(op, 30, omega0=t64(w["omega0"])))
+    x, info = nys.nys_pcg_solve(op, P, 1e-2, t64(b), tol=1e-10, maxit=2000)
+    assert info.status[0] == 0
+    assert oracle.true_relres(opr, 1e-2, h(x), b) <= 1e-10
+
+
+# ---------------------------------------------------------------- device-info form
+
+def _grid_case(n=600, ell=40, seed=57):
+    w = krr_small(n=n, d=8, ell=ell, seed=seed)
+    opr = oracle.RBFOp(w["X"], w["sigma"])
+    b = opr.matmat(w["w"]) + w["noise"] * w["eps"]
+    B = np.stack([b, np.random.default_rng(seed + 1).standard_normal(n)], axis=1)
+    return w, opr, B
+
+
+def _dev_info(k):
+    return (torch.zeros(k, dtype=torch.int32, device=DEV), torch.zeros(k, dtype=torch.float64, device=DEV),
+            torch.full((k,), 99, dtype=torch.int32, device=DEV))
+
+
+@pytest.mark.parametrize("prec", [0, 2])
+def test_device_info_solve_matches_oracle(prec):
+    """mu grid x right-hand sides without host polls: every column reaches the
+    tolerance on the oracle's residual, the device relres equals the oracle's
+    to rounding, and the float64 mode's per-column iteration counts are those
+    of the host-polled solve."""
+    w, opr, B = _grid_case()
+    mus = [1e-3, 1e-2, 1e-1]
+    data = t64(w["X"]) if prec == 0 else t32(w["X"])
+    op = nys.Operator.rbf(data, w["sigma"])
+    udt = torch.float64 if prec == 0 else torch.float32
+    P = nys.nys_factor(*nys.nys_sketch(op, 40, omega0=t64(w["omega0"]), prec=prec), dtype=udt, prec=prec)
+    k = len(mus) * 2
+    X = torch.zeros(600, k, dtype=torch.float64, device=DEV)
+    it, rr, st = _dev_info(k)
+    maxit = 600 if prec == 0 else 300
+    ref_steps, total = nys.nys_pcg_solve_device(op, P, mus, t64(B), X, it, rr, st, tol=1e-10, maxit=maxit,
+                                                prec=prec, max_refine=6, inner_tol=1e-3)
+    torch.cuda.synchronize()
+    Xh, it, rr, st = h(X), it.cpu().numpy(), h(rr), st.cpu().numpy()
+    opr32 = oracle.RBFOp(np.asarray(w["X"], dtype=np.float32) if prec else w["X"], w["sigma"])
+    for m, mu in enumerate(mus):
+        for r in range(2):
+            c = m * 2 + r
+            true = oracle.true_relres(opr32, mu, Xh[:, c], B[:, r])
+            assert st[c] == nys.NYS_OK and true <= 1.02e-10, (c, st[c], true)
+            assert abs(rr[c] - true) <= 1e-12
+            assert 0 < it[c] <= (maxit if prec == 0 else maxit * ref_steps)
+    assert (ref_steps, total) == ((0, maxit) if prec == 0 else (6, 6 * maxit))
+    if prec == 0:
+        _, info = nys.nys_pcg_solve(op, P, mus, t64(B), tol=1e-10, maxit=maxit, check_every=1)
+        for c in range(k):
+            assert abs(int(it[c]) - info.iters[c]) <= max(2, info.iters[c] // 20)
+
+
+def test_device_info_reports_unconverged_columns():
+    w, opr, B = _grid_case(seed=58)
+    op = nys.Operator.rbf(t64(w["X"]), w["sigma"])
+    P = nys.nys_factor(*nys.nys_sketch(op, 40, omega0=t64(w["omega0"])))
+    X = torch.zeros(600, 2, dtype=torch.float64, device=DEV)
+    it, rr, st = _dev_info(2)
+    nys.nys_pcg_solve_device(op, P, 1e-3, t64(B), X, it, rr, st, tol=1e-10, maxit=5)
+    torch.cuda.synchronize()
+    assert list(st.cpu().numpy()) == [nys.NYS_NOT_CONVERGED] * 2
+    assert list(it.cpu().numpy()) == [5, 5]
+    for c in range(2):
+        assert h(rr)[c] == pytest.approx(oracle.true_relres(opr, 1e-3, h(X)[:, c], B[:, c]), rel=1e-10)
+
+
+@pytest.mark.parametrize("prec", [0, 2])
+def test_device_info_solve_in_captured_graph(prec):
+    """The device-info solve captured once with torch.cuda.graph and replayed
+    for three right-hand-side blocks written into the captured input between
+    replays (eager work and synchronisation in between): every replay equals
+    the eager device-info solve of the same block bit for bit and meets the
+    tolerance on the oracle's residual."""
+    w, opr, B0 = _grid_case(n=500, ell=30, seed=59)
+    mus = [1e-2, 1e-1]
+    data = t64(w["X"]) if prec == 0 else t32(w["X"])
+    op = nys.Operator.rbf(data, w["sigma"])
+    udt = torch.float64 if prec == 0 else torch.float32
+    P = nys.nys_factor(*nys.nys_sketch(op, 30, omega0=t64(w["omega0"]), prec=prec), dtype=udt, prec=prec)
+    k = 4
+    ws = nys.workspace(op, 30, k, prec)
+    Bc = t64(B0)
+    Xc = torch.zeros(500, k, dtype=torch.float64, device=DEV)
+    it, rr, st = _dev_info(k)
+    kw = dict(tol=1e-10, maxit=400 if prec == 0 else 150, prec=prec, max_refine=5, inner_tol=1e-3, ws=ws)
+    # eager run first (warms up the library's one-time set-up outside the capture)
+    nys.nys_pcg_solve_device(op, P, mus, Bc, Xc, it, rr, st, **kw)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        Xc.zero_()
+        nys.nys_pcg_solve_device(op, P, mus, Bc, Xc, it, rr, st, **kw)
+    rng = np.random.default_rng(60)
+    opr_d = oracle.RBFOp(np.asarray(w["X"], dtype=np.float32) if prec else w["X"], w["sigma"])
+    for rep in range(3):
+        Bn = B0 * (1.0 + rep) + (rep > 0) * rng.standard_normal(B0.shape)
+        Bc.copy_(t64(Bn))
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        Xg, itg, rrg, stg = h(Xc), it.clone(), rr.clone(), st.clone()
+        # eager reference of the same block (own buffers)
+        Xe = torch.zeros(500, k, dtype=torch.float64, device=DEV)
+        ie, re_, se = _dev_info(k)
+        nys.nys_pcg_solve_device(op, P, mus, t64(Bn), Xe, ie, re_, se, **kw)
+        torch.cuda.synchronize()
+        assert np.array_equal(Xg, h(Xe))
+        assert torch.equal(itg, ie) and torch.equal(rrg, re_) and torch.equal(stg, se)
+        for m, mu in enumerate(mus):
+            for r in range(2):
+                c = m * 2 + r
+                assert int(stg[c]) == nys.NYS_OK
+                assert oracle.true_relres(opr_d, mu, Xg[:, c], Bn[:, r]) <= 1.02e-10
