@@ -52,5 +52,5 @@ from .adaptive import ada_rand_nystrom, effective_dimension  # noqa: F401
 from .columns import column_nystrom, selection_matrix  # noqa: F401
 from .sketch_solve import nystrom_sketch_solve  # noqa: F401
 from .block_pcg import block_nystrom_pcg  # noqa: F401
-from .grad import adjoint_gradients  # noqa: F401
+from .grad import adjoint_gradients, validation_loss, validation_loss_grads  # noqa: F401
 from .philox import philox4x32_10, gaussian_philox  # noqa: F401

@@ -35,6 +35,7 @@ class NystromSolve(torch.autograd.Function):
         ctx.inner_tol = inner_tol
         ctx.kind = kind
         ctx.info = info
+        ctx.mu_shape, ctx.sigma_shape = mu.shape, sigma.shape
         return x
 
     @staticmethod
@@ -51,8 +52,11 @@ class NystromSolve(torch.autograd.Function):
                              tol=ctx.tol, maxit=ctx.maxit, prec=ctx.prec, inner_tol=ctx.inner_tol,
                              raise_on_not_converged=True)
         dev = x.device
-        gmu = torch.tensor(r["gmu"], dtype=torch.float64, device=dev) if ctx.needs_input_grad[1] else None
-        gsig = torch.tensor(r["gsigma"], dtype=torch.float64, device=dev) if want_sigma else None
+        # scalar gradients in the shape of the inputs they belong to
+        gmu = (torch.tensor(r["gmu"], dtype=torch.float64, device=dev).reshape(ctx.mu_shape)
+               if ctx.needs_input_grad[1] else None)
+        gsig = (torch.tensor(r["gsigma"], dtype=torch.float64, device=dev).reshape(ctx.sigma_shape)
+                if want_sigma else None)
         gX = r["gX"].to(data.dtype) if want_X else None
         gb = r["gb"] if ctx.needs_input_grad[0] else None
         return gb, gmu, gsig, gX, None, None, None, None, None, None, None
@@ -91,6 +95,7 @@ class RbfCross(torch.autograd.Function):
         out = nys_rbf_cross(op, Xv_d, v_d)
         ctx.save_for_backward(v_d)
         ctx.op, ctx.Xv = op, Xv_d
+        ctx.sigma_shape, ctx.v_shape, ctx.v_dtype = sigma.shape, v.shape, v.dtype
         return out
 
     @staticmethod
@@ -100,11 +105,12 @@ class RbfCross(torch.autograd.Function):
             raise NotImplementedError("rbf_cross: gradients with respect to the points are not formed; detach them")
         (v,) = ctx.saved_tensors
         g = g.reshape(-1).to(torch.float64).contiguous()
-        gv = nys_rbf_cross(ctx.op, ctx.Xv, g, transpose=True) if ctx.needs_input_grad[0] else None
+        gv = (nys_rbf_cross(ctx.op, ctx.Xv, g, transpose=True).reshape(ctx.v_shape).to(ctx.v_dtype)
+              if ctx.needs_input_grad[0] else None)
         gsig = None
         if ctx.needs_input_grad[1]:
             _, ds = nys_rbf_cross(ctx.op, ctx.Xv, g, wvec=v)
-            gsig = torch.tensor(ds, dtype=torch.float64, device=v.device)
+            gsig = torch.tensor(ds, dtype=torch.float64, device=v.device).reshape(ctx.sigma_shape)
         return gv, gsig, None, None
 
 
