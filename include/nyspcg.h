@@ -231,6 +231,26 @@ nys_status nys_pcg_solve(const nys_operator* A, const nys_precond* P, const doub
                          const nys_solve_opts* o, nys_solve_info* info, void* ws, size_t ws_bytes,
                          void* stream);
 
+/* Allocation-free form of nys_pcg_solve, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  Same arguments and results as nys_pcg_solve in its
+ * device-info form (o->device_info must be 1, else NYS_ERR_ARG), without the
+ * workspace: the call uses a static device array of
+ * nys_noalloc_scratch_bytes() bytes (64 MiB) that the library holds on each
+ * GPU it runs on until the process ends.  A solve whose workspace
+ * (nys_workspace_size for the same operator, rank and column count) exceeds
+ * that returns NYS_ERR_WORKSPACE before anything is enqueued.  The call makes
+ * no device or pinned-host allocation, no hipFree and no memset; the first
+ * call on a device looks the array's address up once (before capture, make
+ * one call on each device outside it).  Every call on one GPU shares that
+ * GPU's array, whatever its stream: calls that overlap in time on one GPU
+ * race and give undefined results.  The array keeps the last call's contents;
+ * the call initialises everything it reads. */
+nys_status nys_pcg_solve_noalloc(const nys_operator* A, const nys_precond* P, const double* mu, int64_t nmu,
+                                 const double* B, int64_t nrhs, int64_t ldb, double* X, int64_t ldx,
+                                 const nys_solve_opts* o, nys_solve_info* info, void* stream);
+size_t nys_noalloc_scratch_bytes(void);
+
 /* Ragged batch: nprob independent systems (A_k + mu_k I) x_k = b_k, each with
  * its own operator and preconditioner, solved together (one iteration sweep
  * advances every unfinished problem).  ops, Ps, mu, B, X: host arrays of

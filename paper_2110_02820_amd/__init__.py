@@ -27,7 +27,8 @@ NYS_OP_DENSE, NYS_OP_XTX, NYS_OP_RBF, NYS_OP_CALLBACK = 0, 1, 2, 3
 NYS_ADA_ERR, NYS_ADA_ERR_LAM, NYS_ADA_RATIO = 0, 1, 2
 
 EXPORTED = ["nys_workspace_size", "nys_gaussian", "nys_sketch", "nys_factor", "nys_op_apply",
-            "nys_precond_apply", "nys_pcg_solve", "nys_workspace_size_ragged", "nys_pcg_solve_ragged",
+            "nys_precond_apply", "nys_pcg_solve", "nys_pcg_solve_noalloc", "nys_noalloc_scratch_bytes",
+            "nys_workspace_size_ragged", "nys_pcg_solve_ragged",
             "nys_pcg_backward", "nys_rbf_cross", "nys_workspace_size_adaptive", "nys_power_err_est",
             "nys_nystrom_adaptive", "nys_workspace_size_columns", "nys_sketch_columns",
             "nys_workspace_size_sketch_solve", "nys_sketch_solve", "nys_workspace_size_block",
@@ -93,6 +94,10 @@ def lib():
         L.nys_precond_apply.argtypes = [P(_Precond), dbl, vp, i64, i64, vp, i64, vp, sz, vp]
         L.nys_pcg_solve.argtypes = [P(_Operator), P(_Precond), P(dbl), i64, vp, i64, i64, vp, i64,
                                     P(_Opts), P(_Info), vp, sz, vp]
+        L.nys_pcg_solve_noalloc.argtypes = [P(_Operator), P(_Precond), P(dbl), i64, vp, i64, i64, vp, i64,
+                                            P(_Opts), P(_Info), vp]
+        L.nys_noalloc_scratch_bytes.restype = sz
+        L.nys_noalloc_scratch_bytes.argtypes = []
         L.nys_workspace_size_ragged.restype = sz
         L.nys_workspace_size_ragged.argtypes = [P(_Operator), P(_Precond), i32, i32]
         L.nys_pcg_solve_ragged.argtypes = [P(_Operator), P(_Precond), P(dbl), P(vp), P(vp), i32,
@@ -121,7 +126,7 @@ def lib():
         L.nys_workspace_size_weight_rows.argtypes = []
         L.nys_weight_rows.argtypes = [i64, i64, i32, vp, i64, vp, vp, i64, vp, sz, vp]
         for f in ("nys_gaussian", "nys_sketch", "nys_factor", "nys_op_apply", "nys_precond_apply",
-                  "nys_pcg_solve", "nys_pcg_solve_ragged", "nys_pcg_backward", "nys_rbf_cross",
+                  "nys_pcg_solve", "nys_pcg_solve_noalloc", "nys_pcg_solve_ragged", "nys_pcg_backward", "nys_rbf_cross",
                   "nys_power_err_est", "nys_nystrom_adaptive", "nys_sketch_columns", "nys_sketch_solve",
                   "nys_block_pcg_solve", "nys_weight_rows", "nys_timing_begin", "nys_timing_end"):
             getattr(L, f).restype = ctypes.c_int
@@ -510,6 +515,33 @@ def nys_pcg_solve_device(op: Operator, P: Precond, mu, B: torch.Tensor, X: torch
     o = _opts(tol, maxit, prec, max_refine, 1, inner_tol, device_info=1)
     _check(lib().nys_pcg_solve(ctypes.byref(op.c()), ctypes.byref(P.c()), mu_arr, len(mus), _ptr(B2), nrhs, nrhs,
                                _ptr(X), k, ctypes.byref(o), ctypes.byref(info), _ptr(w), w.numel(), _stream()))
+    return info.refine_steps, info.total_iters
+
+
+def nys_pcg_solve_noalloc(op: Operator, P: Precond, mu, B: torch.Tensor, X: torch.Tensor, iters: torch.Tensor,
+                          relres: torch.Tensor, status: torch.Tensor, tol: float = 1e-10, maxit: int = 500,
+                          prec: int = NYS_PREC_FP64, max_refine: int = 10, inner_tol: float = 1e-4):
+    """Allocation-free form of nys_pcg_solve_device: the same call without a
+    workspace (the library's static per-GPU scratch serves instead; calls that
+    overlap on one GPU race).  Returns (refine_steps, total_iters)."""
+    mus = [float(m) for m in (mu if isinstance(mu, (list, tuple)) else [mu])]
+    if B.dtype != torch.float64 or X.dtype != torch.float64 or not B.is_contiguous() or not X.is_contiguous():
+        raise ValueError("B and X must be contiguous float64 device tensors")
+    B2 = B.reshape(B.shape[0], -1)
+    nrhs = B2.shape[1]
+    k = len(mus) * nrhs
+    if X.numel() != B2.shape[0] * k:
+        raise ValueError("X must have n x (nmu * nrhs) entries")
+    for t, dt in ((iters, torch.int32), (relres, torch.float64), (status, torch.int32)):
+        if t.dtype != dt or t.numel() < k or not t.is_cuda:
+            raise ValueError("iters / relres / status: device tensors of int32 / float64 / int32, %d entries" % k)
+    info = _Info(ctypes.cast(ctypes.c_void_p(iters.data_ptr()), ctypes.POINTER(ctypes.c_int32)),
+                 ctypes.cast(ctypes.c_void_p(relres.data_ptr()), ctypes.POINTER(ctypes.c_double)),
+                 ctypes.cast(ctypes.c_void_p(status.data_ptr()), ctypes.POINTER(ctypes.c_int32)), 0, 0)
+    mu_arr = (ctypes.c_double * len(mus))(*mus)
+    o = _opts(tol, maxit, prec, max_refine, 1, inner_tol, device_info=1)
+    _check(lib().nys_pcg_solve_noalloc(ctypes.byref(op.c()), ctypes.byref(P.c()), mu_arr, len(mus), _ptr(B2), nrhs,
+                                       nrhs, _ptr(X), k, ctypes.byref(o), ctypes.byref(info), _stream()))
     return info.refine_steps, info.total_iters
 
 

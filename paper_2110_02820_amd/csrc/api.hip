@@ -3,6 +3,7 @@
 // HIP kernels of this directory; the host only enqueues work and reads flags.
 #include <atomic>
 #include <chrono>
+#include <mutex>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -1258,6 +1259,45 @@ nys_status check_solve_common(const OpDesc& op, const PrecDesc& P, const double*
 }  // namespace
 }  // namespace nys
 
+// ---------------------------------------------------------------- static scratch
+// Device memory of the allocation-free solve (nys_pcg_solve_noalloc): one
+// array per GPU, held by the code object until the process ends.  In host
+// code `scratch` only names the symbol; its device address on the current GPU
+// comes from hipGetSymbolAddress (kept per device below) and is what kernels
+// receive.
+static constexpr size_t kStaticScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+namespace nys {
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of this GPU's scratch array, looked up once per device with
+// that device current.
+nys_status static_scratch(void** out) {
+  int dev = -1;
+  NYS_HIP(hipGetDevice(&dev));
+  NYS_ARG(dev >= 0 && dev < kMaxDevices, "device index %d out of range for the static scratch", dev);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || p == nullptr) {
+      set_error("hipGetSymbolAddress(scratch) failed on device %d: %s", dev, hipGetErrorString(e));
+      return NYS_ERR_DEVICE;
+    }
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return NYS_OK;
+}
+
+}  // namespace
+}  // namespace nys
+
 using namespace nys;
 
 extern "C" {
@@ -1752,5 +1792,40 @@ nys_status nys_rbf_cross(const nys_operator* A, const void* Xv, int64_t nv, int6
     return rbf_rect_mv(Xv, nv, ldxv, op.data, n, op.ld, (int)op.cols, op.dtype, op.sigma, 0, v, out, scr, se, s);
   return rbf_rect_mv(op.data, n, op.ld, Xv, nv, ldxv, (int)op.cols, op.dtype, op.sigma, 0, v, out, scr, se, s);
 }
+
+nys_status nys_pcg_solve_noalloc(const nys_operator* A, const nys_precond* P, const double* mu, int64_t nmu,
+                                 const double* B, int64_t nrhs, int64_t ldb, double* X, int64_t ldx,
+                                 const nys_solve_opts* o, nys_solve_info* info, void* stream) {
+  NYS_ARG(o != nullptr && o->device_info == 1,
+          "nys_pcg_solve_noalloc: only the device-info form (opts.device_info = 1) is available");
+  OpDesc op;
+  NYS_TRY(check_op(A, op));
+  PrecDesc pd;
+  NYS_TRY(check_prec(P, pd));
+  NYS_ARG(B && X && nrhs >= 1 && ldb >= nrhs, "nys_pcg_solve_noalloc: invalid B");
+  const int64_t k = nmu * nrhs;
+  NYS_ARG(k >= 1 && k <= kMaxCols, "nys_pcg_solve_noalloc: nmu * nrhs must be in [1, 256]");
+  NYS_ARG(ldx >= k, "nys_pcg_solve_noalloc: ldx < nmu * nrhs");
+  hipStream_t s = S(stream);
+  NYS_TRY(check_solve_common(op, pd, mu, nmu, o, s));
+  {
+    Arena probe(nullptr, 0);
+    SolveWs w;
+    carve_solve(probe, op, pd.ell, k, o->prec, w);
+    if (probe.off > kStaticScratchBytes) {
+      set_error("nys_pcg_solve_noalloc: this solve needs %zu bytes of scratch; the static scratch holds %zu",
+                probe.off, kStaticScratchBytes);
+      return NYS_ERR_WORKSPACE;
+    }
+  }
+  void* base = nullptr;
+  NYS_TRY(static_scratch(&base));
+  Arena a(base, kStaticScratchBytes);
+  SolveWs w;
+  carve_solve(a, op, pd.ell, k, o->prec, w);
+  return solve_impl(op, pd, mu, nmu, B, nrhs, ldb, X, ldx, o, info, w, s);
+}
+
+size_t nys_noalloc_scratch_bytes(void) { return kStaticScratchBytes; }
 
 }  // extern "C"
