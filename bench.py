@@ -84,6 +84,13 @@ def parse():
                     help="relative tolerance of each float32 inner solve (0: the workload's default)")
     ap.add_argument("--prec", default="", choices=["", "fp32_refine64", "bf16x3_refine64"],
                     help="ridge: precision mode of the chosen form (empty: the workload's default)")
+    ap.add_argument("--graph", action="store_true",
+                    help="batched: every PCG solve of a step (block + ragged, device-info forms) replayed as one "
+                         "captured graph; sketches and factors stay eager")
+    ap.add_argument("--graph-maxit", type=int, default=400, help="batched --graph: block iterations per step")
+    ap.add_argument("--graph-refine", type=int, default=8, help="batched --graph: block refinement steps")
+    ap.add_argument("--autotune", action="store_true",
+                    help="batched / krr: run the block-product autotuner before the timed region")
     ap.add_argument("--kernel-only", action="store_true",
                     help="ridge: only the X^T X product (and a 256 MiB device copy as the counter "
                          "calibration), for hardware-counter runs")
@@ -397,8 +404,10 @@ def run_sketch_solve(args, nys, torch):
 def run_weighted(args, nys, torch):
     """The ALOOCV operator X^T D X + mu I on the ridge data (X 20000 x 4000
     float32, l = 500, mu = 1e-4) with seeded logistic Hessian weights
-    d = p (1 - p): the weights are folded once (nys_weight_rows, timed with
-    its own roofline), then whole solves in the ridge line's chosen form."""
+    d = p (1 - p): the X^T X operator with float64 row weights applied inside
+    every product, whole solves in the ridge line's chosen form; the float64
+    refinement residuals use the float64 weights, so the tolerance holds for
+    X^T D X itself (checked by the oracle after the timed region)."""
     from workloads import logistic_weights, ridge_dense
     dev = "cuda:0"
     m, n, ell = 20000, (args.n or 4000), 500
@@ -407,11 +416,10 @@ def run_weighted(args, nys, torch):
     X = torch.as_tensor(w["X"], device=dev)
     d = torch.as_tensor(d_h, device=dev)
     # right-hand side X^T D y (input synthesis on the host, float64)
-    b = torch.as_tensor(w["X"].astype(np.float64).T @ (d_h * w["y"]), device=dev)
+    b_h = w["X"].astype(np.float64).T @ (d_h * w["y"])
+    b = torch.as_tensor(b_h, device=dev)
     mu, tol = w["mu"], 1e-10
-    Xw = torch.empty_like(X)
-    fold_ms = kernel_avg_ms(torch, lambda: nys.nys_weight_rows(X, d, out=Xw), 10)
-    op = nys.Operator.xtx(Xw)
+    op = nys.Operator.xtdx(X, d)
     prec = nys.NYS_PREC_BF16X3_REFINE64
     ws = nys.workspace(op, ell, 1, prec)
     kw = dict(maxit=1000, inner_tol=3e-6)
@@ -422,23 +430,23 @@ def run_weighted(args, nys, torch):
     torch.cuda.synchronize()
     t = time.perf_counter()
     for i in range(args.steps):
-        _, info, _ = full_solve(nys, torch, op, ell, 20211002 + i, prec, torch.float32, mu, b, ws, tol, tm, **kw)
+        x, info, _ = full_solve(nys, torch, op, ell, 20211002 + i, prec, torch.float32, mu, b, ws, tol, tm, **kw)
         infos.append(info)
     torch.cuda.synchronize()
     el = time.perf_counter() - t
-    fold_bytes = 2 * m * n * 4 + m * 8
-    fold_gbs = fold_bytes / (fold_ms * 1e-3) / 1e9
+    # the oracle's float64 residual of the last solution on X^T D X (outside the timed region)
+    import oracle
+    rr_or = oracle.true_relres(oracle.XtDXOp(w["X"], d_h), mu, x.cpu().numpy().reshape(-1), b_h)
     return base_record(
         args, args.steps / el, 1e3 * el / args.steps, "bf16x3+f32+f64",
-        {"workload": "ALOOCV operator X^T D X + mu I, X %dx%d float32 (ridge data), d = p(1-p) logistic weights, "
-                     "mu=1e-4, l=%d, tol 1e-10 (true float64 residual of the folded operator)" % (m, n, ell),
-         "precision": "weights folded once (D^{1/2} X, float32); then the ridge line's chosen form",
-         "step": "Gaussian Omega + sketch + factor + PCG solve (folding excluded: once per operator)"},
-        {"correct": all(i.relres[0] <= tol and i.status[0] == 0 for i in infos),
-         "relres": max(i.relres[0] for i in infos), "iters": infos[-1].iters[0],
-         "refine_steps": infos[-1].refine_steps, "phase_ms": {k: 1e3 * v / args.steps for k, v in tm.t.items()},
-         "fold": {"kernel": "check_weights + weight_rows", "ms": fold_ms, "bytes": fold_bytes,
-                  "achieved_gbs": fold_gbs, "frac_of_hbm_peak": fold_gbs / HBM_PEAK_GBS}})
+        {"workload": "ALOOCV operator X^T D X + mu I, X %dx%d float32 (ridge data), d = p(1-p) logistic weights "
+                     "(float64), mu=1e-4, l=%d, tol 1e-10 (true float64 residual of X^T D X)" % (m, n, ell),
+         "precision": "row weights inside every product (float64 in the refinement residuals, float32 in the "
+                      "inner products); then the ridge line's chosen form",
+         "step": "Gaussian Omega + sketch + factor + PCG solve"},
+        {"correct": all(i.relres[0] <= tol and i.status[0] == 0 for i in infos) and rr_or <= 1.01 * tol,
+         "relres": max(i.relres[0] for i in infos), "oracle_relres_last": rr_or, "iters": infos[-1].iters[0],
+         "refine_steps": infos[-1].refine_steps, "phase_ms": {k: 1e3 * v / args.steps for k, v in tm.t.items()}})
 
 
 # --------------------------------------------------------------------------- block PCG
@@ -658,6 +666,17 @@ def run_batched(args, nys, torch):
         rops.append(nys.Operator.xtx(Xk))
         rbs.append(torch.as_tensor(p["X"].astype(np.float64).T @ p["y"], device=dev))
 
+    tuned = None
+    if args.autotune:
+        t = time.perf_counter()
+        ks = [8, 16, 32, 64, 128, 192, 256, ell]
+        nys.nys_autotune(op, prec, ks)
+        tuned = {"seconds": time.perf_counter() - t,
+                 "choices": {k: nys.nys_autotune_query(op, prec, k)[:3] for k in ks}}
+        log("autotune: %s" % tuned)
+    if args.graph:
+        return run_batched_graph(args, nys, torch, w, op, B, mus, ell, prec, ws, rops, rbs, rag, tol, tuned)
+
     def step(seed):
         tm = Timer(torch)
         t = time.perf_counter()
@@ -693,14 +712,181 @@ def run_batched(args, nys, torch):
     nsolves = len(mus) * B.shape[1] + len(rag)
     ok = all(max(a.relres) <= tol and max(r.relres) <= tol for a, r in infos)
     phases = {k: 1e3 * sum(tm.t.get(k, 0.0) for tm in tms) / args.steps for k in tms[0].t}
+    plain = None if args.no_plain else batched_plain_fp64(nys, torch, w, X, B, mus, rops, rbs, rag, tol)
+    extra = {} if tuned is None else {"autotune": tuned}
+    if plain is not None:
+        extra.update({"plain_fp64": plain, "speedup_vs_plain_fp64": (nsolves * args.steps / el) / plain["value"]})
     return base_record(
         args, nsolves * args.steps / el, 1e3 * el / args.steps, "f32+f64",
         {"workload": "batched cross-validation: RBF n=%d d=16 l=%d, 32 mu x 8 rhs in one block solve, plus 64 "
                      "ragged ridge problems (n_k = m_k/4, m_k in [1000, 20000])" % (n, ell),
          "precision": "float32 Gram tiles (RBF) / float32 data (ridge), float32 inner PCG, float64 refinement",
          "step": "all 320 solves incl. sketches"},
-        {"correct": ok, "phase_ms": phases, "solves_per_step": nsolves,
-         "block_iters_max": max(infos[-1][0].iters), "block_refine": infos[-1][0].refine_steps})
+        dict({"correct": ok, "phase_ms": phases, "solves_per_step": nsolves,
+              "block_iters_max": max(infos[-1][0].iters), "block_refine": infos[-1][0].refine_steps}, **extra))
+
+
+def run_batched_graph(args, nys, torch, w, op, B, mus, ell, prec, ws, rops, rbs, rag, tol, tuned):
+    """The batched step with every PCG solve in one captured graph: the block
+    solve (32 mu x 8 right-hand sides, device-info form: fixed iteration
+    counts, stopped column blocks skip their products) and the ragged batch
+    (device-info form) are captured once on buffers that hold the current
+    preconditioners; each step sketches and factors eagerly, copies the
+    factors into those buffers and replays the graph."""
+    dev = B.device
+    n, k = B.shape[0], len(mus) * B.shape[1]
+    Ub = torch.empty(n, ell, dtype=torch.float32, device=dev)
+    lb = torch.empty(ell, dtype=torch.float64, device=dev)
+    Pb = nys.Precond(Ub, lb, 0.0)
+    rUs = [torch.empty(o.n, p["ell"], dtype=torch.float32, device=dev) for o, p in zip(rops, rag)]
+    rls = [torch.empty(p["ell"], dtype=torch.float64, device=dev) for p in rag]
+    rPb = [nys.Precond(u, l, 0.0) for u, l in zip(rUs, rls)]
+    rmus = [p["mu"] for p in rag]
+    X = torch.zeros(n, k, dtype=torch.float64, device=dev)
+    Xr = [torch.zeros_like(b) for b in rbs]
+    ib = [torch.zeros(k, dtype=torch.int32, device=dev), torch.zeros(k, dtype=torch.float64, device=dev),
+          torch.zeros(k, dtype=torch.int32, device=dev)]
+    ir = [torch.zeros(len(rag), dtype=torch.int32, device=dev), torch.zeros(len(rag), dtype=torch.float64, device=dev),
+          torch.zeros(len(rag), dtype=torch.int32, device=dev)]
+    wsr = torch.empty(nys.lib().nys_workspace_size_ragged(
+        (nys._Operator * len(rops))(*[o.c() for o in rops]), (nys._Precond * len(rPb))(*[p.c() for p in rPb]),
+        len(rops), prec), dtype=torch.uint8, device=dev)
+    kwb = dict(tol=tol, maxit=args.graph_maxit, prec=prec, max_refine=args.graph_refine,
+               inner_tol=args.inner_tol or 3e-2, ws=ws)
+    kwr = dict(tol=tol, maxit=150, prec=prec, max_refine=4, inner_tol=1e-5, ws=wsr)
+
+    def factors(seed, tm):
+        t = time.perf_counter()
+        Om, Y = nys.nys_sketch(op, ell, seed=seed, prec=prec, ws=ws)
+        P = nys.nys_factor(Om, Y, dtype=torch.float32, ws=ws, prec=prec)
+        del Om, Y
+        Ub.copy_(P.U)
+        lb.copy_(P.lam)
+        t = tm.lap("block_factor", t)
+        for q, (o, p) in enumerate(zip(rops, rag)):
+            Om, Y = nys.nys_sketch(o, p["ell"], seed=seed + q, prec=prec)
+            Pq = nys.nys_factor(Om, Y, dtype=torch.float32, prec=prec)
+            rUs[q].copy_(Pq.U)
+            rls[q].copy_(Pq.lam)
+        tm.lap("ragged_factor", t)
+
+    def body():
+        X.zero_()
+        for x in Xr:
+            x.zero_()
+        nys.nys_pcg_solve_device(op, Pb, mus, B, X, *ib, **kwb)
+        nys.nys_pcg_solve_ragged_device(rops, rPb, rmus, rbs, Xr, *ir, **kwr)
+
+    tm0 = Timer(torch)
+    factors(99, tm0)
+    t = time.perf_counter()
+    body()  # eager run outside the capture (one-time set-up, warm-up)
+    torch.cuda.synchronize()
+    log("eager device-info solves: %.1f ms" % (1e3 * (time.perf_counter() - t)))
+    t = time.perf_counter()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        body()
+    torch.cuda.synchronize()
+    t_capture = time.perf_counter() - t
+    log("graph captured in %.1f ms" % (1e3 * t_capture))
+
+    def step(seed):
+        tm = Timer(torch)
+        factors(seed, tm)
+        t = time.perf_counter()
+        g.replay()
+        tm.lap("graph_pcg", t)
+        return tm
+
+    for i in range(args.warmup):
+        step(100 + i)
+    t = time.perf_counter()
+    tms, oks = [], []
+    for i in range(args.steps):
+        tm = step(20211004 + i)
+        tms.append(tm)
+        rb, sb, rr, sr = ib[1].cpu(), ib[2].cpu(), ir[1].cpu(), ir[2].cpu()
+        oks.append(bool((sb == 0).all()) and bool((sr == 0).all()) and float(rb.max()) <= tol and
+                   float(rr.max()) <= tol)
+        log("graph step %d: %s; block relres max %.2e, iters max %d; ragged relres max %.2e" %
+            (i, {kk: round(1e3 * v, 1) for kk, v in tm.t.items()}, float(rb.max()), int(ib[0].max()),
+             float(rr.max())))
+    el = time.perf_counter() - t
+    nsolves = k + len(rag)
+    phases = {kk: 1e3 * sum(tm.t.get(kk, 0.0) for tm in tms) / args.steps for kk in tms[0].t}
+    extra = {"correct": all(oks), "phase_ms": phases, "solves_per_step": nsolves, "capture_ms": 1e3 * t_capture,
+             "graph": {"block_maxit": args.graph_maxit, "block_refine": args.graph_refine, "ragged_maxit": 150,
+                       "ragged_refine": 4}}
+    if tuned is not None:
+        extra["autotune"] = tuned
+    return base_record(
+        args, nsolves * args.steps / el, 1e3 * el / args.steps, "f32+f64",
+        {"workload": "batched cross-validation: RBF n=%d d=16 l=%d, 32 mu x 8 rhs in one block solve, plus 64 "
+                     "ragged ridge problems (n_k = m_k/4, m_k in [1000, 20000]); every PCG solve of the step in one "
+                     "captured graph" % (n, ell),
+         "precision": "float32 Gram tiles (RBF) / float32 data (ridge), float32 inner PCG, float64 refinement",
+         "step": "all 320 solves incl. sketches (sketches and factors eager, PCG as one graph replay)"},
+        extra)
+
+
+def batched_plain_fp64(nys, torch, w, X, B, mus, rops, rbs, rag, tol):
+    """The plain float64 GPU path on a documented subset of the batched
+    workload, one system at a time: the RBF data upcast to float64 in HBM, a
+    float64 sketch and factor (the preconditioner does not depend on mu, so the
+    plain path also builds it once), then 8 columns spanning the mu grid (mu
+    indices 0, 4, ..., 28 with right-hand side m mod 8), each solved alone in
+    float64; and 4 ragged problems (every 16th) each with its own float64
+    sketch, factor and solve.  The per-solve rate extrapolates the subset to
+    the whole batch: 320 / (t_setup + 256 mean(t_column) + 64 mean(t_ragged))."""
+    dev = X.device
+    f64 = nys.NYS_PREC_FP64
+    X64 = X.double()
+    op64 = nys.Operator.rbf(X64, w["sigma"])
+    ell = w["ell"]
+    ws = nys.workspace(op64, ell, 1, f64)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    Om, Y = nys.nys_sketch(op64, ell, seed=5, prec=f64, ws=ws)
+    P = nys.nys_factor(Om, Y, dtype=torch.float64, ws=ws, prec=f64)
+    del Om, Y
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t
+    cols = list(range(0, len(mus), 4))
+    t_cols, it_cols, ok = [], [], True
+    for m in cols:
+        b = B[:, m % B.shape[1]].contiguous()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        _, info = nys.nys_pcg_solve(op64, P, mus[m], b, tol=tol, maxit=5000, prec=f64, ws=ws)
+        torch.cuda.synchronize()
+        t_cols.append(time.perf_counter() - t)
+        it_cols.append(info.iters[0])
+        ok = ok and info.relres[0] <= tol
+        log("plain fp64 column mu=%.3g: %.1f ms, %d iters" % (mus[m], 1e3 * t_cols[-1], info.iters[0]))
+    del P, ws, op64, X64
+    t_rag = []
+    for k in range(0, len(rag), 16):
+        Xk64 = rops[k].data.double()
+        o64 = nys.Operator.xtx(Xk64)
+        wsk = nys.workspace(o64, rag[k]["ell"], 1, f64)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        Om, Y = nys.nys_sketch(o64, rag[k]["ell"], seed=11 + k, prec=f64, ws=wsk)
+        Pk = nys.nys_factor(Om, Y, dtype=torch.float64, ws=wsk, prec=f64)
+        _, info = nys.nys_pcg_solve(o64, Pk, rag[k]["mu"], rbs[k], tol=tol, maxit=1000, prec=f64, ws=wsk)
+        torch.cuda.synchronize()
+        t_rag.append(time.perf_counter() - t)
+        ok = ok and info.relres[0] <= tol
+        log("plain fp64 ragged problem %d (%dx%d): %.1f ms" % (k, Xk64.shape[0], Xk64.shape[1], 1e3 * t_rag[-1]))
+        del Xk64, o64, wsk, Pk
+    ncol, nrag = len(mus) * B.shape[1], len(rag)
+    total = t_setup + ncol * float(np.mean(t_cols)) + nrag * float(np.mean(t_rag))
+    return {"value": (ncol + nrag) / total, "unit": "solves/s", "seconds_extrapolated": total,
+            "setup_ms": 1e3 * t_setup, "column_ms": [1e3 * v for v in t_cols], "column_iters": it_cols,
+            "ragged_ms": [1e3 * v for v in t_rag], "correct": bool(ok),
+            "sample": "float64 sketch + factor once, 8 of 256 columns (mu indices 0, 4, ..., 28) solved one at "
+                      "a time, 4 of 64 ragged problems (sketch + factor + solve each); extrapolated to 320 solves"}
 
 
 # --------------------------------------------------------------------------- differentiation
@@ -769,6 +955,37 @@ def run_diff(args, nys, torch):
     rv_dev = (nys.nys_rbf_cross(op, Xv, x) - yv).cpu().numpy()[vidx]
     rv_err = np.abs(rv_dev - rv_or).max() / max(np.abs(rv_or).max(), 1e-300)
     ok = r_fwd <= tol and rv_err <= 1e-10
+    extra = {}
+    if not args.no_plain:
+        # plain float64 GPU path: data upcast to float64 in HBM, float64 sketch,
+        # factor, forward and adjoint solves, one evaluation; its loss and
+        # gradients also cross-check the chosen form's (relative agreement)
+        X64, Xv64 = X.double(), Xv.double()
+        op64 = nys.Operator.rbf(X64, sigma)
+        ws64 = nys.workspace(op64, ell, 1, nys.NYS_PREC_FP64)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        Om, Y = nys.nys_sketch(op64, ell, seed=20211005, prec=nys.NYS_PREC_FP64, ws=ws64)
+        P64 = nys.nys_factor(Om, Y, dtype=torch.float64, ws=ws64, prec=nys.NYS_PREC_FP64)
+        del Om, Y
+        bt = b.clone().requires_grad_(True)
+        mut = torch.tensor(mu, dtype=torch.float64, device=dev, requires_grad=True)
+        sgt = torch.tensor(sigma, dtype=torch.float64, device=dev, requires_grad=True)
+        x64 = nys.nystrom_solve(bt, mut, P64, X=X64, sigma=sgt, tol=tol, maxit=5000, prec=nys.NYS_PREC_FP64)
+        rv64 = nys.rbf_cross(x64, sgt, X64, Xv64) - yv
+        L64 = (rv64 * rv64).sum()
+        gb64, gmu64, gs64 = torch.autograd.grad(L64, [bt, mut, sgt])
+        torch.cuda.synchronize()
+        el64 = time.perf_counter() - t
+        rel = lambda a, c: abs(a - c) / max(abs(c), 1e-300)
+        agree = {"L": rel(L, float(L64)), "dL_dmu": rel(gmu, float(gmu64)), "dL_dsigma": rel(gs, float(gs64)),
+                 "dL_db": float((gb - gb64).norm() / gb64.norm())}
+        log("plain fp64 evaluation: %.1f ms; relative agreement %s" % (1e3 * el64, agree))
+        extra = {"plain_fp64": {"value": 1.0 / el64, "unit": "evaluations/s", "ms_per_step": 1e3 * el64,
+                                "agreement_with_chosen": agree},
+                 "speedup_vs_plain_fp64": (args.steps / el) * el64}
+        ok = ok and max(agree.values()) <= 1e-5
+        del X64, Xv64, op64, ws64, P64
     return base_record(
         args, args.steps / el, 1e3 * el / args.steps, "bf16x3+f32+f64",
         {"workload": "validation loss L = ||K_val x - y_val||^2 through the RBF solve, n=%d, nval=%d, d=16, l=%d"
@@ -780,7 +997,7 @@ def run_diff(args, nys, torch):
          "correct": bool(ok), "check": {"forward_residual_rows_max_over_bnorm": r_fwd,
                                         "val_residual_rows_rel_err": rv_err, "rows": 48, "val_rows": 32},
          "phase_ms": {k: 1e3 * sum(tm.t.get(k, 0.0) for tm in tms) / args.steps for k in tms[0].t},
-         "L": L, "dL_dmu": gmu, "dL_dsigma": gs})
+         "L": L, "dL_dmu": gmu, "dL_dsigma": gs, **extra})
 
 
 def main():

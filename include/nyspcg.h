@@ -99,6 +99,17 @@ typedef struct {
   double scale;      /* A = scale * (base operator); must be > 0              */
   nys_apply_fn apply;/* NYS_OP_CALLBACK: the product routine; NULL otherwise  */
   void* ctx;         /* NYS_OP_CALLBACK: passed to apply unchanged            */
+  const double* weights; /* NYS_OP_XTX only, nullable: device float64 row
+                         weights d (rows entries, each finite and >= 0, not
+                         checked by the products), A = scale X^T D X with
+                         D = diag(d) -- the data term of a generalised linear
+                         model's Hessian (Section 6.3, approximate
+                         cross-validation).  Applied in the arithmetic of each
+                         product (float64 in the float64 products and
+                         residuals, rounded to float32 in the float32 ones).
+                         Not available to nys_sketch_columns or the gX output
+                         of nys_pcg_backward (NYS_ERR_ARG); must be NULL for
+                         the other kinds.                                     */
 } nys_operator;
 
 /* Factored Nystrom approximation A_hat = U diag(lam) U^T (output of the
@@ -448,6 +459,42 @@ const char* nys_last_error(void);
 
 /* Library version string. */
 const char* nys_version(void);
+
+/* ---- Autotuner of the tile shapes of the RBF block products ---- */
+
+/* The reduced-precision RBF block product V = K P (the sketch Y = K Omega and
+ * the products of the batched solves) has several tile shapes: a register
+ * kernel with 16, 32 or 64 columns per workgroup, an LDS kernel with 128 or
+ * 256, and a split over points sized for 4, 8 or 16 workgroups per compute
+ * unit.  Without tuning a built-in rule picks one from the column count.
+ * nys_autotune times every shape on the caller's operator (n, d), precision
+ * mode and each column count ks[i] (2 <= ks[i] <= 4096, nks <= 64) on stream
+ * (which it synchronises), and records the fastest in a process-wide table;
+ * a later product with k columns on the same n, d and Gram precision takes
+ * the entry with the smallest tuned column count >= k (none: the built-in
+ * rule).  The shape changes neither the arithmetic of an entry of K nor the
+ * result beyond float32 summation order.  The table persists through a text
+ * file: nys_autotune_load merges a file (lines "rbf_kv n d mode k reg cf bpc
+ * microseconds"; a malformed line rejects the whole file, NYS_ERR_ARG),
+ * nys_autotune_save writes the table.  If the environment variable
+ * NYS_AUTOTUNE_CACHE names a file, it is loaded before the first lookup and
+ * rewritten after each nys_autotune call.  A is an NYS_OP_RBF operator with
+ * d <= 32; prec a reduced-precision mode (NYS_PREC_BF16X3_REFINE64 tunes the
+ * bf16x3 Gram, the float32 modes the float32 Gram).  ws: at least
+ * nys_workspace_size_autotune(A, max ks) bytes.  This is the project's own
+ * tuner; the paper has no counterpart. */
+size_t nys_workspace_size_autotune(const nys_operator* A, int64_t kmax);
+nys_status nys_autotune(const nys_operator* A, int32_t prec, const int64_t* ks, int32_t nks, void* ws,
+                        size_t ws_bytes, void* stream);
+/* The shape a product with k columns would use now: choice[0] = 1 for the
+ * register kernel (0: LDS kernel), choice[1] = column tiles of 16 per
+ * workgroup, choice[2] = workgroups per compute unit; *tuned (nullable) = 1
+ * when it comes from the table.  Host only. */
+nys_status nys_autotune_query(const nys_operator* A, int32_t prec, int64_t k, int32_t* choice, int32_t* tuned);
+int64_t nys_autotune_entries(void);
+nys_status nys_autotune_clear(void);
+nys_status nys_autotune_load(const char* path);
+nys_status nys_autotune_save(const char* path);
 
 #ifdef __cplusplus
 }

@@ -92,11 +92,25 @@ class RBFOp:
     def rows(self, idx) -> np.ndarray:
         return rbf_kernel_block(self.X[idx], self.X, self.sigma)
 
-    def matmat(self, V: np.ndarray) -> np.ndarray:
+    def matmat(self, V: np.ndarray, workers: int = 1, block: int = _BLOCK) -> np.ndarray:
+        """K V by row blocks.  workers > 1 evaluates the independent row blocks
+        on that many threads: the same formula per block, with one BLAS thread
+        per block (so sums inside a block may be ordered differently)."""
         V = np.asarray(V, dtype=np.float64)
         out = np.empty((self.n,) + V.shape[1:], dtype=np.float64)
-        for i in range(0, self.n, _BLOCK):
-            out[i:i + _BLOCK] = rbf_kernel_block(self.X[i:i + _BLOCK], self.X, self.sigma) @ V
+
+        def one(i):
+            out[i:i + block] = rbf_kernel_block(self.X[i:i + block], self.X, self.sigma) @ V
+
+        starts = range(0, self.n, block)
+        if workers <= 1:
+            for i in starts:
+                one(i)
+        else:
+            from concurrent.futures import ThreadPoolExecutor
+            from threadpoolctl import threadpool_limits
+            with threadpool_limits(limits=1, user_api="blas"), ThreadPoolExecutor(workers) as ex:
+                list(ex.map(one, starts))
         return out
 
     def dense(self) -> np.ndarray:

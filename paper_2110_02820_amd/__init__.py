@@ -33,7 +33,9 @@ EXPORTED = ["nys_workspace_size", "nys_gaussian", "nys_sketch", "nys_factor", "n
             "nys_nystrom_adaptive", "nys_workspace_size_columns", "nys_sketch_columns",
             "nys_workspace_size_sketch_solve", "nys_sketch_solve", "nys_workspace_size_block",
             "nys_block_pcg_solve", "nys_workspace_size_weight_rows", "nys_weight_rows", "nys_timing_begin",
-            "nys_timing_end", "nys_last_error", "nys_version"]
+            "nys_timing_end", "nys_workspace_size_autotune", "nys_autotune", "nys_autotune_query",
+            "nys_autotune_entries", "nys_autotune_clear", "nys_autotune_load", "nys_autotune_save",
+            "nys_last_error", "nys_version"]
 
 
 class NysError(RuntimeError):
@@ -52,7 +54,7 @@ class _Operator(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("dtype", ctypes.c_int32), ("n", ctypes.c_int64),
                 ("data", ctypes.c_void_p), ("rows", ctypes.c_int64), ("cols", ctypes.c_int64),
                 ("ld", ctypes.c_int64), ("sigma", ctypes.c_double), ("scale", ctypes.c_double),
-                ("apply", APPLY_FN), ("ctx", ctypes.c_void_p)]
+                ("apply", APPLY_FN), ("ctx", ctypes.c_void_p), ("weights", ctypes.c_void_p)]
 
 
 class _Precond(ctypes.Structure):
@@ -98,6 +100,15 @@ def lib():
                                             P(_Opts), P(_Info), vp]
         L.nys_noalloc_scratch_bytes.restype = sz
         L.nys_noalloc_scratch_bytes.argtypes = []
+        L.nys_workspace_size_autotune.restype = sz
+        L.nys_workspace_size_autotune.argtypes = [P(_Operator), i64]
+        L.nys_autotune.argtypes = [P(_Operator), i32, P(i64), i32, vp, sz, vp]
+        L.nys_autotune_query.argtypes = [P(_Operator), i32, i64, P(i32), P(i32)]
+        L.nys_autotune_entries.restype = i64
+        L.nys_autotune_entries.argtypes = []
+        L.nys_autotune_clear.argtypes = []
+        L.nys_autotune_load.argtypes = [ctypes.c_char_p]
+        L.nys_autotune_save.argtypes = [ctypes.c_char_p]
         L.nys_workspace_size_ragged.restype = sz
         L.nys_workspace_size_ragged.argtypes = [P(_Operator), P(_Precond), i32, i32]
         L.nys_pcg_solve_ragged.argtypes = [P(_Operator), P(_Precond), P(dbl), P(vp), P(vp), i32,
@@ -128,7 +139,9 @@ def lib():
         for f in ("nys_gaussian", "nys_sketch", "nys_factor", "nys_op_apply", "nys_precond_apply",
                   "nys_pcg_solve", "nys_pcg_solve_noalloc", "nys_pcg_solve_ragged", "nys_pcg_backward", "nys_rbf_cross",
                   "nys_power_err_est", "nys_nystrom_adaptive", "nys_sketch_columns", "nys_sketch_solve",
-                  "nys_block_pcg_solve", "nys_weight_rows", "nys_timing_begin", "nys_timing_end"):
+                  "nys_block_pcg_solve", "nys_weight_rows", "nys_timing_begin", "nys_timing_end",
+                  "nys_autotune", "nys_autotune_query", "nys_autotune_clear", "nys_autotune_load",
+                  "nys_autotune_save"):
             getattr(L, f).restype = ctypes.c_int
         L.nys_last_error.restype = ctypes.c_char_p
         L.nys_version.restype = ctypes.c_char_p
@@ -190,6 +203,7 @@ class Operator:
     sigma: float = 0.0
     scale: float = 1.0
     fn: Optional[object] = None  # NYS_OP_CALLBACK: the ctypes product routine (kept alive here)
+    weights: Optional[torch.Tensor] = None  # NYS_OP_XTX: float64 row weights d (A = scale X^T D X)
 
     @staticmethod
     def callback(apply, n: int, device="cuda", scale: float = 1.0) -> "Operator":
@@ -235,9 +249,16 @@ class Operator:
 
     @staticmethod
     def xtdx(X: torch.Tensor, d: torch.Tensor, scale: float = 1.0) -> "Operator":
-        """A = scale X^T D X, D = diag(d), d >= 0: the rows are weighted once on
-        the device (nys_weight_rows) and A is the X^T X operator of D^{1/2} X."""
-        return Operator.xtx(nys_weight_rows(X, d), scale)
+        """A = scale X^T D X, D = diag(d), d >= 0 (finite): the X^T X operator with
+        row weights, applied inside every product (float64 d in the float64
+        products and residuals).  The weights are checked here."""
+        d = d.reshape(-1).to(torch.float64).contiguous()
+        if d.numel() != X.shape[0]:
+            raise ValueError("xtdx: one weight per row of X")
+        if not bool(torch.isfinite(d).all()) or bool((d < 0).any()):
+            raise ValueError("xtdx: weights must be finite and >= 0")
+        X = X.contiguous()
+        return Operator(NYS_OP_XTX, X, X.shape[1], scale=scale, weights=d)
 
     @staticmethod
     def rbf(X: torch.Tensor, sigma: float, scale: float = 1.0) -> "Operator":
@@ -248,9 +269,9 @@ class Operator:
         d = self.data
         if self.kind == NYS_OP_CALLBACK:
             return _Operator(self.kind, NYS_F64, self.n, None, self.n, self.n, self.n, 0.0, self.scale, self.fn,
-                             None)
+                             None, None)
         return _Operator(self.kind, _dt(d), self.n, _ptr(d), d.shape[0], d.shape[1], d.stride(0),
-                         self.sigma, self.scale, APPLY_FN(), None)
+                         self.sigma, self.scale, APPLY_FN(), None, _ptr(self.weights))
 
 
 @dataclass
@@ -545,6 +566,44 @@ def nys_pcg_solve_noalloc(op: Operator, P: Precond, mu, B: torch.Tensor, X: torc
     return info.refine_steps, info.total_iters
 
 
+def nys_autotune(op: Operator, prec: int, ks: Sequence[int], ws: Optional[torch.Tensor] = None) -> None:
+    """Time every tile shape of the reduced-precision RBF block product for each
+    column count in ks on this operator and record the fastest (process-wide
+    table; saved to $NYS_AUTOTUNE_CACHE when set)."""
+    ks = [int(k) for k in ks]
+    if ws is None:
+        nb = lib().nys_workspace_size_autotune(ctypes.byref(op.c()), max(ks))
+        if nb == 0:
+            _check(NYS_ERR_ARG)
+        ws = torch.empty(nb, dtype=torch.uint8, device=op.data.device)
+    arr = (ctypes.c_int64 * len(ks))(*ks)
+    _check(lib().nys_autotune(ctypes.byref(op.c()), prec, arr, len(ks), _ptr(ws), ws.numel(), _stream()))
+
+
+def nys_autotune_query(op: Operator, prec: int, k: int):
+    """(register kernel?, 16-column tiles per workgroup, workgroups per CU, tuned?) of a k-column product."""
+    ch = (ctypes.c_int32 * 3)()
+    tuned = ctypes.c_int32(0)
+    _check(lib().nys_autotune_query(ctypes.byref(op.c()), prec, k, ch, ctypes.byref(tuned)))
+    return bool(ch[0]), int(ch[1]), int(ch[2]), bool(tuned.value)
+
+
+def nys_autotune_entries() -> int:
+    return int(lib().nys_autotune_entries())
+
+
+def nys_autotune_clear() -> None:
+    _check(lib().nys_autotune_clear())
+
+
+def nys_autotune_load(path: str) -> None:
+    _check(lib().nys_autotune_load(str(path).encode()))
+
+
+def nys_autotune_save(path: str) -> None:
+    _check(lib().nys_autotune_save(str(path).encode()))
+
+
 def timing_begin() -> None:
     """Start timing launches of the X^T X product kernel with HIP events."""
     _check(lib().nys_timing_begin())
@@ -605,6 +664,41 @@ def nys_pcg_solve_ragged(ops: Sequence[Operator], Ps: Sequence[Precond], mus: Se
                                       _ptr(ws), ws.numel(), _stream())
     _check(code, allow_not_converged=True)
     return Xs, SolveInfo(list(it), list(rr), list(st), info.refine_steps, info.total_iters, code)
+
+
+def nys_pcg_solve_ragged_device(ops: Sequence[Operator], Ps: Sequence[Precond], mus: Sequence[float],
+                                Bs: Sequence[torch.Tensor], Xs: Sequence[torch.Tensor], iters: torch.Tensor,
+                                relres: torch.Tensor, status: torch.Tensor, tol: float = 1e-10, maxit: int = 500,
+                                prec: int = NYS_PREC_FP64, max_refine: int = 10, inner_tol: float = 1e-4,
+                                ws: Optional[torch.Tensor] = None):
+    """Device-info form of nys_pcg_solve_ragged (opts.device_info = 1): no host
+    synchronisation, so it can be captured into a graph.  Bs, Xs: contiguous
+    float64 device vectors (Xs: in x0, out x); iters / relres / status: device
+    tensors of len(ops) entries written by the call's last kernels.  Runs
+    exactly maxit iterations per step (float64: one step; refinement modes:
+    max_refine steps).  Returns (refine_steps, total_iters)."""
+    npb = len(ops)
+    for v in list(Bs) + list(Xs):
+        if v.dtype != torch.float64 or not v.is_contiguous() or not v.is_cuda:
+            raise ValueError("Bs and Xs must be contiguous float64 device vectors")
+    for t, dt in ((iters, torch.int32), (relres, torch.float64), (status, torch.int32)):
+        if t.dtype != dt or t.numel() < npb or not t.is_cuda:
+            raise ValueError("iters / relres / status: device tensors of int32 / float64 / int32, %d entries" % npb)
+    cops = (_Operator * npb)(*[o.c() for o in ops])
+    cps = (_Precond * npb)(*[p.c() for p in Ps])
+    mu_arr = (ctypes.c_double * npb)(*[float(m) for m in mus])
+    barr = (ctypes.c_void_p * npb)(*[_ptr(b) for b in Bs])
+    xarr = (ctypes.c_void_p * npb)(*[_ptr(x) for x in Xs])
+    if ws is None:
+        nb = lib().nys_workspace_size_ragged(cops, cps, npb, prec)
+        ws = torch.empty(nb, dtype=torch.uint8, device=Bs[0].device)
+    info = _Info(ctypes.cast(ctypes.c_void_p(iters.data_ptr()), ctypes.POINTER(ctypes.c_int32)),
+                 ctypes.cast(ctypes.c_void_p(relres.data_ptr()), ctypes.POINTER(ctypes.c_double)),
+                 ctypes.cast(ctypes.c_void_p(status.data_ptr()), ctypes.POINTER(ctypes.c_int32)), 0, 0)
+    o = _opts(tol, maxit, prec, max_refine, 1, inner_tol, device_info=1)
+    _check(lib().nys_pcg_solve_ragged(cops, cps, mu_arr, barr, xarr, npb, ctypes.byref(o), ctypes.byref(info),
+                                      _ptr(ws), ws.numel(), _stream()))
+    return info.refine_steps, info.total_iters
 
 
 def nys_pcg_backward(op: Operator, P: Precond, mu: float, x: torch.Tensor, gx: torch.Tensor,

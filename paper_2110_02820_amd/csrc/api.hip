@@ -134,8 +134,10 @@ nys_status check_op(const nys_operator* A, OpDesc& o) {
   NYS_ARG(A->kind >= NYS_OP_DENSE && A->kind <= NYS_OP_CALLBACK, "unknown operator kind %d", A->kind);
   NYS_ARG(A->n >= 1, "operator dimension n = %lld < 1", (long long)A->n);
   NYS_ARG(std::isfinite(A->scale) && A->scale > 0.0, "operator scale must be finite and > 0");
+  NYS_ARG(A->weights == nullptr || A->kind == NYS_OP_XTX, "row weights belong to the X^T X operator only");
   o.apply = nullptr;
   o.ctx = nullptr;
+  o.w = nullptr;
   if (A->kind == NYS_OP_CALLBACK) {
     NYS_ARG(A->apply != nullptr, "callback operator: apply is NULL");
     o.kind = A->kind;
@@ -172,6 +174,7 @@ nys_status check_op(const nys_operator* A, OpDesc& o) {
   o.sigma = A->sigma;
   o.scale = A->scale;
   o.skip = nullptr;
+  o.w = A->kind == NYS_OP_XTX ? A->weights : nullptr;
   return NYS_OK;
 }
 
@@ -678,7 +681,8 @@ nys_status matvec<float>(const OpDesc& op, const float* P, int64_t k, const doub
   if (k == 1 && (op.kind == NYS_OP_XTX || op.kind == NYS_OP_DENSE))
     return op_matvec<float>(op, P, (float)mu_host, V, b.opscr, b.opscr_elems, s);
   if (op.kind == NYS_OP_RBF && op.lowp)
-    return rbf_lowp_kv(*op.lowp, op.gram, P, k, k, mu_dev, nrhs, V, k, b.opscr, b.opscr_elems, op.skip, s);
+    return rbf_lowp_kv(*op.lowp, op.gram, P, k, k, mu_dev, nrhs, V, k, b.opscr, b.opscr_elems, op.skip, s,
+                       op.coldone);
   set_error("float32 arithmetic is available for X^T X, dense, callback and prepared RBF operators (k = 1 for "
             "X^T X)");
   return NYS_ERR_ARG;
@@ -723,6 +727,10 @@ nys_status pcg_run(const OpDesc& op0, const PrecDesc& P, int64_t k, const double
   }
   NYS_TRY(pcg_setup<T>(n, k, P, b.mu, 1, B, b.V, b.R, b.Z, b.P, b.w, b.sc, tol, s));
   op.skip = b.sc.alldone;
+  // device-info form (no compaction): block products skip column blocks whose
+  // columns have all stopped (their products are not read: a stopped
+  // column's alpha is 0); the host-polled form compacts such columns away
+  op.coldone = dev_mode && k > 1 ? b.sc.done : nullptr;
   res.iters.assign(k, 0);
   res.status.assign(k, 0);
   res.rnorm2.assign(k, 0.0);
@@ -1421,11 +1429,13 @@ nys_status nys_sketch(const nys_operator* A, int64_t ell, uint64_t seed, const d
     if (prec == NYS_PREC_BF16X3_REFINE64) {  // products on bf16 MFMA (hi/lo split)
       NYS_TRY(gemm_bf16x3(false, false, op.rows, l, n, 1.0f, X, op.ld, w.Om32, l, 0.0f, w.T32, l, w.f32scr,
                           w.f32scr_elems, s));
+      if (op.w) NYS_TRY(scale_rows<float>(w.T32, op.rows, l, op.w, s));  // X^T D X: D between the products
       NYS_TRY(gemm_bf16x3(true, false, n, l, op.rows, (float)op.scale, X, op.ld, w.T32, l, 0.0f, w.Y32, l,
                           w.f32scr, w.f32scr_elems, s));
     } else {
       NYS_TRY((gemm<float, float, float>(false, false, op.rows, l, n, 1.0f, X, op.ld, w.Om32, l, 0.0f,
                                          w.T32, l, w.f32scr, w.f32scr_elems, s)));
+      if (op.w) NYS_TRY(scale_rows<float>(w.T32, op.rows, l, op.w, s));
       NYS_TRY((gemm<float, float, float>(true, false, n, l, op.rows, (float)op.scale, X, op.ld, w.T32, l,
                                          0.0f, w.Y32, l, w.f32scr, w.f32scr_elems, s)));
     }
@@ -1637,7 +1647,7 @@ nys_status nys_pcg_solve_ragged(const nys_operator* ops, const nys_precond* Ps, 
                                 const nys_solve_opts* o, nys_solve_info* info, void* ws,
                                 size_t ws_bytes, void* stream) {
   NYS_ARG(ops && Ps && mu && B && X && nprob >= 1, "nys_pcg_solve_ragged: NULL argument");
-  NYS_ARG(o != nullptr && o->device_info == 0, "nys_pcg_solve_ragged: the device-info form is not available here");
+  NYS_ARG(o != nullptr, "nys_pcg_solve_ragged: options are NULL");
   hipStream_t s = S(stream);
   std::vector<OpDesc> od(nprob);
   std::vector<PrecDesc> pd(nprob);
@@ -1657,11 +1667,16 @@ nys_status nys_pcg_solve_ragged(const nys_operator* ops, const nys_precond* Ps, 
     int it = 0, st = 0;
     double rr = 0.0;
     nys_solve_info inf{&it, &rr, &st, 0, 0};
+    if (o->device_info) {  // the caller's device arrays, entry i
+      inf.iters = info && info->iters ? info->iters + i : nullptr;
+      inf.relres = info && info->relres ? info->relres + i : nullptr;
+      inf.status = info && info->status ? info->status + i : nullptr;
+    }
     const nys_status r = nys_pcg_solve(&ops[i], &Ps[i], &mu[i], 1, B[i], 1, 1, X[i], 1, o, &inf, ws,
                                        ws_bytes, stream);
     if (r < 0) return r;
     if (r != NYS_OK) worst = r;
-    if (info) {
+    if (info && !o->device_info) {
       if (info->iters) info->iters[i] = it;
       if (info->relres) info->relres[i] = rr;
       if (info->status) info->status[i] = st;
@@ -1734,6 +1749,7 @@ nys_status nys_pcg_backward(const nys_operator* A, const nys_precond* P, double 
   }
   if (gX) {
     NYS_ARG(op.kind == NYS_OP_XTX, "gX is defined for the X^T X operator only");
+    NYS_ARG(op.w == nullptr, "gX is not formed for a weighted X^T X operator");
     const int64_t m = op.rows;
     // t1 = X x, t2 = X lambda;  gX = -scale (t1 lambda^T + t2 x^T)
     if (op.dtype == NYS_F64) {
@@ -1827,5 +1843,95 @@ nys_status nys_pcg_solve_noalloc(const nys_operator* A, const nys_precond* P, co
 }
 
 size_t nys_noalloc_scratch_bytes(void) { return kStaticScratchBytes; }
+
+// ---- autotuner of the RBF block-product tile shapes
+
+namespace {
+nys_status autotune_op(const nys_operator* A, int32_t prec, OpDesc& op, int& mode) {
+  NYS_TRY(check_op(A, op));
+  NYS_ARG(op.kind == NYS_OP_RBF, "autotune: the tuned products are the reduced-precision RBF block products");
+  NYS_ARG(op.cols <= 32, "autotune: reduced-precision RBF products need d <= 32");
+  NYS_ARG(prec == NYS_PREC_FP32 || prec == NYS_PREC_FP32_REFINE64 || prec == NYS_PREC_BF16X3_REFINE64,
+          "autotune: prec must be a reduced-precision mode");
+  mode = rbf_gram(prec);
+  return NYS_OK;
+}
+}  // namespace
+
+size_t nys_workspace_size_autotune(const nys_operator* A, int64_t kmax) {
+  OpDesc op;
+  int mode = 0;
+  if (kmax < 1 || autotune_op(A, NYS_PREC_FP32, op, mode) != NYS_OK) return 0;
+  Arena a(nullptr, 0);
+  (void)a.take<char>(rbf_lowp_bytes(op.n));
+  (void)a.take<float>(op.n * kmax);
+  (void)a.take<float>(op.n * kmax);
+  (void)a.take<float>(rbf_lowp_kv_scratch(op.n, kmax));
+  return a.off + 256;
+}
+
+nys_status nys_autotune(const nys_operator* A, int32_t prec, const int64_t* ks, int32_t nks, void* ws,
+                        size_t ws_bytes, void* stream) {
+  OpDesc op;
+  int mode = 0;
+  NYS_TRY(autotune_op(A, prec, op, mode));
+  NYS_ARG(ks != nullptr && nks >= 1 && nks <= 64, "autotune: 1 <= nks <= 64 column counts");
+  int64_t kmax = 0;
+  for (int i = 0; i < nks; ++i) {
+    NYS_ARG(ks[i] >= 2 && ks[i] <= 4096, "autotune: column counts must lie in [2, 4096] (ks[%d] = %lld)", i,
+            (long long)ks[i]);
+    kmax = ks[i] > kmax ? ks[i] : kmax;
+  }
+  Arena a(ws, ws_bytes);
+  char* lp = a.take<char>(rbf_lowp_bytes(op.n));
+  float* P = a.take<float>(op.n * kmax);
+  float* V = a.take<float>(op.n * kmax);
+  const size_t se = rbf_lowp_kv_scratch(op.n, kmax);
+  float* scr = a.take<float>(se);
+  if (!ws || !a.ok()) {
+    set_error("autotune: workspace too small: need %zu bytes", a.off);
+    return NYS_ERR_WORKSPACE;
+  }
+  hipStream_t s = S(stream);
+  RbfLowp L{};
+  NYS_TRY(rbf_lowp_prepare(op, lp, L, s));
+  NYS_TRY(rbf_lowp_autotune(L, mode, ks, nks, P, V, scr, se, s));
+  kv_tune_env_save();
+  return NYS_OK;
+}
+
+nys_status nys_autotune_query(const nys_operator* A, int32_t prec, int64_t k, int32_t* choice, int32_t* tuned) {
+  OpDesc op;
+  int mode = 0;
+  NYS_TRY(autotune_op(A, prec, op, mode));
+  NYS_ARG(k >= 1 && choice != nullptr, "autotune query: k >= 1 and a 3-entry choice array");
+  RbfLowp L{};
+  L.n = op.n;
+  L.d = (int)op.cols;
+  bool t = false;
+  const KvChoice c = kv_choice(L, k, mode, &t);
+  choice[0] = c.reg;
+  choice[1] = c.cf;
+  choice[2] = c.bpc;
+  if (tuned) *tuned = t ? 1 : 0;
+  return NYS_OK;
+}
+
+int64_t nys_autotune_entries(void) { return kv_tune_entries(); }
+
+nys_status nys_autotune_clear(void) {
+  kv_tune_clear();
+  return NYS_OK;
+}
+
+nys_status nys_autotune_load(const char* path) {
+  NYS_ARG(path != nullptr, "autotune load: NULL path");
+  return kv_tune_load(path);
+}
+
+nys_status nys_autotune_save(const char* path) {
+  NYS_ARG(path != nullptr, "autotune save: NULL path");
+  return kv_tune_save(path);
+}
 
 }  // extern "C"

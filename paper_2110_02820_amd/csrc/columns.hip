@@ -173,6 +173,7 @@ nys_status nys_sketch_columns(const nys_operator* A, int64_t ell, const int64_t*
   NYS_ARG(A->ld >= A->cols && A->rows >= 1 && A->cols >= 1, "invalid operator shape");
   NYS_ARG(A->kind != NYS_OP_DENSE || (A->rows == A->n && A->cols == A->n), "dense operator must be n x n");
   NYS_ARG(A->kind != NYS_OP_XTX || A->cols == A->n, "X^T X operator: data must have n columns");
+  NYS_ARG(A->weights == nullptr, "column sampling: weighted X^T X operators are not supported");
   NYS_ARG(A->kind != NYS_OP_RBF || A->rows == A->n, "RBF operator: data must have n rows");
   const int64_t n = A->n;
   NYS_ARG(ell >= 1 && ell <= n, "need 1 <= ell <= n");

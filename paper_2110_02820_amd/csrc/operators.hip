@@ -433,6 +433,24 @@ template nys_status callback_apply<double>(const OpDesc&, const double*, int64_t
 template nys_status callback_apply<float>(const OpDesc&, const float*, int64_t, int64_t, const double*, int64_t,
                                           double, float*, int64_t, hipStream_t);
 
+namespace {
+template <typename T>
+__global__ void scale_rows_kernel(T* __restrict__ t, int64_t m, int64_t k, const double* __restrict__ w) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= m * k) return;
+  t[idx] = T(double(t[idx]) * w[idx / k]);
+}
+}  // namespace
+
+template <typename T>
+nys_status scale_rows(T* t, int64_t m, int64_t k, const double* w, hipStream_t s) {
+  hipLaunchKernelGGL(scale_rows_kernel<T>, dim3((unsigned)cdiv(m * k, 256)), dim3(256), 0, s, t, m, k, w);
+  NYS_CHECK_LAUNCH();
+  return NYS_OK;
+}
+template nys_status scale_rows<double>(double*, int64_t, int64_t, const double*, hipStream_t);
+template nys_status scale_rows<float>(float*, int64_t, int64_t, const double*, hipStream_t);
+
 size_t op_scratch_elems(const OpDesc& op, int64_t k) {
   if (op.kind == NYS_OP_CALLBACK) return 1;
   if (op.kind == NYS_OP_XTX) {
@@ -498,12 +516,14 @@ nys_status op_apply_f64(const OpDesc& op, const double* P, int64_t k, int64_t ld
       const double* X = static_cast<const double*>(op.data);
       NYS_TRY((gemm<double, double, double>(false, false, op.rows, k, n, 1.0, X, op.ld, P, ldp, 0.0,
                                             T, k, rest, rest_elems, s, op.skip)));
+      if (op.w) NYS_TRY(scale_rows<double>(T, op.rows, k, op.w, s));
       NYS_TRY((gemm<double, double, double>(true, false, n, k, op.rows, op.scale, X, op.ld, T, k,
                                             0.0, V, ldv, rest, rest_elems, s, op.skip)));
     } else {
       const float* X = static_cast<const float*>(op.data);
       NYS_TRY((gemm<double, float, double>(false, false, op.rows, k, n, 1.0, X, op.ld, P, ldp, 0.0,
                                            T, k, rest, rest_elems, s, op.skip)));
+      if (op.w) NYS_TRY(scale_rows<double>(T, op.rows, k, op.w, s));
       NYS_TRY((gemm<double, float, double>(true, false, n, k, op.rows, op.scale, X, op.ld, T, k, 0.0,
                                            V, ldv, rest, rest_elems, s, op.skip)));
     }

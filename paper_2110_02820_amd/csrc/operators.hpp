@@ -14,11 +14,18 @@ struct OpDesc {
   int64_t rows, cols, ld;
   double sigma, scale;
   const int* skip = nullptr;  // device flag: kernels return at once when *skip != 0
+  const int* coldone = nullptr;  // device per-column flags of a block product: finished columns (nullable)
+  const double* w = nullptr;     // NYS_OP_XTX: row weights d (A = scale X^T D X), nullable
   const RbfLowp* lowp = nullptr;  // prepared points for reduced-precision RBF products
   int gram = 0;                   // RBF_GRAM_BF16X3 or RBF_GRAM_F32 (with lowp)
   nys_apply_fn apply = nullptr;   // NYS_OP_CALLBACK: the caller's product routine
   void* ctx = nullptr;
 };
+
+// T[i][c] *= w[i] for an m x k row-major block (ld k): the row weights of a
+// weighted X^T X product between its two GEMMs.
+template <typename T>
+nys_status scale_rows(T* t, int64_t m, int64_t k, const double* w, hipStream_t s);
 
 // NYS_OP_CALLBACK product: V = scale * (caller's A P) + mu_c P_c for k
 // columns of type T (mu_dev: device array indexed by c / nrhs, or nullptr and

@@ -538,6 +538,160 @@ __global__ __launch_bounds__(NT) void uc_rz(int64_t n, int64_t l, const TU* __re
   }
 }
 
+// ---------------------------------------------------------------- apply, k = 1, 16-byte U loads
+//
+// Rows of U that are 16-byte aligned with ell a multiple of the vector width
+// (4 floats or 2 doubles) are read with one 16-byte load per lane, a wave
+// covering 64 vectors of a row.  U^T r: each thread accumulates its columns
+// over its rows (in float32 for a float32 U, float64 otherwise); the four
+// waves are combined in float64 in a fixed order.  U c: the wave forms four
+// rows' dot products at a time from 16-byte loads.
+
+template <typename TU>
+struct UVec;
+template <>
+struct UVec<float> {
+  typedef float4 type;
+  typedef float acc;
+  static constexpr int E = 4;
+  static __device__ __forceinline__ float get(const float4& v, int e) {
+    return e == 0 ? v.x : e == 1 ? v.y : e == 2 ? v.z : v.w;
+  }
+};
+template <>
+struct UVec<double> {
+  typedef double2 type;
+  typedef double acc;
+  static constexpr int E = 2;
+  static __device__ __forceinline__ double get(const double2& v, int e) { return e == 0 ? v.x : v.y; }
+};
+
+// part[chunk][j] = sum over the chunk's rows of U[i][j] r[i]; grid (column
+// groups of 64 E, row chunks); wave w takes rows w, w + 4, ... of the chunk,
+// RU rows in flight per pass.
+template <typename TU, typename T, int RU>
+__global__ __launch_bounds__(NT) void utr_vec(int64_t n, int64_t l, const TU* __restrict__ U, int64_t ldu,
+                                              const T* __restrict__ r, double* __restrict__ part,
+                                              int64_t rows_per_chunk, const int* __restrict__ alldone) {
+  typedef typename UVec<TU>::type VT;
+  typedef typename UVec<TU>::acc TA;
+  constexpr int E = UVec<TU>::E;
+  const int skip_all = alldone ? *alldone : 0;  // tested once the first loads are issued
+  __shared__ double red[4][64 * E];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t j0 = ((int64_t)blockIdx.x * 64 + lane) * E;
+  const bool ok = j0 < l;
+  const int64_t jc = ok ? j0 : 0;
+  const int64_t i0 = (int64_t)blockIdx.y * rows_per_chunk;
+  const int64_t i1 = i0 + rows_per_chunk < n ? i0 + rows_per_chunk : n;
+  TA acc[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) acc[e] = TA(0);
+  for (int64_t ib = i0 + wave; ib < i1; ib += 4 * RU) {
+    VT uv[RU];
+    TA rv[RU];
+#pragma unroll
+    for (int u = 0; u < RU; ++u) {
+      const int64_t i = ib + 4 * u;
+      const int64_t ic = i < i1 ? i : i1 - 1;
+      uv[u] = *reinterpret_cast<const VT*>(U + ic * ldu + jc);
+      rv[u] = i < i1 ? TA(r[ic]) : TA(0);
+    }
+    if (skip_all) return;
+#pragma unroll
+    for (int u = 0; u < RU; ++u)
+#pragma unroll
+      for (int e = 0; e < E; ++e) acc[e] += TA(UVec<TU>::get(uv[u], e)) * rv[u];
+  }
+  if (skip_all) return;
+#pragma unroll
+  for (int e = 0; e < E; ++e) red[wave][lane * E + e] = double(acc[e]);
+  __syncthreads();
+  for (int q = threadIdx.x; q < 64 * E; q += NT) {
+    const int64_t j = (int64_t)blockIdx.x * 64 * E + q;
+    if (j < l) part[(int64_t)blockIdx.y * l + j] = (red[0][q] + red[1][q]) + (red[2][q] + red[3][q]);
+  }
+  (void)ok;
+}
+
+// z_i = r_i + sum_j U[i][j] C'[j] with 16-byte loads: lane owns vectors
+// lane + 64 g (g < NG) of every row, four rows per pass.  Modes as uc_rz.
+template <typename TU, typename T, int NG>
+__global__ __launch_bounds__(NT) void uc_vec(int64_t n, int64_t l, const TU* __restrict__ U, int64_t ldu,
+                                             const double* __restrict__ Cs, const T* __restrict__ r,
+                                             T* __restrict__ z, int64_t rows_per_wave,
+                                             double* __restrict__ prz, CgScalars sc, int par, int mode,
+                                             T* __restrict__ Pd) {
+  typedef typename UVec<TU>::type VT;
+  constexpr int E = UVec<TU>::E;
+  const int skip_all = mode == 2 ? *sc.alldone : 0;
+  __shared__ double sh[NT];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  T cs[NG][E];
+  int64_t off[NG];
+#pragma unroll
+  for (int g = 0; g < NG; ++g) {
+    const int64_t j0 = ((int64_t)g * 64 + lane) * E;
+    off[g] = j0 < l ? j0 : 0;
+#pragma unroll
+    for (int e = 0; e < E; ++e) cs[g][e] = j0 < l ? T(Cs[j0 + e]) : T(0);
+  }
+  const int64_t w0 = ((int64_t)blockIdx.x * 4 + wave) * rows_per_wave;
+  const int64_t w1 = w0 + rows_per_wave < n ? w0 + rows_per_wave : n;
+  double rzp = 0.0;
+  for (int64_t ib = w0; ib < w1; ib += 4) {
+    const int64_t nr = (w1 - ib) < 4 ? (w1 - ib) : 4;
+    VT u[4][NG];
+    T rv[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) rv[q] = r[ib + (q < nr ? q : 0)];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int64_t row = ib + (q < nr ? q : 0);
+#pragma unroll
+      for (int g = 0; g < NG; ++g) u[q][g] = *reinterpret_cast<const VT*>(U + row * ldu + off[g]);
+    }
+    if (skip_all) return;
+    T sv[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      T acc = T(0);
+#pragma unroll
+      for (int g = 0; g < NG; ++g)
+#pragma unroll
+        for (int e = 0; e < E; ++e) acc += T(UVec<TU>::get(u[q][g], e)) * cs[g][e];  // cs = 0 past l
+      sv[q] = wave_sum(acc);
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      if (q < nr) {
+        const T zi = rv[q] + sv[q];
+        if (lane == q) z[ib + q] = zi;
+        rzp += double(rv[q]) * double(zi);
+      }
+    }
+  }
+  if (mode == 0 || skip_all) return;
+  const double tot = block_sum(lane == 0 ? rzp : 0.0, sh);
+  if (threadIdx.x == 0) prz[blockIdx.x] = tot;
+  if (!last_block(sc.ctr, gridDim.x)) return;
+  rz_tail(prz, gridDim.x, 1, sh, sc, par, mode == 1);
+  if (Pd == nullptr) return;
+  __syncthreads();
+  const T b = mode == 1 ? T(0) : T(sc.beta[0]);
+  if (mode == 1 || !sc.done[0]) {
+    if (n <= 16 * NT) update_dir<T, 16>(n, b, mode == 1, z, Pd);
+    else update_dir<T, 4>(n, b, mode == 1, z, Pd);
+  }
+}
+
+template <typename TU>
+bool uvec_ok(const PrecDesc& P) {
+  constexpr int E = UVec<TU>::E;
+  return P.ell % E == 0 && P.ldu % E == 0 && (reinterpret_cast<uintptr_t>(P.U) % 16) == 0 &&
+         P.ell <= 64 * E * 8;
+}
+
 // ---------------------------------------------------------------- apply, k > 1
 
 // C'[j][c] = ((lam_l + mu_c)/(lam_j + mu_c) - 1) C[j][c]
@@ -574,6 +728,32 @@ nys_status utr_launch(const PrecDesc& P, const double* mu_dev, const void* R, bo
                       double* Cs, unsigned* ctr, const int* alldone, hipStream_t s) {
   (void)ctr;
   const int64_t n = P.n, l = P.ell;
+  const bool vec = P.dtype == NYS_F64 ? uvec_ok<double>(P) : uvec_ok<float>(P);
+  if (vec) {
+    // 16-byte U loads: column groups of 64 vectors, row chunks sized for about
+    // four workgroups per compute unit (at most 512 chunks, >= 32 rows each)
+    const int E = P.dtype == NYS_F64 ? 2 : 4;
+    const int64_t cg = cdiv(l, (int64_t)64 * E);
+    int64_t want = cdiv((int64_t)4 * num_cus(), cg);
+    want = want < 1 ? 1 : want > 512 ? 512 : want;
+    int64_t rpc = cdiv(n, want);
+    rpc = cdiv(rpc < 32 ? 32 : rpc, 32) * 32;
+    const int64_t rc = cdiv(n, rpc);
+    dim3 grid((unsigned)cg, (unsigned)rc);
+#define LV(TU_, T_)                                                                                  \
+  hipLaunchKernelGGL((utr_vec<TU_, T_, 8>), grid, dim3(NT), 0, s, n, l, static_cast<const TU_*>(P.U), \
+                     P.ldu, static_cast<const T_*>(R), part, rpc, alldone)
+    if (P.dtype == NYS_F64 && !f32) LV(double, double);
+    else if (P.dtype == NYS_F64 && f32) LV(double, float);
+    else if (P.dtype == NYS_F32 && !f32) LV(float, double);
+    else LV(float, float);
+#undef LV
+    NYS_CHECK_LAUNCH();
+    hipLaunchKernelGGL(utr_final, dim3((unsigned)cdiv(l, 64)), dim3(NT), 0, s, l, (int)rc, part, P.lam, mu_dev,
+                       Cs, alldone);
+    NYS_CHECK_LAUNCH();
+    return NYS_OK;
+  }
   const int64_t cb = cdiv(l, 64);
   // chunks of 32 rows (8 loads per thread, all in flight), at most 512 chunks
   int64_t rpc = cdiv(n, 512);
@@ -598,7 +778,17 @@ nys_status utr_launch(const PrecDesc& P, const double* mu_dev, const void* R, bo
 template <typename TU, typename T>
 void uc_dispatch(int64_t n, int64_t l, const TU* U, int64_t ldu, const double* Cs, const T* R, T* Z,
                  int64_t rpw, double* prz, const CgScalars& sc, int par, int mode, T* Pd, unsigned nb,
-                 hipStream_t s) {
+                 hipStream_t s, bool vec) {
+  if (vec) {
+    constexpr int W = 64 * UVec<TU>::E;  // columns per vector group
+#define LG(NG) hipLaunchKernelGGL((uc_vec<TU, T, NG>), dim3(nb), dim3(NT), 0, s, n, l, U, ldu, Cs, R, Z, rpw, prz, sc, par, mode, Pd)
+    if (l <= W) LG(1);
+    else if (l <= 2 * W) LG(2);
+    else if (l <= 4 * W) LG(4);
+    else LG(8);
+#undef LG
+    return;
+  }
 #define LC(NJ) hipLaunchKernelGGL((uc_rz<TU, T, NJ>), dim3(nb), dim3(NT), 0, s, n, l, U, ldu, Cs, R, Z, rpw, prz, sc, par, mode, Pd)
   if (l <= 128) LC(2);
   else if (l <= 256) LC(4);
@@ -618,18 +808,19 @@ nys_status uc_launch(const PrecDesc& P, const double* Cs, const void* R, void* Z
   int64_t rpw = cdiv(n, 4 * 512);  // at most 512 workgroups (partial buffer size)
   rpw = cdiv(rpw < 4 ? 4 : rpw, 4) * 4;
   const unsigned nb = (unsigned)cdiv(cdiv(n, rpw), 4);
+  const bool vec = P.dtype == NYS_F64 ? uvec_ok<double>(P) : uvec_ok<float>(P);
   if (P.dtype == NYS_F64 && !f32)
     uc_dispatch<double, double>(n, l, static_cast<const double*>(P.U), P.ldu, Cs, static_cast<const double*>(R),
-                                static_cast<double*>(Z), rpw, prz, sc, par, mode, static_cast<double*>(Pd), nb, s);
+                                static_cast<double*>(Z), rpw, prz, sc, par, mode, static_cast<double*>(Pd), nb, s, vec);
   else if (P.dtype == NYS_F64 && f32)
     uc_dispatch<double, float>(n, l, static_cast<const double*>(P.U), P.ldu, Cs, static_cast<const float*>(R),
-                               static_cast<float*>(Z), rpw, prz, sc, par, mode, static_cast<float*>(Pd), nb, s);
+                               static_cast<float*>(Z), rpw, prz, sc, par, mode, static_cast<float*>(Pd), nb, s, vec);
   else if (P.dtype == NYS_F32 && !f32)
     uc_dispatch<float, double>(n, l, static_cast<const float*>(P.U), P.ldu, Cs, static_cast<const double*>(R),
-                               static_cast<double*>(Z), rpw, prz, sc, par, mode, static_cast<double*>(Pd), nb, s);
+                               static_cast<double*>(Z), rpw, prz, sc, par, mode, static_cast<double*>(Pd), nb, s, vec);
   else
     uc_dispatch<float, float>(n, l, static_cast<const float*>(P.U), P.ldu, Cs, static_cast<const float*>(R),
-                              static_cast<float*>(Z), rpw, prz, sc, par, mode, static_cast<float*>(Pd), nb, s);
+                              static_cast<float*>(Z), rpw, prz, sc, par, mode, static_cast<float*>(Pd), nb, s, vec);
   NYS_CHECK_LAUNCH();
   return NYS_OK;
 }

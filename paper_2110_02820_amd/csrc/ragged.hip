@@ -309,6 +309,103 @@ __global__ void rag_set_ints(int* __restrict__ dst, int64_t count, IntList l) {
   if ((int64_t)threadIdx.x < count) dst[threadIdx.x] = l.v[threadIdx.x];
 }
 
+// ---- device-info form: tables set by value, every decision on the device
+
+constexpr int kTabChunk = 8;  // problems per table upload (kernel argument size, ~1.6 KB)
+
+struct TabChunk {
+  RagProb tab[kTabChunk];
+  double mu[kTabChunk];
+  const double* bsrc[kTabChunk];
+  double* xdst[kTabChunk];
+};
+
+__global__ void rag_set_tab(TabChunk c, int first, int count, RagProb* __restrict__ tab, double* __restrict__ mu,
+                            const double** __restrict__ bsrc, double** __restrict__ xdst) {
+  const int i = threadIdx.x;
+  if (i >= count) return;
+  tab[first + i] = c.tab[i];
+  mu[first + i] = c.mu[i];
+  bsrc[first + i] = c.bsrc[i];
+  xdst[first + i] = c.xdst[i];
+}
+
+// relres[c] from the rag_residual partials (groups summed in order)
+__global__ void rag_relres(int64_t k, int ng, const double* __restrict__ part, double* __restrict__ relres) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= k) return;
+  double rr = 0.0, bb = 0.0;
+  for (int q = 0; q < ng; ++q) {
+    rr += part[(int64_t)q * k + c];
+    bb += part[(int64_t)(ng + q) * k + c];
+  }
+  relres[c] = bb > 0.0 ? sqrt(rr / bb) : sqrt(rr);
+}
+
+__global__ void rag_state_init(int64_t k, double* __restrict__ prev, int* __restrict__ iters, int* __restrict__ brk) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= k) return;
+  prev[c] = __builtin_huge_val();
+  iters[c] = 0;
+  brk[c] = 0;
+}
+
+// a problem is refined while its true residual exceeds tol, it has not
+// broken down and the last step at least halved its residual; prev <- relres
+__global__ void rag_select(int64_t k, const double* __restrict__ relres, double* __restrict__ prev,
+                           const int* __restrict__ brk, int* __restrict__ active, double tol) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= k) return;
+  const double r = relres[c];
+  active[c] = (!brk[c] && !(r <= tol) && r <= 0.5 * prev[c]) ? 1 : 0;
+  prev[c] = r;
+}
+
+// inner iterations and breakdowns of the active problems added to the totals
+__global__ void rag_count(int64_t k, CgScalars sc, const int* __restrict__ active, int* __restrict__ iters,
+                          int* __restrict__ brk) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= k || !active[c]) return;
+  iters[c] += sc.iters[c];
+  if (sc.status[c] == NYS_ERR_BREAKDOWN) brk[c] = 1;
+}
+
+// float64 form: the inner solve on r = b - A x0 stops at ||r_inner|| <= tol ||b||
+// (the outer test), so its reference norm is ||b||^2 from the residual partials
+__global__ void rag_bnorm_from_parts(int64_t k, int ng, const double* __restrict__ part, CgScalars sc, double tol) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= k) return;
+  double bb = 0.0;
+  for (int q = 0; q < ng; ++q) bb += part[(int64_t)(ng + q) * k + c];
+  sc.bnorm2[c] = bb;
+  const bool conv = sc.rnorm2[c] <= tol * tol * bb;
+  sc.done[c] = conv ? 1 : 0;
+  sc.conv[c] = conv ? 1 : 0;
+  sc.status[c] = conv ? NYS_OK : NYS_NOT_CONVERGED;
+}
+
+// all-done flag after the flags above changed
+__global__ void rag_alldone(int64_t k, CgScalars sc) {
+  __shared__ int any;
+  if (threadIdx.x == 0) any = 0;
+  __syncthreads();
+  for (int64_t c = threadIdx.x; c < k; c += blockDim.x)
+    if (!sc.done[c]) any = 1;
+  __syncthreads();
+  if (threadIdx.x == 0) *sc.alldone = any ? 0 : 1;
+}
+
+__global__ void rag_write_info(int64_t k, const int* __restrict__ iters, const int* __restrict__ brk,
+                               const double* __restrict__ relres, double tol, int32_t* __restrict__ o_iters,
+                               double* __restrict__ o_relres, int32_t* __restrict__ o_status) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= k) return;
+  const double r = relres[c];
+  if (o_iters) o_iters[c] = iters[c];
+  if (o_relres) o_relres[c] = r;
+  if (o_status) o_status[c] = brk[c] ? NYS_ERR_BREAKDOWN : (r <= tol ? NYS_OK : NYS_NOT_CONVERGED);
+}
+
 unsigned nb256(int64_t count) { return (unsigned)(count > 0 ? cdiv(count, (int64_t)NT) : 1); }
 
 // ---------------------------------------------------------------- host side
@@ -400,6 +497,8 @@ struct RagWs {
   RagProb* tab;
   double* mu;
   int* active;
+  double *relres_d, *prev_d;  // device-info form
+  int *iters_d, *brk_d;
   double *B64, *X64, *R64, *V64, *dots;
   double *part, *partu, *Cs;
   const double** bsrc;
@@ -442,6 +541,10 @@ void carve_rag(Arena& a, const Plan& p, int prec, RagWs& w) {
   w.tab = a.take<RagProb>(k);
   w.mu = a.take<double>(k);
   w.active = a.take<int>(k);
+  w.relres_d = a.take<double>(k);
+  w.prev_d = a.take<double>(k);
+  w.iters_d = a.take<int>(k);
+  w.brk_d = a.take<int>(k);
   w.bsrc = a.take<const double*>(k);
   w.xdst = a.take<double*>(k);
   w.B64 = a.take<double>(nk);
@@ -593,12 +696,115 @@ nys_status rag_correct(const Plan& p, RagWs& w, RagBufs<T>& b, const std::vector
   return NYS_OK;
 }
 
+// Device-info PCG: exactly maxit iterations on every column (stopped
+// columns are frozen by their flags, finished problems skip the products).
+// bnorm_parts (float64 form): stopping test against ||b|| instead of the
+// inner right-hand side.
+template <typename T>
+nys_status rag_pcg_dev(const Plan& p, RagWs& w, RagBufs<T>& b, double tol, int maxit, const double* bnorm_parts,
+                       int ng, hipStream_t s) {
+  const int64_t k = p.np, n = p.nmax, nk = n * k;
+  hipLaunchKernelGGL(rag_zero<unsigned>, dim3(1), dim3(NT), 0, s, (int64_t)64, b.sc.ctr);
+  hipLaunchKernelGGL(rag_zero<T>, dim3(nb256(nk)), dim3(NT), 0, s, nk, b.X);
+  hipLaunchKernelGGL(rag_zero<T>, dim3(nb256(nk)), dim3(NT), 0, s, nk, b.V);
+  hipLaunchKernelGGL(rag_zero<T>, dim3(nb256(nk)), dim3(NT), 0, s, nk, b.Z);
+  NYS_CHECK_LAUNCH();
+  NYS_TRY(cg_block_init<T>(n, k, b.B, b.V, b.R, b.w, b.sc, tol, s));
+  if (bnorm_parts) {
+    hipLaunchKernelGGL(rag_bnorm_from_parts, dim3(nb256(k)), dim3(NT), 0, s, k, ng, bnorm_parts, b.sc, tol);
+    hipLaunchKernelGGL(rag_alldone, dim3(1), dim3(NT), 0, s, k, b.sc);
+    NYS_CHECK_LAUNCH();
+  }
+  NYS_TRY(rag_apply<T>(p, w, b.R, b.Z, nullptr, nullptr, s));
+  NYS_TRY(cg_block_direction<T>(n, k, b.R, b.Z, b.P, b.w, b.sc, 0, true, s));
+  for (int it = 0; it < maxit; ++it) {
+    const int par = it & 1;
+    NYS_TRY((rag_matvec<T, T>(p, w, b.P, b.V, b.sc.done, b.sc.alldone, s)));
+    NYS_TRY(cg_block_update<T>(n, k, b.V, b.X, b.R, b.P, b.w, b.sc, par, tol, s));
+    NYS_TRY(rag_apply<T>(p, w, b.R, b.Z, b.sc.done, b.sc.alldone, s));
+    NYS_TRY(cg_block_direction<T>(n, k, b.R, b.Z, b.P, b.w, b.sc, par, false, s));
+  }
+  return NYS_OK;
+}
+
+// R64 = B64 - (A + mu I) X64 and relres_d on the device
+nys_status rag_true_residual_dev(const Plan& p, RagWs& w, hipStream_t s) {
+  const int64_t k = p.np, n = p.nmax;
+  NYS_TRY((rag_matvec<double, double>(p, w, w.X64, w.V64, nullptr, nullptr, s)));
+  const int g = 64;
+  hipLaunchKernelGGL(rag_residual, dim3(g), dim3(NT), 0, s, n, k, w.B64, w.V64, w.R64, w.dots);
+  hipLaunchKernelGGL(rag_relres, dim3(nb256(k)), dim3(NT), 0, s, k, g, w.dots, w.relres_d);
+  NYS_CHECK_LAUNCH();
+  return NYS_OK;
+}
+
+nys_status ragged_solve_device(const Plan& p, const double* mu, const double* const* B, double* const* X,
+                               const nys_solve_opts* o, nys_solve_info* info, RagWs& w, hipStream_t s) {
+  const int64_t k = p.np, nk = p.nmax * k;
+  const double tol = o->tol;
+  const int maxit = o->maxit > 0 ? o->maxit : 500;
+  // problem table, mu and vector pointers by value (no host-to-device copy)
+  for (int64_t c0 = 0; c0 < k; c0 += kTabChunk) {
+    TabChunk ch{};
+    const int cnt = (int)std::min<int64_t>(kTabChunk, k - c0);
+    for (int i = 0; i < cnt; ++i) {
+      ch.tab[i] = p.tab[c0 + i];
+      ch.mu[i] = mu[c0 + i];
+      ch.bsrc[i] = B[c0 + i];
+      ch.xdst[i] = X[c0 + i];
+    }
+    hipLaunchKernelGGL(rag_set_tab, dim3(1), dim3(kTabChunk), 0, s, ch, (int)c0, cnt, w.tab, w.mu, w.bsrc, w.xdst);
+    NYS_CHECK_LAUNCH();
+  }
+  hipLaunchKernelGGL(rag_zero<double>, dim3(nb256(nk)), dim3(NT), 0, s, nk, w.V64);
+  hipLaunchKernelGGL(rag_zero<double>, dim3(nb256(nk)), dim3(NT), 0, s, nk, w.R64);
+  hipLaunchKernelGGL((rag_pack<double, double>), dim3(nb256(p.nmax), (unsigned)k), dim3(NT), 0, s, w.tab, k, p.nmax,
+                     w.bsrc, w.B64);
+  hipLaunchKernelGGL((rag_pack<double, double>), dim3(nb256(p.nmax), (unsigned)k), dim3(NT), 0, s, w.tab, k, p.nmax,
+                     (const double* const*)w.xdst, w.X64);
+  hipLaunchKernelGGL(rag_state_init, dim3(nb256(k)), dim3(NT), 0, s, k, w.prev_d, w.iters_d, w.brk_d);
+  NYS_CHECK_LAUNCH();
+  NYS_TRY(rag_true_residual_dev(p, w, s));
+  const bool f64 = o->prec == NYS_PREC_FP64;
+  const int steps = f64 ? 1 : (o->max_refine > 0 ? o->max_refine : 10);
+  const double itol = o->inner_tol > 0 ? o->inner_tol : 1e-4;
+  for (int step = 0; step < steps; ++step) {
+    hipLaunchKernelGGL(rag_select, dim3(nb256(k)), dim3(NT), 0, s, k, w.relres_d, w.prev_d, w.brk_d, w.active, tol);
+    NYS_CHECK_LAUNCH();
+    if (f64) {
+      hipLaunchKernelGGL((rag_masked_copy<double>), dim3(nb256(nk)), dim3(NT), 0, s, nk, k, w.R64, w.active, w.d.B);
+      NYS_CHECK_LAUNCH();
+      NYS_TRY(rag_pcg_dev<double>(p, w, w.d, tol, maxit, w.dots, 64, s));
+      hipLaunchKernelGGL((rag_add<double>), dim3(nb256(nk)), dim3(NT), 0, s, nk, w.X64, w.d.X);
+      hipLaunchKernelGGL(rag_count, dim3(nb256(k)), dim3(NT), 0, s, k, w.d.sc, w.active, w.iters_d, w.brk_d);
+    } else {
+      hipLaunchKernelGGL((rag_masked_copy<float>), dim3(nb256(nk)), dim3(NT), 0, s, nk, k, w.R64, w.active, w.f.B);
+      NYS_CHECK_LAUNCH();
+      NYS_TRY(rag_pcg_dev<float>(p, w, w.f, itol, maxit, nullptr, 0, s));
+      hipLaunchKernelGGL((rag_add<float>), dim3(nb256(nk)), dim3(NT), 0, s, nk, w.X64, w.f.X);
+      hipLaunchKernelGGL(rag_count, dim3(nb256(k)), dim3(NT), 0, s, k, w.f.sc, w.active, w.iters_d, w.brk_d);
+    }
+    NYS_CHECK_LAUNCH();
+    NYS_TRY(rag_true_residual_dev(p, w, s));
+  }
+  hipLaunchKernelGGL(rag_write_info, dim3(nb256(k)), dim3(NT), 0, s, k, w.iters_d, w.brk_d, w.relres_d, tol,
+                     info ? info->iters : nullptr, info ? info->relres : nullptr, info ? info->status : nullptr);
+  hipLaunchKernelGGL(rag_unpack, dim3(nb256(p.nmax), (unsigned)k), dim3(NT), 0, s, w.tab, k, w.X64, w.xdst);
+  NYS_CHECK_LAUNCH();
+  if (info) {
+    info->refine_steps = f64 ? 0 : steps;
+    info->total_iters = steps * maxit;
+  }
+  return NYS_OK;
+}
+
 }  // namespace
 
 bool ragged_supported(const OpDesc* ops, const PrecDesc* pds, int nprob) {
   if (nprob < 1 || nprob > kMaxProb) return false;
   for (int c = 0; c < nprob; ++c) {
     if (ops[c].kind != NYS_OP_XTX || ops[c].dtype != ops[0].dtype || pds[c].dtype != pds[0].dtype) return false;
+    if (ops[c].w != nullptr) return false;  // weighted operators: one solve after the other
     if (ops[c].n > kMaxN || pds[c].ell > kMaxEll || pds[c].n != ops[c].n) return false;
   }
   return true;
@@ -623,6 +829,7 @@ nys_status ragged_solve(const OpDesc* ops, const PrecDesc* pds, const double* mu
     set_error("workspace too small: need %zu bytes", a.off);
     return NYS_ERR_WORKSPACE;
   }
+  if (o->device_info) return ragged_solve_device(p, mu, B, X, o, info, w, s);
   const int64_t k = nprob, nk = p.nmax * k;
   const double tol = o->tol;
   const int maxit = o->maxit > 0 ? o->maxit : 500;

@@ -15,11 +15,25 @@
 // 256 with zeros, so operand loads never leave the prepared arrays.
 #include "rbf_lowp.hpp"
 
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
 #include <type_traits>
+#include <vector>
 
 namespace nys {
 
 namespace {
+
+// True when every column c0 .. c0 + nc - 1 (below k) is flagged in done
+// (uniform across the block: every thread reads the same flags).
+__device__ __forceinline__ bool cols_done(const int* __restrict__ done, int64_t c0, int nc, int64_t k) {
+  if (!done) return false;
+  for (int64_t c = c0; c < c0 + nc && c < k; ++c)
+    if (!done[c]) return false;
+  return true;
+}
 
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
@@ -315,6 +329,7 @@ __global__ __launch_bounds__(256) void rbf_kv_lowp(RbfLowp L, const float* __res
   const int64_t n = L.n;
   const int64_t i0 = (int64_t)blockIdx.x * 64;
   const int64_t c0 = (int64_t)blockIdx.y * NC;
+  const bool dead = cols_done(L.coldone, c0, NC, k);  // zeros out, no products
   const float two_s = L.two_s;
   Operand<MODE> a;
   a.load(L, i0 + wave * 16 + (lane & 15), lane);
@@ -327,6 +342,7 @@ __global__ __launch_bounds__(256) void rbf_kv_lowp(RbfLowp L, const float* __res
   const int64_t j0 = (int64_t)blockIdx.z * pts_per_split;
   int64_t j1 = j0 + pts_per_split;
   if (j1 > n) j1 = n;
+  if (dead) j1 = j0;
   // registers for the next tile: P entries and the two 16-point operands
   uint4 pr[PE];
   Operand<MODE> b0, b1;
@@ -417,6 +433,7 @@ __global__ __launch_bounds__(256) void rbf_kv_reg32(RbfLowp L, const float* __re
   const int64_t j0 = (int64_t)blockIdx.z * pts_per_split;
   int64_t j1 = j0 + pts_per_split;
   if (j1 > n) j1 = n;
+  if (cols_done(L.coldone, c0, 16 * CF, k)) j1 = j0;  // zeros out, no products
   for (int64_t jt = j0; jt < j1; jt += 16) {
     // points jt .. jt + 15 lie inside the padded arrays (jt < n, npad a multiple of 256)
     Operand<1> b;
@@ -521,6 +538,7 @@ __global__ __launch_bounds__(256) void rbf_kv_reg(RbfLowp L, const uint4* __rest
   const int64_t j0 = (int64_t)blockIdx.z * pts_per_split;
   int64_t j1 = j0 + pts_per_split;
   if (j1 > n) j1 = n;
+  if (cols_done(L.coldone, c0, 16 * CF, k)) j1 = j0;  // zeros out, no products
   for (int64_t jt = j0; jt < j1; jt += 32) {
     // points jt .. jt + 31 lie inside the padded arrays (jt < n, npad a
     // multiple of 256); P pieces are zero for points >= n
@@ -609,6 +627,9 @@ nys_status rbf_lowp_prepare(const OpDesc& op, void* buf, RbfLowp& L, hipStream_t
   L.two_s = (float)(2.0 * sc);
   L.scale = (float)op.scale;
   L.ksteps = (int)cdiv(d, (int64_t)4);
+  L.d = (int)d;
+  L.kq = 0;
+  L.coldone = nullptr;
   if (op.dtype == NYS_F64)
     hipLaunchKernelGGL(rbf_prepare<double>, dim3((unsigned)cdiv(npad, 256)), dim3(256), 0, s,
                        static_cast<const double*>(op.data), n, d, op.ld, npad, sc, L.Xhi, L.Xlo, L.X32, L.hs);
@@ -660,24 +681,34 @@ nys_status rbf_lowp_mv(const RbfLowp& L, int mode, const float* p, const double*
 // block, P pre-split into bf16 pieces.
 struct KvPlan {
   bool reg;
-  int cf, f;
+  int cf, f, bpc;
   int64_t nc, kq, rows, tiles;
   size_t prep_elems;  // float elements of the prepared P
 };
 
-KvPlan kv_plan(int64_t n, int64_t k, int mode) {
+// The built-in choice: register kernel up to 64 columns (one, two or four
+// 16-column tiles), the LDS kernel past that (256 columns per block past 128
+// columns: half the Gram / exp / split work per column), about eight
+// workgroups per compute unit.
+KvChoice kv_heuristic(int64_t k) {
+  KvChoice c{};
+  c.reg = k <= 64 ? 1 : 0;
+  c.cf = c.reg ? (k <= 16 ? 1 : k <= 32 ? 2 : 4) : (k > 128 ? 16 : 8);
+  c.bpc = 8;
+  return c;
+}
+
+KvPlan make_plan(int64_t n, int64_t k, int mode, KvChoice c) {
   KvPlan p{};
   const int64_t npad = cdiv(n, 256) * 256;
-  p.reg = k <= 64;
+  p.reg = c.reg != 0;
+  p.cf = c.cf;
+  p.bpc = c.bpc;
   if (p.reg) {
-    p.cf = k <= 16 ? 1 : k <= 32 ? 2 : 4;
     p.f = mode == RBF_GRAM_F32 && p.cf < 4 ? 4 : 2;
     p.nc = 16 * p.cf;
     p.rows = 64 * p.f;
   } else {
-    // past 128 columns: 256 columns per block halve the Gram / exp / split
-    // work per column (two workgroups per CU instead of three)
-    p.cf = k > 128 ? 16 : 8;
     p.f = 1;
     p.nc = 16 * p.cf;
     p.rows = 64;
@@ -691,12 +722,158 @@ KvPlan kv_plan(int64_t n, int64_t k, int mode) {
   return p;
 }
 
+// Every choice the autotuner times (and that a tuned table may name).
+std::vector<KvChoice> kv_candidates() {
+  std::vector<KvChoice> v;
+  const int regcf[3] = {1, 2, 4}, ldscf[2] = {8, 16}, bpcs[3] = {4, 8, 16};
+  for (int b : bpcs) {
+    for (int cf : regcf) v.push_back(KvChoice{1, cf, b});
+    for (int cf : ldscf) v.push_back(KvChoice{0, cf, b});
+  }
+  return v;
+}
+
+bool valid_choice(const KvChoice& c) {
+  const bool cf_ok = c.reg ? (c.cf == 1 || c.cf == 2 || c.cf == 4) : (c.cf == 8 || c.cf == 16);
+  return (c.reg == 0 || c.reg == 1) && cf_ok && (c.bpc == 4 || c.bpc == 8 || c.bpc == 16);
+}
+
+// ---- autotuner table
+
+struct TuneEntry {
+  int64_t n, k;
+  int d, mode;
+  KvChoice c;
+  double us;
+};
+
+static std::mutex g_tune_mu;
+static std::vector<TuneEntry> g_tune;
+static bool g_tune_env_done = false;
+
+// caller holds g_tune_mu
+static void tune_put(const TuneEntry& e) {
+  for (TuneEntry& t : g_tune)
+    if (t.n == e.n && t.k == e.k && t.d == e.d && t.mode == e.mode) {
+      t = e;
+      return;
+    }
+  g_tune.push_back(e);
+}
+
+// caller holds g_tune_mu
+static nys_status tune_load_locked(const char* path) {
+  FILE* f = std::fopen(path, "r");
+  if (!f) {
+    set_error("autotune cache %s cannot be opened", path);
+    return NYS_ERR_ARG;
+  }
+  std::vector<TuneEntry> got;
+  char line[512];
+  int lineno = 0;
+  nys_status st = NYS_OK;
+  while (std::fgets(line, sizeof(line), f)) {
+    ++lineno;
+    if (line[0] == '#' || line[0] == '\n' || line[0] == '\0') continue;
+    TuneEntry e{};
+    long long n = 0, k = 0;
+    char tag[32] = "";
+    const int got_n = std::sscanf(line, "%31s %lld %d %d %lld %d %d %d %lf", tag, &n, &e.d, &e.mode, &k, &e.c.reg,
+                                  &e.c.cf, &e.c.bpc, &e.us);
+    e.n = n;
+    e.k = k;
+    if (got_n != 9 || std::strcmp(tag, "rbf_kv") != 0 || n < 1 || k < 1 || e.d < 1 || e.d > 32 ||
+        (e.mode != RBF_GRAM_BF16X3 && e.mode != RBF_GRAM_F32) || !valid_choice(e.c)) {
+      set_error("autotune cache %s: line %d is not a valid entry", path, lineno);
+      st = NYS_ERR_ARG;
+      break;
+    }
+    got.push_back(e);
+  }
+  std::fclose(f);
+  if (st != NYS_OK) return st;
+  for (const TuneEntry& e : got) tune_put(e);
+  return NYS_OK;
+}
+
+static void tune_env_load_locked() {
+  if (g_tune_env_done) return;
+  g_tune_env_done = true;
+  const char* p = std::getenv("NYS_AUTOTUNE_CACHE");
+  if (p && *p) {
+    FILE* f = std::fopen(p, "r");
+    if (f) {
+      std::fclose(f);
+      (void)tune_load_locked(p);  // an unreadable cache leaves the heuristic in place
+    }
+  }
+}
+
+KvChoice kv_choice(const RbfLowp& L, int64_t k, int mode, bool* tuned) {
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  tune_env_load_locked();
+  const TuneEntry* best = nullptr;
+  for (const TuneEntry& t : g_tune)
+    if (t.n == L.n && t.d == L.d && t.mode == mode && t.k >= k && (!best || t.k < best->k)) best = &t;
+  if (tuned) *tuned = best != nullptr;
+  return best ? best->c : kv_heuristic(k);
+}
+
+int64_t kv_tune_entries() {
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  return (int64_t)g_tune.size();
+}
+
+void kv_tune_clear() {
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  g_tune.clear();
+  g_tune_env_done = true;  // a cleared table stays empty until loaded again
+}
+
+nys_status kv_tune_load(const char* path) {
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  return tune_load_locked(path);
+}
+
+nys_status kv_tune_save(const char* path) {
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  FILE* f = std::fopen(path, "w");
+  if (!f) {
+    set_error("autotune cache %s cannot be written", path);
+    return NYS_ERR_ARG;
+  }
+  std::fprintf(f, "# nyspcg autotune cache: rbf_kv n d mode k reg cf bpc microseconds\n");
+  for (const TuneEntry& t : g_tune)
+    std::fprintf(f, "rbf_kv %lld %d %d %lld %d %d %d %.3f\n", (long long)t.n, t.d, t.mode, (long long)t.k, t.c.reg,
+                 t.c.cf, t.c.bpc, t.us);
+  const bool ok = std::fclose(f) == 0;
+  if (!ok) {
+    set_error("autotune cache %s: write failed", path);
+    return NYS_ERR_ARG;
+  }
+  return NYS_OK;
+}
+
+void kv_tune_env_save() {
+  const char* p = std::getenv("NYS_AUTOTUNE_CACHE");
+  if (p && *p) (void)kv_tune_save(p);
+}
+
 size_t rbf_lowp_kv_scratch(int64_t n, int64_t k) {
+  // the largest prepared P over every choice, plus the point-split partial
+  // sums at eight workgroups per compute unit (choices that ask for more
+  // splits are cut to what the scratch holds)
   size_t m = 0;
   for (int mode = 0; mode < 2; ++mode) {
-    const KvPlan p = kv_plan(n, k, mode);
-    const int64_t nz = cdiv(8 * 256, p.tiles);
-    const size_t e = p.prep_elems + (nz > 1 ? (size_t)nz * (size_t)n * (size_t)k : 0);
+    size_t prep = 0;
+    int64_t tiles_min = 0;
+    for (const KvChoice& c : kv_candidates()) {
+      const KvPlan p = make_plan(n, k, mode, c);
+      prep = p.prep_elems > prep ? p.prep_elems : prep;
+      tiles_min = tiles_min == 0 || p.tiles < tiles_min ? p.tiles : tiles_min;
+    }
+    const int64_t nz = cdiv(8 * 256, tiles_min);
+    const size_t e = prep + (nz > 1 ? (size_t)nz * (size_t)n * (size_t)k : 0);
     m = e > m ? e : m;
   }
   return m;
@@ -713,11 +890,26 @@ __global__ void rbf_lowp_add_mu(int64_t n, int64_t k, const float* __restrict__ 
   V[i * ldv + c] += float(mu[c / nrhs]) * P[i * ldp + c];
 }
 
+nys_status rbf_lowp_kv_plan(const RbfLowp& L, int mode, const KvPlan& pl, const float* P, int64_t ldp, int64_t k,
+                            const double* mu_dev, int64_t nrhs, float* V, int64_t ldv, float* scratch,
+                            size_t scratch_elems, const int* skip, hipStream_t s);
+
 nys_status rbf_lowp_kv(const RbfLowp& L, int mode, const float* P, int64_t ldp, int64_t k, const double* mu_dev,
                        int64_t nrhs, float* V, int64_t ldv, float* scratch, size_t scratch_elems, const int* skip,
-                       hipStream_t s) {
+                       hipStream_t s, const int* coldone) {
   const int64_t n = L.n;
-  const KvPlan pl = kv_plan(n, k, mode);
+  RbfLowp Lc = L;
+  Lc.coldone = coldone;
+  // with column flags, the shape chosen for 16 columns (blocks of 16 columns
+  // at most), so that finished columns free whole blocks
+  const KvPlan pl = make_plan(n, k, mode, kv_choice(L, coldone && k > 16 ? 16 : k, mode, nullptr));
+  return rbf_lowp_kv_plan(Lc, mode, pl, P, ldp, k, mu_dev, nrhs, V, ldv, scratch, scratch_elems, skip, s);
+}
+
+nys_status rbf_lowp_kv_plan(const RbfLowp& L, int mode, const KvPlan& pl, const float* P, int64_t ldp, int64_t k,
+                            const double* mu_dev, int64_t nrhs, float* V, int64_t ldv, float* scratch,
+                            size_t scratch_elems, const int* skip, hipStream_t s) {
+  const int64_t n = L.n;
   const int64_t nc = pl.nc;
   // the kernels read P split once into bf16 pieces (front of the scratch)
   const size_t se = pl.prep_elems;
@@ -749,9 +941,9 @@ nys_status rbf_lowp_kv(const RbfLowp& L, int mode, const float* P, int64_t ldp, 
   scratch += se;
   scratch_elems -= se;
   const int64_t tiles = pl.tiles;
-  // about eight blocks per compute unit: the per-tile chain (loads, LDS,
-  // barriers, MFMA) is latency-bound with fewer waves per SIMD
-  int64_t nz = cdiv(8 * (num_cus() < 256 ? num_cus() : 256), tiles);
+  // about bpc blocks per compute unit (eight by default): the per-tile chain
+  // (loads, LDS, barriers, MFMA) is latency-bound with fewer waves per SIMD
+  int64_t nz = cdiv(pl.bpc * (num_cus() < 256 ? num_cus() : 256), tiles);
   if (nz < 1) nz = 1;
   while (nz > 1 && (size_t)(nz * n * k) > scratch_elems) --nz;
   const int64_t pps = cdiv(cdiv(n, nz), 32) * 32;
@@ -794,6 +986,74 @@ nys_status rbf_lowp_kv(const RbfLowp& L, int mode, const float* P, int64_t ldp, 
     hipLaunchKernelGGL(rbf_lowp_add_mu, dim3((unsigned)cdiv(n * k, 256)), dim3(256), 0, s, n, k, P, ldp, mu_dev, nrhs,
                        V, ldv, skip);
     NYS_CHECK_LAUNCH();
+  }
+  return NYS_OK;
+}
+
+__global__ void fill_value(float* __restrict__ p, int64_t count, float v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) p[i] = v;
+}
+
+nys_status rbf_lowp_autotune(const RbfLowp& L0, int mode, const int64_t* ks, int nks, float* P, float* V,
+                             float* scratch, size_t scratch_elems, hipStream_t s) {
+  RbfLowp L = L0;
+  L.coldone = nullptr;
+  const int64_t n = L.n;
+  int64_t kmax = 0;
+  for (int i = 0; i < nks; ++i) kmax = ks[i] > kmax ? ks[i] : kmax;
+  // any finite block: the timing does not depend on the values
+  hipLaunchKernelGGL(fill_value, dim3((unsigned)cdiv(n * kmax, 256)), dim3(256), 0, s, P, n * kmax, 1.0f / 64.0f);
+  NYS_CHECK_LAUNCH();
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  NYS_HIP(hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    set_error("autotune: event creation failed");
+    return NYS_ERR_DEVICE;
+  }
+  nys_status st = NYS_OK;
+  std::vector<TuneEntry> found;
+  for (int i = 0; i < nks && st == NYS_OK; ++i) {
+    const int64_t k = ks[i];
+    double best_us = 0.0;
+    KvChoice best{};
+    for (const KvChoice& c : kv_candidates()) {
+      const KvPlan pl = make_plan(n, k, mode, c);
+      if (pl.prep_elems > scratch_elems) continue;
+      // one untimed launch, then the mean of three
+      st = rbf_lowp_kv_plan(L, mode, pl, P, k, k, nullptr, 1, V, k, scratch, scratch_elems, nullptr, s);
+      if (st != NYS_OK) break;
+      if (hipEventRecord(e0, s) != hipSuccess) {
+        set_error("autotune: event record failed");
+        st = NYS_ERR_DEVICE;
+        break;
+      }
+      for (int r = 0; r < 3 && st == NYS_OK; ++r)
+        st = rbf_lowp_kv_plan(L, mode, pl, P, k, k, nullptr, 1, V, k, scratch, scratch_elems, nullptr, s);
+      if (st != NYS_OK) break;
+      float ms = 0.0f;
+      if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+          hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+        set_error("autotune: event timing failed");
+        st = NYS_ERR_DEVICE;
+        break;
+      }
+      const double us = 1e3 * (double)ms / 3.0;
+      if (best_us == 0.0 || us < best_us) {
+        best_us = us;
+        best = c;
+      }
+    }
+    if (st == NYS_OK && best_us > 0.0) found.push_back(TuneEntry{n, k, L.d, mode, best, best_us});
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st != NYS_OK) return st;
+  {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    tune_env_load_locked();
+    for (const TuneEntry& e : found) tune_put(e);
   }
   return NYS_OK;
 }

@@ -15,6 +15,7 @@ namespace nys {
 namespace {
 
 // ------------------------------------------------------------- X^T X
+// (with row weights d, X^T D X: t_r = d_r x_r^T p)
 
 template <typename TD>
 struct Vec16;
@@ -60,7 +61,7 @@ template <typename TD, typename TA, typename VP, int NV, int R>
 __global__ __launch_bounds__(256) void xtx_fused(const TD* __restrict__ X, int64_t m, int64_t n,
                                                  int64_t ld, const TA* __restrict__ p,
                                                  TA* __restrict__ part, int64_t rows_per_wg,
-                                                 const int* __restrict__ skip) {
+                                                 const int* __restrict__ skip, const double* __restrict__ wts) {
   const int sk = skip ? *skip : 0;  // tested once the first loads are issued
   typedef typename VP::type VT;
   constexpr int E = VP::E;
@@ -86,7 +87,7 @@ __global__ __launch_bounds__(256) void xtx_fused(const TD* __restrict__ X, int64
   const int64_t r1 = (r0 + rows_per_wg < m) ? r0 + rows_per_wg : m;
   int buf = 0;
   // one group of RR rows held in registers: t_r = x_r^T p, acc += t_r x_r
-  auto process = [&](VT(&xr)[R][NV], int rr) {
+  auto process = [&](VT(&xr)[R][NV], int rr, int64_t row0) {
     TA d[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -109,7 +110,8 @@ __global__ __launch_bounds__(256) void xtx_fused(const TD* __restrict__ X, int64
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       if (r >= rr) break;
-      const TA tr = red[buf][0][r] + red[buf][1][r] + red[buf][2][r] + red[buf][3][r];
+      TA tr = red[buf][0][r] + red[buf][1][r] + red[buf][2][r] + red[buf][3][r];
+      if (wts) tr *= TA(wts[row0 + r]);  // weighted operator: d_r x_r^T p
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
         if (!ok[v]) continue;
@@ -133,12 +135,12 @@ __global__ __launch_bounds__(256) void xtx_fused(const TD* __restrict__ X, int64
   // issued one group ahead and the last prefetch of a range re-reads valid rows
   for (; rb + 2 * R <= r1; rb += 2 * R) {
     load(nxt, rb + R);
-    process(cur, R);
+    process(cur, R, rb);
     load(cur, (rb + 3 * R <= r1) ? rb + 2 * R : rb + R);
-    process(nxt, R);
+    process(nxt, R, rb + R);
   }
   if (rb + R <= r1) {  // cur holds rows rb .. rb + R - 1
-    process(cur, R);
+    process(cur, R, rb);
     rb += R;
   }
   if (rb < r1) {  // fewer than R rows left
@@ -148,7 +150,7 @@ __global__ __launch_bounds__(256) void xtx_fused(const TD* __restrict__ X, int64
 #pragma unroll
       for (int v = 0; v < NV; ++v)
         cur[r][v] = *reinterpret_cast<const VT*>(X + (rb + (r < rr ? r : 0)) * ld + off[v]);
-    process(cur, rr);
+    process(cur, rr, rb);
   }
   TA* out = part + (int64_t)blockIdx.x * n;
 #pragma unroll
@@ -212,7 +214,7 @@ nys_status xtx_partials(const OpDesc& op, const TA* p, TA* scratch, size_t scrat
     set_error("X^T X operator: n = %lld too large for the one-pass kernel", (long long)n);
     return NYS_ERR_ARG;
   }
-#define LX(VP_, NV, RR) hipLaunchKernelGGL((xtx_fused<TD, TA, VP_, NV, RR>), dim3((unsigned)ng), dim3(256), 0, s, X, m, n, op.ld, p, scratch, rpw, op.skip)
+#define LX(VP_, NV, RR) hipLaunchKernelGGL((xtx_fused<TD, TA, VP_, NV, RR>), dim3((unsigned)ng), dim3(256), 0, s, X, m, n, op.ld, p, scratch, rpw, op.skip, op.w)
   timing_mark_begin(s);
   if (aligned) {
     if (need_nv <= 1) LX(Vec16<TD>, 1, 4);

@@ -22,7 +22,7 @@ def L():
 
 def declared_functions():
     src = open(os.path.join(ROOT, "include", "nyspcg.h")).read()
-    return sorted(set(re.findall(r"^\s*(?:const\s+char\*|size_t|nys_status)\s+(nys_\w+)\s*\(", src, re.M)))
+    return sorted(set(re.findall(r"^\s*(?:const\s+char\*|size_t|int64_t|nys_status)\s+(nys_\w+)\s*\(", src, re.M)))
 
 
 def test_header_declares_the_four_entry_points():
@@ -144,3 +144,60 @@ def test_workspace_size_grows_with_problem(L):
     a = L.nys_workspace_size(ctypes.byref(_op(nys, n=1000, rows=1000, cols=1000)), 50, 1, 0)
     b = L.nys_workspace_size(ctypes.byref(_op(nys, n=2000, rows=2000, cols=2000)), 100, 1, 0)
     assert 0 < a < b
+
+
+def test_autotune_table_load_save_query(L, tmp_path):
+    """The tile-shape table of the RBF block products: a cache file is merged
+    into the table, a lookup takes the entry with the smallest tuned column
+    count >= k for the same (n, d, Gram precision) and falls back to the
+    built-in rule otherwise, save writes what was loaded, and a malformed
+    file is rejected as a whole.  Host only: the operator's data pointer is
+    never dereferenced by these calls."""
+    import paper_2110_02820_amd as nys
+    L.nys_autotune_clear()
+    assert L.nys_autotune_entries() == 0
+    # RBF operator, n = 5000 points in d = 16 (pointer not used by the lookup)
+    op = nys._Operator(nys.NYS_OP_RBF, nys.NYS_F32, 5000, ctypes.c_void_p(1), 5000, 16, 16, 4.0, 1.0)
+    ch = (ctypes.c_int32 * 3)()
+    tuned = ctypes.c_int32(7)
+    f32 = nys.NYS_PREC_FP32_REFINE64
+    bf = nys.NYS_PREC_BF16X3_REFINE64
+    # built-in rule: register kernel with 1 / 2 / 4 tiles up to 64 columns, LDS kernel past that
+    for k, want in ((8, (1, 1, 8)), (32, (1, 2, 8)), (64, (1, 4, 8)), (100, (0, 8, 8)), (256, (0, 16, 8))):
+        assert L.nys_autotune_query(ctypes.byref(op), f32, k, ch, ctypes.byref(tuned)) == 0
+        assert tuple(ch) == want and tuned.value == 0
+    cache = tmp_path / "tune.txt"
+    cache.write_text("# comment\n"
+                     "rbf_kv 5000 16 1 16 1 4 16 10.5\n"
+                     "rbf_kv 5000 16 1 128 0 16 4 99.0\n"
+                     "rbf_kv 5000 16 0 128 1 2 8 77.0\n"
+                     "rbf_kv 6000 16 1 512 1 1 4 1.0\n")
+    assert L.nys_autotune_load(str(cache).encode()) == 0
+    assert L.nys_autotune_entries() == 4
+    cases = [(f32, 10, (1, 4, 16), 1), (f32, 16, (1, 4, 16), 1), (f32, 17, (0, 16, 4), 1),
+             (f32, 128, (0, 16, 4), 1), (f32, 129, (0, 16, 8), 0), (bf, 100, (1, 2, 8), 1), (bf, 8, (1, 2, 8), 1)]
+    for prec, k, want, t in cases:
+        assert L.nys_autotune_query(ctypes.byref(op), prec, k, ch, ctypes.byref(tuned)) == 0
+        assert (tuple(ch), tuned.value) == (want, t), (prec, k)
+    # another d: no entry applies
+    op_d8 = nys._Operator(nys.NYS_OP_RBF, nys.NYS_F32, 5000, ctypes.c_void_p(1), 5000, 8, 8, 4.0, 1.0)
+    assert L.nys_autotune_query(ctypes.byref(op_d8), f32, 16, ch, ctypes.byref(tuned)) == 0
+    assert tuned.value == 0
+    out = tmp_path / "saved.txt"
+    assert L.nys_autotune_save(str(out).encode()) == 0
+    rows = sorted(l.split()[:8] for l in out.read_text().splitlines() if not l.startswith("#"))
+    src = sorted(l.split()[:8] for l in cache.read_text().splitlines() if not l.startswith("#"))
+    assert rows == src
+    # a malformed file (cf 3 is no shape) changes nothing
+    bad = tmp_path / "bad.txt"
+    bad.write_text("rbf_kv 5000 16 1 32 1 3 8 1.0\n")
+    assert L.nys_autotune_load(str(bad).encode()) == nys.NYS_ERR_ARG
+    assert L.nys_autotune_entries() == 4
+    assert L.nys_autotune_load(str(tmp_path / "missing.txt").encode()) == nys.NYS_ERR_ARG
+    # loading again replaces entries with the same key instead of adding them
+    assert L.nys_autotune_load(str(cache).encode()) == 0
+    assert L.nys_autotune_entries() == 4
+    # only reduced-precision RBF products are tuned
+    assert L.nys_autotune_query(ctypes.byref(op), nys.NYS_PREC_FP64, 16, ch, None) == nys.NYS_ERR_ARG
+    L.nys_autotune_clear()
+    assert L.nys_autotune_entries() == 0

@@ -99,10 +99,17 @@ def test_large_tile_products(case):
         Om, Y = nys.nys_sketch(op, 212, omega0=t64(om0), prec=prec)
         Om, Y = h(Om), h(Y)
         Q = oracle.orthonormalize(om0)
-        ref = oracle.XtXOp(X.astype(np.float64)).matmat(Q)
+        Xd = X.astype(np.float64)
+        ref = oracle.XtXOp(Xd).matmat(Q)
         # float32 products over K = 4001 and 1204 terms: relative error ~1e-6;
         # bf16x3 products (hi/lo split, lo*lo dropped): ~3 * 2^-18 per product
         assert rel(Y @ Om.T, ref @ Q.T) < (1e-4 if bf else 2e-5)
+        # entry by entry against X^T X times the device's own test matrix, each
+        # entry bounded by c |X|^T |X| |Omega| (c: the per-product relative error
+        # of the two roundings with margin), ragged tail tiles included
+        err = np.abs(Y - oracle.XtXOp(Xd).matmat(Om))
+        scale = np.abs(Xd).T @ (np.abs(Xd) @ np.abs(Om))
+        assert (err / scale).max() < (1e-4 if bf else 5e-5), (err / scale).max()
 
 
 @pytest.mark.parametrize("d", [1, 8, 33])
@@ -158,6 +165,13 @@ def test_factor_matches_oracle(n, ell):
     bound = 1e-13 + 4e-14 * s2.max() / np.sqrt(np.outer(s2, s2))
     assert np.all(np.abs(U.T @ U - np.eye(ell)) <= bound)
     assert np.all(np.diff(lam) <= 0)
+    # the shift nu = eps(||Y||_F): the same float64 number as the oracle's, unless
+    # ||Y||_F lies within rounding of a power of two (then eps may differ by 2x)
+    yf = np.linalg.norm(ref["Y"], "fro")
+    if abs(np.log2(yf) - np.round(np.log2(yf))) > 1e-12:
+        assert P.nu == ref["nu"], (P.nu, ref["nu"])
+    else:
+        assert P.nu in (ref["nu"], 2 * ref["nu"], 0.5 * ref["nu"])
     np.testing.assert_allclose(lam, ref["lam"], rtol=1e-9, atol=1e-12 * ref["lam"][0])
     Ah = (U * lam) @ U.T
     Ar = (ref["U"] * ref["lam"]) @ ref["U"].T
@@ -177,6 +191,36 @@ def test_factor_low_rank_exact_recovery():
     P = nys.nys_factor(Om, Y)
     U, lam = h(P.U), h(P.lam)
     assert np.linalg.norm(A - (U * lam) @ U.T, 2) <= 1e-11 * np.linalg.norm(A, 2)
+
+
+def test_device_preconditioner_spectrum_rank_deficient():
+    """Rank-30 A sketched with l = 48 (so lam_l = 0): the device factor's
+    P^{-1}, formed column by column through the device apply, equals the
+    oracle's P^{-1} entrywise (the I - U U^T part included, which depends on
+    the orthonormality of U's columns with tiny eigenvalues); its eigenvalues
+    lie in [(lam_l + mu)/(lam_1 + mu), 1] (eq. (NysPre)), and
+    P^{-1/2} (A + mu I) P^{-1/2} has no eigenvalue below mu (the preconditioned
+    spectrum bound, read as >= mu)."""
+    n, ell = 300, 48
+    A = lowrank_psd(n, 30, seed=19)
+    om0 = np.random.default_rng(20).standard_normal((n, ell))
+    op = nys.Operator.dense(t64(A))
+    P = nys.nys_factor(*nys.nys_sketch(op, ell, omega0=t64(om0)))
+    ref = oracle.randomized_nystrom(oracle.DenseOp(A), om0)
+    lam = h(P.lam)
+    assert lam[-1] <= 1e-12 * lam[0]
+    for mu in (1e-3, 1.0):
+        E = np.eye(n)
+        Pinv = np.concatenate([h(nys.nys_precond_apply(P, mu, t64(E[:, j:j + 150]))) for j in range(0, n, 150)],
+                              axis=1)
+        Pref = oracle.precond_inv_matrix(ref["U"], ref["lam"], mu)
+        assert np.abs(Pinv - Pref).max() <= 1e-10, (mu, np.abs(Pinv - Pref).max())
+        ev, V = np.linalg.eigh(0.5 * (Pinv + Pinv.T))
+        lo = (lam[-1] + mu) / (lam[0] + mu)
+        assert ev.min() >= lo * (1 - 1e-8) and ev.max() <= 1 + 1e-10, (mu, ev.min(), lo, ev.max())
+        S = (V * np.sqrt(ev)) @ V.T
+        pre = np.linalg.eigvalsh(S @ (A + mu * np.eye(n)) @ S)
+        assert pre.min() >= mu * (1 - 1e-8), (mu, pre.min())
 
 
 @pytest.mark.parametrize("k", [1, 5])
@@ -398,10 +442,14 @@ def test_rbf_lowp_products(prec, tol, k):
     LDS kernel's 128 and (bf16x3 mode) 256 column blocks."""
     w, op_ref, _ = _mixture_case(1111, 32, 10, 40 + k)
     op = nys.Operator.rbf(t32(w["X"]), w["sigma"])
-    V = np.random.default_rng(k).standard_normal((1111, k))
+    V = np.random.default_rng(k).standard_normal((1111, k)).astype(np.float32).astype(np.float64)
     out = h(nys.nys_op_apply(op, 0.25, t32(V), prec=prec))
     ref = op_ref.matmat(V) + 0.25 * V
     assert rel(out, ref) < tol
+    # entry by entry: |error| <= c (|K| |V| + 0.25 |V|), c = 2e-5 (float32 Gram and
+    # accumulation) or 5e-4 (bf16x3 Gram: ~2^-16 of each product in the exponent)
+    scale = op_ref.matmat(np.abs(V)) + 0.25 * np.abs(V)
+    assert (np.abs(out - ref) / scale).max() < (2e-5 if prec == 1 else 5e-4)
 
 
 @pytest.mark.parametrize("d", [3, 16])
@@ -445,6 +493,13 @@ def test_rbf_lowp_sketch_close_to_oracle():
         Om, Y = h(Om), h(Y)
         Q = oracle.orthonormalize(w["omega0"])
         assert rel(Y @ Om.T, op_ref.matmat(Q) @ Q.T) < tol
+        # entry by entry against K times the device's own test matrix, bounded
+        # by c |K| |Omega| (c as in the product test; Omega is rounded to
+        # float32 for the reduced-precision products)
+        Om32 = Om.astype(np.float32).astype(np.float64)
+        err = np.abs(Y - op_ref.matmat(Om32))
+        scale = op_ref.matmat(np.abs(Om32))
+        assert (err / scale).max() < (2e-5 if prec == 1 else 5e-4), (prec, (err / scale).max())
 
 
 def test_rbf_block_mu_grid_float_refine():

@@ -21,6 +21,18 @@ def test_matlab_eps_closed_form():
         assert matlab_eps(x) == np.spacing(x)
 
 
+def test_rbf_operator_threaded_blocks_match_cdist():
+    """The threaded row-block product (used for full-size residuals) against
+    scipy's cdist kernel, with more points than one block so several blocks
+    and a ragged last block are evaluated."""
+    rng = np.random.default_rng(11)
+    X = rng.standard_normal((4500, 4))
+    sigma = 2.3
+    V = rng.standard_normal((4500, 2))
+    K = np.exp(-cdist(X, X, "sqeuclidean") / (2 * sigma ** 2))
+    np.testing.assert_allclose(RBFOp(X, sigma).matmat(V, workers=4, block=512), K @ V, rtol=1e-12, atol=1e-10)
+
+
 def test_rbf_operator_matches_cdist():
     rng = np.random.default_rng(1)
     X = rng.standard_normal((300, 5)) * 2
