@@ -558,6 +558,12 @@ def run_krr(args, nys, torch, small=False, columns=False):
     op = nys.Operator.rbf(X, w["sigma"])
     b = rbf_rhs(nys, torch, op, w, dev)
     ws = nys.workspace(op, ell, 1, prec)
+    tuned = None
+    if args.autotune and not small:
+        t = time.perf_counter()
+        nys.nys_autotune(op, prec, [ell])  # the sketch's block product (ell columns)
+        tuned = {"seconds": time.perf_counter() - t, "choices": {ell: nys.nys_autotune_query(op, prec, ell)[:4]}}
+        log("autotune: %s" % tuned)
     # column sampling: the index sets are inputs, drawn and uploaded before the timed steps
     cols = {}
     if columns:
@@ -610,6 +616,8 @@ def run_krr(args, nys, torch, small=False, columns=False):
          "relres": max(i.relres[0] for i in infos), "iters": infos[-1].iters[0],
          "refine_steps": infos[-1].refine_steps,
          "phase_ms": {k: 1e3 * v / args.steps for k, v in tm.t.items()}, "roofline": roof})
+    if tuned is not None:
+        out["autotune"] = tuned
     if not args.no_plain and not small and not columns:
         ws64 = nys.workspace(op, ell, 1, nys.NYS_PREC_FP64)
         tm64 = Timer(torch)
@@ -672,7 +680,7 @@ def run_batched(args, nys, torch):
         ks = [8, 16, 32, 64, 128, 192, 256, ell]
         nys.nys_autotune(op, prec, ks)
         tuned = {"seconds": time.perf_counter() - t,
-                 "choices": {k: nys.nys_autotune_query(op, prec, k)[:3] for k in ks}}
+                 "choices": {k: nys.nys_autotune_query(op, prec, k)[:4] for k in ks}}
         log("autotune: %s" % tuned)
     if args.graph:
         return run_batched_graph(args, nys, torch, w, op, B, mus, ell, prec, ws, rops, rbs, rag, tol, tuned)

@@ -466,7 +466,8 @@ const char* nys_version(void);
  * the products of the batched solves) has several tile shapes: a register
  * kernel with 16, 32 or 64 columns per workgroup, an LDS kernel with 128 or
  * 256, and a split over points sized for 4, 8 or 16 workgroups per compute
- * unit.  Without tuning a built-in rule picks one from the column count.
+ * unit, and for the LDS kernel one or two 16-row fragments per wave.  Without
+ * tuning a built-in rule picks one from the column count.
  * nys_autotune times every shape on the caller's operator (n, d), precision
  * mode and each column count ks[i] (2 <= ks[i] <= 4096, nks <= 64) on stream
  * (which it synchronises), and records the fastest in a process-wide table;
@@ -475,7 +476,8 @@ const char* nys_version(void);
  * rule).  The shape changes neither the arithmetic of an entry of K nor the
  * result beyond float32 summation order.  The table persists through a text
  * file: nys_autotune_load merges a file (lines "rbf_kv n d mode k reg cf bpc
- * microseconds"; a malformed line rejects the whole file, NYS_ERR_ARG),
+ * microseconds fr", fr optional; a malformed line rejects the whole file,
+ * NYS_ERR_ARG),
  * nys_autotune_save writes the table.  If the environment variable
  * NYS_AUTOTUNE_CACHE names a file, it is loaded before the first lookup and
  * rewritten after each nys_autotune call.  A is an NYS_OP_RBF operator with
@@ -488,8 +490,9 @@ nys_status nys_autotune(const nys_operator* A, int32_t prec, const int64_t* ks, 
                         size_t ws_bytes, void* stream);
 /* The shape a product with k columns would use now: choice[0] = 1 for the
  * register kernel (0: LDS kernel), choice[1] = column tiles of 16 per
- * workgroup, choice[2] = workgroups per compute unit; *tuned (nullable) = 1
- * when it comes from the table.  Host only. */
+ * workgroup, choice[2] = workgroups per compute unit, choice[3] = row
+ * fragments of 16 per wave of the LDS kernel (1 or 2; 1 for the register
+ * kernel); *tuned (nullable) = 1 when it comes from the table.  Host only. */
 nys_status nys_autotune_query(const nys_operator* A, int32_t prec, int64_t k, int32_t* choice, int32_t* tuned);
 int64_t nys_autotune_entries(void);
 nys_status nys_autotune_clear(void);

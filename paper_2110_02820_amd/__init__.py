@@ -581,11 +581,12 @@ def nys_autotune(op: Operator, prec: int, ks: Sequence[int], ws: Optional[torch.
 
 
 def nys_autotune_query(op: Operator, prec: int, k: int):
-    """(register kernel?, 16-column tiles per workgroup, workgroups per CU, tuned?) of a k-column product."""
-    ch = (ctypes.c_int32 * 3)()
+    """(register kernel?, 16-column tiles per workgroup, workgroups per CU, 16-row
+    fragments per wave, tuned?) of a k-column product."""
+    ch = (ctypes.c_int32 * 4)()
     tuned = ctypes.c_int32(0)
     _check(lib().nys_autotune_query(ctypes.byref(op.c()), prec, k, ch, ctypes.byref(tuned)))
-    return bool(ch[0]), int(ch[1]), int(ch[2]), bool(tuned.value)
+    return bool(ch[0]), int(ch[1]), int(ch[2]), int(ch[3]), bool(tuned.value)
 
 
 def nys_autotune_entries() -> int:

@@ -20,6 +20,16 @@
 #include "rbf_lowp.hpp"
 #include "rng.hpp"
 
+// Eigensolver stopping ratio when U is stored in float32 (see jac_end_sweep):
+// a sweep whose subproblems met no |a_pq| above this times sqrt(|a_pp a_qq|)
+// is the last.  Its own rotations leave ratios of about its square (1e-6),
+// which bounds the departure of U's float32 columns from orthonormality;
+// P^{-1} = I + U F U^T stays positive definite while that departure is well
+// below (lam_l + mu) / (lam_1 + mu).
+#ifndef NYS_JACOBI_RATIO_F32
+#define NYS_JACOBI_RATIO_F32 1e-3
+#endif
+
 namespace nys {
 
 static thread_local char g_err[1024] = "";
@@ -1503,7 +1513,7 @@ nys_status nys_factor(const double* Omega, double* Y, nys_precond* P, int32_t pr
                                         c.gscr_elems, s)));
   // eigenvectors kept in float32 need off-diagonal ratios ~1e-8, not ~1e-16
   NYS_TRY(sym_eig(c.G, l, c.eig, c.flags, kMaxSweeps, c.sweeps, c.conv, c.T, P->lam, c.sig2,
-                  c.nu, s, P->dtype == NYS_F32 ? 1e-4 : 1e-9));
+                  c.nu, s, P->dtype == NYS_F32 ? NYS_JACOBI_RATIO_F32 : 1e-9));
   if (P->dtype == NYS_F64) {
     NYS_TRY((gemm<double, double, double>(false, false, n, l, l, 1.0, w.B, l, c.T, l, 0.0,
                                           static_cast<double*>(P->U), P->ldu, c.gscr, c.gscr_elems, s)));
@@ -1904,7 +1914,7 @@ nys_status nys_autotune_query(const nys_operator* A, int32_t prec, int64_t k, in
   OpDesc op;
   int mode = 0;
   NYS_TRY(autotune_op(A, prec, op, mode));
-  NYS_ARG(k >= 1 && choice != nullptr, "autotune query: k >= 1 and a 3-entry choice array");
+  NYS_ARG(k >= 1 && choice != nullptr, "autotune query: k >= 1 and a 4-entry choice array");
   RbfLowp L{};
   L.n = op.n;
   L.d = (int)op.cols;
@@ -1913,6 +1923,7 @@ nys_status nys_autotune_query(const nys_operator* A, int32_t prec, int64_t k, in
   choice[0] = c.reg;
   choice[1] = c.cf;
   choice[2] = c.bpc;
+  choice[3] = c.fr;
   if (tuned) *tuned = t ? 1 : 0;
   return NYS_OK;
 }

@@ -639,20 +639,27 @@ __global__ __launch_bounds__(NT) void uc_vec(int64_t n, int64_t l, const TU* __r
   const int64_t w0 = ((int64_t)blockIdx.x * 4 + wave) * rows_per_wave;
   const int64_t w1 = w0 + rows_per_wave < n ? w0 + rows_per_wave : n;
   double rzp = 0.0;
-  for (int64_t ib = w0; ib < w1; ib += 4) {
-    const int64_t nr = (w1 - ib) < 4 ? (w1 - ib) : 4;
-    VT u[4][NG];
-    T rv[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) rv[q] = r[ib + (q < nr ? q : 0)];
+  // four rows per pass; the next pass's rows are loaded while this one is
+  // reduced (ping-pong buffers; a pass past the range re-reads row w0)
+  VT ua[4][NG], ub[4][NG];
+  T ra[4], rb[4];
+  auto load = [&](VT(&u)[4][NG], T(&rv)[4], int64_t ib) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const int64_t row = ib + (q < nr ? q : 0);
+      const int64_t row = ib + q < w1 ? ib + q : w0;
+      rv[q] = r[row];
 #pragma unroll
       for (int g = 0; g < NG; ++g) u[q][g] = *reinterpret_cast<const VT*>(U + row * ldu + off[g]);
     }
-    if (skip_all) return;
-    T sv[4];
+  };
+  // lane l finishes row q = (l >> 4) & 3 of the pass: the four per-lane sums
+  // are halved across lanes l ^ 32, then l ^ 16 (seven shuffles for the four
+  // rows instead of 24), then summed over the 16 lanes of the group
+  const int myq = (lane >> 4) & 3;
+  const bool hi32 = (lane & 32) != 0, hi16 = (lane & 16) != 0;
+  auto finish = [&](VT(&u)[4][NG], T(&rv)[4], int64_t ib) {
+    const int64_t nr = (w1 - ib) < 4 ? (w1 - ib) : 4;
+    T a[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       T acc = T(0);
@@ -660,19 +667,32 @@ __global__ __launch_bounds__(NT) void uc_vec(int64_t n, int64_t l, const TU* __r
       for (int g = 0; g < NG; ++g)
 #pragma unroll
         for (int e = 0; e < E; ++e) acc += T(UVec<TU>::get(u[q][g], e)) * cs[g][e];  // cs = 0 past l
-      sv[q] = wave_sum(acc);
+      a[q] = acc;
     }
+    const T b0 = (hi32 ? a[2] : a[0]) + __shfl_xor(hi32 ? a[0] : a[2], 32, 64);
+    const T b1 = (hi32 ? a[3] : a[1]) + __shfl_xor(hi32 ? a[1] : a[3], 32, 64);
+    T c = (hi16 ? b1 : b0) + __shfl_xor(hi16 ? b0 : b1, 16, 64);
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      if (q < nr) {
-        const T zi = rv[q] + sv[q];
-        if (lane == q) z[ib + q] = zi;
-        rzp += double(rv[q]) * double(zi);
-      }
+    for (int o = 8; o >= 1; o >>= 1) c += __shfl_xor(c, o, 64);
+    if (myq < nr && (lane & 15) == 0) {
+      const T zi = rv[myq] + c;
+      z[ib + myq] = zi;
+      rzp += double(rv[myq]) * double(zi);
     }
+  };
+  int64_t ib = w0;
+  if (ib < w1) load(ua, ra, ib);
+  if (skip_all) return;
+  for (; ib + 4 < w1; ib += 8) {
+    load(ub, rb, ib + 4);
+    finish(ua, ra, ib);
+    if (ib + 8 < w1) load(ua, ra, ib + 8);
+    finish(ub, rb, ib + 4);
   }
+  if (ib < w1) finish(ua, ra, ib);
   if (mode == 0 || skip_all) return;
-  const double tot = block_sum(lane == 0 ? rzp : 0.0, sh);
+  // lanes 0, 16, 32 and 48 hold the rows' parts of r^T z
+  const double tot = block_sum(rzp, sh);
   if (threadIdx.x == 0) prz[blockIdx.x] = tot;
   if (!last_block(sc.ctr, gridDim.x)) return;
   rz_tail(prz, gridDim.x, 1, sh, sc, par, mode == 1);

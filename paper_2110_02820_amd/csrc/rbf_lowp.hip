@@ -177,13 +177,15 @@ __global__ __launch_bounds__(256) void rbf_mv_lowp(RbfLowp L, const float* __res
 // 32: stage 1 forms K (64 x 32, wave w rows w*16..) with the Gram MFMA and
 // exp, splits it into bf16 hi/lo in LDS; stage 2 multiplies K (hi/lo) by the
 // P tile (hi/lo, staged transposed in LDS) with three bf16 MFMAs per tile.
-template <int MODE, int CF>
+template <int MODE, int CF, int FR>
 struct KvStage2;
 
-// BF16X3 second stage: K and P split into bf16 hi/lo in LDS, three bf16 MFMAs
-template <int CF>
-struct KvStage2<0, CF> {
-  unsigned short Khi[64][40], Klo[64][40];            // [row][point]
+// BF16X3 second stage: K and P split into bf16 hi/lo in LDS, three bf16 MFMAs.
+// FR row fragments of 16 per wave: every P fragment read from LDS serves FR
+// MFMA chains, which halves the LDS reads per MFMA at FR = 2.
+template <int CF, int FR>
+struct KvStage2<0, CF, FR> {
+  unsigned short Khi[64 * FR][40], Klo[64 * FR][40];  // [row][point]
   unsigned short Phi[16 * CF][40], Plo[16 * CF][40];  // [col][point]
   // 8 points (part) of column cc, already split (piece 0: hi, 1: lo)
   __device__ __forceinline__ void put_p16(int piece, int cc, int part, uint4 v) {
@@ -194,22 +196,28 @@ struct KvStage2<0, CF> {
     Khi[r][pc] = hi;
     Klo[r][pc] = bf16_rne(e - bf16_to_f(hi));
   }
-  __device__ __forceinline__ void mac(int wave, int lane, f4 (&acc)[CF]) {
-    const int r = wave * 16 + (lane & 15);
-    const bf8 khi = *reinterpret_cast<const bf8*>(&Khi[r][8 * (lane >> 4)]);
-    const bf8 klo = *reinterpret_cast<const bf8*>(&Klo[r][8 * (lane >> 4)]);
+  __device__ __forceinline__ void mac(int wave, int lane, f4 (&acc)[FR][CF]) {
+    bf8 khi[FR], klo[FR];
+#pragma unroll
+    for (int f = 0; f < FR; ++f) {
+      const int r = wave * 16 * FR + f * 16 + (lane & 15);
+      khi[f] = *reinterpret_cast<const bf8*>(&Khi[r][8 * (lane >> 4)]);
+      klo[f] = *reinterpret_cast<const bf8*>(&Klo[r][8 * (lane >> 4)]);
+    }
 #pragma unroll
     for (int cf = 0; cf < CF; ++cf) {
       const int cc = cf * 16 + (lane & 15);
       const bf8 phi = *reinterpret_cast<const bf8*>(&Phi[cc][8 * (lane >> 4)]);
       const bf8 plo = *reinterpret_cast<const bf8*>(&Plo[cc][8 * (lane >> 4)]);
-      acc[cf] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(khi, phi, acc[cf], 0, 0, 0);
-      acc[cf] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(khi, plo, acc[cf], 0, 0, 0);
-      acc[cf] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(klo, phi, acc[cf], 0, 0, 0);
+#pragma unroll
+      for (int f = 0; f < FR; ++f) {
+        acc[f][cf] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(khi[f], phi, acc[f][cf], 0, 0, 0);
+        acc[f][cf] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(khi[f], plo, acc[f][cf], 0, 0, 0);
+        acc[f][cf] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(klo[f], phi, acc[f][cf], 0, 0, 0);
+      }
     }
   }
 };
-
 // F32 second stage: K and P each split exactly into three bf16 pieces
 // (8 + 8 + 8 significant bits = the float32 significand), and K P formed from
 // all nine piece products with v_mfma_f32_16x16x32_bf16 and float32
@@ -223,9 +231,11 @@ __device__ __forceinline__ void split3(float v, unsigned short& h0, unsigned sho
   h2 = bf16_rne(r1 - bf16_to_f(h1));
 }
 
-template <int CF>
-struct KvStage2<1, CF> {
-  unsigned short Kp[3][64][40];       // [piece][row][point]
+// Float32 second stage: K and P each split into three exact bf16 pieces (nine
+// piece products, smallest first).  FR as above.
+template <int CF, int FR>
+struct KvStage2<1, CF, FR> {
+  unsigned short Kp[3][64 * FR][40];  // [piece][row][point]
   unsigned short Pp[3][16 * CF][40];  // [piece][col][point]
   __device__ __forceinline__ void put_p16(int piece, int cc, int part, uint4 v) {
     *reinterpret_cast<uint4*>(&Pp[piece][cc][8 * part]) = v;
@@ -237,28 +247,33 @@ struct KvStage2<1, CF> {
     Kp[1][r][pc] = h1;
     Kp[2][r][pc] = h2;
   }
-  __device__ __forceinline__ void mac(int wave, int lane, f4 (&acc)[CF]) {
-    const int r = wave * 16 + (lane & 15);
-    bf8 kk[3];
+  __device__ __forceinline__ void mac(int wave, int lane, f4 (&acc)[FR][CF]) {
+    bf8 kk[FR][3];
 #pragma unroll
-    for (int q = 0; q < 3; ++q) kk[q] = *reinterpret_cast<const bf8*>(&Kp[q][r][8 * (lane >> 4)]);
+    for (int f = 0; f < FR; ++f) {
+      const int r = wave * 16 * FR + f * 16 + (lane & 15);
+#pragma unroll
+      for (int q = 0; q < 3; ++q) kk[f][q] = *reinterpret_cast<const bf8*>(&Kp[q][r][8 * (lane >> 4)]);
+    }
 #pragma unroll
     for (int cf = 0; cf < CF; ++cf) {
       const int cc = cf * 16 + (lane & 15);
       bf8 pp[3];
 #pragma unroll
       for (int q = 0; q < 3; ++q) pp[q] = *reinterpret_cast<const bf8*>(&Pp[q][cc][8 * (lane >> 4)]);
-      // smallest products first
-      f4 c = acc[cf];
-      c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(kk[2], pp[2], c, 0, 0, 0);
-      c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(kk[1], pp[2], c, 0, 0, 0);
-      c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(kk[2], pp[1], c, 0, 0, 0);
-      c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(kk[0], pp[2], c, 0, 0, 0);
-      c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(kk[1], pp[1], c, 0, 0, 0);
-      c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(kk[2], pp[0], c, 0, 0, 0);
-      c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(kk[0], pp[1], c, 0, 0, 0);
-      c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(kk[1], pp[0], c, 0, 0, 0);
-      acc[cf] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(kk[0], pp[0], c, 0, 0, 0);
+#pragma unroll
+      for (int f = 0; f < FR; ++f) {
+        f4 c = acc[f][cf];
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(kk[f][2], pp[2], c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(kk[f][1], pp[2], c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(kk[f][2], pp[1], c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(kk[f][0], pp[2], c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(kk[f][1], pp[1], c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(kk[f][2], pp[0], c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(kk[f][0], pp[1], c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(kk[f][1], pp[0], c, 0, 0, 0);
+        acc[f][cf] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(kk[f][0], pp[0], c, 0, 0, 0);
+      }
     }
   }
 };
@@ -313,7 +328,7 @@ __global__ __launch_bounds__(256) void split_p_bf16(const float* __restrict__ P,
 // MFMA and exp into LDS; stage 2 multiplies K by the P tile staged in LDS.
 // The P tile and the point operands of the next tile are loaded into
 // registers while the current tile is multiplied.
-template <int MODE, int CF, int KS>
+template <int MODE, int CF, int KS, int FR>
 __global__ __launch_bounds__(256) void rbf_kv_lowp(RbfLowp L, const float* __restrict__ P, int64_t ldp, int64_t k,
                                                    const uint4* __restrict__ Pq, int64_t ldq,
                                                    float* __restrict__ out, int64_t ldo, int64_t pts_per_split,
@@ -324,21 +339,27 @@ __global__ __launch_bounds__(256) void rbf_kv_lowp(RbfLowp L, const float* __res
   // pre-split bf16 pieces, NPC pieces (MODE 0: hi / lo; MODE 1: three)
   constexpr int NPC = MODE == 0 ? 2 : 3;
   constexpr int PE = NPC * NC * 4 / 256;
-  __shared__ __attribute__((aligned(16))) KvStage2<MODE, CF> st;
+  __shared__ __attribute__((aligned(16))) KvStage2<MODE, CF, FR> st;
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int64_t n = L.n;
-  const int64_t i0 = (int64_t)blockIdx.x * 64;
+  const int64_t i0 = (int64_t)blockIdx.x * 64 * FR;  // wave w: rows i0 + 16 FR w .. + 16 FR - 1
   const int64_t c0 = (int64_t)blockIdx.y * NC;
   const bool dead = cols_done(L.coldone, c0, NC, k);  // zeros out, no products
   const float two_s = L.two_s;
-  Operand<MODE> a;
-  a.load(L, i0 + wave * 16 + (lane & 15), lane);
-  f4 cinit;
+  Operand<MODE> a[FR];
+  f4 cinit[FR];
 #pragma unroll
-  for (int q = 0; q < 4; ++q) cinit[q] = -L.hs[i0 + wave * 16 + 4 * (lane >> 4) + q] / two_s;
-  f4 acc[CF];
+  for (int f = 0; f < FR; ++f) {
+    const int64_t rb = i0 + wave * 16 * FR + f * 16;
+    a[f].load(L, rb + (lane & 15), lane);
 #pragma unroll
-  for (int cf = 0; cf < CF; ++cf) acc[cf] = f4{0, 0, 0, 0};
+    for (int q = 0; q < 4; ++q) cinit[f][q] = -L.hs[rb + 4 * (lane >> 4) + q] / two_s;
+  }
+  f4 acc[FR][CF];
+#pragma unroll
+  for (int f = 0; f < FR; ++f)
+#pragma unroll
+    for (int cf = 0; cf < CF; ++cf) acc[f][cf] = f4{0, 0, 0, 0};
   const int64_t j0 = (int64_t)blockIdx.z * pts_per_split;
   int64_t j1 = j0 + pts_per_split;
   if (j1 > n) j1 = n;
@@ -369,16 +390,20 @@ __global__ __launch_bounds__(256) void rbf_kv_lowp(RbfLowp L, const float* __res
       const int e = t + 256 * u;
       st.put_p16((e >> 2) / NC, (e >> 2) % NC, e & 3, pr[u]);
     }
-    // stage 1: K rows wave*16 .. +15, points jt .. jt+31 (two 16-point tiles)
-    const f4 dg0 = gram_tile<KS>(a, b0, cinit);
-    const f4 dg1 = gram_tile<KS>(a, b1, cinit);
+    // stage 1: K rows of each fragment, points jt .. jt+31 (two 16-point tiles)
     const int64_t ja = jt + (lane & 15), jb = jt + 16 + (lane & 15);
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const float e0 = (ja < j1) ? __builtin_amdgcn_exp2f(fmaf(two_s, dg0[q], -h0)) : 0.0f;
-      const float e1 = (jb < j1) ? __builtin_amdgcn_exp2f(fmaf(two_s, dg1[q], -h1)) : 0.0f;
-      st.put_k(wave * 16 + 4 * (lane >> 4) + q, (lane & 15), e0);
-      st.put_k(wave * 16 + 4 * (lane >> 4) + q, 16 + (lane & 15), e1);
+    for (int f = 0; f < FR; ++f) {
+      const f4 dg0 = gram_tile<KS>(a[f], b0, cinit[f]);
+      const f4 dg1 = gram_tile<KS>(a[f], b1, cinit[f]);
+      const int rl = wave * 16 * FR + f * 16 + 4 * (lane >> 4);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const float e0 = (ja < j1) ? __builtin_amdgcn_exp2f(fmaf(two_s, dg0[q], -h0)) : 0.0f;
+        const float e1 = (jb < j1) ? __builtin_amdgcn_exp2f(fmaf(two_s, dg1[q], -h1)) : 0.0f;
+        st.put_k(rl + q, (lane & 15), e0);
+        st.put_k(rl + q, 16 + (lane & 15), e1);
+      }
     }
     __syncthreads();
     if (jt + 32 < j1) fetch(jt + 32);  // in flight during stage 2
@@ -386,13 +411,15 @@ __global__ __launch_bounds__(256) void rbf_kv_lowp(RbfLowp L, const float* __res
   }
   float* o = out + (int64_t)blockIdx.z * n * ldo;
 #pragma unroll
-  for (int cf = 0; cf < CF; ++cf)
+  for (int f = 0; f < FR; ++f)
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int64_t row = i0 + wave * 16 + 4 * (lane >> 4) + q;
-      const int64_t col = c0 + cf * 16 + (lane & 15);
-      if (row < n && col < k) o[row * ldo + col] = oscale * acc[cf][q];
-    }
+    for (int cf = 0; cf < CF; ++cf)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int64_t row = i0 + wave * 16 * FR + f * 16 + 4 * (lane >> 4) + q;
+        const int64_t col = c0 + cf * 16 + (lane & 15);
+        if (row < n && col < k) o[row * ldo + col] = oscale * acc[f][cf][q];
+      }
 }
 
 // Float32 mode, few columns (k <= 64): out[I, c0 .. c0 + 16 CF - 1] =
@@ -695,6 +722,7 @@ KvChoice kv_heuristic(int64_t k) {
   c.reg = k <= 64 ? 1 : 0;
   c.cf = c.reg ? (k <= 16 ? 1 : k <= 32 ? 2 : 4) : (k > 128 ? 16 : 8);
   c.bpc = 8;
+  c.fr = 1;
   return c;
 }
 
@@ -709,9 +737,9 @@ KvPlan make_plan(int64_t n, int64_t k, int mode, KvChoice c) {
     p.nc = 16 * p.cf;
     p.rows = 64 * p.f;
   } else {
-    p.f = 1;
+    p.f = c.fr == 2 ? 2 : 1;  // row fragments per wave
     p.nc = 16 * p.cf;
-    p.rows = 64;
+    p.rows = 64 * p.f;
   }
   p.kq = cdiv(k, p.nc) * p.nc;
   p.tiles = cdiv(n, p.rows) * cdiv(k, p.nc);
@@ -727,15 +755,17 @@ std::vector<KvChoice> kv_candidates() {
   std::vector<KvChoice> v;
   const int regcf[3] = {1, 2, 4}, ldscf[2] = {8, 16}, bpcs[3] = {4, 8, 16};
   for (int b : bpcs) {
-    for (int cf : regcf) v.push_back(KvChoice{1, cf, b});
-    for (int cf : ldscf) v.push_back(KvChoice{0, cf, b});
+    for (int cf : regcf) v.push_back(KvChoice{1, cf, b, 1});
+    for (int cf : ldscf)
+      for (int fr = 1; fr <= 2; ++fr) v.push_back(KvChoice{0, cf, b, fr});
   }
   return v;
 }
 
 bool valid_choice(const KvChoice& c) {
   const bool cf_ok = c.reg ? (c.cf == 1 || c.cf == 2 || c.cf == 4) : (c.cf == 8 || c.cf == 16);
-  return (c.reg == 0 || c.reg == 1) && cf_ok && (c.bpc == 4 || c.bpc == 8 || c.bpc == 16);
+  const bool fr_ok = c.reg ? c.fr == 1 : (c.fr == 1 || c.fr == 2);
+  return (c.reg == 0 || c.reg == 1) && cf_ok && fr_ok && (c.bpc == 4 || c.bpc == 8 || c.bpc == 16);
 }
 
 // ---- autotuner table
@@ -778,11 +808,12 @@ static nys_status tune_load_locked(const char* path) {
     TuneEntry e{};
     long long n = 0, k = 0;
     char tag[32] = "";
-    const int got_n = std::sscanf(line, "%31s %lld %d %d %lld %d %d %d %lf", tag, &n, &e.d, &e.mode, &k, &e.c.reg,
-                                  &e.c.cf, &e.c.bpc, &e.us);
+    e.c.fr = 1;  // lines without the last field: one row fragment per wave
+    const int got_n = std::sscanf(line, "%31s %lld %d %d %lld %d %d %d %lf %d", tag, &n, &e.d, &e.mode, &k,
+                                  &e.c.reg, &e.c.cf, &e.c.bpc, &e.us, &e.c.fr);
     e.n = n;
     e.k = k;
-    if (got_n != 9 || std::strcmp(tag, "rbf_kv") != 0 || n < 1 || k < 1 || e.d < 1 || e.d > 32 ||
+    if (got_n < 9 || std::strcmp(tag, "rbf_kv") != 0 || n < 1 || k < 1 || e.d < 1 || e.d > 32 ||
         (e.mode != RBF_GRAM_BF16X3 && e.mode != RBF_GRAM_F32) || !valid_choice(e.c)) {
       set_error("autotune cache %s: line %d is not a valid entry", path, lineno);
       st = NYS_ERR_ARG;
@@ -842,10 +873,10 @@ nys_status kv_tune_save(const char* path) {
     set_error("autotune cache %s cannot be written", path);
     return NYS_ERR_ARG;
   }
-  std::fprintf(f, "# nyspcg autotune cache: rbf_kv n d mode k reg cf bpc microseconds\n");
+  std::fprintf(f, "# nyspcg autotune cache: rbf_kv n d mode k reg cf bpc microseconds fr\n");
   for (const TuneEntry& t : g_tune)
-    std::fprintf(f, "rbf_kv %lld %d %d %lld %d %d %d %.3f\n", (long long)t.n, t.d, t.mode, (long long)t.k, t.c.reg,
-                 t.c.cf, t.c.bpc, t.us);
+    std::fprintf(f, "rbf_kv %lld %d %d %lld %d %d %d %.3f %d\n", (long long)t.n, t.d, t.mode, (long long)t.k,
+                 t.c.reg, t.c.cf, t.c.bpc, t.us, t.c.fr);
   const bool ok = std::fclose(f) == 0;
   if (!ok) {
     set_error("autotune cache %s: write failed", path);
@@ -969,12 +1000,14 @@ nys_status rbf_lowp_kv_plan(const RbfLowp& L, int mode, const KvPlan& pl, const 
 #undef K32
 #undef KR
   } else {
-#define KV(M, CF, KS) hipLaunchKernelGGL((rbf_kv_lowp<M, CF, KS>), grid, dim3(256), 0, s, Lq, P, ldp, k, Pq, Lq.npad / 8, dst, ldo, pps, oscale, skip)
+#define KV(M, CF, KS, FR) hipLaunchKernelGGL((rbf_kv_lowp<M, CF, KS, FR>), grid, dim3(256), 0, s, Lq, P, ldp, k, Pq, Lq.npad / 8, dst, ldo, pps, oscale, skip)
+#define KVF(M, CF, KS) do { if (pl.f == 2) KV(M, CF, KS, 2); else KV(M, CF, KS, 1); } while (0)
     if (mode == 0) {
-      if (pl.cf == 16) KV(0, 16, 1); else KV(0, 8, 1);
+      if (pl.cf == 16) KVF(0, 16, 1); else KVF(0, 8, 1);
     } else if (pl.cf == 16) {
-      if (kss == 2) KV(1, 16, 2); else if (kss == 4) KV(1, 16, 4); else KV(1, 16, 8);
-    } else if (kss == 2) KV(1, 8, 2); else if (kss == 4) KV(1, 8, 4); else KV(1, 8, 8);
+      if (kss == 2) KVF(1, 16, 2); else if (kss == 4) KVF(1, 16, 4); else KVF(1, 16, 8);
+    } else if (kss == 2) KVF(1, 8, 2); else if (kss == 4) KVF(1, 8, 4); else KVF(1, 8, 8);
+#undef KVF
 #undef KV
   }
   NYS_CHECK_LAUNCH();

@@ -43,13 +43,13 @@ nys_status rbf_lowp_kv(const RbfLowp& L, int mode, const float* P, int64_t ldp, 
                        int64_t nrhs, float* V, int64_t ldv, float* scratch, size_t scratch_elems, const int* skip,
                        hipStream_t s, const int* coldone = nullptr);
 
-// Tile-shape choice of the block product V = K P (see kv_plan in
+// Tile-shape choice of the block product V = K P (see make_plan in
 // rbf_lowp.hip): the register kernel (reg = 1, 16 cf columns per block,
-// cf in {1, 2, 4}) or the LDS kernel (reg = 0, cf in {8, 16}), and the target
-// number of workgroups per compute unit that sets the split over points
-// (bpc in {4, 8, 16}).
+// cf in {1, 2, 4}) or the LDS kernel (reg = 0, cf in {8, 16}, fr in {1, 2}
+// row fragments of 16 per wave), and the target number of workgroups per
+// compute unit that sets the split over points (bpc in {4, 8, 16}).
 struct KvChoice {
-  int reg, cf, bpc;
+  int reg, cf, bpc, fr;
 };
 
 // The choice a call with k columns would use on these prepared points:

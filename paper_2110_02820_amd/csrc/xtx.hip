@@ -1,7 +1,8 @@
 // X^T X products for the ridge normal equations (Section 1.3, eq.
 // (RidgeRegression)), one contiguous vector, gfx950.
 //
-// One pass over X per product: each workgroup owns a contiguous range of rows
+// One pass over X per product (X up to 8192 columns; wider X takes two
+// passes, a row-dot kernel and a column-partial kernel): each workgroup owns a contiguous range of rows
 // of X, keeps R rows in registers (16-byte vector loads), forms t_r = x_r^T p
 // with a block reduction and at once accumulates t_r x_r into a per-workgroup
 // partial of X^T t held in registers.  X is read from HBM exactly once; a
@@ -192,6 +193,73 @@ __global__ __launch_bounds__(256) void reduce_cols(const TA* __restrict__ part, 
   }
 }
 
+// ---- two passes for wide X (more columns than the one-pass kernel keeps
+// in registers): t = D X p (one wave per row), then per-group partials of
+// X^T t in the same layout as the one-pass kernel.  X is read twice.
+
+// t[r] = w_r x_r^T p, one wave per row (w_r = 1 without weights)
+template <typename TD, typename TA, typename VP>
+__global__ __launch_bounds__(256) void xtx_rowdot(const TD* __restrict__ X, int64_t m, int64_t n, int64_t ld,
+                                                  const TA* __restrict__ p, TA* __restrict__ t,
+                                                  const int* __restrict__ skip, const double* __restrict__ wts) {
+  if (skip && *skip) return;
+  typedef typename VP::type VT;
+  constexpr int E = VP::E;
+  const int lane = threadIdx.x & 63;
+  const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (r >= m) return;
+  const TD* x = X + r * ld;
+  TA s = TA(0);
+  for (int64_t j = (int64_t)lane * E; j < n; j += 64 * E) {
+    const VT v = VP::load(x + j);
+#pragma unroll
+    for (int e = 0; e < E; ++e) s += TA(VP::get(v, e)) * p[j + e];
+  }
+  s = wave_sum(s);
+  if (lane == 0) t[r] = wts ? s * TA(wts[r]) : s;
+}
+
+// part[g][j] = sum over rows r of group g of t[r] x_r[j]: thread owns E
+// consecutive columns of a block of 256 E, groups of rows_per_group rows
+template <typename TD, typename TA, typename VP>
+__global__ __launch_bounds__(256) void xtx_colpart(const TD* __restrict__ X, int64_t m, int64_t n, int64_t ld,
+                                                   const TA* __restrict__ t, TA* __restrict__ part,
+                                                   int64_t rows_per_group, const int* __restrict__ skip) {
+  if (skip && *skip) return;
+  typedef typename VP::type VT;
+  constexpr int E = VP::E;
+  const int64_t j0 = ((int64_t)blockIdx.x * 256 + threadIdx.x) * E;
+  if (j0 >= n) return;
+  const int64_t r0 = (int64_t)blockIdx.y * rows_per_group;
+  const int64_t r1 = r0 + rows_per_group < m ? r0 + rows_per_group : m;
+  TA acc[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) acc[e] = TA(0);
+  int64_t r = r0;
+  for (; r + 4 <= r1; r += 4) {  // four rows' loads in flight
+    VT v[4];
+    TA tr[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      v[q] = VP::load(X + (r + q) * ld + j0);
+      tr[q] = t[r + q];
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int e = 0; e < E; ++e) acc[e] += tr[q] * TA(VP::get(v[q], e));
+  }
+  for (; r < r1; ++r) {
+    const VT v = VP::load(X + r * ld + j0);
+    const TA tr = t[r];
+#pragma unroll
+    for (int e = 0; e < E; ++e) acc[e] += tr * TA(VP::get(v, e));
+  }
+  TA* out = part + (int64_t)blockIdx.y * n + j0;
+#pragma unroll
+  for (int e = 0; e < E; ++e) out[e] = acc[e];
+}
+
 }  // namespace
 
 template <typename TD, typename TA>
@@ -210,21 +278,50 @@ nys_status xtx_partials(const OpDesc& op, const TA* p, TA* scratch, size_t scrat
   while (ng > 1 && (size_t)(ng * n) > scratch_elems) ng /= 2;
   int64_t rpw = cdiv(cdiv(m, ng), R) * R;
   ng = cdiv(m, rpw);
-  if ((aligned && need_nv > 8) || (!aligned && need_nv > 32)) {
-    set_error("X^T X operator: n = %lld too large for the one-pass kernel", (long long)n);
-    return NYS_ERR_ARG;
+  const bool vec = aligned && need_nv <= 8;
+  const int64_t nv1 = cdiv(n, (int64_t)256);
+  if (!vec && nv1 > 32) {
+    // wide X: two passes (row dots, then column partials); t takes the last
+    // m entries of the scratch, the partials the front
+    if (scratch_elems < (size_t)(m + n)) {
+      set_error("X^T X operator: scratch too small for the two-pass product");
+      return NYS_ERR_WORKSPACE;
+    }
+    TA* t = scratch + (scratch_elems - (size_t)m);
+    int64_t ng2 = (num_cus() < 256 ? num_cus() : 256) * 2 / (int64_t)cdiv(n, (int64_t)256 * E);
+    if (ng2 < 1) ng2 = 1;
+    if (ng2 > cdiv(m, (int64_t)4)) ng2 = cdiv(m, (int64_t)4);
+    while (ng2 > 1 && (size_t)(ng2 * n) > scratch_elems - (size_t)m) ng2 /= 2;
+    const int64_t rpg = cdiv(m, ng2);
+    ng2 = cdiv(m, rpg);
+    timing_mark_begin(s);
+    if (aligned) {
+      hipLaunchKernelGGL((xtx_rowdot<TD, TA, Vec16<TD>>), dim3((unsigned)cdiv(m, (int64_t)4)), dim3(256), 0, s, X,
+                         m, n, op.ld, p, t, op.skip, op.w);
+      hipLaunchKernelGGL((xtx_colpart<TD, TA, Vec16<TD>>), dim3((unsigned)cdiv(n, (int64_t)256 * E), (unsigned)ng2),
+                         dim3(256), 0, s, X, m, n, op.ld, t, scratch, rpg, op.skip);
+    } else {
+      hipLaunchKernelGGL((xtx_rowdot<TD, TA, Vec1<TD>>), dim3((unsigned)cdiv(m, (int64_t)4)), dim3(256), 0, s, X, m,
+                         n, op.ld, p, t, op.skip, op.w);
+      hipLaunchKernelGGL((xtx_colpart<TD, TA, Vec1<TD>>), dim3((unsigned)cdiv(n, (int64_t)256), (unsigned)ng2),
+                         dim3(256), 0, s, X, m, n, op.ld, t, scratch, rpg, op.skip);
+    }
+    NYS_CHECK_LAUNCH();
+    timing_mark_end(s);
+    *ng_out = (int)ng2;
+    return NYS_OK;
   }
 #define LX(VP_, NV, RR) hipLaunchKernelGGL((xtx_fused<TD, TA, VP_, NV, RR>), dim3((unsigned)ng), dim3(256), 0, s, X, m, n, op.ld, p, scratch, rpw, op.skip, op.w)
   timing_mark_begin(s);
-  if (aligned) {
+  if (vec) {
     if (need_nv <= 1) LX(Vec16<TD>, 1, 4);
     else if (need_nv <= 2) LX(Vec16<TD>, 2, 4);
     else if (need_nv <= 4) LX(Vec16<TD>, 4, 4);
     else LX(Vec16<TD>, 8, 2);
-  } else {
-    if (need_nv <= 4) LX(Vec1<TD>, 4, 4);
-    else if (need_nv <= 8) LX(Vec1<TD>, 8, 4);
-    else if (need_nv <= 16) LX(Vec1<TD>, 16, 4);
+  } else {  // scalar loads: rows not 16-byte aligned, or too many 16-byte vectors per thread
+    if (nv1 <= 4) LX(Vec1<TD>, 4, 4);
+    else if (nv1 <= 8) LX(Vec1<TD>, 8, 4);
+    else if (nv1 <= 16) LX(Vec1<TD>, 16, 4);
     else LX(Vec1<TD>, 32, 2);
   }
 #undef LX

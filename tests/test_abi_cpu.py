@@ -158,24 +158,26 @@ def test_autotune_table_load_save_query(L, tmp_path):
     assert L.nys_autotune_entries() == 0
     # RBF operator, n = 5000 points in d = 16 (pointer not used by the lookup)
     op = nys._Operator(nys.NYS_OP_RBF, nys.NYS_F32, 5000, ctypes.c_void_p(1), 5000, 16, 16, 4.0, 1.0)
-    ch = (ctypes.c_int32 * 3)()
+    ch = (ctypes.c_int32 * 4)()
     tuned = ctypes.c_int32(7)
     f32 = nys.NYS_PREC_FP32_REFINE64
     bf = nys.NYS_PREC_BF16X3_REFINE64
     # built-in rule: register kernel with 1 / 2 / 4 tiles up to 64 columns, LDS kernel past that
-    for k, want in ((8, (1, 1, 8)), (32, (1, 2, 8)), (64, (1, 4, 8)), (100, (0, 8, 8)), (256, (0, 16, 8))):
+    for k, want in ((8, (1, 1, 8, 1)), (32, (1, 2, 8, 1)), (64, (1, 4, 8, 1)), (100, (0, 8, 8, 1)),
+                    (256, (0, 16, 8, 1))):
         assert L.nys_autotune_query(ctypes.byref(op), f32, k, ch, ctypes.byref(tuned)) == 0
         assert tuple(ch) == want and tuned.value == 0
     cache = tmp_path / "tune.txt"
     cache.write_text("# comment\n"
                      "rbf_kv 5000 16 1 16 1 4 16 10.5\n"
-                     "rbf_kv 5000 16 1 128 0 16 4 99.0\n"
+                     "rbf_kv 5000 16 1 128 0 16 4 99.0 2\n"
                      "rbf_kv 5000 16 0 128 1 2 8 77.0\n"
                      "rbf_kv 6000 16 1 512 1 1 4 1.0\n")
     assert L.nys_autotune_load(str(cache).encode()) == 0
     assert L.nys_autotune_entries() == 4
-    cases = [(f32, 10, (1, 4, 16), 1), (f32, 16, (1, 4, 16), 1), (f32, 17, (0, 16, 4), 1),
-             (f32, 128, (0, 16, 4), 1), (f32, 129, (0, 16, 8), 0), (bf, 100, (1, 2, 8), 1), (bf, 8, (1, 2, 8), 1)]
+    cases = [(f32, 10, (1, 4, 16, 1), 1), (f32, 16, (1, 4, 16, 1), 1), (f32, 17, (0, 16, 4, 2), 1),
+             (f32, 128, (0, 16, 4, 2), 1), (f32, 129, (0, 16, 8, 1), 0), (bf, 100, (1, 2, 8, 1), 1),
+             (bf, 8, (1, 2, 8, 1), 1)]
     for prec, k, want, t in cases:
         assert L.nys_autotune_query(ctypes.byref(op), prec, k, ch, ctypes.byref(tuned)) == 0
         assert (tuple(ch), tuned.value) == (want, t), (prec, k)
@@ -185,12 +187,15 @@ def test_autotune_table_load_save_query(L, tmp_path):
     assert tuned.value == 0
     out = tmp_path / "saved.txt"
     assert L.nys_autotune_save(str(out).encode()) == 0
-    rows = sorted(l.split()[:8] for l in out.read_text().splitlines() if not l.startswith("#"))
-    src = sorted(l.split()[:8] for l in cache.read_text().splitlines() if not l.startswith("#"))
+    rows = sorted(l.split()[:8] + l.split()[9:10] for l in out.read_text().splitlines() if not l.startswith("#"))
+    src = sorted(l.split()[:8] + (l.split()[9:10] or ["1"]) for l in cache.read_text().splitlines()
+                 if not l.startswith("#"))
     assert rows == src
     # a malformed file (cf 3 is no shape) changes nothing
     bad = tmp_path / "bad.txt"
     bad.write_text("rbf_kv 5000 16 1 32 1 3 8 1.0\n")
+    assert L.nys_autotune_load(str(bad).encode()) == nys.NYS_ERR_ARG
+    bad.write_text("rbf_kv 5000 16 1 32 1 4 8 1.0 2\n")  # the register kernel has one fragment
     assert L.nys_autotune_load(str(bad).encode()) == nys.NYS_ERR_ARG
     assert L.nys_autotune_entries() == 4
     assert L.nys_autotune_load(str(tmp_path / "missing.txt").encode()) == nys.NYS_ERR_ARG

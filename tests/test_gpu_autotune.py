@@ -49,7 +49,7 @@ def test_autotune_records_shapes_that_match_the_oracle(prec, tmp_path):
     assert nys.nys_autotune_entries() == len(ks)
     rng = np.random.default_rng(5)
     for k in ks + [5, 37]:
-        reg, cf, bpc, tuned = nys.nys_autotune_query(op, prec, k)
+        reg, cf, bpc, fr, tuned = nys.nys_autotune_query(op, prec, k)
         assert tuned
         P = rng.standard_normal((n, k)).astype(np.float32)
         _check_product(op, X, sigma, P, prec, mu=0.3)
@@ -70,12 +70,12 @@ def test_every_tile_shape_matches_the_oracle(prec, tmp_path):
     rng = np.random.default_rng(6)
     for k in (23, 150):
         P = rng.standard_normal((n, k)).astype(np.float32)
-        for reg, cf in ((1, 1), (1, 2), (1, 4), (0, 8), (0, 16)):
+        for reg, cf, fr in ((1, 1, 1), (1, 2, 1), (1, 4, 1), (0, 8, 1), (0, 16, 1), (0, 8, 2), (0, 16, 2)):
             for bpc in (4, 16):
                 path = tmp_path / "force.txt"
-                path.write_text("rbf_kv %d 16 %d %d %d %d %d 1.0\n" % (n, mode, k, reg, cf, bpc))
+                path.write_text("rbf_kv %d 16 %d %d %d %d %d 1.0 %d\n" % (n, mode, k, reg, cf, bpc, fr))
                 nys.nys_autotune_clear()
                 nys.nys_autotune_load(str(path))
-                assert nys.nys_autotune_query(op, prec, k) == (bool(reg), cf, bpc, True)
+                assert nys.nys_autotune_query(op, prec, k) == (bool(reg), cf, bpc, fr, True)
                 _check_product(op, X, sigma, P, prec)
     nys.nys_autotune_clear()

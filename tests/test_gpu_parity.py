@@ -223,6 +223,35 @@ def test_device_preconditioner_spectrum_rank_deficient():
         assert pre.min() >= mu * (1 - 1e-8), (mu, pre.min())
 
 
+def test_float32_factor_orthonormality_and_spectrum():
+    """The float32-U factor (the mixed-precision modes' storage, eigensolver
+    stopped at ratio 1e-3): U's columns orthonormal to 2e-5 in the 2-norm, so
+    P^{-1} = I + U F U^T keeps its eigenvalues in [(lam_l + mu)/(lam_1 + mu), 1]
+    up to that departure, far inside positive definiteness here; and the
+    approximation equals the oracle's to float32 accuracy."""
+    w = ridge_dense(m=3000, n=800, ell=160, seed=21)
+    X = w["X"]
+    op = nys.Operator.xtx(t32(X))
+    prec = nys.NYS_PREC_FP32_REFINE64
+    P = nys.nys_factor(*nys.nys_sketch(op, 160, omega0=t64(w["omega0"]), prec=prec), dtype=torch.float32,
+                       prec=prec)
+    U, lam = h(P.U), h(P.lam)
+    dev = np.linalg.norm(U.T @ U - np.eye(160), 2)
+    assert dev <= 2e-5, dev
+    mu = w["mu"]
+    E = np.eye(800)
+    Pinv = np.concatenate([h(nys.nys_precond_apply(P, mu, t64(E[:, j:j + 200]))) for j in range(0, 800, 200)],
+                          axis=1)
+    ev = np.linalg.eigvalsh(0.5 * (Pinv + Pinv.T))
+    lo = (lam[-1] + mu) / (lam[0] + mu)
+    assert ev.min() >= lo - 2 * dev and ev.max() <= 1 + 2 * dev, (ev.min(), lo, ev.max())
+    assert lo > 10 * dev
+    ref = oracle.randomized_nystrom(oracle.XtXOp(X), w["omega0"])
+    Ah = (U * lam) @ U.T
+    Ar = (ref["U"] * ref["lam"]) @ ref["U"].T
+    assert rel(Ah, Ar) < 1e-4
+
+
 @pytest.mark.parametrize("k", [1, 5])
 def test_precond_apply_with_oracle_factors(k):
     """Oracle U, lam passed in: P^{-1} R agrees to rounding (eq. (NysPre))."""
