@@ -604,6 +604,10 @@ __device__ __forceinline__ int rr_js(int pos, int ir) {
 // 2 x 2 block (rows of pair k1, columns of pair k2) of S = Sb[cur] into
 // Sb[cur ^ 1] and its J entries, one barrier per round.  CROSS: round ir
 // pairs i with JB + (i + ir) mod JB; else the round-robin over JS indices.
+// Each lane computes the rotation of its column pair k2 = lane mod 16 (so
+// lanes 0..15 of every wave hold all 16 rotations) and takes its row pair's
+// rotation from lane k1 of its own wave: one rotation per thread instead of
+// two, and no barrier for the exchange.
 template <bool CROSS>
 __device__ __forceinline__ void jac_inner(double (*Sb)[JS][JSS], double (*Jm)[JSS], int k1, int k2,
                                           int nround, double floor_abs, int& cur, bool& any_local,
@@ -623,9 +627,8 @@ __device__ __forceinline__ void jac_inner(double (*Sb)[JS][JSS], double (*Jm)[JS
       p2 = rr_js(k2, ir);
       q2 = rr_js(JS - 1 - k2, ir);
     }
-    // every LDS read of the round first: the entries of both rotations, the
-    // 2 x 2 block and this thread's J entries
-    const double r1pp = Si[p1][p1], r1qq = Si[q1][q1], r1pq = Si[p1][q1];
+    // every LDS read of the round first: the entries of this lane's
+    // rotation, the 2 x 2 block and this thread's J entries
     const double r2pp = Si[p2][p2], r2qq = Si[q2][q2], r2pq = Si[p2][q2];
     const double app = Si[p1][p2], apq = Si[p1][q2], aqp = Si[q1][p2], aqq = Si[q1][q2];
     double jp[2], jq[2];
@@ -634,13 +637,14 @@ __device__ __forceinline__ void jac_inner(double (*Sb)[JS][JSS], double (*Jm)[JS
       jp[h] = Jm[k1 + h * JH][p2];
       jq[h] = Jm[k1 + h * JH][q2];
     }
-    // both rotations (pair k2 == k1 on the diagonal blocks gives the same one twice)
-    double c1, s1, c2, s2;
-    const bool d1 = jacobi_rot_bf(r1pp, r1qq, r1pq, floor_abs, c1, s1);
+    double c2, s2;
     const bool d2 = jacobi_rot_bf(r2pp, r2qq, r2pq, floor_abs, c2, s2);
-    any_local |= d1 || d2;
-    if (k2 == 0 && d1) {
-      const float r2 = (float)(r1pq * r1pq) * __builtin_amdgcn_rcpf(fmaxf((float)fabs(r1pp * r1qq), 1e-30f));
+    // row rotation from lane k1 (k1 < 16) of this wave: bit-identical to
+    // the one every other thread of pair k1 uses
+    const double c1 = __shfl(c2, k1, 64), s1 = __shfl(s2, k1, 64);
+    any_local |= d2;
+    if (k1 == 0 && d2) {  // each pair's ratio once: the threads of row pair 0
+      const float r2 = (float)(r2pq * r2pq) * __builtin_amdgcn_rcpf(fmaxf((float)fabs(r2pp * r2qq), 1e-30f));
       r2loc = fmaxf(r2loc, fminf(r2, 1e30f));
     }
     // S <- R^T S R on the 2 x 2 block (on the diagonal blocks the rotated
@@ -788,13 +792,13 @@ __device__ void phase1_task(const JacArgs& a, int64_t g, int k) {
     if ((t & 63) == 0 && r2loc > 0.0f) atomicMax(&maxr, __float_as_uint(r2loc));
   }
   __syncthreads();
+  // the sweep's flag first, so its latency overlaps the stores below
+  if (t == 0 && rotated) atomicMax(reinterpret_cast<unsigned*>(a.flags) + sweep, maxr > 1u ? maxr : 1u);
   #pragma unroll
   for (int e = t; e < JS * JS; e += 256) {
     Jg[(int64_t)k * JS * JS + e] = Jm[e / JS][e % JS];
     Aout[gi[e / JS] * m + gi[e % JS]] = Sb[cur][e / JS][e % JS];
   }
-  __syncthreads();
-  if (t == 0 && rotated) atomicMax(reinterpret_cast<unsigned*>(a.flags) + sweep, maxr > 1u ? maxr : 1u);
 }
 
 // Phase 2 of round g - 1: A^(g) off-diagonal pair tiles from A^(g-1); V <- V J.

@@ -720,9 +720,12 @@ struct KvPlan {
 KvChoice kv_heuristic(int64_t k) {
   KvChoice c{};
   c.reg = k <= 64 ? 1 : 0;
-  c.cf = c.reg ? (k <= 16 ? 1 : k <= 32 ? 2 : 4) : (k > 128 ? 16 : 8);
+  // past 64 columns: the LDS kernel with 128 rows and 128 columns per
+  // workgroup, the shape the autotuner picks for both Gram modes at
+  // n = 5e4 .. 1e5 (k = 128 .. 1000)
+  c.cf = c.reg ? (k <= 16 ? 1 : k <= 32 ? 2 : 4) : 8;
   c.bpc = 8;
-  c.fr = 1;
+  c.fr = c.reg ? 1 : 2;
   return c;
 }
 

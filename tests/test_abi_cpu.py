@@ -162,9 +162,10 @@ def test_autotune_table_load_save_query(L, tmp_path):
     tuned = ctypes.c_int32(7)
     f32 = nys.NYS_PREC_FP32_REFINE64
     bf = nys.NYS_PREC_BF16X3_REFINE64
-    # built-in rule: register kernel with 1 / 2 / 4 tiles up to 64 columns, LDS kernel past that
-    for k, want in ((8, (1, 1, 8, 1)), (32, (1, 2, 8, 1)), (64, (1, 4, 8, 1)), (100, (0, 8, 8, 1)),
-                    (256, (0, 16, 8, 1))):
+    # built-in rule: register kernel with 1 / 2 / 4 tiles up to 64 columns, past that the LDS
+    # kernel with 128 columns and two row fragments per wave
+    for k, want in ((8, (1, 1, 8, 1)), (32, (1, 2, 8, 1)), (64, (1, 4, 8, 1)), (100, (0, 8, 8, 2)),
+                    (256, (0, 8, 8, 2))):
         assert L.nys_autotune_query(ctypes.byref(op), f32, k, ch, ctypes.byref(tuned)) == 0
         assert tuple(ch) == want and tuned.value == 0
     cache = tmp_path / "tune.txt"
@@ -176,7 +177,7 @@ def test_autotune_table_load_save_query(L, tmp_path):
     assert L.nys_autotune_load(str(cache).encode()) == 0
     assert L.nys_autotune_entries() == 4
     cases = [(f32, 10, (1, 4, 16, 1), 1), (f32, 16, (1, 4, 16, 1), 1), (f32, 17, (0, 16, 4, 2), 1),
-             (f32, 128, (0, 16, 4, 2), 1), (f32, 129, (0, 16, 8, 1), 0), (bf, 100, (1, 2, 8, 1), 1),
+             (f32, 128, (0, 16, 4, 2), 1), (f32, 129, (0, 8, 8, 2), 0), (bf, 100, (1, 2, 8, 1), 1),
              (bf, 8, (1, 2, 8, 1), 1)]
     for prec, k, want, t in cases:
         assert L.nys_autotune_query(ctypes.byref(op), prec, k, ch, ctypes.byref(tuned)) == 0
