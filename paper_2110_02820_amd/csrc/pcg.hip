@@ -14,6 +14,10 @@
 
 namespace nys {
 
+#ifndef NYS_UC_MIN_RPW
+#define NYS_UC_MIN_RPW 8  // rows per wave: >= 8 keeps small applies to fewer workgroups
+#endif
+
 namespace {
 
 constexpr int NT = 256;
@@ -45,18 +49,22 @@ __device__ __forceinline__ void colmap_reduce(double v, const ColMap& cm, double
 
 // True in exactly one workgroup: the last of `nblocks` to arrive.  Partial
 // results written before the call are visible to it afterwards.  The last
-// workgroup re-arms the counter for the next kernel.
+// workgroup re-arms the counter for the next kernel.  Arriving workgroups
+// publish with a release fence only (an L2 write-back, no invalidate) and
+// only the last one acquires: each arrival costs ~20 ns of serialised
+// fence and atomic traffic on this GPU (~9 us for 481 workgroups, measured),
+// so the launches that use this keep their workgroup counts modest.
 __device__ __forceinline__ bool last_block(unsigned* ctr, unsigned nblocks) {
   __shared__ int am;
   __syncthreads();
   if (threadIdx.x == 0) {
-    __threadfence();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     const unsigned t = atomicAdd(ctr, 1u);
     am = (t == nblocks - 1) ? 1 : 0;
   }
   __syncthreads();
   if (am) {
-    __threadfence();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     if (threadIdx.x == 0) *ctr = 0u;
   }
   return am != 0;
@@ -264,6 +272,38 @@ __global__ void cg_direction(int64_t n, int64_t k, const T* __restrict__ Z, T* _
   }
 }
 
+// k = 1 after the partial-only apply (mode 3): every workgroup sums the
+// apply's per-workgroup parts of r^T z in the same fixed order (the order of
+// the last-workgroup tail), so all agree on beta without a hand-off between
+// workgroups; then P = Z + beta P on its slice.  Workgroup 0 records beta,
+// r^T z, the done flag and the all-done flag as the tail would; the others
+// may read those flags before or after that store and decide the same.
+template <typename T>
+__global__ __launch_bounds__(NT) void cg_beta_direction(int64_t n, const T* __restrict__ Z, T* __restrict__ P,
+                                                        const double* __restrict__ prz, int nprz, CgScalars sc,
+                                                        int par) {
+  if (*sc.alldone) return;
+  __shared__ double sh[NT];
+  double s = 0.0;
+  for (int g = threadIdx.x; g < nprz; g += NT) s += prz[g];
+  const double rzn = block_sum(s, sh);
+  const int done_old = sc.done[0];
+  const int done_new = done_old || sc.conv[0];
+  const double beta = done_old ? 0.0 : rzn / sc.rz[par];
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (!done_old) {
+      sc.beta[0] = beta;
+      sc.rz[1 - par] = rzn;
+      sc.done[0] = done_new;
+    }
+    *sc.alldone = done_new;  // also after a breakdown flagged earlier in the iteration
+  }
+  if (done_new) return;
+  const T b = T(beta);
+  for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < n; i += (int64_t)gridDim.x * NT)
+    P[i] = Z[i] + b * P[i];
+}
+
 // x += a p, r -= a v over a whole vector by one workgroup, UN entries per
 // thread in flight per pass; returns this thread's part of ||r||^2 (entries in
 // increasing order, so the sum does not depend on UN).
@@ -469,7 +509,8 @@ __global__ __launch_bounds__(NT) void utr_final(int64_t l, int nch, const double
 // z_i = r_i + sum_j U[i][j] C'[j]: one wave per group of four rows, whose
 // 4 x NJ loads per lane (columns lane + 64 jj, l <= 64 NJ) are issued together.
 // mode 0: plain apply; mode 1: also r^T z for the set-up; mode 2: r^T z,
-// beta and flags.
+// beta and flags; mode 3: per-workgroup parts of r^T z only (cg_beta_direction
+// finishes them).
 template <typename TU, typename T, int NJ>
 __global__ __launch_bounds__(NT) void uc_rz(int64_t n, int64_t l, const TU* __restrict__ U, int64_t ldu,
                                             const double* __restrict__ Cs, const T* __restrict__ r,
@@ -477,7 +518,7 @@ __global__ __launch_bounds__(NT) void uc_rz(int64_t n, int64_t l, const TU* __re
                                             double* __restrict__ prz, CgScalars sc, int par, int mode,
                                             T* __restrict__ Pd) {
   // the flag is read with the first loads and tested before anything is stored
-  const int skip_all = mode == 2 ? *sc.alldone : 0;
+  const int skip_all = mode >= 2 ? *sc.alldone : 0;
   __shared__ double sh[NT];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   T cs[NJ];
@@ -526,6 +567,7 @@ __global__ __launch_bounds__(NT) void uc_rz(int64_t n, int64_t l, const TU* __re
   // every lane of a wave holds the same rzp; lane 0 contributes it
   const double tot = block_sum(lane == 0 ? rzp : 0.0, sh);
   if (threadIdx.x == 0) prz[blockIdx.x] = tot;
+  if (mode == 3) return;
   if (!last_block(sc.ctr, gridDim.x)) return;
   rz_tail(prz, gridDim.x, 1, sh, sc, par, mode == 1);
   if (Pd == nullptr) return;
@@ -624,7 +666,7 @@ __global__ __launch_bounds__(NT) void uc_vec(int64_t n, int64_t l, const TU* __r
                                              T* __restrict__ Pd) {
   typedef typename UVec<TU>::type VT;
   constexpr int E = UVec<TU>::E;
-  const int skip_all = mode == 2 ? *sc.alldone : 0;
+  const int skip_all = mode >= 2 ? *sc.alldone : 0;
   __shared__ double sh[NT];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   T cs[NG][E];
@@ -694,6 +736,7 @@ __global__ __launch_bounds__(NT) void uc_vec(int64_t n, int64_t l, const TU* __r
   // lanes 0, 16, 32 and 48 hold the rows' parts of r^T z
   const double tot = block_sum(rzp, sh);
   if (threadIdx.x == 0) prz[blockIdx.x] = tot;
+  if (mode == 3) return;
   if (!last_block(sc.ctr, gridDim.x)) return;
   rz_tail(prz, gridDim.x, 1, sh, sc, par, mode == 1);
   if (Pd == nullptr) return;
@@ -818,6 +861,14 @@ void uc_dispatch(int64_t n, int64_t l, const TU* U, int64_t ldu, const double* C
 #undef LC
 }
 
+// rows per wave of the k = 1 apply: at most 512 workgroups (partial buffer
+// size) and at least NYS_UC_MIN_RPW rows per wave
+int64_t uc_rows_per_wave(int64_t n) {
+  const int64_t rpw = cdiv(n, 4 * 512);
+  return cdiv(rpw < NYS_UC_MIN_RPW ? NYS_UC_MIN_RPW : rpw, 4) * 4;
+}
+unsigned uc_blocks(int64_t n) { return (unsigned)cdiv(cdiv(n, uc_rows_per_wave(n)), 4); }
+
 nys_status uc_launch(const PrecDesc& P, const double* Cs, const void* R, void* Z, bool f32, double* prz,
                      const CgScalars& sc, int par, int mode, hipStream_t s, void* Pd = nullptr) {
   const int64_t n = P.n, l = P.ell;
@@ -825,8 +876,7 @@ nys_status uc_launch(const PrecDesc& P, const double* Cs, const void* R, void* Z
     set_error("preconditioner apply: l = %lld > 2048 not supported", (long long)l);
     return NYS_ERR_ARG;
   }
-  int64_t rpw = cdiv(n, 4 * 512);  // at most 512 workgroups (partial buffer size)
-  rpw = cdiv(rpw < 4 ? 4 : rpw, 4) * 4;
+  const int64_t rpw = uc_rows_per_wave(n);
   const unsigned nb = (unsigned)cdiv(cdiv(n, rpw), 4);
   const bool vec = P.dtype == NYS_F64 ? uvec_ok<double>(P) : uvec_ok<float>(P);
   if (P.dtype == NYS_F64 && !f32)
@@ -965,6 +1015,18 @@ nys_status pcg_setup(int64_t n, int64_t k, const PrecDesc& P, const double* mu_d
   return NYS_OK;
 }
 
+// k = 1: beta and P = Z + beta P after a mode-3 apply
+template <typename T>
+nys_status beta_direction_launch(int64_t n, const T* Z, T* Pd, PcgWork& w, const CgScalars& sc, int par,
+                                 hipStream_t s) {
+  int64_t g = cdiv(n, 4 * NT);  // four entries per thread
+  g = g < 1 ? 1 : g > 1024 ? 1024 : g;
+  hipLaunchKernelGGL(cg_beta_direction<T>, dim3((unsigned)g), dim3(NT), 0, s, n, Z, Pd, w.prz, (int)uc_blocks(n),
+                     sc, par);
+  NYS_CHECK_LAUNCH();
+  return NYS_OK;
+}
+
 template <typename T>
 nys_status pcg_iteration(int64_t n, int64_t k, const PrecDesc& P, const double* mu_dev, int64_t nrhs,
                          const T* V, T* X, int64_t ldx, T* R, T* Z, T* Pd, PcgWork& w, const CgScalars& sc,
@@ -979,12 +1041,12 @@ nys_status pcg_iteration(int64_t n, int64_t k, const PrecDesc& P, const double* 
   NYS_CHECK_LAUNCH();
   if (k == 1) {
     NYS_TRY(utr_launch(P, mu_dev, R, f32, w.apart, w.Cs, sc.ctr + 1, sc.alldone, s));
-    NYS_TRY(uc_launch(P, w.Cs, R, Z, f32, w.prz, sc, par, 2, s));
-  } else {
-    NYS_TRY(apply_block_t<T>(P, mu_dev, nrhs, R, Z, k, sc.done, sc.alldone, w, s));
-    hipLaunchKernelGGL(cg_rz<T>, dim3((unsigned)ng), dim3(NT), 0, s, n, k, R, Z, w.prz, rpw, sc, par, 0);
-    NYS_CHECK_LAUNCH();
+    NYS_TRY(uc_launch(P, w.Cs, R, Z, f32, w.prz, sc, par, 3, s));
+    return beta_direction_launch<T>(n, Z, Pd, w, sc, par, s);
   }
+  NYS_TRY(apply_block_t<T>(P, mu_dev, nrhs, R, Z, k, sc.done, sc.alldone, w, s));
+  hipLaunchKernelGGL(cg_rz<T>, dim3((unsigned)ng), dim3(NT), 0, s, n, k, R, Z, w.prz, rpw, sc, par, 0);
+  NYS_CHECK_LAUNCH();
   hipLaunchKernelGGL(cg_direction<T>, dim3((unsigned)cdiv(n * k, 256)), dim3(256), 0, s, n, k, Z, Pd, sc, 0);
   NYS_CHECK_LAUNCH();
   return NYS_OK;
@@ -1002,6 +1064,9 @@ __global__ void pcg_snapshot_kernel(CgScalars sc, PcgSnap* out, int seq) {
 }
 
 constexpr int64_t kFuseMaxN = 16384;
+#ifndef NYS_FIN_FUSED_BLOCKS
+#define NYS_FIN_FUSED_BLOCKS 64  // matvec finish when it also updates x and r (n <= kFuseMaxN)
+#endif
 
 nys_status pcg_snapshot(const CgScalars& sc, PcgSnap* out, int seq, hipStream_t s) {
   hipLaunchKernelGGL(pcg_snapshot_kernel, dim3(1), dim3(1), 0, s, sc, out, seq);
@@ -1015,7 +1080,8 @@ nys_status pcg_iteration_fused(int64_t n, const PrecDesc& P, const double* mu_de
                                const CgScalars& sc, int par, double tol, hipStream_t s) {
   const bool f32 = sizeof(T) == 4;
   const bool fuse = n <= kFuseMaxN;
-  const int64_t nfb = cdiv(n, 32) < 512 ? cdiv(n, 32) : 512;
+  const int64_t fmax = fuse ? NYS_FIN_FUSED_BLOCKS : 512;
+  const int64_t nfb = cdiv(n, 32) < fmax ? cdiv(n, 32) : fmax;
   hipLaunchKernelGGL(cg_finish_mv<T>, dim3((unsigned)nfb), dim3(NT), 0, s, n, part, ng, scale, mu, Pd,
                      V, w.ppv, sc, par, fuse ? 1 : 0, X, R, w.prr, tol);
   NYS_CHECK_LAUNCH();
@@ -1026,12 +1092,9 @@ nys_status pcg_iteration_fused(int64_t n, const PrecDesc& P, const double* mu_de
     NYS_CHECK_LAUNCH();
   }
   NYS_TRY(utr_launch(P, mu_dev, R, f32, w.apart, w.Cs, sc.ctr + 1, sc.alldone, s));
-  NYS_TRY(uc_launch(P, w.Cs, R, Z, f32, w.prz, sc, par, 2, s, fuse ? Pd : nullptr));
-  if (!fuse) {
-    hipLaunchKernelGGL(cg_direction<T>, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, s, n, (int64_t)1, Z, Pd, sc, 0);
-    NYS_CHECK_LAUNCH();
-  }
-  return NYS_OK;
+  if (fuse) return uc_launch(P, w.Cs, R, Z, f32, w.prz, sc, par, 2, s, Pd);
+  NYS_TRY(uc_launch(P, w.Cs, R, Z, f32, w.prz, sc, par, 3, s));
+  return beta_direction_launch<T>(n, Z, Pd, w, sc, par, s);
 }
 
 template <typename T>
