@@ -298,7 +298,12 @@ __device__ __forceinline__ void split_bf16x4(const float (&v)[4], bf4v& hi, bf4v
   }
 }
 
-constexpr int XK = 32, XPAD = 40;
+#ifndef NYS_GEMM_XK
+#define NYS_GEMM_XK 32
+#endif
+constexpr int XK = NYS_GEMM_XK, XPAD = XK + 8;  // k per staged slab (a multiple of 32)
+constexpr int XR = XK / 8;                      // runs of 4 k per thread per operand and slab
+constexpr int XQ = XK / 4;                      // runs of 4 k per row of a slab
 
 template <bool TA, bool TB>
 __global__ __launch_bounds__(NT) void gemm_bf16x3(int64_t M, int64_t N, int64_t K, int64_t kchunk, float alpha,
@@ -318,15 +323,15 @@ __global__ __launch_bounds__(NT) void gemm_bf16x3(int64_t M, int64_t N, int64_t 
   const int wm = wave >> 1, wn = wave & 1;
   const int64_t kb = (int64_t)blockIdx.y * kchunk;
   const int64_t ke = (kb + kchunk < K) ? kb + kchunk : K;
-  // each thread stages 4 runs of 4 consecutive k for A and for B (128 x 32 each)
-  float ra[4][4], rb[4][4];
+  // each thread stages XR runs of 4 consecutive k for A and for B (128 x XK each)
+  float ra[XR][4], rb[XR][4];
   auto load = [&](int64_t k0) {
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
+    for (int r = 0; r < XR; ++r) {
       const int e = t + NT * r;
-      // A run: row (e % 128) when A is transposed, else row e / 8; k offset 4 * (e / 128) or 4 * (e % 8)
-      const int row = TA ? (e & (LM - 1)) : (e >> 3);
-      const int kq = TA ? (e >> 7) : (e & 7);
+      // A run: row (e % 128) when A is transposed, else row e / XQ; k offset 4 * (e / 128) or 4 * (e % XQ)
+      const int row = TA ? (e & (LM - 1)) : (e / XQ);
+      const int kq = TA ? (e >> 7) : (e % XQ);
       const int64_t gm = m0 + row, gk = k0 + 4 * kq;
       if (!TA && gm < M && gk + 3 < ke) {
         const float4 v = *reinterpret_cast<const float4*>(A + gm * lda + gk);
@@ -336,8 +341,8 @@ __global__ __launch_bounds__(NT) void gemm_bf16x3(int64_t M, int64_t N, int64_t 
         for (int u = 0; u < 4; ++u)
           ra[r][u] = (gm < M && gk + u < ke) ? (TA ? A[(gk + u) * lda + gm] : A[gm * lda + gk + u]) : 0.0f;
       }
-      const int col = TB ? (e >> 3) : (e & (LN - 1));
-      const int kqb = TB ? (e & 7) : (e >> 7);
+      const int col = TB ? (e / XQ) : (e & (LN - 1));
+      const int kqb = TB ? (e % XQ) : (e >> 7);
       const int64_t gn = n0 + col, gkb = k0 + 4 * kqb;
       if (TB && gn < N && gkb + 3 < ke) {
         const float4 v = *reinterpret_cast<const float4*>(B + gn * ldb + gkb);
@@ -351,16 +356,16 @@ __global__ __launch_bounds__(NT) void gemm_bf16x3(int64_t M, int64_t N, int64_t 
   };
   auto store = [&]() {
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
+    for (int r = 0; r < XR; ++r) {
       const int e = t + NT * r;
-      const int row = TA ? (e & (LM - 1)) : (e >> 3);
-      const int kq = TA ? (e >> 7) : (e & 7);
+      const int row = TA ? (e & (LM - 1)) : (e / XQ);
+      const int kq = TA ? (e >> 7) : (e % XQ);
       bf4v h, l;
       split_bf16x4(ra[r], h, l);
       *reinterpret_cast<bf4v*>(&Ah[row][4 * kq]) = h;
       *reinterpret_cast<bf4v*>(&Al[row][4 * kq]) = l;
-      const int col = TB ? (e >> 3) : (e & (LN - 1));
-      const int kqb = TB ? (e & 7) : (e >> 7);
+      const int col = TB ? (e / XQ) : (e & (LN - 1));
+      const int kqb = TB ? (e % XQ) : (e >> 7);
       split_bf16x4(rb[r], h, l);
       *reinterpret_cast<bf4v*>(&Bh[col][4 * kqb]) = h;
       *reinterpret_cast<bf4v*>(&Bl[col][4 * kqb]) = l;
@@ -377,23 +382,26 @@ __global__ __launch_bounds__(NT) void gemm_bf16x3(int64_t M, int64_t N, int64_t 
     store();
     __syncthreads();
     if (k0 + XK < ke) load(k0 + XK);
-    const int ks = 8 * (lane >> 4);
-    bf8v ah[4], al[4], bh[4], bl[4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      ah[i] = *reinterpret_cast<const bf8v*>(&Ah[wm * 64 + i * 16 + (lane & 15)][ks]);
-      al[i] = *reinterpret_cast<const bf8v*>(&Al[wm * 64 + i * 16 + (lane & 15)][ks]);
-      bh[i] = *reinterpret_cast<const bf8v*>(&Bh[wn * 64 + i * 16 + (lane & 15)][ks]);
-      bl[i] = *reinterpret_cast<const bf8v*>(&Bl[wn * 64 + i * 16 + (lane & 15)][ks]);
-    }
+    for (int kk = 0; kk < XK; kk += 32) {
+      const int ks = kk + 8 * (lane >> 4);
+      bf8v ah[4], al[4], bh[4], bl[4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        f4 c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
-        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], c, 0, 0, 0);
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], c, 0, 0, 0);
+      for (int i = 0; i < 4; ++i) {
+        ah[i] = *reinterpret_cast<const bf8v*>(&Ah[wm * 64 + i * 16 + (lane & 15)][ks]);
+        al[i] = *reinterpret_cast<const bf8v*>(&Al[wm * 64 + i * 16 + (lane & 15)][ks]);
+        bh[i] = *reinterpret_cast<const bf8v*>(&Bh[wn * 64 + i * 16 + (lane & 15)][ks]);
+        bl[i] = *reinterpret_cast<const bf8v*>(&Bl[wn * 64 + i * 16 + (lane & 15)][ks]);
       }
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          f4 c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
+          c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], c, 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], c, 0, 0, 0);
+        }
+    }
   }
 #pragma unroll
   for (int i = 0; i < 4; ++i)
