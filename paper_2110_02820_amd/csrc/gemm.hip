@@ -544,8 +544,22 @@ nys_status gemm_bf16x3(bool ta, bool tb, int64_t M, int64_t N, int64_t K, float 
   const bool vec_b = !tb || ((ldb % 4 == 0) && ((uintptr_t)B % 16 == 0));
   if (!vec_a || !vec_b || K % 4 != 0)
     return gemm<float, float, float>(ta, tb, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, scratch, scratch_elems, s);
-  const int64_t lt = cdiv(M, LM) * cdiv(N, LN);
+  const int64_t nt = cdiv(N, LN), lt = cdiv(M, LM) * nt;
+  // two workgroups of this kernel fit on a compute unit: one round of tiles
   const int64_t target = 2 * (int64_t)(num_cus() < 256 ? num_cus() : 256);
+  if (lt > target && lt < 2 * target) {
+    // between one and two rounds: the rows of one full round first, then
+    // the remaining rows on their own, split over k, instead of a second
+    // round that leaves most compute units idle (the ridge sketch's
+    // 20000 x 500 product: 628 tiles for 512 slots)
+    const int64_t m1 = (target / nt) * LM;
+    if (m1 > 0 && m1 < M) {
+      NYS_TRY(gemm_bf16x3(ta, tb, m1, N, K, alpha, A, lda, B, ldb, beta, C, ldc, scratch, scratch_elems, s));
+      const float* A2 = ta ? A + m1 : A + m1 * lda;
+      return gemm_bf16x3(ta, tb, M - m1, N, K, alpha, A2, lda, B, ldb, beta, C + m1 * ldc, ldc, scratch,
+                         scratch_elems, s);
+    }
+  }
   int64_t nz = 1;
   if (lt < target) {
     nz = cdiv(target, lt);

@@ -71,11 +71,14 @@ def test_op_apply(kind, k):
     np.testing.assert_allclose(out, ref.matmat(V) + mu * V, rtol=1e-12, atol=1e-12)
 
 
-@pytest.mark.parametrize("case", ["dense64", "xtx32_f64", "xtx32_sketch_f32", "xtx32_sketch_bf16x3"])
+@pytest.mark.parametrize("case", ["dense64", "xtx32_f64", "xtx32_sketch_f32", "xtx32_sketch_bf16x3",
+                                  "xtx32_sketch_bf16x3_rounds"])
 def test_large_tile_products(case):
     """Products of at least 1e9 multiply-adds with 16-byte aligned operands take
     the 128 x 128 tile GEMM (split-K when the output has few tiles); the sizes
-    leave ragged tiles in every dimension."""
+    leave ragged tiles in every dimension.  The last case's X Omega has
+    between one and two rounds of tiles (157 x 4 = 628 on 512 slots), so its
+    rows are done in two parts, the second split over k."""
     rng = np.random.default_rng(7)
     if case == "dense64":
         n, k = 2050, 250
@@ -91,12 +94,13 @@ def test_large_tile_products(case):
         ref = oracle.XtXOp(X.astype(np.float64), 0.5).matmat(V) + 0.25 * V
         assert rel(out, ref) < 1e-13
     else:
-        X = rng.standard_normal((4001, 1204)).astype(np.float32)
-        om0 = rng.standard_normal((1204, 212))
+        m, n, ell = (20000, 1100, 400) if case.endswith("rounds") else (4001, 1204, 212)
+        X = rng.standard_normal((m, n)).astype(np.float32)
+        om0 = rng.standard_normal((n, ell))
         op = nys.Operator.xtx(t32(X))
-        bf = case.endswith("bf16x3")
+        bf = "bf16x3" in case
         prec = nys.NYS_PREC_BF16X3_REFINE64 if bf else nys.NYS_PREC_FP32_REFINE64
-        Om, Y = nys.nys_sketch(op, 212, omega0=t64(om0), prec=prec)
+        Om, Y = nys.nys_sketch(op, ell, omega0=t64(om0), prec=prec)
         Om, Y = h(Om), h(Y)
         Q = oracle.orthonormalize(om0)
         Xd = X.astype(np.float64)
