@@ -19,6 +19,7 @@
 #include "ragged.hpp"
 #include "rbf_lowp.hpp"
 #include "rng.hpp"
+#include "xtx.hpp"
 
 // Eigensolver stopping ratio when U is stored in float32 (see jac_end_sweep):
 // a sweep whose subproblems met no |a_pq| above this times sqrt(|a_pp a_qq|)
@@ -785,13 +786,28 @@ nys_status pcg_run(const OpDesc& op0, const PrecDesc& P, int64_t k, const double
   bool tune = check_every <= 0;
   const auto t_start = std::chrono::steady_clock::now();
   int last_poll = 0;
+  const bool xtx_path = op.kind == NYS_OP_XTX && pcg_xtx_ok(P, n);
   // one iteration on the current kc columns
   auto step = [&]() -> nys_status {
     const int par = it & 1;
     // single column with a partial-sum operator product: fused iteration
     const bool fused = kc == 1 && (op.kind == NYS_OP_XTX ||
                                    (op.kind == NYS_OP_RBF && (sizeof(T) == 8 || op.lowp != nullptr)));
-    if (fused) {
+    if (fused && xtx_path) {
+      // X^T X: the product also gives p^T A p, so alpha needs no summed product
+      int ng = 0;
+      bool filled = false;
+      if (op.dtype == NYS_F64)
+        NYS_TRY((xtx_partials<double, T>(op, b.P, b.opscr, b.opscr_elems, &ng, s, b.w.ppv, &filled)));
+      else
+        NYS_TRY((xtx_partials<float, T>(op, b.P, b.opscr, b.opscr_elems, &ng, s, b.w.ppv, &filled)));
+      if (filled)
+        NYS_TRY(pcg_iteration_xtx<T>(n, P, b.mu, mu_host[map[0]], b.opscr, ng, b.w.ppv, op.scale, b.V, Xc, b.R,
+                                     b.Z, b.P, b.w, b.sc, par, tol, s));
+      else
+        NYS_TRY(pcg_iteration_fused<T>(n, P, b.mu, mu_host[map[0]], b.opscr, ng, op.scale, b.V, Xc, b.R, b.Z,
+                                       b.P, b.w, b.sc, par, tol, s));
+    } else if (fused) {
       int ng = 0;
       NYS_TRY(op_matvec_partials<T>(op, b.P, b.opscr, b.opscr_elems, &ng, s));
       NYS_TRY(pcg_iteration_fused<T>(n, P, b.mu, mu_host[map[0]], b.opscr, ng, op.scale, b.V, Xc, b.R, b.Z,

@@ -656,6 +656,166 @@ __global__ __launch_bounds__(NT) void utr_vec(int64_t n, int64_t l, const TU* __
   (void)ok;
 }
 
+// k = 1, X^T X operator, after a product that also gave pvq (see
+// xtx_partials): p^T (A + mu I) p = scale sum_g pvq[g] + mu ||p||^2, summed
+// by every workgroup in the same fixed order, so each knows alpha at once and
+// no workgroup hands it to another.  Tiles of 32 entries: v_j from the ng
+// partials (8 slices of 32 columns, as cg_finish_mv), x_j += alpha p_j,
+// r_j -= alpha v_j, a part of ||r||^2, and this workgroup's part of U^T r over
+// the tile's rows of U (thread t owns the 16-byte vectors t, t + NT of a row;
+// float64 accumulation).  Workgroup 0 records alpha and a breakdown.
+template <typename T, typename TU>
+__global__ __launch_bounds__(NT) void cg_finish_xtx(int64_t n, const T* __restrict__ part, int ng,
+                                                    const double* __restrict__ pvq, double scale, double mu,
+                                                    const T* __restrict__ P, T* __restrict__ V, T* __restrict__ X,
+                                                    T* __restrict__ R, const TU* __restrict__ U, int64_t l,
+                                                    int64_t ldu, double* __restrict__ apart,
+                                                    double* __restrict__ prr, CgScalars sc, int par) {
+  typedef typename UVec<TU>::type VT;
+  constexpr int E = UVec<TU>::E;
+  constexpr int CG = 2;  // vectors per thread: l <= 2 NT E (uvec_ok allows 64 E 8 = 2 NT E)
+  const int skip_all = *sc.alldone;
+  __shared__ T shp[8][33];
+  __shared__ double sh[NT];
+  __shared__ double rs[32];
+  double q = 0.0;
+  for (int g = threadIdx.x; g < ng; g += NT) q += pvq[g];
+  const double pv = scale * block_sum(q, sh) + mu * pvq[ng];
+  if (skip_all) return;  // the same value for every thread
+  const int done = sc.done[0];
+  const double a_d = (done || !(pv > 0.0)) ? 0.0 : sc.rz[par] / pv;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    sc.alpha[0] = a_d;
+    if (!done && !(pv > 0.0)) {
+      sc.status[0] = NYS_ERR_BREAKDOWN;
+      sc.done[0] = 1;
+    }
+  }
+  const T a = T(a_d);
+  const int c = threadIdx.x & 31, sl = threadIdx.x >> 5;
+  const int64_t nvec = l / E;
+  int64_t uo[CG];
+  bool uok[CG];
+#pragma unroll
+  for (int v = 0; v < CG; ++v) {
+    const int64_t vi = (int64_t)v * NT + threadIdx.x;
+    uok[v] = vi < nvec;
+    uo[v] = uok[v] ? vi * E : 0;
+  }
+  double acc[CG][E];
+#pragma unroll
+  for (int v = 0; v < CG; ++v)
+#pragma unroll
+    for (int e = 0; e < E; ++e) acc[v][e] = 0.0;
+  double rrp = 0.0;
+  const int64_t ntiles = cdiv(n, 32);
+  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const int64_t j = tile * 32 + c;
+    const int64_t jc = j < n ? j : n - 1;
+    T a0 = T(0);
+    for (int g0 = sl; g0 < ng; g0 += 256) {
+      T v[32];
+#pragma unroll
+      for (int u = 0; u < 32; ++u) {
+        const int g = g0 + 8 * u;
+        v[u] = g < ng ? part[(int64_t)g * n + jc] : T(0);
+      }
+#pragma unroll
+      for (int u = 0; u < 32; ++u) a0 += v[u];
+    }
+    __syncthreads();  // the previous tile's readers of shp and rs are done
+    shp[sl][c] = a0;
+    __syncthreads();
+    if (sl == 0) {
+      double rj_d = 0.0;
+      if (j < n) {
+        const T sum = ((shp[0][c] + shp[1][c]) + (shp[2][c] + shp[3][c])) +
+                      ((shp[4][c] + shp[5][c]) + (shp[6][c] + shp[7][c]));
+        const T pj = P[j];
+        const T vj = T(scale) * sum + T(mu) * pj;
+        V[j] = vj;
+        X[j] += a * pj;
+        const T rj = R[j] - a * vj;
+        R[j] = rj;
+        rrp += double(rj) * double(rj);
+        rj_d = double(rj);
+      }
+      rs[c] = rj_d;  // 0 past n
+    }
+    __syncthreads();
+    const int64_t rows = n - tile * 32 < 32 ? n - tile * 32 : 32;
+    const TU* ub = U + tile * 32 * ldu;
+    for (int r0 = 0; r0 < 32; r0 += 8) {
+      VT uv[8][CG];
+#pragma unroll
+      for (int rr = 0; rr < 8; ++rr) {
+        const int64_t row = r0 + rr < rows ? r0 + rr : 0;  // rows past n re-read the tile's first (rs = 0)
+#pragma unroll
+        for (int v = 0; v < CG; ++v) uv[rr][v] = *reinterpret_cast<const VT*>(ub + row * ldu + uo[v]);
+      }
+#pragma unroll
+      for (int rr = 0; rr < 8; ++rr) {
+        const double rv = rs[r0 + rr];
+#pragma unroll
+        for (int v = 0; v < CG; ++v)
+#pragma unroll
+          for (int e = 0; e < E; ++e) acc[v][e] += double(UVec<TU>::get(uv[rr][v], e)) * rv;
+      }
+    }
+  }
+#pragma unroll
+  for (int v = 0; v < CG; ++v)
+    if (uok[v])
+#pragma unroll
+      for (int e = 0; e < E; ++e) apart[(int64_t)blockIdx.x * l + uo[v] + e] = acc[v][e];
+  const double rr = block_sum(rrp, sh);
+  if (threadIdx.x == 0) prr[blockIdx.x] = rr;
+}
+
+// utr_final plus, in workgroup 0, the stopping test of the update that
+// cg_finish_xtx made: ||r||^2 from its per-workgroup parts (fixed order).
+__global__ __launch_bounds__(NT) void utr_final_rr(int64_t l, int nch, const double* __restrict__ part,
+                                                   const double* __restrict__ lam, const double* __restrict__ mu,
+                                                   double* __restrict__ Cs, const double* __restrict__ prr, int nprr,
+                                                   CgScalars sc, double tol) {
+  const int skip_all = *sc.alldone;
+  __shared__ double red[4][64];
+  __shared__ double sh[NT];
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  const int64_t j = (int64_t)blockIdx.x * 64 + tx;
+  const int64_t jc = j < l ? j : l - 1;
+  double acc = 0.0;
+  for (int q0 = ty; q0 < nch; q0 += 4 * 16) {  // 16 loads in flight per thread
+    double v[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int q = q0 + 4 * u;
+      v[u] = q < nch ? part[(int64_t)q * l + jc] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 16; ++u) acc += v[u];
+  }
+  if (skip_all) return;
+  red[ty][tx] = acc;
+  __syncthreads();
+  if (ty == 0 && j < l) {
+    const double tot = (red[0][tx] + red[1][tx]) + (red[2][tx] + red[3][tx]);
+    const double m = mu[0];
+    Cs[j] = ((lam[l - 1] + m) / (lam[j] + m) - 1.0) * tot;
+  }
+  if (blockIdx.x != 0) return;
+  double s = 0.0;
+  for (int q = threadIdx.x; q < nprr; q += NT) s += prr[q];
+  const double rr = block_sum(s, sh);
+  if (threadIdx.x == 0 && !sc.done[0]) {
+    sc.rnorm2[0] = rr;
+    sc.iters[0] += 1;
+    const bool conv = rr <= tol * tol * sc.bnorm2[0];
+    sc.conv[0] = conv ? 1 : 0;
+    if (conv) sc.status[0] = NYS_OK;
+  }
+}
+
 // z_i = r_i + sum_j U[i][j] C'[j] with 16-byte loads: lane owns vectors
 // lane + 64 g (g < NG) of every row, four rows per pass.  Modes as uc_rz.
 template <typename TU, typename T, int NG>
@@ -1097,6 +1257,36 @@ nys_status pcg_iteration_fused(int64_t n, const PrecDesc& P, const double* mu_de
   return beta_direction_launch<T>(n, Z, Pd, w, sc, par, s);
 }
 
+bool pcg_xtx_ok(const PrecDesc& P, int64_t n) {
+  return n <= kFuseMaxN && (P.dtype == NYS_F64 ? uvec_ok<double>(P) : uvec_ok<float>(P));
+}
+
+template <typename T>
+nys_status pcg_iteration_xtx(int64_t n, const PrecDesc& P, const double* mu_dev, double mu, const T* part, int ng,
+                             const double* pvq, double scale, T* V, T* X, T* R, T* Z, T* Pd, PcgWork& w,
+                             const CgScalars& sc, int par, double tol, hipStream_t s) {
+  const bool f32 = sizeof(T) == 4;
+  if (!pcg_xtx_ok(P, n)) {
+    set_error("pcg_iteration_xtx: needs n <= %lld and a 16-byte U layout", (long long)kFuseMaxN);
+    return NYS_ERR_ARG;
+  }
+  const int64_t l = P.ell;
+  // tiles of 32 entries over at most 64 workgroups (each also reads its
+  // tiles' rows of U for U^T r)
+  const int64_t nfb = cdiv(n, 32) < 64 ? cdiv(n, 32) : 64;
+  if (P.dtype == NYS_F64)
+    hipLaunchKernelGGL((cg_finish_xtx<T, double>), dim3((unsigned)nfb), dim3(NT), 0, s, n, part, ng, pvq, scale, mu,
+                       Pd, V, X, R, static_cast<const double*>(P.U), l, P.ldu, w.apart, w.prr, sc, par);
+  else
+    hipLaunchKernelGGL((cg_finish_xtx<T, float>), dim3((unsigned)nfb), dim3(NT), 0, s, n, part, ng, pvq, scale, mu,
+                       Pd, V, X, R, static_cast<const float*>(P.U), l, P.ldu, w.apart, w.prr, sc, par);
+  NYS_CHECK_LAUNCH();
+  hipLaunchKernelGGL(utr_final_rr, dim3((unsigned)cdiv(l, 64)), dim3(NT), 0, s, l, (int)nfb, w.apart, P.lam, mu_dev,
+                     w.Cs, w.prr, (int)nfb, sc, tol);
+  NYS_CHECK_LAUNCH();
+  return uc_launch(P, w.Cs, R, Z, f32, w.prz, sc, par, 2, s, Pd);
+}
+
 template <typename T>
 nys_status cg_block_init(int64_t n, int64_t k, const T* B, const T* V, T* R, PcgWork& w, const CgScalars& sc,
                          double tol, hipStream_t s) {
@@ -1146,6 +1336,12 @@ template nys_status cg_block_direction<float>(int64_t, int64_t, const float*, co
 template nys_status cg_block_direction<double>(int64_t, int64_t, const double*, const double*, double*,
                                                PcgWork&, const CgScalars&, int, bool, hipStream_t);
 
+template nys_status pcg_iteration_xtx<double>(int64_t, const PrecDesc&, const double*, double, const double*, int,
+                                              const double*, double, double*, double*, double*, double*, double*,
+                                              PcgWork&, const CgScalars&, int, double, hipStream_t);
+template nys_status pcg_iteration_xtx<float>(int64_t, const PrecDesc&, const double*, double, const float*, int,
+                                             const double*, double, float*, float*, float*, float*, float*, PcgWork&,
+                                             const CgScalars&, int, double, hipStream_t);
 template nys_status pcg_iteration_fused<double>(int64_t, const PrecDesc&, const double*, double, const double*, int,
                                                 double, double*, double*, double*, double*, double*, PcgWork&,
                                                 const CgScalars&, int, double, hipStream_t);

@@ -62,7 +62,8 @@ template <typename TD, typename TA, typename VP, int NV, int R>
 __global__ __launch_bounds__(256) void xtx_fused(const TD* __restrict__ X, int64_t m, int64_t n,
                                                  int64_t ld, const TA* __restrict__ p,
                                                  TA* __restrict__ part, int64_t rows_per_wg,
-                                                 const int* __restrict__ skip, const double* __restrict__ wts) {
+                                                 const int* __restrict__ skip, const double* __restrict__ wts,
+                                                 double* __restrict__ pvq) {
   const int sk = skip ? *skip : 0;  // tested once the first loads are issued
   typedef typename VP::type VT;
   constexpr int E = VP::E;
@@ -87,6 +88,7 @@ __global__ __launch_bounds__(256) void xtx_fused(const TD* __restrict__ X, int64
   const int64_t r0 = (int64_t)blockIdx.x * rows_per_wg;
   const int64_t r1 = (r0 + rows_per_wg < m) ? r0 + rows_per_wg : m;
   int buf = 0;
+  double tq = 0.0;  // thread 0, when pvq is given: sum over this workgroup's rows of w_r (x_r^T p)^2
   // one group of RR rows held in registers: t_r = x_r^T p, acc += t_r x_r
   auto process = [&](VT(&xr)[R][NV], int rr, int64_t row0) {
     TA d[R];
@@ -111,8 +113,10 @@ __global__ __launch_bounds__(256) void xtx_fused(const TD* __restrict__ X, int64
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       if (r >= rr) break;
-      TA tr = red[buf][0][r] + red[buf][1][r] + red[buf][2][r] + red[buf][3][r];
+      const TA tu = red[buf][0][r] + red[buf][1][r] + red[buf][2][r] + red[buf][3][r];
+      TA tr = tu;
       if (wts) tr *= TA(wts[row0 + r]);  // weighted operator: d_r x_r^T p
+      if (pvq && t == 0) tq += double(tu) * double(tr);
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
         if (!ok[v]) continue;
@@ -161,6 +165,21 @@ __global__ __launch_bounds__(256) void xtx_fused(const TD* __restrict__ X, int64
 #pragma unroll
       for (int e = 0; e < E; ++e) out[vi * E + e] = acc[v][e];
     }
+  if (pvq) {
+    // pvq[g] = sum over workgroup g's rows of w_r (x_r^T p)^2, so p^T X^T D X p
+    // is known without summing the partials; workgroup 0 also writes ||p||^2
+    if (t == 0) pvq[blockIdx.x] = tq;
+    if (blockIdx.x == 0) {
+      __shared__ double shq[4];
+      double q = 0.0;
+#pragma unroll
+      for (int v = 0; v < NV; ++v)
+#pragma unroll
+        for (int e = 0; e < E; ++e) q += double(pr[v][e]) * double(pr[v][e]);  // 0 past n
+      q = block_sum(q, shq);
+      if (t == 0) pvq[gridDim.x] = q;
+    }
+  }
 }
 
 // out[j] = alpha * sum_g part[g][j] + beta * y[j].  Block = 32 columns x 8
@@ -264,7 +283,8 @@ __global__ __launch_bounds__(256) void xtx_colpart(const TD* __restrict__ X, int
 
 template <typename TD, typename TA>
 nys_status xtx_partials(const OpDesc& op, const TA* p, TA* scratch, size_t scratch_elems, int* ng_out,
-                          hipStream_t s) {
+                          hipStream_t s, double* pvq, bool* pvq_filled) {
+  if (pvq_filled) *pvq_filled = false;
   const TD* X = static_cast<const TD*>(op.data);
   const int64_t m = op.rows, n = op.n;
   constexpr int E = Vec16<TD>::E;
@@ -309,9 +329,11 @@ nys_status xtx_partials(const OpDesc& op, const TA* p, TA* scratch, size_t scrat
     NYS_CHECK_LAUNCH();
     timing_mark_end(s);
     *ng_out = (int)ng2;
+    // the two-pass form does not produce the p^T A p parts (*pvq_filled stays false)
     return NYS_OK;
   }
-#define LX(VP_, NV, RR) hipLaunchKernelGGL((xtx_fused<TD, TA, VP_, NV, RR>), dim3((unsigned)ng), dim3(256), 0, s, X, m, n, op.ld, p, scratch, rpw, op.skip, op.w)
+  if (pvq && pvq_filled) *pvq_filled = true;
+#define LX(VP_, NV, RR) hipLaunchKernelGGL((xtx_fused<TD, TA, VP_, NV, RR>), dim3((unsigned)ng), dim3(256), 0, s, X, m, n, op.ld, p, scratch, rpw, op.skip, op.w, pvq_filled ? pvq : nullptr)
   timing_mark_begin(s);
   if (vec) {
     if (need_nv <= 1) LX(Vec16<TD>, 1, 4);
@@ -344,10 +366,14 @@ nys_status xtx_apply(const OpDesc& op, const TA* p, TA mu, TA* v, TA* scratch,
 }
 
 
-template nys_status xtx_partials<float, float>(const OpDesc&, const float*, float*, size_t, int*, hipStream_t);
-template nys_status xtx_partials<float, double>(const OpDesc&, const double*, double*, size_t, int*, hipStream_t);
-template nys_status xtx_partials<double, float>(const OpDesc&, const float*, float*, size_t, int*, hipStream_t);
-template nys_status xtx_partials<double, double>(const OpDesc&, const double*, double*, size_t, int*, hipStream_t);
+template nys_status xtx_partials<float, float>(const OpDesc&, const float*, float*, size_t, int*, hipStream_t,
+                                               double*, bool*);
+template nys_status xtx_partials<float, double>(const OpDesc&, const double*, double*, size_t, int*, hipStream_t,
+                                                double*, bool*);
+template nys_status xtx_partials<double, float>(const OpDesc&, const float*, float*, size_t, int*, hipStream_t,
+                                                double*, bool*);
+template nys_status xtx_partials<double, double>(const OpDesc&, const double*, double*, size_t, int*, hipStream_t,
+                                                 double*, bool*);
 template nys_status xtx_apply<float, float>(const OpDesc&, const float*, float, float*, float*, size_t, hipStream_t);
 template nys_status xtx_apply<float, double>(const OpDesc&, const double*, double, double*, double*, size_t,
                                              hipStream_t);
