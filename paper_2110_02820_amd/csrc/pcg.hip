@@ -1224,6 +1224,9 @@ __global__ void pcg_snapshot_kernel(CgScalars sc, PcgSnap* out, int seq) {
 }
 
 constexpr int64_t kFuseMaxN = 16384;
+#ifndef NYS_FINX_BLOCKS
+#define NYS_FINX_BLOCKS 512
+#endif
 #ifndef NYS_FIN_FUSED_BLOCKS
 #define NYS_FIN_FUSED_BLOCKS 64  // matvec finish when it also updates x and r (n <= kFuseMaxN)
 #endif
@@ -1271,9 +1274,9 @@ nys_status pcg_iteration_xtx(int64_t n, const PrecDesc& P, const double* mu_dev,
     return NYS_ERR_ARG;
   }
   const int64_t l = P.ell;
-  // tiles of 32 entries over at most 64 workgroups (each also reads its
-  // tiles' rows of U for U^T r)
-  const int64_t nfb = cdiv(n, 32) < 64 ? cdiv(n, 32) : 64;
+  // tiles of 32 entries, one per workgroup up to NYS_FINX_BLOCKS (each also
+  // reads its tiles' rows of U for U^T r; nothing here waits on the others)
+  const int64_t nfb = cdiv(n, 32) < NYS_FINX_BLOCKS ? cdiv(n, 32) : NYS_FINX_BLOCKS;
   if (P.dtype == NYS_F64)
     hipLaunchKernelGGL((cg_finish_xtx<T, double>), dim3((unsigned)nfb), dim3(NT), 0, s, n, part, ng, pvq, scale, mu,
                        Pd, V, X, R, static_cast<const double*>(P.U), l, P.ldu, w.apart, w.prr, sc, par);
