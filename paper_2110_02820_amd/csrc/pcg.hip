@@ -510,7 +510,8 @@ __global__ __launch_bounds__(NT) void utr_final(int64_t l, int nch, const double
 // 4 x NJ loads per lane (columns lane + 64 jj, l <= 64 NJ) are issued together.
 // mode 0: plain apply; mode 1: also r^T z for the set-up; mode 2: r^T z,
 // beta and flags; mode 3: per-workgroup parts of r^T z only (cg_beta_direction
-// finishes them).
+// finishes them); mode 4 (uc_vec only): r^T z from utr_final_rr's parts, beta
+// and the direction update on each wave's own rows.
 template <typename TU, typename T, int NJ>
 __global__ __launch_bounds__(NT) void uc_rz(int64_t n, int64_t l, const TU* __restrict__ U, int64_t ldu,
                                             const double* __restrict__ Cs, const T* __restrict__ r,
@@ -774,10 +775,12 @@ __global__ __launch_bounds__(NT) void cg_finish_xtx(int64_t n, const T* __restri
 
 // utr_final plus, in workgroup 0, the stopping test of the update that
 // cg_finish_xtx made: ||r||^2 from its per-workgroup parts (fixed order).
+// rzq[b] (b < gridDim.x) receives workgroup b's part of w^T D w and
+// rzq[gridDim.x] = ||r||^2, from which uc_vec's mode 4 forms r^T z.
 __global__ __launch_bounds__(NT) void utr_final_rr(int64_t l, int nch, const double* __restrict__ part,
                                                    const double* __restrict__ lam, const double* __restrict__ mu,
                                                    double* __restrict__ Cs, const double* __restrict__ prr, int nprr,
-                                                   CgScalars sc, double tol) {
+                                                   CgScalars sc, double tol, double* __restrict__ rzq) {
   const int skip_all = *sc.alldone;
   __shared__ double red[4][64];
   __shared__ double sh[NT];
@@ -798,15 +801,23 @@ __global__ __launch_bounds__(NT) void utr_final_rr(int64_t l, int nch, const dou
   if (skip_all) return;
   red[ty][tx] = acc;
   __syncthreads();
+  double wdw = 0.0;  // this column's w_j d_j w_j, w = U^T r (unscaled), d_j the apply's diagonal
   if (ty == 0 && j < l) {
     const double tot = (red[0][tx] + red[1][tx]) + (red[2][tx] + red[3][tx]);
     const double m = mu[0];
-    Cs[j] = ((lam[l - 1] + m) / (lam[j] + m) - 1.0) * tot;
+    const double cj = ((lam[l - 1] + m) / (lam[j] + m) - 1.0) * tot;
+    Cs[j] = cj;
+    wdw = cj * tot;
   }
+  // r^T z = ||r||^2 + w^T D w (z = r + U D w): this workgroup's part of the
+  // second term, and ||r||^2 from workgroup 0, for the apply that follows
+  wdw = block_sum(wdw, sh);
+  if (threadIdx.x == 0) rzq[blockIdx.x] = wdw;
   if (blockIdx.x != 0) return;
   double s = 0.0;
   for (int q = threadIdx.x; q < nprr; q += NT) s += prr[q];
   const double rr = block_sum(s, sh);
+  if (threadIdx.x == 0) rzq[gridDim.x] = rr;
   if (threadIdx.x == 0 && !sc.done[0]) {
     sc.rnorm2[0] = rr;
     sc.iters[0] += 1;
@@ -827,6 +838,30 @@ __global__ __launch_bounds__(NT) void uc_vec(int64_t n, int64_t l, const TU* __r
   typedef typename UVec<TU>::type VT;
   constexpr int E = UVec<TU>::E;
   const int skip_all = mode >= 2 ? *sc.alldone : 0;
+  // mode 4 (after utr_final_rr, whose cdiv(l, 64) workgroups left their parts
+  // of w^T D w in prz, then ||r||^2): r^T z and so beta are known before the
+  // apply, and each wave sets p = z + beta p on its own rows
+  T bz = T(0);
+  int dn = 0;
+  if (mode == 4) {
+    __shared__ double shq[NT / 64];
+    const int nq = (int)cdiv(l, 64);
+    double q = 0.0;
+    for (int i = threadIdx.x; i <= nq; i += NT) q += prz[i];
+    const double rzn = block_sum(q, shq);
+    const int done_old = sc.done[0];
+    dn = done_old || sc.conv[0];
+    const double beta = done_old ? 0.0 : rzn / sc.rz[par];
+    bz = T(beta);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      if (!done_old) {
+        sc.beta[0] = beta;
+        sc.rz[1 - par] = rzn;
+        sc.done[0] = dn;
+      }
+      *sc.alldone = dn;  // also after a breakdown flagged earlier in the iteration
+    }
+  }
   __shared__ double sh[NT];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   T cs[NG][E];
@@ -880,6 +915,7 @@ __global__ __launch_bounds__(NT) void uc_vec(int64_t n, int64_t l, const TU* __r
       const T zi = rv[myq] + c;
       z[ib + myq] = zi;
       rzp += double(rv[myq]) * double(zi);
+      if (mode == 4 && !dn) Pd[ib + myq] = zi + bz * Pd[ib + myq];
     }
   };
   int64_t ib = w0;
@@ -892,7 +928,7 @@ __global__ __launch_bounds__(NT) void uc_vec(int64_t n, int64_t l, const TU* __r
     finish(ub, rb, ib + 4);
   }
   if (ib < w1) finish(ua, ra, ib);
-  if (mode == 0 || skip_all) return;
+  if (mode == 0 || mode == 4 || skip_all) return;
   // lanes 0, 16, 32 and 48 hold the rows' parts of r^T z
   const double tot = block_sum(rzp, sh);
   if (threadIdx.x == 0) prz[blockIdx.x] = tot;
@@ -1285,9 +1321,11 @@ nys_status pcg_iteration_xtx(int64_t n, const PrecDesc& P, const double* mu_dev,
                        Pd, V, X, R, static_cast<const float*>(P.U), l, P.ldu, w.apart, w.prr, sc, par);
   NYS_CHECK_LAUNCH();
   hipLaunchKernelGGL(utr_final_rr, dim3((unsigned)cdiv(l, 64)), dim3(NT), 0, s, l, (int)nfb, w.apart, P.lam, mu_dev,
-                     w.Cs, w.prr, (int)nfb, sc, tol);
+                     w.Cs, w.prr, (int)nfb, sc, tol, w.prz);
   NYS_CHECK_LAUNCH();
-  return uc_launch(P, w.Cs, R, Z, f32, w.prz, sc, par, 2, s, Pd);
+  // r^T z from utr_final_rr's parts: the apply also sets the direction, with
+  // no workgroup waiting for another
+  return uc_launch(P, w.Cs, R, Z, f32, w.prz, sc, par, 4, s, Pd);
 }
 
 template <typename T>
