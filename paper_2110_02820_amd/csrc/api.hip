@@ -310,7 +310,7 @@ void carve_pcg(Arena& a, const OpDesc& op, int64_t l, int64_t k, PcgBufs<T>& b) 
   b.cmap = a.take<int>(k);
   b.w.pb = a.take<double>(kMaxGroups * k);
   b.w.prr = a.take<double>(kMaxGroups * k);
-  b.w.ppv = a.take<double>(kMaxGroups * k);
+  b.w.ppv = a.take<double>(std::max<int64_t>(kMaxGroups * k, kPvqMax + 1));
   b.w.prz = a.take<double>(kMaxGroups * k);
   b.w.apart_elems = precond_part_elems(n, l, k);
   b.w.apart = a.take<double>(b.w.apart_elems);
@@ -786,24 +786,21 @@ nys_status pcg_run(const OpDesc& op0, const PrecDesc& P, int64_t k, const double
   bool tune = check_every <= 0;
   const auto t_start = std::chrono::steady_clock::now();
   int last_poll = 0;
-  const bool xtx_path = op.kind == NYS_OP_XTX && pcg_xtx_ok(P, n);
+  // p^T A p from the product itself: X^T X, and square RBF products in float64
+  const bool pvq_path = (op.kind == NYS_OP_XTX || (op.kind == NYS_OP_RBF && sizeof(T) == 8)) && pcg_pvq_ok(P, n);
   // one iteration on the current kc columns
   auto step = [&]() -> nys_status {
     const int par = it & 1;
     // single column with a partial-sum operator product: fused iteration
     const bool fused = kc == 1 && (op.kind == NYS_OP_XTX ||
                                    (op.kind == NYS_OP_RBF && (sizeof(T) == 8 || op.lowp != nullptr)));
-    if (fused && xtx_path) {
-      // X^T X: the product also gives p^T A p, so alpha needs no summed product
-      int ng = 0;
-      bool filled = false;
-      if (op.dtype == NYS_F64)
-        NYS_TRY((xtx_partials<double, T>(op, b.P, b.opscr, b.opscr_elems, &ng, s, b.w.ppv, &filled)));
-      else
-        NYS_TRY((xtx_partials<float, T>(op, b.P, b.opscr, b.opscr_elems, &ng, s, b.w.ppv, &filled)));
-      if (filled)
-        NYS_TRY(pcg_iteration_xtx<T>(n, P, b.mu, mu_host[map[0]], b.opscr, ng, b.w.ppv, op.scale, b.V, Xc, b.R,
-                                     b.Z, b.P, b.w, b.sc, par, tol, s));
+    if (fused && pvq_path) {
+      // the product also gives its p^T A p parts, so alpha needs no summed product
+      int ng = 0, npvq = 0;
+      NYS_TRY(op_matvec_partials<T>(op, b.P, b.opscr, b.opscr_elems, &ng, s, b.w.ppv, &npvq));
+      if (npvq > 0)
+        NYS_TRY(pcg_iteration_pvq<T>(n, P, b.mu, mu_host[map[0]], b.opscr, ng, b.w.ppv, npvq, op.scale, b.V, Xc,
+                                     b.R, b.Z, b.P, b.w, b.sc, par, tol, s));
       else
         NYS_TRY(pcg_iteration_fused<T>(n, P, b.mu, mu_host[map[0]], b.opscr, ng, op.scale, b.V, Xc, b.R, b.Z,
                                        b.P, b.w, b.sc, par, tol, s));

@@ -80,7 +80,7 @@ __global__ __launch_bounds__(256) void rbf_mv_f64m(const TD* __restrict__ Xr, in
                                                    const TD* __restrict__ Xc, int64_t nc, int64_t ldc, int d,
                                                    double c2, double inv_s3, const double* __restrict__ p,
                                                    double* __restrict__ part, int64_t pts_per_split,
-                                                   const int* __restrict__ skip) {
+                                                   const int* __restrict__ skip, double* __restrict__ pvq) {
   if (skip && *skip) return;
   constexpr int DW = 4 * KS;
   __shared__ double Xs[RB_PTS][DW + 1];
@@ -152,12 +152,30 @@ __global__ __launch_bounds__(256) void rbf_mv_f64m(const TD* __restrict__ Xr, in
     }
   }
   // rows 4 q + l / 16: add the 16 lanes (points) of each group in a fixed tree
+  double pq = 0.0;
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     double v = acc[q] - cmp[q];
     for (int o = 1; o < 16; o <<= 1) v += __shfl_xor(v, o, 64);
     const int64_t row = i0 + 4 * q + (lane >> 4);
-    if ((lane & 15) == 0 && row < nr) part[(int64_t)blockIdx.y * nr + row] = v;
+    if ((lane & 15) == 0 && row < nr) {
+      part[(int64_t)blockIdx.y * nr + row] = v;
+      if (pvq) pq += p[row] * v;
+    }
+  }
+  if (pvq) {
+    // square operator (Xr = Xc): this workgroup's part of p^T W p, and ||p||^2
+    // from workgroup (0, 0), so that a CG step knows p^T A p before the
+    // partials are summed
+    __shared__ double shq[4];
+    pq = block_sum(pq, shq);
+    if (t == 0) pvq[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = pq;
+    if (blockIdx.x == 0 && blockIdx.y == 0) {
+      double q2 = 0.0;
+      for (int64_t j = t; j < nc; j += 256) q2 += p[j] * p[j];
+      q2 = block_sum(q2, shq);
+      if (t == 0) pvq[(int64_t)gridDim.x * gridDim.y] = q2;
+    }
   }
 }
 
@@ -165,8 +183,8 @@ __global__ __launch_bounds__(256) void rbf_mv_f64m(const TD* __restrict__ Xr, in
 template <typename TD, int MODE>
 void launch_rbf_mv_f64(dim3 grid, hipStream_t s, const TD* Xr, int64_t nr, int64_t ldr, const TD* Xc,
                        int64_t nc, int64_t ldc, int d, double c2, double is3, const double* p,
-                       double* part, int64_t pps, const int* skip) {
-#define LM(KS) hipLaunchKernelGGL((rbf_mv_f64m<TD, KS, MODE>), grid, dim3(256), 0, s, Xr, nr, ldr, Xc, nc, ldc, d, c2, is3, p, part, pps, skip)
+                       double* part, int64_t pps, const int* skip, double* pvq = nullptr) {
+#define LM(KS) hipLaunchKernelGGL((rbf_mv_f64m<TD, KS, MODE>), grid, dim3(256), 0, s, Xr, nr, ldr, Xc, nc, ldc, d, c2, is3, p, part, pps, skip, pvq)
   if (d <= 4) LM(1);
   else if (d <= 8) LM(2);
   else if (d <= 16) LM(4);
@@ -570,17 +588,20 @@ nys_status op_matvec(const OpDesc& op, const TA* p, TA mu, TA* v, TA* scratch, s
 // Single vector in partial-sum form: (A p)[j] = scale * sum_{g < ng} part[g][j].
 template <typename TA>
 nys_status op_matvec_partials(const OpDesc& op, const TA* p, TA* part, size_t part_elems, int* ng_out,
-                              hipStream_t s);
+                              hipStream_t s, double* pvq, int* npvq);
 
 template <>
 nys_status op_matvec_partials<double>(const OpDesc& op, const double* p, double* part, size_t part_elems,
-                                      int* ng_out, hipStream_t s) {
+                                      int* ng_out, hipStream_t s, double* pvq, int* npvq) {
   const int64_t n = op.n;
+  if (npvq) *npvq = 0;
   if (op.kind == NYS_OP_XTX) {
-    const int64_t m = op.rows;
-    if (op.dtype == NYS_F64) return xtx_partials<double, double>(op, p, part, part_elems, ng_out, s);
-    return xtx_partials<float, double>(op, p, part, part_elems, ng_out, s);
-    (void)m;
+    bool filled = false;
+    nys_status st = op.dtype == NYS_F64
+                        ? xtx_partials<double, double>(op, p, part, part_elems, ng_out, s, pvq, npvq ? &filled : nullptr)
+                        : xtx_partials<float, double>(op, p, part, part_elems, ng_out, s, pvq, npvq ? &filled : nullptr);
+    if (st == NYS_OK && filled) *npvq = *ng_out;
+    return st;
   }
   if (op.kind == NYS_OP_RBF) {
     const int d = (int)op.cols;
@@ -594,18 +615,24 @@ nys_status op_matvec_partials<double>(const OpDesc& op, const double* p, double*
     int64_t ns = cdiv(4 * (num_cus() < 256 ? num_cus() : 256), nrb);
     if (ns < 1) ns = 1;
     while (ns > 1 && (size_t)(ns * n) > part_elems) --ns;
+    // p^T K p parts, one per workgroup, when they fit the caller's kPvqMax slots
+    const bool want_pvq = pvq && npvq && nrb + 1 <= kPvqMax;
+    if (want_pvq)
+      while (ns > 1 && nrb * ns + 1 > kPvqMax) --ns;
     const int64_t pps = cdiv(cdiv(n, ns), RB_PTS) * RB_PTS;
     ns = cdiv(n, pps);
     dim3 grid((unsigned)nrb, (unsigned)ns);
+    double* pq = want_pvq ? pvq : nullptr;
     if (op.dtype == NYS_F64) {
       const double* X = static_cast<const double*>(op.data);
-      launch_rbf_mv_f64<double, 0>(grid, s, X, n, op.ld, X, n, op.ld, d, c2, 0.0, p, part, pps, op.skip);
+      launch_rbf_mv_f64<double, 0>(grid, s, X, n, op.ld, X, n, op.ld, d, c2, 0.0, p, part, pps, op.skip, pq);
     } else {
       const float* X = static_cast<const float*>(op.data);
-      launch_rbf_mv_f64<float, 0>(grid, s, X, n, op.ld, X, n, op.ld, d, c2, 0.0, p, part, pps, op.skip);
+      launch_rbf_mv_f64<float, 0>(grid, s, X, n, op.ld, X, n, op.ld, d, c2, 0.0, p, part, pps, op.skip, pq);
     }
     NYS_CHECK_LAUNCH();
     *ng_out = (int)ns;
+    if (want_pvq) *npvq = (int)(nrb * ns);
     return NYS_OK;
   }
   set_error("op_matvec_partials: operator has no partial form");
@@ -614,12 +641,17 @@ nys_status op_matvec_partials<double>(const OpDesc& op, const double* p, double*
 
 template <>
 nys_status op_matvec_partials<float>(const OpDesc& op, const float* p, float* part, size_t part_elems,
-                                     int* ng_out, hipStream_t s) {
+                                     int* ng_out, hipStream_t s, double* pvq, int* npvq) {
+  if (npvq) *npvq = 0;
   if (op.kind == NYS_OP_RBF && op.lowp)
     return rbf_lowp_mv_partials(*op.lowp, op.gram, p, part, part_elems, ng_out, op.skip, s);
   if (op.kind == NYS_OP_XTX) {
-    if (op.dtype == NYS_F64) return xtx_partials<double, float>(op, p, part, part_elems, ng_out, s);
-    return xtx_partials<float, float>(op, p, part, part_elems, ng_out, s);
+    bool filled = false;
+    nys_status st = op.dtype == NYS_F64
+                        ? xtx_partials<double, float>(op, p, part, part_elems, ng_out, s, pvq, npvq ? &filled : nullptr)
+                        : xtx_partials<float, float>(op, p, part, part_elems, ng_out, s, pvq, npvq ? &filled : nullptr);
+    if (st == NYS_OK && filled) *npvq = *ng_out;
+    return st;
   }
   set_error("op_matvec_partials: float32 form needs X^T X or a prepared RBF operator");
   return NYS_ERR_ARG;

@@ -657,17 +657,18 @@ __global__ __launch_bounds__(NT) void utr_vec(int64_t n, int64_t l, const TU* __
   (void)ok;
 }
 
-// k = 1, X^T X operator, after a product that also gave pvq (see
-// xtx_partials): p^T (A + mu I) p = scale sum_g pvq[g] + mu ||p||^2, summed
-// by every workgroup in the same fixed order, so each knows alpha at once and
-// no workgroup hands it to another.  Tiles of 32 entries: v_j from the ng
+// k = 1, after a product that also gave pvq (see op_matvec_partials: X^T X,
+// or a square RBF operator): p^T (A + mu I) p = scale sum_g pvq[g] + mu ||p||^2
+// (g < npvq, ||p||^2 at pvq[npvq]), summed by every workgroup in the same
+// fixed order, so each knows alpha at once and no workgroup hands it to another.  Tiles of 32 entries: v_j from the ng
 // partials (8 slices of 32 columns, as cg_finish_mv), x_j += alpha p_j,
 // r_j -= alpha v_j, a part of ||r||^2, and this workgroup's part of U^T r over
 // the tile's rows of U (thread t owns the 16-byte vectors t, t + NT of a row;
 // float64 accumulation).  Workgroup 0 records alpha and a breakdown.
 template <typename T, typename TU>
-__global__ __launch_bounds__(NT) void cg_finish_xtx(int64_t n, const T* __restrict__ part, int ng,
-                                                    const double* __restrict__ pvq, double scale, double mu,
+__global__ __launch_bounds__(NT) void cg_finish_pvq(int64_t n, const T* __restrict__ part, int ng,
+                                                    const double* __restrict__ pvq, int npvq, double scale,
+                                                    double mu,
                                                     const T* __restrict__ P, T* __restrict__ V, T* __restrict__ X,
                                                     T* __restrict__ R, const TU* __restrict__ U, int64_t l,
                                                     int64_t ldu, double* __restrict__ apart,
@@ -680,8 +681,8 @@ __global__ __launch_bounds__(NT) void cg_finish_xtx(int64_t n, const T* __restri
   __shared__ double sh[NT];
   __shared__ double rs[32];
   double q = 0.0;
-  for (int g = threadIdx.x; g < ng; g += NT) q += pvq[g];
-  const double pv = scale * block_sum(q, sh) + mu * pvq[ng];
+  for (int g = threadIdx.x; g < npvq; g += NT) q += pvq[g];
+  const double pv = scale * block_sum(q, sh) + mu * pvq[npvq];
   if (skip_all) return;  // the same value for every thread
   const int done = sc.done[0];
   const double a_d = (done || !(pv > 0.0)) ? 0.0 : sc.rz[par] / pv;
@@ -774,7 +775,7 @@ __global__ __launch_bounds__(NT) void cg_finish_xtx(int64_t n, const T* __restri
 }
 
 // utr_final plus, in workgroup 0, the stopping test of the update that
-// cg_finish_xtx made: ||r||^2 from its per-workgroup parts (fixed order).
+// cg_finish_pvq made: ||r||^2 from its per-workgroup parts (fixed order).
 // rzq[b] (b < gridDim.x) receives workgroup b's part of w^T D w and
 // rzq[gridDim.x] = ||r||^2, from which uc_vec's mode 4 forms r^T z.
 __global__ __launch_bounds__(NT) void utr_final_rr(int64_t l, int nch, const double* __restrict__ part,
@@ -1296,17 +1297,17 @@ nys_status pcg_iteration_fused(int64_t n, const PrecDesc& P, const double* mu_de
   return beta_direction_launch<T>(n, Z, Pd, w, sc, par, s);
 }
 
-bool pcg_xtx_ok(const PrecDesc& P, int64_t n) {
+bool pcg_pvq_ok(const PrecDesc& P, int64_t n) {
   return n <= kFuseMaxN && (P.dtype == NYS_F64 ? uvec_ok<double>(P) : uvec_ok<float>(P));
 }
 
 template <typename T>
-nys_status pcg_iteration_xtx(int64_t n, const PrecDesc& P, const double* mu_dev, double mu, const T* part, int ng,
-                             const double* pvq, double scale, T* V, T* X, T* R, T* Z, T* Pd, PcgWork& w,
+nys_status pcg_iteration_pvq(int64_t n, const PrecDesc& P, const double* mu_dev, double mu, const T* part, int ng,
+                             const double* pvq, int npvq, double scale, T* V, T* X, T* R, T* Z, T* Pd, PcgWork& w,
                              const CgScalars& sc, int par, double tol, hipStream_t s) {
   const bool f32 = sizeof(T) == 4;
-  if (!pcg_xtx_ok(P, n)) {
-    set_error("pcg_iteration_xtx: needs n <= %lld and a 16-byte U layout", (long long)kFuseMaxN);
+  if (!pcg_pvq_ok(P, n)) {
+    set_error("pcg_iteration_pvq: needs n <= %lld and a 16-byte U layout", (long long)kFuseMaxN);
     return NYS_ERR_ARG;
   }
   const int64_t l = P.ell;
@@ -1314,10 +1315,10 @@ nys_status pcg_iteration_xtx(int64_t n, const PrecDesc& P, const double* mu_dev,
   // reads its tiles' rows of U for U^T r; nothing here waits on the others)
   const int64_t nfb = cdiv(n, 32) < NYS_FINX_BLOCKS ? cdiv(n, 32) : NYS_FINX_BLOCKS;
   if (P.dtype == NYS_F64)
-    hipLaunchKernelGGL((cg_finish_xtx<T, double>), dim3((unsigned)nfb), dim3(NT), 0, s, n, part, ng, pvq, scale, mu,
+    hipLaunchKernelGGL((cg_finish_pvq<T, double>), dim3((unsigned)nfb), dim3(NT), 0, s, n, part, ng, pvq, npvq, scale, mu,
                        Pd, V, X, R, static_cast<const double*>(P.U), l, P.ldu, w.apart, w.prr, sc, par);
   else
-    hipLaunchKernelGGL((cg_finish_xtx<T, float>), dim3((unsigned)nfb), dim3(NT), 0, s, n, part, ng, pvq, scale, mu,
+    hipLaunchKernelGGL((cg_finish_pvq<T, float>), dim3((unsigned)nfb), dim3(NT), 0, s, n, part, ng, pvq, npvq, scale, mu,
                        Pd, V, X, R, static_cast<const float*>(P.U), l, P.ldu, w.apart, w.prr, sc, par);
   NYS_CHECK_LAUNCH();
   hipLaunchKernelGGL(utr_final_rr, dim3((unsigned)cdiv(l, 64)), dim3(NT), 0, s, l, (int)nfb, w.apart, P.lam, mu_dev,
@@ -1377,12 +1378,12 @@ template nys_status cg_block_direction<float>(int64_t, int64_t, const float*, co
 template nys_status cg_block_direction<double>(int64_t, int64_t, const double*, const double*, double*,
                                                PcgWork&, const CgScalars&, int, bool, hipStream_t);
 
-template nys_status pcg_iteration_xtx<double>(int64_t, const PrecDesc&, const double*, double, const double*, int,
-                                              const double*, double, double*, double*, double*, double*, double*,
+template nys_status pcg_iteration_pvq<double>(int64_t, const PrecDesc&, const double*, double, const double*, int,
+                                              const double*, int, double, double*, double*, double*, double*, double*,
                                               PcgWork&, const CgScalars&, int, double, hipStream_t);
-template nys_status pcg_iteration_xtx<float>(int64_t, const PrecDesc&, const double*, double, const float*, int,
-                                             const double*, double, float*, float*, float*, float*, float*, PcgWork&,
-                                             const CgScalars&, int, double, hipStream_t);
+template nys_status pcg_iteration_pvq<float>(int64_t, const PrecDesc&, const double*, double, const float*, int,
+                                             const double*, int, double, float*, float*, float*, float*, float*,
+                                             PcgWork&, const CgScalars&, int, double, hipStream_t);
 template nys_status pcg_iteration_fused<double>(int64_t, const PrecDesc&, const double*, double, const double*, int,
                                                 double, double*, double*, double*, double*, double*, PcgWork&,
                                                 const CgScalars&, int, double, hipStream_t);

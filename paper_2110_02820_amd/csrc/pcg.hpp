@@ -64,18 +64,19 @@ nys_status pcg_iteration_fused(int64_t n, const PrecDesc& P, const double* mu_de
                                int ng, double scale, T* V, T* X, T* R, T* Z, T* Pd, PcgWork& w,
                                const CgScalars& sc, int par, double tol, hipStream_t s);
 
-// pcg_iteration_fused for the X^T X operator when its one-pass product also
-// gave pvq (per-workgroup parts of p^T X^T D X p and ||p||^2, see
-// xtx_partials): alpha is known before the partials are summed, so one
-// launch sums them, updates x and r and forms this launch's parts of U^T r;
-// then the scaling of U^T r (with the stopping test) and the apply.
-// Requires the 16-byte U layout of uvec_ok; returns NYS_ERR_ARG otherwise.
+// pcg_iteration_fused for a product that also gave pvq (op_matvec_partials:
+// npvq parts of p^T A p / scale and ||p||^2): alpha is known before the
+// partials are summed, so one launch sums them, updates x and r and forms
+// this launch's parts of U^T r; then the scaling of U^T r (with the stopping
+// test and the parts of r^T z = ||r||^2 + w^T D w) and the apply with the
+// direction update.  Requires pcg_pvq_ok; returns NYS_ERR_ARG otherwise.
 template <typename T>
-nys_status pcg_iteration_xtx(int64_t n, const PrecDesc& P, const double* mu_dev, double mu, const T* part, int ng,
-                             const double* pvq, double scale, T* V, T* X, T* R, T* Z, T* Pd, PcgWork& w,
-                             const CgScalars& sc, int par, double tol, hipStream_t s);
-// whether pcg_iteration_xtx supports this preconditioner's U layout
-bool pcg_xtx_ok(const PrecDesc& P, int64_t n);
+nys_status pcg_iteration_pvq(int64_t n, const PrecDesc& P, const double* mu_dev, double mu, const T* part, int ng,
+                             const double* pvq, int npvq, double scale, T* V, T* X, T* R, T* Z, T* Pd,
+                             PcgWork& w, const CgScalars& sc, int par, double tol, hipStream_t s);
+// whether pcg_iteration_pvq supports this size and U layout (n <= 16384,
+// 16-byte U rows)
+bool pcg_pvq_ok(const PrecDesc& P, int64_t n);
 
 // State of column 0 after a batch of iterations, written by the device into
 // host memory (pcg_snapshot) for host loops that poll without synchronising.
