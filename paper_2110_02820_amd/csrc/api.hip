@@ -416,6 +416,20 @@ __global__ void zero_fill(T* __restrict__ p, int64_t count) {
   if (i < count) p[i] = T(0);
 }
 
+// PCG set-up in one launch: mu (k values) into the run's buffer, the 64
+// counters cleared, and, for a zero initial guess, X and V (n k each) cleared.
+template <typename T>
+__global__ void pcg_start(const double* __restrict__ mu_src, double* __restrict__ mu_dst, int64_t k,
+                          unsigned* __restrict__ ctr, T* __restrict__ X, T* __restrict__ V, int64_t nk) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < k) mu_dst[i] = mu_src[i];
+  if (i < 64) ctr[i] = 0u;
+  if (X && i < nk) {
+    X[i] = T(0);
+    V[i] = T(0);
+  }
+}
+
 template <typename TS>
 __global__ void add_to(double* __restrict__ dst, const TS* __restrict__ src, int64_t count) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -727,15 +741,11 @@ nys_status pcg_run(const OpDesc& op0, const PrecDesc& P, int64_t k, const double
   const int64_t n = op0.n;
   OpDesc op = op0;
   op.skip = nullptr;
-  hipLaunchKernelGGL(copy_dev<double>, dim3(nblk(k)), dim3(256), 0, s, mu_dev, b.mu, k);
+  const int64_t cover = std::max<int64_t>(std::max<int64_t>(k, 64), x0_zero ? n * k : 0);
+  hipLaunchKernelGGL(pcg_start<T>, dim3(nblk(cover)), dim3(256), 0, s, mu_dev, b.mu, k, b.sc.ctr,
+                     x0_zero ? X : (T*)nullptr, b.V, n * k);
   NYS_CHECK_LAUNCH();
-  NYS_TRY(zero<unsigned>(b.sc.ctr, 64, s));
-  if (x0_zero) {
-    NYS_TRY(zero<T>(X, n * k, s));
-    NYS_TRY(zero<T>(b.V, n * k, s));
-  } else {
-    NYS_TRY(matvec<T>(op, X, k, b.mu, 1, mu_host[0], b.V, b, s));
-  }
+  if (!x0_zero) NYS_TRY(matvec<T>(op, X, k, b.mu, 1, mu_host[0], b.V, b, s));
   NYS_TRY(pcg_setup<T>(n, k, P, b.mu, 1, B, b.V, b.R, b.Z, b.P, b.w, b.sc, tol, s));
   op.skip = b.sc.alldone;
   // device-info form (no compaction): block products skip column blocks whose
@@ -796,11 +806,11 @@ nys_status pcg_run(const OpDesc& op0, const PrecDesc& P, int64_t k, const double
                                    (op.kind == NYS_OP_RBF && (sizeof(T) == 8 || op.lowp != nullptr)));
     if (fused && pvq_path) {
       // the product also gives its p^T A p parts, so alpha needs no summed product
-      int ng = 0, npvq = 0;
-      NYS_TRY(op_matvec_partials<T>(op, b.P, b.opscr, b.opscr_elems, &ng, s, b.w.ppv, &npvq));
+      int ng = 0, npvq = 0, npp = 0;
+      NYS_TRY(op_matvec_partials<T>(op, b.P, b.opscr, b.opscr_elems, &ng, s, b.w.ppv, &npvq, &npp));
       if (npvq > 0)
-        NYS_TRY(pcg_iteration_pvq<T>(n, P, b.mu, mu_host[map[0]], b.opscr, ng, b.w.ppv, npvq, op.scale, b.V, Xc,
-                                     b.R, b.Z, b.P, b.w, b.sc, par, tol, s));
+        NYS_TRY(pcg_iteration_pvq<T>(n, P, b.mu, mu_host[map[0]], b.opscr, ng, b.w.ppv, npvq, npp, op.scale, b.V,
+                                     Xc, b.R, b.Z, b.P, b.w, b.sc, par, tol, s));
       else
         NYS_TRY(pcg_iteration_fused<T>(n, P, b.mu, mu_host[map[0]], b.opscr, ng, op.scale, b.V, Xc, b.R, b.Z,
                                        b.P, b.w, b.sc, par, tol, s));
@@ -1204,17 +1214,26 @@ nys_status solve_impl(const OpDesc& op, const PrecDesc& P, const double* mu, int
       prev = relres;
       const int64_t ka = (int64_t)act.size();
       if (ka == 0) break;
-      NYS_TRY(upload_indices(w.omap, act, s));
-      hipLaunchKernelGGL((gather_idx<double, float>), dim3(nblk(n * ka)), dim3(256), 0, s, n, k, w.R64, w.omap,
-                         ka, w.f.B);
-      hipLaunchKernelGGL((gather_idx<double, double>), dim3(1), dim3(256), 0, s, (int64_t)1, k, w.mu, w.omap, ka,
-                         w.mu_act);
-      NYS_CHECK_LAUNCH();
       PcgResult r;
-      NYS_TRY(pcg_run<float>(opf, P, ka, w.mu_act, mu_act, w.f.B, w.f.X, true, itol, maxit, check, w.f, r, s));
-      hipLaunchKernelGGL((scatter_idx<float, true>), dim3(nblk(n * ka)), dim3(256), 0, s, n, ka, w.f.X, w.omap, k,
-                         w.X64);
-      NYS_CHECK_LAUNCH();
+      if (ka == k) {  // every column: no index map
+        hipLaunchKernelGGL((gather_cols<double, float>), dim3(nblk(n * k)), dim3(256), 0, s, n, k, w.R64, k, k,
+                           w.f.B, k);
+        NYS_CHECK_LAUNCH();
+        NYS_TRY(pcg_run<float>(opf, P, k, w.mu, mu_act, w.f.B, w.f.X, true, itol, maxit, check, w.f, r, s));
+        hipLaunchKernelGGL(add_to<float>, dim3(nblk(n * k)), dim3(256), 0, s, w.X64, w.f.X, n * k);
+        NYS_CHECK_LAUNCH();
+      } else {
+        NYS_TRY(upload_indices(w.omap, act, s));
+        hipLaunchKernelGGL((gather_idx<double, float>), dim3(nblk(n * ka)), dim3(256), 0, s, n, k, w.R64, w.omap,
+                           ka, w.f.B);
+        hipLaunchKernelGGL((gather_idx<double, double>), dim3(1), dim3(256), 0, s, (int64_t)1, k, w.mu, w.omap,
+                           ka, w.mu_act);
+        NYS_CHECK_LAUNCH();
+        NYS_TRY(pcg_run<float>(opf, P, ka, w.mu_act, mu_act, w.f.B, w.f.X, true, itol, maxit, check, w.f, r, s));
+        hipLaunchKernelGGL((scatter_idx<float, true>), dim3(nblk(n * ka)), dim3(256), 0, s, n, ka, w.f.X, w.omap,
+                           k, w.X64);
+        NYS_CHECK_LAUNCH();
+      }
       for (int64_t j = 0; j < ka; ++j) {
         iters[act[j]] += r.iters[j];
         if (r.status[j] == NYS_ERR_BREAKDOWN) status[act[j]] = NYS_ERR_BREAKDOWN;
@@ -1275,12 +1294,18 @@ nys_status check_solve_common(const OpDesc& op, const PrecDesc& P, const double*
       NYS_ARG(op.cols <= 32, "reduced-precision RBF modes need d <= 32");
     return NYS_OK;
   }
-  double lam_l = 0.0;
-  NYS_HIP(hipMemcpyAsync(&lam_l, P.lam + (P.ell - 1), sizeof(double), hipMemcpyDeviceToHost, s));
-  NYS_HIP(hipStreamSynchronize(s));
+  bool any_zero = false;
   for (int64_t i = 0; i < nmu; ++i) {
     NYS_ARG(std::isfinite(mu[i]) && mu[i] >= 0.0, "mu[%lld] must be finite and >= 0", (long long)i);
-    NYS_ARG(lam_l + mu[i] > 0.0, "lam_l + mu must be > 0 (mu = 0 needs a positive lam_l)");
+    any_zero = any_zero || mu[i] == 0.0;
+  }
+  // lam >= 0 (the preconditioner's contract), so only mu = 0 needs lam_l
+  // itself, which costs a device round trip
+  if (any_zero) {
+    double lam_l = 0.0;
+    NYS_HIP(hipMemcpyAsync(&lam_l, P.lam + (P.ell - 1), sizeof(double), hipMemcpyDeviceToHost, s));
+    NYS_HIP(hipStreamSynchronize(s));
+    NYS_ARG(lam_l > 0.0, "lam_l + mu must be > 0 (mu = 0 needs a positive lam_l)");
   }
   if (o->prec != NYS_PREC_FP64 && op.kind == NYS_OP_RBF)
     NYS_ARG(op.cols <= 32, "reduced-precision RBF modes need d <= 32");

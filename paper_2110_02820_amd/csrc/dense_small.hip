@@ -14,6 +14,7 @@
 //     off-diagonal tiles on FP64 MFMA
 //   * descending sort of the eigenvalues and the scaled eigenvector matrix
 #include <cstdlib>
+#include <cstring>
 
 #include "dense_small.hpp"
 
@@ -102,74 +103,166 @@ struct CholArgs {
 // sub-diagonal blocks keep their Schur-complement values A[ib][kb] until one
 // last launch turns them all into L[ib][kb] = A[ib][kb] L_kk^{-T}.
 
-// Cholesky + inverse of one NB x NB diagonal block held in T (lower part,
-// identity outside the matrix): thread t works on row i = t mod NB and keeps
-// it in registers (left-looking: column j is A[i][j] - sum_{k<j} L[i][k]
-// L[j][k], row j read back from LDS as a broadcast); then it forms column i
-// of L^{-1} by forward substitution.  Threads t >= NB repeat threads t mod NB
-// and store nothing, so any block size that is a multiple of NB works.
-__device__ __forceinline__ void diag_factor(const CholArgs& a, int kb, double (*T)[NB + 1], double* Piv,
-                                            double* Ys) {
+// The 16 x 16 steps of diag_factor run on one wave, lane l holding row
+// l mod 16 of the block in registers (four copies of each row): in the
+// factorisation, entries of other rows come from v_readlane, so no LDS round
+// trip or barrier sits on the chain of dependent column steps.
+__device__ __forceinline__ double lane_bcast(double v, int lane) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), lane);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Right-looking Cholesky of the 16 x 16 block T[o..o+15][o..o+15] (lower part
+// read) into L (written back to T, zeros above the diagonal) and its inverse
+// into Li[o..o+15][o..o+15] (zeros above).  Column j: the pivot from lane j,
+// l_i = a_ij / sqrt(pivot), then a_ik -= l_i l_k for k > j.  A pivot that is
+// not positive and finite is replaced by 1 (recorded in *bad, the first one).
+// The inverse is forward substitution by columns: lane i forms column i,
+// x_m = (delta_mi - sum_{k<m} L_mk x_k) / L_mm, with the rows of L read back
+// from LDS.
+__device__ __forceinline__ void chol16(double (*T)[NB + 1], double (*Li)[NB + 1], int o, int& bad) {
+  const int lane = threadIdx.x & 63, i = lane & 15;
+  double r[16];
+#pragma unroll
+  for (int j = 0; j < 16; ++j) r[j] = (j <= i) ? T[o + i][o + j] : 0.0;
+  double ys[16];
+#pragma unroll
+  for (int j = 0; j < 16; ++j) {
+    double d = lane_bcast(r[j], j);
+    double y;
+    if (!(d > 0.0) || !isfinite(d)) {  // the same for every lane
+      if (bad < 0) bad = j;
+      d = 1.0;
+      y = 1.0;
+    } else {
+      y = frsq(d);
+    }
+    ys[j] = y;
+    const double l = (i > j) ? r[j] * y : (i == j ? d * y : 0.0);
+    r[j] = l;
+#pragma unroll
+    for (int k = j + 1; k < 16; ++k) r[k] -= l * lane_bcast(l, k);  // rows i < k: unused values
+  }
+  if (lane < 16) {
+#pragma unroll
+    for (int j = 0; j < 16; ++j) T[o + i][o + j] = (j <= i) ? r[j] : 0.0;
+  }
+  wave_lds_sync();
+  // rows of L as LDS broadcasts (every lane reads the same address)
+  double x[16];
+#pragma unroll
+  for (int m = 0; m < 16; ++m) {
+    double s0 = (m == i) ? 1.0 : 0.0, s1 = 0.0;
+#pragma unroll
+    for (int k = 0; k < m; k += 2) {
+      s0 -= T[o + m][o + k] * x[k];
+      if (k + 1 < m) s1 -= T[o + m][o + k + 1] * x[k + 1];
+    }
+    x[m] = (s0 + s1) * ys[m];
+  }
+  if (lane < 16) {
+#pragma unroll
+    for (int j = 0; j < 16; ++j) Li[o + j][o + i] = x[j];  // column i of the inverse (0 above the diagonal)
+  }
+}
+
+typedef double cd4 __attribute__((ext_vector_type(4)));
+
+// out = sgn * X Y (+ C) for 16 x 16 blocks on MFMA f64 (one wave): X[r][k]
+// = xm(r, k), Y[k][c] = ym(k, c); accumulator element q of lane l is
+// out[4 q + l / 16][l % 16].
+template <typename FX, typename FY>
+__device__ __forceinline__ cd4 mm16(FX xm, FY ym, cd4 acc) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int k0 = 0; k0 < 16; k0 += 4) {
+    const int kk = k0 + (lane >> 4);
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(xm(lane & 15, kk), ym(kk, lane & 15), acc, 0, 0, 0);
+  }
+  return acc;
+}
+
+// out = X Y (+ acc) for 32 x 32 blocks on MFMA f64, four waves: wave w
+// forms the 16 x 16 quadrant (w / 2, w % 2); X[r][k] = xm(r, k), Y[k][c] =
+// ym(k, c); accumulator element q of lane l is out[16 (w / 2) + 4 q + l / 16]
+// [16 (w % 2) + l % 16].
+template <typename FX, typename FY>
+__device__ __forceinline__ cd4 mm32q(FX xm, FY ym, cd4 acc) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int r = (wave >> 1) * 16 + (lane & 15), c = (wave & 1) * 16 + (lane & 15);
+#pragma unroll
+  for (int k0 = 0; k0 < NB; k0 += 4) {
+    const int kk = k0 + (lane >> 4);
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(xm(r, kk), ym(kk, c), acc, 0, 0, 0);
+  }
+  return acc;
+}
+
+// Cholesky + inverse of one NB x NB (= 32) diagonal block held in T (lower
+// part, identity outside the matrix), by one wave in two 16-column halves:
+// L11 = chol(A11), L21 = A21 L11^{-T}, L22 = chol(A22 - L21 L21^T), and
+// L^{-1} = [L11^{-1} 0; -L22^{-1} L21 L11^{-1}  L22^{-1}], the 16 x 16
+// products on MFMA.  Writes the factor block to L, the inverse to Dinv (kb),
+// the first bad pivot to info.  Li, Mb: LDS scratch (NB x NB + 1).  Only
+// wave 0 of the workgroup may call it, and no barrier is taken inside.
+__device__ __forceinline__ void diag_factor(const CholArgs& a, int kb, double (*T)[NB + 1], double (*Li)[NB + 1],
+                                            double (*Mb)[NB + 1]) {
   double* __restrict__ Lg = a.L;
   double* __restrict__ Dg = a.Dinv;
   const int64_t n = a.n;
   const int64_t base = (int64_t)kb * NB;
   const int nbk = (int)((n - base) < NB ? (n - base) : NB);
-  const int t = threadIdx.x;
-  const int i = t & (NB - 1);
-  const bool own = t < NB;
-  double r[NB];
+  const int lane = threadIdx.x & 63;
+  const int r16 = lane & 15, q4 = lane >> 4;
+  int bad = -1, bad2 = -1;
+  chol16(T, Li, 0, bad);
+  wave_lds_sync();
+  // L21 = A21 L11^{-T}
+  cd4 acc = mm16([&](int r, int k) { return T[16 + r][k]; }, [&](int k, int c) { return Li[c][k]; },
+                 cd4{0.0, 0.0, 0.0, 0.0});
+  wave_lds_sync();  // every lane has read A21
 #pragma unroll
-  for (int j = 0; j < NB; ++j) r[j] = (j <= i) ? T[i][j] : 0.0;
-  __syncthreads();
-  // from here T[j][k], k < j, holds the finished factor entry L[j][k]
-  int bad = -1;
+  for (int q = 0; q < 4; ++q) T[16 + 4 * q + q4][r16] = acc[q];
+  wave_lds_sync();
+  // A22 - L21 L21^T
+  cd4 c22;
 #pragma unroll
-  for (int j = 0; j < NB; ++j) {
-    double s0 = r[j], s1 = 0.0;
+  for (int q = 0; q < 4; ++q) c22[q] = T[16 + 4 * q + q4][16 + r16];
+  acc = mm16([&](int r, int k) { return -T[16 + r][k]; }, [&](int k, int c) { return T[16 + c][k]; }, c22);
 #pragma unroll
-    for (int k = 0; k < j; k += 2) {
-      s0 -= r[k] * T[j][k];
-      if (k + 1 < j) s1 -= r[k + 1] * T[j][k + 1];
-    }
-    const double sj = s0 + s1;
-    if (own && i == j) *Piv = sj;
-    __syncthreads();
-    double d = *Piv;
-    double yj;
-    if (!(d > 0.0) || !isfinite(d)) {
-      if (bad < 0) bad = j;
-      d = 1.0;
-      yj = 1.0;
-    } else {
-      yj = frsq(d);  // 1 / sqrt(d)
-    }
-    r[j] = (i == j) ? d * yj : (i > j ? sj * yj : 0.0);
-    if (own) T[i][j] = r[j];
-    if (t == 0) Ys[j] = yj;
-    __syncthreads();
+  for (int q = 0; q < 4; ++q) T[16 + 4 * q + q4][16 + r16] = acc[q];
+  wave_lds_sync();
+  chol16(T, Li, 16, bad2);
+  if (bad < 0 && bad2 >= 0) bad = 16 + bad2;
+  // M = L21 L11^{-1}, then L21' = -L22^{-1} M
+  acc = mm16([&](int r, int k) { return T[16 + r][k]; }, [&](int k, int c) { return Li[k][c]; },
+             cd4{0.0, 0.0, 0.0, 0.0});
+#pragma unroll
+  for (int q = 0; q < 4; ++q) Mb[4 * q + q4][r16] = acc[q];
+  wave_lds_sync();
+  acc = mm16([&](int r, int k) { return -Li[16 + r][16 + k]; }, [&](int k, int c) { return Mb[k][c]; },
+             cd4{0.0, 0.0, 0.0, 0.0});
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    Li[16 + 4 * q + q4][r16] = acc[q];
+    Li[4 * q + q4][16 + r16] = 0.0;
   }
-  if (bad >= 0 && bad < nbk && t == 0) atomicCAS(a.info, 0, (int)(base + bad + 1));
-  if (own) {
+  wave_lds_sync();
+  if (bad >= 0 && bad < nbk && lane == 0) atomicCAS(a.info, 0, (int)(base + bad + 1));
+  // the block of L (rows and columns inside the matrix) and all of L^{-1}
 #pragma unroll
-    for (int j = 0; j < NB; ++j)
-      if (i < nbk && j < nbk) Lg[(base + i) * n + base + j] = r[j];
-  }
-  // column i of the inverse: x[m] = (delta_mi - sum_{k<m} L[m][k] x[k]) / L[m][m]
-  double x[NB];
-#pragma unroll
-  for (int m = 0; m < NB; ++m) {
-    double s0 = (m == i) ? 1.0 : 0.0, s1 = 0.0;
-#pragma unroll
-    for (int k = 0; k < m; k += 2) {
-      s0 -= T[m][k] * x[k];
-      if (k + 1 < m) s1 -= T[m][k + 1] * x[k + 1];
-    }
-    x[m] = (s0 + s1) * Ys[m];
-  }
-  if (own) {
-#pragma unroll
-    for (int m = 0; m < NB; ++m) Dg[(int64_t)kb * NB * NB + m * NB + i] = x[m];
+  for (int u = 0; u < NB * NB / 64; ++u) {
+    const int e = lane + 64 * u, i = e / NB, j = e % NB;
+    if (i < nbk && j < nbk) Lg[(base + i) * n + base + j] = T[i][j];
+    Dg[(int64_t)kb * NB * NB + e] = Li[i][j];
   }
 }
 
@@ -178,8 +271,8 @@ __device__ __forceinline__ void diag_factor(const CholArgs& a, int kb, double (*
 __global__ __launch_bounds__(64) void chol_diag(CholArgs a, int kb) {
   if (*((volatile int*)a.info) != 0) return;
   __shared__ double T[NB][NB + 1];
-  __shared__ double Piv;
-  __shared__ double Ys[NB];  // 1 / L[j][j]
+  __shared__ double Li[NB][NB + 1];
+  __shared__ double Mb[NB][NB + 1];
   const int64_t n = a.n;
   const int64_t base = (int64_t)kb * NB;
   const int nbk = (int)((n - base) < NB ? (n - base) : NB);
@@ -196,7 +289,7 @@ __global__ __launch_bounds__(64) void chol_diag(CholArgs a, int kb) {
     T[e / NB][e % NB] = v[u];  // padding outside the matrix: identity
   }
   __syncthreads();
-  diag_factor(a, kb, T, &Piv, Ys);
+  diag_factor(a, kb, T, Li, Mb);
 }
 
 // Row and column (ii >= jj) of lower-triangle tile number tt.
@@ -215,8 +308,6 @@ __device__ __forceinline__ void tri_tile(int tt, int& ii, int& jj) {
 // then factors and inverts that block.
 __global__ __launch_bounds__(256) void chol_step(CholArgs a, int kb) {
   __shared__ double Pi[NB][NB + 1], Pj[NB][NB + 1], Di[NB][NB + 1], T[NB][NB + 1];
-  __shared__ double Piv;
-  __shared__ double Ys[NB];
   __shared__ int stop;
   const int64_t n = a.n;
   const int t = threadIdx.x;
@@ -248,56 +339,46 @@ __global__ __launch_bounds__(256) void chol_step(CholArgs a, int kb) {
   }
   __syncthreads();
   if (stop != 0) return;  // the same value for every thread
-  {  // panel blocks: P <- P Dinv^T (Dinv lower triangular)
-    double pi[NB * NB / 256], pj[NB * NB / 256];
-#pragma unroll
-    for (int u = 0; u < NB * NB / 256; ++u) {
-      const int e = t + 256 * u, i = e / NB, j = e % NB;
-      double si = 0.0, sj = 0.0;
-      for (int k = 0; k <= j; ++k) {
-        si += Pi[i][k] * Di[j][k];
-        sj += Pj[i][k] * Di[j][k];
-      }
-      pi[u] = si;
-      pj[u] = sj;
-    }
+  static_assert(NB == 32, "the MFMA quadrants assume 32 x 32 blocks");
+  const int lane = t & 63, wave = t >> 6;
+  const int qr = (wave >> 1) * 16 + (lane >> 4), qc = (wave & 1) * 16 + (lane & 15);  // + 4 q: this lane's rows
+  // panel blocks: P <- P Dinv^T (Dinv lower triangular, zeros above)
+  {
+    const cd4 zero = {0.0, 0.0, 0.0, 0.0};
+    const cd4 ai = mm32q([&](int r, int k) { return Pi[r][k]; }, [&](int k, int c) { return Di[c][k]; }, zero);
+    const cd4 aj = mm32q([&](int r, int k) { return Pj[r][k]; }, [&](int k, int c) { return Di[c][k]; }, zero);
     __syncthreads();
 #pragma unroll
-    for (int u = 0; u < NB * NB / 256; ++u) {
-      const int e = t + 256 * u;
-      Pi[e / NB][e % NB] = pi[u];
-      Pj[e / NB][e % NB] = pj[u];
+    for (int q = 0; q < 4; ++q) {
+      Pi[qr + 4 * q][qc] = ai[q];
+      Pj[qr + 4 * q][qc] = aj[q];
     }
   }
   __syncthreads();
   const bool diag_next = ii == 0;  // tile (kb + 1, kb + 1)
   const int nbk = (int)((n - cj) < NB ? (n - cj) : NB);
-  double upd[NB * NB / 256];
+  // A[ib][jb] - L[ib][kb] L[jb][kb]^T
+  cd4 upd;
 #pragma unroll
-  for (int u = 0; u < NB * NB / 256; ++u) {
-    const int e = t + 256 * u, i = e / NB, j = e % NB;
-    double sacc = 0.0;
-#pragma unroll 8
-    for (int k = 0; k < NB; ++k) sacc += Pi[i][k] * Pj[j][k];
-    upd[u] = T[i][j] - sacc;
-  }
+  for (int q = 0; q < 4; ++q) upd[q] = T[qr + 4 * q][qc];
+  upd = mm32q([&](int r, int k) { return -Pi[r][k]; }, [&](int k, int c) { return Pj[c][k]; }, upd);
   if (!diag_next) {
 #pragma unroll
-    for (int u = 0; u < NB * NB / 256; ++u) {
-      const int e = t + 256 * u, i = e / NB, j = e % NB;
-      const int64_t gi = (int64_t)ib * NB + i, gj = cj + j;
-      if (gi < n && gj < n && gj <= gi) Lg[gi * n + gj] = upd[u];
+    for (int q = 0; q < 4; ++q) {
+      const int64_t gi = (int64_t)ib * NB + qr + 4 * q, gj = cj + qc;
+      if (gi < n && gj < n && gj <= gi) Lg[gi * n + gj] = upd[q];
     }
     return;
   }
   __syncthreads();
 #pragma unroll
-  for (int u = 0; u < NB * NB / 256; ++u) {
-    const int e = t + 256 * u, i = e / NB, j = e % NB;
-    T[i][j] = (i < nbk && j < nbk && j <= i) ? upd[u] : (i == j ? 1.0 : 0.0);
+  for (int q = 0; q < 4; ++q) {
+    const int i = qr + 4 * q, j = qc;
+    T[i][j] = (i < nbk && j < nbk && j <= i) ? upd[q] : (i == j ? 1.0 : 0.0);
   }
   __syncthreads();
-  diag_factor(a, jb, T, &Piv, Ys);
+  // the panels and Dinv_kb are no longer read: their LDS serves as scratch
+  if (t < 64) diag_factor(a, jb, T, Di, Pi);
 }
 
 // All sub-diagonal blocks: L[ib][kb] = A[ib][kb] Dinv_kb^T, one workgroup
@@ -330,13 +411,13 @@ __global__ __launch_bounds__(256) void chol_panels(CholArgs a) {
     }
   }
   __syncthreads();
+  const int lane = t & 63, wave = t >> 6;
+  const int qr = (wave >> 1) * 16 + (lane >> 4), qc = (wave & 1) * 16 + (lane & 15);
+  const cd4 acc = mm32q([&](int r, int k) { return Lb[r][k]; }, [&](int k, int c) { return Ti[c][k]; },
+                        cd4{0.0, 0.0, 0.0, 0.0});
 #pragma unroll
-  for (int u = 0; u < NB * NB / 256; ++u) {
-    const int e = t + 256 * u, i = e / NB, j = e % NB;
-    double sacc = 0.0;
-    for (int k = 0; k <= j; ++k) sacc += Lb[i][k] * Ti[j][k];
-    if (r0 + i < n) Lg[(r0 + i) * n + c0 + j] = sacc;
-  }
+  for (int q = 0; q < 4; ++q)
+    if (r0 + qr + 4 * q < n) Lg[(r0 + qr + 4 * q) * n + c0 + qc] = acc[q];
 }
 
 // ---------------------------------------------------------------- L^{-1}
@@ -897,6 +978,7 @@ __global__ void jac_end_sweep(JacArgs a, int sweep, int* host_conv, int seq) {
   }
   if (host_conv) {
     host_conv[0] = a.conv[0];
+    host_conv[2] = a.flags[sweep];  // the sweep's largest ratio^2 (float bits)
     __threadfence_system();
     ((volatile int*)host_conv)[1] = seq;
   }
@@ -1090,7 +1172,7 @@ nys_status sym_eig(const double* G, int64_t l, double* work, int* flags, int max
   // most one sweep of early-returning launches follows convergence.  Without
   // pinned memory the flag is copied and the stream synchronised every third
   // sweep.
-  int* hpin = pinned_flags();  // [0] converged flag, [1] sequence tag
+  int* hpin = pinned_flags();  // [0] converged flag, [1] sequence tag, [2] sweep ratio^2
   int seqs[2] = {0, 0};
   nys_status st = NYS_OK;
   for (int sweep = 0; sweep < max_sweeps; ++sweep) {
@@ -1112,6 +1194,23 @@ nys_status sym_eig(const double* G, int64_t l, double* work, int* flags, int max
           break;
         }
         if (*(volatile int*)hpin) break;
+        // Near the end the sweep ratios fall quadratically: when sweep s - 1
+        // ended within a factor 5 of the stopping ratio, sweep s (running
+        // now) is most likely the last, so its flag is awaited before another
+        // sweep is enqueued.  That saves the sweep of early-returning launches
+        // that would follow convergence; a wrong guess costs one host round
+        // trip of device idle time.
+        const int tag = ((volatile int*)hpin)[1];
+        float r2prev;
+        const int bits = ((volatile int*)hpin)[2];
+        std::memcpy(&r2prev, &bits, sizeof(float));
+        if (tag != seqs[sweep & 1] && r2prev < 25.0f * a.conv_r2) {
+          if (!wait_pinned(hpin + 1, seqs[sweep & 1], s, 0)) {
+            st = NYS_ERR_DEVICE;
+            break;
+          }
+          if (*(volatile int*)hpin) break;
+        }
       }
     } else if (sweep >= 5 && (sweep % 3 == 2)) {
       int c = 0;

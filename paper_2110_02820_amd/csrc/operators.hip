@@ -108,6 +108,15 @@ __global__ __launch_bounds__(256) void rbf_mv_f64m(const TD* __restrict__ Xr, in
   const int64_t j0 = (int64_t)blockIdx.y * pts_per_split;
   const int64_t j1 = (j0 + pts_per_split < nc) ? j0 + pts_per_split : nc;
   double acc[4] = {0.0, 0.0, 0.0, 0.0}, cmp[4] = {0.0, 0.0, 0.0, 0.0};
+  // with pvq (square operator): p on this lane's output rows, loaded now
+  double pr[4] = {0.0, 0.0, 0.0, 0.0};
+  if (pvq) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int64_t row = i0 + 4 * q + (lane >> 4);
+      pr[q] = row < nr ? p[row] : 0.0;
+    }
+  }
   for (int64_t jt = j0; jt < j1; jt += RB_PTS) {
     __syncthreads();
     {
@@ -152,7 +161,7 @@ __global__ __launch_bounds__(256) void rbf_mv_f64m(const TD* __restrict__ Xr, in
     }
   }
   // rows 4 q + l / 16: add the 16 lanes (points) of each group in a fixed tree
-  double pq = 0.0;
+  double pq = 0.0, pp = 0.0;
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     double v = acc[q] - cmp[q];
@@ -160,21 +169,21 @@ __global__ __launch_bounds__(256) void rbf_mv_f64m(const TD* __restrict__ Xr, in
     const int64_t row = i0 + 4 * q + (lane >> 4);
     if ((lane & 15) == 0 && row < nr) {
       part[(int64_t)blockIdx.y * nr + row] = v;
-      if (pvq) pq += p[row] * v;
+      pq += pr[q] * v;
+      pp += pr[q] * pr[q];
     }
   }
   if (pvq) {
-    // square operator (Xr = Xc): this workgroup's part of p^T W p, and ||p||^2
-    // from workgroup (0, 0), so that a CG step knows p^T A p before the
+    // square operator (Xr = Xc): this workgroup's part of p^T W p at
+    // pvq[y gx + x], and the split-0 workgroups' parts of ||p||^2 over their
+    // rows at pvq[gx gy + x], so that a CG step knows p^T A p before the
     // partials are summed
     __shared__ double shq[4];
     pq = block_sum(pq, shq);
     if (t == 0) pvq[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = pq;
-    if (blockIdx.x == 0 && blockIdx.y == 0) {
-      double q2 = 0.0;
-      for (int64_t j = t; j < nc; j += 256) q2 += p[j] * p[j];
-      q2 = block_sum(q2, shq);
-      if (t == 0) pvq[(int64_t)gridDim.x * gridDim.y] = q2;
+    if (blockIdx.y == 0) {
+      pp = block_sum(pp, shq);
+      if (t == 0) pvq[(int64_t)gridDim.x * gridDim.y + blockIdx.x] = pp;
     }
   }
 }
@@ -588,19 +597,24 @@ nys_status op_matvec(const OpDesc& op, const TA* p, TA mu, TA* v, TA* scratch, s
 // Single vector in partial-sum form: (A p)[j] = scale * sum_{g < ng} part[g][j].
 template <typename TA>
 nys_status op_matvec_partials(const OpDesc& op, const TA* p, TA* part, size_t part_elems, int* ng_out,
-                              hipStream_t s, double* pvq, int* npvq);
+                              hipStream_t s, double* pvq, int* npvq, int* npp);
 
 template <>
 nys_status op_matvec_partials<double>(const OpDesc& op, const double* p, double* part, size_t part_elems,
-                                      int* ng_out, hipStream_t s, double* pvq, int* npvq) {
+                                      int* ng_out, hipStream_t s, double* pvq, int* npvq, int* npp) {
   const int64_t n = op.n;
   if (npvq) *npvq = 0;
+  if (npp) *npp = 0;
+  if (!npvq || !npp) pvq = nullptr;
   if (op.kind == NYS_OP_XTX) {
     bool filled = false;
     nys_status st = op.dtype == NYS_F64
-                        ? xtx_partials<double, double>(op, p, part, part_elems, ng_out, s, pvq, npvq ? &filled : nullptr)
-                        : xtx_partials<float, double>(op, p, part, part_elems, ng_out, s, pvq, npvq ? &filled : nullptr);
-    if (st == NYS_OK && filled) *npvq = *ng_out;
+                        ? xtx_partials<double, double>(op, p, part, part_elems, ng_out, s, pvq, pvq ? &filled : nullptr)
+                        : xtx_partials<float, double>(op, p, part, part_elems, ng_out, s, pvq, pvq ? &filled : nullptr);
+    if (st == NYS_OK && filled) {
+      *npvq = *ng_out;
+      *npp = 1;
+    }
     return st;
   }
   if (op.kind == NYS_OP_RBF) {
@@ -615,10 +629,11 @@ nys_status op_matvec_partials<double>(const OpDesc& op, const double* p, double*
     int64_t ns = cdiv(4 * (num_cus() < 256 ? num_cus() : 256), nrb);
     if (ns < 1) ns = 1;
     while (ns > 1 && (size_t)(ns * n) > part_elems) --ns;
-    // p^T K p parts, one per workgroup, when they fit the caller's kPvqMax slots
-    const bool want_pvq = pvq && npvq && nrb + 1 <= kPvqMax;
+    // p^T K p parts, one per workgroup, and ||p||^2 parts, one per row block,
+    // when they fit the caller's kPvqMax slots
+    const bool want_pvq = pvq && 2 * nrb <= kPvqMax;
     if (want_pvq)
-      while (ns > 1 && nrb * ns + 1 > kPvqMax) --ns;
+      while (ns > 1 && nrb * (ns + 1) > kPvqMax) --ns;
     const int64_t pps = cdiv(cdiv(n, ns), RB_PTS) * RB_PTS;
     ns = cdiv(n, pps);
     dim3 grid((unsigned)nrb, (unsigned)ns);
@@ -632,7 +647,10 @@ nys_status op_matvec_partials<double>(const OpDesc& op, const double* p, double*
     }
     NYS_CHECK_LAUNCH();
     *ng_out = (int)ns;
-    if (want_pvq) *npvq = (int)(nrb * ns);
+    if (want_pvq) {
+      *npvq = (int)(nrb * ns);
+      *npp = (int)nrb;
+    }
     return NYS_OK;
   }
   set_error("op_matvec_partials: operator has no partial form");
@@ -641,16 +659,21 @@ nys_status op_matvec_partials<double>(const OpDesc& op, const double* p, double*
 
 template <>
 nys_status op_matvec_partials<float>(const OpDesc& op, const float* p, float* part, size_t part_elems,
-                                     int* ng_out, hipStream_t s, double* pvq, int* npvq) {
+                                     int* ng_out, hipStream_t s, double* pvq, int* npvq, int* npp) {
   if (npvq) *npvq = 0;
+  if (npp) *npp = 0;
+  if (!npvq || !npp) pvq = nullptr;
   if (op.kind == NYS_OP_RBF && op.lowp)
     return rbf_lowp_mv_partials(*op.lowp, op.gram, p, part, part_elems, ng_out, op.skip, s);
   if (op.kind == NYS_OP_XTX) {
     bool filled = false;
     nys_status st = op.dtype == NYS_F64
-                        ? xtx_partials<double, float>(op, p, part, part_elems, ng_out, s, pvq, npvq ? &filled : nullptr)
-                        : xtx_partials<float, float>(op, p, part, part_elems, ng_out, s, pvq, npvq ? &filled : nullptr);
-    if (st == NYS_OK && filled) *npvq = *ng_out;
+                        ? xtx_partials<double, float>(op, p, part, part_elems, ng_out, s, pvq, pvq ? &filled : nullptr)
+                        : xtx_partials<float, float>(op, p, part, part_elems, ng_out, s, pvq, pvq ? &filled : nullptr);
+    if (st == NYS_OK && filled) {
+      *npvq = *ng_out;
+      *npp = 1;
+    }
     return st;
   }
   set_error("op_matvec_partials: float32 form needs X^T X or a prepared RBF operator");

@@ -53,11 +53,12 @@ nys_status op_matvec(const OpDesc& op, const TA* p, TA mu, TA* v, TA* scratch, s
 // (X^T X: float or double arithmetic; RBF: double).  *ng_out = number of groups.
 template <typename TA>
 nys_status op_matvec_partials(const OpDesc& op, const TA* p, TA* part, size_t part_elems, int* ng_out,
-                              hipStream_t s, double* pvq = nullptr, int* npvq = nullptr);
+                              hipStream_t s, double* pvq = nullptr, int* npvq = nullptr, int* npp = nullptr);
 
 // Slots of pvq that op_matvec_partials may fill: *npvq parts of p^T A p / scale
 // (XTX: per product workgroup; square RBF: per (row block, split) workgroup)
-// plus ||p||^2 at pvq[*npvq]; *npvq = 0 when the product form has none.
+// then *npp parts of ||p||^2 from pvq[*npvq] on (XTX: one; RBF: per row
+// block); *npvq = *npp = 0 when the product form has none.
 constexpr int64_t kPvqMax = 2048;
 
 // out (nr) = W p with W = K(Xr, Xc) (mode 0) or dK/dsigma (mode 1), float64

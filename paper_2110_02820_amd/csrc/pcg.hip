@@ -658,31 +658,84 @@ __global__ __launch_bounds__(NT) void utr_vec(int64_t n, int64_t l, const TU* __
 }
 
 // k = 1, after a product that also gave pvq (see op_matvec_partials: X^T X,
-// or a square RBF operator): p^T (A + mu I) p = scale sum_g pvq[g] + mu ||p||^2
-// (g < npvq, ||p||^2 at pvq[npvq]), summed by every workgroup in the same
-// fixed order, so each knows alpha at once and no workgroup hands it to another.  Tiles of 32 entries: v_j from the ng
-// partials (8 slices of 32 columns, as cg_finish_mv), x_j += alpha p_j,
+// or a square RBF operator): p^T (A + mu I) p = scale sum_{g < npvq} pvq[g] +
+// mu sum_{g < npp} pvq[npvq + g], summed by every workgroup in the same fixed
+// order, so each knows alpha at once and no workgroup hands it to another.
+// Workgroup b owns entries 32 b .. 32 b + 31 (n <= 32 gridDim.x): v_j from
+// the ng partials (8 slices of 32 columns, as cg_finish_mv), x_j += alpha p_j,
 // r_j -= alpha v_j, a part of ||r||^2, and this workgroup's part of U^T r over
-// the tile's rows of U (thread t owns the 16-byte vectors t, t + NT of a row;
-// float64 accumulation).  Workgroup 0 records alpha and a breakdown.
-template <typename T, typename TU>
+// its 32 rows of U in float64.  With nvec = l / E 16-byte vectors per row, G
+// groups of nvec threads (G nvec <= NT) share the rows (group g takes rows g,
+// g + G, ...; their sums are added in a fixed order through LDS); with G = 1
+// thread t owns vectors t and t + NT (CG = 2).  Every load that does not need
+// alpha (the first rows of U, the partials, p, x, r) is issued before alpha is
+// formed.  Workgroup 0 records alpha and a breakdown.
+template <typename T, typename TU, int CG>
 __global__ __launch_bounds__(NT) void cg_finish_pvq(int64_t n, const T* __restrict__ part, int ng,
-                                                    const double* __restrict__ pvq, int npvq, double scale,
-                                                    double mu,
-                                                    const T* __restrict__ P, T* __restrict__ V, T* __restrict__ X,
-                                                    T* __restrict__ R, const TU* __restrict__ U, int64_t l,
-                                                    int64_t ldu, double* __restrict__ apart,
-                                                    double* __restrict__ prr, CgScalars sc, int par) {
+                                                    const double* __restrict__ pvq, int npvq, int npp,
+                                                    double scale, double mu, const T* __restrict__ P,
+                                                    T* __restrict__ V, T* __restrict__ X, T* __restrict__ R,
+                                                    const TU* __restrict__ U, int64_t l, int64_t ldu, int G,
+                                                    double* __restrict__ apart, double* __restrict__ prr,
+                                                    CgScalars sc, int par) {
   typedef typename UVec<TU>::type VT;
   constexpr int E = UVec<TU>::E;
-  constexpr int CG = 2;  // vectors per thread: l <= 2 NT E (uvec_ok allows 64 E 8 = 2 NT E)
-  const int skip_all = *sc.alldone;
+  constexpr int RB = 8;  // rows of U in flight per thread
   __shared__ T shp[8][33];
   __shared__ double sh[NT];
   __shared__ double rs[32];
-  double q = 0.0;
+  __shared__ double red[NT * E];  // the groups' sums when G > 1
+  const int skip_all = *sc.alldone;
+  const int c = threadIdx.x & 31, sl = threadIdx.x >> 5;
+  const int64_t tile = blockIdx.x;
+  const int64_t j = tile * 32 + c;
+  const int64_t jc = j < n ? j : n - 1;
+  const int64_t rows = n - tile * 32 < 32 ? n - tile * 32 : 32;
+  const int nvec = (int)(l / E);
+  const int grp = G > 1 ? (int)threadIdx.x / nvec : 0;
+  const int rpt = 32 / G;  // rows per thread
+  int64_t uo[CG];
+  bool uok[CG];
+#pragma unroll
+  for (int v = 0; v < CG; ++v) {
+    const int vi = G > 1 ? (int)threadIdx.x % nvec : v * NT + (int)threadIdx.x;
+    uok[v] = vi < nvec && grp < G;
+    uo[v] = uok[v] ? (int64_t)vi * E : 0;
+  }
+  const TU* ub = U + tile * 32 * ldu;
+  VT uv[RB][CG];
+  auto load_u = [&](int k0) {
+#pragma unroll
+    for (int rr = 0; rr < RB; ++rr) {
+      const int k = k0 + rr, r = grp + G * k;
+      const int64_t row = r < rows ? r : 0;  // rows past n re-read the tile's first (rs = 0)
+#pragma unroll
+      for (int v = 0; v < CG; ++v)
+        if (uok[v] && k < rpt) uv[rr][v] = *reinterpret_cast<const VT*>(ub + row * ldu + uo[v]);
+    }
+  };
+  load_u(0);
+  T a0 = T(0);
+  for (int g0 = sl; g0 < ng; g0 += 256) {
+    T w[32];
+#pragma unroll
+    for (int u = 0; u < 32; ++u) {
+      const int g = g0 + 8 * u;
+      w[u] = g < ng ? part[(int64_t)g * n + jc] : T(0);
+    }
+#pragma unroll
+    for (int u = 0; u < 32; ++u) a0 += w[u];
+  }
+  T pj = T(0), xj = T(0), rj = T(0);
+  if (sl == 0 && j < n) {
+    pj = P[j];
+    xj = X[j];
+    rj = R[j];
+  }
+  double q = 0.0, qp = 0.0;
   for (int g = threadIdx.x; g < npvq; g += NT) q += pvq[g];
-  const double pv = scale * block_sum(q, sh) + mu * pvq[npvq];
+  for (int g = threadIdx.x; g < npp; g += NT) qp += pvq[npvq + g];
+  const double pv = block_sum(scale * q + mu * qp, sh);
   if (skip_all) return;  // the same value for every thread
   const int done = sc.done[0];
   const double a_d = (done || !(pv > 0.0)) ? 0.0 : sc.rz[par] / pv;
@@ -694,82 +747,62 @@ __global__ __launch_bounds__(NT) void cg_finish_pvq(int64_t n, const T* __restri
     }
   }
   const T a = T(a_d);
-  const int c = threadIdx.x & 31, sl = threadIdx.x >> 5;
-  const int64_t nvec = l / E;
-  int64_t uo[CG];
-  bool uok[CG];
-#pragma unroll
-  for (int v = 0; v < CG; ++v) {
-    const int64_t vi = (int64_t)v * NT + threadIdx.x;
-    uok[v] = vi < nvec;
-    uo[v] = uok[v] ? vi * E : 0;
+  shp[sl][c] = a0;
+  __syncthreads();
+  double rrp = 0.0;
+  if (sl == 0) {
+    double rj_d = 0.0;
+    if (j < n) {
+      const T sum = ((shp[0][c] + shp[1][c]) + (shp[2][c] + shp[3][c])) +
+                    ((shp[4][c] + shp[5][c]) + (shp[6][c] + shp[7][c]));
+      const T vj = T(scale) * sum + T(mu) * pj;
+      V[j] = vj;
+      X[j] = xj + a * pj;
+      rj = rj - a * vj;
+      R[j] = rj;
+      rrp = double(rj) * double(rj);
+      rj_d = double(rj);
+    }
+    rs[c] = rj_d;  // 0 past n
   }
+  __syncthreads();
   double acc[CG][E];
 #pragma unroll
   for (int v = 0; v < CG; ++v)
 #pragma unroll
     for (int e = 0; e < E; ++e) acc[v][e] = 0.0;
-  double rrp = 0.0;
-  const int64_t ntiles = cdiv(n, 32);
-  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-    const int64_t j = tile * 32 + c;
-    const int64_t jc = j < n ? j : n - 1;
-    T a0 = T(0);
-    for (int g0 = sl; g0 < ng; g0 += 256) {
-      T v[32];
+  for (int k0 = 0; k0 < rpt; k0 += RB) {
+    if (k0 > 0) load_u(k0);
 #pragma unroll
-      for (int u = 0; u < 32; ++u) {
-        const int g = g0 + 8 * u;
-        v[u] = g < ng ? part[(int64_t)g * n + jc] : T(0);
-      }
-#pragma unroll
-      for (int u = 0; u < 32; ++u) a0 += v[u];
-    }
-    __syncthreads();  // the previous tile's readers of shp and rs are done
-    shp[sl][c] = a0;
-    __syncthreads();
-    if (sl == 0) {
-      double rj_d = 0.0;
-      if (j < n) {
-        const T sum = ((shp[0][c] + shp[1][c]) + (shp[2][c] + shp[3][c])) +
-                      ((shp[4][c] + shp[5][c]) + (shp[6][c] + shp[7][c]));
-        const T pj = P[j];
-        const T vj = T(scale) * sum + T(mu) * pj;
-        V[j] = vj;
-        X[j] += a * pj;
-        const T rj = R[j] - a * vj;
-        R[j] = rj;
-        rrp += double(rj) * double(rj);
-        rj_d = double(rj);
-      }
-      rs[c] = rj_d;  // 0 past n
-    }
-    __syncthreads();
-    const int64_t rows = n - tile * 32 < 32 ? n - tile * 32 : 32;
-    const TU* ub = U + tile * 32 * ldu;
-    for (int r0 = 0; r0 < 32; r0 += 8) {
-      VT uv[8][CG];
-#pragma unroll
-      for (int rr = 0; rr < 8; ++rr) {
-        const int64_t row = r0 + rr < rows ? r0 + rr : 0;  // rows past n re-read the tile's first (rs = 0)
-#pragma unroll
-        for (int v = 0; v < CG; ++v) uv[rr][v] = *reinterpret_cast<const VT*>(ub + row * ldu + uo[v]);
-      }
-#pragma unroll
-      for (int rr = 0; rr < 8; ++rr) {
-        const double rv = rs[r0 + rr];
+    for (int rr = 0; rr < RB; ++rr) {
+      const int k = k0 + rr;
+      if (k < rpt) {
+        const double rv = rs[grp + G * k < 32 ? grp + G * k : 0];
 #pragma unroll
         for (int v = 0; v < CG; ++v)
+          if (uok[v])
 #pragma unroll
-          for (int e = 0; e < E; ++e) acc[v][e] += double(UVec<TU>::get(uv[rr][v], e)) * rv;
+            for (int e = 0; e < E; ++e) acc[v][e] += double(UVec<TU>::get(uv[rr][v], e)) * rv;
       }
     }
   }
+  if (G == 1) {
 #pragma unroll
-  for (int v = 0; v < CG; ++v)
-    if (uok[v])
+    for (int v = 0; v < CG; ++v)
+      if (uok[v])
 #pragma unroll
-      for (int e = 0; e < E; ++e) apart[(int64_t)blockIdx.x * l + uo[v] + e] = acc[v][e];
+        for (int e = 0; e < E; ++e) apart[(int64_t)blockIdx.x * l + uo[v] + e] = acc[v][e];
+  } else {
+    if (uok[0])
+#pragma unroll
+      for (int e = 0; e < E; ++e) red[grp * nvec * E + uo[0] + e] = acc[0][e];
+    __syncthreads();
+    for (int i = threadIdx.x; i < nvec * E; i += NT) {
+      double tot = 0.0;
+      for (int g = 0; g < G; ++g) tot += red[g * nvec * E + i];
+      apart[(int64_t)blockIdx.x * l + i] = tot;
+    }
+  }
   const double rr = block_sum(rrp, sh);
   if (threadIdx.x == 0) prr[blockIdx.x] = rr;
 }
@@ -788,6 +821,16 @@ __global__ __launch_bounds__(NT) void utr_final_rr(int64_t l, int nch, const dou
   const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
   const int64_t j = (int64_t)blockIdx.x * 64 + tx;
   const int64_t jc = j < l ? j : l - 1;
+  // loads that need nothing from this launch, issued first
+  const double m = mu[0], lam_l = lam[l - 1], lam_j = lam[jc];
+  double s = 0.0;
+  int done0 = 1;
+  double bn2 = 0.0;
+  if (blockIdx.x == 0) {
+    for (int q = threadIdx.x; q < nprr; q += NT) s += prr[q];
+    done0 = sc.done[0];
+    bn2 = sc.bnorm2[0];
+  }
   double acc = 0.0;
   for (int q0 = ty; q0 < nch; q0 += 4 * 16) {  // 16 loads in flight per thread
     double v[16];
@@ -805,8 +848,7 @@ __global__ __launch_bounds__(NT) void utr_final_rr(int64_t l, int nch, const dou
   double wdw = 0.0;  // this column's w_j d_j w_j, w = U^T r (unscaled), d_j the apply's diagonal
   if (ty == 0 && j < l) {
     const double tot = (red[0][tx] + red[1][tx]) + (red[2][tx] + red[3][tx]);
-    const double m = mu[0];
-    const double cj = ((lam[l - 1] + m) / (lam[j] + m) - 1.0) * tot;
+    const double cj = ((lam_l + m) / (lam_j + m) - 1.0) * tot;
     Cs[j] = cj;
     wdw = cj * tot;
   }
@@ -815,14 +857,12 @@ __global__ __launch_bounds__(NT) void utr_final_rr(int64_t l, int nch, const dou
   wdw = block_sum(wdw, sh);
   if (threadIdx.x == 0) rzq[blockIdx.x] = wdw;
   if (blockIdx.x != 0) return;
-  double s = 0.0;
-  for (int q = threadIdx.x; q < nprr; q += NT) s += prr[q];
   const double rr = block_sum(s, sh);
   if (threadIdx.x == 0) rzq[gridDim.x] = rr;
-  if (threadIdx.x == 0 && !sc.done[0]) {
+  if (threadIdx.x == 0 && !done0) {
     sc.rnorm2[0] = rr;
     sc.iters[0] += 1;
-    const bool conv = rr <= tol * tol * sc.bnorm2[0];
+    const bool conv = rr <= tol * tol * bn2;
     sc.conv[0] = conv ? 1 : 0;
     if (conv) sc.status[0] = NYS_OK;
   }
@@ -839,30 +879,8 @@ __global__ __launch_bounds__(NT) void uc_vec(int64_t n, int64_t l, const TU* __r
   typedef typename UVec<TU>::type VT;
   constexpr int E = UVec<TU>::E;
   const int skip_all = mode >= 2 ? *sc.alldone : 0;
-  // mode 4 (after utr_final_rr, whose cdiv(l, 64) workgroups left their parts
-  // of w^T D w in prz, then ||r||^2): r^T z and so beta are known before the
-  // apply, and each wave sets p = z + beta p on its own rows
   T bz = T(0);
   int dn = 0;
-  if (mode == 4) {
-    __shared__ double shq[NT / 64];
-    const int nq = (int)cdiv(l, 64);
-    double q = 0.0;
-    for (int i = threadIdx.x; i <= nq; i += NT) q += prz[i];
-    const double rzn = block_sum(q, shq);
-    const int done_old = sc.done[0];
-    dn = done_old || sc.conv[0];
-    const double beta = done_old ? 0.0 : rzn / sc.rz[par];
-    bz = T(beta);
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-      if (!done_old) {
-        sc.beta[0] = beta;
-        sc.rz[1 - par] = rzn;
-        sc.done[0] = dn;
-      }
-      *sc.alldone = dn;  // also after a breakdown flagged earlier in the iteration
-    }
-  }
   __shared__ double sh[NT];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   T cs[NG][E];
@@ -921,6 +939,31 @@ __global__ __launch_bounds__(NT) void uc_vec(int64_t n, int64_t l, const TU* __r
   };
   int64_t ib = w0;
   if (ib < w1) load(ua, ra, ib);
+  // mode 4 (after utr_final_rr, whose cdiv(l, 64) workgroups left their parts
+  // of w^T D w in prz, then ||r||^2): r^T z and so beta are known before the
+  // apply, and each wave sets p = z + beta p on its own rows (formed after the
+  // first rows of U are on their way)
+  if (mode == 4) {
+    __shared__ double shq[NT / 64];
+    const int nq = (int)cdiv(l, 64);
+    const int done_old = sc.done[0];
+    const int conv = sc.conv[0];
+    const double rz_old = sc.rz[par];
+    double q = 0.0;
+    for (int i = threadIdx.x; i <= nq; i += NT) q += prz[i];
+    const double rzn = block_sum(q, shq);
+    dn = done_old || conv;
+    const double beta = done_old ? 0.0 : rzn / rz_old;
+    bz = T(beta);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      if (!done_old) {
+        sc.beta[0] = beta;
+        sc.rz[1 - par] = rzn;
+        sc.done[0] = dn;
+      }
+      *sc.alldone = dn;  // also after a breakdown flagged earlier in the iteration
+    }
+  }
   if (skip_all) return;
   for (; ib + 4 < w1; ib += 8) {
     load(ub, rb, ib + 4);
@@ -1303,23 +1346,36 @@ bool pcg_pvq_ok(const PrecDesc& P, int64_t n) {
 
 template <typename T>
 nys_status pcg_iteration_pvq(int64_t n, const PrecDesc& P, const double* mu_dev, double mu, const T* part, int ng,
-                             const double* pvq, int npvq, double scale, T* V, T* X, T* R, T* Z, T* Pd, PcgWork& w,
-                             const CgScalars& sc, int par, double tol, hipStream_t s) {
+                             const double* pvq, int npvq, int npp, double scale, T* V, T* X, T* R, T* Z, T* Pd,
+                             PcgWork& w, const CgScalars& sc, int par, double tol, hipStream_t s) {
   const bool f32 = sizeof(T) == 4;
   if (!pcg_pvq_ok(P, n)) {
     set_error("pcg_iteration_pvq: needs n <= %lld and a 16-byte U layout", (long long)kFuseMaxN);
     return NYS_ERR_ARG;
   }
   const int64_t l = P.ell;
-  // tiles of 32 entries, one per workgroup up to NYS_FINX_BLOCKS (each also
-  // reads its tiles' rows of U for U^T r; nothing here waits on the others)
-  const int64_t nfb = cdiv(n, 32) < NYS_FINX_BLOCKS ? cdiv(n, 32) : NYS_FINX_BLOCKS;
-  if (P.dtype == NYS_F64)
-    hipLaunchKernelGGL((cg_finish_pvq<T, double>), dim3((unsigned)nfb), dim3(NT), 0, s, n, part, ng, pvq, npvq, scale, mu,
-                       Pd, V, X, R, static_cast<const double*>(P.U), l, P.ldu, w.apart, w.prr, sc, par);
-  else
-    hipLaunchKernelGGL((cg_finish_pvq<T, float>), dim3((unsigned)nfb), dim3(NT), 0, s, n, part, ng, pvq, npvq, scale, mu,
-                       Pd, V, X, R, static_cast<const float*>(P.U), l, P.ldu, w.apart, w.prr, sc, par);
+  // one tile of 32 entries per workgroup (n <= kFuseMaxN keeps it within the
+  // partial-sum slots); each also reads its rows of U for U^T r, and nothing
+  // here waits on another workgroup
+  const int64_t nfb = cdiv(n, 32);
+  if (nfb > NYS_FINX_BLOCKS) {
+    set_error("pcg_iteration_pvq: n = %lld needs %lld > %d tiles", (long long)n, (long long)nfb, NYS_FINX_BLOCKS);
+    return NYS_ERR_ARG;
+  }
+  const int E = P.dtype == NYS_F64 ? 2 : 4;
+  const int nvec = (int)(l / E);
+  int G = 1;  // groups of nvec threads sharing the tile's rows
+  while (G < 32 && 2 * G * nvec <= NT) G *= 2;
+  const bool cg2 = nvec > NT;  // G = 1 and two vectors per thread
+#define NYS_FINX(TU, CGV)                                                                                            hipLaunchKernelGGL((cg_finish_pvq<T, TU, CGV>), dim3((unsigned)nfb), dim3(NT), 0, s, n, part, ng, pvq, npvq, npp,                      scale, mu, Pd, V, X, R, static_cast<const TU*>(P.U), l, P.ldu, G, w.apart, w.prr, sc, par)
+  if (P.dtype == NYS_F64) {
+    if (cg2) NYS_FINX(double, 2);
+    else NYS_FINX(double, 1);
+  } else {
+    if (cg2) NYS_FINX(float, 2);
+    else NYS_FINX(float, 1);
+  }
+#undef NYS_FINX
   NYS_CHECK_LAUNCH();
   hipLaunchKernelGGL(utr_final_rr, dim3((unsigned)cdiv(l, 64)), dim3(NT), 0, s, l, (int)nfb, w.apart, P.lam, mu_dev,
                      w.Cs, w.prr, (int)nfb, sc, tol, w.prz);
@@ -1379,10 +1435,10 @@ template nys_status cg_block_direction<double>(int64_t, int64_t, const double*, 
                                                PcgWork&, const CgScalars&, int, bool, hipStream_t);
 
 template nys_status pcg_iteration_pvq<double>(int64_t, const PrecDesc&, const double*, double, const double*, int,
-                                              const double*, int, double, double*, double*, double*, double*, double*,
-                                              PcgWork&, const CgScalars&, int, double, hipStream_t);
+                                              const double*, int, int, double, double*, double*, double*, double*,
+                                              double*, PcgWork&, const CgScalars&, int, double, hipStream_t);
 template nys_status pcg_iteration_pvq<float>(int64_t, const PrecDesc&, const double*, double, const float*, int,
-                                             const double*, int, double, float*, float*, float*, float*, float*,
+                                             const double*, int, int, double, float*, float*, float*, float*, float*,
                                              PcgWork&, const CgScalars&, int, double, hipStream_t);
 template nys_status pcg_iteration_fused<double>(int64_t, const PrecDesc&, const double*, double, const double*, int,
                                                 double, double*, double*, double*, double*, double*, PcgWork&,

@@ -65,14 +65,14 @@ nys_status pcg_iteration_fused(int64_t n, const PrecDesc& P, const double* mu_de
                                const CgScalars& sc, int par, double tol, hipStream_t s);
 
 // pcg_iteration_fused for a product that also gave pvq (op_matvec_partials:
-// npvq parts of p^T A p / scale and ||p||^2): alpha is known before the
+// npvq parts of p^T A p / scale, then npp parts of ||p||^2): alpha is known before the
 // partials are summed, so one launch sums them, updates x and r and forms
 // this launch's parts of U^T r; then the scaling of U^T r (with the stopping
 // test and the parts of r^T z = ||r||^2 + w^T D w) and the apply with the
 // direction update.  Requires pcg_pvq_ok; returns NYS_ERR_ARG otherwise.
 template <typename T>
 nys_status pcg_iteration_pvq(int64_t n, const PrecDesc& P, const double* mu_dev, double mu, const T* part, int ng,
-                             const double* pvq, int npvq, double scale, T* V, T* X, T* R, T* Z, T* Pd,
+                             const double* pvq, int npvq, int npp, double scale, T* V, T* X, T* R, T* Z, T* Pd,
                              PcgWork& w, const CgScalars& sc, int par, double tol, hipStream_t s);
 // whether pcg_iteration_pvq supports this size and U layout (n <= 16384,
 // 16-byte U rows)
