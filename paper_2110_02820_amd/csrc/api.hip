@@ -340,6 +340,7 @@ struct SolveWs {
   // device-info form: per-column state kept on the device
   double *relres_d, *prev_d;
   int *iters_d, *brk_d, *active_d;
+  int* xzero;  // 1 while the start vectors are all zero (their product is skipped)
   bool has_f;
   void* lowp_buf;
   RbfLowp L;
@@ -356,6 +357,7 @@ void carve_solve(Arena& a, const OpDesc& op, int64_t l, int64_t k, int prec, Sol
   w.iters_d = a.take<int>(k);
   w.brk_d = a.take<int>(k);
   w.active_d = a.take<int>(k);
+  w.xzero = a.take<int>(1);
   w.R64 = a.take<double>(n * k);
   w.V64 = a.take<double>(n * k);
   w.X64 = a.take<double>(n * k);
@@ -418,16 +420,39 @@ __global__ void zero_fill(T* __restrict__ p, int64_t count) {
 
 // PCG set-up in one launch: mu (k values) into the run's buffer, the 64
 // counters cleared, and, for a zero initial guess, X and V (n k each) cleared.
+// With xflag (a given start X that may be zero): V cleared and *xflag = 1,
+// which zero_test then clears if X has a nonzero entry.
 template <typename T>
 __global__ void pcg_start(const double* __restrict__ mu_src, double* __restrict__ mu_dst, int64_t k,
-                          unsigned* __restrict__ ctr, T* __restrict__ X, T* __restrict__ V, int64_t nk) {
+                          unsigned* __restrict__ ctr, T* __restrict__ X, T* __restrict__ V, int64_t nk,
+                          int* __restrict__ xflag) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < k) mu_dst[i] = mu_src[i];
   if (i < 64) ctr[i] = 0u;
-  if (X && i < nk) {
-    X[i] = T(0);
+  if ((X || xflag) && i < nk) {
+    if (X) X[i] = T(0);
     V[i] = T(0);
   }
+  if (xflag && i == 0) *xflag = 1;
+}
+
+// *flag = 0 if any of x[0 .. count) is nonzero (all writers store the same
+// value).  A product launched with skip = flag then runs only for a nonzero
+// start: every product kernel returns at once while *flag != 0.
+template <typename T>
+__global__ void zero_test(const T* __restrict__ x, int64_t count, int* __restrict__ flag) {
+  bool nz = false;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+       i += (int64_t)gridDim.x * blockDim.x)
+    nz = nz || x[i] != T(0);
+  if (nz) *flag = 0;
+}
+
+// V (count values) cleared and *flag = 1 (see zero_test)
+__global__ void zero_flag_init(double* __restrict__ V, int64_t count, int* __restrict__ flag) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) V[i] = 0.0;
+  if (i == 0) *flag = 1;
 }
 
 template <typename TS>
@@ -737,15 +762,27 @@ struct PcgResult {
 template <typename T>
 nys_status pcg_run(const OpDesc& op0, const PrecDesc& P, int64_t k, const double* mu_dev,
                    const std::vector<double>& mu_host, const T* B, T* X, bool x0_zero, double tol, int maxit,
-                   int check_every, PcgBufs<T>& b, PcgResult& res, hipStream_t s, bool dev_mode = false) {
+                   int check_every, PcgBufs<T>& b, PcgResult& res, hipStream_t s, bool dev_mode = false,
+                   int* xflag = nullptr) {
   const int64_t n = op0.n;
   OpDesc op = op0;
   op.skip = nullptr;
-  const int64_t cover = std::max<int64_t>(std::max<int64_t>(k, 64), x0_zero ? n * k : 0);
+  // a given start X that is all zero (xflag; not for host callbacks) needs no product
+  if (x0_zero || op.kind == NYS_OP_CALLBACK) xflag = nullptr;
+  const int64_t cover = std::max<int64_t>(std::max<int64_t>(k, 64), (x0_zero || xflag) ? n * k : 0);
   hipLaunchKernelGGL(pcg_start<T>, dim3(nblk(cover)), dim3(256), 0, s, mu_dev, b.mu, k, b.sc.ctr,
-                     x0_zero ? X : (T*)nullptr, b.V, n * k);
+                     x0_zero ? X : (T*)nullptr, b.V, n * k, xflag);
   NYS_CHECK_LAUNCH();
-  if (!x0_zero) NYS_TRY(matvec<T>(op, X, k, b.mu, 1, mu_host[0], b.V, b, s));
+  if (!x0_zero) {
+    if (xflag) {
+      hipLaunchKernelGGL(zero_test<T>, dim3((unsigned)std::min<int64_t>(nblk(n * k), 1024)), dim3(256), 0, s, X,
+                         n * k, xflag);
+      NYS_CHECK_LAUNCH();
+      op.skip = xflag;
+    }
+    NYS_TRY(matvec<T>(op, X, k, b.mu, 1, mu_host[0], b.V, b, s));
+    op.skip = nullptr;
+  }
   NYS_TRY(pcg_setup<T>(n, k, P, b.mu, 1, B, b.V, b.R, b.Z, b.P, b.w, b.sc, tol, s));
   op.skip = b.sc.alldone;
   // device-info form (no compaction): block products skip column blocks whose
@@ -987,10 +1024,18 @@ nys_status pcg_run(const OpDesc& op0, const PrecDesc& P, int64_t k, const double
 // R64 = B64 - (A + mu_c I) X64 in float64 (mu_dev: one mu per column);
 // returns per-column relative residuals.
 nys_status true_residual(const OpDesc& op, int64_t k, const double* mu_dev, double mu0, SolveWs& w,
-                         std::vector<double>& relres, hipStream_t s) {
+                         std::vector<double>& relres, hipStream_t s, bool maybe_zero = false) {
   const int64_t n = op.n;
   OpDesc o = op;
   o.skip = nullptr;
+  if (maybe_zero && op.kind != NYS_OP_CALLBACK) {
+    // an all-zero X (the usual start) needs no product: V stays zero
+    hipLaunchKernelGGL(zero_flag_init, dim3(nblk(n * k)), dim3(256), 0, s, w.V64, n * k, w.xzero);
+    hipLaunchKernelGGL(zero_test<double>, dim3((unsigned)std::min<int64_t>(nblk(n * k), 1024)), dim3(256), 0, s,
+                       w.X64, n * k, w.xzero);
+    NYS_CHECK_LAUNCH();
+    o.skip = w.xzero;
+  }
   if (k == 1 && (op.kind == NYS_OP_XTX || op.kind == NYS_OP_DENSE))
     NYS_TRY(op_matvec<double>(o, w.X64, mu0, w.V64, w.d.opscr, w.d.opscr_elems, s));
   else
@@ -1133,7 +1178,8 @@ nys_status solve_impl(const OpDesc& op, const PrecDesc& P, const double* mu, int
   }
   if (prec == NYS_PREC_FP64) {
     PcgResult r;
-    NYS_TRY(pcg_run<double>(op, P, k, w.mu, mu_col, w.B64, w.X64, false, tol, maxit, check, w.d, r, s));
+    NYS_TRY(pcg_run<double>(op, P, k, w.mu, mu_col, w.B64, w.X64, false, tol, maxit, check, w.d, r, s, false,
+                            w.xzero));
     iters = r.iters;
     status = r.status;
     total = r.sweeps;
@@ -1194,7 +1240,7 @@ nys_status solve_impl(const OpDesc& op, const PrecDesc& P, const double* mu, int
     // the columns that have not yet met the tolerance
     const int max_ref = o->max_refine > 0 ? o->max_refine : 10;
     const double itol = o->inner_tol > 0 ? o->inner_tol : 1e-4;
-    NYS_TRY(true_residual(op, k, w.mu, mu_col[0], w, relres, s));
+    NYS_TRY(true_residual(op, k, w.mu, mu_col[0], w, relres, s, true));
     std::vector<double> prev(relres);
     for (int step = 0; step < max_ref; ++step) {
       std::vector<int> act;
