@@ -172,6 +172,100 @@ __global__ __launch_bounds__(256) void rbf_mv_lowp(RbfLowp L, const float* __res
     }
 }
 
+// One vector using the symmetry of K: the points are cut into super-blocks of
+// 256 cb (cb <= kSymCb) and workgroup (I, J), I <= J, evaluates the tile K_IJ
+// once.  Its rows give part[J][i] = sum_{j in J} K_ij p_j for i in I, and for
+// I < J its columns give part[I][j] = sum_{i in I} K_ij p_i for j in J, so
+// every slot part[Y][x] is written by exactly one workgroup and
+// (K p)[x] = sum_{Y < nsb} part[Y][x]: half the exponentials of the plain
+// form.  Waves take 64 rows of a 256-row sub-block of I as in rbf_mv_lowp;
+// each wave adds its column sums into its own LDS row, and the four rows are
+// added in a fixed order at the end (deterministic).
+constexpr int kSymCb = 8;
+template <int MODE, int KS>
+__global__ __launch_bounds__(256) void rbf_mv_lowp_sym(RbfLowp L, const float* __restrict__ p,
+                                                       float* __restrict__ part, int nsb, int cb,
+                                                       const int* __restrict__ skip) {
+  if (skip && *skip) return;
+  __shared__ float colsum[4][kSymCb * 256];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t n = L.n, npad = L.npad;
+  int I = 0;
+  int64_t b = blockIdx.x;
+  while (b >= nsb - I) {
+    b -= nsb - I;
+    ++I;
+  }
+  const int J = I + (int)b;
+  const bool offd = I != J;
+  const int64_t bs = (int64_t)cb * 256;
+  const int64_t i0 = I * bs, j0 = J * bs;
+  const int64_t i1 = i0 + bs < npad ? i0 + bs : npad, j1 = j0 + bs < npad ? j0 + bs : npad;
+  const float two_s = L.two_s;
+  if (offd)
+    for (int x = lane; x < bs; x += 64) colsum[wave][x] = 0.0f;
+  for (int64_t rb = i0; rb < i1; rb += 256) {
+    const int64_t row0 = rb + wave * 64;
+    Operand<MODE> a[4];
+    f4 cinit[4], acc[4];
+    float prow[4][4];
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+      a[f].load(L, row0 + f * 16 + (lane & 15), lane);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int64_t row = row0 + f * 16 + 4 * (lane >> 4) + q;
+        cinit[f][q] = -L.hs[row] / two_s;
+        acc[f][q] = 0.0f;
+        prow[f][q] = row < n ? p[row] : 0.0f;
+      }
+    }
+    for (int64_t jt = j0; jt < j1; jt += 16) {
+      const int64_t j = jt + (lane & 15);
+      Operand<MODE> bo;
+      bo.load(L, j, lane);  // rows beyond n are zero padding
+      const float hj = L.hs[j];
+      const float pj = (j < n) ? p[j] : 0.0f;
+      float cs = 0.0f;
+#pragma unroll
+      for (int f = 0; f < 4; ++f) {
+        const f4 dg = gram_tile<KS>(a[f], bo, cinit[f]);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const float e = __builtin_amdgcn_exp2f(fmaf(two_s, dg[q], -hj));
+          acc[f][q] = fmaf(e, pj, acc[f][q]);
+          cs = fmaf(e, prow[f][q], cs);
+        }
+      }
+      if (offd) {
+        // column l % 16 of the wave's 64 rows: add the four lane groups
+        cs += __shfl_xor(cs, 16, 64);
+        cs += __shfl_xor(cs, 32, 64);
+        if (lane < 16) colsum[wave][jt - j0 + lane] += cs;
+      }
+    }
+    // rows: sum over the 16 columns held by lanes with the same l / 16
+#pragma unroll
+    for (int f = 0; f < 4; ++f)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        float v = acc[f][q];
+        v += __shfl_xor(v, 1, 64);
+        v += __shfl_xor(v, 2, 64);
+        v += __shfl_xor(v, 4, 64);
+        v += __shfl_xor(v, 8, 64);
+        const int64_t row = row0 + f * 16 + 4 * (lane >> 4) + q;
+        if ((lane & 15) == 0 && row < n) part[(int64_t)J * n + row] = v;
+      }
+  }
+  if (offd) {
+    __syncthreads();
+    for (int64_t x = threadIdx.x; x < j1 - j0; x += 256)
+      if (j0 + x < n)
+        part[(int64_t)I * n + j0 + x] = (colsum[0][x] + colsum[1][x]) + (colsum[2][x] + colsum[3][x]);
+  }
+}
+
 // Block of columns: V[I, cb*64 .. +63] = scale * K_IJ P_J (+ mu_c P) over all J,
 // float32.  Block = 4 waves, 64 rows x 64 output columns; per point tile of
 // 32: stage 1 forms K (64 x 32, wave w rows w*16..) with the Gram MFMA and
@@ -670,6 +764,39 @@ nys_status rbf_lowp_prepare(const OpDesc& op, void* buf, RbfLowp& L, hipStream_t
 nys_status rbf_lowp_mv_partials(const RbfLowp& L, int mode, const float* p, float* part, size_t part_elems,
                                 int* ng_out, const int* skip, hipStream_t s) {
   const int64_t n = L.n;
+  // symmetric form: super-blocks of 256 cb points, about 48 of them (at most
+  // 64 partial slots; larger n keeps the plain form, whose slots stay few)
+  {
+    const int64_t nb256 = cdiv(L.npad, 256);
+    int64_t cb = cdiv(nb256, 48);
+    if (cb < 1) cb = 1;
+    if (cb > kSymCb) cb = kSymCb;
+    const int64_t nsb = cdiv(nb256, cb);
+    if (cb <= kSymCb && nsb <= 64 && (size_t)(nsb * n) <= part_elems) {
+      const unsigned pairs = (unsigned)(nsb * (nsb + 1) / 2);
+      if (mode == 0)
+        hipLaunchKernelGGL((rbf_mv_lowp_sym<0, 1>), dim3(pairs), dim3(256), 0, s, L, p, part, (int)nsb, (int)cb,
+                           skip);
+      else
+        switch (ks_for(L.ksteps)) {
+          case 2:
+            hipLaunchKernelGGL((rbf_mv_lowp_sym<1, 2>), dim3(pairs), dim3(256), 0, s, L, p, part, (int)nsb, (int)cb,
+                               skip);
+            break;
+          case 4:
+            hipLaunchKernelGGL((rbf_mv_lowp_sym<1, 4>), dim3(pairs), dim3(256), 0, s, L, p, part, (int)nsb, (int)cb,
+                               skip);
+            break;
+          default:
+            hipLaunchKernelGGL((rbf_mv_lowp_sym<1, 8>), dim3(pairs), dim3(256), 0, s, L, p, part, (int)nsb, (int)cb,
+                               skip);
+            break;
+        }
+      NYS_CHECK_LAUNCH();
+      *ng_out = (int)nsb;
+      return NYS_OK;
+    }
+  }
   const int64_t nrb = cdiv(n, 256);
   const int cus = num_cus() < 256 ? num_cus() : 256;
   int64_t ns = cdiv(8 * cus, nrb);  // about eight blocks per compute unit
