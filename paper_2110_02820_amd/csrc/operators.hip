@@ -188,6 +188,124 @@ __global__ __launch_bounds__(256) void rbf_mv_f64m(const TD* __restrict__ Xr, in
   }
 }
 
+// Pair b of the upper triangle (I <= J) of an nsb x nsb block grid, row by
+// row: I = the largest with I nsb - I (I - 1) / 2 <= b.
+__device__ __forceinline__ void tri_pair(int64_t b, int nsb, int& I, int& J) {
+  const double w = 2.0 * nsb + 1.0;
+  int64_t i = (int64_t)((w - sqrt(w * w - 8.0 * (double)b)) * 0.5);
+  auto off = [&](int64_t x) { return x * nsb - x * (x - 1) / 2; };
+  if (i < 0) i = 0;
+  while (i > 0 && off(i) > b) --i;
+  while (off(i + 1) <= b) ++i;
+  I = (int)i;
+  J = (int)(i + (b - off(i)));
+}
+
+// One vector, square, float64, using the symmetry of K: the points are cut
+// into super-blocks of SP and workgroup (I, J), I <= J, evaluates K_IJ once.
+// Its rows give part[J][i] = sum_{j in J} K_ij p_j (i in I) and, for I < J,
+// its columns give part[I][j] = sum_{i in I} K_ij p_i (j in J): every slot is
+// written by one workgroup and (K p)[x] = sum_{Y < nsb} part[Y][x], with half
+// the exponentials of rbf_mv_f64m.  J's points are staged in LDS once; the
+// rows of I pass in sub-blocks of 64 (wave w: 16 rows, lane layout as in
+// rbf_mv_f64m, compensated row sums); column sums go to per-wave LDS rows
+// added in a fixed order at the end.
+template <typename TD, int KS>
+__global__ __launch_bounds__(256) void rbf_mv_f64_sym(const TD* __restrict__ X, int64_t n, int64_t ld, int d,
+                                                      double c2, const double* __restrict__ p,
+                                                      double* __restrict__ part, int nsb,
+                                                      const int* __restrict__ skip) {
+  if (skip && *skip) return;
+  constexpr int DW = 4 * KS;
+  constexpr int SP = KS <= 8 ? 256 : 128;
+  __shared__ double Xs[SP][DW + 1];
+  __shared__ double Ns[SP], Ps[SP];
+  __shared__ double colsum[4][SP];
+  int I, J;
+  tri_pair(blockIdx.x, nsb, I, J);
+  const bool offd = I != J;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int64_t i0 = (int64_t)I * SP, j0 = (int64_t)J * SP;
+  for (int e = t; e < SP * DW; e += 256) {
+    const int jj = e / DW, kk = e % DW;
+    const int64_t j = j0 + jj;
+    Xs[jj][kk] = (j < n && kk < d) ? double(X[j * ld + kk]) : 0.0;
+  }
+  __syncthreads();
+  for (int x = t; x < SP; x += 256) {
+    double sn = 0.0;
+#pragma unroll
+    for (int kk = 0; kk < DW; ++kk) sn += Xs[x][kk] * Xs[x][kk];
+    Ns[x] = sn;
+    Ps[x] = (j0 + x < n) ? p[j0 + x] : 0.0;
+#pragma unroll
+    for (int w = 0; w < 4; ++w) colsum[w][x] = 0.0;
+  }
+  __syncthreads();
+  for (int sb = 0; sb < SP / 64; ++sb) {
+    const int64_t ib = i0 + sb * 64 + wave * 16;  // this wave's 16 rows
+    double a[KS];
+    double nrm = 0.0;
+    {
+      const int64_t r = ib + (lane & 15);
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks) {
+        const int kk = 4 * ks + (lane >> 4);
+        a[ks] = (r < n && kk < d) ? double(X[r * ld + kk]) : 0.0;
+        nrm += a[ks] * a[ks];
+      }
+    }
+    nrm += __shfl_xor(nrm, 16, 64);
+    nrm += __shfl_xor(nrm, 32, 64);  // every lane: ||x||^2 of row l % 16
+    double ni[4], prow[4];
+    double acc[4] = {0.0, 0.0, 0.0, 0.0}, cmp[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      ni[q] = __shfl(nrm, 4 * q + (lane >> 4), 64);
+      const int64_t row = ib + 4 * q + (lane >> 4);
+      prow[q] = row < n ? p[row] : 0.0;
+    }
+    for (int st = 0; st < SP / 16; ++st) {
+      const int pt = st * 16 + (lane & 15);
+      d4 g = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks) g = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ks], Xs[pt][4 * ks + (lane >> 4)], g, 0, 0, 0);
+      const double nj = Ns[pt], pj = Ps[pt];
+      double cs = 0.0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const double d2 = fmax(ni[q] + nj - 2.0 * g[q], 0.0);
+        const double kv = exp(-d2 * c2);
+        const double y = kv * pj - cmp[q];
+        const double ts = acc[q] + y;
+        cmp[q] = (ts - acc[q]) - y;
+        acc[q] = ts;
+        cs = fma(kv, prow[q], cs);
+      }
+      if (offd) {
+        cs += __shfl_xor(cs, 16, 64);
+        cs += __shfl_xor(cs, 32, 64);
+        if (lane < 16) colsum[wave][st * 16 + lane] += cs;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      double v = acc[q] - cmp[q];
+      for (int o = 1; o < 16; o <<= 1) v += __shfl_xor(v, o, 64);
+      const int64_t row = ib + 4 * q + (lane >> 4);
+      if ((lane & 15) == 0 && row < n) part[(int64_t)J * n + row] = v;
+    }
+  }
+  if (offd) {
+    __syncthreads();
+    for (int x = t; x < SP; x += 256)
+      if (j0 + x < n) part[(int64_t)I * n + j0 + x] = (colsum[0][x] + colsum[1][x]) + (colsum[2][x] + colsum[3][x]);
+  }
+}
+
+// Points per super-block of rbf_mv_f64_sym for d coordinates.
+int rbf_sym_sp(int d) { return d <= 32 ? 256 : 128; }
+
 // Launches rbf_mv_f64m with the fewest coordinate steps that cover d (<= 64).
 template <typename TD, int MODE>
 void launch_rbf_mv_f64(dim3 grid, hipStream_t s, const TD* Xr, int64_t nr, int64_t ldr, const TD* Xc,
@@ -366,6 +484,24 @@ nys_status rbf_apply_f64_t(const OpDesc& op, const double* P, int64_t k, int64_t
   const int64_t nrb = cdiv(n, RB_ROWS);
   const int cus = num_cus() < 256 ? num_cus() : 256;
   if (k == 1 && ldp == 1) {
+    // large n: the symmetric form (half the exponentials; n / SP partial slots)
+    const int sp = rbf_sym_sp(d);
+    const int64_t nsb = cdiv(n, sp);
+    if (n >= 16384 && (size_t)(nsb * n) <= scratch_elems) {
+      const unsigned pairs = (unsigned)(nsb * (nsb + 1) / 2);
+#define LS(KS) hipLaunchKernelGGL((rbf_mv_f64_sym<TD, KS>), dim3(pairs), dim3(256), 0, s, X, n, op.ld, d, c2, P, scratch, (int)nsb, op.skip)
+      if (d <= 4) LS(1);
+      else if (d <= 8) LS(2);
+      else if (d <= 16) LS(4);
+      else if (d <= 32) LS(8);
+      else LS(16);
+#undef LS
+      NYS_CHECK_LAUNCH();
+      hipLaunchKernelGGL(reduce_splits_mu, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, s, scratch,
+                         (int)nsb, n, (int64_t)1, op.scale, P, ldp, mu_dev, nrhs, V, ldv, op.skip);
+      NYS_CHECK_LAUNCH();
+      return NYS_OK;
+    }
     int64_t ns = cdiv(4 * cus, nrb);
     if (ns < 1) ns = 1;
     while (ns > 1 && (size_t)(ns * n) > scratch_elems) --ns;

@@ -182,6 +182,9 @@ __global__ __launch_bounds__(256) void rbf_mv_lowp(RbfLowp L, const float* __res
 // each wave adds its column sums into its own LDS row, and the four rows are
 // added in a fixed order at the end (deterministic).
 constexpr int kSymCb = 8;
+#ifndef NYS_SYM_NSB
+#define NYS_SYM_NSB 128
+#endif
 template <int MODE, int KS>
 __global__ __launch_bounds__(256) void rbf_mv_lowp_sym(RbfLowp L, const float* __restrict__ p,
                                                        float* __restrict__ part, int nsb, int cb,
@@ -764,15 +767,16 @@ nys_status rbf_lowp_prepare(const OpDesc& op, void* buf, RbfLowp& L, hipStream_t
 nys_status rbf_lowp_mv_partials(const RbfLowp& L, int mode, const float* p, float* part, size_t part_elems,
                                 int* ng_out, const int* skip, hipStream_t s) {
   const int64_t n = L.n;
-  // symmetric form: super-blocks of 256 cb points, about 48 of them (at most
-  // 64 partial slots; larger n keeps the plain form, whose slots stay few)
+  // symmetric form: super-blocks of 256 cb points, about NYS_SYM_NSB of them
+  // (at most 256 partial slots; larger n keeps the plain form, whose slots
+  // stay few)
   {
     const int64_t nb256 = cdiv(L.npad, 256);
-    int64_t cb = cdiv(nb256, 48);
+    int64_t cb = cdiv(nb256, NYS_SYM_NSB);
     if (cb < 1) cb = 1;
     if (cb > kSymCb) cb = kSymCb;
     const int64_t nsb = cdiv(nb256, cb);
-    if (cb <= kSymCb && nsb <= 64 && (size_t)(nsb * n) <= part_elems) {
+    if (nsb <= 256 && (size_t)(nsb * n) <= part_elems) {
       const unsigned pairs = (unsigned)(nsb * (nsb + 1) / 2);
       if (mode == 0)
         hipLaunchKernelGGL((rbf_mv_lowp_sym<0, 1>), dim3(pairs), dim3(256), 0, s, L, p, part, (int)nsb, (int)cb,

@@ -125,6 +125,31 @@ def test_krr_100000x32_products_and_full_residual():
     assert abs(rel - info.relres[0]) <= 1e-12
 
 
+def test_rbf_symmetric_products_every_row():
+    """The single-vector RBF products that evaluate each pair of point
+    super-blocks once (rows and columns of the tile): n = 20000 (a ragged last
+    super-block), d = 8, every entry against the oracle's float64 product.
+    Float64 product (the refinement residual at n >= 16384): |error_i| <=
+    1e-12 (|K| |v| + mu |v|)_i; bf16x3 product: 5e-4 of the same bound, as for
+    the other bf16x3 Gram products."""
+    w = krr_mixture(n=20000, d=8, ell=8, with_omega=False)
+    Xd = w["X"].astype(np.float64)
+    mu, sigma = w["mu"], w["sigma"]
+    op = nys.Operator.rbf(dev(w["X"], torch.float32), sigma)
+    opr = oracle.RBFOp(Xd, sigma)
+    rng = np.random.default_rng(73)
+    v = rng.standard_normal(20000)
+    say("symmetric products: oracle K v, K |v| (%d threads)" % WORKERS)
+    want = opr.matmat(v, workers=WORKERS, block=512) + mu * v
+    scale = opr.matmat(np.abs(v), workers=WORKERS, block=512) + mu * np.abs(v)
+    z64 = h(nys.nys_op_apply(op, mu, dev(v)))
+    assert (np.abs(z64 - want) / scale).max() <= 1e-12
+    v32 = v.astype(np.float32).astype(np.float64)
+    want32 = opr.matmat(v32, workers=WORKERS, block=512) + mu * v32
+    z3 = h(nys.nys_op_apply(op, mu, dev(v, torch.float32), prec=nys.NYS_PREC_BF16X3_REFINE64))
+    assert (np.abs(z3 - want32) / scale).max() <= 5e-4
+
+
 def test_batched_50000x16_mu_grid_full_residuals():
     """Batched cross-validation: one sketch (n = 5e4, d = 16, l = 800, float32
     Gram tiles) for 32 mu x 8 right-hand sides in one block solve.  The
