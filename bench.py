@@ -98,15 +98,35 @@ def parse():
 
 
 class Timer:
+    """Phase times from events recorded on the current stream at the end of
+    each phase: nothing synchronises inside the timed region, so the host
+    enqueues the next phase while the device still runs the last one.  A
+    phase runs from the previous event (or the timer's creation) to its own;
+    reading .t synchronises once and returns seconds per phase."""
+
     def __init__(self, torch):
         self.torch = torch
-        self.t = {}
+        self.ev = []
+        self.last = self._event()
+
+    def _event(self):
+        e = self.torch.cuda.Event(enable_timing=True)
+        e.record()
+        return e
 
     def lap(self, key, t0):
+        e = self._event()
+        self.ev.append((key, self.last, e))
+        self.last = e
+        return time.perf_counter()
+
+    @property
+    def t(self):
         self.torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        self.t[key] = self.t.get(key, 0.0) + (t1 - t0)
-        return t1
+        out = {}
+        for key, a, b in self.ev:
+            out[key] = out.get(key, 0.0) + 1e-3 * a.elapsed_time(b)
+        return out
 
 
 def full_solve(nys, torch, op, ell, seed, prec, udtype, mus, B, ws, tol, timer, cols=None, **kw):
