@@ -107,4 +107,18 @@ __device__ __forceinline__ T block_sum(T v, T* sh) {
   return r;
 }
 
+// block_sum with one barrier: every thread adds the per-wave sums in the same
+// order.  `sh` (blockDim.x/64 entries) must not be written again until every
+// thread has read it: give each call its own array, or put a barrier between.
+template <typename T>
+__device__ __forceinline__ T block_sum1(T v, T* sh) {
+  v = wave_sum(v);
+  const int nw = blockDim.x >> 6;
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  T r = sh[0];
+  for (int w = 1; w < nw; ++w) r += sh[w];
+  return r;
+}
+
 }  // namespace nys

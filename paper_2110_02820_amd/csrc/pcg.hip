@@ -680,9 +680,9 @@ __global__ __launch_bounds__(NT) void cg_finish_pvq(int64_t n, const T* __restri
                                                     CgScalars sc, int par) {
   typedef typename UVec<TU>::type VT;
   constexpr int E = UVec<TU>::E;
-  constexpr int RB = 8;  // rows of U in flight per thread
+  constexpr int RB = CG == 1 ? 16 : 8;  // rows of U in flight per thread
   __shared__ T shp[8][33];
-  __shared__ double sh[NT];
+  __shared__ double sh[NT / 64], sh2[NT / 64];
   __shared__ double rs[32];
   __shared__ double red[NT * E];  // the groups' sums when G > 1
   const int skip_all = *sc.alldone;
@@ -735,7 +735,7 @@ __global__ __launch_bounds__(NT) void cg_finish_pvq(int64_t n, const T* __restri
   double q = 0.0, qp = 0.0;
   for (int g = threadIdx.x; g < npvq; g += NT) q += pvq[g];
   for (int g = threadIdx.x; g < npp; g += NT) qp += pvq[npvq + g];
-  const double pv = block_sum(scale * q + mu * qp, sh);
+  const double pv = block_sum1(scale * q + mu * qp, sh);
   if (skip_all) return;  // the same value for every thread
   const int done = sc.done[0];
   const double a_d = (done || !(pv > 0.0)) ? 0.0 : sc.rz[par] / pv;
@@ -803,7 +803,7 @@ __global__ __launch_bounds__(NT) void cg_finish_pvq(int64_t n, const T* __restri
       apart[(int64_t)blockIdx.x * l + i] = tot;
     }
   }
-  const double rr = block_sum(rrp, sh);
+  const double rr = block_sum1(rrp, sh2);
   if (threadIdx.x == 0) prr[blockIdx.x] = rr;
 }
 
@@ -854,10 +854,12 @@ __global__ __launch_bounds__(NT) void utr_final_rr(int64_t l, int nch, const dou
   }
   // r^T z = ||r||^2 + w^T D w (z = r + U D w): this workgroup's part of the
   // second term, and ||r||^2 from workgroup 0, for the apply that follows
-  wdw = block_sum(wdw, sh);
-  if (threadIdx.x == 0) rzq[blockIdx.x] = wdw;
+  if (ty == 0) {  // only wave 0 holds columns
+    wdw = wave_sum(wdw);
+    if (tx == 0) rzq[blockIdx.x] = wdw;
+  }
   if (blockIdx.x != 0) return;
-  const double rr = block_sum(s, sh);
+  const double rr = block_sum1(s, sh);
   if (threadIdx.x == 0) rzq[gridDim.x] = rr;
   if (threadIdx.x == 0 && !done0) {
     sc.rnorm2[0] = rr;
@@ -951,7 +953,7 @@ __global__ __launch_bounds__(NT) void uc_vec(int64_t n, int64_t l, const TU* __r
     const double rz_old = sc.rz[par];
     double q = 0.0;
     for (int i = threadIdx.x; i <= nq; i += NT) q += prz[i];
-    const double rzn = block_sum(q, shq);
+    const double rzn = block_sum1(q, shq);
     dn = done_old || conv;
     const double beta = done_old ? 0.0 : rzn / rz_old;
     bz = T(beta);
