@@ -853,20 +853,28 @@ __device__ void phase1_task(const JacArgs& a, int64_t g, int k) {
   const bool cross = r > 0 && a.inner_sweeps == 1;
   int cur = 0;
   float r2loc = 0.0f;
-  for (int isw = 0; isw < a.inner_sweeps; ++isw) {
-    if (t == 0) any_s = 0;
-    __syncthreads();
+  if (a.inner_sweeps == 1) {
+    // one inner sweep: no early exit to decide, so no barrier around it
+    // (every writer of `rotated` stores 1; the barrier below publishes it)
     bool any_local = false;
     if (cross)
       jac_inner<true>(Sb, Jm, k1, k2, JB, floor_abs, cur, any_local, r2loc);
     else
       jac_inner<false>(Sb, Jm, k1, k2, JS - 1, floor_abs, cur, any_local, r2loc);
-    if (any_local) any_s = 1;
-    __syncthreads();
-    if (any_s) rotated = 1;
-    __syncthreads();
-    if (!any_s) break;
-    __syncthreads();
+    if (any_local) rotated = 1;
+  } else {
+    for (int isw = 0; isw < a.inner_sweeps; ++isw) {
+      if (t == 0) any_s = 0;
+      __syncthreads();
+      bool any_local = false;
+      jac_inner<false>(Sb, Jm, k1, k2, JS - 1, floor_abs, cur, any_local, r2loc);
+      if (any_local) any_s = 1;
+      __syncthreads();
+      if (any_s) rotated = 1;
+      __syncthreads();
+      if (!any_s) break;
+      __syncthreads();
+    }
   }
   {  // wave maximum of the rotated ratios first: one LDS atomic per wave
     for (int off = 32; off > 0; off >>= 1) r2loc = fmaxf(r2loc, __shfl_xor(r2loc, off));
