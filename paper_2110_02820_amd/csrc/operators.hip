@@ -7,8 +7,10 @@
 //  * RBF      : K_ij = exp(-||x_i - x_j||^2 / (2 sigma^2)) evaluated tile by
 //               tile and never stored (Section 6.5 kernel ridge regression).
 //               float64 forms, both with the Gram on v_mfma_f64_16x16x4f64:
-//               one vector (exp and compensated sum on the vector units),
-//               and blocks of columns (the sketch A Omega, block PCG).
+//               one vector (exp and compensated sum on the vector units;
+//               for n >= 16384 each pair of point super-blocks once, K being
+//               symmetric), and blocks of columns (the sketch A Omega, block
+//               PCG).
 #include "operators.hpp"
 #include "xtx.hpp"
 #include "gemm.hpp"

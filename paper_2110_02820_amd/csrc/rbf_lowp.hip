@@ -12,7 +12,9 @@
 // MFMA accumulator input (C = -h_i / (2 s)), so each kernel entry costs one
 // FMA, one v_exp_f32 and one FMA with the vector.  Coordinates are padded to
 // 32 (one bf16 MFMA step, eight f32 steps); rows are padded to a multiple of
-// 256 with zeros, so operand loads never leave the prepared arrays.
+// 256 with zeros, so operand loads never leave the prepared arrays.  Products
+// with one vector evaluate each pair of point super-blocks once (K is
+// symmetric: its rows and its columns both serve), block products every tile.
 #include "rbf_lowp.hpp"
 
 #include <cstdio>
@@ -115,7 +117,8 @@ __device__ __forceinline__ f4 gram_tile(const Operand<0>& a, const Operand<0>& b
 // coordinates are zero); the bf16x3 Gram always takes one 32-wide step
 __host__ __device__ constexpr int ks_for(int ksteps) { return ksteps <= 2 ? 2 : ksteps <= 4 ? 4 : 8; }
 
-// One vector: part[split][i] = sum_{j in split} K_ij p_j.  Block = 4 waves,
+// One vector, every entry evaluated (the form for n past the symmetric
+// form's 256 partial slots): part[split][i] = sum_{j in split} K_ij p_j.  Block = 4 waves,
 // wave w owns rows rb*256 + w*64 .. + 63 (four 16-row fragments); the lanes
 // of a wave walk the points of the split 16 at a time.  Accumulator element
 // q of lane l belongs to row 4 (l/16) + q of a fragment and column l % 16.
