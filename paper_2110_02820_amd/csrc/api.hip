@@ -269,6 +269,9 @@ void carve_sketch(Arena& a, const OpDesc& op, int64_t l, int prec, SketchWs& w) 
     w.T32 = a.take<float>(op.rows * l);
     w.Y32 = a.take<float>(op.n * l);
     w.f32scr_elems = gemm_scratch_elems(op.n, l);
+    // bf16x3 products: room for B split into bf16 pieces once per product
+    if (prec == NYS_PREC_BF16X3_REFINE64)
+      w.f32scr_elems += gemm_bf16x3_split_elems(op.rows > op.n ? op.rows : op.n, l) + 4;
     w.f32scr = a.take<float>(w.f32scr_elems);
   }
 }

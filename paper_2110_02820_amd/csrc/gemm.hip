@@ -305,10 +305,20 @@ constexpr int XK = NYS_GEMM_XK, XPAD = XK + 8;  // k per staged slab (a multiple
 constexpr int XR = XK / 8;                      // runs of 4 k per thread per operand and slab
 constexpr int XQ = XK / 4;                      // runs of 4 k per row of a slab
 
-template <bool TA, bool TB>
+// B split once into bf16 hi / lo, column-major by k: element (k, n) at
+// [n * ldk + k], ldk a multiple of XK, zeros past K (split_b_bf16).
+struct SplitB {
+  const __bf16* hi;
+  const __bf16* lo;
+  int64_t ldk;
+};
+
+// PB: B comes pre-split (SplitB) and is copied into LDS as it stands, two
+// 16-byte runs of 8 k per thread and piece; else B is split on the way in.
+template <bool TA, bool TB, bool PB>
 __global__ __launch_bounds__(NT) void gemm_bf16x3(int64_t M, int64_t N, int64_t K, int64_t kchunk, float alpha,
                                                   const float* __restrict__ A, int64_t lda,
-                                                  const float* __restrict__ B, int64_t ldb, float beta,
+                                                  const float* __restrict__ B, int64_t ldb, SplitB bs, float beta,
                                                   float* __restrict__ C, int64_t ldc, float* __restrict__ part,
                                                   const int* __restrict__ skip) {
   if (skip && *skip) return;
@@ -325,7 +335,24 @@ __global__ __launch_bounds__(NT) void gemm_bf16x3(int64_t M, int64_t N, int64_t 
   const int64_t ke = (kb + kchunk < K) ? kb + kchunk : K;
   // each thread stages XR runs of 4 consecutive k for A and for B (128 x XK each)
   float ra[XR][4], rb[XR][4];
+  constexpr int PR = LN * XK / 8 / NT;  // pre-split B: 16-byte runs of 8 k per thread and piece
+  uint4 rbh[PR], rbl[PR];
   auto load = [&](int64_t k0) {
+    if (PB) {
+#pragma unroll
+      for (int r = 0; r < PR; ++r) {
+        const int e = t + NT * r, col = e / (XK / 8), k8 = e % (XK / 8);
+        const int64_t gn = n0 + col;
+        if (gn < N) {
+          const int64_t o = gn * bs.ldk + k0 + 8 * k8;  // k0 + XK <= ldk (zero padded)
+          rbh[r] = *reinterpret_cast<const uint4*>(bs.hi + o);
+          rbl[r] = *reinterpret_cast<const uint4*>(bs.lo + o);
+        } else {
+          rbh[r] = make_uint4(0u, 0u, 0u, 0u);
+          rbl[r] = make_uint4(0u, 0u, 0u, 0u);
+        }
+      }
+    }
 #pragma unroll
     for (int r = 0; r < XR; ++r) {
       const int e = t + NT * r;
@@ -341,6 +368,7 @@ __global__ __launch_bounds__(NT) void gemm_bf16x3(int64_t M, int64_t N, int64_t 
         for (int u = 0; u < 4; ++u)
           ra[r][u] = (gm < M && gk + u < ke) ? (TA ? A[(gk + u) * lda + gm] : A[gm * lda + gk + u]) : 0.0f;
       }
+      if (PB) continue;
       const int col = TB ? (e / XQ) : (e & (LN - 1));
       const int kqb = TB ? (e % XQ) : (e >> 7);
       const int64_t gn = n0 + col, gkb = k0 + 4 * kqb;
@@ -364,11 +392,20 @@ __global__ __launch_bounds__(NT) void gemm_bf16x3(int64_t M, int64_t N, int64_t 
       split_bf16x4(ra[r], h, l);
       *reinterpret_cast<bf4v*>(&Ah[row][4 * kq]) = h;
       *reinterpret_cast<bf4v*>(&Al[row][4 * kq]) = l;
+      if (PB) continue;
       const int col = TB ? (e / XQ) : (e & (LN - 1));
       const int kqb = TB ? (e % XQ) : (e >> 7);
       split_bf16x4(rb[r], h, l);
       *reinterpret_cast<bf4v*>(&Bh[col][4 * kqb]) = h;
       *reinterpret_cast<bf4v*>(&Bl[col][4 * kqb]) = l;
+    }
+    if (PB) {
+#pragma unroll
+      for (int r = 0; r < PR; ++r) {
+        const int e = t + NT * r, col = e / (XK / 8), k8 = e % (XK / 8);
+        *reinterpret_cast<uint4*>(&Bh[col][8 * k8]) = rbh[r];
+        *reinterpret_cast<uint4*>(&Bl[col][8 * k8]) = rbl[r];
+      }
     }
   };
   f4 acc[4][4];
@@ -422,6 +459,42 @@ __global__ __launch_bounds__(NT) void gemm_bf16x3(int64_t M, int64_t N, int64_t 
           }
         }
       }
+}
+
+// B (K x N, or N x K stored when tb) -> hi / lo bf16 pieces at [n * ldk + k]
+// (round to nearest even, as split_bf16x4), zeros for K <= k < ldk.  32 x 32
+// tiles through LDS so that both the reads of B and the writes are coalesced.
+__global__ __launch_bounds__(256) void split_b_bf16(int64_t K, int64_t N, const float* __restrict__ B, int64_t ldb,
+                                                    int tb, int64_t ldk, __bf16* __restrict__ hi,
+                                                    __bf16* __restrict__ lo) {
+  __shared__ float tile[32][33];
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
+  const int64_t k0 = (int64_t)blockIdx.x * 32, n0 = (int64_t)blockIdx.y * 32;
+  // read: rows of B's storage run along its contiguous index
+#pragma unroll
+  for (int r = ty; r < 32; r += 8) {
+    float v = 0.0f;
+    if (tb) {  // B stored N x K: contiguous in k
+      const int64_t n = n0 + r, k = k0 + tx;
+      if (n < N && k < K) v = B[n * ldb + k];
+      tile[r][tx] = v;  // [n][k]
+    } else {   // B stored K x N: contiguous in n
+      const int64_t k = k0 + r, n = n0 + tx;
+      if (n < N && k < K) v = B[k * ldb + n];
+      tile[tx][r] = v;  // [n][k]
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = ty; r < 32; r += 8) {
+    const int64_t n = n0 + r, k = k0 + tx;
+    if (n < N && k < ldk) {
+      const float v = tile[r][tx];
+      const __bf16 h = (__bf16)v;
+      hi[n * ldk + k] = h;
+      lo[n * ldk + k] = (__bf16)(v - (float)h);
+    }
+  }
 }
 
 template <typename TC>
@@ -535,15 +608,12 @@ template nys_status gemm<float, float, double>(bool, bool, int64_t, int64_t, int
                                                const float*, int64_t, const double*, int64_t, float,
                                                float*, int64_t, float*, size_t, hipStream_t, const int*);
 
-nys_status gemm_bf16x3(bool ta, bool tb, int64_t M, int64_t N, int64_t K, float alpha, const float* A, int64_t lda,
-                       const float* B, int64_t ldb, float beta, float* C, int64_t ldc, float* scratch,
-                       size_t scratch_elems, hipStream_t s) {
-  if (M <= 0 || N <= 0) return NYS_OK;
-  // float4 loads along k need 16-byte aligned rows
-  const bool vec_a = ta || ((lda % 4 == 0) && ((uintptr_t)A % 16 == 0));
-  const bool vec_b = !tb || ((ldb % 4 == 0) && ((uintptr_t)B % 16 == 0));
-  if (!vec_a || !vec_b || K % 4 != 0)
-    return gemm<float, float, float>(ta, tb, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, scratch, scratch_elems, s);
+namespace {
+
+// Launches of one bf16x3 product; bs.hi != nullptr: B pre-split.
+nys_status gemm_bf16x3_run(bool ta, bool tb, int64_t M, int64_t N, int64_t K, float alpha, const float* A,
+                           int64_t lda, const float* B, int64_t ldb, SplitB bs, float beta, float* C, int64_t ldc,
+                           float* scratch, size_t scratch_elems, hipStream_t s) {
   const int64_t nt = cdiv(N, LN), lt = cdiv(M, LM) * nt;
   // two workgroups of this kernel fit on a compute unit: one round of tiles
   const int64_t target = 2 * (int64_t)(num_cus() < 256 ? num_cus() : 256);
@@ -554,10 +624,11 @@ nys_status gemm_bf16x3(bool ta, bool tb, int64_t M, int64_t N, int64_t K, float 
     // 20000 x 500 product: 628 tiles for 512 slots)
     const int64_t m1 = (target / nt) * LM;
     if (m1 > 0 && m1 < M) {
-      NYS_TRY(gemm_bf16x3(ta, tb, m1, N, K, alpha, A, lda, B, ldb, beta, C, ldc, scratch, scratch_elems, s));
+      NYS_TRY(gemm_bf16x3_run(ta, tb, m1, N, K, alpha, A, lda, B, ldb, bs, beta, C, ldc, scratch, scratch_elems,
+                              s));
       const float* A2 = ta ? A + m1 : A + m1 * lda;
-      return gemm_bf16x3(ta, tb, M - m1, N, K, alpha, A2, lda, B, ldb, beta, C + m1 * ldc, ldc, scratch,
-                         scratch_elems, s);
+      return gemm_bf16x3_run(ta, tb, M - m1, N, K, alpha, A2, lda, B, ldb, bs, beta, C + m1 * ldc, ldc, scratch,
+                             scratch_elems, s);
     }
   }
   int64_t nz = 1;
@@ -571,13 +642,21 @@ nys_status gemm_bf16x3(bool ta, bool tb, int64_t M, int64_t N, int64_t K, float 
   nz = cdiv(K, kchunk);
   dim3 grid((unsigned)(8 * cdiv(lt, 8)), (unsigned)nz);
   float* part = nz > 1 ? scratch : nullptr;
-#define NYS_GEMM_B3(TA_, TB_)                                                                             \
-  hipLaunchKernelGGL((gemm_bf16x3<TA_, TB_>), grid, dim3(NT), 0, s, M, N, K, kchunk, alpha, A, lda, B, ldb, beta, \
-                     C, ldc, part, (const int*)nullptr)
-  if (!ta && !tb) NYS_GEMM_B3(false, false);
-  else if (!ta && tb) NYS_GEMM_B3(false, true);
-  else if (ta && !tb) NYS_GEMM_B3(true, false);
-  else NYS_GEMM_B3(true, true);
+#define NYS_GEMM_B3(TA_, TB_, PB_)                                                                            \
+  hipLaunchKernelGGL((gemm_bf16x3<TA_, TB_, PB_>), grid, dim3(NT), 0, s, M, N, K, kchunk, alpha, A, lda, B, ldb, \
+                     bs, beta, C, ldc, part, (const int*)nullptr)
+  if (bs.hi) {
+    if (ta) NYS_GEMM_B3(true, false, true);
+    else NYS_GEMM_B3(false, false, true);
+  } else if (!ta && !tb) {
+    NYS_GEMM_B3(false, false, false);
+  } else if (!ta && tb) {
+    NYS_GEMM_B3(false, true, false);
+  } else if (ta && !tb) {
+    NYS_GEMM_B3(true, false, false);
+  } else {
+    NYS_GEMM_B3(true, true, false);
+  }
 #undef NYS_GEMM_B3
   NYS_CHECK_LAUNCH();
   if (nz > 1) {
@@ -586,6 +665,43 @@ nys_status gemm_bf16x3(bool ta, bool tb, int64_t M, int64_t N, int64_t K, float 
     NYS_CHECK_LAUNCH();
   }
   return NYS_OK;
+}
+
+}  // namespace
+
+size_t gemm_bf16x3_split_elems(int64_t K, int64_t N) { return (size_t)(cdiv(K, XK) * XK) * (size_t)N; }
+
+nys_status gemm_bf16x3(bool ta, bool tb, int64_t M, int64_t N, int64_t K, float alpha, const float* A, int64_t lda,
+                       const float* B, int64_t ldb, float beta, float* C, int64_t ldc, float* scratch,
+                       size_t scratch_elems, hipStream_t s) {
+  if (M <= 0 || N <= 0) return NYS_OK;
+  // float4 loads along k need 16-byte aligned rows
+  const bool vec_a = ta || ((lda % 4 == 0) && ((uintptr_t)A % 16 == 0));
+  const bool vec_b = !tb || ((ldb % 4 == 0) && ((uintptr_t)B % 16 == 0));
+  if (!vec_a || !vec_b || K % 4 != 0)
+    return gemm<float, float, float>(ta, tb, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, scratch, scratch_elems, s);
+  // B split into bf16 pieces once (every row block of A reads it) when the
+  // scratch's tail holds the pieces and its front the split-K partials the
+  // product would take anyway
+  SplitB bs{nullptr, nullptr, 0};
+  const int64_t ldk = cdiv(K, XK) * XK;
+  const size_t pieces = (size_t)ldk * (size_t)N;  // hi + lo bf16: one float's room each
+  const int64_t lt = cdiv(M, LM) * cdiv(N, LN);
+  const int64_t target = 2 * (int64_t)(num_cus() < 256 ? num_cus() : 256);
+  int64_t nzw = lt < target ? cdiv(target, lt) : 1;
+  if (nzw > 64) nzw = 64;
+  const size_t want = pieces + (nzw > 1 ? (size_t)nzw * (size_t)M * (size_t)N : 0) + 4;
+  if (scratch && want <= scratch_elems) {
+    const size_t off = (scratch_elems - pieces) & ~(size_t)3;  // 16-byte aligned pieces
+    __bf16* hi = reinterpret_cast<__bf16*>(scratch + off);
+    __bf16* lo = hi + (size_t)ldk * (size_t)N;
+    hipLaunchKernelGGL(split_b_bf16, dim3((unsigned)cdiv(ldk, 32), (unsigned)cdiv(N, 32)), dim3(256), 0, s, K, N,
+                       B, ldb, tb ? 1 : 0, ldk, hi, lo);
+    NYS_CHECK_LAUNCH();
+    bs = SplitB{hi, lo, ldk};
+    scratch_elems = off;
+  }
+  return gemm_bf16x3_run(ta, tb, M, N, K, alpha, A, lda, B, ldb, bs, beta, C, ldc, scratch, scratch_elems, s);
 }
 
 }  // namespace nys

@@ -19,6 +19,10 @@ nys_status gemm_bf16x3(bool ta, bool tb, int64_t M, int64_t N, int64_t K, float 
                        const float* B, int64_t ldb, float beta, float* C, int64_t ldc, float* scratch,
                        size_t scratch_elems, hipStream_t s);
 
+// Scratch (floats) that lets gemm_bf16x3 split B (K x N) into bf16 pieces once
+// instead of in every workgroup that reads it; added to the split-K share.
+size_t gemm_bf16x3_split_elems(int64_t K, int64_t N);
+
 // Scratch that lets gemm() split K for an M x N output.
 // gemm() splits K only when the output has fewer than 512 tiles of 64 x 64.
 inline size_t gemm_scratch_elems(int64_t M, int64_t N) {
