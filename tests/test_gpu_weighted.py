@@ -54,6 +54,19 @@ def test_weight_rows_folds_square_roots(dtype, n):
 
 
 @pytest.mark.parametrize("dtype", [np.float64, np.float32])
+@pytest.mark.parametrize("n", [3, 8])
+def test_weight_rows_more_rows_than_workgroups(dtype, n):
+    """70001 rows: more than the 65536 workgroups the fold launches, so the
+    grid strides over the rows; 3 columns take the scalar kernel, 8 the
+    16-byte one.  Every row is checked."""
+    X, d = _case(m=70001, n=n, seed=83, dtype=dtype)
+    Xw = h(nys.nys_weight_rows(torch.as_tensor(X, device=DEV), torch.as_tensor(d, device=DEV)))
+    want = np.sqrt(d).astype(dtype)[:, None] * X
+    np.testing.assert_allclose(Xw, want.astype(np.float64), rtol=2.0 ** -52 if dtype == np.float64 else 2.0 ** -23,
+                               atol=0.0)
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
 @pytest.mark.parametrize("k", [1, 7])
 def test_weighted_products(dtype, k):
     """float64 products: float32 data is promoted exactly and the float64
