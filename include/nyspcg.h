@@ -17,8 +17,14 @@
  *     thread, made once and kept until the process ends, into which the
  *     device writes the flags that nys_factor and nys_pcg_solve* poll.
  *   - `stream` is the caller's hipStream_t (NULL = default stream).  Work is
- *     enqueued on it in order.  nys_factor and nys_pcg_solve* synchronise that
- *     stream to read convergence and failure flags; the other calls do not.
+ *     enqueued on it in order.  nys_pcg_solve* synchronise that stream to
+ *     read convergence and failure flags.  nys_sketch and nys_factor read
+ *     theirs from pinned host memory as the device writes them and return
+ *     once their last kernels are enqueued: their outputs are complete when
+ *     the stream reaches that point (they synchronise the stream only when
+ *     the pinned memory could not be had, and nys_factor also with
+ *     NYS_VERBOSE set).  Calls documented as synchronising say so; the
+ *     others do not.
  *     nys_pcg_solve with opts.device_info = 1 neither synchronises nor reads
  *     device memory on the host, so it can be captured into a HIP graph.
  *   - Inputs are never written, except the buffers documented as in/out.
@@ -175,7 +181,9 @@ nys_status nys_gaussian(uint64_t seed, int64_t n, int64_t ell, double* out, int6
  * with nys_gaussian(seed).  Omega_out, Y_out: device float64 n x ell (ld = ell).
  * prec selects the arithmetic of Y = A Omega (FP64, FP32 or BF16X3 tiles);
  * Omega is float64 in every mode.  Errors: NYS_ERR_ARG (1 <= ell <= min(n, 2048)
- * violated, bad operator), NYS_ERR_NOT_PSD (Omega0 rank deficient). */
+ * violated, bad operator), NYS_ERR_NOT_PSD (Omega0 rank deficient).
+ * Waits for the CholeskyQR pivot flags, then returns with Y = A Omega still
+ * enqueued on the stream (see the stream note at the top). */
 nys_status nys_sketch(const nys_operator* A, int64_t ell, uint64_t seed, const double* omega0,
                       double* Omega_out, double* Y_out, int32_t prec, void* ws, size_t ws_bytes,
                       void* stream);
@@ -191,7 +199,9 @@ nys_status nys_sketch(const nys_operator* A, int64_t ell, uint64_t seed, const d
  * the caller (1 <= P->ell <= min(n, 2048), else NYS_ERR_ARG; the same bound
  * holds for every call that takes a preconditioner); P->nu is written (host).
  * A failed Cholesky is retried with nu <- 10 nu up to three times, then
- * NYS_ERR_NOT_PSD.  Synchronises stream. */
+ * NYS_ERR_NOT_PSD.  Waits for the Cholesky's pivot flag and the eigensolver's
+ * sweep flags, then returns with the last kernels (U, lam) still enqueued on
+ * the stream (see the stream note at the top). */
 nys_status nys_factor(const double* Omega, double* Y, nys_precond* P, int32_t prec, void* ws,
                       size_t ws_bytes, void* stream);
 

@@ -227,7 +227,7 @@ void carve_core(Arena& a, int64_t l, Core& c) {
   c.nu = a.take<double>(1);
   c.part = a.take<double>(frob_partials());
   c.sig2 = a.take<double>(l);
-  c.info = a.take<int>(1);
+  c.info = a.take<int>(2);  // pivot flags: [0] the core Cholesky / first CholeskyQR pass, [1] second pass
   c.flags = a.take<int>(kMaxSweeps);
   c.sweeps = a.take<int>(1);
   c.conv = a.take<int>(1);
@@ -683,6 +683,41 @@ nys_status set_mu(double* mu_dev, const double* mu, int64_t nmu, hipStream_t s) 
   return NYS_OK;
 }
 
+// Pivot flags (and the shift) of a Cholesky, published to pinned host memory
+// (bytes 128..151 of pinned_flags()) with the sequence tag written last, so
+// that the host can read them while the device goes on with later kernels.
+// The sketch (two CholeskyQR passes) and the factorisation (the core
+// Cholesky and its shift) share the slot: each call waits for its tag.
+struct PivotSnap {
+  int seq;
+  int info[2];
+  int pad;
+  double nu;
+};
+
+PivotSnap* pivot_snap() {
+  int* p = pinned_flags();
+  return p ? reinterpret_cast<PivotSnap*>(reinterpret_cast<char*>(p) + 128) : nullptr;
+}
+
+// info: ninfo (1 or 2) device flags; nu: device shift or null
+__global__ void pivot_snapshot(const int* __restrict__ info, int ninfo, const double* __restrict__ nu, PivotSnap* out,
+                               int seq) {
+  volatile PivotSnap* o = out;
+  o->info[0] = info[0];
+  o->info[1] = ninfo > 1 ? info[1] : 0;
+  o->nu = nu ? nu[0] : 0.0;
+  __threadfence_system();
+  o->seq = seq;
+}
+
+// Publish the flags and return the tag to wait for.
+int publish_pivots(const int* info, int ninfo, const double* nu, PivotSnap* snap, hipStream_t s) {
+  const int seq = next_pinned_seq();
+  hipLaunchKernelGGL(pivot_snapshot, dim3(1), dim3(1), 0, s, info, ninfo, nu, snap, seq);
+  return seq;
+}
+
 // ---------------------------------------------------------------- CholQR
 
 // Omega <- Omega C^{-1} with C^T C = Omega^T Omega (CholeskyQR), using tmp
@@ -690,17 +725,18 @@ nys_status set_mu(double* mu_dev, const double* mu, int64_t nmu, hipStream_t s) 
 // n x l matrix with n >= 3 l has kappa <= (sqrt(3) + 1)/(sqrt(3) - 1) ~ 3.7
 // with overwhelming probability, so one pass is orthonormal to ~1e-15 there;
 // squarer test matrices, and any caller-supplied matrix, get a second pass.
-nys_status cholqr(double* Om, double* tmp, int64_t n, int64_t l, bool gaussian, Core& c, int* info_host,
+nys_status cholqr(double* Om, double* tmp, int64_t n, int64_t l, bool gaussian, Core& c, int* passes_out,
                   hipStream_t s) {
   const int passes = gaussian && n >= 3 * l ? 1 : 2;
-  info_host[0] = info_host[1] = 0;
+  *passes_out = passes;
   double* src = Om;
   double* dst = tmp;
   for (int pass = 0; pass < passes; ++pass) {
     NYS_TRY((gemm<double, double, double>(true, false, l, l, n, 1.0, src, l, src, l, 0.0, c.G, l,
                                           c.gscr, c.gscr_elems, s)));
-    NYS_TRY(cholesky(c.G, l, c.L, c.Dinv, c.info, s));
-    NYS_HIP(hipMemcpyAsync(&info_host[pass], c.info, sizeof(int), hipMemcpyDeviceToHost, s));
+    // pass p's pivot flag stays in c.info[p] for the caller to read with the
+    // products that follow (no host round trip here)
+    NYS_TRY(cholesky(c.G, l, c.L, c.Dinv, c.info + pass, s));
     NYS_TRY(tri_inverse(c.L, l, c.Dinv, c.Linv, s));
     NYS_TRY((gemm<double, double, double>(false, true, n, l, l, 1.0, src, l, c.Linv, l, 0.0, dst, l,
                                           c.gscr, c.gscr_elems, s)));
@@ -1502,8 +1538,16 @@ nys_status nys_sketch(const nys_operator* A, int64_t ell, uint64_t seed, const d
   hipStream_t s = S(stream);
   if (omega0) NYS_HIP(hipMemcpyAsync(Omega, omega0, sizeof(double) * n * l, hipMemcpyDeviceToDevice, s));
   else NYS_TRY(gaussian(seed, n, l, Omega, l, s));
-  int info[2] = {0, 0};
-  NYS_TRY(cholqr(Omega, Y, n, l, omega0 == nullptr, w.c, info, s));
+  int passes = 1;
+  NYS_TRY(cholqr(Omega, Y, n, l, omega0 == nullptr, w.c, &passes, s));
+  // with pinned host memory the pivot flags are read while Y = A Omega runs,
+  // and the call returns with the product still enqueued
+  PivotSnap* hsnap = pivot_snap();
+  int seq = 0;
+  if (hsnap) {
+    seq = publish_pivots(w.c.info, passes, nullptr, hsnap, s);
+    NYS_CHECK_LAUNCH();
+  }
   if (rbf_lowp_mode(op, prec)) {
     NYS_ARG(op.cols <= 32, "reduced-precision RBF modes need d <= 32");
     // Y = K Omega with the reduced-precision Gram tiles, float32 accumulation
@@ -1542,7 +1586,16 @@ nys_status nys_sketch(const nys_operator* A, int64_t ell, uint64_t seed, const d
   } else {
     NYS_TRY(op_apply_f64(op, Omega, l, l, nullptr, 1, Y, l, w.opscr, w.opscr_elems, s));
   }
-  NYS_HIP(hipStreamSynchronize(s));
+  int info[2] = {0, 0};
+  if (hsnap) {
+    if (!wait_pinned(&hsnap->seq, seq, s)) return NYS_ERR_DEVICE;
+    const volatile PivotSnap* v = hsnap;
+    info[0] = v->info[0];
+    info[1] = v->info[1];
+  } else {
+    NYS_HIP(hipMemcpyAsync(info, w.c.info, sizeof(int) * passes, hipMemcpyDeviceToHost, s));
+    NYS_HIP(hipStreamSynchronize(s));
+  }
   if (info[0] != 0 || info[1] != 0) {
     set_error("test matrix is numerically rank deficient (CholeskyQR pivot %d/%d)", info[0], info[1]);
     return NYS_ERR_NOT_PSD;
@@ -1573,7 +1626,23 @@ nys_status nys_factor(const double* Omega, double* Y, nys_precond* P, int32_t pr
                                                                                       : 9.5367431640625e-07;
   NYS_TRY(frob_shift(Y, n * l, c.part, c.nu, u_rel, s));
   NYS_TRY(add_shift(Y, Omega, n * l, c.nu, 1.0, s));
+  // B = Y_nu C^{-1} = Y_nu L^{-T}, then the Gram B^T B of the thin SVD of B
+  // (B^T B = W S W^T:  U = B W S^{-1/2}, lam = max(0, S - nu))
+  const auto b_and_gram = [&]() -> nys_status {
+    NYS_TRY(tri_inverse(c.L, l, c.Dinv, c.Linv, s));
+    NYS_TRY((gemm<double, double, double>(false, true, n, l, l, 1.0, Y, l, c.Linv, l, 0.0, w.B, l, c.gscr,
+                                          c.gscr_elems, s)));
+    return gemm<double, double, double>(true, false, l, l, n, 1.0, w.B, l, w.B, l, 0.0, c.G, l, c.gscr,
+                                        c.gscr_elems, s);
+  };
+  // With pinned host memory the pivot flag and the shift are published there
+  // and B and its Gram are enqueued before the host reads them, so the device
+  // does not idle on the round trip; after a failed pivot they are discarded
+  // (they read Y_nu and write only B, L^{-1} and the Gram, which the retry
+  // recomputes).
+  PivotSnap* hsnap = pivot_snap();
   int info = 0;
+  double nu = 0.0;
   for (int attempt = 0; attempt <= 3; ++attempt) {
     if (attempt > 0) {  // nu <- 10 nu: Y_10nu = Y_nu + 9 nu Omega
       NYS_TRY(add_shift(Y, Omega, n * l, c.nu, 9.0, s));
@@ -1583,21 +1652,25 @@ nys_status nys_factor(const double* Omega, double* Y, nys_precond* P, int32_t pr
     NYS_TRY((gemm<double, double, double>(true, false, l, l, n, 1.0, Omega, l, Y, l, 0.0, c.G, l, c.gscr,
                                           c.gscr_elems, s)));
     NYS_TRY(cholesky(c.G, l, c.L, c.Dinv, c.info, s));
-    NYS_HIP(hipMemcpyAsync(&info, c.info, sizeof(int), hipMemcpyDeviceToHost, s));
-    NYS_HIP(hipStreamSynchronize(s));
+    if (hsnap) {
+      const int seq = publish_pivots(c.info, 1, c.nu, hsnap, s);
+      NYS_CHECK_LAUNCH();
+      NYS_TRY(b_and_gram());
+      if (!wait_pinned(&hsnap->seq, seq, s)) return NYS_ERR_DEVICE;
+      const volatile PivotSnap* v = hsnap;
+      info = v->info[0];
+      nu = v->nu;
+    } else {
+      NYS_HIP(hipMemcpyAsync(&info, c.info, sizeof(int), hipMemcpyDeviceToHost, s));
+      NYS_HIP(hipStreamSynchronize(s));
+    }
     if (info == 0) break;
   }
   if (info != 0) {
     set_error("Cholesky of Omega^T Y_nu failed at column %d after shift retries", info - 1);
     return NYS_ERR_NOT_PSD;
   }
-  // B = Y_nu C^{-1} = Y_nu L^{-T}
-  NYS_TRY(tri_inverse(c.L, l, c.Dinv, c.Linv, s));
-  NYS_TRY((gemm<double, double, double>(false, true, n, l, l, 1.0, Y, l, c.Linv, l, 0.0, w.B, l, c.gscr,
-                                        c.gscr_elems, s)));
-  // thin SVD of B through B^T B = W S W^T:  U = B W S^{-1/2}, lam = max(0, S - nu)
-  NYS_TRY((gemm<double, double, double>(true, false, l, l, n, 1.0, w.B, l, w.B, l, 0.0, c.G, l, c.gscr,
-                                        c.gscr_elems, s)));
+  if (!hsnap) NYS_TRY(b_and_gram());
   // eigenvectors kept in float32 need off-diagonal ratios ~1e-8, not ~1e-16
   NYS_TRY(sym_eig(c.G, l, c.eig, c.flags, kMaxSweeps, c.sweeps, c.conv, c.T, P->lam, c.sig2,
                   c.nu, s, P->dtype == NYS_F32 ? NYS_JACOBI_RATIO_F32 : 1e-9));
@@ -1611,7 +1684,12 @@ nys_status nys_factor(const double* Omega, double* Y, nys_precond* P, int32_t pr
                        static_cast<float*>(P->U), P->ldu);
     NYS_CHECK_LAUNCH();
   }
-  double nu = 0.0;
+  if (hsnap && !verbose()) {
+    // nu came with the pivot flag; U and lam are complete when the stream
+    // reaches this point (the call returns once their kernels are enqueued)
+    P->nu = nu;
+    return NYS_OK;
+  }
   int sweeps = 0;
   NYS_HIP(hipMemcpyAsync(&nu, c.nu, sizeof(double), hipMemcpyDeviceToHost, s));
   NYS_HIP(hipMemcpyAsync(&sweeps, c.sweeps, sizeof(int), hipMemcpyDeviceToHost, s));

@@ -66,7 +66,9 @@ void timing_mark_end(hipStream_t s);
 // 256 bytes of pinned host memory per host thread, kept for the life of the
 // process (null if it cannot be had): state the device writes for host loops
 // that poll without synchronising the stream.  Bytes 0..63: eigensolver
-// sweeps; bytes 64..127: PCG batch snapshots.
+// sweeps; bytes 64..127: PCG batch snapshots; bytes 128..151: the pivot
+// flags (and shift) of the sketch's CholeskyQR and the factorisation's
+// Cholesky.
 int* pinned_flags();
 
 // Next value of a per-thread sequence that tags what the device writes into

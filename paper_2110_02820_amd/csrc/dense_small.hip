@@ -1182,11 +1182,13 @@ nys_status sym_eig(const double* G, int64_t l, double* work, int* flags, int max
   // sweep.
   int* hpin = pinned_flags();  // [0] converged flag, [1] sequence tag, [2] sweep ratio^2
   int seqs[2] = {0, 0};
+  int last_seq = 0;  // tag of the last end-of-sweep kernel enqueued
   nys_status st = NYS_OK;
   for (int sweep = 0; sweep < max_sweeps; ++sweep) {
     for (int64_t r = 0; r < nb - 1; ++r, ++g)
       hipLaunchKernelGGL(jac_round, dim3((unsigned)(npair + (g > 0 ? tasks : 0))), dim3(256), 0, s, a, g, 1);
     seqs[sweep & 1] = hpin ? next_pinned_seq() : 0;
+    last_seq = seqs[sweep & 1];
     hipLaunchKernelGGL(jac_end_sweep, dim3(1), dim3(1), 0, s, a, sweep, hpin, seqs[sweep & 1]);
     if (hipGetLastError() != hipSuccess) {
       set_error("sym_eig: kernel launch failed");
@@ -1236,6 +1238,10 @@ nys_status sym_eig(const double* G, int64_t l, double* work, int* flags, int max
   hipLaunchKernelGGL(eig_rank, dim3((unsigned)cdiv(l, 256)), dim3(256), 0, s, ev, l, nu, rk, inv, lam, sig2);
   hipLaunchKernelGGL(eig_permute, dim3((unsigned)cdiv(l * l, 256)), dim3(256), 0, s, V, l, m, rk, inv, T);
   NYS_CHECK_LAUNCH();
+  // The last end-of-sweep kernel writes the pinned flags; it has run before
+  // the call returns, so a later call that reuses them (on any stream) never
+  // meets a late write.  The kernels above are already enqueued behind it.
+  if (hpin && last_seq != 0 && !wait_pinned(hpin + 1, last_seq, s)) return NYS_ERR_DEVICE;
   return NYS_OK;
 }
 
