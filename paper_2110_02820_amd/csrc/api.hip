@@ -409,6 +409,35 @@ __global__ void residual_norms(int64_t n, int64_t k, const double* __restrict__ 
   }
 }
 
+// The relative residual of a single column (from residual_norms' partials,
+// summed in the host's order) and a completion tag, published to pinned host
+// memory (bytes 160..175 of pinned_flags()) with the tag written last.
+struct ResSnap {
+  int seq;
+  int pad;
+  double relres;
+};
+
+ResSnap* res_snap() {
+  int* p = pinned_flags();
+  return p ? reinterpret_cast<ResSnap*>(reinterpret_cast<char*>(p) + 160) : nullptr;
+}
+
+// part: residual_norms' output for k = 1 over g workgroups; null: the tag only
+__global__ void residual_snapshot(const double* __restrict__ part, int g, ResSnap* out, int seq) {
+  volatile ResSnap* o = out;
+  if (part) {
+    double rr = 0.0, bb = 0.0;
+    for (int q = 0; q < g; ++q) {
+      rr += part[q];
+      bb += part[g + q];
+    }
+    o->relres = bb > 0.0 ? sqrt(rr / bb) : sqrt(rr);
+  }
+  __threadfence_system();
+  o->seq = seq;
+}
+
 template <typename T>
 __global__ void copy_dev(const T* __restrict__ src, T* __restrict__ dst, int64_t count) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1082,6 +1111,18 @@ nys_status true_residual(const OpDesc& op, int64_t k, const double* mu_dev, doub
   const int g = 64;
   hipLaunchKernelGGL(residual_norms, dim3(g), dim3(256), 0, s, n, k, w.B64, w.V64, w.R64, w.dots);
   NYS_CHECK_LAUNCH();
+  if (ResSnap* rs = k == 1 ? res_snap() : nullptr) {
+    // one column: the device sums the partials and the host spins on pinned
+    // memory instead of synchronising the stream
+    const int seq = next_pinned_seq();
+    hipLaunchKernelGGL(residual_snapshot, dim3(1), dim3(1), 0, s, w.dots, g, rs, seq);
+    NYS_CHECK_LAUNCH();
+    if (!wait_pinned(&rs->seq, seq, s)) return NYS_ERR_DEVICE;
+    const volatile ResSnap* v = rs;
+    const double rv = v->relres;
+    relres.assign(1, rv);
+    return NYS_OK;
+  }
   std::vector<double> h(2 * g * k);
   NYS_HIP(hipMemcpyAsync(h.data(), w.dots, sizeof(double) * 2 * g * k, hipMemcpyDeviceToHost, s));
   NYS_HIP(hipStreamSynchronize(s));
@@ -1337,11 +1378,19 @@ nys_status solve_impl(const OpDesc& op, const PrecDesc& P, const double* mu, int
     for (int64_t c = 0; c < k; ++c)
       if (status[c] != NYS_ERR_BREAKDOWN) status[c] = relres[c] <= tol ? NYS_OK : NYS_NOT_CONVERGED;
   }
-  // write back X
+  // write back X, and wait for it (a tag in pinned memory when there is
+  // some: the host spins instead of synchronising the stream)
   hipLaunchKernelGGL((gather_cols<double, double>), dim3(nblk(n * k)), dim3(256), 0, s, n, k, w.X64, k,
                      k, X, ldx);
   NYS_CHECK_LAUNCH();
-  NYS_HIP(hipStreamSynchronize(s));
+  if (ResSnap* rs = res_snap()) {
+    const int seq = next_pinned_seq();
+    hipLaunchKernelGGL(residual_snapshot, dim3(1), dim3(1), 0, s, nullptr, 0, rs, seq);
+    NYS_CHECK_LAUNCH();
+    if (!wait_pinned(&rs->seq, seq, s)) return NYS_ERR_DEVICE;
+  } else {
+    NYS_HIP(hipStreamSynchronize(s));
+  }
   nys_status worst = NYS_OK;
   for (int64_t c = 0; c < k; ++c) {
     if (status[c] == NYS_ERR_BREAKDOWN) worst = NYS_ERR_BREAKDOWN;

@@ -68,7 +68,8 @@ void timing_mark_end(hipStream_t s);
 // that poll without synchronising the stream.  Bytes 0..63: eigensolver
 // sweeps; bytes 64..127: PCG batch snapshots; bytes 128..151: the pivot
 // flags (and shift) of the sketch's CholeskyQR and the factorisation's
-// Cholesky.
+// Cholesky; bytes 160..175: a solve's single-column residual and its
+// completion tag.
 int* pinned_flags();
 
 // Next value of a per-thread sequence that tags what the device writes into
